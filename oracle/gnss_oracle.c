@@ -1,0 +1,392 @@
+/*
+ * gnss_oracle.c -- plain, slow, obviously-correct CPU oracle for the GPS L1 C/A
+ * software-correlator hot path (carrier wipe-off, code replica, per-tap
+ * multiply-accumulate, code-epoch-aligned dumps).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only tests/, __graft_entry__.smoke() and the
+ * cpu_baseline leg of bench.py may load this library.  It shares no code,
+ * header, table or constant with the HIP path: the Gold-code construction,
+ * sin/cos table, NCO word conversion and correlation loop below are written
+ * independently from the definitions they cite.
+ *
+ * What the paper fixes (Schmidt & Akopian, "Exploiting Acceleration Features
+ * of LabVIEW platform for Real-Time GNSS Software Receiver Optimization"):
+ *   - the C/A signal model, Eq. (1): the C/A code rides the in-phase carrier;
+ *   - C/A code facts, Sec. 3.1: 1023 chips of +-1 at 1.023 Mcps, 1 ms period,
+ *     one code per satellite 1..32, 50 bps navigation data (20 code periods);
+ *   - synchronisation by code-phase alignment plus carrier wipe-off, Sec. 3.1;
+ *   - early-late spacing of 1/2 chip, Table 3; 1 ms integrations, Sec. 4.
+ * The paper gives none of the correlator arithmetic; the readings used here
+ * (LUT size and amplitude, NCO word sizes, wipe-off sign, dump alignment,
+ * 2-bit coding, chip-to-sign mapping) are stated at each function below.
+ * The Gold-code generator polynomials and per-PRN G2 phase-selector taps
+ * come from IS-GPS-200, Sec. 3.2.1.3 and Table 3-Ia.
+ *
+ * Parity pins: every function here is pinned by -m "not gpu" tests against
+ * values that do not come from this file (IS-GPS-200 first-ten-chip octal
+ * words, Gold-family correlation values, closed-form correlations of
+ * noiseless signals, a hand formula for the fs/4 carrier, brute force).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_CODE_LEN 1023
+#define ORC_LUT_SIZE 256
+#define ORC_LUT_AMP 24.0
+#define ORC_TWO32 4294967296.0
+
+enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ERANGE = -4, ORC_ENOSPC = -7 };
+enum { ORC_I8_REAL = 0, ORC_I8_IQ = 1, ORC_I2_REAL = 2 };
+
+/* ------------------------------------------------------------------------ */
+/* C/A Gold code, IS-GPS-200 Sec. 3.2.1.3.                                   */
+/*   G1 = 1 + x^3 + x^10,  G2 = 1 + x^2 + x^3 + x^6 + x^8 + x^9 + x^10.       */
+/* Both 10-stage registers start all ones at the code epoch.  G1's output is */
+/* stage 10; the satellite's G2 output is the XOR of two G2 stages (the      */
+/* phase-selector taps of Table 3-Ia).  Chip = G1 out XOR G2i out.           */
+/* ------------------------------------------------------------------------ */
+static const int orc_g2_sel[32][2] = {
+    {2, 6},  {3, 7},  {4, 8},  {5, 9},  {1, 9},  {2, 10}, {1, 8},  {2, 9},
+    {3, 10}, {2, 3},  {3, 4},  {5, 6},  {6, 7},  {7, 8},  {8, 9},  {9, 10},
+    {1, 4},  {2, 5},  {3, 6},  {4, 7},  {5, 8},  {6, 9},  {1, 3},  {4, 6},
+    {5, 7},  {6, 8},  {7, 9},  {8, 10}, {1, 6},  {2, 7},  {3, 8},  {4, 9}};
+
+/* Logic levels of the C/A code for one PRN: out[i] in {0,1}, i = 0..1022. */
+int orc_ca_bits(int prn, uint8_t* out)
+{
+    if (prn < 1 || prn > 32 || !out) return ORC_EINVAL;
+    int g1[11], g2[11]; /* stage s at index s, 1..10 */
+    for (int s = 1; s <= 10; ++s) { g1[s] = 1; g2[s] = 1; }
+    const int a = orc_g2_sel[prn - 1][0], b = orc_g2_sel[prn - 1][1];
+    for (int i = 0; i < ORC_CODE_LEN; ++i) {
+        int g1_out = g1[10];
+        int g2_out = g2[a] ^ g2[b];
+        out[i] = (uint8_t)(g1_out ^ g2_out);
+        int f1 = g1[3] ^ g1[10];
+        int f2 = g2[2] ^ g2[3] ^ g2[6] ^ g2[8] ^ g2[9] ^ g2[10];
+        for (int s = 10; s > 1; --s) { g1[s] = g1[s - 1]; g2[s] = g2[s - 1]; }
+        g1[1] = f1;
+        g2[1] = f2;
+    }
+    return ORC_OK;
+}
+
+/* Plain G2 sequence (stage-10 output), used by the tests to check the
+ * "G2 delayed by the listed delay" column of Table 3-Ia. */
+int orc_g2_bits(uint8_t* out)
+{
+    if (!out) return ORC_EINVAL;
+    int g2[11];
+    for (int s = 1; s <= 10; ++s) g2[s] = 1;
+    for (int i = 0; i < ORC_CODE_LEN; ++i) {
+        out[i] = (uint8_t)g2[10];
+        int f2 = g2[2] ^ g2[3] ^ g2[6] ^ g2[8] ^ g2[9] ^ g2[10];
+        for (int s = 10; s > 1; --s) g2[s] = g2[s - 1];
+        g2[1] = f2;
+    }
+    return ORC_OK;
+}
+
+/* The satellite's G2 output alone (XOR of its two phase-selector stages),
+ * used by the tests for the same column check. */
+int orc_g2i_bits(int prn, uint8_t* out)
+{
+    if (prn < 1 || prn > 32 || !out) return ORC_EINVAL;
+    int g2[11];
+    for (int s = 1; s <= 10; ++s) g2[s] = 1;
+    const int a = orc_g2_sel[prn - 1][0], b = orc_g2_sel[prn - 1][1];
+    for (int i = 0; i < ORC_CODE_LEN; ++i) {
+        out[i] = (uint8_t)(g2[a] ^ g2[b]);
+        int f2 = g2[2] ^ g2[3] ^ g2[6] ^ g2[8] ^ g2[9] ^ g2[10];
+        for (int s = 10; s > 1; --s) g2[s] = g2[s - 1];
+        g2[1] = f2;
+    }
+    return ORC_OK;
+}
+
+/* Chip values: logic 0 -> +1, logic 1 -> -1 (Sec. 3.1 says only "+1's and
+ * -1's"; the mapping is a global sign). */
+int orc_ca_code(int prn, int8_t* out)
+{
+    uint8_t bits[ORC_CODE_LEN];
+    int rc = orc_ca_bits(prn, bits);
+    if (rc) return rc;
+    for (int i = 0; i < ORC_CODE_LEN; ++i) out[i] = bits[i] ? -1 : 1;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Carrier sin/cos table.  256 entries indexed by the top 8 bits of the      */
+/* 32-bit carrier phase word; entry l holds round(24*cos(2*pi*(l+1/2)/256))  */
+/* and round(24*sin(...)), rounding half away from zero (no ties occur).     */
+/* ------------------------------------------------------------------------ */
+static int8_t orc_round_away(double v)
+{
+    return (int8_t)(v >= 0.0 ? floor(v + 0.5) : -floor(-v + 0.5));
+}
+
+int orc_lut(int8_t* cos_out, int8_t* sin_out)
+{
+    if (!cos_out || !sin_out) return ORC_EINVAL;
+    for (int l = 0; l < ORC_LUT_SIZE; ++l) {
+        double ang = 2.0 * M_PI * ((double)l + 0.5) / (double)ORC_LUT_SIZE;
+        cos_out[l] = orc_round_away(ORC_LUT_AMP * cos(ang));
+        sin_out[l] = orc_round_away(ORC_LUT_AMP * sin(ang));
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* NCO words from physical parameters.                                       */
+/*   carrier step  = round_half_even(f_carr / fs * 2^32) mod 2^32            */
+/*   carrier phase = round_half_even(frac(phase_cycles) * 2^32) mod 2^32     */
+/*   code step     = round_half_even(code_rate / fs * 2^32)   (Q32 chips)    */
+/*   code phase    = round_half_even(p * 2^32) mod W,  p = chips mod T*1023  */
+/* W = T*1023*2^32 is the integration window of T code periods.             */
+/* ------------------------------------------------------------------------ */
+int orc_nco_words(double fs_hz, double carr_hz, double carr_phase_cyc,
+                  double code_rate_cps, double code_phase_chips, int int_periods,
+                  uint32_t* carr_phase, uint32_t* carr_step,
+                  uint64_t* code_phase, uint64_t* code_step)
+{
+    if (!(fs_hz > 0.0) || int_periods < 1 || !(code_rate_cps > 0.0)) return ORC_EINVAL;
+    double span = (double)int_periods * ORC_CODE_LEN;
+    uint64_t W = (uint64_t)int_periods * ORC_CODE_LEN * (uint64_t)4294967296ULL;
+
+    double cs = nearbyint(carr_hz / fs_hz * ORC_TWO32);
+    *carr_step = (uint32_t)(uint64_t)(int64_t)cs;
+
+    double fr = carr_phase_cyc - floor(carr_phase_cyc);
+    double cp = nearbyint(fr * ORC_TWO32);
+    *carr_phase = (uint32_t)(uint64_t)(int64_t)cp;
+
+    double ks = nearbyint(code_rate_cps / fs_hz * ORC_TWO32);
+    if (!(ks >= 1.0) || ks >= 18446744073709551616.0) return ORC_EINVAL;
+    *code_step = (uint64_t)ks;
+
+    double p = fmod(code_phase_chips, span);
+    if (p < 0.0) p += span;
+    double kp = nearbyint(p * ORC_TWO32);
+    uint64_t w = (uint64_t)kp;
+    *code_phase = w % W;
+    return ORC_OK;
+}
+
+/* floor(v / 2^32) for a signed 64-bit value, written out. */
+static int64_t orc_floor_div_2_32(int64_t v)
+{
+    const int64_t d = (int64_t)4294967296LL;
+    int64_t q = v / d;
+    if ((v % d) != 0 && v < 0) q -= 1;
+    return q;
+}
+
+static int64_t orc_mod(int64_t a, int64_t m)
+{
+    int64_t r = a % m;
+    return r < 0 ? r + m : r;
+}
+
+/* One sample, unpacked: real formats set xq = 0 and is_complex = 0.
+ * 2-bit real: value codes 0,1,2,3 -> -3,-1,+1,+3, four samples per byte,
+ * sample j of a byte in bits [2j, 2j+1] (least significant pair first). */
+static void orc_sample(int fmt, const uint8_t* buf, uint64_t n, int* xi, int* xq)
+{
+    if (fmt == ORC_I8_REAL) {
+        *xi = (int)(int8_t)buf[n];
+        *xq = 0;
+    } else if (fmt == ORC_I8_IQ) {
+        *xi = (int)(int8_t)buf[2 * n];
+        *xq = (int)(int8_t)buf[2 * n + 1];
+    } else {
+        int code = (buf[n >> 2] >> (2 * (n & 3))) & 3;
+        *xi = 2 * code - 3;
+        *xq = 0;
+    }
+}
+
+static int orc_fits_i32(int64_t v) { return v >= INT32_MIN && v <= INT32_MAX; }
+
+/*
+ * Integer (LUT) correlator for one channel over one block of samples.
+ *
+ * Per sample n = 0..N-1 (all integer, exact):
+ *   Phi_n = Phi_0 + n*dPhi (mod 2^32),  l = Phi_n >> 24,  (c, s) = LUT[l]
+ *   wipe-off by exp(-j*theta):
+ *     real     wI =  x*c,            wQ = -x*s
+ *     complex  wI =  xI*c + xQ*s,    wQ =  xQ*c - xI*s
+ *   U_n = P_0 + n*dP (unwrapped Q32 chips), window m = floor(U_n / W)
+ *   a sample of a later window closes the open dump first
+ *   P = U_n - m*W;  for each tap k: chip = floor((P + delta_k) / 2^32) mod 1023
+ *     I_k += wI * C[chip],  Q_k += wQ * C[chip]
+ * At the end of the block every window that U_N (the phase of the next
+ * sample) has passed is closed as well, so the open dump always holds the
+ * samples of window floor(U_N / W) and any split of a stream into blocks
+ * gives the same dumps.
+ *
+ * acc[] (int64, n_taps*2, I then Q per tap) and acc_n carry the open dump in
+ * and out; dumps[] receives closed dumps as [dump][tap][I,Q], dump_n[] their
+ * sample counts.  Returns ORC_ERANGE if any accumulation leaves int32,
+ * ORC_ENOSPC if more than max_dumps dumps close.
+ */
+int orc_correlate_lut(int fmt, const uint8_t* buf, uint64_t n_samples,
+                      int prn, int n_taps, const int64_t* tap_q32, int int_periods,
+                      uint32_t* carr_phase, uint32_t carr_step,
+                      uint64_t* code_phase, uint64_t code_step,
+                      int64_t* acc, uint32_t* acc_n,
+                      int64_t* dumps, uint32_t* dump_n, uint32_t max_dumps,
+                      uint32_t* n_dumps)
+{
+    if (fmt < 0 || fmt > 2 || n_taps < 1 || int_periods < 1 || !acc || !acc_n || !n_dumps)
+        return ORC_EINVAL;
+    int8_t code[ORC_CODE_LEN], lc[ORC_LUT_SIZE], ls[ORC_LUT_SIZE];
+    if (orc_ca_code(prn, code)) return ORC_EINVAL;
+    orc_lut(lc, ls);
+
+    const uint64_t W = (uint64_t)int_periods * ORC_CODE_LEN * 4294967296ULL;
+    const uint32_t phi0 = *carr_phase;
+    const uint64_t p0 = *code_phase;
+    if (p0 >= W) return ORC_EINVAL;
+    uint64_t cur = 0;      /* window index of the open dump */
+    uint32_t nd = 0;
+    int rc = ORC_OK;
+
+    for (uint64_t n = 0; n < n_samples; ++n) {
+        uint32_t phi = phi0 + (uint32_t)n * carr_step;
+        int l = (int)(phi >> 24);
+        int c = lc[l], s = ls[l];
+        int xi, xq;
+        orc_sample(fmt, buf, n, &xi, &xq);
+        int64_t wi, wq;
+        if (fmt == ORC_I8_IQ) {
+            wi = (int64_t)xi * c + (int64_t)xq * s;
+            wq = (int64_t)xq * c - (int64_t)xi * s;
+        } else {
+            wi = (int64_t)xi * c;
+            wq = -(int64_t)xi * s;
+        }
+        uint64_t u = p0 + n * code_step;
+        uint64_t m = u / W;
+        while (m > cur) {
+            if (nd >= max_dumps || !dumps || !dump_n) return ORC_ENOSPC;
+            for (int k = 0; k < 2 * n_taps; ++k) {
+                if (!orc_fits_i32(acc[k])) rc = ORC_ERANGE;
+                dumps[(uint64_t)nd * 2 * n_taps + k] = acc[k];
+                acc[k] = 0;
+            }
+            dump_n[nd++] = *acc_n;
+            *acc_n = 0;
+            ++cur;
+        }
+        int64_t p = (int64_t)(u - m * W);
+        for (int k = 0; k < n_taps; ++k) {
+            int64_t chip = orc_mod(orc_floor_div_2_32(p + tap_q32[k]), ORC_CODE_LEN);
+            int r = code[chip];
+            acc[2 * k] += wi * r;
+            acc[2 * k + 1] += wq * r;
+        }
+        *acc_n += 1;
+    }
+    uint64_t u_end = p0 + n_samples * code_step;
+    uint64_t m_end = u_end / W;
+    while (m_end > cur) {
+        if (nd >= max_dumps || !dumps || !dump_n) return ORC_ENOSPC;
+        for (int k = 0; k < 2 * n_taps; ++k) {
+            if (!orc_fits_i32(acc[k])) rc = ORC_ERANGE;
+            dumps[(uint64_t)nd * 2 * n_taps + k] = acc[k];
+            acc[k] = 0;
+        }
+        dump_n[nd++] = *acc_n;
+        *acc_n = 0;
+        ++cur;
+    }
+    for (int k = 0; k < 2 * n_taps; ++k)
+        if (!orc_fits_i32(acc[k])) rc = ORC_ERANGE;
+    *carr_phase = phi0 + (uint32_t)n_samples * carr_step;
+    *code_phase = u_end - m_end * W;
+    *n_dumps = nd;
+    return rc;
+}
+
+/*
+ * FP64 form of the same correlator, the reference for the FP32 carrier
+ * variant.  The carrier is (cos, sin)(2*pi*frac(phi_0 + n*f)) in double,
+ * with phi_0 in cycles and f in cycles per sample, and wipe-off and
+ * accumulation are in double; the code NCO, replica, taps and dump rule are
+ * the integer ones of orc_correlate_lut unchanged.  On return *carr_phase_cyc
+ * is frac(phi_0 + N*f).
+ */
+int orc_correlate_f64(int fmt, const uint8_t* buf, uint64_t n_samples,
+                      int prn, int n_taps, const int64_t* tap_q32, int int_periods,
+                      double* carr_phase_cyc, double carr_freq_cyc,
+                      uint64_t* code_phase, uint64_t code_step,
+                      double* acc, uint32_t* acc_n,
+                      double* dumps, uint32_t* dump_n, uint32_t max_dumps,
+                      uint32_t* n_dumps)
+{
+    if (fmt < 0 || fmt > 2 || n_taps < 1 || int_periods < 1 || !acc || !acc_n || !n_dumps)
+        return ORC_EINVAL;
+    int8_t code[ORC_CODE_LEN];
+    if (orc_ca_code(prn, code)) return ORC_EINVAL;
+    const uint64_t W = (uint64_t)int_periods * ORC_CODE_LEN * 4294967296ULL;
+    const double ph0 = *carr_phase_cyc;
+    const uint64_t p0 = *code_phase;
+    if (p0 >= W) return ORC_EINVAL;
+    uint64_t cur = 0;
+    uint32_t nd = 0;
+
+    for (uint64_t n = 0; n < n_samples; ++n) {
+        double t = ph0 + (double)n * carr_freq_cyc;
+        double th = 2.0 * M_PI * (t - floor(t));
+        double c = cos(th), s = sin(th);
+        int xi, xq;
+        orc_sample(fmt, buf, n, &xi, &xq);
+        double wi, wq;
+        if (fmt == ORC_I8_IQ) {
+            wi = xi * c + xq * s;
+            wq = xq * c - xi * s;
+        } else {
+            wi = xi * c;
+            wq = -xi * s;
+        }
+        uint64_t u = p0 + n * code_step;
+        uint64_t m = u / W;
+        while (m > cur) {
+            if (nd >= max_dumps || !dumps || !dump_n) return ORC_ENOSPC;
+            for (int k = 0; k < 2 * n_taps; ++k) {
+                dumps[(uint64_t)nd * 2 * n_taps + k] = acc[k];
+                acc[k] = 0.0;
+            }
+            dump_n[nd++] = *acc_n;
+            *acc_n = 0;
+            ++cur;
+        }
+        int64_t p = (int64_t)(u - m * W);
+        for (int k = 0; k < n_taps; ++k) {
+            int64_t chip = orc_mod(orc_floor_div_2_32(p + tap_q32[k]), ORC_CODE_LEN);
+            int r = code[chip];
+            acc[2 * k] += wi * r;
+            acc[2 * k + 1] += wq * r;
+        }
+        *acc_n += 1;
+    }
+    uint64_t u_end = p0 + n_samples * code_step;
+    uint64_t m_end = u_end / W;
+    while (m_end > cur) {
+        if (nd >= max_dumps || !dumps || !dump_n) return ORC_ENOSPC;
+        for (int k = 0; k < 2 * n_taps; ++k) {
+            dumps[(uint64_t)nd * 2 * n_taps + k] = acc[k];
+            acc[k] = 0.0;
+        }
+        dump_n[nd++] = *acc_n;
+        *acc_n = 0;
+        ++cur;
+    }
+    double t_end = ph0 + (double)n_samples * carr_freq_cyc;
+    *carr_phase_cyc = t_end - floor(t_end);
+    *code_phase = u_end - m_end * W;
+    *n_dumps = nd;
+    return ORC_OK;
+}
