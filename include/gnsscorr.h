@@ -1,0 +1,216 @@
+/*
+ * gnsscorr.h -- C ABI of libgnsscorr, a GPS L1 C/A software correlator for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library implements the tracking correlator of a GPS software receiver:
+ * per channel, carrier wipe-off, C/A code replica generation and a
+ * multiply-accumulate per replica tap (early / prompt / late, or many taps),
+ * integrated over code-epoch-aligned dumps.  This is the part of the
+ * receiver that Schmidt & Akopian ("Exploiting Acceleration Features of
+ * LabVIEW platform for Real-Time GNSS Software Receiver Optimization")
+ * accelerate with SIMD software correlators (Sec. 3.7, Table 4) and that
+ * dominates tracking time (Sec. 3.5).  Their tracking call takes the raw
+ * sample block, its size, the system parameters and the array of channel
+ * parameter clusters by reference (Sec. 3.4) and processes channels
+ * independently (Sec. 3.5); this ABI keeps that shape:
+ *
+ *   system parameters   -> gc_format + the NCO words derived from fs and IF
+ *   channel clusters    -> gc_chan_cfg (static) + gc_chan_state (in/out)
+ *   raw block + size    -> device sample pointer + n_samples
+ *
+ * Conventions (the paper is silent on all of them; these are this
+ * library's definitions, reproduced bit for bit by its test oracle):
+ *   - C/A code: IS-GPS-200 Sec. 3.2.1.3 / Table 3-Ia; logic 0 -> +1,
+ *     logic 1 -> -1 (Sec. 3.1 says only that chips are +1 and -1).
+ *   - Carrier NCO: 32-bit phase word Phi (cycles * 2^32); Phi_n = Phi_0 +
+ *     n*dPhi mod 2^32.  Table index l = Phi_n >> 24; the table holds
+ *     round(24*cos(2*pi*(l+1/2)/256)) and round(24*sin(...)) (GC_LUT_AMP).
+ *   - Wipe-off multiplies by exp(-j*theta): real x gives (x*c, -x*s);
+ *     complex (xI, xQ) gives (xI*c + xQ*s, xQ*c - xI*s).
+ *   - Code NCO: 64-bit phase U in Q32.32 chips, U_n = U_0 + n*dU; tap k
+ *     uses chip floor((U_n + tap_q32[k]) / 2^32) mod 1023.  Positive
+ *     offsets lead the prompt (early).
+ *   - Dumps: a dump integrates int_periods code periods (window W =
+ *     int_periods*1023*2^32 of code phase) and starts at a code epoch (Sec.
+ *     4 uses 1 ms = one period).  Sample n belongs to window
+ *     floor(U_n / W).  A dump is emitted once the code phase reached at the
+ *     end of the block (U_N) has passed its end; the open dump is carried in
+ *     gc_chan_state, so any split of a stream into blocks gives identical
+ *     dumps.
+ *   - Sample formats: GC_I8_REAL one int8 per sample; GC_I8_IQ int8 I then
+ *     Q; GC_I2_REAL four samples per byte, sample j in bits [2j, 2j+1],
+ *     value codes 0,1,2,3 -> -3,-1,+1,+3.
+ *   - Integer path results are exact int32; a channel whose dump could
+ *     leave int32 is refused (GC_ERANGE), never wrapped.
+ *
+ * Memory: every pointer named "device" is HIP device memory (e.g. a torch
+ * tensor's data_ptr) owned by the caller and kept alive until the stream
+ * reaches the call.  Calls are asynchronous and stream-ordered unless they
+ * say otherwise.  A context or plan may be used from one host thread at a
+ * time.  No call throws; all return gc_status.
+ */
+#ifndef GNSSCORR_H
+#define GNSSCORR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GC_VERSION_MAJOR 1
+#define GC_VERSION_MINOR 0
+#define GC_LUT_BITS 8
+#define GC_LUT_AMP 24
+#define GC_CODE_LEN 1023
+#define GC_MAX_TAPS 128
+#define GC_MAX_CHANNELS 65536
+
+typedef enum {
+    GC_OK = 0,
+    GC_EINVAL = -1,  /* bad argument: null pointer, PRN, format, taps, sizes */
+    GC_ENOMEM = -2,  /* device or host allocation failed */
+    GC_EDEVICE = -3, /* HIP runtime error */
+    GC_ERANGE = -4,  /* a dump could leave int32 (bound on samples per dump) */
+    GC_EBUSY = -5,   /* admission refused: over the HBM budget */
+    GC_EAGAIN = -6,  /* result not ready yet */
+    GC_ENOSPC = -7   /* more dumps close in this block than max_dumps */
+} gc_status;
+
+typedef enum { GC_I8_REAL = 0, GC_I8_IQ = 1, GC_I2_REAL = 2 } gc_format;
+
+typedef enum {
+    GC_CARRIER_LUT = 0, /* integer NCO + sin/cos table, exact int32 results */
+    GC_CARRIER_F32 = 1  /* FP32 sin/cos carrier, float results (FP64 block start phases) */
+} gc_carrier;
+
+typedef struct gc_ctx gc_ctx;
+typedef struct gc_plan gc_plan;
+
+/* Static part of one channel (the paper's per-channel cluster, Sec. 3.4). */
+typedef struct {
+    int32_t prn;                  /* satellite PRN, 1..32 */
+    int32_t n_taps;               /* 1..GC_MAX_TAPS */
+    int32_t int_periods;          /* code periods per dump, >= 1 */
+    int32_t reserved;             /* must be 0 */
+    int64_t tap_q32[GC_MAX_TAPS]; /* replica offsets from prompt, Q32 chips, |offset| < 2^40 */
+} gc_chan_cfg;
+
+/* Dynamic part of one channel, in/out for every call (device memory).
+ * The layout is part of the ABI (size 2096 bytes, 8-byte aligned). */
+typedef struct {
+    uint64_t code_phase;   /* Q32.32 chips, in [0, W) */
+    uint64_t code_step;    /* Q32.32 chips per sample, 1 .. 2^31-1 (>= 2 samples/chip) */
+    uint32_t carr_phase;   /* cycles * 2^32 (GC_CARRIER_LUT) */
+    uint32_t carr_step;    /* cycles * 2^32 per sample, two's complement */
+    uint32_t acc_n;        /* samples in the open dump */
+    uint32_t flags;        /* reserved, 0 */
+    double carr_phase_f;   /* cycles in [0, 1) (GC_CARRIER_F32) */
+    double carr_freq_f;    /* cycles per sample (GC_CARRIER_F32) */
+    int32_t acc[GC_MAX_TAPS][2];   /* open dump I, Q per tap (GC_CARRIER_LUT) */
+    float acc_f[GC_MAX_TAPS][2];   /* open dump I, Q per tap (GC_CARRIER_F32) */
+} gc_chan_state;
+
+/* Text of a status code.  Never NULL. */
+const char* gc_strerror(gc_status s);
+
+/* Library version (GC_VERSION_MAJOR/MINOR of the built library). */
+gc_status gc_version(int32_t* major, int32_t* minor);
+
+/* Create a context on HIP device `device`: selects the device, generates the
+ * G1/G2 register sequences of IS-GPS-200 Sec. 3.2.1.3 on the GPU and keeps
+ * them in device memory.  Synchronous.  *out is owned by the caller and
+ * released with gc_destroy.  Errors: GC_EINVAL (null out, bad device),
+ * GC_EDEVICE, GC_ENOMEM. */
+gc_status gc_create(gc_ctx** out, int32_t device);
+
+/* Release a context and everything it owns.  Plans made from it must be
+ * destroyed first.  Synchronous (waits for the device). */
+gc_status gc_destroy(gc_ctx* ctx);
+
+/* Host helper: NCO words for one channel from physical parameters, into a
+ * host gc_chan_state with empty open dump (Sec. 3.1: code-phase alignment
+ * and carrier wipe-off are the correlator's inputs).
+ *   carr_step  = round_half_even(carr_hz / fs_hz * 2^32) mod 2^32
+ *   carr_phase = round_half_even(frac(carr_phase_cyc) * 2^32) mod 2^32
+ *   code_step  = round_half_even(code_rate_cps / fs_hz * 2^32)
+ *   code_phase = round_half_even((code_phase_chips mod W') * 2^32) mod W,
+ *                W' = int_periods*1023 chips
+ *   carr_phase_f = frac(carr_phase_cyc), carr_freq_f = carr_hz / fs_hz
+ * Errors: GC_EINVAL (null out, fs <= 0, rate <= 0, int_periods < 1, or a
+ * code step outside 1 .. 2^31-1). */
+gc_status gc_nco_init(double fs_hz, double carr_hz, double carr_phase_cyc,
+                      double code_rate_cps, double code_phase_chips,
+                      int32_t int_periods, gc_chan_state* out);
+
+/* C/A code of one PRN as generated on the GPU (G1 XOR delayed G2, IS-GPS-200
+ * Table 3-Ia), copied to host: out[i] in {+1, -1}, i = 0..1022.
+ * Synchronous.  Errors: GC_EINVAL (prn, null), GC_EDEVICE. */
+gc_status gc_code_table(gc_ctx* ctx, int32_t prn, int8_t* host_out);
+
+/* Build a plan for a fixed set of channels that share one sample stream
+ * (one receiver; channels run independently as in Sec. 3.5).  Validates
+ * every cfg on the host, uploads them to device memory (synchronous) and
+ * chooses kernels.  fmt and carrier apply to every channel of the plan.
+ * *out is released with gc_plan_destroy.
+ * Errors: GC_EINVAL (null, n_chan outside 1..GC_MAX_CHANNELS, fmt, carrier,
+ * prn outside 1..32, n_taps outside 1..GC_MAX_TAPS, int_periods < 1,
+ * reserved != 0, tap offset out of range), GC_ENOMEM, GC_EDEVICE. */
+gc_status gc_plan_create(gc_ctx* ctx, gc_format fmt, gc_carrier carrier,
+                         const gc_chan_cfg* cfg, int32_t n_chan, gc_plan** out);
+
+/* Release a plan (waits for the device). */
+gc_status gc_plan_destroy(gc_plan* plan);
+
+/* Query: taps per dump row in the output layout (the largest n_taps of the
+ * plan's channels) and the number of channels. */
+gc_status gc_plan_info(const gc_plan* plan, int32_t* tap_stride, int32_t* n_chan);
+
+/* Correlate one block of samples for every channel of the plan.
+ *
+ *   samples   device, the block in the plan's format; n_samples samples
+ *             (n_samples bytes, 2*n_samples bytes, or ceil(n_samples/4) bytes)
+ *   n_samples 0 .. 2^31-1
+ *   state     device, gc_chan_state[n_chan], read and updated in place:
+ *             NCO phases advance by n_samples, the open dump is carried
+ *   out       device, [n_chan][max_dumps][tap_stride][2] of int32 (LUT) or
+ *             float (F32): I then Q of each tap of each dump closed here
+ *   dump_n    device, uint32 [n_chan][max_dumps]: samples in each dump
+ *             (including samples of the open dump from earlier blocks)
+ *   n_dumps   device, uint32 [n_chan]: dumps closed by this block
+ *   status    device, int32 [n_chan]: GC_OK, or per channel GC_EINVAL
+ *             (state out of range: code_phase >= W or code_step not in
+ *             1..2^31-1), GC_ENOSPC (more than max_dumps would close),
+ *             GC_ERANGE (int32 bound: (floor((W-1)/code_step)+1) * max|w| must
+ *             stay below 2^31, max|w| = 24*max|x| real, 34*128 complex);
+ *             a refused channel's state and outputs are left untouched and
+ *             its n_dumps is 0
+ *   max_dumps rows per channel in out and dump_n
+ *   stream    hipStream_t, or NULL for the default stream
+ *
+ * Asynchronous: returns once the work is enqueued.  Rows past n_dumps[c]
+ * are left as they were.  Errors returned directly: GC_EINVAL (null
+ * pointers, n_samples too large, max_dumps == 0), GC_EDEVICE. */
+gc_status gc_correlate(gc_plan* plan, const void* samples, uint64_t n_samples,
+                       gc_chan_state* state, void* out, uint32_t* dump_n,
+                       uint32_t* n_dumps, int32_t* status, uint32_t max_dumps,
+                       void* stream);
+
+/* Per-launch timing of the plan's main correlation kernel (the paper reports
+ * tracking time per epoch per channel, Sec. 4, Table 5).  With n_slots > 0,
+ * every later gc_correlate records a HIP event pair on its stream around its
+ * main kernel into slot (call index mod n_slots); n_slots = 0 turns timing
+ * off.  At most 4096 slots.  Synchronous set-up.  Errors: GC_EINVAL,
+ * GC_ENOMEM, GC_EDEVICE. */
+gc_status gc_plan_timing(gc_plan* plan, int32_t n_slots);
+
+/* Duration in milliseconds of the kernel timed in `slot`; waits for its stop
+ * event.  Errors: GC_EINVAL (timing off, slot out of range or never
+ * recorded), GC_EDEVICE. */
+gc_status gc_plan_kernel_ms(gc_plan* plan, int32_t slot, float* ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GNSSCORR_H */

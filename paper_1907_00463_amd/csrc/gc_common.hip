@@ -1,0 +1,164 @@
+// gc_common.hip -- context tables and per-call set-up kernels of libgnsscorr.
+//
+// Tables generated on the GPU at context creation:
+//   * the G1 and G2 register sequences of IS-GPS-200 Sec. 3.2.1.3 (1023 bits
+//     each, bit i of word i/32), from which every block composes its PRN's
+//     C/A code in LDS as G1[i] XOR G2[i - delay] (delay from Table 3-Ia);
+//   * the carrier table: entry l = round_half_away(24*cos(2*pi*(l+1/2)/256))
+//     in the low 16 bits and the same of sin in the high 16 bits.
+#include "gc_internal.h"
+#include "gc_device.h"
+
+namespace gc {
+
+// One thread steps both 10-stage registers (all ones at the epoch; G1 taps
+// 3,10; G2 taps 2,3,6,8,9,10; output stage 10).  Threads 0..255 fill the
+// carrier table.
+__global__ void k_init_tables(uint32_t* tables) {
+    uint32_t* g1 = tables + kTabG1;
+    uint32_t* g2 = tables + kTabG2;
+    uint32_t* lut = tables + kTabLut;
+    const int t = threadIdx.x;
+    if (t == 0) {
+        uint32_t r1 = 0x3FF, r2 = 0x3FF;  // bit s-1 holds stage s
+        for (int w = 0; w < 32; ++w) { g1[w] = 0; g2[w] = 0; }
+        for (int i = 0; i < kCodeLen; ++i) {
+            g1[i >> 5] |= ((r1 >> 9) & 1u) << (i & 31);
+            g2[i >> 5] |= ((r2 >> 9) & 1u) << (i & 31);
+            uint32_t f1 = ((r1 >> 2) ^ (r1 >> 9)) & 1u;
+            uint32_t f2 = ((r2 >> 1) ^ (r2 >> 2) ^ (r2 >> 5) ^ (r2 >> 7) ^ (r2 >> 8) ^ (r2 >> 9)) & 1u;
+            r1 = ((r1 << 1) | f1) & 0x3FF;
+            r2 = ((r2 << 1) | f2) & 0x3FF;
+        }
+    }
+    if (t < 256) {
+        double ang = 6.283185307179586476925286766559 * ((double)t + 0.5) / 256.0;
+        double vc = (double)GC_LUT_AMP * cos(ang);
+        double vs = (double)GC_LUT_AMP * sin(ang);
+        int ic = (int)(vc >= 0.0 ? floor(vc + 0.5) : -floor(-vc + 0.5));
+        int is = (int)(vs >= 0.0 ? floor(vs + 0.5) : -floor(-vs + 0.5));
+        lut[t] = ((uint32_t)(uint16_t)(int16_t)ic) | ((uint32_t)(uint16_t)(int16_t)is << 16);
+    }
+}
+
+__global__ void k_code_table(const uint32_t* tables, int d, int8_t* out) {
+    for (int i = threadIdx.x; i < kCodeLen; i += blockDim.x) out[i] = ca_chip(tables, d, i);
+}
+
+hipError_t launch_make_tables(uint32_t* d_tables, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_tables, dim3(1), dim3(256), 0, s, d_tables);
+    return hipGetLastError();
+}
+
+hipError_t launch_code_table(const uint32_t* d_tables, int g2_delay, int8_t* d_out, hipStream_t s) {
+    hipLaunchKernelGGL(k_code_table, dim3(1), dim3(256), 0, s, d_tables, g2_delay, d_out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Per-call set-up, one block per channel:
+//   * validate the channel state and compute M = floor(U_N / W), the number
+//     of dumps this block closes;
+//   * write rows 0..M-1 of the outputs (row 0 starts from the open dump
+//     carried in the state, the others from zero) and their sample counts;
+//   * move the NCO words of the state to the end of the block.
+// The accumulation kernels read the start-of-block NCO words from DevMeta
+// and add into the rows (windows < M) or into the state's open dump (M).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_setup(const DevChan* __restrict__ chans,
+                                               DevMeta* __restrict__ metas,
+                                               gc_chan_state* __restrict__ state,
+                                               uint64_t n, int fmt, int carrier,
+                                               uint32_t max_dumps, void* out, int tap_stride,
+                                               uint32_t* __restrict__ dump_n,
+                                               uint32_t* __restrict__ n_dumps,
+                                               int32_t* __restrict__ status_out) {
+    const int ch = blockIdx.x;
+    const int tid = threadIdx.x;
+    const DevChan& c = chans[ch];
+    gc_chan_state* st = state + ch;
+    __shared__ DevMeta sm;
+    if (tid == 0) {
+        DevMeta m;
+        m.p0 = st->code_phase;
+        m.dp = st->code_step;
+        m.window = c.window;
+        m.phi0 = st->carr_phase;
+        m.dphi = st->carr_step;
+        m.phf0 = st->carr_phase_f;
+        m.ff = st->carr_freq_f;
+        m.acc_n0 = st->acc_n;
+        m.pad = 0;
+        m.m_close = 0;
+        int32_t s = GC_OK;
+        if (m.dp == 0 || m.dp >= (1ull << 31) || m.p0 >= m.window) {
+            s = GC_EINVAL;
+        } else {
+            const uint64_t u_end = m.p0 + n * m.dp;
+            const uint64_t mc = u_end / m.window;
+            const uint64_t nmax = (m.window - 1) / m.dp + 1;
+            const uint64_t maxw = fmt == GC_I8_REAL ? 128ull * GC_LUT_AMP
+                                : fmt == GC_I8_IQ   ? 128ull * kLutAbsSumMax
+                                                    : 3ull * GC_LUT_AMP;
+            if (carrier == GC_CARRIER_LUT && nmax * maxw > 2147483647ull) s = GC_ERANGE;
+            else if (mc > max_dumps) s = GC_ENOSPC;
+            else m.m_close = (uint32_t)mc;
+        }
+        m.status = s;
+        metas[ch] = m;
+        status_out[ch] = s;
+        n_dumps[ch] = s == GC_OK ? m.m_close : 0u;
+        sm = m;
+    }
+    __syncthreads();
+    const DevMeta m = sm;
+    if (m.status != GC_OK) return;
+    const uint32_t M = m.m_close;
+    const int K = c.n_taps;
+    for (uint32_t r = tid; r < M; r += blockDim.x) {
+        const uint64_t s0 = r == 0 ? 0 : (r * m.window - m.p0 + m.dp - 1) / m.dp;
+        const uint64_t s1 = ((r + 1) * m.window - m.p0 + m.dp - 1) / m.dp;
+        dump_n[(uint64_t)ch * max_dumps + r] = (uint32_t)(s1 - s0) + (r == 0 ? m.acc_n0 : 0u);
+        const uint64_t row = ((uint64_t)ch * max_dumps + r) * tap_stride * 2;
+        if (carrier == GC_CARRIER_LUT) {
+            int32_t* o = (int32_t*)out + row;
+            for (int k = 0; k < K; ++k) {
+                o[2 * k] = r == 0 ? st->acc[k][0] : 0;
+                o[2 * k + 1] = r == 0 ? st->acc[k][1] : 0;
+            }
+        } else {
+            float* o = (float*)out + row;
+            for (int k = 0; k < K; ++k) {
+                o[2 * k] = r == 0 ? st->acc_f[k][0] : 0.0f;
+                o[2 * k + 1] = r == 0 ? st->acc_f[k][1] : 0.0f;
+            }
+        }
+    }
+    __syncthreads();
+    if (M >= 1) {
+        for (int k = tid; k < K; k += blockDim.x) {
+            if (carrier == GC_CARRIER_LUT) { st->acc[k][0] = 0; st->acc[k][1] = 0; }
+            else { st->acc_f[k][0] = 0.0f; st->acc_f[k][1] = 0.0f; }
+        }
+    }
+    if (tid == 0) {
+        const uint64_t u_end = m.p0 + n * m.dp;
+        const uint64_t sM = M == 0 ? 0 : ((uint64_t)M * m.window - m.p0 + m.dp - 1) / m.dp;
+        st->acc_n = M == 0 ? m.acc_n0 + (uint32_t)n : (uint32_t)(n - sM);
+        st->carr_phase = m.phi0 + (uint32_t)n * m.dphi;
+        st->code_phase = u_end - (uint64_t)M * m.window;
+        double t = m.phf0 + (double)n * m.ff;
+        st->carr_phase_f = t - floor(t);
+    }
+}
+
+hipError_t launch_setup(const DevChan* chans, DevMeta* meta, gc_chan_state* state, int n_chan,
+                        uint64_t n_samples, int fmt, int carrier, uint32_t max_dumps, void* out,
+                        int tap_stride, uint32_t* dump_n, uint32_t* n_dumps, int32_t* status,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_setup, dim3(n_chan), dim3(256), 0, s, chans, meta, state, n_samples, fmt,
+                       carrier, max_dumps, out, tap_stride, dump_n, n_dumps, status);
+    return hipGetLastError();
+}
+
+}  // namespace gc

@@ -1,0 +1,293 @@
+// gc_runtime.hip -- host runtime of libgnsscorr: contexts, plans, argument
+// validation, NCO word conversion and kernel dispatch behind the C ABI.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "gc_internal.h"
+#include "gc_device.h"
+
+struct gc_ctx {
+    int device;
+    uint32_t* d_tables;  // G1, G2, carrier table (gc::kTabWords words)
+    hipStream_t stream;  // context-private stream for synchronous helpers
+};
+
+struct gc_plan {
+    gc_ctx* ctx;
+    int fmt;
+    int carrier;
+    int n_chan;
+    int max_taps;
+    gc::DevChan* d_chans;
+    gc::DevMeta* d_meta;
+    std::vector<hipEvent_t> ev_start, ev_stop;  // timing slots (empty: off)
+    std::vector<uint8_t> ev_used;
+    uint64_t calls;
+};
+
+namespace {
+
+// G2 delay in chips of PRN 1..32 (IS-GPS-200, Table 3-Ia).
+const int32_t kG2Delay[32] = {5,   6,   7,   8,   17,  18,  139, 140, 141, 251, 252,
+                              254, 255, 256, 257, 258, 469, 470, 471, 472, 473, 474,
+                              509, 512, 513, 514, 515, 516, 859, 860, 861, 862};
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+gc_status from_hip(hipError_t e) {
+    if (e == hipSuccess) return GC_OK;
+    if (e == hipErrorOutOfMemory) return GC_ENOMEM;
+    return GC_EDEVICE;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gc_strerror(gc_status s) {
+    switch (s) {
+        case GC_OK: return "ok";
+        case GC_EINVAL: return "invalid argument";
+        case GC_ENOMEM: return "out of memory";
+        case GC_EDEVICE: return "HIP device error";
+        case GC_ERANGE: return "dump could exceed the int32 accumulator range";
+        case GC_EBUSY: return "admission refused: over the HBM budget";
+        case GC_EAGAIN: return "result not ready";
+        case GC_ENOSPC: return "more dumps than max_dumps";
+    }
+    return "unknown status";
+}
+
+gc_status gc_version(int32_t* major, int32_t* minor) {
+    if (!major || !minor) return GC_EINVAL;
+    *major = GC_VERSION_MAJOR;
+    *minor = GC_VERSION_MINOR;
+    return GC_OK;
+}
+
+gc_status gc_create(gc_ctx** out, int32_t device) {
+    if (!out) return GC_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) return GC_EDEVICE;
+    if (device < 0 || device >= n) return GC_EINVAL;
+    DeviceGuard g(device);
+    if (!g.ok) return GC_EDEVICE;
+    gc_ctx* c = new (std::nothrow) gc_ctx();
+    if (!c) return GC_ENOMEM;
+    c->device = device;
+    c->d_tables = nullptr;
+    c->stream = nullptr;
+    hipError_t e = hipMalloc(&c->d_tables, gc::kTabWords * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = gc::launch_make_tables(c->d_tables, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        if (c->d_tables) (void)hipFree(c->d_tables);
+        if (c->stream) (void)hipStreamDestroy(c->stream);
+        delete c;
+        return from_hip(e);
+    }
+    *out = c;
+    return GC_OK;
+}
+
+gc_status gc_destroy(gc_ctx* ctx) {
+    if (!ctx) return GC_EINVAL;
+    DeviceGuard g(ctx->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(ctx->d_tables);
+    (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return GC_OK;
+}
+
+gc_status gc_nco_init(double fs_hz, double carr_hz, double carr_phase_cyc, double code_rate_cps,
+                      double code_phase_chips, int32_t int_periods, gc_chan_state* out) {
+    if (!out || !(fs_hz > 0.0) || !(code_rate_cps > 0.0) || int_periods < 1) return GC_EINVAL;
+    if (!isfinite(carr_hz) || !isfinite(carr_phase_cyc) || !isfinite(code_phase_chips))
+        return GC_EINVAL;
+    const double two32 = 4294967296.0;
+    const double step_code = nearbyint(code_rate_cps / fs_hz * two32);
+    if (!(step_code >= 1.0) || !(step_code < 2147483648.0)) return GC_EINVAL;
+    memset(out, 0, sizeof(*out));
+    const double cstep = nearbyint(carr_hz / fs_hz * two32);
+    out->carr_step = (uint32_t)(uint64_t)(int64_t)cstep;
+    const double frac_ph = carr_phase_cyc - floor(carr_phase_cyc);
+    out->carr_phase = (uint32_t)(uint64_t)(int64_t)nearbyint(frac_ph * two32);
+    out->code_step = (uint64_t)step_code;
+    const double span = (double)int_periods * GC_CODE_LEN;
+    double p = fmod(code_phase_chips, span);
+    if (p < 0.0) p += span;
+    const uint64_t W = (uint64_t)int_periods * GC_CODE_LEN * gc::kTwo32;
+    out->code_phase = ((uint64_t)nearbyint(p * two32)) % W;
+    out->carr_phase_f = frac_ph;
+    out->carr_freq_f = carr_hz / fs_hz;
+    return GC_OK;
+}
+
+gc_status gc_code_table(gc_ctx* ctx, int32_t prn, int8_t* host_out) {
+    if (!ctx || !host_out || prn < 1 || prn > 32) return GC_EINVAL;
+    DeviceGuard g(ctx->device);
+    int8_t* d = nullptr;
+    hipError_t e = hipMalloc(&d, 1024);
+    if (e == hipSuccess) e = gc::launch_code_table(ctx->d_tables, kG2Delay[prn - 1], d, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(host_out, d, GC_CODE_LEN, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (d) (void)hipFree(d);
+    return from_hip(e);
+}
+
+gc_status gc_plan_create(gc_ctx* ctx, gc_format fmt, gc_carrier carrier, const gc_chan_cfg* cfg,
+                         int32_t n_chan, gc_plan** out) {
+    if (!ctx || !cfg || !out) return GC_EINVAL;
+    *out = nullptr;
+    if (n_chan < 1 || n_chan > GC_MAX_CHANNELS) return GC_EINVAL;
+    if (fmt != GC_I8_REAL && fmt != GC_I8_IQ && fmt != GC_I2_REAL) return GC_EINVAL;
+    if (carrier != GC_CARRIER_LUT && carrier != GC_CARRIER_F32) return GC_EINVAL;
+    std::vector<gc::DevChan> h((size_t)n_chan);
+    int max_taps = 0;
+    for (int i = 0; i < n_chan; ++i) {
+        const gc_chan_cfg& c = cfg[i];
+        if (c.prn < 1 || c.prn > 32 || c.n_taps < 1 || c.n_taps > GC_MAX_TAPS ||
+            c.int_periods < 1 || c.int_periods > 1000 || c.reserved != 0)
+            return GC_EINVAL;
+        gc::DevChan& d = h[(size_t)i];
+        memset(&d, 0, sizeof(d));
+        d.prn = c.prn;
+        d.n_taps = c.n_taps;
+        d.int_periods = c.int_periods;
+        d.g2_delay = kG2Delay[c.prn - 1];
+        d.window = (uint64_t)c.int_periods * GC_CODE_LEN * gc::kTwo32;
+        for (int k = 0; k < c.n_taps; ++k) {
+            const int64_t t = c.tap_q32[k];
+            if (t <= -(int64_t(1) << 40) || t >= (int64_t(1) << 40)) return GC_EINVAL;
+            d.taps[k] = t;
+        }
+        if (c.n_taps > max_taps) max_taps = c.n_taps;
+    }
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return GC_EDEVICE;
+    gc_plan* p = new (std::nothrow) gc_plan();
+    if (!p) return GC_ENOMEM;
+    p->ctx = ctx;
+    p->fmt = fmt;
+    p->carrier = carrier;
+    p->n_chan = n_chan;
+    p->max_taps = max_taps;
+    p->d_chans = nullptr;
+    p->d_meta = nullptr;
+    p->calls = 0;
+    hipError_t e = hipMalloc(&p->d_chans, sizeof(gc::DevChan) * (size_t)n_chan);
+    if (e == hipSuccess) e = hipMalloc(&p->d_meta, sizeof(gc::DevMeta) * (size_t)n_chan);
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_chans, h.data(), sizeof(gc::DevChan) * (size_t)n_chan,
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (p->d_chans) (void)hipFree(p->d_chans);
+        if (p->d_meta) (void)hipFree(p->d_meta);
+        delete p;
+        return from_hip(e);
+    }
+    *out = p;
+    return GC_OK;
+}
+
+static void drop_timing(gc_plan* plan) {
+    for (auto e : plan->ev_start) (void)hipEventDestroy(e);
+    for (auto e : plan->ev_stop) (void)hipEventDestroy(e);
+    plan->ev_start.clear();
+    plan->ev_stop.clear();
+    plan->ev_used.clear();
+}
+
+gc_status gc_plan_timing(gc_plan* plan, int32_t n_slots) {
+    if (!plan || n_slots < 0 || n_slots > 4096) return GC_EINVAL;
+    DeviceGuard g(plan->ctx->device);
+    (void)hipDeviceSynchronize();
+    drop_timing(plan);
+    for (int i = 0; i < n_slots; ++i) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess) { drop_timing(plan); return GC_EDEVICE; }
+        if (hipEventCreate(&b) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            drop_timing(plan);
+            return GC_EDEVICE;
+        }
+        plan->ev_start.push_back(a);
+        plan->ev_stop.push_back(b);
+    }
+    plan->ev_used.assign((size_t)n_slots, 0);
+    plan->calls = 0;
+    return GC_OK;
+}
+
+gc_status gc_plan_kernel_ms(gc_plan* plan, int32_t slot, float* ms) {
+    if (!plan || !ms || slot < 0 || (size_t)slot >= plan->ev_stop.size()) return GC_EINVAL;
+    if (!plan->ev_used[(size_t)slot]) return GC_EINVAL;
+    DeviceGuard g(plan->ctx->device);
+    hipError_t e = hipEventSynchronize(plan->ev_stop[(size_t)slot]);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, plan->ev_start[(size_t)slot],
+                                                 plan->ev_stop[(size_t)slot]);
+    return from_hip(e);
+}
+
+gc_status gc_plan_destroy(gc_plan* plan) {
+    if (!plan) return GC_EINVAL;
+    DeviceGuard g(plan->ctx->device);
+    (void)hipDeviceSynchronize();
+    drop_timing(plan);
+    (void)hipFree(plan->d_chans);
+    (void)hipFree(plan->d_meta);
+    delete plan;
+    return GC_OK;
+}
+
+gc_status gc_plan_info(const gc_plan* plan, int32_t* tap_stride, int32_t* n_chan) {
+    if (!plan || !tap_stride || !n_chan) return GC_EINVAL;
+    *tap_stride = plan->max_taps;
+    *n_chan = plan->n_chan;
+    return GC_OK;
+}
+
+gc_status gc_correlate(gc_plan* plan, const void* samples, uint64_t n_samples,
+                       gc_chan_state* state, void* out, uint32_t* dump_n, uint32_t* n_dumps,
+                       int32_t* status, uint32_t max_dumps, void* stream) {
+    if (!plan || !state || !out || !dump_n || !n_dumps || !status) return GC_EINVAL;
+    if (n_samples >= (1ull << 31) || max_dumps == 0) return GC_EINVAL;
+    if (n_samples > 0 && !samples) return GC_EINVAL;
+    DeviceGuard g(plan->ctx->device);
+    if (!g.ok) return GC_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = gc::launch_setup(plan->d_chans, plan->d_meta, state, plan->n_chan, n_samples,
+                                    plan->fmt, plan->carrier, max_dumps, out, plan->max_taps,
+                                    dump_n, n_dumps, status, s);
+    const size_t slot = plan->ev_stop.empty() ? 0 : (size_t)(plan->calls % plan->ev_stop.size());
+    if (e == hipSuccess && !plan->ev_start.empty()) e = hipEventRecord(plan->ev_start[slot], s);
+    if (e == hipSuccess)
+        e = gc::launch_generic((const uint8_t*)samples, n_samples, plan->fmt, plan->carrier,
+                               plan->d_chans, plan->d_meta, state, plan->n_chan, plan->max_taps,
+                               out, plan->max_taps, max_dumps, plan->ctx->d_tables, s);
+    if (e == hipSuccess && !plan->ev_stop.empty()) {
+        e = hipEventRecord(plan->ev_stop[slot], s);
+        plan->ev_used[slot] = 1;
+    }
+    plan->calls++;
+    return from_hip(e);
+}
+
+}  // extern "C"

@@ -1,0 +1,235 @@
+"""Python binding of libgnsscorr (ctypes; argument marshalling only).
+
+Every function named ``gc_*`` calls the C entry point of the same name in
+``libgnsscorr.so``; every step of the correlator runs in the library's HIP
+kernels.  torch is used for device memory and streams only.  There is no
+fallback: if the built library is missing, importing the binding raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgnsscorr.so")
+
+GC_OK, GC_EINVAL, GC_ENOMEM, GC_EDEVICE, GC_ERANGE, GC_EBUSY, GC_EAGAIN, GC_ENOSPC = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+GC_I8_REAL, GC_I8_IQ, GC_I2_REAL = 0, 1, 2
+GC_CARRIER_LUT, GC_CARRIER_F32 = 0, 1
+GC_MAX_TAPS = 128
+GC_LUT_AMP = 24
+TWO32 = 1 << 32
+
+# ABI structs (layouts fixed by include/gnsscorr.h)
+CHAN_CFG = np.dtype([("prn", "<i4"), ("n_taps", "<i4"), ("int_periods", "<i4"),
+                     ("reserved", "<i4"), ("tap_q32", "<i8", (GC_MAX_TAPS,))])
+CHAN_STATE = np.dtype([("code_phase", "<u8"), ("code_step", "<u8"), ("carr_phase", "<u4"),
+                       ("carr_step", "<u4"), ("acc_n", "<u4"), ("flags", "<u4"),
+                       ("carr_phase_f", "<f8"), ("carr_freq_f", "<f8"),
+                       ("acc", "<i4", (GC_MAX_TAPS, 2)), ("acc_f", "<f4", (GC_MAX_TAPS, 2))])
+assert CHAN_CFG.itemsize == 1040 and CHAN_STATE.itemsize == 2096
+
+
+class GcError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__("%s: %s (%d)" % (where, gc_strerror(status), status))
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libgnsscorr.so is not built (run __graft_entry__.build() or "
+                          "python -m paper_1907_00463_amd.build)")
+    lib = C.CDLL(LIB_PATH)
+    P, I32, U32, U64, D = C.c_void_p, C.c_int32, C.c_uint32, C.c_uint64, C.c_double
+    sig = {
+        "gc_strerror": ([I32], C.c_char_p),
+        "gc_version": ([P, P], I32),
+        "gc_create": ([P, I32], I32),
+        "gc_destroy": ([P], I32),
+        "gc_nco_init": ([D, D, D, D, D, I32, P], I32),
+        "gc_code_table": ([P, I32, P], I32),
+        "gc_plan_create": ([P, I32, I32, P, I32, P], I32),
+        "gc_plan_destroy": ([P], I32),
+        "gc_plan_info": ([P, P, P], I32),
+        "gc_correlate": ([P, P, U64, P, P, P, P, P, U32, P], I32),
+        "gc_plan_timing": ([P, I32], I32),
+        "gc_plan_kernel_ms": ([P, I32, P], I32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+_lib = _load()
+EXPORTED = ("gc_strerror", "gc_version", "gc_create", "gc_destroy", "gc_nco_init",
+            "gc_code_table", "gc_plan_create", "gc_plan_destroy", "gc_plan_info",
+            "gc_correlate", "gc_plan_timing", "gc_plan_kernel_ms")
+
+
+def _check(rc: int, where: str):
+    if rc != GC_OK:
+        raise GcError(rc, where)
+
+
+def _ptr(a) -> Optional[int]:
+    """Address of a numpy array, a torch tensor or an int."""
+    if a is None:
+        return None
+    if isinstance(a, int):
+        return a
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+# ------------------------------------------------------------------ C entry points
+def gc_strerror(status: int) -> str:
+    return _lib.gc_strerror(status).decode()
+
+
+def gc_version():
+    a, b = C.c_int32(), C.c_int32()
+    _check(_lib.gc_version(C.byref(a), C.byref(b)), "gc_version")
+    return a.value, b.value
+
+
+def gc_create(device: int = 0) -> int:
+    h = C.c_void_p()
+    _check(_lib.gc_create(C.byref(h), device), "gc_create")
+    return h.value
+
+
+def gc_destroy(ctx: int) -> None:
+    _check(_lib.gc_destroy(ctx), "gc_destroy")
+
+
+def gc_nco_init(fs_hz, carr_hz, carr_phase_cyc, code_rate_cps, code_phase_chips,
+                int_periods) -> np.ndarray:
+    st = np.zeros(1, CHAN_STATE)
+    _check(_lib.gc_nco_init(fs_hz, carr_hz, carr_phase_cyc, code_rate_cps, code_phase_chips,
+                            int_periods, st.ctypes.data), "gc_nco_init")
+    return st[0]
+
+
+def gc_code_table(ctx: int, prn: int) -> np.ndarray:
+    out = np.zeros(1023, np.int8)
+    _check(_lib.gc_code_table(ctx, prn, out.ctypes.data), "gc_code_table")
+    return out
+
+
+def gc_plan_create(ctx: int, fmt: int, carrier: int, cfg: np.ndarray) -> int:
+    cfg = np.ascontiguousarray(cfg, dtype=CHAN_CFG)
+    h = C.c_void_p()
+    _check(_lib.gc_plan_create(ctx, fmt, carrier, cfg.ctypes.data, len(cfg), C.byref(h)),
+           "gc_plan_create")
+    return h.value
+
+
+def gc_plan_destroy(plan: int) -> None:
+    _check(_lib.gc_plan_destroy(plan), "gc_plan_destroy")
+
+
+def gc_plan_info(plan: int):
+    a, b = C.c_int32(), C.c_int32()
+    _check(_lib.gc_plan_info(plan, C.byref(a), C.byref(b)), "gc_plan_info")
+    return a.value, b.value
+
+
+def gc_correlate(plan: int, samples, n_samples: int, state, out, dump_n, n_dumps, status,
+                 max_dumps: int, stream=None) -> int:
+    """Enqueue one block; returns the gc_status of the call (per-channel status in ``status``)."""
+    return _lib.gc_correlate(plan, _ptr(samples), n_samples, _ptr(state), _ptr(out),
+                             _ptr(dump_n), _ptr(n_dumps), _ptr(status), max_dumps,
+                             _stream_ptr(stream))
+
+
+def gc_plan_timing(plan: int, n_slots: int) -> None:
+    _check(_lib.gc_plan_timing(plan, n_slots), "gc_plan_timing")
+
+
+def gc_plan_kernel_ms(plan: int, slot: int) -> float:
+    ms = C.c_float()
+    _check(_lib.gc_plan_kernel_ms(plan, slot, C.byref(ms)), "gc_plan_kernel_ms")
+    return ms.value
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ------------------------------------------------------------------ conveniences
+def make_cfg(prn: int, taps_q32: Sequence[int], int_periods: int = 1) -> np.ndarray:
+    c = np.zeros((), CHAN_CFG)
+    taps = np.asarray(taps_q32, dtype=np.int64)
+    c["prn"] = prn
+    c["n_taps"] = len(taps)
+    c["int_periods"] = int_periods
+    c["tap_q32"][: len(taps)] = taps
+    return c
+
+
+def max_dumps_for(n_samples: int, code_step_max: int, int_periods_min: int = 1) -> int:
+    """Upper bound on dumps one block can close (phase < W at entry)."""
+    W = int_periods_min * 1023 * TWO32
+    return (n_samples * code_step_max) // W + 2
+
+
+class Plan:
+    """A plan plus the device buffers one call needs (torch tensors on the plan's device)."""
+
+    def __init__(self, ctx: int, fmt: int, carrier: int, cfgs: np.ndarray, device=None):
+        import torch
+
+        self.torch = torch
+        self.device = device or torch.device("cuda", torch.cuda.current_device())
+        self.cfgs = np.ascontiguousarray(cfgs, dtype=CHAN_CFG)
+        self.fmt, self.carrier = fmt, carrier
+        self.handle = gc_plan_create(ctx, fmt, carrier, self.cfgs)
+        self.tap_stride, self.n_chan = gc_plan_info(self.handle)
+
+    def close(self):
+        if self.handle:
+            gc_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def states_to_device(self, states: np.ndarray):
+        b = np.ascontiguousarray(states, dtype=CHAN_STATE).view(np.uint8)
+        return self.torch.from_numpy(b.copy()).to(self.device)
+
+    @staticmethod
+    def states_from_device(t) -> np.ndarray:
+        return t.cpu().numpy().view(CHAN_STATE).copy()
+
+    def outputs(self, max_dumps: int):
+        torch = self.torch
+        dt = torch.int32 if self.carrier == GC_CARRIER_LUT else torch.float32
+        out = torch.zeros((self.n_chan, max_dumps, self.tap_stride, 2), dtype=dt, device=self.device)
+        dump_n = torch.zeros((self.n_chan, max_dumps), dtype=torch.int32, device=self.device)
+        n_dumps = torch.zeros(self.n_chan, dtype=torch.int32, device=self.device)
+        status = torch.zeros(self.n_chan, dtype=torch.int32, device=self.device)
+        return out, dump_n, n_dumps, status
+
+    def correlate(self, samples, n_samples: int, state, out, dump_n, n_dumps, status,
+                  stream=None):
+        max_dumps = out.shape[1]
+        rc = gc_correlate(self.handle, samples, n_samples, state, out, dump_n, n_dumps, status,
+                          max_dumps, stream if stream is not None
+                          else self.torch.cuda.current_stream(self.device))
+        _check(rc, "gc_correlate")

@@ -1,0 +1,212 @@
+"""GPU parity: the HIP path against the CPU oracle, through the C ABI.
+
+Integer (LUT) path: bit-exact int32 dumps, dump sample counts and final NCO
+state.  FP32 carrier path: |P| within 1e-5 * max(|P_ref|, 3 sigma) of the
+FP64 oracle (sigma = noise std of the dump component).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import (TWO32, assert_exact, block_bytes, c10_check, run_library, run_oracle)
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+MAXW = {0: 128 * 24, 1: 128 * 34, 2: 3 * 24}
+
+
+@pytest.fixture(scope="module")
+def g():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1907_00463_amd import gnsscorr
+    return gnsscorr
+
+
+@pytest.fixture(scope="module")
+def ctx(g):
+    c = g.gc_create(0)
+    yield c
+    g.gc_destroy(c)
+
+
+def _random_channels(g, rng, fmt, n_chan, taps_kind="random"):
+    cfgs = np.zeros(n_chan, g.CHAN_CFG)
+    states = np.zeros(n_chan, g.CHAN_STATE)
+    for i in range(n_chan):
+        T = int(rng.choice([1, 2, 4, 20]))
+        if taps_kind == "epl":
+            taps = np.array([1 << 31, 0, -(1 << 31)], np.int64)
+        else:
+            K = int(rng.integers(1, 9))
+            taps = rng.integers(-3 * TWO32, 3 * TWO32, size=K, dtype=np.int64)
+            taps[: K // 2] &= ~np.int64((1 << 31) - 1)  # some on half-chip grid
+        cfgs[i] = g.make_cfg(int(rng.integers(1, 33)), taps, T)
+        W = T * 1023 * TWO32
+        min_step = (W * MAXW[fmt]) // (2 ** 31 - 1) + 1
+        step = int(rng.integers(max(min_step, TWO32 // 40), 1 << 31))
+        states[i]["code_step"] = step
+        states[i]["code_phase"] = int(rng.integers(0, W))
+        states[i]["carr_phase"] = int(rng.integers(0, TWO32))
+        states[i]["carr_step"] = int(rng.integers(0, TWO32))
+        states[i]["carr_phase_f"] = float(rng.random())
+        states[i]["carr_freq_f"] = float(rng.uniform(-0.5, 0.5))
+    return cfgs, states
+
+
+def _random_blocks(rng, fmt, lens):
+    return [rng.integers(0, 256, size=block_bytes(fmt, n), dtype=np.uint8) for n in lens]
+
+
+def test_code_tables_equal_oracle(g, ctx):
+    for prn in range(1, 33):
+        assert np.array_equal(g.gc_code_table(ctx, prn), oracle.ca_code(prn)), prn
+
+
+@pytest.mark.parametrize("fmt", [0, 1, 2])
+@pytest.mark.parametrize("seed", range(4))
+def test_random_blocks_bit_exact(g, ctx, fmt, seed):
+    rng = np.random.default_rng(1000 * fmt + seed)
+    cfgs, states = _random_channels(g, rng, fmt, int(rng.integers(1, 6)))
+    lens = [int(rng.integers(1, 70000)), int(rng.integers(0, 3)) * 4, int(rng.integers(1, 90000))]
+    if fmt == 2:
+        lens = [n - n % 4 for n in lens]
+    blocks = _random_blocks(rng, fmt, lens)
+    lib, lst = run_library(torch, ctx, fmt, g.GC_CARRIER_LUT, cfgs, states, blocks, lens)
+    orc, ost = run_oracle(fmt, cfgs, states, blocks, lens)
+    assert_exact(lib, lst, orc, ost, cfgs)
+
+
+@pytest.mark.parametrize("fmt", [0, 1, 2])
+def test_epl_many_short_dumps_bit_exact(g, ctx, fmt):
+    # T = 1, 2 samples per chip: many windows per tile, windows straddling tiles
+    rng = np.random.default_rng(77 + fmt)
+    cfgs, states = _random_channels(g, rng, fmt, 3, taps_kind="epl")
+    cfgs["int_periods"] = 1
+    for i in range(3):
+        states[i]["code_step"] = (1 << 31) - int(rng.integers(1, 1000))
+        states[i]["code_phase"] = int(rng.integers(0, 1023 * TWO32))
+    lens = [50000, 12345 * 4]
+    blocks = _random_blocks(rng, fmt, lens)
+    lib, lst = run_library(torch, ctx, fmt, g.GC_CARRIER_LUT, cfgs, states, blocks, lens)
+    orc, ost = run_oracle(fmt, cfgs, states, blocks, lens)
+    assert_exact(lib, lst, orc, ost, cfgs)
+
+
+def test_block_ending_on_a_window_boundary(g, ctx):
+    cfgs = np.zeros(1, g.CHAN_CFG)
+    cfgs[0] = g.make_cfg(5, [1 << 31, 0, -(1 << 31)], 1)
+    states = np.zeros(1, g.CHAN_STATE)
+    states[0]["code_step"] = TWO32 // 4
+    states[0]["carr_step"] = 123456789
+    rng = np.random.default_rng(5)
+    lens = [4092, 4092, 100, 3992]
+    blocks = _random_blocks(rng, 0, lens)
+    lib, lst = run_library(torch, ctx, 0, g.GC_CARRIER_LUT, cfgs, states, blocks, lens)
+    orc, ost = run_oracle(0, cfgs, states, blocks, lens)
+    assert [int(r[2][0]) for r in lib] == [1, 1, 0, 1]
+    assert_exact(lib, lst, orc, ost, cfgs)
+
+
+def test_state_refusals_leave_channels_untouched(g, ctx):
+    cfgs = np.zeros(4, g.CHAN_CFG)
+    for i in range(4):
+        cfgs[i] = g.make_cfg(i + 1, [0], 20 if i == 1 else 1)
+    states = np.zeros(4, g.CHAN_STATE)
+    states["code_step"] = TWO32 // 4
+    states[0]["code_phase"] = 1023 * TWO32          # >= W: EINVAL
+    states[1]["code_step"] = TWO32 // 40            # 20 periods at 40 spc: int32 bound
+    states[2]["code_step"] = (1 << 31) - 1          # fine, but too many dumps for max_dumps
+    states[3]["code_step"] = TWO32 // 4             # fine
+    states["acc"][:, 0, 0] = 17
+    rng = np.random.default_rng(9)
+    n = 3 * 2046 * 2
+    blocks = _random_blocks(rng, 0, [n])
+    lib, lst = run_library(torch, ctx, 0, g.GC_CARRIER_LUT, cfgs, states, blocks, [n], max_dumps=3)
+    out, dump_n, n_dumps, status = lib[0]
+    assert list(status) == [g.GC_EINVAL, g.GC_ERANGE, g.GC_ENOSPC, g.GC_OK]
+    assert list(n_dumps[:3]) == [0, 0, 0]
+    for i in range(3):
+        assert lst[i].tobytes() == states[i].tobytes()
+    assert not out[:3].any() and not dump_n[:3].any()
+    orc, ost = run_oracle(0, cfgs[3:], states[3:], blocks, [n])
+    assert int(n_dumps[3]) == len(orc[0][0][0])
+    assert np.array_equal(out[3, : n_dumps[3], :1].astype(np.int64), orc[0][0][0])
+
+
+def test_chunking_invariance_on_gpu(g, ctx):
+    rng = np.random.default_rng(31)
+    fmt = 1
+    cfgs, states = _random_channels(g, rng, fmt, 4, taps_kind="epl")
+    n = 200000
+    buf = rng.integers(0, 256, size=2 * n, dtype=np.uint8)
+    whole, wst = run_library(torch, ctx, fmt, g.GC_CARRIER_LUT, cfgs, states, [buf], [n])
+    cuts = [0, 1, 4095, 4097, 70001, 150000, n]
+    blocks = [buf[2 * a: 2 * b] for a, b in zip(cuts[:-1], cuts[1:])]
+    parts, pst = run_library(torch, ctx, fmt, g.GC_CARRIER_LUT, cfgs, states, blocks,
+                             [b - a for a, b in zip(cuts[:-1], cuts[1:])])
+    for i in range(4):
+        K = int(cfgs[i]["n_taps"])
+        a = np.concatenate([p[0][i, : p[2][i], :K] for p in parts])
+        assert np.array_equal(a, whole[0][0][i, : whole[0][2][i], :K])
+        assert np.array_equal(np.concatenate([p[1][i, : p[2][i]] for p in parts]),
+                              whole[0][1][i, : whole[0][2][i]])
+    # integer state exact; the FP64 carrier phase of the FP32 variant is reduced
+    # mod 1 once per block, so it agrees to fp64 rounding of n*f (~1e-11 cycles here)
+    for f in ("code_phase", "code_step", "carr_phase", "carr_step", "acc_n", "acc"):
+        assert np.array_equal(pst[f], wst[f]), f
+    assert np.allclose(pst["carr_phase_f"], wst["carr_phase_f"], rtol=0, atol=1e-9)
+
+
+# ------------------------------------------------------------------ workloads
+def _cfgs_states_for(g, stream, chans):
+    cfgs = np.zeros(len(chans), g.CHAN_CFG)
+    states = np.zeros(len(chans), g.CHAN_STATE)
+    for i, ch in enumerate(chans):
+        taps = np.array([int(round(t * TWO32)) for t in ch.taps_chips], np.int64)
+        cfgs[i] = g.make_cfg(ch.prn, taps, ch.int_periods)
+        states[i] = g.gc_nco_init(stream.fs, ch.carr_hz, ch.carr_phase0, ch.code_rate,
+                                  ch.code_phase0, ch.int_periods)
+    return cfgs, states
+
+
+def test_single_channel_workload_bit_exact(g, ctx):
+    from paper_1907_00463_amd import synth
+    st, chans, rng = synth.workload_single_channel()
+    buf = synth.synth_samples(st, rng)
+    cfgs, states = _cfgs_states_for(g, st, chans)
+    lib, lst = run_library(torch, ctx, st.fmt, g.GC_CARRIER_LUT, cfgs, states, [buf], [st.n])
+    orc, ost = run_oracle(st.fmt, cfgs, states, [buf], [st.n])
+    assert int(lib[0][2][0]) == 1000
+    assert_exact(lib, lst, orc, ost, cfgs)
+
+
+@pytest.mark.parametrize("fmt", [0, 1, 2])
+def test_fp32_carrier_within_tolerance(g, ctx, fmt):
+    rng = np.random.default_rng(400 + fmt)
+    cfgs, states = _random_channels(g, rng, fmt, 3, taps_kind="epl")
+    cfgs["int_periods"] = 1
+    states["code_phase"] %= np.uint64(1023 * TWO32)
+    lens = [60000, 30000 - (30000 % 4)]
+    blocks = _random_blocks(rng, fmt, lens)
+    lib, lst = run_library(torch, ctx, fmt, g.GC_CARRIER_F32, cfgs, states, blocks, lens)
+    orc, ost = run_oracle(fmt, cfgs, states, blocks, lens, f64=True)
+    worst = 0.0
+    for (out, dump_n, n_dumps, status), (dumps, dns) in zip(lib, orc):
+        assert np.all(status == 0)
+        for i in range(3):
+            nd = int(n_dumps[i])
+            assert nd == len(dumps[i])
+            assert np.array_equal(dump_n[i, :nd], dns[i])
+            if nd == 0:
+                continue
+            ex2 = {0: 128 ** 2 / 3, 1: 2 * 128 ** 2 / 3, 2: 5.0}[fmt]  # E|x|^2 of uniform bytes
+            sigma = np.sqrt(dns[i].astype(np.float64) * ex2 / 2)[:, None]
+            ok, w = c10_check(out[i, :nd, :3].astype(np.float64), dumps[i], sigma)
+            assert ok.all(), w
+            worst = max(worst, w)
+    for i in range(3):
+        assert int(lst[i]["code_phase"]) == ost[i].code_phase
+        assert int(lst[i]["acc_n"]) == ost[i].acc_n
+        assert abs(float(lst[i]["carr_phase_f"]) - ost[i].carr_phase_f) < 1e-9
+    print("worst relative |P| error", worst)
