@@ -14,6 +14,11 @@ namespace gc {
 // One thread steps both 10-stage registers (all ones at the epoch; G1 taps
 // 3,10; G2 taps 2,3,6,8,9,10; output stage 10).  Threads 0..255 fill the
 // carrier table.
+// G2 delay in chips of PRN 1..32 (IS-GPS-200, Table 3-Ia), for the sign tables.
+__constant__ int32_t c_g2_delay_dev[32] = {5,   6,   7,   8,   17,  18,  139, 140, 141, 251, 252,
+                                           254, 255, 256, 257, 258, 469, 470, 471, 472, 473, 474,
+                                           509, 512, 513, 514, 515, 516, 859, 860, 861, 862};
+
 __global__ void k_init_tables(uint32_t* tables) {
     uint32_t* g1 = tables + kTabG1;
     uint32_t* g2 = tables + kTabG2;
@@ -30,6 +35,25 @@ __global__ void k_init_tables(uint32_t* tables) {
             r1 = ((r1 << 1) | f1) & 0x3FF;
             r2 = ((r2 << 1) | f2) & 0x3FF;
         }
+    }
+    if (t < 256) {
+        // 2-bit byte t -> its four samples (codes 0..3 -> -3,-1,+1,+3) as int16
+        for (int h = 0; h < 2; ++h) {
+            uint32_t ex = 0;
+            for (int j = 0; j < 2; ++j) {
+                const int v = 2 * (int)((t >> (2 * (2 * h + j))) & 3) - 3;
+                ex |= (uint32_t)(uint16_t)(int16_t)v << (16 * j);
+            }
+            tables[kTabExpand + 2 * t + h] = ex;
+        }
+    }
+    __syncthreads();
+    // code signs of every PRN, (s, s) as int16 pairs, chips 0..1022 then a
+    // wrapped copy so that runs of chips need no modulo
+    for (int idx = t; idx < 32 * kSignLen; idx += blockDim.x) {
+        const int prn = idx / kSignLen + 1;
+        const int i = (idx % kSignLen) % kCodeLen;
+        tables[kTabSign + idx] = ca_chip(tables, c_g2_delay_dev[prn - 1], i) < 0 ? 0xFFFFFFFFu : 0x00010001u;
     }
     if (t < 256) {
         double ang = 6.283185307179586476925286766559 * ((double)t + 0.5) / 256.0;
@@ -88,8 +112,10 @@ __global__ __launch_bounds__(256) void k_setup(const DevChan* __restrict__ chans
         m.phf0 = st->carr_phase_f;
         m.ff = st->carr_freq_f;
         m.acc_n0 = st->acc_n;
-        m.pad = 0;
         m.m_close = 0;
+        m.path = kPathDirect;
+        m.c_full0 = m.c_full1 = 0;
+        m.head_end = m.tail_beg = 0;
         int32_t s = GC_OK;
         if (m.dp == 0 || m.dp >= (1ull << 31) || m.p0 >= m.window) {
             s = GC_EINVAL;
@@ -103,6 +129,21 @@ __global__ __launch_bounds__(256) void k_setup(const DevChan* __restrict__ chans
             if (carrier == GC_CARRIER_LUT && nmax * maxw > 2147483647ull) s = GC_ERANGE;
             else if (mc > max_dumps) s = GC_ENOSPC;
             else m.m_close = (uint32_t)mc;
+            // whole chips of this block: [c_full0, c_full1); the samples before
+            // and after them are handled by the direct per-sample path
+            m.c_full0 = (m.p0 + 0xFFFFFFFFull) >> 32;
+            m.c_full1 = u_end >> 32;
+            auto chip_start = [&](uint64_t c) -> uint64_t {
+                const uint64_t ph = c << 32;
+                return ph <= m.p0 ? 0 : (ph - m.p0 + m.dp - 1) / m.dp;
+            };
+            const uint64_t he = min(n, chip_start(m.c_full0));
+            uint64_t tb = m.c_full1 > m.c_full0 ? chip_start(m.c_full1) : he;
+            if (tb < he) tb = he;
+            m.head_end = (uint32_t)he;
+            m.tail_beg = (uint32_t)tb;
+            m.path = (c.epl && carrier == GC_CARRIER_LUT && binned_ok(fmt, m.dp) &&
+                      m.c_full1 > m.c_full0) ? kPathBinned : kPathDirect;
         }
         m.status = s;
         metas[ch] = m;

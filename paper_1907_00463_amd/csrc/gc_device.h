@@ -9,7 +9,10 @@ namespace gc {
 constexpr int kTabG1 = 0;     // 32 words: G1 sequence, bit i of word i/32
 constexpr int kTabG2 = 32;    // 32 words: G2 sequence
 constexpr int kTabLut = 64;   // 256 words: (cos low 16 | sin high 16), int16 each
-constexpr int kTabWords = 320;
+constexpr int kTabExpand = 320;  // 512 words: packed 2-bit byte -> its 4 samples as int16 (2 words)
+constexpr int kTabSign = 832;    // 32 PRNs x kSignLen words: chip i -> (s, s) int16, s = +-1
+constexpr int kSignLen = 1023 + 129;  // chip index 0..1022 followed by a wrapped copy
+constexpr int kTabWords = kTabSign + 32 * kSignLen;
 constexpr int kLutAbsSumMax = 34;  // max over l of |cos_l| + |sin_l| at amplitude 24
 
 // Chip i of the C/A code whose G2 delay is d: G1[i] XOR G2[(i - d) mod 1023],
@@ -57,9 +60,34 @@ __device__ __forceinline__ void wipe(T xi, T xq, T c, T s, T& wi, T& wq) {
     }
 }
 
+// Binned E/P/L form: tile geometry and the per-channel condition on the code
+// step.  A chip must fit in the staged margin, and a half-chip bin sum must
+// fit int16 (bin length <= q + 1 samples, q = floor(2^31 / dp)).
+constexpr int kEplMarginSamples = 128;
+__device__ __forceinline__ bool binned_ok(int fmt, uint64_t dp) {
+    if (dp == 0 || dp >= (1ull << 31)) return false;
+    if (dp * (kEplMarginSamples - 1) < (1ull << 32)) return false;
+    const uint64_t q = (1ull << 31) / dp;
+    const uint64_t maxw = fmt == GC_I8_REAL ? 128ull * GC_LUT_AMP : 3ull * GC_LUT_AMP;
+    return (q + 1) * maxw <= 32767ull;
+}
+
 // First sample index of window m (m >= 1): ceil((m*W - p0) / dp).
 __device__ __forceinline__ uint64_t window_start(uint64_t m, uint64_t W, uint64_t p0, uint64_t dp) {
     return m == 0 ? 0 : (m * W - p0 + dp - 1) / dp;
+}
+
+// Wavefront sum of v over all 64 lanes, returned to every lane: an
+// inclusive scan with DPP row shifts (within 16-lane rows) and row
+// broadcasts (across rows) leaves the total in lane 63.
+__device__ __forceinline__ int wave_total_dpp(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
 // Wavefront sum (64 lanes) with DPP-backed cross-lane moves.

@@ -1,0 +1,433 @@
+// gc_epl.hip -- binned early/prompt/late correlator for real int8 and 2-bit
+// sample streams (integer carrier path).
+//
+// The replicas of E, P and L (offsets +1/2, 0, -1/2 chip) are constant over
+// each half chip of code phase, so the kernel first sums the wiped-off
+// samples of every half chip (a "bin"), then applies the three taps' code
+// signs once per bin:
+//   bin 0 of chip c (phase in [c, c+1/2)):   E, P use C[c],   L uses C[c-1]
+//   bin 1 of chip c (phase in [c+1/2, c+1)): E uses C[c+1],   P, L use C[c]
+// This is the same sum as the per-sample definition, regrouped; all
+// arithmetic is integer, so the result is identical bit for bit.
+//
+// Work layout (one persistent block per CU):
+//   * a tile of kTile samples is staged once in LDS as int16 (2-bit codes
+//     expanded) and read by every channel of the plan; a packed multiply
+//     picks either sample of a dword through its operand select, so samples
+//     need no unpacking;
+//   * per channel, the chips whose first sample lies in the tile are split
+//     into 512 runs of consecutive whole chips, one per lane (~90 samples,
+//     an odd number of LDS dwords apart, so lanes hit different banks);
+//   * a lane walks its run sample by sample: the carrier phase advances by
+//     one add, the sin/cos entry comes from a per-lane copy of the table in
+//     LDS (address = one v_perm, no bank conflicts), and one packed int16
+//     multiply-add folds x*(c, s) into the bin sum; bin lengths come from an
+//     exact integer Bresenham step on the code phase (q or q+1 samples);
+//   * lanes keep E/P/L sums in registers, flush them with atomics at a dump
+//     boundary inside their run (rare), and at the end of the run the wave
+//     sums lanes of the same dump with DPP and adds once per dump.
+// Chips cut by the ends of the block, and channels whose steps do not fit
+// the binned form, go through a direct per-sample path on the same tile.
+#include "gc_device.h"
+
+namespace gc {
+
+namespace {
+
+constexpr int kThreads = 512;
+constexpr int kRun = 90;                      // samples per lane per channel (45 LDS dwords: odd)
+constexpr int kTile = kThreads * kRun;        // 46080 samples per tile
+constexpr int kMargin = kEplMarginSamples;    // chips that start in a tile end within this
+constexpr int kXSamples = kTile + kMargin;    // staged as int16
+constexpr int kLutWords = 256 * 64;           // entry l of lane L at word l*64 + L
+constexpr int kLdsBytes = kLutWords * 4 + kXSamples * 2;  // table at LDS offset 0
+constexpr uint32_t kPermSel = 0x0C0C0700u;    // byte1 = phase[31:24], byte0 = lane*4
+
+typedef short short2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ short2_t as_s2(uint32_t v) { return __builtin_bit_cast(short2_t, v); }
+__device__ __forceinline__ uint32_t as_u32(short2_t v) { return __builtin_bit_cast(uint32_t, v); }
+
+// One sample: x * (c, s) accumulated into the packed bin sum (I = x*c, Q = x*s;
+// the Q sign of the wipe-off is applied when the bin is folded).
+__device__ __forceinline__ short2_t mac_sample(short2_t a, short x, uint32_t phi, uint32_t lane4,
+                                               const uint8_t* lut_bytes) {
+    const uint32_t off = __builtin_amdgcn_perm(phi, lane4, kPermSel);
+    const short2_t cs = as_s2(*reinterpret_cast<const uint32_t*>(lut_bytes + off));
+    const short2_t xx = {x, x};
+    return xx * cs + a;
+}
+
+// Sum over one bin of len samples starting at phase phi, len in {Q-1, Q, Q+1}
+// (Q > 0: straight-line code, the last two samples weighted by 0 or 1 so that
+// no branch splits the chip body), or any len (Q == 0).  The bin's phase
+// advance is len*dphi, applied by the caller.
+template <int Q>
+__device__ __forceinline__ short2_t bin_sum(const short* __restrict__ xs, uint32_t phi,
+                                            uint32_t dphi, uint32_t lane4, const uint8_t* lut,
+                                            uint32_t len) {
+    short2_t a = {0, 0};
+    if constexpr (Q > 0) {
+#pragma unroll
+        for (int j = 0; j < Q - 1; ++j) a = mac_sample(a, xs[j], phi + j * dphi, lane4, lut);
+        const short x1 = len >= (uint32_t)Q ? xs[Q - 1] : (short)0;
+        a = mac_sample(a, x1, phi + (Q - 1) * dphi, lane4, lut);
+        const short x2 = len > (uint32_t)Q ? xs[Q] : (short)0;
+        a = mac_sample(a, x2, phi + Q * dphi, lane4, lut);
+    } else {
+        for (uint32_t j = 0; j < len; ++j) a = mac_sample(a, xs[j], phi + j * dphi, lane4, lut);
+    }
+    return a;
+}
+
+struct Dest {
+    int32_t* out;
+    gc_chan_state* st;
+    uint64_t row0;        // ch * max_dumps
+    int tap_stride;
+    uint32_t m_close;
+    __device__ __forceinline__ int32_t* at(uint32_t w, int slot, int comp) const {
+        if (w < m_close) return out + ((row0 + w) * tap_stride + slot) * 2 + comp;
+        return &st->acc[slot][comp];
+    }
+};
+
+// E/P/L sums of one lane (I, Q for each).  For 2-bit input they live as
+// packed int16 (|sum| <= run length * 72 < 2^15); for int8 as int32.
+template <int FMT>
+struct EplAcc;
+
+template <>
+struct EplAcc<GC_I2_REAL> {
+    short2_t e, p, l;
+    __device__ __forceinline__ void zero() { e = p = l = short2_t{0, 0}; }
+    __device__ __forceinline__ void fold0(short2_t a, uint32_t mp, uint32_t mc, uint32_t) {
+        e = a * as_s2(mc) + e;
+        p = a * as_s2(mc) + p;
+        l = a * as_s2(mp) + l;
+    }
+    __device__ __forceinline__ void fold1(short2_t a, uint32_t, uint32_t mc, uint32_t mn) {
+        e = a * as_s2(mn) + e;
+        p = a * as_s2(mc) + p;
+        l = a * as_s2(mc) + l;
+    }
+    __device__ __forceinline__ void get(int v[6]) const {
+        v[0] = e.x; v[1] = e.y; v[2] = p.x; v[3] = p.y; v[4] = l.x; v[5] = l.y;
+    }
+};
+
+template <>
+struct EplAcc<GC_I8_REAL> {
+    int ei, eq, pi, pq, li, lq;
+    __device__ __forceinline__ void zero() { ei = eq = pi = pq = li = lq = 0; }
+    __device__ __forceinline__ void fold0(short2_t a, uint32_t mp, uint32_t mc, uint32_t) {
+        const int ai = a.x, aq = a.y;
+        const int sc = (int)(short)(mc & 0xFFFF), sp = (int)(short)(mp & 0xFFFF);
+        ei += ai * sc; eq += aq * sc;
+        pi += ai * sc; pq += aq * sc;
+        li += ai * sp; lq += aq * sp;
+    }
+    __device__ __forceinline__ void fold1(short2_t a, uint32_t, uint32_t mc, uint32_t mn) {
+        const int ai = a.x, aq = a.y;
+        const int sc = (int)(short)(mc & 0xFFFF), sn = (int)(short)(mn & 0xFFFF);
+        ei += ai * sn; eq += aq * sn;
+        pi += ai * sc; pq += aq * sc;
+        li += ai * sc; lq += aq * sc;
+    }
+    __device__ __forceinline__ void get(int v[6]) const {
+        v[0] = ei; v[1] = eq; v[2] = pi; v[3] = pq; v[4] = li; v[5] = lq;
+    }
+};
+
+// Lane-private atomics of one run's sums (dump boundary inside a run).
+template <int FMT>
+__device__ __forceinline__ void flush_lane(const EplAcc<FMT>& acc, const Dest& d, uint32_t w,
+                                           const DevChan& c) {
+    int v[6];
+    acc.get(v);
+    const int slot[3] = {c.slot_e, c.slot_p, c.slot_l};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        atomicAdd(d.at(w, slot[k], 0), v[2 * k]);
+        atomicAdd(d.at(w, slot[k], 1), -v[2 * k + 1]);  // wipe-off Q = -x*s
+    }
+}
+
+// Binned run of one lane over chips [c, c + K) whose samples start at tile
+// offset nb with code-phase overshoot e past the chip start.
+template <int FMT, int Q>
+__device__ __forceinline__ void epl_run(const short* __restrict__ sx, const uint8_t* lut,
+                                     uint32_t lane4, uint32_t nb, uint32_t phi, uint32_t dphi,
+                                     uint32_t e, uint32_t dp, uint32_t q, uint32_t r, uint32_t c,
+                                     uint32_t K, uint32_t Kmax, uint32_t span,
+                                     const uint32_t* __restrict__ sgn, const Dest d,
+                                     const DevChan& ch) {
+    EplAcc<FMT> acc;
+    acc.zero();
+    // window of chip c: floor(c / span), float estimate corrected exactly
+    uint32_t w = (uint32_t)max(0.0f, (float)c * (1.0f / (float)span) - 1.0f);
+    while ((w + 1) * span <= c) ++w;
+    uint32_t wnext = (w + 1) * span;
+    uint32_t mp = sgn[0], mc = sgn[1], mn = sgn[2];
+    const bool active = K > 0;
+    for (uint32_t k = 0; k < Kmax; ++k) {
+        if (k < K) {
+            if (c == wnext) {  // a dump closes before this chip
+                flush_lane<FMT>(acc, d, w, ch);
+                acc.zero();
+                w += 1;
+                wnext += span;
+            }
+            const uint32_t mnn = sgn[k + 3];
+            // bin 0: phase [c, c + 1/2)
+            bool lt = e < r;
+            uint32_t len = q + (lt ? 1u : 0u);
+            e = lt ? e + dp - r : e - r;
+            short2_t a = bin_sum<Q>(sx + nb, phi, dphi, lane4, lut, len);
+            nb += len;
+            phi += len * dphi;
+            acc.fold0(a, mp, mc, mn);
+            // bin 1: phase [c + 1/2, c + 1)
+            lt = e < r;
+            len = q + (lt ? 1u : 0u);
+            e = lt ? e + dp - r : e - r;
+            a = bin_sum<Q>(sx + nb, phi, dphi, lane4, lut, len);
+            nb += len;
+            phi += len * dphi;
+            acc.fold1(a, mp, mc, mn);
+            mp = mc;
+            mc = mn;
+            mn = mnn;
+            c += 1;
+        }
+    }
+    // dump of the lane's last chip; lanes of one wave hold consecutive chips,
+    // so equal dumps are contiguous: sum each group once
+    int v[6];
+    acc.get(v);
+    const int slot[3] = {ch.slot_e, ch.slot_p, ch.slot_l};
+    uint64_t pending = __ballot(active);
+    while (pending) {
+        const int first = __ffsll((unsigned long long)pending) - 1;
+        const uint32_t wsel = __builtin_amdgcn_readlane(w, first);
+        const bool mine = active && w == wsel;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const int t = wave_total_dpp(mine ? v[k] : 0);
+            if ((int)(threadIdx.x & 63) == first)
+                atomicAdd(d.at(wsel, slot[k >> 1], k & 1), (k & 1) ? -t : t);
+        }
+        pending &= ~__ballot(mine);
+    }
+}
+
+// Direct per-sample form over tile offsets [lo, hi) for up to 4 taps (chips
+// cut by the block ends, and channels the binned form does not cover).
+__device__ __forceinline__ void direct_range(const short* __restrict__ sx, const uint8_t* lut,
+                                             uint32_t lane4, uint64_t t0, uint32_t lo, uint32_t hi,
+                                             const DevMeta& m, const DevChan& ch,
+                                             const uint32_t* __restrict__ sgn_prn, const Dest d) {
+    if (lo >= hi) return;
+    const uint64_t W = m.window;
+    const uint64_t wa = (m.p0 + (t0 + lo) * m.dp) / W;
+    const uint64_t wb = (m.p0 + (t0 + hi - 1) * m.dp) / W;
+    const int nk = ch.n_taps;
+    for (uint64_t w = wa; w <= wb; ++w) {
+        const uint64_t s_lo = window_start(w, W, m.p0, m.dp);
+        const uint64_t s_hi = window_start(w + 1, W, m.p0, m.dp);
+        const uint32_t a = (uint32_t)max((uint64_t)lo, s_lo > t0 ? s_lo - t0 : 0);
+        const uint32_t b = (uint32_t)min((uint64_t)hi, s_hi - t0);
+        int acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (uint32_t i = a + threadIdx.x; i < b; i += kThreads) {
+            const uint64_t n = t0 + i;
+            const uint32_t phi = m.phi0 + (uint32_t)n * m.dphi;
+            const uint32_t off = __builtin_amdgcn_perm(phi, lane4, kPermSel);
+            const uint32_t e = *reinterpret_cast<const uint32_t*>(lut + off);
+            int c, s;
+            lut_cs(e, c, s);
+            const int x = sx[i];
+            const int wi = x * c, wq = -(x * s);
+            const uint64_t u = m.p0 + n * m.dp;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (k < nk) {
+                    const int64_t v = (int64_t)u + ch.taps[k];
+                    int32_t chip = (int32_t)(v >> 32) % kCodeLen;
+                    if (chip < 0) chip += kCodeLen;
+                    const int r = (int)(short)(sgn_prn[chip] & 0xFFFF);
+                    acc[2 * k] += wi * r;
+                    acc[2 * k + 1] += wq * r;
+                }
+            }
+        }
+        for (int k = 0; k < 2 * nk; ++k) {
+            const int t = wave_total_dpp(acc[k]);
+            if ((threadIdx.x & 63) == 0 && t != 0) atomicAdd(d.at((uint32_t)w, k >> 1, k & 1), t);
+        }
+    }
+}
+
+template <int FMT>
+__device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, uint64_t n,
+                                           uint64_t t0, short* sx, const uint32_t* tables) {
+    uint2* dst = reinterpret_cast<uint2*>(sx);  // 4 samples per 8 bytes
+    if constexpr (FMT == GC_I2_REAL) {
+        // t0 is a multiple of 4: byte t0/4 + i holds tile samples 4i .. 4i+3
+        const uint64_t nbytes = (n + 3) / 4;
+        const uint64_t b0 = t0 / 4;
+        for (int i = threadIdx.x; i < kXSamples / 4; i += kThreads) {
+            const uint64_t b = b0 + i;
+            uint2 o = {0u, 0u};
+            if (b < nbytes) {
+                const uint32_t* e = tables + kTabExpand + 2 * samples[b];  // 4 x int16
+                o.x = e[0];
+                o.y = e[1];
+            }
+            dst[i] = o;
+        }
+    } else {
+        for (int i = threadIdx.x; i < kXSamples / 4; i += kThreads) {
+            const uint64_t b = t0 + 4ull * i;
+            uint32_t v = 0;
+            if (b + 4 <= n) {
+                v = *reinterpret_cast<const uint32_t*>(samples + b);  // t0 % 4 == 0
+            } else {
+                for (int j = 0; j < 4; ++j)
+                    if (b + j < n) v |= (uint32_t)samples[b + j] << (8 * j);
+            }
+            uint2 o;
+            o.x = ((uint32_t)(uint16_t)(int16_t)(int8_t)(v & 0xFF)) |
+                  ((uint32_t)(uint16_t)(int16_t)(int8_t)((v >> 8) & 0xFF) << 16);
+            o.y = ((uint32_t)(uint16_t)(int16_t)(int8_t)((v >> 16) & 0xFF)) |
+                  ((uint32_t)(uint16_t)(int16_t)(int8_t)(v >> 24) << 16);
+            dst[i] = o;
+        }
+    }
+}
+
+template <int FMT>
+__global__ __launch_bounds__(kThreads) void k_epl(const uint8_t* __restrict__ samples, uint64_t n,
+                                                  const DevChan* __restrict__ chans,
+                                                  const DevMeta* __restrict__ metas,
+                                                  gc_chan_state* __restrict__ state,
+                                                  int32_t* __restrict__ out, int tap_stride,
+                                                  uint32_t max_dumps,
+                                                  const uint32_t* __restrict__ tables, int n_chan,
+                                                  uint32_t n_tiles) {
+    // one LDS block: the per-lane carrier tables at offset 0 (so the v_perm
+    // result is the address itself), then the staged samples
+    __shared__ __attribute__((aligned(16))) uint8_t s_lds[kLdsBytes];
+    uint32_t* s_lut = reinterpret_cast<uint32_t*>(s_lds);
+    short* s_x = reinterpret_cast<short*>(s_lds + kLutWords * 4);
+    const int tid = threadIdx.x;
+    const uint32_t lane = tid & 63;
+    const uint32_t lane4 = lane * 4;
+    const uint8_t* lut = s_lds;
+    for (int i = tid; i < kLutWords; i += kThreads) s_lut[i] = tables[kTabLut + (i >> 6)];
+
+    for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const uint64_t t0 = (uint64_t)tile * kTile;
+        const uint64_t t1 = min(n, t0 + kTile);
+        __syncthreads();
+        stage_tile<FMT>(samples, n, t0, s_x, tables);
+        __syncthreads();
+        for (int chn = 0; chn < n_chan; ++chn) {
+            const DevMeta m = metas[chn];
+            if (m.status != GC_OK) continue;
+            const DevChan& ch = chans[chn];
+            const Dest d{out, state + chn, (uint64_t)chn * max_dumps, tap_stride, m.m_close};
+            const uint32_t* sgn_prn = tables + kTabSign + (ch.prn - 1) * kSignLen;
+            const uint32_t tl = (uint32_t)(t1 - t0);
+            if (m.path != kPathBinned) {
+                direct_range(s_x, lut, lane4, t0, 0, tl, m, ch, sgn_prn, d);
+                continue;
+            }
+            // block-edge samples outside whole chips
+            {
+                const uint64_t he = m.head_end, tb = m.tail_beg;
+                if (he > t0) direct_range(s_x, lut, lane4, t0, 0, (uint32_t)min(he, t1) - (uint32_t)t0,
+                                          m, ch, sgn_prn, d);
+                if (t1 > tb) direct_range(s_x, lut, lane4, t0, (uint32_t)(max(tb, t0) - t0), tl, m,
+                                          ch, sgn_prn, d);
+            }
+            // whole chips whose first sample lies in [t0, t1)
+            const uint64_t u0 = m.p0 + t0 * m.dp;
+            const uint64_t u1 = m.p0 + t1 * m.dp;
+            uint64_t ca = (u0 + 0xFFFFFFFFull) >> 32;
+            uint64_t cb = (u1 + 0xFFFFFFFFull) >> 32;
+            if (ca < m.c_full0) ca = m.c_full0;
+            if (cb > m.c_full1) cb = m.c_full1;
+            if (cb <= ca) continue;
+            const uint32_t N = (uint32_t)(cb - ca);
+            const uint32_t k0 = (uint32_t)(((uint64_t)tid * N) / kThreads);
+            const uint32_t k1 = (uint32_t)(((uint64_t)(tid + 1) * N) / kThreads);
+            const uint32_t K = k1 - k0;
+            const uint32_t Kmax = (N + kThreads - 1) / kThreads;
+            const uint32_t c = (uint32_t)(ca + k0);
+            const uint32_t dp = (uint32_t)m.dp;
+            const float inv_dp = 1.0f / (float)dp;
+            uint32_t nrel = 0, e = 0, phi = 0;
+            if (K > 0) {
+                // first sample of chip c: ceil((c*2^32 - u0) / dp), estimated with
+                // a float reciprocal (D < 2^47, so the estimate is within a few
+                // samples) and made exact with integer checks
+                const uint64_t D = ((uint64_t)c << 32) - u0;
+                const float df = (float)(uint32_t)(D >> 32) * 4294967296.0f + (float)(uint32_t)D;
+                uint64_t nr = (uint64_t)(uint32_t)max(0.0f, df * inv_dp - 2.0f);
+                while (nr * dp < D) ++nr;
+                nrel = (uint32_t)nr;
+                e = (uint32_t)(nr * dp - D);
+                phi = m.phi0 + (uint32_t)(t0 + nrel) * m.dphi;
+            }
+            const uint32_t q = (uint32_t)((1ull << 31) / dp);
+            const uint32_t r = (uint32_t)((1ull << 31) - (uint64_t)q * dp);
+            const uint32_t span = (uint32_t)(m.window >> 32);
+            const uint32_t* sgn = sgn_prn + (c + kCodeLen - 1) % kCodeLen;
+#define GC_RUN(QQ)                                                                          \
+    epl_run<FMT, QQ>(s_x, lut, lane4, nrel, phi, m.dphi, e, dp, q, r, c, K, Kmax, span, sgn, \
+                     d, ch)
+            switch (q) {
+                case 1: GC_RUN(2); break;
+                case 2: GC_RUN(3); break;
+                case 3: GC_RUN(4); break;
+                case 4: GC_RUN(5); break;
+                case 7: GC_RUN(8); break;
+                case 8: GC_RUN(9); break;
+                case 9: GC_RUN(10); break;
+                case 10: GC_RUN(11); break;
+                default: GC_RUN(0); break;
+            }
+#undef GC_RUN
+        }
+    }
+}
+
+}  // namespace
+
+int epl_blocks_per_device(int device) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+        cus = 256;
+    return cus > 0 ? cus : 256;
+}
+
+hipError_t launch_epl(const uint8_t* samples, uint64_t n, int fmt, const DevChan* chans,
+                      const DevMeta* meta, gc_chan_state* state, int n_chan, int32_t* out,
+                      int tap_stride, uint32_t max_dumps, const uint32_t* tables, int grid,
+                      hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const uint32_t n_tiles = (uint32_t)((n + kTile - 1) / kTile);
+    const int g = (int)min((uint32_t)grid, n_tiles);
+    if (fmt == GC_I2_REAL) {
+        hipLaunchKernelGGL((k_epl<GC_I2_REAL>), dim3(g), dim3(kThreads), 0, s, samples, n, chans,
+                           meta, state, out, tap_stride, max_dumps, tables, n_chan, n_tiles);
+    } else if (fmt == GC_I8_REAL) {
+        hipLaunchKernelGGL((k_epl<GC_I8_REAL>), dim3(g), dim3(kThreads), 0, s, samples, n, chans,
+                           meta, state, out, tap_stride, max_dumps, tables, n_chan, n_tiles);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gc

@@ -20,6 +20,8 @@ struct DevChan {
     int32_t int_periods;
     int32_t g2_delay;      // IS-GPS-200 Table 3-Ia G2 delay of this PRN, chips
     uint64_t window;       // W = int_periods * 1023 * 2^32
+    int32_t epl;           // 1: taps are early/prompt/late at +1/2, 0, -1/2 chip
+    int32_t slot_e, slot_p, slot_l;  // output tap slots of E, P, L when epl
     int64_t taps[GC_MAX_TAPS];
 };
 
@@ -36,8 +38,15 @@ struct DevMeta {
     uint32_t m_close;      // windows closed by this block (dumps emitted)
     int32_t status;        // gc_status of this channel for this call
     uint32_t acc_n0;       // samples already in the open dump
-    uint32_t pad;
+    int32_t path;          // kPathDirect or kPathBinned (chosen per call from the steps)
+    uint64_t c_full0;      // first chip whose samples all lie in this block
+    uint64_t c_full1;      // one past the last such chip
+    uint32_t head_end;     // samples [0, head_end) precede chip c_full0
+    uint32_t tail_beg;     // samples [tail_beg, n) follow chip c_full1 - 1
 };
+
+constexpr int32_t kPathDirect = 0;
+constexpr int32_t kPathBinned = 1;
 
 // Kernel launch entry points (defined in the .hip files, called by the runtime).
 hipError_t launch_make_tables(uint32_t* d_tables, hipStream_t s);
@@ -46,6 +55,11 @@ hipError_t launch_setup(const DevChan* chans, DevMeta* meta, gc_chan_state* stat
                         uint64_t n_samples, int fmt, int carrier, uint32_t max_dumps,
                         void* out, int tap_stride, uint32_t* dump_n, uint32_t* n_dumps,
                         int32_t* status, hipStream_t s);
+hipError_t launch_epl(const uint8_t* samples, uint64_t n_samples, int fmt, const DevChan* chans,
+                      const DevMeta* meta, gc_chan_state* state, int n_chan, int32_t* out,
+                      int tap_stride, uint32_t max_dumps, const uint32_t* d_tables, int grid,
+                      hipStream_t s);
+int epl_blocks_per_device(int device);
 hipError_t launch_generic(const uint8_t* samples, uint64_t n_samples, int fmt, int carrier,
                           const DevChan* chans, const DevMeta* meta, gc_chan_state* state,
                           int n_chan, int max_taps, void* out, int tap_stride,

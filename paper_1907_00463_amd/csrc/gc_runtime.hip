@@ -24,6 +24,8 @@ struct gc_plan {
     int max_taps;
     gc::DevChan* d_chans;
     gc::DevMeta* d_meta;
+    int use_epl;      // all channels <= 4 taps, real int8 / 2-bit, integer carrier
+    int epl_grid;     // persistent blocks of the binned kernel
     std::vector<hipEvent_t> ev_start, ev_stop;  // timing slots (empty: off)
     std::vector<uint8_t> ev_used;
     uint64_t calls;
@@ -178,6 +180,18 @@ gc_status gc_plan_create(gc_ctx* ctx, gc_format fmt, gc_carrier carrier, const g
             if (t <= -(int64_t(1) << 40) || t >= (int64_t(1) << 40)) return GC_EINVAL;
             d.taps[k] = t;
         }
+        // early / prompt / late at +1/2, 0, -1/2 chip, in any order
+        d.epl = 0;
+        d.slot_e = d.slot_p = d.slot_l = -1;
+        if (c.n_taps == 3) {
+            const int64_t h = int64_t(1) << 31;
+            for (int k = 0; k < 3; ++k) {
+                if (c.tap_q32[k] == h) d.slot_e = k;
+                else if (c.tap_q32[k] == 0) d.slot_p = k;
+                else if (c.tap_q32[k] == -h) d.slot_l = k;
+            }
+            d.epl = d.slot_e >= 0 && d.slot_p >= 0 && d.slot_l >= 0;
+        }
         if (c.n_taps > max_taps) max_taps = c.n_taps;
     }
     DeviceGuard g(ctx->device);
@@ -192,6 +206,9 @@ gc_status gc_plan_create(gc_ctx* ctx, gc_format fmt, gc_carrier carrier, const g
     p->d_chans = nullptr;
     p->d_meta = nullptr;
     p->calls = 0;
+    p->use_epl = carrier == GC_CARRIER_LUT && (fmt == GC_I8_REAL || fmt == GC_I2_REAL) &&
+                 max_taps <= 4;
+    p->epl_grid = gc::epl_blocks_per_device(ctx->device);
     hipError_t e = hipMalloc(&p->d_chans, sizeof(gc::DevChan) * (size_t)n_chan);
     if (e == hipSuccess) e = hipMalloc(&p->d_meta, sizeof(gc::DevMeta) * (size_t)n_chan);
     if (e == hipSuccess)
@@ -278,10 +295,17 @@ gc_status gc_correlate(gc_plan* plan, const void* samples, uint64_t n_samples,
                                     dump_n, n_dumps, status, s);
     const size_t slot = plan->ev_stop.empty() ? 0 : (size_t)(plan->calls % plan->ev_stop.size());
     if (e == hipSuccess && !plan->ev_start.empty()) e = hipEventRecord(plan->ev_start[slot], s);
-    if (e == hipSuccess)
-        e = gc::launch_generic((const uint8_t*)samples, n_samples, plan->fmt, plan->carrier,
-                               plan->d_chans, plan->d_meta, state, plan->n_chan, plan->max_taps,
-                               out, plan->max_taps, max_dumps, plan->ctx->d_tables, s);
+    if (e == hipSuccess) {
+        if (plan->use_epl)
+            e = gc::launch_epl((const uint8_t*)samples, n_samples, plan->fmt, plan->d_chans,
+                               plan->d_meta, state, plan->n_chan, (int32_t*)out, plan->max_taps,
+                               max_dumps, plan->ctx->d_tables, plan->epl_grid, s);
+        else
+            e = gc::launch_generic((const uint8_t*)samples, n_samples, plan->fmt, plan->carrier,
+                                   plan->d_chans, plan->d_meta, state, plan->n_chan,
+                                   plan->max_taps, out, plan->max_taps, max_dumps,
+                                   plan->ctx->d_tables, s);
+    }
     if (e == hipSuccess && !plan->ev_stop.empty()) {
         e = hipEventRecord(plan->ev_stop[slot], s);
         plan->ev_used[slot] = 1;

@@ -210,3 +210,45 @@ def test_fp32_carrier_within_tolerance(g, ctx, fmt):
         assert int(lst[i]["acc_n"]) == ost[i].acc_n
         assert abs(float(lst[i]["carr_phase_f"]) - ost[i].carr_phase_f) < 1e-9
     print("worst relative |P| error", worst)
+
+
+@pytest.mark.parametrize("fs", [4.092e6, 8.184e6, 16.368e6, 20.46e6, 5e6])
+@pytest.mark.parametrize("fmt", [0, 2])
+def test_binned_epl_rates_bit_exact(g, ctx, fs, fmt):
+    # E/P/L channels at the workloads' sample rates, several tiles per block,
+    # dumps of 1, 4 and 20 periods, Doppler of either sign
+    rng = np.random.default_rng(int(fs) % 100000 + fmt)
+    n_chan = 5
+    cfgs = np.zeros(n_chan, g.CHAN_CFG)
+    states = np.zeros(n_chan, g.CHAN_STATE)
+    for i in range(n_chan):
+        T = [1, 4, 20, 1, 4][i]
+        cfgs[i] = g.make_cfg(int(rng.integers(1, 33)), [1 << 31, 0, -(1 << 31)], T)
+        fd = float(rng.uniform(-5000, 5000))
+        states[i] = g.gc_nco_init(fs, fs / 4 + fd, float(rng.random()), 1.023e6 * (1 + fd / 1575.42e6),
+                                  float(rng.uniform(0, 1023 * T)), T)
+    lens = [300000, 123456 * 4]
+    blocks = _random_blocks(rng, fmt, lens)
+    lib, lst = run_library(torch, ctx, fmt, g.GC_CARRIER_LUT, cfgs, states, blocks, lens)
+    orc, ost = run_oracle(fmt, cfgs, states, blocks, lens)
+    assert_exact(lib, lst, orc, ost, cfgs)
+
+
+def test_binned_epl_permuted_taps_and_mixed_channels(g, ctx):
+    # E/P/L given in L, E, P order next to a 2-tap channel (direct path in the same kernel)
+    rng = np.random.default_rng(2024)
+    fs = 16.368e6
+    cfgs = np.zeros(3, g.CHAN_CFG)
+    cfgs[0] = g.make_cfg(3, [-(1 << 31), 1 << 31, 0], 1)
+    cfgs[1] = g.make_cfg(17, [0, 1 << 30], 2)
+    cfgs[2] = g.make_cfg(29, [1 << 31, 0, -(1 << 31)], 1)
+    states = np.zeros(3, g.CHAN_STATE)
+    for i in range(3):
+        fd = float(rng.uniform(-5000, 5000))
+        states[i] = g.gc_nco_init(fs, 4.092e6 + fd, 0.3, 1.023e6 * (1 + fd / 1575.42e6),
+                                  float(rng.uniform(0, 1023)), int(cfgs[i]["int_periods"]))
+    lens = [200000]
+    blocks = _random_blocks(rng, 2, lens)
+    lib, lst = run_library(torch, ctx, 2, g.GC_CARRIER_LUT, cfgs, states, blocks, lens)
+    orc, ost = run_oracle(2, cfgs, states, blocks, lens)
+    assert_exact(lib, lst, orc, ost, cfgs)
