@@ -162,6 +162,21 @@ gc_status gc_plan_create(gc_ctx* ctx, gc_format fmt, gc_carrier carrier,
 /* Release a plan (waits for the device). */
 gc_status gc_plan_destroy(gc_plan* plan);
 
+/* Kernel families a plan may use for its E/P/L channels (bit mask).  Every
+ * family computes the same integer sums (the definition of Eqs. (1)-(3)
+ * with the table carrier); the choice only changes speed.
+ *   GC_KERNEL_PERIODIC  half chips of exactly 8 or 10 samples with a bounded
+ *                       grid slip (fs an integer multiple of twice the code
+ *                       rate)
+ *   GC_KERNEL_BINNED    any rate of >= 2^32/127 code step, chip by chip
+ * Channels that no allowed family takes, and every channel of a plan with
+ * more than 4 taps, a complex format or the float carrier, use the direct
+ * per-sample kernel.  Default: both bits set.  Takes effect at the next
+ * gc_correlate.  Errors: GC_EINVAL (null plan, bits outside the mask). */
+#define GC_KERNEL_PERIODIC 1
+#define GC_KERNEL_BINNED 2
+gc_status gc_plan_set_kernels(gc_plan* plan, int32_t mask);
+
 /* Query: taps per dump row in the output layout (the largest n_taps of the
  * plan's channels) and the number of channels. */
 gc_status gc_plan_info(const gc_plan* plan, int32_t* tap_stride, int32_t* n_chan);

@@ -96,7 +96,8 @@ __global__ __launch_bounds__(256) void k_setup(const DevChan* __restrict__ chans
                                                uint32_t max_dumps, void* out, int tap_stride,
                                                uint32_t* __restrict__ dump_n,
                                                uint32_t* __restrict__ n_dumps,
-                                               int32_t* __restrict__ status_out) {
+                                               int32_t* __restrict__ status_out,
+                                               int32_t allow) {
     const int ch = blockIdx.x;
     const int tid = threadIdx.x;
     const DevChan& c = chans[ch];
@@ -116,6 +117,8 @@ __global__ __launch_bounds__(256) void k_setup(const DevChan* __restrict__ chans
         m.path = kPathDirect;
         m.c_full0 = m.c_full1 = 0;
         m.head_end = m.tail_beg = 0;
+        m.bin_len = 0;
+        m.pad2 = 0;
         int32_t s = GC_OK;
         if (m.dp == 0 || m.dp >= (1ull << 31) || m.p0 >= m.window) {
             s = GC_EINVAL;
@@ -142,8 +145,16 @@ __global__ __launch_bounds__(256) void k_setup(const DevChan* __restrict__ chans
             if (tb < he) tb = he;
             m.head_end = (uint32_t)he;
             m.tail_beg = (uint32_t)tb;
-            m.path = (c.epl && carrier == GC_CARRIER_LUT && binned_ok(fmt, m.dp) &&
-                      m.c_full1 > m.c_full0) ? kPathBinned : kPathDirect;
+            m.path = kPathDirect;
+            m.bin_len = 0;
+            const bool epl_ok = c.epl && carrier == GC_CARRIER_LUT && m.c_full1 > m.c_full0 &&
+                                (fmt == GC_I8_REAL || fmt == GC_I2_REAL);
+            if (epl_ok && (allow & kAllowPeriodic)) {
+                m.bin_len = periodic_bin_len(fmt, m.dp);
+                if (m.bin_len) m.path = kPathPeriodic;
+            }
+            if (m.path == kPathDirect && epl_ok && (allow & kAllowBinned) && binned_ok(fmt, m.dp))
+                m.path = kPathBinned;
         }
         m.status = s;
         metas[ch] = m;
@@ -196,9 +207,9 @@ __global__ __launch_bounds__(256) void k_setup(const DevChan* __restrict__ chans
 hipError_t launch_setup(const DevChan* chans, DevMeta* meta, gc_chan_state* state, int n_chan,
                         uint64_t n_samples, int fmt, int carrier, uint32_t max_dumps, void* out,
                         int tap_stride, uint32_t* dump_n, uint32_t* n_dumps, int32_t* status,
-                        hipStream_t s) {
+                        int32_t allow, hipStream_t s) {
     hipLaunchKernelGGL(k_setup, dim3(n_chan), dim3(256), 0, s, chans, meta, state, n_samples, fmt,
-                       carrier, max_dumps, out, tap_stride, dump_n, n_dumps, status);
+                       carrier, max_dumps, out, tap_stride, dump_n, n_dumps, status, allow);
     return hipGetLastError();
 }
 

@@ -11,7 +11,7 @@ constexpr int kTabG2 = 32;    // 32 words: G2 sequence
 constexpr int kTabLut = 64;   // 256 words: (cos low 16 | sin high 16), int16 each
 constexpr int kTabExpand = 320;  // 512 words: packed 2-bit byte -> its 4 samples as int16 (2 words)
 constexpr int kTabSign = 832;    // 32 PRNs x kSignLen words: chip i -> (s, s) int16, s = +-1
-constexpr int kSignLen = 1023 + 129;  // chip index 0..1022 followed by a wrapped copy
+constexpr int kSignLen = 1023 + 1152;  // chip index 0..1022 followed by a wrapped copy
 constexpr int kTabWords = kTabSign + 32 * kSignLen;
 constexpr int kLutAbsSumMax = 34;  // max over l of |cos_l| + |sin_l| at amplitude 24
 
@@ -70,6 +70,20 @@ __device__ __forceinline__ bool binned_ok(int fmt, uint64_t dp) {
     const uint64_t q = (1ull << 31) / dp;
     const uint64_t maxw = fmt == GC_I8_REAL ? 128ull * GC_LUT_AMP : 3ull * GC_LUT_AMP;
     return (q + 1) * maxw <= 32767ull;
+}
+
+// Periodic form: half chips of exactly L samples (L = 8 or 10), with at most
+// one one-sample slip of the bin grid per tile of kPbinTileSamples samples.
+constexpr int kPbinTileSamples = 16384;
+__device__ __forceinline__ int periodic_bin_len(int fmt, uint64_t dp) {
+    if (dp == 0 || dp >= (1ull << 31)) return 0;
+    const uint64_t L = ((1ull << 31) + dp / 2) / dp;  // nearest integer to 2^31 / dp
+    if (L != 8 && L != 10) return 0;
+    const uint64_t maxw = fmt == GC_I8_REAL ? 128ull * GC_LUT_AMP : 3ull * GC_LUT_AMP;
+    if (L * maxw > 32767ull) return 0;
+    const int64_t D = (int64_t)(L * dp) - (int64_t)(1ull << 31);
+    const uint64_t drift = (uint64_t)(D < 0 ? -D : D) * (kPbinTileSamples / L + 2);
+    return drift < dp ? (int)L : 0;
 }
 
 // First sample index of window m (m >= 1): ceil((m*W - p0) / dp).

@@ -323,6 +323,13 @@ __global__ __launch_bounds__(kThreads) void k_epl(const uint8_t* __restrict__ sa
     const uint32_t lane = tid & 63;
     const uint32_t lane4 = lane * 4;
     const uint8_t* lut = s_lds;
+    // channels left to this kernel: not refused and not on the periodic path
+    {
+        int mine = 0;
+        for (int c = 0; c < n_chan; ++c)
+            mine |= metas[c].status == GC_OK && metas[c].path != kPathPeriodic;
+        if (!mine) return;
+    }
     for (int i = tid; i < kLutWords; i += kThreads) s_lut[i] = tables[kTabLut + (i >> 6)];
 
     for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
@@ -333,7 +340,7 @@ __global__ __launch_bounds__(kThreads) void k_epl(const uint8_t* __restrict__ sa
         __syncthreads();
         for (int chn = 0; chn < n_chan; ++chn) {
             const DevMeta m = metas[chn];
-            if (m.status != GC_OK) continue;
+            if (m.status != GC_OK || m.path == kPathPeriodic) continue;
             const DevChan& ch = chans[chn];
             const Dest d{out, state + chn, (uint64_t)chn * max_dumps, tap_stride, m.m_close};
             const uint32_t* sgn_prn = tables + kTabSign + (ch.prn - 1) * kSignLen;

@@ -38,15 +38,22 @@ struct DevMeta {
     uint32_t m_close;      // windows closed by this block (dumps emitted)
     int32_t status;        // gc_status of this channel for this call
     uint32_t acc_n0;       // samples already in the open dump
-    int32_t path;          // kPathDirect or kPathBinned (chosen per call from the steps)
+    int32_t path;          // kPathDirect, kPathBinned or kPathPeriodic (per call, from the steps)
     uint64_t c_full0;      // first chip whose samples all lie in this block
     uint64_t c_full1;      // one past the last such chip
     uint32_t head_end;     // samples [0, head_end) precede chip c_full0
     uint32_t tail_beg;     // samples [tail_beg, n) follow chip c_full1 - 1
+    int32_t bin_len;       // samples per half chip on the periodic path
+    uint32_t pad2;
 };
 
 constexpr int32_t kPathDirect = 0;
 constexpr int32_t kPathBinned = 1;
+constexpr int32_t kPathPeriodic = 2;
+
+// Plan-level switches passed to the set-up kernel.
+constexpr int32_t kAllowBinned = 1;
+constexpr int32_t kAllowPeriodic = 2;
 
 // Kernel launch entry points (defined in the .hip files, called by the runtime).
 hipError_t launch_make_tables(uint32_t* d_tables, hipStream_t s);
@@ -54,7 +61,12 @@ hipError_t launch_code_table(const uint32_t* d_tables, int g2_delay, int8_t* d_o
 hipError_t launch_setup(const DevChan* chans, DevMeta* meta, gc_chan_state* state, int n_chan,
                         uint64_t n_samples, int fmt, int carrier, uint32_t max_dumps,
                         void* out, int tap_stride, uint32_t* dump_n, uint32_t* n_dumps,
-                        int32_t* status, hipStream_t s);
+                        int32_t* status, int32_t allow, hipStream_t s);
+hipError_t launch_pbin(const uint8_t* samples, uint64_t n_samples, int fmt, const DevChan* chans,
+                       const DevMeta* meta, gc_chan_state* state, int n_chan, int32_t* out,
+                       int tap_stride, uint32_t max_dumps, const uint32_t* d_tables, int grid,
+                       hipStream_t s);
+int pbin_tile_samples();
 hipError_t launch_epl(const uint8_t* samples, uint64_t n_samples, int fmt, const DevChan* chans,
                       const DevMeta* meta, gc_chan_state* state, int n_chan, int32_t* out,
                       int tap_stride, uint32_t max_dumps, const uint32_t* d_tables, int grid,

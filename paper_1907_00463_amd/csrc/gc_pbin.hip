@@ -1,0 +1,531 @@
+// gc_pbin.hip -- early/prompt/late correlator for channels whose half-chip
+// bins are periodic in the sample stream (integer carrier path, real int8
+// and 2-bit samples).
+//
+// When fs is close to an integer multiple L of twice the code rate (L = 8 at
+// 16.368 MHz, 10 at 20.46 MHz), every half chip of code phase covers exactly
+// L samples, give or take one sample every |dp / (L*dp - 2^31)| bins (the
+// code Doppler "slip").  Bin k of a run then starts at sample s_0 + k*L, so
+// consecutive lanes can take consecutive bins with fixed per-lane offsets:
+//
+//   * a block streams through a contiguous chunk of tiles of kTile samples,
+//     staged once in LDS as int16 in two copies (aligned, and shifted by one
+//     sample) so that every bin starts on a dword of one of them; each wave
+//     owns one channel and keeps its E/P/L sums in registers across tiles,
+//     reducing across lanes only when a dump closes;
+//   * lane l of a wave takes bins k0 + 64j + l, j = 0, 1, ...: per sample one
+//     phase add, one v_perm (address of the lane's own copy of the carrier
+//     table), one table read and one packed int16 multiply-add; per pair of
+//     samples one dword read; per bin three packed multiply-adds with the
+//     E/P/L code signs of its chip (two consecutive entries of a sign table,
+//     fetched one step ahead);
+//   * with L = 8, bins start 4 dwords apart, so the lanes of each 8-lane
+//     group read the dwords of their bin in a rotated order and one read
+//     instruction touches 64 distinct LDS banks (L = 10: 5 dwords apart,
+//     distinct banks already);
+//   * the step at which a dump closes is found per wave in advance; only that
+//     step (and the ragged last step of a run) carries per-lane checks;
+//   * a tile in which the bin grid slips by one sample is split into two
+//     periodic runs, and the one sample at the seam is corrected with one
+//     atomic update per output word.
+// The result equals the per-sample definition exactly (integer sums
+// regrouped).  Channels whose bins are not periodic use the chip-by-chip
+// binned kernel or the direct path.
+#include "gc_device.h"
+
+namespace gc {
+
+namespace {
+
+constexpr int kTile = kPbinTileSamples;        // samples per tile
+constexpr int kMarginS = 64;                   // bins that start in a tile end within this
+constexpr int kXSamples = kTile + kMarginS;    // int16 samples per staged copy
+constexpr int kXBytes = kXSamples * 2;
+constexpr int kLutWords = 256 * 64;            // per-lane copies of the carrier table
+constexpr int kXA = kLutWords * 4;             // LDS byte offset of copy A: A[i] = x[t0 + i]
+constexpr int kXB = kXA + kXBytes;             // copy B: B[i] = x[t0 + i + 1]
+constexpr int kLdsBytes = kXB + kXBytes;
+constexpr int kMaxWaves = 16;                  // one channel per wave
+constexpr uint32_t kPermSel = 0x0C0C0700u;     // byte1 = phase[31:24], byte0 = lane*4
+
+typedef short short2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ short2_t as_s2(uint32_t v) { return __builtin_bit_cast(short2_t, v); }
+
+__device__ __forceinline__ uint32_t lds_u32(const uint8_t* lds, uint32_t off) {
+    return *reinterpret_cast<const uint32_t*>(lds + off);
+}
+
+struct Dest {
+    int32_t* out;
+    gc_chan_state* st;
+    uint64_t row0;
+    int tap_stride;
+    uint32_t m_close;
+    __device__ __forceinline__ int32_t* at(uint32_t w, int slot, int comp) const {
+        if (w < m_close) return out + ((row0 + w) * tap_stride + slot) * 2 + comp;
+        return &st->acc[slot][comp];
+    }
+};
+
+// Persistent per-wave state of its channel: the E/P/L sums of the open dump
+// (I, Q each; Q holds +x*s), as int32 and, for 2-bit input, as packed int16
+// partial sums folded into the int32 ones at the end of every tile and
+// before a flush (at most 33 bins of |sum| <= 720 per lane per tile).
+struct Slot {
+    int v[6];
+    short2_t e16, p16, l16;
+    uint32_t w;        // dump of the open sums (wave-uniform)
+    uint32_t wnext;    // first chip of dump w + 1
+    bool init;
+};
+
+template <int FMT>
+__device__ __forceinline__ void fold16(Slot& s) {
+    if constexpr (FMT == GC_I2_REAL) {
+        s.v[0] += s.e16.x; s.v[1] += s.e16.y;
+        s.v[2] += s.p16.x; s.v[3] += s.p16.y;
+        s.v[4] += s.l16.x; s.v[5] += s.l16.y;
+        s.e16 = s.p16 = s.l16 = short2_t{0, 0};
+    }
+}
+
+// Sum of the open dump over the wave's 64 lanes (all lanes active), one
+// atomic per output word from lane 0; Q is negated here (wipe-off Q = -x*s).
+__device__ __forceinline__ void wave_flush(const Slot& s, const Dest& d, const DevChan& ch) {
+    const int slot[3] = {ch.slot_e, ch.slot_p, ch.slot_l};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int t = wave_total_dpp(s.v[k]);
+        if ((threadIdx.x & 63) == 0 && t != 0)
+            atomicAdd(d.at(s.w, slot[k >> 1], k & 1), (k & 1) ? -t : t);
+    }
+}
+
+// Bin sum a with code signs (sL, sE) of chips (c + par - 1, c + par), each
+// a packed (s, s) int16 word; the prompt sign is sL for the second half of a
+// chip (par = 1) and sE for the first.
+template <int FMT>
+__device__ __forceinline__ void add_bin(Slot& s, short2_t a, uint2 sg, uint32_t par) {
+    const uint32_t sP = par ? sg.x : sg.y;
+    if constexpr (FMT == GC_I2_REAL) {
+        s.e16 = a * as_s2(sg.y) + s.e16;
+        s.p16 = a * as_s2(sP) + s.p16;
+        s.l16 = a * as_s2(sg.x) + s.l16;
+    } else {
+        const int ai = a.x, aq = a.y;
+        const int e = (int)(short)(sg.y & 0xFFFF), p = (int)(short)(sP & 0xFFFF),
+                  l = (int)(short)(sg.x & 0xFFFF);
+        s.v[0] += ai * e; s.v[1] += aq * e;
+        s.v[2] += ai * p; s.v[3] += aq * p;
+        s.v[4] += ai * l; s.v[5] += aq * l;
+    }
+}
+
+// Sum over one bin of x * (c, s): dword j of the bin (samples 2j, 2j+1) is
+// read at xaddr + roff[j]; sample i takes carrier phase ph + poff[i].
+template <int L>
+__device__ __forceinline__ short2_t bin_sum(const uint8_t* lds, uint32_t xaddr, uint32_t ph,
+                                           const uint32_t (&roff)[L / 2], const uint32_t (&poff)[L],
+                                           uint32_t lane4) {
+    short2_t a = {0, 0};
+#pragma unroll
+    for (int j = 0; j < L / 2; ++j) {
+        const short2_t xw = as_s2(lds_u32(lds, xaddr + roff[j]));
+        const short2_t c0 = as_s2(lds_u32(lds, __builtin_amdgcn_perm(ph + poff[2 * j], lane4, kPermSel)));
+        const short2_t c1 = as_s2(lds_u32(lds, __builtin_amdgcn_perm(ph + poff[2 * j + 1], lane4, kPermSel)));
+        const short2_t x0 = {xw.x, xw.x};
+        const short2_t x1 = {xw.y, xw.y};
+        a = x0 * c0 + a;
+        a = x1 * c1 + a;
+    }
+    return a;
+}
+
+// Bins [kb, ke) of the current tile, bin k starting at tile sample
+// base + k*L, bin index h_a + k.  Lane l takes bins kb + 64j + l.
+template <int FMT, int L>
+__device__ __forceinline__ void periodic_run(Slot& S, const uint8_t* lds, uint32_t lane,
+                                             uint32_t lane4, int64_t base, uint32_t h_a,
+                                             uint32_t kb, uint32_t ke, uint64_t t0,
+                                             const DevMeta& m, const DevChan& ch,
+                                             const uint32_t* __restrict__ sgn_prn, uint32_t span,
+                                             const Dest& d) {
+    if (ke <= kb) return;
+    constexpr int B = L / 2;               // dwords per bin
+    constexpr bool kRot = (B % 2) == 0;    // bin starts share bank classes (B = 4)
+    static_assert(!kRot || B == 4, "rotation is laid out for 4-dword bins");
+    const uint32_t c8 = lane >> 3;
+    const uint32_t g = kRot ? ((c8 ^ (c8 >> 2)) & 3u) : 0u;
+    uint32_t roff[B];
+    uint32_t poff[L];
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+        const uint32_t jr = kRot ? ((j + g) & 3u) : (uint32_t)j;
+        roff[j] = 4u * jr;
+        poff[2 * j] = 2u * jr * m.dphi;
+        poff[2 * j + 1] = (2u * jr + 1u) * m.dphi;
+    }
+    // bins of one run all start on the same parity; pick the copy on which
+    // they start on a dword
+    const uint32_t par_s = (uint32_t)base & 1u;
+    const uint32_t xbase = par_s ? (uint32_t)((int64_t)kXB + 2 * (base - 1))
+                                 : (uint32_t)((int64_t)kXA + 2 * base);
+    const uint32_t k0 = kb + lane;
+    uint32_t xaddr = xbase + (uint32_t)(2 * L) * k0;
+    uint32_t ph = m.phi0 + (uint32_t)(t0 + (uint64_t)(base + (int64_t)k0 * L)) * m.dphi;
+    const uint32_t hk0 = h_a + k0;
+    const uint32_t par = hk0 & 1u;
+    // byte offset of the sign pair (chip c + par - 1, chip c + par); the
+    // table repeats the code so that the offset only grows within a run
+    uint32_t soff = 4u * (((hk0 >> 1) + par + kCodeLen - 1) % kCodeLen);
+    const uint8_t* sgb = reinterpret_cast<const uint8_t*>(sgn_prn);
+    uint2 sg = *reinterpret_cast<const uint2*>(sgb + soff);
+
+    constexpr uint32_t dx = 64u * 2u * L;
+    const uint32_t dph = (uint32_t)(64 * L) * m.dphi;
+    const uint32_t steps = (ke - kb + 63) / 64;
+    const uint32_t full = (ke - kb) / 64;
+    const uint32_t hfirst = h_a + kb;      // bin of lane 0 at step 0
+    uint32_t j = 0;
+    while (j < steps) {
+        // first step at which lane 63's bin reaches chip wnext
+        const uint32_t h_cross = 2u * S.wnext;
+        const uint32_t jx = h_cross > hfirst + 63u ? (h_cross - hfirst - 63u + 63u) / 64u : 0u;
+        const uint32_t jend = min(max(jx, j), full);
+        for (; j < jend; ++j) {
+            const uint2 sn = *reinterpret_cast<const uint2*>(sgb + soff + 128u);
+            const short2_t a = bin_sum<L>(lds, xaddr, ph, roff, poff, lane4);
+            add_bin<FMT>(S, a, sg, par);
+            sg = sn;
+            soff += 128u;
+            xaddr += dx;
+            ph += dph;
+        }
+        if (j >= steps) break;
+        // a step with a dump boundary, or the ragged last step
+        {
+            const uint2 sn = *reinterpret_cast<const uint2*>(sgb + soff + 128u);
+            const uint32_t k = k0 + 64u * j;
+            const bool valid = k < ke;
+            const uint32_t c = (hk0 + 64u * j) >> 1;
+            const bool ahead = valid && c >= S.wnext;
+            short2_t a = bin_sum<L>(lds, valid ? xaddr : (uint32_t)kXA, ph, roff, poff, lane4);
+            if (!valid) a = short2_t{0, 0};
+            if (valid && !ahead) add_bin<FMT>(S, a, sg, par);
+            if (__ballot(ahead) != 0) {
+                fold16<FMT>(S);
+                wave_flush(S, d, ch);
+#pragma unroll
+                for (int q = 0; q < 6; ++q) S.v[q] = 0;
+                S.w += 1;
+                S.wnext += span;
+                if (ahead) add_bin<FMT>(S, a, sg, par);
+            }
+            sg = sn;
+            soff += 128u;
+            xaddr += dx;
+            ph += dph;
+            ++j;
+        }
+    }
+}
+
+// Direct per-sample form over tile offsets [lo, hi) for one E/P/L channel
+// (samples of chips cut by the ends of the block).
+__device__ __forceinline__ void direct_epl(const uint8_t* lds, uint32_t lane4, uint64_t t0,
+                                           uint32_t lo, uint32_t hi, const DevMeta& m,
+                                           const DevChan& ch, const uint32_t* __restrict__ sgn_prn,
+                                           const Dest& d) {
+    if (lo >= hi) return;
+    const short* sx = reinterpret_cast<const short*>(lds + kXA);
+    const uint64_t W = m.window;
+    const uint64_t wa = (m.p0 + (t0 + lo) * m.dp) / W;
+    const uint64_t wb = (m.p0 + (t0 + hi - 1) * m.dp) / W;
+    const int64_t tap[3] = {int64_t(1) << 31, 0, -(int64_t(1) << 31)};
+    const int slot[3] = {ch.slot_e, ch.slot_p, ch.slot_l};
+    for (uint64_t w = wa; w <= wb; ++w) {
+        const uint64_t s_lo = window_start(w, W, m.p0, m.dp);
+        const uint64_t s_hi = window_start(w + 1, W, m.p0, m.dp);
+        const uint32_t a = (uint32_t)max((uint64_t)lo, s_lo > t0 ? s_lo - t0 : 0);
+        const uint32_t b = (uint32_t)min((uint64_t)hi, s_hi - t0);
+        int acc[6] = {0, 0, 0, 0, 0, 0};
+        for (uint32_t i = a + (threadIdx.x & 63); i < b; i += 64) {
+            const uint64_t n = t0 + i;
+            const uint32_t phi = m.phi0 + (uint32_t)n * m.dphi;
+            int cc, ss;
+            lut_cs(lds_u32(lds, __builtin_amdgcn_perm(phi, lane4, kPermSel)), cc, ss);
+            const int x = sx[i];
+            const uint64_t u = m.p0 + n * m.dp;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int64_t v = (int64_t)u + tap[k];
+                int32_t chip = (int32_t)(v >> 32) % kCodeLen;
+                if (chip < 0) chip += kCodeLen;
+                const int r = (int)(short)(sgn_prn[chip] & 0xFFFF);
+                acc[2 * k] += x * cc * r;
+                acc[2 * k + 1] -= x * ss * r;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const int t = wave_total_dpp(acc[k]);
+            if ((threadIdx.x & 63) == 0 && t != 0) atomicAdd(d.at((uint32_t)w, slot[k >> 1], k & 1), t);
+        }
+    }
+}
+
+// One sample added to (sign = +1) or removed from (-1) bin h's E/P/L
+// outputs, by one lane (the seam of a one-sample slip of the bin grid).
+__device__ __forceinline__ void seam_sample(const uint8_t* lds, uint32_t lane4, uint64_t t0,
+                                            int64_t off, uint64_t h, int sign, const DevMeta& m,
+                                            const DevChan& ch, const uint32_t* __restrict__ sgn_prn,
+                                            uint32_t span, const Dest& d) {
+    const short* sx = reinterpret_cast<const short*>(lds + kXA);
+    const uint32_t phi = m.phi0 + (uint32_t)(t0 + (uint64_t)off) * m.dphi;
+    int cc, ss;
+    lut_cs(lds_u32(lds, __builtin_amdgcn_perm(phi, lane4, kPermSel)), cc, ss);
+    const int x = sx[off];
+    const uint32_t c = (uint32_t)(h >> 1), par = (uint32_t)(h & 1);
+    const uint32_t si = (c + par + kCodeLen - 1) % kCodeLen;
+    const int sl = (int)(short)(sgn_prn[si] & 0xFFFF), se = (int)(short)(sgn_prn[si + 1] & 0xFFFF);
+    const int sp = par ? sl : se;
+    const uint32_t w = c / span;
+    const int s3[3] = {se, sp, sl};
+    const int slot[3] = {ch.slot_e, ch.slot_p, ch.slot_l};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        atomicAdd(d.at(w, slot[k], 0), sign * x * cc * s3[k]);
+        atomicAdd(d.at(w, slot[k], 1), -sign * x * ss * s3[k]);
+    }
+}
+
+// Tile samples [t0, t0 + kXSamples) into copies A and B (int16; zero past
+// the end of the block).
+template <int FMT>
+__device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, uint64_t n,
+                                           uint64_t t0, uint8_t* lds, const uint32_t* tables,
+                                           int nthreads) {
+    uint2* dA = reinterpret_cast<uint2*>(lds + kXA);
+    uint2* dB = reinterpret_cast<uint2*>(lds + kXB);
+    if constexpr (FMT == GC_I2_REAL) {
+        const uint64_t nbytes = (n + 3) / 4;
+        const uint64_t b0 = t0 / 4;
+        for (int i = threadIdx.x; i < kXSamples / 4; i += nthreads) {
+            const uint64_t b = b0 + i;
+            uint32_t e0 = 0, e1 = 0, f0 = 0;
+            if (b < nbytes) {
+                const uint32_t* e = tables + kTabExpand + 2 * samples[b];
+                e0 = e[0];
+                e1 = e[1];
+            }
+            if (b + 1 < nbytes) f0 = tables[kTabExpand + 2 * samples[b + 1]];
+            dA[i] = uint2{e0, e1};
+            dB[i] = uint2{__builtin_amdgcn_alignbit(e1, e0, 16), __builtin_amdgcn_alignbit(f0, e1, 16)};
+        }
+    } else {
+        for (int i = threadIdx.x; i < kXSamples / 4; i += nthreads) {
+            const uint64_t b = t0 + 4ull * i;
+            uint32_t v = 0, nx = 0;
+            if (b + 4 <= n) {
+                v = *reinterpret_cast<const uint32_t*>(samples + b);
+            } else {
+                for (int j = 0; j < 4; ++j)
+                    if (b + j < n) v |= (uint32_t)samples[b + j] << (8 * j);
+            }
+            if (b + 4 < n) nx = samples[b + 4];
+            const uint32_t s0 = (uint16_t)(int16_t)(int8_t)(v & 0xFF);
+            const uint32_t s1 = (uint16_t)(int16_t)(int8_t)((v >> 8) & 0xFF);
+            const uint32_t s2 = (uint16_t)(int16_t)(int8_t)((v >> 16) & 0xFF);
+            const uint32_t s3 = (uint16_t)(int16_t)(int8_t)(v >> 24);
+            const uint32_t s4 = (uint16_t)(int16_t)(int8_t)nx;
+            dA[i] = uint2{s0 | (s1 << 16), s2 | (s3 << 16)};
+            dB[i] = uint2{s1 | (s2 << 16), s3 | (s4 << 16)};
+        }
+    }
+}
+
+// First sample (tile offset) of bin h with its overshoot: smallest n with
+// (t0 + n)*dp >= h*2^31 - p0, given u0 = p0 + t0*dp <= h*2^31.
+__device__ __forceinline__ void bin_start(uint64_t h, uint64_t u0, uint32_t dp, float inv_dp,
+                                          uint64_t& n_out, uint64_t& e_out) {
+    const uint64_t D = (h << 31) - u0;
+    const float df = (float)(uint32_t)(D >> 32) * 4294967296.0f + (float)(uint32_t)D;
+    uint64_t nr = (uint64_t)(uint32_t)max(0.0f, df * inv_dp - 2.0f);
+    while (nr * dp < D) ++nr;
+    n_out = nr;
+    e_out = nr * dp - D;
+}
+
+template <int FMT, int L>
+__device__ __forceinline__ void channel_tile(Slot& S, const uint8_t* lds, uint32_t lane,
+                                             uint32_t lane4, uint64_t t0, uint64_t t1,
+                                             const DevMeta& m, const DevChan& ch,
+                                             const uint32_t* __restrict__ sgn_prn, const Dest& d) {
+    const uint32_t span = (uint32_t)(m.window >> 32);
+    const uint32_t tl = (uint32_t)(t1 - t0);
+    // samples of chips cut by the ends of the block
+    if (m.head_end > t0)
+        direct_epl(lds, lane4, t0, 0, (uint32_t)(min((uint64_t)m.head_end, t1) - t0), m, ch,
+                   sgn_prn, d);
+    if (t1 > m.tail_beg)
+        direct_epl(lds, lane4, t0, (uint32_t)(max((uint64_t)m.tail_beg, t0) - t0), tl, m, ch,
+                   sgn_prn, d);
+    // bins of whole chips whose code phase starts in [u(t0), u(t1))
+    const uint64_t u0 = m.p0 + t0 * m.dp;
+    const uint64_t u1 = m.p0 + t1 * m.dp;
+    uint64_t ha = (u0 + 0x7FFFFFFFull) >> 31;
+    uint64_t hb = (u1 + 0x7FFFFFFFull) >> 31;
+    if (ha < 2 * m.c_full0) ha = 2 * m.c_full0;
+    if (hb > 2 * m.c_full1) hb = 2 * m.c_full1;
+    if (hb <= ha) return;
+    const uint32_t nb = (uint32_t)(hb - ha);
+    const uint32_t dp = (uint32_t)m.dp;
+    uint64_t na, ea;
+    bin_start(ha, u0, dp, 1.0f / (float)dp, na, ea);
+    if (!S.init) {  // dump of the first bin this wave sees for the channel
+        S.init = true;
+        S.w = (uint32_t)((ha >> 1) / span);
+        S.wnext = (S.w + 1) * span;
+    }
+    // bin k starts at na + k*L while e_k = ea + k*D stays in [0, dp); bins
+    // 0 .. nb-1 all hold L samples when that holds up to k = nb (the start of
+    // the first bin of the next tile)
+    const int64_t D = (int64_t)L * (int64_t)dp - (int64_t(1) << 31);
+    const int64_t elast = (int64_t)ea + (int64_t)nb * D;
+    if (elast >= 0 && elast < (int64_t)dp) {
+        periodic_run<FMT, L>(S, lds, lane, lane4, (int64_t)na, (uint32_t)ha, 0, nb, t0, m, ch,
+                             sgn_prn, span, d);
+        return;
+    }
+    // one slip: first k (1 <= ks <= nb) whose bin starts one sample earlier
+    // (D > 0) or later (D < 0) than the grid of bin 0
+    uint32_t ks;
+    int sigma;
+    if (D > 0) {
+        ks = (uint32_t)(((int64_t)dp - (int64_t)ea + D - 1) / D);
+        sigma = -1;
+    } else {
+        ks = (uint32_t)((int64_t)ea / (-D) + 1);
+        sigma = 1;
+    }
+    periodic_run<FMT, L>(S, lds, lane, lane4, (int64_t)na, (uint32_t)ha, 0, ks, t0, m, ch, sgn_prn,
+                         span, d);
+    periodic_run<FMT, L>(S, lds, lane, lane4, (int64_t)na + sigma, (uint32_t)ha, ks, nb, t0, m, ch,
+                         sgn_prn, span, d);
+    // bin ks-1 really ends at na + ks*L + sigma: the sample between the two
+    // grids was counted twice (sigma = -1) or not at all (sigma = +1)
+    if (lane == 0) {
+        const int64_t off = (int64_t)na + (int64_t)ks * L + (sigma < 0 ? -1 : 0);
+        seam_sample(lds, lane4, t0, off, ha + ks - 1, sigma < 0 ? -1 : 1, m, ch, sgn_prn, span, d);
+    }
+}
+
+template <int FMT>
+__global__ __launch_bounds__(kMaxWaves * 64) void k_pbin(const uint8_t* __restrict__ samples,
+                                                         uint64_t n,
+                                                         const DevChan* __restrict__ chans,
+                                                         const DevMeta* __restrict__ metas,
+                                                         gc_chan_state* __restrict__ state,
+                                                         int32_t* __restrict__ out, int tap_stride,
+                                                         uint32_t max_dumps,
+                                                         const uint32_t* __restrict__ tables,
+                                                         int n_chan, uint32_t n_tiles) {
+    // one LDS block: the per-lane carrier tables at offset 0 (the v_perm
+    // result is the address itself), the two staged copies, the channel list
+    __shared__ __attribute__((aligned(16))) uint8_t s_lds[kLdsBytes + 4 * (kMaxWaves + 1)];
+    uint32_t* s_lut = reinterpret_cast<uint32_t*>(s_lds);
+    int* s_list = reinterpret_cast<int*>(s_lds + kLdsBytes);
+    const int tid = threadIdx.x;
+    const int nthreads = blockDim.x;
+    const int wave = tid / 64;
+    const uint32_t lane = tid & 63;
+    const uint32_t lane4 = lane * 4;
+
+    // this block's channel group: periodic channels 16*blockIdx.y ...
+    if (tid == 0) {
+        const int first = (int)blockIdx.y * kMaxWaves;
+        int k = 0, seen = 0;
+        for (int c = 0; c < n_chan && k < kMaxWaves; ++c) {
+            const DevMeta& m = metas[c];
+            if (m.status == GC_OK && m.path == kPathPeriodic) {
+                if (seen >= first) s_list[k++] = c;
+                ++seen;
+            }
+        }
+        s_list[kMaxWaves] = k;
+    }
+    __syncthreads();
+    const int nlist = s_list[kMaxWaves];
+    if (nlist == 0) return;
+    for (int i = tid; i < kLutWords; i += nthreads) s_lut[i] = tables[kTabLut + (i >> 6)];
+
+    Slot S;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) S.v[q] = 0;
+    S.e16 = S.p16 = S.l16 = short2_t{0, 0};
+    S.w = 0;
+    S.wnext = 0;
+    S.init = false;
+    const bool active = wave < nlist;
+    const int chn = __builtin_amdgcn_readfirstlane(active ? s_list[wave] : 0);
+    const DevChan& ch = chans[chn];
+    const uint32_t* sgn_prn = tables + kTabSign + (ch.prn - 1) * kSignLen;
+    const DevMeta m = metas[chn];
+    const Dest d{out, state + chn, (uint64_t)chn * max_dumps, tap_stride, m.m_close};
+    // contiguous chunk of tiles for this block
+    const uint32_t tb0 = (uint32_t)(((uint64_t)blockIdx.x * n_tiles) / gridDim.x);
+    const uint32_t tb1 = (uint32_t)(((uint64_t)(blockIdx.x + 1) * n_tiles) / gridDim.x);
+    for (uint32_t tile = tb0; tile < tb1; ++tile) {
+        const uint64_t t0 = (uint64_t)tile * kTile;
+        const uint64_t t1 = min(n, t0 + kTile);
+        __syncthreads();
+        stage_tile<FMT>(samples, n, t0, s_lds, tables, nthreads);
+        __syncthreads();
+        if (active) {
+            if (m.bin_len == 8)
+                channel_tile<FMT, 8>(S, s_lds, lane, lane4, t0, t1, m, ch, sgn_prn, d);
+            else
+                channel_tile<FMT, 10>(S, s_lds, lane, lane4, t0, t1, m, ch, sgn_prn, d);
+            fold16<FMT>(S);
+        }
+    }
+    // the dump still open at the end of the chunk
+    if (active && S.init) {
+        fold16<FMT>(S);
+        wave_flush(S, d, ch);
+    }
+}
+
+template <int FMT>
+void launch_one(const uint8_t* samples, uint64_t n, const DevChan* chans, const DevMeta* meta,
+                gc_chan_state* state, int n_chan, int32_t* out, int tap_stride, uint32_t max_dumps,
+                const uint32_t* tables, int grid, hipStream_t s) {
+    const uint32_t n_tiles = (uint32_t)((n + kTile - 1) / kTile);
+    const int g = (int)min((uint32_t)grid, n_tiles);
+    const int waves = min(n_chan, kMaxWaves);
+    const int groups = (n_chan + kMaxWaves - 1) / kMaxWaves;
+    hipLaunchKernelGGL((k_pbin<FMT>), dim3(g, groups), dim3(64 * waves), 0, s, samples, n, chans,
+                       meta, state, out, tap_stride, max_dumps, tables, n_chan, n_tiles);
+}
+
+}  // namespace
+
+int pbin_tile_samples() { return kTile; }
+
+hipError_t launch_pbin(const uint8_t* samples, uint64_t n, int fmt, const DevChan* chans,
+                       const DevMeta* meta, gc_chan_state* state, int n_chan, int32_t* out,
+                       int tap_stride, uint32_t max_dumps, const uint32_t* tables, int grid,
+                       hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    if (fmt == GC_I2_REAL)
+        launch_one<GC_I2_REAL>(samples, n, chans, meta, state, n_chan, out, tap_stride, max_dumps,
+                               tables, grid, s);
+    else if (fmt == GC_I8_REAL)
+        launch_one<GC_I8_REAL>(samples, n, chans, meta, state, n_chan, out, tap_stride, max_dumps,
+                               tables, grid, s);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace gc

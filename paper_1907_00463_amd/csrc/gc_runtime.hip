@@ -25,6 +25,7 @@ struct gc_plan {
     gc::DevChan* d_chans;
     gc::DevMeta* d_meta;
     int use_epl;      // all channels <= 4 taps, real int8 / 2-bit, integer carrier
+    int kernels;      // GC_KERNEL_* mask
     int epl_grid;     // persistent blocks of the binned kernel
     std::vector<hipEvent_t> ev_start, ev_stop;  // timing slots (empty: off)
     std::vector<uint8_t> ev_used;
@@ -208,6 +209,7 @@ gc_status gc_plan_create(gc_ctx* ctx, gc_format fmt, gc_carrier carrier, const g
     p->calls = 0;
     p->use_epl = carrier == GC_CARRIER_LUT && (fmt == GC_I8_REAL || fmt == GC_I2_REAL) &&
                  max_taps <= 4;
+    p->kernels = GC_KERNEL_PERIODIC | GC_KERNEL_BINNED;
     p->epl_grid = gc::epl_blocks_per_device(ctx->device);
     hipError_t e = hipMalloc(&p->d_chans, sizeof(gc::DevChan) * (size_t)n_chan);
     if (e == hipSuccess) e = hipMalloc(&p->d_meta, sizeof(gc::DevMeta) * (size_t)n_chan);
@@ -274,6 +276,12 @@ gc_status gc_plan_destroy(gc_plan* plan) {
     return GC_OK;
 }
 
+gc_status gc_plan_set_kernels(gc_plan* plan, int32_t mask) {
+    if (!plan || (mask & ~(GC_KERNEL_PERIODIC | GC_KERNEL_BINNED))) return GC_EINVAL;
+    plan->kernels = mask;
+    return GC_OK;
+}
+
 gc_status gc_plan_info(const gc_plan* plan, int32_t* tap_stride, int32_t* n_chan) {
     if (!plan || !tap_stride || !n_chan) return GC_EINVAL;
     *tap_stride = plan->max_taps;
@@ -290,21 +298,35 @@ gc_status gc_correlate(gc_plan* plan, const void* samples, uint64_t n_samples,
     DeviceGuard g(plan->ctx->device);
     if (!g.ok) return GC_EDEVICE;
     hipStream_t s = (hipStream_t)stream;
+    const bool periodic = plan->use_epl && (plan->kernels & GC_KERNEL_PERIODIC);
+    const bool binned = plan->use_epl && (plan->kernels & GC_KERNEL_BINNED);
+    const int32_t allow = (periodic ? gc::kAllowPeriodic : 0) | (binned ? gc::kAllowBinned : 0);
     hipError_t e = gc::launch_setup(plan->d_chans, plan->d_meta, state, plan->n_chan, n_samples,
                                     plan->fmt, plan->carrier, max_dumps, out, plan->max_taps,
-                                    dump_n, n_dumps, status, s);
+                                    dump_n, n_dumps, status, allow, s);
+    const uint8_t* x = (const uint8_t*)samples;
+    // The chip-by-chip kernel takes the E/P/L channels the periodic kernel
+    // leaves (it returns at once when there are none); the timing slot
+    // brackets the plan's main kernel only.
+    if (e == hipSuccess && plan->use_epl && periodic)
+        e = gc::launch_epl(x, n_samples, plan->fmt, plan->d_chans, plan->d_meta, state,
+                           plan->n_chan, (int32_t*)out, plan->max_taps, max_dumps,
+                           plan->ctx->d_tables, plan->epl_grid, s);
     const size_t slot = plan->ev_stop.empty() ? 0 : (size_t)(plan->calls % plan->ev_stop.size());
     if (e == hipSuccess && !plan->ev_start.empty()) e = hipEventRecord(plan->ev_start[slot], s);
     if (e == hipSuccess) {
-        if (plan->use_epl)
-            e = gc::launch_epl((const uint8_t*)samples, n_samples, plan->fmt, plan->d_chans,
-                               plan->d_meta, state, plan->n_chan, (int32_t*)out, plan->max_taps,
-                               max_dumps, plan->ctx->d_tables, plan->epl_grid, s);
+        if (periodic)
+            e = gc::launch_pbin(x, n_samples, plan->fmt, plan->d_chans, plan->d_meta, state,
+                                plan->n_chan, (int32_t*)out, plan->max_taps, max_dumps,
+                                plan->ctx->d_tables, plan->epl_grid, s);
+        else if (plan->use_epl)
+            e = gc::launch_epl(x, n_samples, plan->fmt, plan->d_chans, plan->d_meta, state,
+                               plan->n_chan, (int32_t*)out, plan->max_taps, max_dumps,
+                               plan->ctx->d_tables, plan->epl_grid, s);
         else
-            e = gc::launch_generic((const uint8_t*)samples, n_samples, plan->fmt, plan->carrier,
-                                   plan->d_chans, plan->d_meta, state, plan->n_chan,
-                                   plan->max_taps, out, plan->max_taps, max_dumps,
-                                   plan->ctx->d_tables, s);
+            e = gc::launch_generic(x, n_samples, plan->fmt, plan->carrier, plan->d_chans,
+                                   plan->d_meta, state, plan->n_chan, plan->max_taps, out,
+                                   plan->max_taps, max_dumps, plan->ctx->d_tables, s);
     }
     if (e == hipSuccess && !plan->ev_stop.empty()) {
         e = hipEventRecord(plan->ev_stop[slot], s);

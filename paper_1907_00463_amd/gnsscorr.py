@@ -20,6 +20,7 @@ GC_OK, GC_EINVAL, GC_ENOMEM, GC_EDEVICE, GC_ERANGE, GC_EBUSY, GC_EAGAIN, GC_ENOS
     0, -1, -2, -3, -4, -5, -6, -7)
 GC_I8_REAL, GC_I8_IQ, GC_I2_REAL = 0, 1, 2
 GC_CARRIER_LUT, GC_CARRIER_F32 = 0, 1
+GC_KERNEL_PERIODIC, GC_KERNEL_BINNED = 1, 2
 GC_MAX_TAPS = 128
 GC_LUT_AMP = 24
 TWO32 = 1 << 32
@@ -59,6 +60,7 @@ def _load():
         "gc_correlate": ([P, P, U64, P, P, P, P, P, U32, P], I32),
         "gc_plan_timing": ([P, I32], I32),
         "gc_plan_kernel_ms": ([P, I32, P], I32),
+        "gc_plan_set_kernels": ([P, I32], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -70,7 +72,7 @@ def _load():
 _lib = _load()
 EXPORTED = ("gc_strerror", "gc_version", "gc_create", "gc_destroy", "gc_nco_init",
             "gc_code_table", "gc_plan_create", "gc_plan_destroy", "gc_plan_info",
-            "gc_correlate", "gc_plan_timing", "gc_plan_kernel_ms")
+            "gc_correlate", "gc_plan_timing", "gc_plan_kernel_ms", "gc_plan_set_kernels")
 
 
 def _check(rc: int, where: str):
@@ -134,6 +136,10 @@ def gc_plan_create(ctx: int, fmt: int, carrier: int, cfg: np.ndarray) -> int:
 
 def gc_plan_destroy(plan: int) -> None:
     _check(_lib.gc_plan_destroy(plan), "gc_plan_destroy")
+
+
+def gc_plan_set_kernels(plan: int, mask: int) -> None:
+    _check(_lib.gc_plan_set_kernels(plan, mask), "gc_plan_set_kernels")
 
 
 def gc_plan_info(plan: int):

@@ -26,13 +26,17 @@ def oracle_state(st_rec, K: int, f64: bool = False) -> oracle.OracleState:
     return s
 
 
-def run_library(torch, ctx, fmt, carrier, cfgs, states, blocks, ns, max_dumps=None, stream=None):
+def run_library(torch, ctx, fmt, carrier, cfgs, states, blocks, ns, max_dumps=None, stream=None,
+                kernels=None):
     """Run consecutive blocks through one plan; returns per-block host results
-    [(out, dump_n, n_dumps, status)] and the final host states."""
+    [(out, dump_n, n_dumps, status)] and the final host states.  ``kernels``:
+    GC_KERNEL_* mask for the plan (None: the library default)."""
     from paper_1907_00463_amd import gnsscorr as g
 
     plan = g.Plan(ctx, fmt, carrier, cfgs)
     try:
+        if kernels is not None:
+            g.gc_plan_set_kernels(plan.handle, kernels)
         st_dev = plan.states_to_device(states)
         res = []
         for buf, n in zip(blocks, ns):

@@ -212,9 +212,13 @@ def test_fp32_carrier_within_tolerance(g, ctx, fmt):
     print("worst relative |P| error", worst)
 
 
+KERNEL_SETS = {"default": None, "binned": 2, "direct": 0}
+
+
+@pytest.mark.parametrize("kernels", list(KERNEL_SETS))
 @pytest.mark.parametrize("fs", [4.092e6, 8.184e6, 16.368e6, 20.46e6, 5e6])
 @pytest.mark.parametrize("fmt", [0, 2])
-def test_binned_epl_rates_bit_exact(g, ctx, fs, fmt):
+def test_binned_epl_rates_bit_exact(g, ctx, fs, fmt, kernels):
     # E/P/L channels at the workloads' sample rates, several tiles per block,
     # dumps of 1, 4 and 20 periods, Doppler of either sign
     rng = np.random.default_rng(int(fs) % 100000 + fmt)
@@ -229,9 +233,77 @@ def test_binned_epl_rates_bit_exact(g, ctx, fs, fmt):
                                   float(rng.uniform(0, 1023 * T)), T)
     lens = [300000, 123456 * 4]
     blocks = _random_blocks(rng, fmt, lens)
+    lib, lst = run_library(torch, ctx, fmt, g.GC_CARRIER_LUT, cfgs, states, blocks, lens,
+                           kernels=KERNEL_SETS[kernels])
+    orc, ost = run_oracle(fmt, cfgs, states, blocks, lens)
+    assert_exact(lib, lst, orc, ost, cfgs)
+
+
+def _epl_channels_at(g, rng, fs, n_chan, ratios, periods=(1, 4, 20)):
+    """E/P/L channels at sample rate fs whose code rate is 1.023 MHz * (1 + r)
+    for r drawn from ``ratios`` (r = 0: exact half-chip bins)."""
+    cfgs = np.zeros(n_chan, g.CHAN_CFG)
+    states = np.zeros(n_chan, g.CHAN_STATE)
+    for i in range(n_chan):
+        T = periods[i % len(periods)]
+        cfgs[i] = g.make_cfg(int(rng.integers(1, 33)), [1 << 31, 0, -(1 << 31)], T)
+        r = float(ratios[i % len(ratios)])
+        states[i] = g.gc_nco_init(fs, fs / 4 + r * 1575.42e6, float(rng.random()),
+                                  1.023e6 * (1 + r), float(rng.uniform(0, 1023 * T)), T)
+    return cfgs, states
+
+
+@pytest.mark.parametrize("fs", [16.368e6, 20.46e6])
+@pytest.mark.parametrize("fmt", [0, 2])
+def test_periodic_bins_with_frequent_grid_slips(g, ctx, fs, fmt):
+    # code-rate offsets up to 5e-5 (bin-grid slips about every tile, both
+    # directions) and exactly zero (no slip), blocks that are not whole tiles
+    rng = np.random.default_rng(int(fs) % 9973 + 7 * fmt)
+    cfgs, states = _epl_channels_at(g, rng, fs, 6, [5e-5, -5e-5, 0.0, 3.1e-5, -4.4e-5, 2e-6])
+    lens = [16384 * 37 + 4 * 1001, 16384 * 5, 4 * 3]
+    blocks = _random_blocks(rng, fmt, lens)
     lib, lst = run_library(torch, ctx, fmt, g.GC_CARRIER_LUT, cfgs, states, blocks, lens)
     orc, ost = run_oracle(fmt, cfgs, states, blocks, lens)
     assert_exact(lib, lst, orc, ost, cfgs)
+
+
+def test_periodic_bins_more_channels_than_one_block(g, ctx):
+    # 37 channels: three channel groups of the periodic kernel, with two
+    # channels too fast for it (binned path) and one 2-tap channel (direct)
+    rng = np.random.default_rng(37)
+    fs = 16.368e6
+    cfgs, states = _epl_channels_at(g, rng, fs, 37, [1e-6, -2e-6, 3e-6, 2e-4])
+    cfgs[3] = g.make_cfg(9, [0, 1 << 30], 1)  # its state was drawn for 1-period dumps
+    lens = [16384 * 9 + 4 * 77]
+    blocks = _random_blocks(rng, 2, lens)
+    lib, lst = run_library(torch, ctx, 2, g.GC_CARRIER_LUT, cfgs, states, blocks, lens)
+    orc, ost = run_oracle(2, cfgs, states, blocks, lens)
+    assert_exact(lib, lst, orc, ost, cfgs)
+
+
+def test_twelve_channel_workload_full_size_bit_exact(g, ctx):
+    # the 10 s, 12-channel, 2-bit 16.368 MHz workload in the benchmark's
+    # launch configuration, every dump of every channel against the oracle
+    from concurrent.futures import ThreadPoolExecutor
+
+    from paper_1907_00463_amd import synth
+    st, chans, rng = synth.workload_twelve_channels()
+    buf = synth.synth_samples(st, rng)
+    cfgs, states = _cfgs_states_for(g, st, chans)
+    lib, lst = run_library(torch, ctx, st.fmt, g.GC_CARRIER_LUT, cfgs, states, [buf], [st.n])
+    sts = [None] * len(cfgs)
+
+    def one(i):
+        sub = cfgs[i: i + 1]
+        r, s = run_oracle(st.fmt, sub, states[i: i + 1], [buf], [st.n])
+        sts[i] = s[0]
+        return r[0][0][0], r[0][1][0]
+
+    with ThreadPoolExecutor(max_workers=min(12, 16)) as ex:
+        parts = list(ex.map(one, range(len(cfgs))))
+    orc = [([p[0] for p in parts], [p[1] for p in parts])]
+    assert int(lib[0][2].min()) == 10000
+    assert_exact(lib, lst, orc, sts, cfgs)
 
 
 def test_binned_epl_permuted_taps_and_mixed_channels(g, ctx):
