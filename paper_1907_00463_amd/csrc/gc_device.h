@@ -11,7 +11,14 @@ constexpr int kTabG2 = 32;    // 32 words: G2 sequence
 constexpr int kTabLut = 64;   // 256 words: (cos low 16 | sin high 16), int16 each
 constexpr int kTabExpand = 320;  // 512 words: packed 2-bit byte -> its 4 samples as int16 (2 words)
 constexpr int kTabSign = 832;    // 32 PRNs x kSignLen words: chip i -> (s, s) int16, s = +-1
-constexpr int kSignLen = 1023 + 1152;  // chip index 0..1022 followed by a wrapped copy
+
+// Periodic form (half chips of exactly 8 or 10 samples): tile length, and
+// the most 64-bin steps one lane makes in a tile (at most tile/8 + 2 bins).
+constexpr int kPbinTileSamples = 23552;
+constexpr int kPbinMaxSteps = (kPbinTileSamples / 8 + 2 + 63) / 64;
+// chip index 0..1022 followed by a wrapped copy long enough for a run of
+// periodic steps (32 chips per step, read one step ahead) from any chip
+constexpr int kSignLen = 1023 + 32 * (kPbinMaxSteps + 2);
 constexpr int kTabWords = kTabSign + 32 * kSignLen;
 constexpr int kLutAbsSumMax = 34;  // max over l of |cos_l| + |sin_l| at amplitude 24
 
@@ -74,7 +81,6 @@ __device__ __forceinline__ bool binned_ok(int fmt, uint64_t dp) {
 
 // Periodic form: half chips of exactly L samples (L = 8 or 10), with at most
 // one one-sample slip of the bin grid per tile of kPbinTileSamples samples.
-constexpr int kPbinTileSamples = 16384;
 __device__ __forceinline__ int periodic_bin_len(int fmt, uint64_t dp) {
     if (dp == 0 || dp >= (1ull << 31)) return 0;
     const uint64_t L = ((1ull << 31) + dp / 2) / dp;  // nearest integer to 2^31 / dp

@@ -47,6 +47,10 @@ constexpr int kXB = kXA + kXBytes;             // copy B: B[i] = x[t0 + i + 1]
 constexpr int kLdsBytes = kXB + kXBytes;
 constexpr int kMaxWaves = 16;                  // one channel per wave
 constexpr uint32_t kPermSel = 0x0C0C0700u;     // byte1 = phase[31:24], byte0 = lane*4
+static_assert(kPbinMaxSteps * 3 * GC_LUT_AMP * 8 <= 32767, "2-bit int16 sums, L = 8");
+static_assert((kTile / 10 + 2 + 63) / 64 * 3 * GC_LUT_AMP * 10 <= 32767, "2-bit int16 sums, L = 10");
+static_assert(kCodeLen - 1 + 32 * (kPbinMaxSteps + 1) + 2 <= kSignLen, "sign table padding");
+static_assert(kLdsBytes + 4 * (kMaxWaves + 1) <= 160 * 1024, "LDS per block");
 
 typedef short short2_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ short2_t as_s2(uint32_t v) { return __builtin_bit_cast(short2_t, v); }
@@ -70,7 +74,8 @@ struct Dest {
 // Persistent per-wave state of its channel: the E/P/L sums of the open dump
 // (I, Q each; Q holds +x*s), as int32 and, for 2-bit input, as packed int16
 // partial sums folded into the int32 ones at the end of every tile and
-// before a flush (at most 33 bins of |sum| <= 720 per lane per tile).
+// before a flush (at most kPbinMaxSteps bins of |sum| <= 3*24*L per lane per
+// tile).
 struct Slot {
     int v[6];
     short2_t e16, p16, l16;
@@ -127,18 +132,22 @@ template <int L>
 __device__ __forceinline__ short2_t bin_sum(const uint8_t* lds, uint32_t xaddr, uint32_t ph,
                                            const uint32_t (&roff)[L / 2], const uint32_t (&poff)[L],
                                            uint32_t lane4) {
-    short2_t a = {0, 0};
+    // all reads first, then the multiply-adds
+    uint32_t xw[L / 2], cs[L];
+#pragma unroll
+    for (int j = 0; j < L / 2; ++j) xw[j] = lds_u32(lds, xaddr + roff[j]);
+#pragma unroll
+    for (int i = 0; i < L; ++i) cs[i] = lds_u32(lds, __builtin_amdgcn_perm(ph + poff[i], lane4, kPermSel));
+    short2_t a = {0, 0}, b = {0, 0};  // even and odd samples: two independent chains
 #pragma unroll
     for (int j = 0; j < L / 2; ++j) {
-        const short2_t xw = as_s2(lds_u32(lds, xaddr + roff[j]));
-        const short2_t c0 = as_s2(lds_u32(lds, __builtin_amdgcn_perm(ph + poff[2 * j], lane4, kPermSel)));
-        const short2_t c1 = as_s2(lds_u32(lds, __builtin_amdgcn_perm(ph + poff[2 * j + 1], lane4, kPermSel)));
-        const short2_t x0 = {xw.x, xw.x};
-        const short2_t x1 = {xw.y, xw.y};
-        a = x0 * c0 + a;
-        a = x1 * c1 + a;
+        const short2_t w = as_s2(xw[j]);
+        const short2_t x0 = {w.x, w.x};
+        const short2_t x1 = {w.y, w.y};
+        a = x0 * as_s2(cs[2 * j]) + a;
+        b = x1 * as_s2(cs[2 * j + 1]) + b;
     }
-    return a;
+    return a + b;
 }
 
 // Bins [kb, ke) of the current tile, bin k starting at tile sample
@@ -179,7 +188,9 @@ __device__ __forceinline__ void periodic_run(Slot& S, const uint8_t* lds, uint32
     // table repeats the code so that the offset only grows within a run
     uint32_t soff = 4u * (((hk0 >> 1) + par + kCodeLen - 1) % kCodeLen);
     const uint8_t* sgb = reinterpret_cast<const uint8_t*>(sgn_prn);
-    uint2 sg = *reinterpret_cast<const uint2*>(sgb + soff);
+    // signs of steps j and j + 1 (fetched two steps ahead of their use)
+    uint2 sg0 = *reinterpret_cast<const uint2*>(sgb + soff);
+    uint2 sg1 = *reinterpret_cast<const uint2*>(sgb + soff + 128u);
 
     constexpr uint32_t dx = 64u * 2u * L;
     const uint32_t dph = (uint32_t)(64 * L) * m.dphi;
@@ -192,26 +203,37 @@ __device__ __forceinline__ void periodic_run(Slot& S, const uint8_t* lds, uint32
         const uint32_t h_cross = 2u * S.wnext;
         const uint32_t jx = h_cross > hfirst + 63u ? (h_cross - hfirst - 63u + 63u) / 64u : 0u;
         const uint32_t jend = min(max(jx, j), full);
-        for (; j < jend; ++j) {
-            const uint2 sn = *reinterpret_cast<const uint2*>(sgb + soff + 128u);
-            const short2_t a = bin_sum<L>(lds, xaddr, ph, roff, poff, lane4);
-            add_bin<FMT>(S, a, sg, par);
-            sg = sn;
+        for (; j + 2 <= jend; j += 2) {
+            const short2_t a0 = bin_sum<L>(lds, xaddr, ph, roff, poff, lane4);
+            const short2_t a1 = bin_sum<L>(lds, xaddr + dx, ph + dph, roff, poff, lane4);
+            add_bin<FMT>(S, a0, sg0, par);
+            add_bin<FMT>(S, a1, sg1, par);
+            sg0 = *reinterpret_cast<const uint2*>(sgb + soff + 256u);
+            sg1 = *reinterpret_cast<const uint2*>(sgb + soff + 384u);
+            soff += 256u;
+            xaddr += 2u * dx;
+            ph += 2u * dph;
+        }
+        if (j < jend) {
+            const short2_t a0 = bin_sum<L>(lds, xaddr, ph, roff, poff, lane4);
+            add_bin<FMT>(S, a0, sg0, par);
+            sg0 = sg1;
+            sg1 = *reinterpret_cast<const uint2*>(sgb + soff + 256u);
             soff += 128u;
             xaddr += dx;
             ph += dph;
+            ++j;
         }
         if (j >= steps) break;
         // a step with a dump boundary, or the ragged last step
         {
-            const uint2 sn = *reinterpret_cast<const uint2*>(sgb + soff + 128u);
             const uint32_t k = k0 + 64u * j;
             const bool valid = k < ke;
             const uint32_t c = (hk0 + 64u * j) >> 1;
             const bool ahead = valid && c >= S.wnext;
             short2_t a = bin_sum<L>(lds, valid ? xaddr : (uint32_t)kXA, ph, roff, poff, lane4);
             if (!valid) a = short2_t{0, 0};
-            if (valid && !ahead) add_bin<FMT>(S, a, sg, par);
+            if (valid && !ahead) add_bin<FMT>(S, a, sg0, par);
             if (__ballot(ahead) != 0) {
                 fold16<FMT>(S);
                 wave_flush(S, d, ch);
@@ -219,9 +241,10 @@ __device__ __forceinline__ void periodic_run(Slot& S, const uint8_t* lds, uint32
                 for (int q = 0; q < 6; ++q) S.v[q] = 0;
                 S.w += 1;
                 S.wnext += span;
-                if (ahead) add_bin<FMT>(S, a, sg, par);
+                if (ahead) add_bin<FMT>(S, a, sg0, par);
             }
-            sg = sn;
+            sg0 = sg1;
+            sg1 = *reinterpret_cast<const uint2*>(sgb + soff + 256u);
             soff += 128u;
             xaddr += dx;
             ph += dph;
@@ -299,47 +322,83 @@ __device__ __forceinline__ void seam_sample(const uint8_t* lds, uint32_t lane4, 
     }
 }
 
+// Two 2-bit codes (bits 0-1 and 2-3 of nib) -> packed int16 samples 2c - 3.
+__device__ __forceinline__ uint32_t expand2(uint32_t nib) {
+    const short2_t c = as_s2((nib * 0x4001u) & 0x00030003u);
+    const short2_t two = {2, 2}, m3 = {-3, -3};
+    return __builtin_bit_cast(uint32_t, c * two + m3);
+}
+
 // Tile samples [t0, t0 + kXSamples) into copies A and B (int16; zero past
 // the end of the block).
 template <int FMT>
 __device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, uint64_t n,
-                                           uint64_t t0, uint8_t* lds, const uint32_t* tables,
-                                           int nthreads) {
-    uint2* dA = reinterpret_cast<uint2*>(lds + kXA);
-    uint2* dB = reinterpret_cast<uint2*>(lds + kXB);
+                                           uint64_t t0, uint8_t* lds, int nthreads) {
+    static_assert(kXSamples % 16 == 0, "staging granule");
+    uint4* dA = reinterpret_cast<uint4*>(lds + kXA);
+    uint4* dB = reinterpret_cast<uint4*>(lds + kXB);
     if constexpr (FMT == GC_I2_REAL) {
-        const uint64_t nbytes = (n + 3) / 4;
-        const uint64_t b0 = t0 / 4;
-        for (int i = threadIdx.x; i < kXSamples / 4; i += nthreads) {
-            const uint64_t b = b0 + i;
-            uint32_t e0 = 0, e1 = 0, f0 = 0;
-            if (b < nbytes) {
-                const uint32_t* e = tables + kTabExpand + 2 * samples[b];
-                e0 = e[0];
-                e1 = e[1];
+        // one input dword (16 samples) per thread and pass
+        const uint8_t* src = samples + t0 / 4;
+        const uint32_t avail = (uint32_t)min((n - t0 + 3) / 4, (uint64_t)kXSamples / 4);  // bytes
+        for (int i = threadIdx.x; i < kXSamples / 16; i += nthreads) {
+            const uint32_t b = 4u * i;
+            uint32_t v = 0, nx = 0;
+            if (b + 4 <= avail) {
+                v = *reinterpret_cast<const uint32_t*>(src + b);
+            } else {
+                for (uint32_t q = 0; q < 4; ++q)
+                    if (b + q < avail) v |= (uint32_t)src[b + q] << (8 * q);
             }
-            if (b + 1 < nbytes) f0 = tables[kTabExpand + 2 * samples[b + 1]];
-            dA[i] = uint2{e0, e1};
-            dB[i] = uint2{__builtin_amdgcn_alignbit(e1, e0, 16), __builtin_amdgcn_alignbit(f0, e1, 16)};
+            if (b + 4 < avail) nx = src[b + 4];
+            uint32_t w[9];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) w[k] = expand2((v >> (4 * k)) & 15u);
+            w[8] = expand2(nx & 15u);
+            if (b + 4 > avail) {  // samples past the block read as zero
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    if (b + k / 2 >= avail) w[k] = 0;
+            }
+            if (b + 4 >= avail) w[8] = 0;
+            dA[2 * i] = uint4{w[0], w[1], w[2], w[3]};
+            dA[2 * i + 1] = uint4{w[4], w[5], w[6], w[7]};
+            uint32_t u[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) u[k] = __builtin_amdgcn_alignbit(w[k + 1], w[k], 16);
+            dB[2 * i] = uint4{u[0], u[1], u[2], u[3]};
+            dB[2 * i + 1] = uint4{u[4], u[5], u[6], u[7]};
         }
     } else {
-        for (int i = threadIdx.x; i < kXSamples / 4; i += nthreads) {
-            const uint64_t b = t0 + 4ull * i;
-            uint32_t v = 0, nx = 0;
-            if (b + 4 <= n) {
-                v = *reinterpret_cast<const uint32_t*>(samples + b);
+        // 16 int8 samples per thread and pass
+        const uint8_t* src = samples + t0;
+        const uint32_t avail = (uint32_t)min(n - t0, (uint64_t)kXSamples);
+        for (int i = threadIdx.x; i < kXSamples / 16; i += nthreads) {
+            const uint32_t b = 16u * i;
+            uint32_t v[5] = {0, 0, 0, 0, 0};
+            if (b + 16 <= avail) {
+                const uint4 q = *reinterpret_cast<const uint4*>(src + b);
+                v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
             } else {
-                for (int j = 0; j < 4; ++j)
-                    if (b + j < n) v |= (uint32_t)samples[b + j] << (8 * j);
+                for (uint32_t q = 0; q < 16; ++q)
+                    if (b + q < avail) v[q / 4] |= (uint32_t)src[b + q] << (8 * (q % 4));
             }
-            if (b + 4 < n) nx = samples[b + 4];
-            const uint32_t s0 = (uint16_t)(int16_t)(int8_t)(v & 0xFF);
-            const uint32_t s1 = (uint16_t)(int16_t)(int8_t)((v >> 8) & 0xFF);
-            const uint32_t s2 = (uint16_t)(int16_t)(int8_t)((v >> 16) & 0xFF);
-            const uint32_t s3 = (uint16_t)(int16_t)(int8_t)(v >> 24);
-            const uint32_t s4 = (uint16_t)(int16_t)(int8_t)nx;
-            dA[i] = uint2{s0 | (s1 << 16), s2 | (s3 << 16)};
-            dB[i] = uint2{s1 | (s2 << 16), s3 | (s4 << 16)};
+            if (b + 16 < avail) v[4] = src[b + 16];
+            uint32_t w[9];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const uint32_t d = v[k / 2] >> (16 * (k % 2));
+                w[k] = (uint32_t)(uint16_t)(int16_t)(int8_t)(d & 0xFF) |
+                       ((uint32_t)(uint16_t)(int16_t)(int8_t)((d >> 8) & 0xFF) << 16);
+            }
+            w[8] = (uint32_t)(uint16_t)(int16_t)(int8_t)(v[4] & 0xFF);
+            dA[2 * i] = uint4{w[0], w[1], w[2], w[3]};
+            dA[2 * i + 1] = uint4{w[4], w[5], w[6], w[7]};
+            uint32_t u[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) u[k] = __builtin_amdgcn_alignbit(w[k + 1], w[k], 16);
+            dB[2 * i] = uint4{u[0], u[1], u[2], u[3]};
+            dB[2 * i + 1] = uint4{u[4], u[5], u[6], u[7]};
         }
     }
 }
@@ -479,7 +538,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) void k_pbin(const uint8_t* __restri
         const uint64_t t0 = (uint64_t)tile * kTile;
         const uint64_t t1 = min(n, t0 + kTile);
         __syncthreads();
-        stage_tile<FMT>(samples, n, t0, s_lds, tables, nthreads);
+        stage_tile<FMT>(samples, n, t0, s_lds, nthreads);
         __syncthreads();
         if (active) {
             if (m.bin_len == 8)
