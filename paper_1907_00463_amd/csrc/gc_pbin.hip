@@ -16,9 +16,10 @@
 //   * lane l of a wave takes bins k0 + 64j + l, j = 0, 1, ...: per sample one
 //     phase add, one v_perm (address of the lane's own copy of the carrier
 //     table), one table read and one packed int16 multiply-add; per pair of
-//     samples one dword read; per bin three packed multiply-adds with the
-//     E/P/L code signs of its chip (two consecutive entries of a sign table,
-//     fetched one step ahead);
+//     samples one dword read; per bin two packed multiply-adds with the
+//     early and late code signs of its chip (two consecutive entries of a
+//     sign table, fetched two steps ahead) -- the prompt sign of a bin is its
+//     early or its late sign, fixed for a lane over a run;
 //   * with L = 8, bins start 4 dwords apart, so the lanes of each 8-lane
 //     group read the dwords of their bin in a rotated order and one read
 //     instruction touches 64 distinct LDS banks (L = 10: 5 dwords apart,
@@ -71,26 +72,36 @@ struct Dest {
     }
 };
 
-// Persistent per-wave state of its channel: the E/P/L sums of the open dump
-// (I, Q each; Q holds +x*s), as int32 and, for 2-bit input, as packed int16
-// partial sums folded into the int32 ones at the end of every tile and
-// before a flush (at most kPbinMaxSteps bins of |sum| <= 3*24*L per lane per
-// tile).
+// Persistent per-wave state of its channel: the E, P, L sums of the open
+// dump (I, Q each; Q holds +x*s) as int32, and the sums of the current run.
+// Within a run every bin of a lane lies in the same half of its chip, so
+// its prompt sign equals its early sign (first half) or its late sign
+// (second half): a run accumulates only E and L, and fold() adds the one of
+// them that matches the lane's half to P.  For 2-bit input the run sums are
+// packed int16 (at most kPbinMaxSteps bins of |sum| <= 3*24*L per lane).
 struct Slot {
-    int v[6];
-    short2_t e16, p16, l16;
-    uint32_t w;        // dump of the open sums (wave-uniform)
-    uint32_t wnext;    // first chip of dump w + 1
+    int v[6];              // E I, E Q, P I, P Q, L I, L Q
+    short2_t e16, l16;     // run sums, 2-bit input
+    int r[4];              // run sums, int8 input: E I, E Q, L I, L Q
+    uint32_t w;            // dump of the open sums (wave-uniform)
+    uint32_t wnext;        // first chip of dump w + 1
     bool init;
 };
 
 template <int FMT>
-__device__ __forceinline__ void fold16(Slot& s) {
+__device__ __forceinline__ void fold(Slot& s, uint32_t par) {
     if constexpr (FMT == GC_I2_REAL) {
+        const short2_t p = par ? s.l16 : s.e16;
         s.v[0] += s.e16.x; s.v[1] += s.e16.y;
-        s.v[2] += s.p16.x; s.v[3] += s.p16.y;
+        s.v[2] += p.x;     s.v[3] += p.y;
         s.v[4] += s.l16.x; s.v[5] += s.l16.y;
-        s.e16 = s.p16 = s.l16 = short2_t{0, 0};
+        s.e16 = s.l16 = short2_t{0, 0};
+    } else {
+        s.v[0] += s.r[0]; s.v[1] += s.r[1];
+        s.v[2] += par ? s.r[2] : s.r[0];
+        s.v[3] += par ? s.r[3] : s.r[1];
+        s.v[4] += s.r[2]; s.v[5] += s.r[3];
+        s.r[0] = s.r[1] = s.r[2] = s.r[3] = 0;
     }
 }
 
@@ -106,23 +117,18 @@ __device__ __forceinline__ void wave_flush(const Slot& s, const Dest& d, const D
     }
 }
 
-// Bin sum a with code signs (sL, sE) of chips (c + par - 1, c + par), each
-// a packed (s, s) int16 word; the prompt sign is sL for the second half of a
-// chip (par = 1) and sE for the first.
+// Bin sum a with the code signs sg = (sL, sE) of chips (c + par - 1,
+// c + par), each a packed (s, s) int16 word, into the run's E and L sums.
 template <int FMT>
-__device__ __forceinline__ void add_bin(Slot& s, short2_t a, uint2 sg, uint32_t par) {
-    const uint32_t sP = par ? sg.x : sg.y;
+__device__ __forceinline__ void add_bin(Slot& s, short2_t a, uint2 sg) {
     if constexpr (FMT == GC_I2_REAL) {
         s.e16 = a * as_s2(sg.y) + s.e16;
-        s.p16 = a * as_s2(sP) + s.p16;
         s.l16 = a * as_s2(sg.x) + s.l16;
     } else {
         const int ai = a.x, aq = a.y;
-        const int e = (int)(short)(sg.y & 0xFFFF), p = (int)(short)(sP & 0xFFFF),
-                  l = (int)(short)(sg.x & 0xFFFF);
-        s.v[0] += ai * e; s.v[1] += aq * e;
-        s.v[2] += ai * p; s.v[3] += aq * p;
-        s.v[4] += ai * l; s.v[5] += aq * l;
+        const int e = (int)(short)(sg.y & 0xFFFF), l = (int)(short)(sg.x & 0xFFFF);
+        s.r[0] += ai * e; s.r[1] += aq * e;
+        s.r[2] += ai * l; s.r[3] += aq * l;
     }
 }
 
@@ -206,8 +212,8 @@ __device__ __forceinline__ void periodic_run(Slot& S, const uint8_t* lds, uint32
         for (; j + 2 <= jend; j += 2) {
             const short2_t a0 = bin_sum<L>(lds, xaddr, ph, roff, poff, lane4);
             const short2_t a1 = bin_sum<L>(lds, xaddr + dx, ph + dph, roff, poff, lane4);
-            add_bin<FMT>(S, a0, sg0, par);
-            add_bin<FMT>(S, a1, sg1, par);
+            add_bin<FMT>(S, a0, sg0);
+            add_bin<FMT>(S, a1, sg1);
             sg0 = *reinterpret_cast<const uint2*>(sgb + soff + 256u);
             sg1 = *reinterpret_cast<const uint2*>(sgb + soff + 384u);
             soff += 256u;
@@ -216,7 +222,7 @@ __device__ __forceinline__ void periodic_run(Slot& S, const uint8_t* lds, uint32
         }
         if (j < jend) {
             const short2_t a0 = bin_sum<L>(lds, xaddr, ph, roff, poff, lane4);
-            add_bin<FMT>(S, a0, sg0, par);
+            add_bin<FMT>(S, a0, sg0);
             sg0 = sg1;
             sg1 = *reinterpret_cast<const uint2*>(sgb + soff + 256u);
             soff += 128u;
@@ -233,15 +239,15 @@ __device__ __forceinline__ void periodic_run(Slot& S, const uint8_t* lds, uint32
             const bool ahead = valid && c >= S.wnext;
             short2_t a = bin_sum<L>(lds, valid ? xaddr : (uint32_t)kXA, ph, roff, poff, lane4);
             if (!valid) a = short2_t{0, 0};
-            if (valid && !ahead) add_bin<FMT>(S, a, sg0, par);
+            if (valid && !ahead) add_bin<FMT>(S, a, sg0);
             if (__ballot(ahead) != 0) {
-                fold16<FMT>(S);
+                fold<FMT>(S, par);
                 wave_flush(S, d, ch);
 #pragma unroll
                 for (int q = 0; q < 6; ++q) S.v[q] = 0;
                 S.w += 1;
                 S.wnext += span;
-                if (ahead) add_bin<FMT>(S, a, sg0, par);
+                if (ahead) add_bin<FMT>(S, a, sg0);
             }
             sg0 = sg1;
             sg1 = *reinterpret_cast<const uint2*>(sgb + soff + 256u);
@@ -251,6 +257,7 @@ __device__ __forceinline__ void periodic_run(Slot& S, const uint8_t* lds, uint32
             ++j;
         }
     }
+    fold<FMT>(S, par);
 }
 
 // Direct per-sample form over tile offsets [lo, hi) for one E/P/L channel
@@ -521,7 +528,8 @@ __global__ __launch_bounds__(kMaxWaves * 64) void k_pbin(const uint8_t* __restri
     Slot S;
 #pragma unroll
     for (int q = 0; q < 6; ++q) S.v[q] = 0;
-    S.e16 = S.p16 = S.l16 = short2_t{0, 0};
+    S.e16 = S.l16 = short2_t{0, 0};
+    S.r[0] = S.r[1] = S.r[2] = S.r[3] = 0;
     S.w = 0;
     S.wnext = 0;
     S.init = false;
@@ -545,12 +553,10 @@ __global__ __launch_bounds__(kMaxWaves * 64) void k_pbin(const uint8_t* __restri
                 channel_tile<FMT, 8>(S, s_lds, lane, lane4, t0, t1, m, ch, sgn_prn, d);
             else
                 channel_tile<FMT, 10>(S, s_lds, lane, lane4, t0, t1, m, ch, sgn_prn, d);
-            fold16<FMT>(S);
         }
     }
     // the dump still open at the end of the chunk
     if (active && S.init) {
-        fold16<FMT>(S);
         wave_flush(S, d, ch);
     }
 }
