@@ -89,14 +89,86 @@ def cpu_baseline(st, buf, cfgs, states, seconds: float = 10.0):
                          realtime_channels(len(cfgs), n / st.fs, dt))}
 
 
+KERNEL_SETS = {"auto": None, "binned": 2, "direct": 0}
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_pbin_i2_12ch_10s_counters.md")
+
+
+def kernel_source_tag() -> str:
+    import hashlib
+    src = os.path.join(ROOT, "paper_1907_00463_amd", "csrc", "gc_pbin.hip")
+    with open(src, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def recorded_traffic():
+    """HBM bytes per launch of the periodic kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a copy of known size), or
+    None when the kernel source has changed since those counters were taken."""
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            text = f.read()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    if fields.get("kernel_source_sha256_16") != kernel_source_tag():
+        return None
+    try:
+        return int(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def time_steps(torch, step, steps, warmup):
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def plain_baseline(torch, g, ctx, st, cfgs, states, samples, n, max_dumps, stream, steps, warmup):
+    """Plain per-channel launches: one plan and one launch per channel, each
+    with the direct per-sample kernel, on the same stream and inputs."""
+    plans, bufs = [], []
+    for i in range(len(cfgs)):
+        p = g.Plan(ctx, st.fmt, g.GC_CARRIER_LUT, cfgs[i: i + 1])
+        g.gc_plan_set_kernels(p.handle, 0)
+        s0 = p.states_to_device(states[i: i + 1])
+        plans.append(p)
+        bufs.append((s0, s0.clone()) + p.outputs(max_dumps))
+
+    def step():
+        for p, (s0, s, out, dn, nd, stt) in zip(plans, bufs):
+            s.copy_(s0)
+            p.correlate(samples, n, s, out, dn, nd, stt, stream=stream)
+
+    dt = time_steps(torch, step, steps, warmup)
+    for p in plans:
+        p.close()
+    return dt
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seconds", type=float, default=10.0, help="data per step (workload: 10 s)")
+    ap.add_argument("--kernels", choices=list(KERNEL_SETS), default="auto",
+                    help="kernel families the plan may use (auto: all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the per-channel launch baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="before timing, copy a buffer of this many MiB once (a kernel of known "
+                         "traffic that scales the HBM byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the correlator shards by receiver or channel "
@@ -117,6 +189,8 @@ def main():
     n = st.n
     ctx = g.gc_create(0)
     plan = g.Plan(ctx, st.fmt, g.GC_CARRIER_LUT, cfgs)
+    if KERNEL_SETS[args.kernels] is not None:
+        g.gc_plan_set_kernels(plan.handle, KERNEL_SETS[args.kernels])
     samples = torch.from_numpy(buf).to(dev)
     state0 = plan.states_to_device(states)
     state = state0.clone()
@@ -127,6 +201,13 @@ def main():
     def step():
         state.copy_(state0)
         plan.correlate(samples, n, state, out, dump_n, n_dumps, status, stream=stream)
+
+    if args.copy_probe_mib > 0:
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     print("bench: warmup %d" % args.warmup, file=sys.stderr, flush=True)
     for _ in range(args.warmup):
@@ -168,15 +249,25 @@ def main():
         "config": {"workload": "12 channels, 2-bit real, fs 16.368 MHz, IF 4.092 MHz, "
                                "%g s, 1 ms dumps, E/P/L at +-1/2 chip" % args.seconds,
                    "channels": len(cfgs), "taps_per_channel": 3, "samples": n,
-                   "format": "i2_real", "dumps_per_channel": int(nd.max()),
+                   "format": "i2_real", "kernels": args.kernels,
+                   "dumps_per_channel": int(nd.max()),
                    "realtime_channels": round(realtime_channels(len(cfgs), n / st.fs,
                                                                 wall / args.steps), 1)},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                      "peak": round(VALU_PEAK_TOPS, 2), "unit": "T lane-ops/s",
-                     "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                     "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                     "traffic": recorded_traffic() if args.kernels == "auto" else None,
                      "kernel_ms": round(k_s * 1e3, 4),
                      "ops_per_sample_channel": OPS_PER_SAMPLE_CHANNEL},
     }
+    if not args.no_plain:
+        print("bench: plain per-channel launches", file=sys.stderr, flush=True)
+        dt = plain_baseline(torch, g, ctx, st, cfgs, states, samples, n, max_dumps, stream,
+                            max(1, min(args.steps, 5)), 1)
+        res["plain"] = {"value": round(sample_taps / dt / 1e9, 3), "unit": "G sample·taps/s",
+                        "ms_per_step": round(dt * 1e3, 4),
+                        "kind": "one plan and one direct-kernel launch per channel",
+                        "speedup": round(dt / (wall / args.steps), 2)}
     if not args.no_cpu_baseline:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(st, buf, cfgs, states, args.cpu_seconds)

@@ -80,16 +80,16 @@ hipError_t launch_code_table(const uint32_t* d_tables, int g2_delay, int8_t* d_o
 }
 
 // ---------------------------------------------------------------------------
-// Per-call set-up, one block per channel:
+// Per-call set-up, one block per channel (k_setup):
 //   * validate the channel state and compute M = floor(U_N / W), the number
 //     of dumps this block closes;
-//   * write rows 0..M-1 of the outputs (row 0 starts from the open dump
-//     carried in the state, the others from zero) and their sample counts;
+//   * start output row 0 from the open dump carried in the state;
 //   * move the NCO words of the state to the end of the block.
+// then k_rows clears rows 1..M-1 and writes the sample count of every row.
 // The accumulation kernels read the start-of-block NCO words from DevMeta
 // and add into the rows (windows < M) or into the state's open dump (M).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_setup(const DevChan* __restrict__ chans,
+__global__ __launch_bounds__(64) void k_setup(const DevChan* __restrict__ chans,
                                                DevMeta* __restrict__ metas,
                                                gc_chan_state* __restrict__ state,
                                                uint64_t n, int fmt, int carrier,
@@ -167,35 +167,30 @@ __global__ __launch_bounds__(256) void k_setup(const DevChan* __restrict__ chans
     if (m.status != GC_OK) return;
     const uint32_t M = m.m_close;
     const int K = c.n_taps;
-    for (uint32_t r = tid; r < M; r += blockDim.x) {
-        const uint64_t s0 = r == 0 ? 0 : (r * m.window - m.p0 + m.dp - 1) / m.dp;
-        const uint64_t s1 = ((r + 1) * m.window - m.p0 + m.dp - 1) / m.dp;
-        dump_n[(uint64_t)ch * max_dumps + r] = (uint32_t)(s1 - s0) + (r == 0 ? m.acc_n0 : 0u);
-        const uint64_t row = ((uint64_t)ch * max_dumps + r) * tap_stride * 2;
-        if (carrier == GC_CARRIER_LUT) {
-            int32_t* o = (int32_t*)out + row;
-            for (int k = 0; k < K; ++k) {
-                o[2 * k] = r == 0 ? st->acc[k][0] : 0;
-                o[2 * k + 1] = r == 0 ? st->acc[k][1] : 0;
-            }
-        } else {
-            float* o = (float*)out + row;
-            for (int k = 0; k < K; ++k) {
-                o[2 * k] = r == 0 ? st->acc_f[k][0] : 0.0f;
-                o[2 * k + 1] = r == 0 ? st->acc_f[k][1] : 0.0f;
-            }
-        }
-    }
-    __syncthreads();
+    // row 0 starts with the dump carried in the state; the state's open dump
+    // restarts at zero when at least one window closes in this block
+    // (rows 1 .. M-1 are cleared by k_rows)
     if (M >= 1) {
+        const uint64_t row = (uint64_t)ch * max_dumps * tap_stride * 2;
         for (int k = tid; k < K; k += blockDim.x) {
-            if (carrier == GC_CARRIER_LUT) { st->acc[k][0] = 0; st->acc[k][1] = 0; }
-            else { st->acc_f[k][0] = 0.0f; st->acc_f[k][1] = 0.0f; }
+            if (carrier == GC_CARRIER_LUT) {
+                int32_t* o = (int32_t*)out + row;
+                o[2 * k] = st->acc[k][0];
+                o[2 * k + 1] = st->acc[k][1];
+                st->acc[k][0] = 0;
+                st->acc[k][1] = 0;
+            } else {
+                float* o = (float*)out + row;
+                o[2 * k] = st->acc_f[k][0];
+                o[2 * k + 1] = st->acc_f[k][1];
+                st->acc_f[k][0] = 0.0f;
+                st->acc_f[k][1] = 0.0f;
+            }
         }
     }
     if (tid == 0) {
         const uint64_t u_end = m.p0 + n * m.dp;
-        const uint64_t sM = M == 0 ? 0 : ((uint64_t)M * m.window - m.p0 + m.dp - 1) / m.dp;
+        const uint64_t sM = M == 0 ? 0 : window_start(M, m.window, m.p0, m.dp);
         st->acc_n = M == 0 ? m.acc_n0 + (uint32_t)n : (uint32_t)(n - sM);
         st->carr_phase = m.phi0 + (uint32_t)n * m.dphi;
         st->code_phase = u_end - (uint64_t)M * m.window;
@@ -204,12 +199,52 @@ __global__ __launch_bounds__(256) void k_setup(const DevChan* __restrict__ chans
     }
 }
 
+// ceil(num / d) for d >= 1: a double estimate made exact with integer checks
+// (the estimate is within one of the quotient for d >= 2^20).
+__device__ __forceinline__ uint64_t udiv_ceil(uint64_t num, uint64_t d) {
+    if (d < (1ull << 20)) return (num + d - 1) / d;
+    uint64_t q = (uint64_t)((double)num / (double)d);
+    while (q * d < num) ++q;
+    while (q > 0 && (q - 1) * d >= num) --q;
+    return q;
+}
+
+// Per-call output rows 1 .. M-1 of every channel: cleared, and the sample
+// count of each emitted dump (row 0 also holds the samples carried in).
+__global__ __launch_bounds__(256) void k_rows(const DevChan* __restrict__ chans,
+                                              const DevMeta* __restrict__ metas, int carrier,
+                                              uint32_t max_dumps, void* out, int tap_stride,
+                                              uint32_t* __restrict__ dump_n) {
+    const int ch = blockIdx.y;
+    const DevMeta m = metas[ch];
+    if (m.status != GC_OK) return;
+    const uint32_t M = m.m_close;
+    const int K = chans[ch].n_taps;
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < M; r += gridDim.x * blockDim.x) {
+        const uint64_t s0 = r == 0 ? 0 : udiv_ceil(r * m.window - m.p0, m.dp);
+        const uint64_t s1 = udiv_ceil((r + 1) * m.window - m.p0, m.dp);
+        dump_n[(uint64_t)ch * max_dumps + r] = (uint32_t)(s1 - s0) + (r == 0 ? m.acc_n0 : 0u);
+        if (r == 0) continue;
+        const uint64_t row = ((uint64_t)ch * max_dumps + r) * tap_stride * 2;
+        if (carrier == GC_CARRIER_LUT) {
+            int32_t* o = (int32_t*)out + row;
+            for (int k = 0; k < 2 * K; ++k) o[k] = 0;
+        } else {
+            float* o = (float*)out + row;
+            for (int k = 0; k < 2 * K; ++k) o[k] = 0.0f;
+        }
+    }
+}
+
 hipError_t launch_setup(const DevChan* chans, DevMeta* meta, gc_chan_state* state, int n_chan,
                         uint64_t n_samples, int fmt, int carrier, uint32_t max_dumps, void* out,
                         int tap_stride, uint32_t* dump_n, uint32_t* n_dumps, int32_t* status,
                         int32_t allow, hipStream_t s) {
-    hipLaunchKernelGGL(k_setup, dim3(n_chan), dim3(256), 0, s, chans, meta, state, n_samples, fmt,
+    hipLaunchKernelGGL(k_setup, dim3(n_chan), dim3(64), 0, s, chans, meta, state, n_samples, fmt,
                        carrier, max_dumps, out, tap_stride, dump_n, n_dumps, status, allow);
+    const uint32_t gx = min((max_dumps + 255u) / 256u, 256u);
+    hipLaunchKernelGGL(k_rows, dim3(gx, n_chan), dim3(256), 0, s, chans, meta, carrier, max_dumps,
+                       out, tap_stride, dump_n);
     return hipGetLastError();
 }
 

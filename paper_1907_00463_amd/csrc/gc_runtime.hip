@@ -319,7 +319,7 @@ gc_status gc_correlate(gc_plan* plan, const void* samples, uint64_t n_samples,
             e = gc::launch_pbin(x, n_samples, plan->fmt, plan->d_chans, plan->d_meta, state,
                                 plan->n_chan, (int32_t*)out, plan->max_taps, max_dumps,
                                 plan->ctx->d_tables, plan->epl_grid, s);
-        else if (plan->use_epl)
+        else if (binned)
             e = gc::launch_epl(x, n_samples, plan->fmt, plan->d_chans, plan->d_meta, state,
                                plan->n_chan, (int32_t*)out, plan->max_taps, max_dumps,
                                plan->ctx->d_tables, plan->epl_grid, s);
