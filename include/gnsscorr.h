@@ -169,12 +169,17 @@ gc_status gc_plan_destroy(gc_plan* plan);
  *                       grid slip (fs an integer multiple of twice the code
  *                       rate)
  *   GC_KERNEL_BINNED    any rate of >= 2^32/127 code step, chip by chip
+ *   GC_KERNEL_MTAP      plans with more than 4 taps or complex input: channels
+ *                       whose taps are all multiples of 2^27 (1/32 chip)
+ *                       spanning at most 16 chip shifts, at <= 32 samples per
+ *                       chip (two-stage int8 MFMA form, table carrier)
  * Channels that no allowed family takes, and every channel of a plan with
- * more than 4 taps, a complex format or the float carrier, use the direct
- * per-sample kernel.  Default: both bits set.  Takes effect at the next
- * gc_correlate.  Errors: GC_EINVAL (null plan, bits outside the mask). */
+ * the float carrier, use the direct per-sample kernel.  Default: all bits
+ * set.  Takes effect at the next gc_correlate.
+ * Errors: GC_EINVAL (null plan, bits outside the mask). */
 #define GC_KERNEL_PERIODIC 1
 #define GC_KERNEL_BINNED 2
+#define GC_KERNEL_MTAP 4
 gc_status gc_plan_set_kernels(gc_plan* plan, int32_t mask);
 
 /* Query: taps per dump row in the output layout (the largest n_taps of the

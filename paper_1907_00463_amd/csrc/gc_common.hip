@@ -55,6 +55,18 @@ __global__ void k_init_tables(uint32_t* tables) {
         const int i = (idx % kSignLen) % kCodeLen;
         tables[kTabSign + idx] = ca_chip(tables, c_g2_delay_dev[prn - 1], i) < 0 ? 0xFFFFFFFFu : 0x00010001u;
     }
+    // int8 codes in 4 byte-shifted copies per PRN
+    for (int idx = t; idx < 32 * 4 * kCode8Words; idx += blockDim.x) {
+        const int prn = idx / (4 * kCode8Words) + 1;
+        const int sh = (idx / kCode8Words) % 4;
+        const int w = idx % kCode8Words;
+        uint32_t word = 0;
+        for (int b = 0; b < 4; ++b) {
+            const int i = (4 * w + b + sh) % kCodeLen;
+            word |= (uint32_t)(uint8_t)ca_chip(tables, c_g2_delay_dev[prn - 1], i) << (8 * b);
+        }
+        tables[kTabCode8 + idx] = word;
+    }
     if (t < 256) {
         double ang = 6.283185307179586476925286766559 * ((double)t + 0.5) / 256.0;
         double vc = (double)GC_LUT_AMP * cos(ang);
@@ -155,6 +167,10 @@ __global__ __launch_bounds__(64) void k_setup(const DevChan* __restrict__ chans,
             }
             if (m.path == kPathDirect && epl_ok && (allow & kAllowBinned) && binned_ok(fmt, m.dp))
                 m.path = kPathBinned;
+            // dense taps on the 1/32-chip grid: at most one sample per 1/32 chip
+            if (m.path == kPathDirect && (allow & kAllowMtap) && c.mt_ok &&
+                carrier == GC_CARRIER_LUT && m.dp >= (1ull << 27))
+                m.path = kPathMtap;
         }
         m.status = s;
         metas[ch] = m;

@@ -7,7 +7,8 @@
 // form of the method: the reference path for arbitrary taps and the
 // "one launch, no binning" comparator for the binned kernels.
 //
-// Grid: x = sample tiles of kTile samples, y = channel, z = tap group of 4.
+// Grid: x = sample tiles of kTile samples (or fewer blocks looping over the
+// tiles), y = channel, z = tap group of 4.
 // A tile that straddles dump boundaries is split into per-window segments;
 // each segment ends in a block reduction and one atomic add per output
 // word (integer atomics are order-free, so results are exact).
@@ -34,7 +35,7 @@ __global__ __launch_bounds__(kThreads) void k_generic(const uint8_t* __restrict_
     const int ch = blockIdx.y;
     const int tid = threadIdx.x;
     const DevMeta m = metas[ch];
-    if (m.status != GC_OK) return;
+    if (m.status != GC_OK || m.path == kPathMtap) return;
     const int K = chans[ch].n_taps;
     const int k0 = blockIdx.z * kTapGroup;
     if (k0 >= K) return;
@@ -50,7 +51,9 @@ __global__ __launch_bounds__(kThreads) void k_generic(const uint8_t* __restrict_
     if (tid < kTapGroup) s_taps[tid] = tid < nk ? chans[ch].taps[k0 + tid] : 0;
     __syncthreads();
 
-    const uint64_t t0 = (uint64_t)blockIdx.x * kTile;
+    const uint64_t n_tiles = (n_samples + kTile - 1) / kTile;
+    for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    const uint64_t t0 = tile * kTile;
     const uint64_t t1 = min(n_samples, t0 + kTile);
     const uint64_t W = m.window;
     const uint64_t m_a = (m.p0 + t0 * m.dp) / W;
@@ -127,13 +130,15 @@ __global__ __launch_bounds__(kThreads) void k_generic(const uint8_t* __restrict_
         }
         __syncthreads();
     }
+    }
 }
 
 template <int FMT, int CARR>
 void launch_one(const uint8_t* samples, uint64_t n, const DevChan* chans, const DevMeta* meta,
                 gc_chan_state* state, int n_chan, int max_taps, void* out, int tap_stride,
-                uint32_t max_dumps, const uint32_t* tables, hipStream_t s) {
-    dim3 grid((unsigned)((n + kTile - 1) / kTile), (unsigned)n_chan,
+                uint32_t max_dumps, const uint32_t* tables, int grid_x, hipStream_t s) {
+    const uint64_t n_tiles = (n + kTile - 1) / kTile;
+    dim3 grid((unsigned)(grid_x > 0 ? min((uint64_t)grid_x, n_tiles) : n_tiles), (unsigned)n_chan,
               (unsigned)((max_taps + kTapGroup - 1) / kTapGroup));
     hipLaunchKernelGGL((k_generic<FMT, CARR>), grid, dim3(kThreads), 0, s, samples, n, chans,
                        meta, state, out, tap_stride, max_dumps, tables);
@@ -144,12 +149,13 @@ void launch_one(const uint8_t* samples, uint64_t n, const DevChan* chans, const 
 hipError_t launch_generic(const uint8_t* samples, uint64_t n, int fmt, int carrier,
                           const DevChan* chans, const DevMeta* meta, gc_chan_state* state,
                           int n_chan, int max_taps, void* out, int tap_stride,
-                          uint32_t max_dumps, const uint32_t* tables, hipStream_t s) {
+                          uint32_t max_dumps, const uint32_t* tables, int grid_x,
+                          hipStream_t s) {
     if (n == 0) return hipSuccess;
 #define GC_CASE(F, C)                                                                        \
     if (fmt == F && carrier == C) {                                                         \
         launch_one<F, C>(samples, n, chans, meta, state, n_chan, max_taps, out, tap_stride, \
-                         max_dumps, tables, s);                                             \
+                         max_dumps, tables, grid_x, s);                                     \
         return hipGetLastError();                                                          \
     }
     GC_CASE(GC_I8_REAL, GC_CARRIER_LUT)

@@ -22,6 +22,10 @@ struct DevChan {
     uint64_t window;       // W = int_periods * 1023 * 2^32
     int32_t epl;           // 1: taps are early/prompt/late at +1/2, 0, -1/2 chip
     int32_t slot_e, slot_p, slot_l;  // output tap slots of E, P, L when epl
+    int32_t mt_ok;         // every tap a multiple of 2^27 (1/32 chip) spanning <= 16 chip shifts
+    int32_t mt_jmin;       // smallest chip shift floor(d_min / 32), d = tap / 2^27
+    int32_t mt_nj;         // number of chip shifts
+    int32_t pad0;
     int64_t taps[GC_MAX_TAPS];
 };
 
@@ -38,7 +42,7 @@ struct DevMeta {
     uint32_t m_close;      // windows closed by this block (dumps emitted)
     int32_t status;        // gc_status of this channel for this call
     uint32_t acc_n0;       // samples already in the open dump
-    int32_t path;          // kPathDirect, kPathBinned or kPathPeriodic (per call, from the steps)
+    int32_t path;          // kPath* (per call, from the steps)
     uint64_t c_full0;      // first chip whose samples all lie in this block
     uint64_t c_full1;      // one past the last such chip
     uint32_t head_end;     // samples [0, head_end) precede chip c_full0
@@ -50,10 +54,12 @@ struct DevMeta {
 constexpr int32_t kPathDirect = 0;
 constexpr int32_t kPathBinned = 1;
 constexpr int32_t kPathPeriodic = 2;
+constexpr int32_t kPathMtap = 3;
 
 // Plan-level switches passed to the set-up kernel.
 constexpr int32_t kAllowBinned = 1;
 constexpr int32_t kAllowPeriodic = 2;
+constexpr int32_t kAllowMtap = 4;
 
 // Kernel launch entry points (defined in the .hip files, called by the runtime).
 hipError_t launch_make_tables(uint32_t* d_tables, hipStream_t s);
@@ -67,6 +73,10 @@ hipError_t launch_pbin(const uint8_t* samples, uint64_t n_samples, int fmt, cons
                        int tap_stride, uint32_t max_dumps, const uint32_t* d_tables, int grid,
                        hipStream_t s);
 int pbin_tile_samples();
+hipError_t launch_mtap(const uint8_t* samples, uint64_t n_samples, int fmt, const DevChan* chans,
+                       const DevMeta* meta, gc_chan_state* state, int n_chan, int32_t* out,
+                       int tap_stride, uint32_t max_dumps, const uint32_t* d_tables, int grid,
+                       hipStream_t s);
 hipError_t launch_epl(const uint8_t* samples, uint64_t n_samples, int fmt, const DevChan* chans,
                       const DevMeta* meta, gc_chan_state* state, int n_chan, int32_t* out,
                       int tap_stride, uint32_t max_dumps, const uint32_t* d_tables, int grid,
@@ -75,6 +85,7 @@ int epl_blocks_per_device(int device);
 hipError_t launch_generic(const uint8_t* samples, uint64_t n_samples, int fmt, int carrier,
                           const DevChan* chans, const DevMeta* meta, gc_chan_state* state,
                           int n_chan, int max_taps, void* out, int tap_stride,
-                          uint32_t max_dumps, const uint32_t* d_tables, hipStream_t s);
+                          uint32_t max_dumps, const uint32_t* d_tables, int grid_x,
+                          hipStream_t s);  // grid_x 0: one block per tile
 
 }  // namespace gc

@@ -1,0 +1,390 @@
+// gc_mtap.hip -- dense multi-tap correlator (many taps on a 1/32-chip grid)
+// as an exact two-stage contraction on int8 MFMA.
+//
+// Taps delta_k = d_k * 2^27 (d_k integer, 1/32 chip).  Write the code phase
+// of sample n as U_n = c_n*2^32 + q_n*2^27 + e (q_n in [0, 32), e < 2^27).
+// Then the replica chip of tap k is
+//     floor((U_n + delta_k) / 2^32) = c_n + floor((q_n + d_k) / 32),
+// so with S[q][c] = sum of the wiped-off samples whose (q_n, c_n) = (q, c)
+// (at most one sample per cell when a chip spans <= 32 samples):
+//     T[q][j] = sum_c S[q][c] * C[(c + j) mod 1023]      (stage 2, MFMA)
+//     Y_k     = sum_q T[q][floor((q + d_k) / 32)]         (stage 3)
+// Stage 1 scatters the samples into S, one 32-chip chunk at a time, in
+// LDS.  The wiped-off values (|w| <= 128*34) are split into two int8 planes,
+// w = 128*hi + lo with lo = w & 127 in [0, 127] and hi = w >> 7 in [-34, 34],
+// so that A = S (rows: I lo, I hi, Q lo, Q hi, each 32 q-rows; columns: the
+// chunk's 32 chips) and B = the chips x replica-shift matrix (16 shifts) are
+// int8 and v_mfma_i32_16x16x32_i8 with int32 accumulation is exact.  The
+// eight 16-row tiles of A accumulate over the chunks of one dump; at the
+// dump's end T = 128*T_hi + T_lo, prefix sums over q turn every tap into two
+// range sums (stage 3), and the dump is stored.
+//
+// One wave per channel (16 per block), blocks take contiguous chunks of
+// sample tiles; the tile (8 B per sample: (xI, xQ) and (xQ, -xI) as int16)
+// and a 16-copy carrier table are shared by the block's waves.  The complex
+// wipe-off is two v_dot2 per sample.
+#include "gc_device.h"
+
+namespace gc {
+
+namespace {
+
+constexpr int kWaves = 16;
+constexpr int kChunkChips = 32;                  // K of one MFMA
+constexpr int kRows = 128;                       // 4 planes x 32 q
+constexpr int kRowBytes = 40;                    // 32 chips + 8 pad (banks)
+constexpr int kPlaneBytes = 32 * kRowBytes;      // 1280
+constexpr int kSBytes = kRows * kRowBytes;       // 5120 per wave
+constexpr int kLutCopies = 16;
+constexpr int kLutStride = 257;                  // words between copies
+constexpr int kLutBytes = kLutCopies * kLutStride * 4;
+constexpr int kTile = 7040;                      // samples per tile
+constexpr int kMargin = kChunkChips * 32 + 64;   // a chunk spans <= 32 chips of <= 32 samples
+constexpr int kXSamples = kTile + kMargin;
+constexpr int kOffS = kLutBytes;
+constexpr int kOffX = kOffS + kWaves * kSBytes;
+constexpr int kOffList = kOffX + kXSamples * 8;
+constexpr int kLdsBytes = kOffList + 4 * (kWaves + 1);
+static_assert(kLdsBytes <= 160 * 1024, "LDS per block");
+static_assert(kTile % 16 == 0 && kXSamples % 16 == 0, "staging granule");
+static_assert(2 * 16 * 33 * 4 <= kSBytes, "stage-3 prefix sums fit the wave's S area");
+
+typedef short short2_t __attribute__((ext_vector_type(2)));
+typedef int int4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short2_t as_s2(uint32_t v) { return __builtin_bit_cast(short2_t, v); }
+
+__device__ __forceinline__ void wave_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// ceil(num / d), d in [2^27, 2^31): a double estimate made exact.
+__device__ __forceinline__ uint64_t ceil_div(uint64_t num, uint64_t d) {
+    uint64_t q = (uint64_t)((double)num / (double)d);
+    while (q * d < num) ++q;
+    while (q > 0 && (q - 1) * d >= num) --q;
+    return q;
+}
+
+// First sample of chip c (code phase c*2^32), 0 when it lies before the block.
+__device__ __forceinline__ uint64_t chip_first(uint64_t c, uint64_t p0, uint64_t dp) {
+    const uint64_t ph = c << 32;
+    return ph <= p0 ? 0 : ceil_div(ph - p0, dp);
+}
+
+struct Chunk {
+    uint64_t cs, ce;   // chips [cs, ce)
+    uint64_t sa, sb;   // samples [sa, sb)
+    uint32_t m;        // dump (window) index
+    bool first, last;  // first / last chunk of its dump
+};
+
+// The chunk of chip c: chips [span*m + 32a, min(+32, span*(m+1))).
+__device__ __forceinline__ Chunk chunk_of(uint64_t c, uint64_t span, uint64_t p0, uint64_t dp,
+                                          uint64_t n) {
+    Chunk k;
+    k.m = (uint32_t)(c / span);
+    const uint64_t d0 = (uint64_t)k.m * span;
+    k.cs = d0 + ((c - d0) / kChunkChips) * kChunkChips;
+    k.ce = min(k.cs + kChunkChips, d0 + span);
+    k.first = k.cs == d0;
+    k.last = k.ce == d0 + span;
+    k.sa = min(n, chip_first(k.cs, p0, dp));
+    k.sb = min(n, chip_first(k.ce, p0, dp));
+    return k;
+}
+
+// Tile samples [t0, t0 + kXSamples) as two int16 pairs each: (xI, xQ) and
+// (xQ, -xI) (real input: (x, 0) and (0, -x)); zero past the block.
+template <int FMT>
+__device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, uint64_t n,
+                                           uint64_t t0, uint8_t* lds, int nthreads) {
+    uint4* dst = reinterpret_cast<uint4*>(lds + kOffX);
+    const uint32_t avail = (uint32_t)min(n - t0, (uint64_t)kXSamples);
+    // two samples (16 bytes of LDS) per thread and pass
+    for (int i = threadIdx.x; i < kXSamples / 2; i += nthreads) {
+        const uint32_t s = 2u * i;
+        int xi[2] = {0, 0}, xq[2] = {0, 0};
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (s + u < avail) {
+                const uint64_t g = t0 + s + u;
+                if constexpr (FMT == GC_I8_IQ) {
+                    const uint16_t v = *reinterpret_cast<const uint16_t*>(samples + 2 * g);
+                    xi[u] = (int)(int8_t)(v & 0xFF);
+                    xq[u] = (int)(int8_t)(v >> 8);
+                } else if constexpr (FMT == GC_I8_REAL) {
+                    xi[u] = (int)(int8_t)samples[g];
+                } else {
+                    xi[u] = 2 * (int)((samples[g >> 2] >> (2 * (g & 3))) & 3u) - 3;
+                }
+            }
+        }
+        uint4 o;
+        o.x = (uint32_t)(uint16_t)xi[0] | ((uint32_t)(uint16_t)xq[0] << 16);
+        o.y = (uint32_t)(uint16_t)xq[0] | ((uint32_t)(uint16_t)(-xi[0]) << 16);
+        o.z = (uint32_t)(uint16_t)xi[1] | ((uint32_t)(uint16_t)xq[1] << 16);
+        o.w = (uint32_t)(uint16_t)xq[1] | ((uint32_t)(uint16_t)(-xi[1]) << 16);
+        dst[i] = o;
+    }
+}
+
+// Stage 1 for one chunk: clear the wave's S, scatter samples [sa, sb).
+template <bool CHECK>
+__device__ __forceinline__ void scatter_step(uint8_t* lds, uint32_t s_base, uint32_t xaddr,
+                                             uint32_t ph, uint32_t lut_base, uint64_t U,
+                                             uint32_t cs32, bool valid) {
+    if (CHECK && !valid) return;
+    const uint2 xw = *reinterpret_cast<const uint2*>(lds + xaddr);
+    const uint32_t cs = *reinterpret_cast<const uint32_t*>(lds + lut_base + ((ph >> 24) << 2));
+    const int wi = __builtin_amdgcn_sdot2(as_s2(xw.x), as_s2(cs), 0, false);
+    const int wq = __builtin_amdgcn_sdot2(as_s2(xw.y), as_s2(cs), 0, false);
+    const uint32_t col = (uint32_t)(U >> 32) - cs32;
+    const uint32_t q = (uint32_t)U >> 27;
+    uint8_t* p = lds + s_base + q * kRowBytes + col;
+    p[0] = (uint8_t)(wi & 127);
+    p[kPlaneBytes] = (uint8_t)(wi >> 7);
+    p[2 * kPlaneBytes] = (uint8_t)(wq & 127);
+    p[3 * kPlaneBytes] = (uint8_t)(wq >> 7);
+}
+
+struct Dest {
+    int32_t* out;
+    gc_chan_state* st;
+    uint64_t row0;
+    int tap_stride;
+    uint32_t m_close;
+};
+
+// Stage 3 for the dump held in acc: T = 128*hi + lo, prefix sums over q in
+// the wave's S area, two range sums per tap, stored (plain or atomic).
+__device__ __forceinline__ void finish_dump(int4_t (&acc)[8], uint8_t* lds, uint32_t s_base,
+                                            uint32_t lane, const DevChan& ch, int jmin,
+                                            uint32_t m, bool plain, const Dest& d) {
+    int32_t* P = reinterpret_cast<int32_t*>(lds + s_base);  // [plane][j][33]
+    const uint32_t j = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const uint32_t q = 16 * h + 4 * g + v;
+            P[(0 * 16 + j) * 33 + q] = 128 * acc[2 + h][v] + acc[0 + h][v];
+            P[(1 * 16 + j) * 33 + q] = 128 * acc[6 + h][v] + acc[4 + h][v];
+        }
+    }
+    wave_fence();
+    if (lane < 32) {  // exclusive prefix over q of sequence (plane, j) = (lane/16, lane%16)
+        int32_t* r = P + lane * 33;
+        int run = 0;
+        for (int q = 0; q < 32; ++q) {
+            const int t = r[q];
+            r[q] = run;
+            run += t;
+        }
+        r[32] = run;
+    }
+    wave_fence();
+    const int K = ch.n_taps;
+    for (int k = (int)lane; k < K; k += 64) {
+        const int dk = (int)(ch.taps[k] >> 27);
+        const int fl = dk >= 0 ? dk / 32 : -((31 - dk) / 32);
+        const int r = dk - 32 * fl;  // in [0, 32)
+        const int jA = fl - jmin;
+        const int b = 32 - r;
+        int y[2];
+#pragma unroll
+        for (int pl = 0; pl < 2; ++pl) {
+            const int32_t* PA = P + (pl * 16 + jA) * 33;
+            y[pl] = PA[b];
+            if (r > 0) {
+                const int32_t* PB = PA + 33;
+                y[pl] += PB[32] - PB[b];
+            }
+        }
+        if (m < d.m_close) {
+            int32_t* o = d.out + ((d.row0 + m) * d.tap_stride + k) * 2;
+            if (plain) {
+                o[0] = y[0];
+                o[1] = y[1];
+            } else {
+                if (y[0]) atomicAdd(o, y[0]);
+                if (y[1]) atomicAdd(o + 1, y[1]);
+            }
+        } else {
+            if (y[0]) atomicAdd(&d.st->acc[k][0], y[0]);
+            if (y[1]) atomicAdd(&d.st->acc[k][1], y[1]);
+        }
+    }
+    wave_fence();
+#pragma unroll
+    for (int t = 0; t < 8; ++t) acc[t] = int4_t{0, 0, 0, 0};
+}
+
+template <int FMT>
+__global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict__ samples,
+                                                      uint64_t n,
+                                                      const DevChan* __restrict__ chans,
+                                                      const DevMeta* __restrict__ metas,
+                                                      gc_chan_state* __restrict__ state,
+                                                      int32_t* __restrict__ out, int tap_stride,
+                                                      uint32_t max_dumps,
+                                                      const uint32_t* __restrict__ tables,
+                                                      int n_chan, uint32_t n_tiles) {
+    __shared__ __attribute__((aligned(16))) uint8_t s_lds[kLdsBytes];
+    int* s_list = reinterpret_cast<int*>(s_lds + kOffList);
+    const int tid = threadIdx.x;
+    const int nthreads = blockDim.x;
+    const int wave = tid / 64;
+    const uint32_t lane = tid & 63;
+
+    if (tid == 0) {  // this block's channel group
+        const int first = (int)blockIdx.y * kWaves;
+        int k = 0, seen = 0;
+        for (int c = 0; c < n_chan && k < kWaves; ++c) {
+            const DevMeta& m = metas[c];
+            if (m.status == GC_OK && m.path == kPathMtap) {
+                if (seen >= first) s_list[k++] = c;
+                ++seen;
+            }
+        }
+        s_list[kWaves] = k;
+    }
+    __syncthreads();
+    const int nlist = s_list[kWaves];
+    if (nlist == 0) return;
+    {
+        uint32_t* lut = reinterpret_cast<uint32_t*>(s_lds);
+        for (int i = tid; i < kLutCopies * kLutStride; i += nthreads) {
+            const int e = i % kLutStride;
+            lut[i] = e < 256 ? tables[kTabLut + e] : 0u;
+        }
+    }
+
+    const bool active = wave < nlist;
+    const int chn = __builtin_amdgcn_readfirstlane(active ? s_list[wave] : 0);
+    const DevChan& ch = chans[chn];
+    const DevMeta m = metas[chn];
+    const Dest d{out, state + chn, (uint64_t)chn * max_dumps, tap_stride, m.m_close};
+    const uint64_t span = m.window >> 32;
+    const uint32_t s_base = kOffS + wave * kSBytes;
+    const uint32_t lut_base = (lane & (kLutCopies - 1)) * kLutStride * 4;
+    const int jmin = ch.mt_jmin;
+    // B fragment source: 4 byte-shifted copies of this PRN's code as int8
+    const uint32_t* code8 = tables + kTabCode8 + (ch.prn - 1) * 4 * kCode8Words;
+
+    // contiguous chunk of tiles for this block; chunks belong to the tile
+    // holding their first sample
+    const uint32_t tb0 = (uint32_t)(((uint64_t)blockIdx.x * n_tiles) / gridDim.x);
+    const uint32_t tb1 = (uint32_t)(((uint64_t)(blockIdx.x + 1) * n_tiles) / gridDim.x);
+    const uint64_t T0 = (uint64_t)tb0 * kTile;
+    const uint64_t T1 = min(n, (uint64_t)tb1 * kTile);
+
+    int4_t acc[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) acc[t] = int4_t{0, 0, 0, 0};
+    Chunk k = chunk_of((m.p0 + T0 * m.dp) >> 32, span, m.p0, m.dp, n);
+    if (T0 > 0 && k.sa < T0) k = chunk_of(k.ce, span, m.p0, m.dp, n);
+    bool seen_first = k.first;  // this wave holds the dump from its first chunk
+    bool open = false;          // acc holds part of dump k.m
+
+    for (uint32_t tile = tb0; tile < tb1; ++tile) {
+        const uint64_t t0 = (uint64_t)tile * kTile;
+        const uint64_t t1 = min(n, t0 + kTile);
+        __syncthreads();
+        stage_tile<FMT>(samples, n, t0, s_lds, nthreads);
+        __syncthreads();
+        if (!active) continue;
+        while (k.sa < t1 && k.sa < k.sb) {
+            // stage 1: clear S (rows of 32 chips), scatter the chunk's samples
+            {
+                uint2* z = reinterpret_cast<uint2*>(s_lds + s_base);
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const uint32_t row = 2 * lane + r;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) z[(row * kRowBytes) / 8 + c] = uint2{0u, 0u};
+                }
+            }
+            wave_fence();
+            const uint64_t n0 = k.sa + lane;
+            uint64_t U = m.p0 + n0 * m.dp;
+            uint32_t ph = m.phi0 + (uint32_t)n0 * m.dphi;
+            uint32_t xaddr = kOffX + (uint32_t)(n0 - t0) * 8u;
+            const uint64_t dU = 64ull * m.dp;
+            const uint32_t dph = 64u * m.dphi;
+            const uint32_t cs32 = (uint32_t)k.cs;
+            const uint32_t cnt = (uint32_t)(k.sb - k.sa);
+            const uint32_t full = cnt / 64;
+            for (uint32_t j = 0; j < full; ++j) {
+                scatter_step<false>(s_lds, s_base, xaddr, ph, lut_base, U, cs32, true);
+                U += dU;
+                ph += dph;
+                xaddr += 512u;
+            }
+            if (cnt % 64)
+                scatter_step<true>(s_lds, s_base, xaddr, ph, lut_base, U, cs32,
+                                   lane < cnt % 64);
+            wave_fence();
+            // stage 2: eight 16-row tiles x this chunk's 32 chips x 16 shifts
+            {
+                const uint32_t j = lane & 15, g = lane >> 4;
+                const uint32_t o = (uint32_t)(((int64_t)(k.cs % kCodeLen) + 8 * g + j +
+                                               2 * kCodeLen + jmin) % kCodeLen);
+                const uint32_t* src = code8 + (o & 3) * kCode8Words + (o >> 2);
+                const long b = (long)((uint64_t)src[0] | ((uint64_t)src[1] << 32));
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const long a = *reinterpret_cast<const long*>(
+                        s_lds + s_base + (16 * t + j) * kRowBytes + 8 * g);
+                    acc[t] = __builtin_amdgcn_mfma_i32_16x16x32_i8(a, b, acc[t], 0, 0, 0);
+                }
+            }
+            open = true;
+            if (k.last) {
+                finish_dump(acc, s_lds, s_base, lane, ch, jmin, k.m, seen_first && k.m > 0, d);
+                open = false;
+            }
+            const Chunk nk = chunk_of(k.ce, span, m.p0, m.dp, n);
+            if (nk.m != k.m) seen_first = nk.first;
+            k = nk;
+        }
+    }
+    // the dump still open at the end of this block's range
+    if (active && open) finish_dump(acc, s_lds, s_base, lane, ch, jmin, k.m, false, d);
+}
+
+template <int FMT>
+void launch_one(const uint8_t* samples, uint64_t n, const DevChan* chans, const DevMeta* meta,
+                gc_chan_state* state, int n_chan, int32_t* out, int tap_stride, uint32_t max_dumps,
+                const uint32_t* tables, int grid, hipStream_t s) {
+    const uint32_t n_tiles = (uint32_t)((n + kTile - 1) / kTile);
+    const int g = (int)min((uint32_t)grid, n_tiles);
+    const int waves = min(n_chan, kWaves);
+    const int groups = (n_chan + kWaves - 1) / kWaves;
+    hipLaunchKernelGGL((k_mtap<FMT>), dim3(g, groups), dim3(64 * waves), 0, s, samples, n, chans,
+                       meta, state, out, tap_stride, max_dumps, tables, n_chan, n_tiles);
+}
+
+}  // namespace
+
+hipError_t launch_mtap(const uint8_t* samples, uint64_t n, int fmt, const DevChan* chans,
+                       const DevMeta* meta, gc_chan_state* state, int n_chan, int32_t* out,
+                       int tap_stride, uint32_t max_dumps, const uint32_t* tables, int grid,
+                       hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    if (fmt == GC_I8_IQ)
+        launch_one<GC_I8_IQ>(samples, n, chans, meta, state, n_chan, out, tap_stride, max_dumps,
+                             tables, grid, s);
+    else if (fmt == GC_I8_REAL)
+        launch_one<GC_I8_REAL>(samples, n, chans, meta, state, n_chan, out, tap_stride, max_dumps,
+                               tables, grid, s);
+    else if (fmt == GC_I2_REAL)
+        launch_one<GC_I2_REAL>(samples, n, chans, meta, state, n_chan, out, tap_stride, max_dumps,
+                               tables, grid, s);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace gc

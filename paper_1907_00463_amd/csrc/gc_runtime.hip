@@ -25,6 +25,7 @@ struct gc_plan {
     gc::DevChan* d_chans;
     gc::DevMeta* d_meta;
     int use_epl;      // all channels <= 4 taps, real int8 / 2-bit, integer carrier
+    int use_mtap;     // table carrier and some channel has dense 1/32-chip taps
     int kernels;      // GC_KERNEL_* mask
     int epl_grid;     // persistent blocks of the binned kernel
     std::vector<hipEvent_t> ev_start, ev_stop;  // timing slots (empty: off)
@@ -193,6 +194,24 @@ gc_status gc_plan_create(gc_ctx* ctx, gc_format fmt, gc_carrier carrier, const g
             }
             d.epl = d.slot_e >= 0 && d.slot_p >= 0 && d.slot_l >= 0;
         }
+        // dense taps on the 1/32-chip grid: d = tap / 2^27, chip shifts
+        // floor(d_min / 32) .. floor((d_max + 31) / 32), at most 16 of them
+        {
+            bool grid = true;
+            int64_t dmin = 0, dmax = 0;
+            for (int k = 0; k < c.n_taps; ++k) {
+                const int64_t t = c.tap_q32[k];
+                if (t & ((int64_t(1) << 27) - 1)) grid = false;
+                const int64_t dk = t >> 27;
+                if (k == 0 || dk < dmin) dmin = dk;
+                if (k == 0 || dk > dmax) dmax = dk;
+            }
+            auto fdiv = [](int64_t a, int64_t b) { return a >= 0 ? a / b : -((b - 1 - a) / b); };
+            const int64_t jmin = fdiv(dmin, 32), jmax = fdiv(dmax + 31, 32);
+            d.mt_ok = grid && jmax - jmin + 1 <= 16;
+            d.mt_jmin = (int32_t)jmin;
+            d.mt_nj = (int32_t)(jmax - jmin + 1);
+        }
         if (c.n_taps > max_taps) max_taps = c.n_taps;
     }
     DeviceGuard g(ctx->device);
@@ -209,7 +228,10 @@ gc_status gc_plan_create(gc_ctx* ctx, gc_format fmt, gc_carrier carrier, const g
     p->calls = 0;
     p->use_epl = carrier == GC_CARRIER_LUT && (fmt == GC_I8_REAL || fmt == GC_I2_REAL) &&
                  max_taps <= 4;
-    p->kernels = GC_KERNEL_PERIODIC | GC_KERNEL_BINNED;
+    p->use_mtap = 0;
+    if (carrier == GC_CARRIER_LUT && !p->use_epl)
+        for (int i = 0; i < n_chan; ++i) p->use_mtap |= h[(size_t)i].mt_ok;
+    p->kernels = GC_KERNEL_PERIODIC | GC_KERNEL_BINNED | GC_KERNEL_MTAP;
     p->epl_grid = gc::epl_blocks_per_device(ctx->device);
     hipError_t e = hipMalloc(&p->d_chans, sizeof(gc::DevChan) * (size_t)n_chan);
     if (e == hipSuccess) e = hipMalloc(&p->d_meta, sizeof(gc::DevMeta) * (size_t)n_chan);
@@ -277,7 +299,8 @@ gc_status gc_plan_destroy(gc_plan* plan) {
 }
 
 gc_status gc_plan_set_kernels(gc_plan* plan, int32_t mask) {
-    if (!plan || (mask & ~(GC_KERNEL_PERIODIC | GC_KERNEL_BINNED))) return GC_EINVAL;
+    if (!plan || (mask & ~(GC_KERNEL_PERIODIC | GC_KERNEL_BINNED | GC_KERNEL_MTAP)))
+        return GC_EINVAL;
     plan->kernels = mask;
     return GC_OK;
 }
@@ -300,7 +323,9 @@ gc_status gc_correlate(gc_plan* plan, const void* samples, uint64_t n_samples,
     hipStream_t s = (hipStream_t)stream;
     const bool periodic = plan->use_epl && (plan->kernels & GC_KERNEL_PERIODIC);
     const bool binned = plan->use_epl && (plan->kernels & GC_KERNEL_BINNED);
-    const int32_t allow = (periodic ? gc::kAllowPeriodic : 0) | (binned ? gc::kAllowBinned : 0);
+    const bool mtap = plan->use_mtap && (plan->kernels & GC_KERNEL_MTAP);
+    const int32_t allow = (periodic ? gc::kAllowPeriodic : 0) | (binned ? gc::kAllowBinned : 0) |
+                          (mtap ? gc::kAllowMtap : 0);
     hipError_t e = gc::launch_setup(plan->d_chans, plan->d_meta, state, plan->n_chan, n_samples,
                                     plan->fmt, plan->carrier, max_dumps, out, plan->max_taps,
                                     dump_n, n_dumps, status, allow, s);
@@ -312,10 +337,22 @@ gc_status gc_correlate(gc_plan* plan, const void* samples, uint64_t n_samples,
         e = gc::launch_epl(x, n_samples, plan->fmt, plan->d_chans, plan->d_meta, state,
                            plan->n_chan, (int32_t*)out, plan->max_taps, max_dumps,
                            plan->ctx->d_tables, plan->epl_grid, s);
+    // channels of a multi-tap plan that the MFMA kernel does not take (more
+    // than 32 samples per chip, or taps off the 1/32 grid): the direct kernel
+    // with one block per channel and tap group looping over the tiles (its
+    // blocks return at once for the others)
+    if (e == hipSuccess && mtap)
+        e = gc::launch_generic(x, n_samples, plan->fmt, plan->carrier, plan->d_chans,
+                               plan->d_meta, state, plan->n_chan, plan->max_taps, out,
+                               plan->max_taps, max_dumps, plan->ctx->d_tables, 1, s);
     const size_t slot = plan->ev_stop.empty() ? 0 : (size_t)(plan->calls % plan->ev_stop.size());
     if (e == hipSuccess && !plan->ev_start.empty()) e = hipEventRecord(plan->ev_start[slot], s);
     if (e == hipSuccess) {
-        if (periodic)
+        if (mtap)
+            e = gc::launch_mtap(x, n_samples, plan->fmt, plan->d_chans, plan->d_meta, state,
+                                plan->n_chan, (int32_t*)out, plan->max_taps, max_dumps,
+                                plan->ctx->d_tables, plan->epl_grid, s);
+        else if (periodic)
             e = gc::launch_pbin(x, n_samples, plan->fmt, plan->d_chans, plan->d_meta, state,
                                 plan->n_chan, (int32_t*)out, plan->max_taps, max_dumps,
                                 plan->ctx->d_tables, plan->epl_grid, s);
@@ -326,7 +363,7 @@ gc_status gc_correlate(gc_plan* plan, const void* samples, uint64_t n_samples,
         else
             e = gc::launch_generic(x, n_samples, plan->fmt, plan->carrier, plan->d_chans,
                                    plan->d_meta, state, plan->n_chan, plan->max_taps, out,
-                                   plan->max_taps, max_dumps, plan->ctx->d_tables, s);
+                                   plan->max_taps, max_dumps, plan->ctx->d_tables, 0, s);
     }
     if (e == hipSuccess && !plan->ev_stop.empty()) {
         e = hipEventRecord(plan->ev_stop[slot], s);

@@ -20,7 +20,7 @@ GC_OK, GC_EINVAL, GC_ENOMEM, GC_EDEVICE, GC_ERANGE, GC_EBUSY, GC_EAGAIN, GC_ENOS
     0, -1, -2, -3, -4, -5, -6, -7)
 GC_I8_REAL, GC_I8_IQ, GC_I2_REAL = 0, 1, 2
 GC_CARRIER_LUT, GC_CARRIER_F32 = 0, 1
-GC_KERNEL_PERIODIC, GC_KERNEL_BINNED = 1, 2
+GC_KERNEL_PERIODIC, GC_KERNEL_BINNED, GC_KERNEL_MTAP = 1, 2, 4
 GC_MAX_TAPS = 128
 GC_LUT_AMP = 24
 TWO32 = 1 << 32
