@@ -225,8 +225,9 @@ __device__ __forceinline__ uint64_t udiv_ceil(uint64_t num, uint64_t d) {
     return q;
 }
 
-// Per-call output rows 1 .. M-1 of every channel: cleared, and the sample
-// count of each emitted dump (row 0 also holds the samples carried in).
+// Per-call output rows 1 .. M-1 of every channel: cleared (all tap_stride
+// taps of a row), and the sample count of each emitted dump (row 0 also holds
+// the samples carried in).
 __global__ __launch_bounds__(256) void k_rows(const DevChan* __restrict__ chans,
                                               const DevMeta* __restrict__ metas, int carrier,
                                               uint32_t max_dumps, void* out, int tap_stride,
@@ -236,20 +237,27 @@ __global__ __launch_bounds__(256) void k_rows(const DevChan* __restrict__ chans,
     if (m.status != GC_OK) return;
     const uint32_t M = m.m_close;
     const int K = chans[ch].n_taps;
-    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < M; r += gridDim.x * blockDim.x) {
+    const uint32_t stride = gridDim.x * blockDim.x;
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    for (uint32_t r = t; r < M; r += stride) {
         const uint64_t s0 = r == 0 ? 0 : udiv_ceil(r * m.window - m.p0, m.dp);
         const uint64_t s1 = udiv_ceil((r + 1) * m.window - m.p0, m.dp);
         dump_n[(uint64_t)ch * max_dumps + r] = (uint32_t)(s1 - s0) + (r == 0 ? m.acc_n0 : 0u);
-        if (r == 0) continue;
-        const uint64_t row = ((uint64_t)ch * max_dumps + r) * tap_stride * 2;
-        if (carrier == GC_CARRIER_LUT) {
-            int32_t* o = (int32_t*)out + row;
-            for (int k = 0; k < 2 * K; ++k) o[k] = 0;
-        } else {
-            float* o = (float*)out + row;
-            for (int k = 0; k < 2 * K; ++k) o[k] = 0.0f;
-        }
     }
+    // rows 1 .. M-1 are contiguous: clear their 4-byte words, 16 bytes per
+    // store where the row block is aligned (carrier-independent: 0 and 0.0f
+    // share their bits)
+    if (M <= 1) return;
+    (void)carrier;
+    uint32_t* o = (uint32_t*)out + ((uint64_t)ch * max_dumps + 1) * tap_stride * 2;
+    const uint64_t words = (uint64_t)(M - 1) * tap_stride * 2;
+    const uint64_t head = min(words, (uint64_t)((16 - ((uintptr_t)o & 15)) & 15) / 4);
+    for (uint64_t i = t; i < head; i += stride) o[i] = 0u;
+    uint4* o4 = reinterpret_cast<uint4*>(o + head);
+    const uint64_t n4 = (words - head) / 4;
+    for (uint64_t i = t; i < n4; i += stride) o4[i] = uint4{0u, 0u, 0u, 0u};
+    for (uint64_t i = head + 4 * n4 + t; i < words; i += stride) o[i] = 0u;
+    (void)K;
 }
 
 hipError_t launch_setup(const DevChan* chans, DevMeta* meta, gc_chan_state* state, int n_chan,

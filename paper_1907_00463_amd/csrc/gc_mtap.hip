@@ -67,32 +67,78 @@ __device__ __forceinline__ uint64_t ceil_div(uint64_t num, uint64_t d) {
     return q;
 }
 
-// First sample of chip c (code phase c*2^32), 0 when it lies before the block.
-__device__ __forceinline__ uint64_t chip_first(uint64_t c, uint64_t p0, uint64_t dp) {
-    const uint64_t ph = c << 32;
-    return ph <= p0 ? 0 : ceil_div(ph - p0, dp);
-}
-
+// One 32-chip chunk of a dump: chips [cs, ce), samples [sa, sb).  Chunks
+// are walked in order; the first sample of the next chunk follows from the
+// overshoot of this one (e = sb*dp - (ce*2^32 - p0), in [0, dp)) without a
+// division by the code step.
 struct Chunk {
     uint64_t cs, ce;   // chips [cs, ce)
-    uint64_t sa, sb;   // samples [sa, sb)
+    uint64_t d0;       // first chip of the dump (span * m)
+    uint64_t sa, sb;   // samples [sa, sb), clipped to [0, n]
+    uint64_t fb;       // first sample of chip ce (unclipped)
+    uint64_t eb;       // its overshoot
     uint32_t m;        // dump (window) index
+    uint32_t cmod;     // cs mod 1023
     bool first, last;  // first / last chunk of its dump
 };
+
+// First sample of chip c (code phase c*2^32) with its overshoot; chips that
+// start before the block give sample 0 and overshoot 0.
+__device__ __forceinline__ void chip_first(uint64_t c, uint64_t p0, uint64_t dp, uint64_t& f,
+                                           uint64_t& e) {
+    const uint64_t ph = c << 32;
+    if (ph <= p0) {
+        f = 0;
+        e = 0;
+        return;
+    }
+    f = ceil_div(ph - p0, dp);
+    e = f * dp - (ph - p0);
+}
 
 // The chunk of chip c: chips [span*m + 32a, min(+32, span*(m+1))).
 __device__ __forceinline__ Chunk chunk_of(uint64_t c, uint64_t span, uint64_t p0, uint64_t dp,
                                           uint64_t n) {
     Chunk k;
     k.m = (uint32_t)(c / span);
-    const uint64_t d0 = (uint64_t)k.m * span;
-    k.cs = d0 + ((c - d0) / kChunkChips) * kChunkChips;
-    k.ce = min(k.cs + kChunkChips, d0 + span);
-    k.first = k.cs == d0;
-    k.last = k.ce == d0 + span;
-    k.sa = min(n, chip_first(k.cs, p0, dp));
-    k.sb = min(n, chip_first(k.ce, p0, dp));
+    k.d0 = (uint64_t)k.m * span;
+    k.cs = k.d0 + ((c - k.d0) / kChunkChips) * kChunkChips;
+    k.ce = min(k.cs + kChunkChips, k.d0 + span);
+    k.first = k.cs == k.d0;
+    k.last = k.ce == k.d0 + span;
+    k.cmod = (uint32_t)((k.cs - k.d0) % kCodeLen);
+    uint64_t fa, ea;
+    chip_first(k.cs, p0, dp, fa, ea);
+    chip_first(k.ce, p0, dp, k.fb, k.eb);
+    k.sa = min(n, fa);
+    k.sb = min(n, k.fb);
     return k;
+}
+
+// The chunk after k: its first sample is k's end; its end advances by
+// ceil(((ce' - ce)*2^32 - eb) / dp) samples (one or two candidates around a
+// float estimate, checked exactly).
+__device__ __forceinline__ void chunk_next(Chunk& k, uint64_t span, uint64_t dp, float inv_dp,
+                                           uint64_t n) {
+    if (k.last) {
+        k.m += 1;
+        k.d0 += span;
+        k.cmod = 0;  // a dump starts on a code epoch
+    } else {
+        k.cmod += kChunkChips;
+        if (k.cmod >= kCodeLen) k.cmod -= kCodeLen;
+    }
+    k.cs = k.ce;
+    k.ce = min(k.cs + kChunkChips, k.d0 + span);
+    k.first = k.cs == k.d0;
+    k.last = k.ce == k.d0 + span;
+    k.sa = k.sb;
+    const uint64_t num = ((k.ce - k.cs) << 32) - k.eb;  // > 0
+    uint64_t q = (uint64_t)max(0.0f, (float)num * inv_dp - 2.0f);
+    while (q * dp < num) ++q;
+    k.fb += q;
+    k.eb = q * dp - num;
+    k.sb = min(n, k.fb);
 }
 
 // Tile samples [t0, t0 + kXSamples) as two int16 pairs each: (xI, xQ) and
@@ -270,6 +316,10 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
     const uint32_t s_base = kOffS + wave * kSBytes;
     const uint32_t lut_base = (lane & (kLutCopies - 1)) * kLutStride * 4;
     const int jmin = ch.mt_jmin;
+    const float inv_dp = 1.0f / (float)m.dp;
+    // lane's column offset into the replica-shift matrix: chips 8g.. of the
+    // chunk, shift jmin + (lane & 15), kept non-negative
+    const uint32_t b_off = (uint32_t)(8 * (int)(lane >> 4) + (int)(lane & 15) + 2 * kCodeLen + jmin);
     // B fragment source: 4 byte-shifted copies of this PRN's code as int8
     const uint32_t* code8 = tables + kTabCode8 + (ch.prn - 1) * 4 * kCode8Words;
 
@@ -314,7 +364,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
             const uint64_t dU = 64ull * m.dp;
             const uint32_t dph = 64u * m.dphi;
             const uint32_t cs32 = (uint32_t)k.cs;
-            const uint32_t cnt = (uint32_t)(k.sb - k.sa);
+            const uint32_t cnt = __builtin_amdgcn_readfirstlane((uint32_t)(k.sb - k.sa));
             const uint32_t full = cnt / 64;
             for (uint32_t j = 0; j < full; ++j) {
                 scatter_step<false>(s_lds, s_base, xaddr, ph, lut_base, U, cs32, true);
@@ -329,8 +379,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
             // stage 2: eight 16-row tiles x this chunk's 32 chips x 16 shifts
             {
                 const uint32_t j = lane & 15, g = lane >> 4;
-                const uint32_t o = (uint32_t)(((int64_t)(k.cs % kCodeLen) + 8 * g + j +
-                                               2 * kCodeLen + jmin) % kCodeLen);
+                const uint32_t o = (k.cmod + b_off) % kCodeLen;
                 const uint32_t* src = code8 + (o & 3) * kCode8Words + (o >> 2);
                 const long b = (long)((uint64_t)src[0] | ((uint64_t)src[1] << 32));
 #pragma unroll
@@ -345,9 +394,9 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
                 finish_dump(acc, s_lds, s_base, lane, ch, jmin, k.m, seen_first && k.m > 0, d);
                 open = false;
             }
-            const Chunk nk = chunk_of(k.ce, span, m.p0, m.dp, n);
-            if (nk.m != k.m) seen_first = nk.first;
-            k = nk;
+            const bool was_last = k.last;
+            chunk_next(k, span, m.dp, inv_dp, n);
+            if (was_last) seen_first = true;
         }
     }
     // the dump still open at the end of this block's range
