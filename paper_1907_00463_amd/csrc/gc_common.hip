@@ -55,17 +55,14 @@ __global__ void k_init_tables(uint32_t* tables) {
         const int i = (idx % kSignLen) % kCodeLen;
         tables[kTabSign + idx] = ca_chip(tables, c_g2_delay_dev[prn - 1], i) < 0 ? 0xFFFFFFFFu : 0x00010001u;
     }
-    // int8 codes in 4 byte-shifted copies per PRN
-    for (int idx = t; idx < 32 * 4 * kCode8Words; idx += blockDim.x) {
-        const int prn = idx / (4 * kCode8Words) + 1;
-        const int sh = (idx / kCode8Words) % 4;
-        const int w = idx % kCode8Words;
-        uint32_t word = 0;
-        for (int b = 0; b < 4; ++b) {
-            const int i = (4 * w + b + sh) % kCodeLen;
-            word |= (uint32_t)(uint8_t)ca_chip(tables, c_g2_delay_dev[prn - 1], i) << (8 * b);
-        }
-        tables[kTabCode8 + idx] = word;
+    // int8 code pairs (C, 64*C) per chip for the multi-tap MFMA operands
+    for (int idx = t; idx < 32 * 2 * kCodePairWords; idx += blockDim.x) {
+        const int prn = idx / (2 * kCodePairWords) + 1;
+        const int hi = (idx / kCodePairWords) % 2;
+        const int i = (idx % kCodePairWords) % kCodeLen;
+        const int c = ca_chip(tables, c_g2_delay_dev[prn - 1], i);
+        const uint32_t pair = (uint32_t)(uint8_t)(int8_t)c | ((uint32_t)(uint8_t)(int8_t)(64 * c) << 8);
+        tables[kTabCodePair + idx] = pair << (16 * hi);
     }
     if (t < 256) {
         double ang = 6.283185307179586476925286766559 * ((double)t + 0.5) / 256.0;

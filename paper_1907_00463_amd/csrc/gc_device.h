@@ -19,12 +19,12 @@ constexpr int kPbinMaxSteps = (kPbinTileSamples / 8 + 2 + 63) / 64;
 // chip index 0..1022 followed by a wrapped copy long enough for a run of
 // periodic steps (32 chips per step, read one step ahead) from any chip
 constexpr int kSignLen = 1023 + 32 * (kPbinMaxSteps + 2);
-// 32 PRNs x 4 copies x kCode8Words words: copy s holds bytes
-// C[(i + s) mod 1023] (int8 +-1) for i = 0 .. 4*kCode8Words-1, so that any 8
-// consecutive chips start on a word of one copy (multi-tap MFMA operands).
-constexpr int kCode8Words = 264;
-constexpr int kTabCode8 = kTabSign + 32 * kSignLen;
-constexpr int kTabWords = kTabCode8 + 32 * 4 * kCode8Words;
+// 32 PRNs x 2 x kCodePairWords words: word i holds the int8 pair (C, 64*C)
+// of chip i mod 1023 in its low half-word, then the same pairs in the upper
+// half-words (multi-tap MFMA operands).
+constexpr int kCodePairWords = 1060;
+constexpr int kTabCodePair = kTabSign + 32 * kSignLen;
+constexpr int kTabWords = kTabCodePair + 32 * 2 * kCodePairWords;
 constexpr int kLutAbsSumMax = 34;  // max over l of |cos_l| + |sin_l| at amplitude 24
 
 // Chip i of the C/A code whose G2 delay is d: G1[i] XOR G2[(i - d) mod 1023],

@@ -22,7 +22,7 @@ struct DevChan {
     uint64_t window;       // W = int_periods * 1023 * 2^32
     int32_t epl;           // 1: taps are early/prompt/late at +1/2, 0, -1/2 chip
     int32_t slot_e, slot_p, slot_l;  // output tap slots of E, P, L when epl
-    int32_t mt_ok;         // every tap a multiple of 2^27 (1/32 chip) spanning <= 16 chip shifts
+    int32_t mt_ok;         // every tap a multiple of 2^27 (1/32 chip) spanning <= 8 chip shifts
     int32_t mt_jmin;       // smallest chip shift floor(d_min / 32), d = tap / 2^27
     int32_t mt_nj;         // number of chip shifts
     int32_t pad0;

@@ -5,24 +5,27 @@
 // of sample n as U_n = c_n*2^32 + q_n*2^27 + e (q_n in [0, 32), e < 2^27).
 // Then the replica chip of tap k is
 //     floor((U_n + delta_k) / 2^32) = c_n + floor((q_n + d_k) / 32),
-// so with S[q][c] = sum of the wiped-off samples whose (q_n, c_n) = (q, c)
+// so with S[q][c] = the wiped-off sample whose (q_n, c_n) = (q, c), or 0
 // (at most one sample per cell when a chip spans <= 32 samples):
 //     T[q][j] = sum_c S[q][c] * C[(c + j) mod 1023]      (stage 2, MFMA)
 //     Y_k     = sum_q T[q][floor((q + d_k) / 32)]         (stage 3)
-// Stage 1 scatters the samples into S, one 32-chip chunk at a time, in
-// LDS.  The wiped-off values (|w| <= 128*34) are split into two int8 planes,
-// w = 128*hi + lo with lo = w & 127 in [0, 127] and hi = w >> 7 in [-34, 34],
-// so that A = S (rows: I lo, I hi, Q lo, Q hi, each 32 q-rows; columns: the
-// chunk's 32 chips) and B = the chips x replica-shift matrix (16 shifts) are
-// int8 and v_mfma_i32_16x16x32_i8 with int32 accumulation is exact.  The
-// eight 16-row tiles of A accumulate over the chunks of one dump; at the
-// dump's end T = 128*T_hi + T_lo, prefix sums over q turn every tap into two
-// range sums (stage 3), and the dump is stored.
+// Stage 1 scatters the samples into S, one 32-chip chunk at a time, in LDS.
+// A cell holds four int8: the wiped-off I and Q (|w| <= 128*34) each split
+// as w = 64*hi + lo with lo = w & 63 in [0, 63] and hi = w >> 6 in [-68, 68].
+// The contraction index runs over (chip, byte of the cell); the replica
+// operand holds (C, 64*C, 0, 0) per chip in its I columns and (0, 0, C, 64*C)
+// in its Q columns (8 chip shifts each), so one v_mfma_i32_16x16x64_i8 over
+// 16 chips yields exact int32 T for I and Q at once.  T accumulates over the
+// chunks of a dump; at the dump's end prefix sums over q turn every tap into
+// two range sums (stage 3), and the dump is stored.
 //
 // One wave per channel (16 per block), blocks take contiguous chunks of
 // sample tiles; the tile (8 B per sample: (xI, xQ) and (xQ, -xI) as int16)
 // and a 16-copy carrier table are shared by the block's waves.  The complex
-// wipe-off is two v_dot2 per sample.
+// wipe-off is two v_dot2 per sample; lanes take consecutive samples, so
+// sample and table reads are conflict-free, and a row stride of 34 dwords
+// keeps the cells one instruction writes in distinct banks (rows q differ
+// by less than 32) as well as the 8-byte operand reads of 16 rows.
 #include "gc_device.h"
 
 namespace gc {
@@ -30,15 +33,14 @@ namespace gc {
 namespace {
 
 constexpr int kWaves = 16;
-constexpr int kChunkChips = 32;                  // K of one MFMA
-constexpr int kRows = 128;                       // 4 planes x 32 q
-constexpr int kRowBytes = 40;                    // 32 chips + 8 pad (banks)
-constexpr int kPlaneBytes = 32 * kRowBytes;      // 1280
-constexpr int kSBytes = kRows * kRowBytes;       // 5120 per wave
+constexpr int kChunkChips = 32;                  // chips per chunk (two MFMA K steps)
+constexpr int kRows = 32;                        // q
+constexpr int kRowBytes = 136;                   // 32 chips x 4 B + 8 pad (34 dwords)
+constexpr int kSBytes = kRows * kRowBytes;       // 4352 per wave
 constexpr int kLutCopies = 16;
 constexpr int kLutStride = 257;                  // words between copies
 constexpr int kLutBytes = kLutCopies * kLutStride * 4;
-constexpr int kTile = 7040;                      // samples per tile
+constexpr int kTile = 8576;                      // samples per tile
 constexpr int kMargin = kChunkChips * 32 + 64;   // a chunk spans <= 32 chips of <= 32 samples
 constexpr int kXSamples = kTile + kMargin;
 constexpr int kOffS = kLutBytes;
@@ -47,10 +49,12 @@ constexpr int kOffList = kOffX + kXSamples * 8;
 constexpr int kLdsBytes = kOffList + 4 * (kWaves + 1);
 static_assert(kLdsBytes <= 160 * 1024, "LDS per block");
 static_assert(kTile % 16 == 0 && kXSamples % 16 == 0, "staging granule");
-static_assert(2 * 16 * 33 * 4 <= kSBytes, "stage-3 prefix sums fit the wave's S area");
+static_assert(2 * 8 * 33 * 4 <= kSBytes, "stage-3 prefix sums fit the wave's S area");
+static_assert(kOffS % 8 == 0 && kSBytes % 8 == 0 && kRowBytes % 8 == 0, "8-byte operand reads");
 
 typedef short short2_t __attribute__((ext_vector_type(2)));
 typedef int int4_t __attribute__((ext_vector_type(4)));
+typedef int int2_t __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ short2_t as_s2(uint32_t v) { return __builtin_bit_cast(short2_t, v); }
 
@@ -133,8 +137,10 @@ __device__ __forceinline__ void chunk_next(Chunk& k, uint64_t span, uint64_t dp,
     k.first = k.cs == k.d0;
     k.last = k.ce == k.d0 + span;
     k.sa = k.sb;
-    const uint64_t num = ((k.ce - k.cs) << 32) - k.eb;  // > 0
-    uint64_t q = (uint64_t)max(0.0f, (float)num * inv_dp - 2.0f);
+    const uint32_t nch = (uint32_t)(k.ce - k.cs);          // 1 .. 32
+    const uint64_t num = ((uint64_t)nch << 32) - k.eb;      // > 0
+    const float est = ((float)nch * 4294967296.0f - (float)(uint32_t)k.eb) * inv_dp;
+    uint64_t q = (uint64_t)(uint32_t)max(0.0f, est - 2.0f);
     while (q * dp < num) ++q;
     k.fb += q;
     k.eb = q * dp - num;
@@ -176,23 +182,26 @@ __device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, 
     }
 }
 
-// Stage 1 for one chunk: clear the wave's S, scatter samples [sa, sb).
+// Stage 1, one sample per lane: wipe-off, split into the four int8 of the
+// cell, one dword store into row q, column (chip - cs).
 template <bool CHECK>
-__device__ __forceinline__ void scatter_step(uint8_t* lds, uint32_t s_base, uint32_t xaddr,
-                                             uint32_t ph, uint32_t lut_base, uint64_t U,
-                                             uint32_t cs32, bool valid) {
+__device__ __forceinline__ void scatter_step(uint8_t* lds, uint32_t xaddr, uint32_t ph,
+                                             uint32_t lut_base, uint64_t U, uint32_t cbase,
+                                             bool valid) {
     if (CHECK && !valid) return;
     const uint2 xw = *reinterpret_cast<const uint2*>(lds + xaddr);
     const uint32_t cs = *reinterpret_cast<const uint32_t*>(lds + lut_base + ((ph >> 24) << 2));
     const int wi = __builtin_amdgcn_sdot2(as_s2(xw.x), as_s2(cs), 0, false);
     const int wq = __builtin_amdgcn_sdot2(as_s2(xw.y), as_s2(cs), 0, false);
-    const uint32_t col = (uint32_t)(U >> 32) - cs32;
-    const uint32_t q = (uint32_t)U >> 27;
-    uint8_t* p = lds + s_base + q * kRowBytes + col;
-    p[0] = (uint8_t)(wi & 127);
-    p[kPlaneBytes] = (uint8_t)(wi >> 7);
-    p[2 * kPlaneBytes] = (uint8_t)(wq & 127);
-    p[3 * kPlaneBytes] = (uint8_t)(wq >> 7);
+    // low 16 bits of wi and wq (|w| < 2^15), then per half: bits 0-5 stay,
+    // bits 6-13 move to the upper byte (w >> 6 as a two's complement byte)
+    const uint32_t h = __builtin_amdgcn_perm((uint32_t)wq, (uint32_t)wi, 0x05040100u);
+    const uint32_t cell = ((h << 2) & 0xFF00FF00u) | (h & 0x003F003Fu);
+    // row q, column chip - cs: cbase = s_base - 4*cs (mod 2^32)
+    const uint2 u2 = __builtin_bit_cast(uint2, U);
+    const uint32_t q = u2.x >> 27;
+    const uint32_t a = __umul24(q, kRowBytes) + ((u2.y << 2) + cbase);
+    *reinterpret_cast<uint32_t*>(lds + a) = cell;
 }
 
 struct Dest {
@@ -203,24 +212,21 @@ struct Dest {
     uint32_t m_close;
 };
 
-// Stage 3 for the dump held in acc: T = 128*hi + lo, prefix sums over q in
-// the wave's S area, two range sums per tap, stored (plain or atomic).
-__device__ __forceinline__ void finish_dump(int4_t (&acc)[8], uint8_t* lds, uint32_t s_base,
+// Stage 3 for the dump held in acc (T[q][col]: col < 8 the I sums of shift
+// jmin + col, col >= 8 the Q sums of shift jmin + col - 8): prefix sums over q
+// in the wave's S area, two range sums per tap, stored (plain or atomic).
+__device__ __forceinline__ void finish_dump(int4_t (&acc)[2], uint8_t* lds, uint32_t s_base,
                                             uint32_t lane, const DevChan& ch, int jmin,
                                             uint32_t m, bool plain, const Dest& d) {
     int32_t* P = reinterpret_cast<int32_t*>(lds + s_base);  // [plane][j][33]
-    const uint32_t j = lane & 15, g = lane >> 4;
+    const uint32_t col = lane & 15, g = lane >> 4;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int t = 0; t < 2; ++t) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const uint32_t q = 16 * h + 4 * g + v;
-            P[(0 * 16 + j) * 33 + q] = 128 * acc[2 + h][v] + acc[0 + h][v];
-            P[(1 * 16 + j) * 33 + q] = 128 * acc[6 + h][v] + acc[4 + h][v];
-        }
+        for (int v = 0; v < 4; ++v) P[col * 33 + 16 * t + 4 * g + v] = acc[t][v];
     }
     wave_fence();
-    if (lane < 32) {  // exclusive prefix over q of sequence (plane, j) = (lane/16, lane%16)
+    if (lane < 16) {  // exclusive prefix over q of sequence (plane, j) = (lane/8, lane%8)
         int32_t* r = P + lane * 33;
         int run = 0;
         for (int q = 0; q < 32; ++q) {
@@ -241,7 +247,7 @@ __device__ __forceinline__ void finish_dump(int4_t (&acc)[8], uint8_t* lds, uint
         int y[2];
 #pragma unroll
         for (int pl = 0; pl < 2; ++pl) {
-            const int32_t* PA = P + (pl * 16 + jA) * 33;
+            const int32_t* PA = P + (pl * 8 + jA) * 33;
             y[pl] = PA[b];
             if (r > 0) {
                 const int32_t* PB = PA + 33;
@@ -263,8 +269,8 @@ __device__ __forceinline__ void finish_dump(int4_t (&acc)[8], uint8_t* lds, uint
         }
     }
     wave_fence();
-#pragma unroll
-    for (int t = 0; t < 8; ++t) acc[t] = int4_t{0, 0, 0, 0};
+    acc[0] = int4_t{0, 0, 0, 0};
+    acc[1] = int4_t{0, 0, 0, 0};
 }
 
 template <int FMT>
@@ -317,11 +323,16 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
     const uint32_t lut_base = (lane & (kLutCopies - 1)) * kLutStride * 4;
     const int jmin = ch.mt_jmin;
     const float inv_dp = 1.0f / (float)m.dp;
-    // lane's column offset into the replica-shift matrix: chips 8g.. of the
-    // chunk, shift jmin + (lane & 15), kept non-negative
-    const uint32_t b_off = (uint32_t)(8 * (int)(lane >> 4) + (int)(lane & 15) + 2 * kCodeLen + jmin);
-    // B fragment source: 4 byte-shifted copies of this PRN's code as int8
-    const uint32_t* code8 = tables + kTabCode8 + (ch.prn - 1) * 4 * kCode8Words;
+    // lane's operand columns: chips 4g.. of each 16-chip K step, shift
+    // jmin + (lane & 7), as an offset in [0, 1023) from the chunk's first
+    // chip; lanes 8..15 of a row group read the Q table (pairs in the upper
+    // half-word)
+    const uint32_t b_off = (uint32_t)(4 * (int)(lane >> 4) + (int)(lane & 7) + 2 * kCodeLen + jmin) %
+                           kCodeLen;
+    // replica operand source: (C, 64*C) int8 pairs of this PRN, one word per
+    // chip, then the same pairs in the upper half-words
+    const uint32_t* cpair = tables + kTabCodePair + (ch.prn - 1) * 2 * kCodePairWords;
+    const uint32_t* cpl = cpair + ((lane & 8) ? kCodePairWords : 0);
 
     // contiguous chunk of tiles for this block; chunks belong to the tile
     // holding their first sample
@@ -330,9 +341,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
     const uint64_t T0 = (uint64_t)tb0 * kTile;
     const uint64_t T1 = min(n, (uint64_t)tb1 * kTile);
 
-    int4_t acc[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) acc[t] = int4_t{0, 0, 0, 0};
+    int4_t acc[2] = {int4_t{0, 0, 0, 0}, int4_t{0, 0, 0, 0}};
     Chunk k = chunk_of((m.p0 + T0 * m.dp) >> 32, span, m.p0, m.dp, n);
     if (T0 > 0 && k.sa < T0) k = chunk_of(k.ce, span, m.p0, m.dp, n);
     bool seen_first = k.first;  // this wave holds the dump from its first chunk
@@ -346,15 +355,12 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
         __syncthreads();
         if (!active) continue;
         while (k.sa < t1 && k.sa < k.sb) {
-            // stage 1: clear S (rows of 32 chips), scatter the chunk's samples
+            // stage 1: clear S (32 rows of 32 cells), scatter the chunk's samples
             {
-                uint2* z = reinterpret_cast<uint2*>(s_lds + s_base);
+                uint2* z = reinterpret_cast<uint2*>(s_lds + s_base + (lane >> 1) * kRowBytes +
+                                                    64 * (lane & 1));
 #pragma unroll
-                for (int r = 0; r < 2; ++r) {
-                    const uint32_t row = 2 * lane + r;
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) z[(row * kRowBytes) / 8 + c] = uint2{0u, 0u};
-                }
+                for (int c = 0; c < 8; ++c) z[c] = uint2{0u, 0u};
             }
             wave_fence();
             const uint64_t n0 = k.sa + lane;
@@ -363,30 +369,34 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
             uint32_t xaddr = kOffX + (uint32_t)(n0 - t0) * 8u;
             const uint64_t dU = 64ull * m.dp;
             const uint32_t dph = 64u * m.dphi;
-            const uint32_t cs32 = (uint32_t)k.cs;
+            const uint32_t cbase = s_base - 4u * (uint32_t)k.cs;
             const uint32_t cnt = __builtin_amdgcn_readfirstlane((uint32_t)(k.sb - k.sa));
             const uint32_t full = cnt / 64;
             for (uint32_t j = 0; j < full; ++j) {
-                scatter_step<false>(s_lds, s_base, xaddr, ph, lut_base, U, cs32, true);
+                scatter_step<false>(s_lds, xaddr, ph, lut_base, U, cbase, true);
                 U += dU;
                 ph += dph;
                 xaddr += 512u;
             }
             if (cnt % 64)
-                scatter_step<true>(s_lds, s_base, xaddr, ph, lut_base, U, cs32,
-                                   lane < cnt % 64);
+                scatter_step<true>(s_lds, xaddr, ph, lut_base, U, cbase, lane < cnt % 64);
             wave_fence();
-            // stage 2: eight 16-row tiles x this chunk's 32 chips x 16 shifts
+            // stage 2: two 16-row tiles x two 16-chip K steps x 16 columns
             {
                 const uint32_t j = lane & 15, g = lane >> 4;
-                const uint32_t o = (k.cmod + b_off) % kCodeLen;
-                const uint32_t* src = code8 + (o & 3) * kCode8Words + (o >> 2);
-                const long b = (long)((uint64_t)src[0] | ((uint64_t)src[1] << 32));
+                uint32_t o = k.cmod + b_off;
+                if (o >= kCodeLen) o -= kCodeLen;
 #pragma unroll
-                for (int t = 0; t < 8; ++t) {
-                    const long a = *reinterpret_cast<const long*>(
-                        s_lds + s_base + (16 * t + j) * kRowBytes + 8 * g);
-                    acc[t] = __builtin_amdgcn_mfma_i32_16x16x32_i8(a, b, acc[t], 0, 0, 0);
+                for (int ks = 0; ks < 2; ++ks) {
+                    const int4_t b = *reinterpret_cast<const int4_t*>(cpl + o + 16 * ks);
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) {
+                        const uint8_t* ap = s_lds + s_base + (16 * t + j) * kRowBytes + 64 * ks + 16 * g;
+                        const int2_t a0 = *reinterpret_cast<const int2_t*>(ap);
+                        const int2_t a1 = *reinterpret_cast<const int2_t*>(ap + 8);
+                        const int4_t a = int4_t{a0.x, a0.y, a1.x, a1.y};
+                        acc[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc[t], 0, 0, 0);
+                    }
                 }
             }
             open = true;

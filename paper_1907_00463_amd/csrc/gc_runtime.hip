@@ -195,7 +195,7 @@ gc_status gc_plan_create(gc_ctx* ctx, gc_format fmt, gc_carrier carrier, const g
             d.epl = d.slot_e >= 0 && d.slot_p >= 0 && d.slot_l >= 0;
         }
         // dense taps on the 1/32-chip grid: d = tap / 2^27, chip shifts
-        // floor(d_min / 32) .. floor((d_max + 31) / 32), at most 16 of them
+        // floor(d_min / 32) .. floor((d_max + 31) / 32), at most 8 of them
         {
             bool grid = true;
             int64_t dmin = 0, dmax = 0;
@@ -208,7 +208,7 @@ gc_status gc_plan_create(gc_ctx* ctx, gc_format fmt, gc_carrier carrier, const g
             }
             auto fdiv = [](int64_t a, int64_t b) { return a >= 0 ? a / b : -((b - 1 - a) / b); };
             const int64_t jmin = fdiv(dmin, 32), jmax = fdiv(dmax + 31, 32);
-            d.mt_ok = grid && jmax - jmin + 1 <= 16;
+            d.mt_ok = grid && jmax - jmin + 1 <= 8;
             d.mt_jmin = (int32_t)jmin;
             d.mt_nj = (int32_t)(jmax - jmin + 1);
         }
