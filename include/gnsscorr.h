@@ -171,7 +171,7 @@ gc_status gc_plan_destroy(gc_plan* plan);
  *   GC_KERNEL_BINNED    any rate of >= 2^32/127 code step, chip by chip
  *   GC_KERNEL_MTAP      plans with more than 4 taps or complex input: channels
  *                       whose taps are all multiples of 2^27 (1/32 chip)
- *                       spanning at most 16 chip shifts, at <= 32 samples per
+ *                       spanning at most 8 chip shifts, at <= 32 samples per
  *                       chip (two-stage int8 MFMA form, table carrier)
  * Channels that no allowed family takes, and every channel of a plan with
  * the float carrier, use the direct per-sample kernel.  Default: all bits
@@ -217,17 +217,86 @@ gc_status gc_correlate(gc_plan* plan, const void* samples, uint64_t n_samples,
                        void* stream);
 
 /* Per-launch timing of the plan's main correlation kernel (the paper reports
- * tracking time per epoch per channel, Sec. 4, Table 5).  With n_slots > 0,
- * every later gc_correlate records a HIP event pair on its stream around its
- * main kernel into slot (call index mod n_slots); n_slots = 0 turns timing
- * off.  At most 4096 slots.  Synchronous set-up.  Errors: GC_EINVAL,
- * GC_ENOMEM, GC_EDEVICE. */
+ * tracking time per epoch per channel, Sec. 4, Table 5).  A call runs up to
+ * two correlation kernels after its set-up (which one takes a channel is
+ * decided on the device); with n_slots > 0, every later gc_correlate records
+ * HIP events on its stream before, between and after them into slot (call
+ * index mod n_slots); n_slots = 0 turns timing off.  At most 4096 slots.
+ * Synchronous set-up.  Errors: GC_EINVAL, GC_ENOMEM, GC_EDEVICE. */
 gc_status gc_plan_timing(gc_plan* plan, int32_t n_slots);
 
-/* Duration in milliseconds of the kernel timed in `slot`; waits for its stop
- * event.  Errors: GC_EINVAL (timing off, slot out of range or never
- * recorded), GC_EDEVICE. */
+/* Duration in milliseconds of the longer of the two correlation kernels
+ * timed in `slot` (the one that did the work); waits for its stop event.
+ * Errors: GC_EINVAL (timing off, slot out of range or never recorded),
+ * GC_EDEVICE. */
 gc_status gc_plan_kernel_ms(gc_plan* plan, int32_t slot, float* ms);
+
+/* ------------------------------------------------------------------------
+ * Batches: many receivers in one persistent launch.
+ *
+ * A batch binds the sample blocks of n_rx receivers (each with its own
+ * format and length) and the channels that track them (Sec. 3.5: channels
+ * are independent given their receiver's samples), and correlates all of
+ * them with one launch of the chip-by-chip E/P/L kernel whose blocks walk
+ * every (receiver, tile) work item; the per-call set-up and that launch are
+ * captured once into a HIP graph and replayed by gc_batch_launch.  Results
+ * are those of gc_correlate on one plan per receiver, bit for bit.
+ * ------------------------------------------------------------------------ */
+typedef struct gc_batch gc_batch;
+
+typedef struct {
+    const void* samples;  /* device, the receiver's block in its format */
+    uint64_t n_samples;   /* 0 .. 2^31-1 */
+    int32_t fmt;          /* GC_I8_REAL or GC_I2_REAL */
+    int32_t reserved;     /* must be 0 */
+} gc_rx_desc;
+
+/* Bind a batch.
+ *   rx[n_rx]      receivers (host array; the sample pointers are device
+ *                 pointers that must stay valid while the batch is used)
+ *   cfg[n_chan]   channel configurations, at most 4 taps each
+ *   chan_rx[n_chan] receiver index of each channel, non-decreasing (the
+ *                 channels of a receiver are contiguous)
+ *   state, out, dump_n, n_dumps, status, max_dumps: as for gc_correlate,
+ *                 device buffers owned by the caller and bound to the batch
+ *                 (every launch reads and updates state in place)
+ * Every launch correlates each receiver's whole block.  The default shape
+ * is shape 0 with one block per compute unit until gc_batch_tune or
+ * gc_batch_configure picks another.
+ * Errors: GC_EINVAL (null, counts outside 1..GC_MAX_CHANNELS / 1..65536,
+ * fmt, n_samples, reserved, chan_rx out of range or decreasing, a channel
+ * with more than 4 taps, max_dumps == 0), GC_ENOMEM, GC_EDEVICE. */
+gc_status gc_batch_create(gc_ctx* ctx, const gc_rx_desc* rx, int32_t n_rx,
+                          const gc_chan_cfg* cfg, const int32_t* chan_rx, int32_t n_chan,
+                          gc_chan_state* state, void* out, uint32_t* dump_n,
+                          uint32_t* n_dumps, int32_t* status, uint32_t max_dumps,
+                          gc_batch** out_batch);
+
+/* Choose the block shape (0 .. n_shapes-1, see gc_batch_info) and the number
+ * of persistent blocks (0: one per compute unit).  Drops the captured graph.
+ * Errors: GC_EINVAL, GC_EDEVICE. */
+gc_status gc_batch_configure(gc_batch* b, int32_t shape, int32_t grid);
+
+/* Autotune: time every shape with 1x and 2x one block per compute unit,
+ * `reps` launches each, restoring the bound channel states before every
+ * launch (the states are left as they were), and keep the fastest.
+ * Synchronous.  Errors: GC_EINVAL (reps outside 1..100), GC_ENOMEM,
+ * GC_EDEVICE. */
+gc_status gc_batch_tune(gc_batch* b, int32_t reps);
+
+/* Enqueue one correlation of every receiver's block on `stream` (HIP
+ * stream, NULL = default): replays the captured graph, capturing it first
+ * when needed.  Errors: GC_EDEVICE. */
+gc_status gc_batch_launch(gc_batch* b, void* stream);
+
+/* Query: shape, grid, work items of the current configuration, the number of
+ * shapes, and the best time per launch measured by gc_batch_tune (ms, 0 when
+ * not tuned).  Any output pointer may be NULL. */
+gc_status gc_batch_info(const gc_batch* b, int32_t* shape, int32_t* grid, int32_t* n_items,
+                        int32_t* n_shapes, float* tuned_ms);
+
+/* Release a batch (waits for the device). */
+gc_status gc_batch_destroy(gc_batch* b);
 
 #ifdef __cplusplus
 }

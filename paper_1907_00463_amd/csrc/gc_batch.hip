@@ -1,0 +1,280 @@
+// gc_batch.hip -- batches of receivers behind the C ABI: one persistent
+// launch over every (receiver, tile) work item, captured into a HIP graph,
+// with the block shape and grid picked by timing the candidates on the
+// bound batch.
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "gc_internal.h"
+#include "gc_device.h"
+
+using gc::DeviceGuard;
+using gc::from_hip;
+
+struct gc_batch {
+    gc_ctx* ctx;
+    int n_rx, n_chan, max_taps;
+    uint32_t max_dumps;
+    std::vector<gc_rx_desc> rx;
+    std::vector<int32_t> chan_begin, chan_end;
+    gc::DevChan* d_chans;
+    gc::DevMeta* d_meta;
+    gc::DevRx* d_rx;
+    gc_chan_state* state;
+    void* out;
+    uint32_t* dump_n;
+    uint32_t* n_dumps;
+    int32_t* status;
+    int shape, grid;           // current configuration
+    uint32_t n_items;
+    int cus;
+    float tuned_ms;
+    hipStream_t cap;           // private stream for graph capture
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    bool have_graph;
+};
+
+namespace {
+
+// Receiver table for a shape: work items are the receivers' tiles, in order.
+hipError_t upload_rx(gc_batch* b, int shape) {
+    const uint32_t tile = gc::epl_batch_tile(shape);
+    std::vector<gc::DevRx> h((size_t)b->n_rx);
+    uint32_t items = 0;
+    for (int r = 0; r < b->n_rx; ++r) {
+        gc::DevRx& d = h[(size_t)r];
+        d.samples = (const uint8_t*)b->rx[(size_t)r].samples;
+        d.n = b->rx[(size_t)r].n_samples;
+        d.fmt = b->rx[(size_t)r].fmt;
+        d.chan_begin = b->chan_begin[(size_t)r];
+        d.chan_end = b->chan_end[(size_t)r];
+        d.tile_begin = items;
+        items += (uint32_t)((d.n + tile - 1) / tile);
+    }
+    b->n_items = items;
+    return hipMemcpy(b->d_rx, h.data(), sizeof(gc::DevRx) * h.size(), hipMemcpyHostToDevice);
+}
+
+hipError_t enqueue(gc_batch* b, hipStream_t s) {
+    hipError_t e = gc::launch_setup(b->d_chans, b->d_meta, b->state, b->n_chan, 0, GC_I8_REAL,
+                                    GC_CARRIER_LUT, b->max_dumps, b->out, b->max_taps, b->dump_n,
+                                    b->n_dumps, b->status, gc::kAllowBinned, b->d_rx, s);
+    if (e == hipSuccess)
+        e = gc::launch_epl_batch(b->shape, b->grid > 0 ? b->grid : b->cus, b->d_rx, b->n_rx,
+                                 nullptr, b->n_items, b->d_chans, b->d_meta, b->state,
+                                 (int32_t*)b->out, b->max_taps, b->max_dumps, b->ctx->d_tables,
+                                 s);
+    return e;
+}
+
+void drop_graph(gc_batch* b) {
+    if (b->have_graph) {
+        (void)hipGraphExecDestroy(b->exec);
+        (void)hipGraphDestroy(b->graph);
+        b->have_graph = false;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+gc_status gc_batch_create(gc_ctx* ctx, const gc_rx_desc* rx, int32_t n_rx,
+                          const gc_chan_cfg* cfg, const int32_t* chan_rx, int32_t n_chan,
+                          gc_chan_state* state, void* out, uint32_t* dump_n,
+                          uint32_t* n_dumps, int32_t* status, uint32_t max_dumps,
+                          gc_batch** out_batch) {
+    if (!ctx || !rx || !cfg || !chan_rx || !state || !out || !dump_n || !n_dumps || !status ||
+        !out_batch)
+        return GC_EINVAL;
+    *out_batch = nullptr;
+    if (n_rx < 1 || n_rx > 65536 || n_chan < 1 || n_chan > GC_MAX_CHANNELS || max_dumps == 0)
+        return GC_EINVAL;
+    for (int r = 0; r < n_rx; ++r) {
+        const gc_rx_desc& d = rx[r];
+        if ((d.fmt != GC_I8_REAL && d.fmt != GC_I2_REAL) || d.reserved != 0 ||
+            d.n_samples >= (1ull << 31) || (d.n_samples > 0 && !d.samples))
+            return GC_EINVAL;
+    }
+    std::vector<gc::DevChan> h((size_t)n_chan);
+    std::vector<int32_t> cb((size_t)n_rx, 0), ce((size_t)n_rx, 0);
+    int max_taps = 0;
+    for (int i = 0; i < n_chan; ++i) {
+        const gc_status st = gc::fill_devchan(cfg[i], h[(size_t)i]);
+        if (st != GC_OK) return st;
+        if (cfg[i].n_taps > 4) return GC_EINVAL;
+        const int r = chan_rx[i];
+        if (r < 0 || r >= n_rx || (i > 0 && r < chan_rx[i - 1])) return GC_EINVAL;
+        h[(size_t)i].rx = r;
+        if (i == 0 || r != chan_rx[i - 1]) cb[(size_t)r] = i;
+        ce[(size_t)r] = i + 1;
+        if (cfg[i].n_taps > max_taps) max_taps = cfg[i].n_taps;
+    }
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return GC_EDEVICE;
+    gc_batch* b = new (std::nothrow) gc_batch();
+    if (!b) return GC_ENOMEM;
+    b->ctx = ctx;
+    b->n_rx = n_rx;
+    b->n_chan = n_chan;
+    b->max_taps = max_taps;
+    b->max_dumps = max_dumps;
+    b->rx.assign(rx, rx + n_rx);
+    b->chan_begin = cb;
+    b->chan_end = ce;
+    b->d_chans = nullptr;
+    b->d_meta = nullptr;
+    b->d_rx = nullptr;
+    b->state = state;
+    b->out = out;
+    b->dump_n = dump_n;
+    b->n_dumps = n_dumps;
+    b->status = status;
+    b->shape = 0;
+    b->grid = 0;
+    b->cus = gc::epl_blocks_per_device(ctx->device);
+    b->tuned_ms = 0.0f;
+    b->cap = nullptr;
+    b->have_graph = false;
+    hipError_t e = hipMalloc(&b->d_chans, sizeof(gc::DevChan) * (size_t)n_chan);
+    if (e == hipSuccess) e = hipMalloc(&b->d_meta, sizeof(gc::DevMeta) * (size_t)n_chan);
+    if (e == hipSuccess) e = hipMalloc(&b->d_rx, sizeof(gc::DevRx) * (size_t)n_rx);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_chans, h.data(), sizeof(gc::DevChan) * (size_t)n_chan,
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = upload_rx(b, 0);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        if (b->d_chans) (void)hipFree(b->d_chans);
+        if (b->d_meta) (void)hipFree(b->d_meta);
+        if (b->d_rx) (void)hipFree(b->d_rx);
+        if (b->cap) (void)hipStreamDestroy(b->cap);
+        delete b;
+        return from_hip(e);
+    }
+    *out_batch = b;
+    return GC_OK;
+}
+
+gc_status gc_batch_configure(gc_batch* b, int32_t shape, int32_t grid) {
+    if (!b || shape < 0 || shape >= gc::epl_batch_shapes() || grid < 0 || grid > 65536)
+        return GC_EINVAL;
+    DeviceGuard g(b->ctx->device);
+    if (!g.ok) return GC_EDEVICE;
+    (void)hipDeviceSynchronize();
+    drop_graph(b);
+    b->shape = shape;
+    b->grid = grid;
+    return from_hip(upload_rx(b, shape));
+}
+
+gc_status gc_batch_tune(gc_batch* b, int32_t reps) {
+    if (!b || reps < 1 || reps > 100) return GC_EINVAL;
+    DeviceGuard g(b->ctx->device);
+    if (!g.ok) return GC_EDEVICE;
+    (void)hipDeviceSynchronize();
+    drop_graph(b);
+    const size_t sbytes = sizeof(gc_chan_state) * (size_t)b->n_chan;
+    gc_chan_state* snap = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&snap, sbytes);
+    if (e == hipSuccess) e = hipMemcpyAsync(snap, b->state, sbytes, hipMemcpyDeviceToDevice, b->cap);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    int best_shape = b->shape, best_grid = b->grid;
+    float best = -1.0f;
+    for (int sh = 0; e == hipSuccess && sh < gc::epl_batch_shapes(); ++sh) {
+        e = upload_rx(b, sh);
+        for (int gm = 1; e == hipSuccess && gm <= 2; ++gm) {
+            b->shape = sh;
+            b->grid = gm * b->cus;
+            float total = 0.0f;
+            for (int r = 0; e == hipSuccess && r <= reps; ++r) {  // r == 0: warm-up
+                e = hipMemcpyAsync(b->state, snap, sbytes, hipMemcpyDeviceToDevice, b->cap);
+                if (e == hipSuccess) e = hipEventRecord(e0, b->cap);
+                if (e == hipSuccess) e = enqueue(b, b->cap);
+                if (e == hipSuccess) e = hipEventRecord(e1, b->cap);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.0f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (r > 0) total += ms;
+            }
+            const float mean = total / (float)reps;
+            if (e == hipSuccess && (best < 0.0f || mean < best)) {
+                best = mean;
+                best_shape = sh;
+                best_grid = b->grid;
+            }
+        }
+    }
+    if (snap) {
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->state, snap, sbytes, hipMemcpyDeviceToDevice, b->cap);
+        (void)hipStreamSynchronize(b->cap);
+        (void)hipFree(snap);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    b->shape = best_shape;
+    b->grid = best_grid;
+    const hipError_t e2 = upload_rx(b, best_shape);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) b->tuned_ms = best;
+    return from_hip(e);
+}
+
+gc_status gc_batch_launch(gc_batch* b, void* stream) {
+    if (!b) return GC_EINVAL;
+    DeviceGuard g(b->ctx->device);
+    if (!g.ok) return GC_EDEVICE;
+    hipError_t e = hipSuccess;
+    if (!b->have_graph) {
+        // capture on the private stream (the caller's may be the null
+        // stream), then replay on the caller's
+        e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            const hipError_t el = enqueue(b, b->cap);
+            hipGraph_t graph = nullptr;
+            e = hipStreamEndCapture(b->cap, &graph);
+            if (el != hipSuccess) e = el;
+            if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+            if (e == hipSuccess) {
+                b->graph = graph;
+                b->have_graph = true;
+            } else if (graph) {
+                (void)hipGraphDestroy(graph);
+            }
+        }
+    }
+    if (e == hipSuccess) e = hipGraphLaunch(b->exec, (hipStream_t)stream);
+    return from_hip(e);
+}
+
+gc_status gc_batch_info(const gc_batch* b, int32_t* shape, int32_t* grid, int32_t* n_items,
+                        int32_t* n_shapes, float* tuned_ms) {
+    if (!b) return GC_EINVAL;
+    if (shape) *shape = b->shape;
+    if (grid) *grid = b->grid > 0 ? b->grid : b->cus;
+    if (n_items) *n_items = (int32_t)b->n_items;
+    if (n_shapes) *n_shapes = gc::epl_batch_shapes();
+    if (tuned_ms) *tuned_ms = b->tuned_ms;
+    return GC_OK;
+}
+
+gc_status gc_batch_destroy(gc_batch* b) {
+    if (!b) return GC_EINVAL;
+    DeviceGuard g(b->ctx->device);
+    (void)hipDeviceSynchronize();
+    drop_graph(b);
+    (void)hipFree(b->d_chans);
+    (void)hipFree(b->d_meta);
+    (void)hipFree(b->d_rx);
+    (void)hipStreamDestroy(b->cap);
+    delete b;
+    return GC_OK;
+}
+
+}  // extern "C"

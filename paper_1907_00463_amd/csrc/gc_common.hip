@@ -106,10 +106,15 @@ __global__ __launch_bounds__(64) void k_setup(const DevChan* __restrict__ chans,
                                                uint32_t* __restrict__ dump_n,
                                                uint32_t* __restrict__ n_dumps,
                                                int32_t* __restrict__ status_out,
-                                               int32_t allow) {
+                                               int32_t allow,
+                                               const DevRx* __restrict__ rx) {
     const int ch = blockIdx.x;
     const int tid = threadIdx.x;
     const DevChan& c = chans[ch];
+    if (rx) {  // batch: the block and format of the channel's receiver
+        n = rx[c.rx].n;
+        fmt = rx[c.rx].fmt;
+    }
     gc_chan_state* st = state + ch;
     __shared__ DevMeta sm;
     if (tid == 0) {
@@ -260,9 +265,9 @@ __global__ __launch_bounds__(256) void k_rows(const DevChan* __restrict__ chans,
 hipError_t launch_setup(const DevChan* chans, DevMeta* meta, gc_chan_state* state, int n_chan,
                         uint64_t n_samples, int fmt, int carrier, uint32_t max_dumps, void* out,
                         int tap_stride, uint32_t* dump_n, uint32_t* n_dumps, int32_t* status,
-                        int32_t allow, hipStream_t s) {
+                        int32_t allow, const DevRx* rx, hipStream_t s) {
     hipLaunchKernelGGL(k_setup, dim3(n_chan), dim3(64), 0, s, chans, meta, state, n_samples, fmt,
-                       carrier, max_dumps, out, tap_stride, dump_n, n_dumps, status, allow);
+                       carrier, max_dumps, out, tap_stride, dump_n, n_dumps, status, allow, rx);
     const uint32_t gx = min((max_dumps + 255u) / 256u, 256u);
     hipLaunchKernelGGL(k_rows, dim3(gx, n_chan), dim3(256), 0, s, chans, meta, carrier, max_dumps,
                        out, tap_stride, dump_n);

@@ -34,14 +34,23 @@ namespace gc {
 
 namespace {
 
-constexpr int kThreads = 512;
-constexpr int kRun = 90;                      // samples per lane per channel (45 LDS dwords: odd)
-constexpr int kTile = kThreads * kRun;        // 46080 samples per tile
 constexpr int kMargin = kEplMarginSamples;    // chips that start in a tile end within this
-constexpr int kXSamples = kTile + kMargin;    // staged as int16
 constexpr int kLutWords = 256 * 64;           // entry l of lane L at word l*64 + L
-constexpr int kLdsBytes = kLutWords * 4 + kXSamples * 2;  // table at LDS offset 0
 constexpr uint32_t kPermSel = 0x0C0C0700u;    // byte1 = phase[31:24], byte0 = lane*4
+
+// Block shape: THREADS lanes, each walking a run of about RUN samples per
+// channel (RUN/2 LDS dwords, odd, so that lanes start in different banks).
+template <int THREADS, int RUN>
+struct Shape {
+    static constexpr int kThreads = THREADS;
+    static constexpr int kRun = RUN;
+    static constexpr int kTile = THREADS * RUN;                 // samples per tile
+    static constexpr int kXSamples = kTile + kMargin;           // staged as int16
+    static constexpr int kLdsBytes = kLutWords * 4 + kXSamples * 2;  // table at LDS offset 0
+    static_assert((RUN / 2) % 2 == 1, "odd dword stride between lanes");
+    static_assert(kLdsBytes <= 160 * 1024, "LDS per block");
+};
+using ShapePlan = Shape<512, 90>;             // single-receiver plans: 46080-sample tiles
 
 typedef short short2_t __attribute__((ext_vector_type(2)));
 
@@ -223,6 +232,7 @@ __device__ __forceinline__ void epl_run(const short* __restrict__ sx, const uint
 
 // Direct per-sample form over tile offsets [lo, hi) for up to 4 taps (chips
 // cut by the block ends, and channels the binned form does not cover).
+template <int kThreads>
 __device__ __forceinline__ void direct_range(const short* __restrict__ sx, const uint8_t* lut,
                                              uint32_t lane4, uint64_t t0, uint32_t lo, uint32_t hi,
                                              const DevMeta& m, const DevChan& ch,
@@ -267,7 +277,7 @@ __device__ __forceinline__ void direct_range(const short* __restrict__ sx, const
     }
 }
 
-template <int FMT>
+template <int FMT, int kThreads, int kXSamples>
 __device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, uint64_t n,
                                            uint64_t t0, short* sx, const uint32_t* tables) {
     uint2* dst = reinterpret_cast<uint2*>(sx);  // 4 samples per 8 bytes
@@ -305,24 +315,103 @@ __device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, 
     }
 }
 
+// Channels [c_begin, c_end) of one receiver on its staged tile [t0, t1).
+template <int FMT, class SH>
+__device__ __forceinline__ void epl_tile(const short* __restrict__ s_x, const uint8_t* lut,
+                                         uint64_t t0, uint64_t t1, int c_begin, int c_end,
+                                         const DevChan* __restrict__ chans,
+                                         const DevMeta* __restrict__ metas,
+                                         gc_chan_state* __restrict__ state,
+                                         int32_t* __restrict__ out, int tap_stride,
+                                         uint32_t max_dumps, const uint32_t* __restrict__ tables) {
+    constexpr int kThreads = SH::kThreads;
+    const int tid = threadIdx.x;
+    const uint32_t lane4 = (tid & 63) * 4;
+    for (int chn = c_begin; chn < c_end; ++chn) {
+        const DevMeta m = metas[chn];
+        if (m.status != GC_OK || m.path == kPathPeriodic) continue;
+        const DevChan& ch = chans[chn];
+        const Dest d{out, state + chn, (uint64_t)chn * max_dumps, tap_stride, m.m_close};
+        const uint32_t* sgn_prn = tables + kTabSign + (ch.prn - 1) * kSignLen;
+        const uint32_t tl = (uint32_t)(t1 - t0);
+        if (m.path != kPathBinned) {
+            direct_range<kThreads>(s_x, lut, lane4, t0, 0, tl, m, ch, sgn_prn, d);
+            continue;
+        }
+        // block-edge samples outside whole chips
+        {
+            const uint64_t he = m.head_end, tb = m.tail_beg;
+            if (he > t0)
+                direct_range<kThreads>(s_x, lut, lane4, t0, 0, (uint32_t)min(he, t1) - (uint32_t)t0,
+                                       m, ch, sgn_prn, d);
+            if (t1 > tb)
+                direct_range<kThreads>(s_x, lut, lane4, t0, (uint32_t)(max(tb, t0) - t0), tl, m,
+                                       ch, sgn_prn, d);
+        }
+        // whole chips whose first sample lies in [t0, t1)
+        const uint64_t u0 = m.p0 + t0 * m.dp;
+        const uint64_t u1 = m.p0 + t1 * m.dp;
+        uint64_t ca = (u0 + 0xFFFFFFFFull) >> 32;
+        uint64_t cb = (u1 + 0xFFFFFFFFull) >> 32;
+        if (ca < m.c_full0) ca = m.c_full0;
+        if (cb > m.c_full1) cb = m.c_full1;
+        if (cb <= ca) continue;
+        const uint32_t N = (uint32_t)(cb - ca);
+        const uint32_t k0 = (uint32_t)(((uint64_t)tid * N) / kThreads);
+        const uint32_t k1 = (uint32_t)(((uint64_t)(tid + 1) * N) / kThreads);
+        const uint32_t K = k1 - k0;
+        const uint32_t Kmax = (N + kThreads - 1) / kThreads;
+        const uint32_t c = (uint32_t)(ca + k0);
+        const uint32_t dp = (uint32_t)m.dp;
+        const float inv_dp = 1.0f / (float)dp;
+        uint32_t nrel = 0, e = 0, phi = 0;
+        if (K > 0) {
+            // first sample of chip c: ceil((c*2^32 - u0) / dp), estimated with
+            // a float reciprocal (D < 2^47, so the estimate is within a few
+            // samples) and made exact with integer checks
+            const uint64_t D = ((uint64_t)c << 32) - u0;
+            const float df = (float)(uint32_t)(D >> 32) * 4294967296.0f + (float)(uint32_t)D;
+            uint64_t nr = (uint64_t)(uint32_t)max(0.0f, df * inv_dp - 2.0f);
+            while (nr * dp < D) ++nr;
+            nrel = (uint32_t)nr;
+            e = (uint32_t)(nr * dp - D);
+            phi = m.phi0 + (uint32_t)(t0 + nrel) * m.dphi;
+        }
+        const uint32_t q = (uint32_t)((1ull << 31) / dp);
+        const uint32_t r = (uint32_t)((1ull << 31) - (uint64_t)q * dp);
+        const uint32_t span = (uint32_t)(m.window >> 32);
+        const uint32_t* sgn = sgn_prn + (c + kCodeLen - 1) % kCodeLen;
+#define GC_RUN(QQ)                                                                          \
+    epl_run<FMT, QQ>(s_x, lut, lane4, nrel, phi, m.dphi, e, dp, q, r, c, K, Kmax, span, sgn, \
+                     d, ch)
+        switch (q) {
+            case 1: GC_RUN(2); break;
+            case 2: GC_RUN(3); break;
+            case 3: GC_RUN(4); break;
+            case 4: GC_RUN(5); break;
+            case 7: GC_RUN(8); break;
+            case 8: GC_RUN(9); break;
+            case 9: GC_RUN(10); break;
+            case 10: GC_RUN(11); break;
+            default: GC_RUN(0); break;
+        }
+#undef GC_RUN
+    }
+}
+
 template <int FMT>
-__global__ __launch_bounds__(kThreads) void k_epl(const uint8_t* __restrict__ samples, uint64_t n,
-                                                  const DevChan* __restrict__ chans,
-                                                  const DevMeta* __restrict__ metas,
-                                                  gc_chan_state* __restrict__ state,
-                                                  int32_t* __restrict__ out, int tap_stride,
-                                                  uint32_t max_dumps,
-                                                  const uint32_t* __restrict__ tables, int n_chan,
-                                                  uint32_t n_tiles) {
+__global__ __launch_bounds__(ShapePlan::kThreads) void k_epl(
+    const uint8_t* __restrict__ samples, uint64_t n, const DevChan* __restrict__ chans,
+    const DevMeta* __restrict__ metas, gc_chan_state* __restrict__ state,
+    int32_t* __restrict__ out, int tap_stride, uint32_t max_dumps,
+    const uint32_t* __restrict__ tables, int n_chan, uint32_t n_tiles) {
+    using SH = ShapePlan;
     // one LDS block: the per-lane carrier tables at offset 0 (so the v_perm
     // result is the address itself), then the staged samples
-    __shared__ __attribute__((aligned(16))) uint8_t s_lds[kLdsBytes];
+    __shared__ __attribute__((aligned(16))) uint8_t s_lds[SH::kLdsBytes];
     uint32_t* s_lut = reinterpret_cast<uint32_t*>(s_lds);
     short* s_x = reinterpret_cast<short*>(s_lds + kLutWords * 4);
     const int tid = threadIdx.x;
-    const uint32_t lane = tid & 63;
-    const uint32_t lane4 = lane * 4;
-    const uint8_t* lut = s_lds;
     // channels left to this kernel: not refused and not on the periodic path
     {
         int mine = 0;
@@ -330,82 +419,57 @@ __global__ __launch_bounds__(kThreads) void k_epl(const uint8_t* __restrict__ sa
             mine |= metas[c].status == GC_OK && metas[c].path != kPathPeriodic;
         if (!mine) return;
     }
-    for (int i = tid; i < kLutWords; i += kThreads) s_lut[i] = tables[kTabLut + (i >> 6)];
+    for (int i = tid; i < kLutWords; i += SH::kThreads) s_lut[i] = tables[kTabLut + (i >> 6)];
 
     for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const uint64_t t0 = (uint64_t)tile * kTile;
-        const uint64_t t1 = min(n, t0 + kTile);
+        const uint64_t t0 = (uint64_t)tile * SH::kTile;
+        const uint64_t t1 = min(n, t0 + SH::kTile);
         __syncthreads();
-        stage_tile<FMT>(samples, n, t0, s_x, tables);
+        stage_tile<FMT, SH::kThreads, SH::kXSamples>(samples, n, t0, s_x, tables);
         __syncthreads();
-        for (int chn = 0; chn < n_chan; ++chn) {
-            const DevMeta m = metas[chn];
-            if (m.status != GC_OK || m.path == kPathPeriodic) continue;
-            const DevChan& ch = chans[chn];
-            const Dest d{out, state + chn, (uint64_t)chn * max_dumps, tap_stride, m.m_close};
-            const uint32_t* sgn_prn = tables + kTabSign + (ch.prn - 1) * kSignLen;
-            const uint32_t tl = (uint32_t)(t1 - t0);
-            if (m.path != kPathBinned) {
-                direct_range(s_x, lut, lane4, t0, 0, tl, m, ch, sgn_prn, d);
-                continue;
-            }
-            // block-edge samples outside whole chips
-            {
-                const uint64_t he = m.head_end, tb = m.tail_beg;
-                if (he > t0) direct_range(s_x, lut, lane4, t0, 0, (uint32_t)min(he, t1) - (uint32_t)t0,
-                                          m, ch, sgn_prn, d);
-                if (t1 > tb) direct_range(s_x, lut, lane4, t0, (uint32_t)(max(tb, t0) - t0), tl, m,
-                                          ch, sgn_prn, d);
-            }
-            // whole chips whose first sample lies in [t0, t1)
-            const uint64_t u0 = m.p0 + t0 * m.dp;
-            const uint64_t u1 = m.p0 + t1 * m.dp;
-            uint64_t ca = (u0 + 0xFFFFFFFFull) >> 32;
-            uint64_t cb = (u1 + 0xFFFFFFFFull) >> 32;
-            if (ca < m.c_full0) ca = m.c_full0;
-            if (cb > m.c_full1) cb = m.c_full1;
-            if (cb <= ca) continue;
-            const uint32_t N = (uint32_t)(cb - ca);
-            const uint32_t k0 = (uint32_t)(((uint64_t)tid * N) / kThreads);
-            const uint32_t k1 = (uint32_t)(((uint64_t)(tid + 1) * N) / kThreads);
-            const uint32_t K = k1 - k0;
-            const uint32_t Kmax = (N + kThreads - 1) / kThreads;
-            const uint32_t c = (uint32_t)(ca + k0);
-            const uint32_t dp = (uint32_t)m.dp;
-            const float inv_dp = 1.0f / (float)dp;
-            uint32_t nrel = 0, e = 0, phi = 0;
-            if (K > 0) {
-                // first sample of chip c: ceil((c*2^32 - u0) / dp), estimated with
-                // a float reciprocal (D < 2^47, so the estimate is within a few
-                // samples) and made exact with integer checks
-                const uint64_t D = ((uint64_t)c << 32) - u0;
-                const float df = (float)(uint32_t)(D >> 32) * 4294967296.0f + (float)(uint32_t)D;
-                uint64_t nr = (uint64_t)(uint32_t)max(0.0f, df * inv_dp - 2.0f);
-                while (nr * dp < D) ++nr;
-                nrel = (uint32_t)nr;
-                e = (uint32_t)(nr * dp - D);
-                phi = m.phi0 + (uint32_t)(t0 + nrel) * m.dphi;
-            }
-            const uint32_t q = (uint32_t)((1ull << 31) / dp);
-            const uint32_t r = (uint32_t)((1ull << 31) - (uint64_t)q * dp);
-            const uint32_t span = (uint32_t)(m.window >> 32);
-            const uint32_t* sgn = sgn_prn + (c + kCodeLen - 1) % kCodeLen;
-#define GC_RUN(QQ)                                                                          \
-    epl_run<FMT, QQ>(s_x, lut, lane4, nrel, phi, m.dphi, e, dp, q, r, c, K, Kmax, span, sgn, \
-                     d, ch)
-            switch (q) {
-                case 1: GC_RUN(2); break;
-                case 2: GC_RUN(3); break;
-                case 3: GC_RUN(4); break;
-                case 4: GC_RUN(5); break;
-                case 7: GC_RUN(8); break;
-                case 8: GC_RUN(9); break;
-                case 9: GC_RUN(10); break;
-                case 10: GC_RUN(11); break;
-                default: GC_RUN(0); break;
-            }
-#undef GC_RUN
+        epl_tile<FMT, SH>(s_x, s_lds, t0, t1, 0, n_chan, chans, metas, state, out, tap_stride,
+                          max_dumps, tables);
+    }
+}
+
+// Many receivers in one persistent launch: work item i is tile
+// i - tile_begin[r] of the receiver r with tile_begin[r] <= i < tile_begin[r+1]
+// (items taken in the order given by `order` when it is not null); the tile
+// is staged in the receiver's format and correlated for its channels.
+template <class SH>
+__global__ __launch_bounds__(SH::kThreads) void k_epl_batch(
+    const DevRx* __restrict__ rx, int n_rx, const uint32_t* __restrict__ order,
+    uint32_t n_items, const DevChan* __restrict__ chans, const DevMeta* __restrict__ metas,
+    gc_chan_state* __restrict__ state, int32_t* __restrict__ out, int tap_stride,
+    uint32_t max_dumps, const uint32_t* __restrict__ tables) {
+    __shared__ __attribute__((aligned(16))) uint8_t s_lds[SH::kLdsBytes];
+    uint32_t* s_lut = reinterpret_cast<uint32_t*>(s_lds);
+    short* s_x = reinterpret_cast<short*>(s_lds + kLutWords * 4);
+    const int tid = threadIdx.x;
+    for (int i = tid; i < kLutWords; i += SH::kThreads) s_lut[i] = tables[kTabLut + (i >> 6)];
+    for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const uint32_t item = order ? order[it] : it;
+        // receiver of this item: last r with tile_begin[r] <= item
+        int lo = 0, hi = n_rx - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (rx[mid].tile_begin <= item) lo = mid; else hi = mid - 1;
         }
+        const DevRx& R = rx[lo];
+        const uint64_t t0 = (uint64_t)(item - R.tile_begin) * SH::kTile;
+        const uint64_t t1 = min(R.n, t0 + SH::kTile);
+        __syncthreads();
+        if (R.fmt == GC_I2_REAL)
+            stage_tile<GC_I2_REAL, SH::kThreads, SH::kXSamples>(R.samples, R.n, t0, s_x, tables);
+        else
+            stage_tile<GC_I8_REAL, SH::kThreads, SH::kXSamples>(R.samples, R.n, t0, s_x, tables);
+        __syncthreads();
+        if (R.fmt == GC_I2_REAL)
+            epl_tile<GC_I2_REAL, SH>(s_x, s_lds, t0, t1, R.chan_begin, R.chan_end, chans, metas,
+                                     state, out, tap_stride, max_dumps, tables);
+        else
+            epl_tile<GC_I8_REAL, SH>(s_x, s_lds, t0, t1, R.chan_begin, R.chan_end, chans, metas,
+                                     state, out, tap_stride, max_dumps, tables);
     }
 }
 
@@ -423,17 +487,61 @@ hipError_t launch_epl(const uint8_t* samples, uint64_t n, int fmt, const DevChan
                       int tap_stride, uint32_t max_dumps, const uint32_t* tables, int grid,
                       hipStream_t s) {
     if (n == 0) return hipSuccess;
-    const uint32_t n_tiles = (uint32_t)((n + kTile - 1) / kTile);
+    using SH = ShapePlan;
+    const uint32_t n_tiles = (uint32_t)((n + SH::kTile - 1) / SH::kTile);
     const int g = (int)min((uint32_t)grid, n_tiles);
     if (fmt == GC_I2_REAL) {
-        hipLaunchKernelGGL((k_epl<GC_I2_REAL>), dim3(g), dim3(kThreads), 0, s, samples, n, chans,
+        hipLaunchKernelGGL((k_epl<GC_I2_REAL>), dim3(g), dim3(SH::kThreads), 0, s, samples, n, chans,
                            meta, state, out, tap_stride, max_dumps, tables, n_chan, n_tiles);
     } else if (fmt == GC_I8_REAL) {
-        hipLaunchKernelGGL((k_epl<GC_I8_REAL>), dim3(g), dim3(kThreads), 0, s, samples, n, chans,
+        hipLaunchKernelGGL((k_epl<GC_I8_REAL>), dim3(g), dim3(SH::kThreads), 0, s, samples, n, chans,
                            meta, state, out, tap_stride, max_dumps, tables, n_chan, n_tiles);
     } else {
         return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+// Batch shapes the tuner chooses from (threads per block, samples per lane run).
+namespace {
+using ShapeB0 = Shape<512, 90>;   // 46080-sample tiles
+using ShapeB1 = Shape<256, 90>;   // 23040
+using ShapeB2 = Shape<512, 46>;   // 23552
+using ShapeB3 = Shape<256, 182>;  // 46592
+template <class SH>
+uint32_t tiles_of(uint64_t n) { return (uint32_t)((n + SH::kTile - 1) / SH::kTile); }
+}  // namespace
+
+int epl_batch_shapes() { return 4; }
+
+uint32_t epl_batch_tile(int shape) {
+    switch (shape) {
+        case 0: return ShapeB0::kTile;
+        case 1: return ShapeB1::kTile;
+        case 2: return ShapeB2::kTile;
+        case 3: return ShapeB3::kTile;
+    }
+    return 0;
+}
+
+hipError_t launch_epl_batch(int shape, int grid, const DevRx* rx, int n_rx,
+                            const uint32_t* order, uint32_t n_items, const DevChan* chans,
+                            const DevMeta* meta, gc_chan_state* state, int32_t* out,
+                            int tap_stride, uint32_t max_dumps, const uint32_t* tables,
+                            hipStream_t s) {
+    if (n_items == 0) return hipSuccess;
+    const int g = (int)min((uint32_t)grid, n_items);
+#define GC_B(SH)                                                                              \
+    hipLaunchKernelGGL((k_epl_batch<SH>), dim3(g), dim3(SH::kThreads), 0, s, rx, n_rx, order, \
+                       n_items, chans, meta, state, out, tap_stride, max_dumps, tables)
+    switch (shape) {
+        case 0: GC_B(ShapeB0); break;
+        case 1: GC_B(ShapeB1); break;
+        case 2: GC_B(ShapeB2); break;
+        case 3: GC_B(ShapeB3); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef GC_B
     return hipGetLastError();
 }
 

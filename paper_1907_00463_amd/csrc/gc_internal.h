@@ -7,7 +7,33 @@
 
 #include "gnsscorr.h"
 
+// A context: one device and its tables (opaque in the C ABI).
+struct gc_ctx {
+    int device;
+    uint32_t* d_tables;  // G1, G2, carrier table, sign and code tables (gc::kTabWords words)
+    hipStream_t stream;  // context-private stream for synchronous helpers
+};
+
 namespace gc {
+
+// Makes `dev` current for the guard's lifetime.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+inline gc_status from_hip(hipError_t e) {
+    if (e == hipSuccess) return GC_OK;
+    if (e == hipErrorOutOfMemory) return GC_ENOMEM;
+    return GC_EDEVICE;
+}
 
 constexpr uint64_t kTwo32 = 1ull << 32;
 constexpr int kCodeLen = GC_CODE_LEN;
@@ -25,7 +51,7 @@ struct DevChan {
     int32_t mt_ok;         // every tap a multiple of 2^27 (1/32 chip) spanning <= 8 chip shifts
     int32_t mt_jmin;       // smallest chip shift floor(d_min / 32), d = tap / 2^27
     int32_t mt_nj;         // number of chip shifts
-    int32_t pad0;
+    int32_t rx;            // receiver of the channel in a batch (0 in a plan)
     int64_t taps[GC_MAX_TAPS];
 };
 
@@ -51,6 +77,17 @@ struct DevMeta {
     uint32_t pad2;
 };
 
+// One receiver of a batch: its sample block and the channels and work
+// items (tiles) that belong to it.
+struct DevRx {
+    const uint8_t* samples;
+    uint64_t n;            // samples in the block
+    int32_t fmt;
+    int32_t chan_begin;    // channels [chan_begin, chan_end)
+    int32_t chan_end;
+    uint32_t tile_begin;   // first work item of this receiver
+};
+
 constexpr int32_t kPathDirect = 0;
 constexpr int32_t kPathBinned = 1;
 constexpr int32_t kPathPeriodic = 2;
@@ -61,13 +98,24 @@ constexpr int32_t kAllowBinned = 1;
 constexpr int32_t kAllowPeriodic = 2;
 constexpr int32_t kAllowMtap = 4;
 
+// Validated device form of a channel configuration (host side).
+gc_status fill_devchan(const gc_chan_cfg& c, DevChan& d);
+
 // Kernel launch entry points (defined in the .hip files, called by the runtime).
 hipError_t launch_make_tables(uint32_t* d_tables, hipStream_t s);
 hipError_t launch_code_table(const uint32_t* d_tables, int g2_delay, int8_t* d_out, hipStream_t s);
 hipError_t launch_setup(const DevChan* chans, DevMeta* meta, gc_chan_state* state, int n_chan,
                         uint64_t n_samples, int fmt, int carrier, uint32_t max_dumps,
                         void* out, int tap_stride, uint32_t* dump_n, uint32_t* n_dumps,
-                        int32_t* status, int32_t allow, hipStream_t s);
+                        int32_t* status, int32_t allow, const DevRx* rx, hipStream_t s);
+// batched chip-by-chip kernel (shape 0 .. epl_batch_shapes()-1)
+int epl_batch_shapes();
+uint32_t epl_batch_tile(int shape);
+hipError_t launch_epl_batch(int shape, int grid, const DevRx* rx, int n_rx,
+                            const uint32_t* order, uint32_t n_items, const DevChan* chans,
+                            const DevMeta* meta, gc_chan_state* state, int32_t* out,
+                            int tap_stride, uint32_t max_dumps, const uint32_t* tables,
+                            hipStream_t s);
 hipError_t launch_pbin(const uint8_t* samples, uint64_t n_samples, int fmt, const DevChan* chans,
                        const DevMeta* meta, gc_chan_state* state, int n_chan, int32_t* out,
                        int tap_stride, uint32_t max_dumps, const uint32_t* d_tables, int grid,

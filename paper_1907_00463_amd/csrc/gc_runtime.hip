@@ -10,11 +10,9 @@
 #include "gc_internal.h"
 #include "gc_device.h"
 
-struct gc_ctx {
-    int device;
-    uint32_t* d_tables;  // G1, G2, carrier table (gc::kTabWords words)
-    hipStream_t stream;  // context-private stream for synchronous helpers
-};
+using gc::DeviceGuard;
+using gc::from_hip;
+
 
 struct gc_plan {
     gc_ctx* ctx;
@@ -28,7 +26,9 @@ struct gc_plan {
     int use_mtap;     // table carrier and some channel has dense 1/32-chip taps
     int kernels;      // GC_KERNEL_* mask
     int epl_grid;     // persistent blocks of the binned kernel
-    std::vector<hipEvent_t> ev_start, ev_stop;  // timing slots (empty: off)
+    // timing slots (empty: off): events before, between and after the two
+    // correlation kernels of a call
+    std::vector<hipEvent_t> ev_start, ev_mid, ev_stop;
     std::vector<uint8_t> ev_used;
     uint64_t calls;
 };
@@ -40,25 +40,57 @@ const int32_t kG2Delay[32] = {5,   6,   7,   8,   17,  18,  139, 140, 141, 251, 
                               254, 255, 256, 257, 258, 469, 470, 471, 472, 473, 474,
                               509, 512, 513, 514, 515, 516, 859, 860, 861, 862};
 
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = false;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        ok = hipSetDevice(dev) == hipSuccess;
-    }
-    ~DeviceGuard() {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
+}  // namespace
 
-gc_status from_hip(hipError_t e) {
-    if (e == hipSuccess) return GC_OK;
-    if (e == hipErrorOutOfMemory) return GC_ENOMEM;
-    return GC_EDEVICE;
+namespace gc {
+
+gc_status fill_devchan(const gc_chan_cfg& c, DevChan& d) {
+    if (c.prn < 1 || c.prn > 32 || c.n_taps < 1 || c.n_taps > GC_MAX_TAPS ||
+        c.int_periods < 1 || c.int_periods > 1000 || c.reserved != 0)
+        return GC_EINVAL;
+    memset(&d, 0, sizeof(d));
+    d.prn = c.prn;
+    d.n_taps = c.n_taps;
+    d.int_periods = c.int_periods;
+    d.g2_delay = kG2Delay[c.prn - 1];
+    d.window = (uint64_t)c.int_periods * GC_CODE_LEN * gc::kTwo32;
+    for (int k = 0; k < c.n_taps; ++k) {
+        const int64_t t = c.tap_q32[k];
+        if (t <= -(int64_t(1) << 40) || t >= (int64_t(1) << 40)) return GC_EINVAL;
+        d.taps[k] = t;
+    }
+    // early / prompt / late at +1/2, 0, -1/2 chip, in any order
+    d.epl = 0;
+    d.slot_e = d.slot_p = d.slot_l = -1;
+    if (c.n_taps == 3) {
+        const int64_t h = int64_t(1) << 31;
+        for (int k = 0; k < 3; ++k) {
+            if (c.tap_q32[k] == h) d.slot_e = k;
+            else if (c.tap_q32[k] == 0) d.slot_p = k;
+            else if (c.tap_q32[k] == -h) d.slot_l = k;
+        }
+        d.epl = d.slot_e >= 0 && d.slot_p >= 0 && d.slot_l >= 0;
+    }
+    // dense taps on the 1/32-chip grid: d = tap / 2^27, chip shifts
+    // floor(d_min / 32) .. floor((d_max + 31) / 32), at most 8 of them
+    bool grid = true;
+    int64_t dmin = 0, dmax = 0;
+    for (int k = 0; k < c.n_taps; ++k) {
+        const int64_t t = c.tap_q32[k];
+        if (t & ((int64_t(1) << 27) - 1)) grid = false;
+        const int64_t dk = t >> 27;
+        if (k == 0 || dk < dmin) dmin = dk;
+        if (k == 0 || dk > dmax) dmax = dk;
+    }
+    auto fdiv = [](int64_t a, int64_t b) { return a >= 0 ? a / b : -((b - 1 - a) / b); };
+    const int64_t jmin = fdiv(dmin, 32), jmax = fdiv(dmax + 31, 32);
+    d.mt_ok = grid && jmax - jmin + 1 <= 8;
+    d.mt_jmin = (int32_t)jmin;
+    d.mt_nj = (int32_t)(jmax - jmin + 1);
+    return GC_OK;
 }
 
-}  // namespace
+}  // namespace gc
 
 extern "C" {
 
@@ -166,53 +198,9 @@ gc_status gc_plan_create(gc_ctx* ctx, gc_format fmt, gc_carrier carrier, const g
     std::vector<gc::DevChan> h((size_t)n_chan);
     int max_taps = 0;
     for (int i = 0; i < n_chan; ++i) {
-        const gc_chan_cfg& c = cfg[i];
-        if (c.prn < 1 || c.prn > 32 || c.n_taps < 1 || c.n_taps > GC_MAX_TAPS ||
-            c.int_periods < 1 || c.int_periods > 1000 || c.reserved != 0)
-            return GC_EINVAL;
-        gc::DevChan& d = h[(size_t)i];
-        memset(&d, 0, sizeof(d));
-        d.prn = c.prn;
-        d.n_taps = c.n_taps;
-        d.int_periods = c.int_periods;
-        d.g2_delay = kG2Delay[c.prn - 1];
-        d.window = (uint64_t)c.int_periods * GC_CODE_LEN * gc::kTwo32;
-        for (int k = 0; k < c.n_taps; ++k) {
-            const int64_t t = c.tap_q32[k];
-            if (t <= -(int64_t(1) << 40) || t >= (int64_t(1) << 40)) return GC_EINVAL;
-            d.taps[k] = t;
-        }
-        // early / prompt / late at +1/2, 0, -1/2 chip, in any order
-        d.epl = 0;
-        d.slot_e = d.slot_p = d.slot_l = -1;
-        if (c.n_taps == 3) {
-            const int64_t h = int64_t(1) << 31;
-            for (int k = 0; k < 3; ++k) {
-                if (c.tap_q32[k] == h) d.slot_e = k;
-                else if (c.tap_q32[k] == 0) d.slot_p = k;
-                else if (c.tap_q32[k] == -h) d.slot_l = k;
-            }
-            d.epl = d.slot_e >= 0 && d.slot_p >= 0 && d.slot_l >= 0;
-        }
-        // dense taps on the 1/32-chip grid: d = tap / 2^27, chip shifts
-        // floor(d_min / 32) .. floor((d_max + 31) / 32), at most 8 of them
-        {
-            bool grid = true;
-            int64_t dmin = 0, dmax = 0;
-            for (int k = 0; k < c.n_taps; ++k) {
-                const int64_t t = c.tap_q32[k];
-                if (t & ((int64_t(1) << 27) - 1)) grid = false;
-                const int64_t dk = t >> 27;
-                if (k == 0 || dk < dmin) dmin = dk;
-                if (k == 0 || dk > dmax) dmax = dk;
-            }
-            auto fdiv = [](int64_t a, int64_t b) { return a >= 0 ? a / b : -((b - 1 - a) / b); };
-            const int64_t jmin = fdiv(dmin, 32), jmax = fdiv(dmax + 31, 32);
-            d.mt_ok = grid && jmax - jmin + 1 <= 8;
-            d.mt_jmin = (int32_t)jmin;
-            d.mt_nj = (int32_t)(jmax - jmin + 1);
-        }
-        if (c.n_taps > max_taps) max_taps = c.n_taps;
+        const gc_status st = gc::fill_devchan(cfg[i], h[(size_t)i]);
+        if (st != GC_OK) return st;
+        if (cfg[i].n_taps > max_taps) max_taps = cfg[i].n_taps;
     }
     DeviceGuard g(ctx->device);
     if (!g.ok) return GC_EDEVICE;
@@ -250,8 +238,10 @@ gc_status gc_plan_create(gc_ctx* ctx, gc_format fmt, gc_carrier carrier, const g
 
 static void drop_timing(gc_plan* plan) {
     for (auto e : plan->ev_start) (void)hipEventDestroy(e);
+    for (auto e : plan->ev_mid) (void)hipEventDestroy(e);
     for (auto e : plan->ev_stop) (void)hipEventDestroy(e);
     plan->ev_start.clear();
+    plan->ev_mid.clear();
     plan->ev_stop.clear();
     plan->ev_used.clear();
 }
@@ -262,15 +252,17 @@ gc_status gc_plan_timing(gc_plan* plan, int32_t n_slots) {
     (void)hipDeviceSynchronize();
     drop_timing(plan);
     for (int i = 0; i < n_slots; ++i) {
-        hipEvent_t a, b;
-        if (hipEventCreate(&a) != hipSuccess) { drop_timing(plan); return GC_EDEVICE; }
-        if (hipEventCreate(&b) != hipSuccess) {
-            (void)hipEventDestroy(a);
-            drop_timing(plan);
-            return GC_EDEVICE;
+        hipEvent_t ev[3];
+        for (int k = 0; k < 3; ++k) {
+            if (hipEventCreate(&ev[k]) != hipSuccess) {
+                for (int j = 0; j < k; ++j) (void)hipEventDestroy(ev[j]);
+                drop_timing(plan);
+                return GC_EDEVICE;
+            }
         }
-        plan->ev_start.push_back(a);
-        plan->ev_stop.push_back(b);
+        plan->ev_start.push_back(ev[0]);
+        plan->ev_mid.push_back(ev[1]);
+        plan->ev_stop.push_back(ev[2]);
     }
     plan->ev_used.assign((size_t)n_slots, 0);
     plan->calls = 0;
@@ -281,9 +273,12 @@ gc_status gc_plan_kernel_ms(gc_plan* plan, int32_t slot, float* ms) {
     if (!plan || !ms || slot < 0 || (size_t)slot >= plan->ev_stop.size()) return GC_EINVAL;
     if (!plan->ev_used[(size_t)slot]) return GC_EINVAL;
     DeviceGuard g(plan->ctx->device);
-    hipError_t e = hipEventSynchronize(plan->ev_stop[(size_t)slot]);
-    if (e == hipSuccess) e = hipEventElapsedTime(ms, plan->ev_start[(size_t)slot],
-                                                 plan->ev_stop[(size_t)slot]);
+    const size_t i = (size_t)slot;
+    float a = 0.0f, b = 0.0f;
+    hipError_t e = hipEventSynchronize(plan->ev_stop[i]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&a, plan->ev_start[i], plan->ev_mid[i]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&b, plan->ev_mid[i], plan->ev_stop[i]);
+    if (e == hipSuccess) *ms = a > b ? a : b;
     return from_hip(e);
 }
 
@@ -328,25 +323,19 @@ gc_status gc_correlate(gc_plan* plan, const void* samples, uint64_t n_samples,
                           (mtap ? gc::kAllowMtap : 0);
     hipError_t e = gc::launch_setup(plan->d_chans, plan->d_meta, state, plan->n_chan, n_samples,
                                     plan->fmt, plan->carrier, max_dumps, out, plan->max_taps,
-                                    dump_n, n_dumps, status, allow, s);
+                                    dump_n, n_dumps, status, allow, nullptr, s);
     const uint8_t* x = (const uint8_t*)samples;
-    // The chip-by-chip kernel takes the E/P/L channels the periodic kernel
-    // leaves (it returns at once when there are none); the timing slot
-    // brackets the plan's main kernel only.
-    if (e == hipSuccess && plan->use_epl && periodic)
-        e = gc::launch_epl(x, n_samples, plan->fmt, plan->d_chans, plan->d_meta, state,
-                           plan->n_chan, (int32_t*)out, plan->max_taps, max_dumps,
-                           plan->ctx->d_tables, plan->epl_grid, s);
-    // channels of a multi-tap plan that the MFMA kernel does not take (more
-    // than 32 samples per chip, or taps off the 1/32 grid): the direct kernel
-    // with one block per channel and tap group looping over the tiles (its
-    // blocks return at once for the others)
-    if (e == hipSuccess && mtap)
-        e = gc::launch_generic(x, n_samples, plan->fmt, plan->carrier, plan->d_chans,
-                               plan->d_meta, state, plan->n_chan, plan->max_taps, out,
-                               plan->max_taps, max_dumps, plan->ctx->d_tables, 1, s);
     const size_t slot = plan->ev_stop.empty() ? 0 : (size_t)(plan->calls % plan->ev_stop.size());
-    if (e == hipSuccess && !plan->ev_start.empty()) e = hipEventRecord(plan->ev_start[slot], s);
+    const bool timed = !plan->ev_start.empty();
+    // Two correlation kernels per call; which one does the work is decided on
+    // the device per channel.  Periodic plans: the periodic kernel, then the
+    // chip-by-chip kernel for the E/P/L channels it leaves.  Multi-tap plans:
+    // the MFMA kernel, then the direct kernel (one block per channel and tap
+    // group looping over the tiles) for channels off the 1/32-chip grid or
+    // above 32 samples per chip.  A kernel with no channel returns at once.
+    // The timing slot records events before, between and after the two; the
+    // plan's kernel time is the longer of the two intervals.
+    if (e == hipSuccess && timed) e = hipEventRecord(plan->ev_start[slot], s);
     if (e == hipSuccess) {
         if (mtap)
             e = gc::launch_mtap(x, n_samples, plan->fmt, plan->d_chans, plan->d_meta, state,
@@ -365,7 +354,16 @@ gc_status gc_correlate(gc_plan* plan, const void* samples, uint64_t n_samples,
                                    plan->d_meta, state, plan->n_chan, plan->max_taps, out,
                                    plan->max_taps, max_dumps, plan->ctx->d_tables, 0, s);
     }
-    if (e == hipSuccess && !plan->ev_stop.empty()) {
+    if (e == hipSuccess && timed) e = hipEventRecord(plan->ev_mid[slot], s);
+    if (e == hipSuccess && periodic)
+        e = gc::launch_epl(x, n_samples, plan->fmt, plan->d_chans, plan->d_meta, state,
+                           plan->n_chan, (int32_t*)out, plan->max_taps, max_dumps,
+                           plan->ctx->d_tables, plan->epl_grid, s);
+    if (e == hipSuccess && mtap)
+        e = gc::launch_generic(x, n_samples, plan->fmt, plan->carrier, plan->d_chans,
+                               plan->d_meta, state, plan->n_chan, plan->max_taps, out,
+                               plan->max_taps, max_dumps, plan->ctx->d_tables, 1, s);
+    if (e == hipSuccess && timed) {
         e = hipEventRecord(plan->ev_stop[slot], s);
         plan->ev_used[slot] = 1;
     }

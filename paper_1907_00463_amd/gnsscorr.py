@@ -32,7 +32,9 @@ CHAN_STATE = np.dtype([("code_phase", "<u8"), ("code_step", "<u8"), ("carr_phase
                        ("carr_step", "<u4"), ("acc_n", "<u4"), ("flags", "<u4"),
                        ("carr_phase_f", "<f8"), ("carr_freq_f", "<f8"),
                        ("acc", "<i4", (GC_MAX_TAPS, 2)), ("acc_f", "<f4", (GC_MAX_TAPS, 2))])
-assert CHAN_CFG.itemsize == 1040 and CHAN_STATE.itemsize == 2096
+RX_DESC = np.dtype([("samples", "<u8"), ("n_samples", "<u8"), ("fmt", "<i4"),
+                    ("reserved", "<i4")])
+assert CHAN_CFG.itemsize == 1040 and CHAN_STATE.itemsize == 2096 and RX_DESC.itemsize == 24
 
 
 class GcError(RuntimeError):
@@ -61,6 +63,12 @@ def _load():
         "gc_plan_timing": ([P, I32], I32),
         "gc_plan_kernel_ms": ([P, I32, P], I32),
         "gc_plan_set_kernels": ([P, I32], I32),
+        "gc_batch_create": ([P, P, I32, P, P, I32, P, P, P, P, P, U32, P], I32),
+        "gc_batch_configure": ([P, I32, I32], I32),
+        "gc_batch_tune": ([P, I32], I32),
+        "gc_batch_launch": ([P, P], I32),
+        "gc_batch_info": ([P, P, P, P, P, P], I32),
+        "gc_batch_destroy": ([P], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -72,7 +80,9 @@ def _load():
 _lib = _load()
 EXPORTED = ("gc_strerror", "gc_version", "gc_create", "gc_destroy", "gc_nco_init",
             "gc_code_table", "gc_plan_create", "gc_plan_destroy", "gc_plan_info",
-            "gc_correlate", "gc_plan_timing", "gc_plan_kernel_ms", "gc_plan_set_kernels")
+            "gc_correlate", "gc_plan_timing", "gc_plan_kernel_ms", "gc_plan_set_kernels",
+            "gc_batch_create", "gc_batch_configure", "gc_batch_tune", "gc_batch_launch",
+            "gc_batch_info", "gc_batch_destroy")
 
 
 def _check(rc: int, where: str):
@@ -166,6 +176,44 @@ def gc_plan_kernel_ms(plan: int, slot: int) -> float:
     return ms.value
 
 
+def gc_batch_create(ctx: int, rx: np.ndarray, cfg: np.ndarray, chan_rx: np.ndarray, state, out,
+                    dump_n, n_dumps, status, max_dumps: int) -> int:
+    rx = np.ascontiguousarray(rx, dtype=RX_DESC)
+    cfg = np.ascontiguousarray(cfg, dtype=CHAN_CFG)
+    chan_rx = np.ascontiguousarray(chan_rx, dtype=np.int32)
+    h = C.c_void_p()
+    _check(_lib.gc_batch_create(ctx, rx.ctypes.data, len(rx), cfg.ctypes.data,
+                                chan_rx.ctypes.data, len(cfg), _ptr(state), _ptr(out),
+                                _ptr(dump_n), _ptr(n_dumps), _ptr(status), max_dumps,
+                                C.byref(h)), "gc_batch_create")
+    return h.value
+
+
+def gc_batch_configure(batch: int, shape: int, grid: int = 0) -> None:
+    _check(_lib.gc_batch_configure(batch, shape, grid), "gc_batch_configure")
+
+
+def gc_batch_tune(batch: int, reps: int = 3) -> None:
+    _check(_lib.gc_batch_tune(batch, reps), "gc_batch_tune")
+
+
+def gc_batch_launch(batch: int, stream=None) -> None:
+    _check(_lib.gc_batch_launch(batch, _stream_ptr(stream)), "gc_batch_launch")
+
+
+def gc_batch_info(batch: int) -> dict:
+    a, b, c, d = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    ms = C.c_float()
+    _check(_lib.gc_batch_info(batch, C.byref(a), C.byref(b), C.byref(c), C.byref(d), C.byref(ms)),
+           "gc_batch_info")
+    return {"shape": a.value, "grid": b.value, "n_items": c.value, "n_shapes": d.value,
+            "tuned_ms": ms.value}
+
+
+def gc_batch_destroy(batch: int) -> None:
+    _check(_lib.gc_batch_destroy(batch), "gc_batch_destroy")
+
+
 def _stream_ptr(stream):
     if stream is None:
         return None
@@ -239,3 +287,61 @@ class Plan:
                           max_dumps, stream if stream is not None
                           else self.torch.cuda.current_stream(self.device))
         _check(rc, "gc_correlate")
+
+
+class Batch:
+    """A batch of receivers bound to its device buffers (torch tensors): the
+    receivers' sample blocks, the channel states and the outputs."""
+
+    def __init__(self, ctx: int, blocks, fmts, n_samples, cfgs: np.ndarray, chan_rx,
+                 states: np.ndarray, max_dumps: int, device=None):
+        import torch
+
+        self.torch = torch
+        self.device = device or torch.device("cuda", torch.cuda.current_device())
+        self.blocks = list(blocks)           # keep the sample tensors alive
+        self.cfgs = np.ascontiguousarray(cfgs, dtype=CHAN_CFG)
+        n_chan = len(self.cfgs)
+        self.tap_stride = int(self.cfgs["n_taps"].max())
+        self.max_dumps = max_dumps
+        rx = np.zeros(len(self.blocks), RX_DESC)
+        for r, (b, f, n) in enumerate(zip(self.blocks, fmts, n_samples)):
+            rx[r]["samples"] = b.data_ptr()
+            rx[r]["n_samples"] = n
+            rx[r]["fmt"] = f
+        b = np.ascontiguousarray(states, dtype=CHAN_STATE).view(np.uint8)
+        self.state = torch.from_numpy(b.copy()).to(self.device)
+        self.out = torch.zeros((n_chan, max_dumps, self.tap_stride, 2), dtype=torch.int32,
+                               device=self.device)
+        self.dump_n = torch.zeros((n_chan, max_dumps), dtype=torch.int32, device=self.device)
+        self.n_dumps = torch.zeros(n_chan, dtype=torch.int32, device=self.device)
+        self.status = torch.zeros(n_chan, dtype=torch.int32, device=self.device)
+        self.handle = gc_batch_create(ctx, rx, self.cfgs, chan_rx, self.state, self.out,
+                                      self.dump_n, self.n_dumps, self.status, max_dumps)
+
+    def configure(self, shape: int, grid: int = 0):
+        gc_batch_configure(self.handle, shape, grid)
+
+    def tune(self, reps: int = 3):
+        gc_batch_tune(self.handle, reps)
+
+    def launch(self, stream=None):
+        gc_batch_launch(self.handle, stream if stream is not None
+                        else self.torch.cuda.current_stream(self.device))
+
+    def info(self) -> dict:
+        return gc_batch_info(self.handle)
+
+    def states(self) -> np.ndarray:
+        return self.state.cpu().numpy().view(CHAN_STATE).copy()
+
+    def close(self):
+        if self.handle:
+            gc_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
