@@ -7,7 +7,9 @@ MHz, IF = 4.092 MHz, 10 s of data, 12 PRNs with seeded Doppler / code phase /
 C/N0, 1 ms dumps, early/prompt/late at +-1/2 chip.  One step = one
 correlation of the whole block for all channels (all hot-path stages),
 starting from the same initial channel state, inputs already resident in
-HBM.  Other workloads: "single" (1 channel, int8 real at 4.092 MHz, 1 s) and
+HBM.  Other workloads: "single" (1 channel, int8 real at 4.092 MHz, 1 s),
+"batched" (64 receivers of 8-14 channels, mixed rates, formats and dump
+lengths, 1 s each, one graph-captured persistent launch) and
 "multicorrelator" (256 channels x 128 taps at 1/32 chip, complex int8 at
 20.46 MHz, 2 s).
 
@@ -59,10 +61,19 @@ WORKLOADS = {
         describe="1 channel (PRN 7), int8 real, fs 4.092 MHz, IF 1.023 MHz, %g s, 1 ms dumps, "
                  "E/P/L at +-1/2 chip", seconds=1.0, ops=6, fmt_name="i8_real",
         cpu_seconds=1.0),
+    "batched": dict(
+        describe="64 receivers x 8-14 channels, fs 4.092/8.184/16.368 MHz (IF fs/4), int8 or "
+                 "2-bit real, 1/4/20 ms dumps per channel, %g s each, E/P/L at +-1/2 chip",
+        seconds=1.0, ops=6, fmt_name="i8_real+i2_real", cpu_seconds=1.0),
     "multicorrelator": dict(
         describe="256 channels x 128 taps (-2 + k/32 chips), complex int8, fs 20.46 MHz, IF 0, "
                  "%g s, 1 ms dumps", seconds=2.0, ops=14, fmt_name="i8_iq",
         cpu_seconds=0.05),
+    "serving": dict(
+        describe="500 receivers x 4-14 channels (fs 4.092/8.184/16.368 MHz, IF fs/4, int8 or "
+                 "2-bit real, 1/4/20 ms dumps, E/P/L at +-1/2 chip), Poisson arrivals at 2000 "
+                 "requests/s over %g s, each request U{1..20} ms of one receiver's samples",
+        seconds=10.0, ops=6, fmt_name="i8_real+i2_real", cpu_seconds=0.0),
 }
 
 
@@ -180,6 +191,336 @@ def plain_baseline(torch, g, ctx, st, cfgs, states, samples, n, max_dumps, strea
     return dt
 
 
+def main_batched(args, wl, seconds, cpu_seconds):
+    """Workload "batched": one batch (persistent graph-captured launch, tuned
+    block shape) against one plan per receiver and one direct launch per
+    channel, all on the same inputs."""
+    import torch
+
+    from paper_1907_00463_amd import gnsscorr as g
+    from paper_1907_00463_amd import synth
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    print("bench: generating %.3f s of the batched workload" % seconds, file=sys.stderr,
+          flush=True)
+    work = synth.workload_batched(seconds=seconds)
+    bufs = synth.synth_batched(work)
+    cfgs, states, chan_rx = [], [], []
+    for r, (st, chans, _) in enumerate(work):
+        for ch in chans:
+            cfgs.append(g.make_cfg(ch.prn, synth.taps_to_q32(ch.taps_chips), ch.int_periods))
+            states.append(g.gc_nco_init(st.fs, ch.carr_hz, ch.carr_phase0, ch.code_rate,
+                                        ch.code_phase0, ch.int_periods))
+            chan_rx.append(r)
+    cfgs = np.array(cfgs, g.CHAN_CFG)
+    states = np.array(states, g.CHAN_STATE)
+    chan_rx = np.array(chan_rx, np.int32)
+    ctx = g.gc_create(0)
+    blocks = [torch.from_numpy(b).to(dev) for b in bufs]
+    ns = [st.n for (st, _, _) in work]
+    max_dumps = max(g.max_dumps_for(n, int(states["code_step"].max()), 1) for n in ns)
+    batch = g.Batch(ctx, blocks, [st.fmt for (st, _, _) in work], ns, cfgs, chan_rx, states,
+                    max_dumps)
+    s0 = batch.state.clone()
+    stream = torch.cuda.current_stream(dev)
+    print("bench: tuning", file=sys.stderr, flush=True)
+    batch.tune(reps=2)
+    info = batch.info()
+
+    def step():
+        batch.state.copy_(s0)
+        batch.launch(stream)
+
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    graph_ms = ev0.elapsed_time(ev1) / args.steps
+    assert int(batch.status.abs().sum()) == 0, "channel refused"
+    sample_ch = sum(n * int((chan_rx == r).sum()) for r, n in enumerate(ns))
+    sample_taps = 3 * sample_ch
+    data_s = sum(int((chan_rx == r).sum()) * n / st.fs for r, (n, (st, _, _)) in
+                 enumerate(zip(ns, work)))
+    achieved = wl["ops"] * sample_ch / (graph_ms / 1e3) / 1e12
+    res = {
+        "metric": METRIC, "value": round(sample_taps / wall / 1e9, 3),
+        "unit": "G sample·taps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": wl["describe"] % seconds, "receivers": len(work),
+                   "channels": len(cfgs), "samples": int(sum(ns)),
+                   "sample_channels": int(sample_ch), "kernels": "batch",
+                   "shape": info["shape"], "grid": info["grid"], "work_items": info["n_items"],
+                   "tuned_ms": round(info["tuned_ms"], 4),
+                   "realtime_channels": round(data_s / wall, 1)},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3),
+                     "peak": round(VALU_PEAK_TOPS, 2), "unit": "T lane-ops/s",
+                     "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                     "kernel_ms": round(graph_ms, 4), "ops_per_sample_channel": wl["ops"],
+                     "note": "kernel_ms is the whole graph (set-up, rows, batch kernel)"},
+    }
+    # one plan per receiver (all kernel families), launched one after another
+    plans = []
+    for r, (st, _, _) in enumerate(work):
+        idx = np.nonzero(chan_rx == r)[0]
+        p = g.Plan(ctx, st.fmt, g.GC_CARRIER_LUT, cfgs[idx])
+        sp0 = p.states_to_device(states[idx])
+        plans.append((p, sp0, sp0.clone(), p.outputs(max_dumps), blocks[r], ns[r]))
+
+    def step_plans():
+        for p, sp0, sp, (o, dn, nd, stt), blk, n in plans:
+            sp.copy_(sp0)
+            p.correlate(blk, n, sp, o, dn, nd, stt, stream=stream)
+
+    dt = time_steps(torch, step_plans, max(1, min(args.steps, 5)), 1)
+    res["per_receiver_plans"] = {"value": round(sample_taps / dt / 1e9, 3),
+                                 "unit": "G sample·taps/s", "ms_per_step": round(dt * 1e3, 4),
+                                 "speedup_of_batch": round(dt / wall, 2)}
+    for p, *_ in plans:
+        p.close()
+    if not args.no_plain:
+        print("bench: plain per-channel launches", file=sys.stderr, flush=True)
+        pl = []
+        for i in range(len(cfgs)):
+            r = int(chan_rx[i])
+            p = g.Plan(ctx, work[r][0].fmt, g.GC_CARRIER_LUT, cfgs[i: i + 1])
+            g.gc_plan_set_kernels(p.handle, 0)
+            sp0 = p.states_to_device(states[i: i + 1])
+            pl.append((p, sp0, sp0.clone(), p.outputs(max_dumps), blocks[r], ns[r]))
+
+        def step_plain():
+            for p, sp0, sp, (o, dn, nd, stt), blk, n in pl:
+                sp.copy_(sp0)
+                p.correlate(blk, n, sp, o, dn, nd, stt, stream=stream)
+
+        dt = time_steps(torch, step_plain, 1, 1)
+        res["plain"] = {"value": round(sample_taps / dt / 1e9, 3), "unit": "G sample·taps/s",
+                        "ms_per_step": round(dt * 1e3, 4),
+                        "kind": "one plan and one direct-kernel launch per channel",
+                        "speedup": round(dt / wall, 2)}
+        for p, *_ in pl:
+            p.close()
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline", file=sys.stderr, flush=True)
+        # the oracle on the first 8 receivers (all their channels), scaled
+        # as a rate (G sample*taps/s)
+        from concurrent.futures import ThreadPoolExecutor
+
+        import oracle
+        sel = [i for i in range(len(cfgs)) if chan_rx[i] < 8]
+        threads = min(len(sel), os.cpu_count() or 1)
+
+        def one(i):
+            r = int(chan_rx[i])
+            s = states[i]
+            os_ = oracle.OracleState(int(s["carr_phase"]), int(s["carr_step"]),
+                                     int(s["code_phase"]), int(s["code_step"]), 3)
+            return oracle.correlate_lut(work[r][0].fmt, bufs[r], ns[r], int(cfgs[i]["prn"]),
+                                        cfgs[i]["tap_q32"][:3], int(cfgs[i]["int_periods"]), os_)
+
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            list(ex.map(one, sel))
+        dt = time.perf_counter() - t0
+        st_sel = sum(3 * ns[int(chan_rx[i])] for i in sel)
+        res["cpu_baseline"] = {"value": st_sel / dt / 1e9, "unit": "G sample·taps/s",
+                               "cores": threads, "kind": "oracle",
+                               "sample": "receivers 0-7 (%d channels) of the same workload, "
+                                         "threads over channels; %.2f s wall" % (len(sel), dt)}
+    batch.close()
+    g.gc_destroy(ctx)
+    print(json.dumps(res), flush=True)
+
+
+def serve_schedule(g, server, sched, payload, n_chan, deadline_s=1e-3):
+    """Open-loop client: submit every request at its arrival time (a request
+    refused by admission is retried until admitted), collect results as they
+    finish.  Latency runs from the scheduled arrival to the host seeing the
+    result, so it includes client delay, admission, the H2D copy, queueing,
+    the launch and the D2H copy of the results."""
+    import ctypes as C
+
+    t_arr, rx, _, ns = sched
+    lib = g._lib
+    n_req = len(t_arr)
+    lat = np.full(n_req, np.nan)
+    svc = np.zeros(1, np.float64)
+    status = np.zeros(max(n_chan), np.int32)
+    ids = np.zeros(4096, np.uint64)
+    rid, nd = C.c_uint64(), C.c_int32()
+    pending = {}
+    refused = bad = i = done = 0
+    t_done_last = 0.0
+    t0 = time.perf_counter() + 0.02
+    while done < n_req:
+        now = time.perf_counter() - t0
+        while i < n_req and t_arr[i] <= now:
+            ptr, n = payload[i]
+            rc = lib.gc_server_submit(server, int(rx[i]), ptr, n, C.byref(rid))
+            if rc == g.GC_EBUSY:
+                refused += 1
+                break
+            if rc != g.GC_OK:
+                raise g.GcError(rc, "gc_server_submit")
+            pending[rid.value] = i
+            i += 1
+        rc = lib.gc_server_poll(server, ids.ctypes.data, len(ids), C.byref(nd))
+        if rc != g.GC_OK:
+            raise g.GcError(rc, "gc_server_poll")
+        if nd.value:
+            t = time.perf_counter() - t0
+            for k in range(nd.value):
+                j = pending.pop(int(ids[k]))
+                lat[j] = t - t_arr[j]
+                rc = lib.gc_server_result(server, int(ids[k]), None, None, None,
+                                          status.ctypes.data, svc.ctypes.data)
+                if rc != g.GC_OK:
+                    raise g.GcError(rc, "gc_server_result")
+                bad += int(np.any(status[: n_chan[int(rx[j])]] != 0))
+            done += nd.value
+            t_done_last = t
+    ms = lat * 1e3
+    return {"requests": n_req, "p50_ms": round(float(np.percentile(ms, 50)), 4),
+            "p99_ms": round(float(np.percentile(ms, 99)), 4),
+            "p999_ms": round(float(np.percentile(ms, 99.9)), 4),
+            "max_ms": round(float(ms.max()), 4),
+            "deadline_ms": deadline_s * 1e3,
+            "deadline_miss_frac": round(float(np.mean(lat > deadline_s)), 5),
+            "admission_retries": refused, "channel_errors": bad,
+            "makespan_s": round(t_done_last, 4)}
+
+
+def main_serving(args, wl, seconds):
+    """Workload "serving": the open-loop Poisson schedule through the
+    continuous-batching server, then through the same server in plain mode
+    (every request alone, one set-up and one direct-kernel launch per
+    channel)."""
+    import torch
+
+    from paper_1907_00463_amd import gnsscorr as g
+    from paper_1907_00463_amd import synth
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    print("bench: generating the serving workload", file=sys.stderr, flush=True)
+    work = synth.workload_serving()
+    bufs = synth.synth_batched(work)
+    sched = synth.serving_schedule(work, seconds=seconds)
+    t_arr, rx, off, ns = sched
+    per = {0: 1, 2: 4}     # samples per byte
+    payload = []
+    for r, o, n in zip(rx, off, ns):
+        st = work[int(r)][0]
+        b = bufs[int(r)]
+        payload.append((b.ctypes.data + int(o) // per[st.fmt], int(n)))
+    cfgs, states = [], []
+    for st, chans, _ in work:
+        cfgs.append(np.array([g.make_cfg(ch.prn, synth.taps_to_q32(ch.taps_chips),
+                                         ch.int_periods) for ch in chans], g.CHAN_CFG))
+        states.append(np.array([g.gc_nco_init(st.fs, ch.carr_hz, ch.carr_phase0, ch.code_rate,
+                                              ch.code_phase0, ch.int_periods) for ch in chans],
+                               g.CHAN_STATE))
+    n_chan = [len(c) for c in cfgs]
+    step_max = max(int(s["code_step"].max()) for s in states)
+    max_dumps = g.max_dumps_for(int(ns.max()), step_max, 1)
+    sample_ch = int(sum(int(n) * n_chan[int(r)] for r, n in zip(rx, ns)))
+    ctx = g.gc_create(0)
+    res = None
+    for mode in ("batched", "plain"):
+        if mode == "plain" and args.no_plain:
+            continue
+        flags = g.GC_SERVER_PLAIN if mode == "plain" else 0
+        srv = g.gc_server_create(ctx, 256 << 20, 1 << 30, sum(n_chan), len(work), max_dumps,
+                                 n_streams=2, max_batch_rx=len(work), flags=flags)
+        for (st, _, _), c, s0 in zip(work, cfgs, states):
+            g.gc_server_open_rx(srv, st.fmt, c, s0)
+        # warm-up: the first requests of the schedule, one after another
+        # (they advance those receivers' states; results are not used)
+        for k in range(min(args.warmup, len(t_arr))):
+            r, p = int(rx[k]), per[work[int(rx[k])][0].fmt]
+            q = g.gc_server_submit(srv, r, bufs[r][int(off[k]) // p: (int(off[k]) + int(ns[k]))
+                                                  // p], int(ns[k]))
+            while not len(g.gc_server_poll(srv)):
+                time.sleep(1e-4)
+            g.gc_server_result(srv, q, n_chan[int(rx[k])], max_dumps)
+        print("bench: serving (%s), %d requests over %g s" % (mode, len(t_arr), seconds),
+              file=sys.stderr, flush=True)
+        stats = serve_schedule(g, srv, sched, payload, n_chan)
+        info = g.gc_server_info(srv)
+        stats["launches"] = info["launches"]
+        stats["requests_per_launch"] = round(info["launched_requests"] / max(1, info["launches"]),
+                                             3)
+        g.gc_server_destroy(srv)
+        print("bench: %s p50 %.3f ms p99 %.3f ms" % (mode, stats["p50_ms"], stats["p99_ms"]),
+              file=sys.stderr, flush=True)
+        tput = 3 * sample_ch / stats["makespan_s"] / 1e9
+        if mode == "batched":
+            achieved = wl["ops"] * sample_ch / stats["makespan_s"] / 1e12
+            res = {
+                "metric": METRIC, "value": round(tput, 3), "unit": "G sample·taps/s",
+                "n_gpus": 1, "steps": len(t_arr), "warmup": 0,
+                "ms_per_step": round(stats["makespan_s"] * 1e3 / len(t_arr), 4),
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                "dtype": "int32", "data": "synthetic",
+                "config": {"workload": wl["describe"] % seconds, "receivers": len(work),
+                           "channels": sum(n_chan), "requests": len(t_arr),
+                           "sample_channels": sample_ch, "max_dumps": max_dumps,
+                           "streams": 2, "kernels": "server"},
+                "serving": stats,
+                "roofline": {"bound": "alu", "achieved": round(achieved, 4),
+                             "peak": round(VALU_PEAK_TOPS, 2), "unit": "T lane-ops/s",
+                             "frac": round(achieved / VALU_PEAK_TOPS, 5), "traffic": None,
+                             "note": "offered-load bound: the value is the offered rate once "
+                                     "the server keeps up; the kernel's own fraction is that of "
+                                     "the batched workload"},
+            }
+        else:
+            stats["value"] = round(tput, 3)
+            stats["kind"] = "same server, every request alone, one set-up and one direct-kernel " \
+                            "launch per channel"
+            res["plain"] = stats
+    if not args.no_cpu_baseline:
+        # the oracle over the first 2000 requests of the schedule, each from
+        # its receiver's initial states, threads over requests
+        from concurrent.futures import ThreadPoolExecutor
+
+        import oracle
+        k_req = min(2000, len(t_arr))
+        threads = min(16, os.cpu_count() or 1)
+
+        def one(k):
+            r, p = int(rx[k]), per[work[int(rx[k])][0].fmt]
+            blk = bufs[r][int(off[k]) // p: (int(off[k]) + int(ns[k])) // p]
+            for i in range(n_chan[r]):
+                s_ = states[r][i]
+                c = cfgs[r][i]
+                os_ = oracle.OracleState(int(s_["carr_phase"]), int(s_["carr_step"]),
+                                         int(s_["code_phase"]), int(s_["code_step"]), 3)
+                oracle.correlate_lut(work[r][0].fmt, blk, int(ns[k]), int(c["prn"]),
+                                     c["tap_q32"][:3], int(c["int_periods"]), os_)
+
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            list(ex.map(one, range(k_req)))
+        dt = time.perf_counter() - t0
+        st_k = 3 * sum(int(ns[k]) * n_chan[int(rx[k])] for k in range(k_req))
+        res["cpu_baseline"] = {"value": st_k / dt / 1e9, "unit": "G sample·taps/s",
+                               "cores": threads, "kind": "oracle",
+                               "sample": "the first %d requests of the schedule, all their "
+                                         "channels, threads over requests; %.2f s wall"
+                                         % (k_req, dt)}
+    g.gc_destroy(ctx)
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -204,6 +545,10 @@ def main():
     wl = WORKLOADS[args.workload]
     seconds = args.seconds if args.seconds is not None else wl["seconds"]
     cpu_seconds = args.cpu_seconds if args.cpu_seconds is not None else wl["cpu_seconds"]
+    if args.workload == "batched":
+        return main_batched(args, wl, seconds, cpu_seconds)
+    if args.workload == "serving":
+        return main_serving(args, wl, seconds)
 
     import torch
 

@@ -298,6 +298,104 @@ gc_status gc_batch_info(const gc_batch* b, int32_t* shape, int32_t* grid, int32_
 /* Release a batch (waits for the device). */
 gc_status gc_batch_destroy(gc_batch* b);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of requests from many receivers.
+ *
+ * A server owns the channels of its registered receivers (configuration and
+ * NCO state stay resident in device memory between requests, Sec. 3.5: a
+ * channel continues from the state of its previous block) and a device
+ * arena for request samples of hbm_budget_bytes.  A request is one sample
+ * block of one receiver, given in host memory: gc_server_submit admits it
+ * when its samples fit the arena and the pinned host arena, else refuses it
+ * with GC_EBUSY (the caller retries after collecting results).  The
+ * server's dispatcher thread keeps up to n_streams launches in flight; each
+ * runs the oldest waiting request of up to max_batch_rx idle receivers
+ * together (set-up and one persistent launch of the chip-by-chip E/P/L
+ * kernel over all their tiles), so requests that arrive while others run
+ * join the next launch.  The requests of one receiver run in submission
+ * order.  Results equal those of gc_correlate on one plan per receiver
+ * called once per request, bit for bit, whatever the mix.  With
+ * GC_SERVER_PLAIN every request runs alone and every channel with its own
+ * set-up and direct-kernel launch (the per-channel baseline).
+ * Every function is thread-safe except gc_server_destroy.
+ * ------------------------------------------------------------------------ */
+typedef struct gc_server gc_server;
+
+#define GC_SERVER_PLAIN 1
+
+/* Create a server on the context's device.
+ *   hbm_budget_bytes   device arena for admitted request samples (>= 4096)
+ *   host_budget_bytes  pinned host arena for staged samples and results
+ *   max_channels       channel capacity over all receivers (1..GC_MAX_CHANNELS)
+ *   max_receivers      receiver capacity (1..65536)
+ *   max_dumps          output rows per channel per request (2..4096); a
+ *                      request that would close more reports GC_ENOSPC in
+ *                      its channels' status
+ *   n_streams          launches in flight (1..16), each on its own
+ *                      default-priority HIP stream
+ *   max_batch_rx       receivers per launch (1..4096)
+ *   flags              0 or GC_SERVER_PLAIN
+ * Errors: GC_EINVAL, GC_ENOMEM, GC_EDEVICE. */
+gc_status gc_server_create(gc_ctx* ctx, uint64_t hbm_budget_bytes, uint64_t host_budget_bytes,
+                           int32_t max_channels, int32_t max_receivers, uint32_t max_dumps,
+                           int32_t n_streams, int32_t max_batch_rx, int32_t flags,
+                           gc_server** out);
+
+/* Register a receiver: sample format (GC_I8_REAL or GC_I2_REAL), n_chan
+ * channel configurations with at most 4 taps each, and their initial NCO
+ * states (host arrays, copied).  Its id, counted from 0, goes to *rx_id.
+ * Synchronous.  Errors: GC_EINVAL (null, fmt, a configuration), GC_ENOMEM
+ * (channel or receiver capacity reached), GC_EDEVICE. */
+gc_status gc_server_open_rx(gc_server* s, int32_t fmt, const gc_chan_cfg* cfg,
+                            const gc_chan_state* state0, int32_t n_chan, int32_t* rx_id);
+
+/* Submit a request: n_samples (0 .. 2^31-1) samples of receiver rx_id in its
+ * format, in host memory (copied before return; the buffer may be reused at
+ * once).  The request id (never 0) goes to *req_id.
+ * Errors: GC_EINVAL, GC_EBUSY (over the HBM or host budget: nothing was
+ * queued), GC_EDEVICE (also after an earlier device error). */
+gc_status gc_server_submit(gc_server* s, int32_t rx_id, const void* host_samples,
+                           uint64_t n_samples, uint64_t* req_id);
+
+/* Stop (hold = 1) or resume (hold = 0) forming launches; launches already
+ * made run to completion and submissions are still admitted.  For callers
+ * that submit a group of requests to run together, and for draining.
+ * Errors: GC_EINVAL. */
+gc_status gc_server_hold(gc_server* s, int32_t hold);
+
+/* Collect up to max_n ids of finished requests, oldest first, into ids
+ * (host); their number goes to *n_done.  Non-blocking.
+ * Errors: GC_EINVAL, GC_EDEVICE (a launch failed; results are not valid). */
+gc_status gc_server_poll(gc_server* s, uint64_t* ids, int32_t max_n, int32_t* n_done);
+
+/* Copy a finished request's results to host arrays (any may be NULL) and
+ * release it:
+ *   out        int32 [n_chan][max_dumps][4][2]   (dump I, Q per tap slot)
+ *   dump_n     uint32 [n_chan][max_dumps]
+ *   n_dumps    uint32 [n_chan]
+ *   status     int32 [n_chan]
+ *   service_s  double [1]: seconds from submission to the host seeing the
+ *              launch complete
+ * with n_chan the receiver's channel count, rows as gc_correlate writes
+ * them.  Errors: GC_EINVAL (unknown id), GC_EAGAIN (not finished). */
+gc_status gc_server_result(gc_server* s, uint64_t req_id, int32_t* out, uint32_t* dump_n,
+                           uint32_t* n_dumps, int32_t* status, double* service_s);
+
+/* Wait until the receiver has no request queued or running, then copy its
+ * channels' NCO states to host_out[n_chan].  Errors: GC_EINVAL, GC_EDEVICE. */
+gc_status gc_server_state(gc_server* s, int32_t rx_id, gc_chan_state* host_out);
+
+/* Query (any pointer may be NULL): rows per channel, tap stride (4),
+ * requests admitted and not finished, device arena bytes in use, launches
+ * made and requests they carried. */
+gc_status gc_server_info(gc_server* s, uint32_t* max_dumps, int32_t* tap_stride,
+                         int32_t* in_flight, uint64_t* hbm_in_use, uint64_t* launches,
+                         uint64_t* launched_requests);
+
+/* Stop the dispatcher, wait for the device and release everything
+ * (unfetched results are dropped). */
+gc_status gc_server_destroy(gc_server* s);
+
 #ifdef __cplusplus
 }
 #endif

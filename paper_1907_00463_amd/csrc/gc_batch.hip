@@ -61,7 +61,7 @@ hipError_t upload_rx(gc_batch* b, int shape) {
 hipError_t enqueue(gc_batch* b, hipStream_t s) {
     hipError_t e = gc::launch_setup(b->d_chans, b->d_meta, b->state, b->n_chan, 0, GC_I8_REAL,
                                     GC_CARRIER_LUT, b->max_dumps, b->out, b->max_taps, b->dump_n,
-                                    b->n_dumps, b->status, gc::kAllowBinned, b->d_rx, s);
+                                    b->n_dumps, b->status, gc::kAllowBinned, b->d_rx, nullptr, nullptr, s);
     if (e == hipSuccess)
         e = gc::launch_epl_batch(b->shape, b->grid > 0 ? b->grid : b->cus, b->d_rx, b->n_rx,
                                  nullptr, b->n_items, b->d_chans, b->d_meta, b->state,

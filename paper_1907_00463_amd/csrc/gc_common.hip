@@ -107,13 +107,16 @@ __global__ __launch_bounds__(64) void k_setup(const DevChan* __restrict__ chans,
                                                uint32_t* __restrict__ n_dumps,
                                                int32_t* __restrict__ status_out,
                                                int32_t allow,
-                                               const DevRx* __restrict__ rx) {
-    const int ch = blockIdx.x;
+                                               const DevRx* __restrict__ rx,
+                                               const int32_t* __restrict__ list,
+                                               const int32_t* __restrict__ list_rx) {
+    const int ch = list ? list[blockIdx.x] : (int)blockIdx.x;
     const int tid = threadIdx.x;
     const DevChan& c = chans[ch];
     if (rx) {  // batch: the block and format of the channel's receiver
-        n = rx[c.rx].n;
-        fmt = rx[c.rx].fmt;
+        const int r = list_rx ? list_rx[blockIdx.x] : c.rx;
+        n = rx[r].n;
+        fmt = rx[r].fmt;
     }
     gc_chan_state* st = state + ch;
     __shared__ DevMeta sm;
@@ -233,8 +236,9 @@ __device__ __forceinline__ uint64_t udiv_ceil(uint64_t num, uint64_t d) {
 __global__ __launch_bounds__(256) void k_rows(const DevChan* __restrict__ chans,
                                               const DevMeta* __restrict__ metas, int carrier,
                                               uint32_t max_dumps, void* out, int tap_stride,
-                                              uint32_t* __restrict__ dump_n) {
-    const int ch = blockIdx.y;
+                                              uint32_t* __restrict__ dump_n,
+                                              const int32_t* __restrict__ list) {
+    const int ch = list ? list[blockIdx.y] : (int)blockIdx.y;
     const DevMeta m = metas[ch];
     if (m.status != GC_OK) return;
     const uint32_t M = m.m_close;
@@ -265,12 +269,14 @@ __global__ __launch_bounds__(256) void k_rows(const DevChan* __restrict__ chans,
 hipError_t launch_setup(const DevChan* chans, DevMeta* meta, gc_chan_state* state, int n_chan,
                         uint64_t n_samples, int fmt, int carrier, uint32_t max_dumps, void* out,
                         int tap_stride, uint32_t* dump_n, uint32_t* n_dumps, int32_t* status,
-                        int32_t allow, const DevRx* rx, hipStream_t s) {
+                        int32_t allow, const DevRx* rx, const int32_t* list,
+                        const int32_t* list_rx, hipStream_t s) {
     hipLaunchKernelGGL(k_setup, dim3(n_chan), dim3(64), 0, s, chans, meta, state, n_samples, fmt,
-                       carrier, max_dumps, out, tap_stride, dump_n, n_dumps, status, allow, rx);
+                       carrier, max_dumps, out, tap_stride, dump_n, n_dumps, status, allow, rx,
+                       list, list_rx);
     const uint32_t gx = min((max_dumps + 255u) / 256u, 256u);
     hipLaunchKernelGGL(k_rows, dim3(gx, n_chan), dim3(256), 0, s, chans, meta, carrier, max_dumps,
-                       out, tap_stride, dump_n);
+                       out, tap_stride, dump_n, list);
     return hipGetLastError();
 }
 

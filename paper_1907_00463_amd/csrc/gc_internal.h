@@ -107,7 +107,11 @@ hipError_t launch_code_table(const uint32_t* d_tables, int g2_delay, int8_t* d_o
 hipError_t launch_setup(const DevChan* chans, DevMeta* meta, gc_chan_state* state, int n_chan,
                         uint64_t n_samples, int fmt, int carrier, uint32_t max_dumps,
                         void* out, int tap_stride, uint32_t* dump_n, uint32_t* n_dumps,
-                        int32_t* status, int32_t allow, const DevRx* rx, hipStream_t s);
+                        int32_t* status, int32_t allow, const DevRx* rx,
+                        const int32_t* list, const int32_t* list_rx, hipStream_t s);
+// list: the channels to set up (null: 0 .. n_chan-1); rx: receiver table of a
+// batch (null: one block of n_samples in fmt), indexed by list_rx[i] when
+// given, else by the channel's rx field
 // batched chip-by-chip kernel (shape 0 .. epl_batch_shapes()-1)
 int epl_batch_shapes();
 uint32_t epl_batch_tile(int shape);

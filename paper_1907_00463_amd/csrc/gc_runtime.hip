@@ -323,7 +323,7 @@ gc_status gc_correlate(gc_plan* plan, const void* samples, uint64_t n_samples,
                           (mtap ? gc::kAllowMtap : 0);
     hipError_t e = gc::launch_setup(plan->d_chans, plan->d_meta, state, plan->n_chan, n_samples,
                                     plan->fmt, plan->carrier, max_dumps, out, plan->max_taps,
-                                    dump_n, n_dumps, status, allow, nullptr, s);
+                                    dump_n, n_dumps, status, allow, nullptr, nullptr, nullptr, s);
     const uint8_t* x = (const uint8_t*)samples;
     const size_t slot = plan->ev_stop.empty() ? 0 : (size_t)(plan->calls % plan->ev_stop.size());
     const bool timed = !plan->ev_start.empty();

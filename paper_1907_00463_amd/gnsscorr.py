@@ -21,6 +21,7 @@ GC_OK, GC_EINVAL, GC_ENOMEM, GC_EDEVICE, GC_ERANGE, GC_EBUSY, GC_EAGAIN, GC_ENOS
 GC_I8_REAL, GC_I8_IQ, GC_I2_REAL = 0, 1, 2
 GC_CARRIER_LUT, GC_CARRIER_F32 = 0, 1
 GC_KERNEL_PERIODIC, GC_KERNEL_BINNED, GC_KERNEL_MTAP = 1, 2, 4
+GC_SERVER_PLAIN = 1
 GC_MAX_TAPS = 128
 GC_LUT_AMP = 24
 TWO32 = 1 << 32
@@ -69,6 +70,15 @@ def _load():
         "gc_batch_launch": ([P, P], I32),
         "gc_batch_info": ([P, P, P, P, P, P], I32),
         "gc_batch_destroy": ([P], I32),
+        "gc_server_create": ([P, U64, U64, I32, I32, U32, I32, I32, I32, P], I32),
+        "gc_server_open_rx": ([P, I32, P, P, I32, P], I32),
+        "gc_server_submit": ([P, I32, P, U64, P], I32),
+        "gc_server_hold": ([P, I32], I32),
+        "gc_server_poll": ([P, P, I32, P], I32),
+        "gc_server_result": ([P, U64, P, P, P, P, P], I32),
+        "gc_server_state": ([P, I32, P], I32),
+        "gc_server_info": ([P, P, P, P, P, P, P], I32),
+        "gc_server_destroy": ([P], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -82,7 +92,9 @@ EXPORTED = ("gc_strerror", "gc_version", "gc_create", "gc_destroy", "gc_nco_init
             "gc_code_table", "gc_plan_create", "gc_plan_destroy", "gc_plan_info",
             "gc_correlate", "gc_plan_timing", "gc_plan_kernel_ms", "gc_plan_set_kernels",
             "gc_batch_create", "gc_batch_configure", "gc_batch_tune", "gc_batch_launch",
-            "gc_batch_info", "gc_batch_destroy")
+            "gc_batch_info", "gc_batch_destroy", "gc_server_create", "gc_server_open_rx",
+            "gc_server_submit", "gc_server_hold", "gc_server_poll", "gc_server_result", "gc_server_state",
+            "gc_server_info", "gc_server_destroy")
 
 
 def _check(rc: int, where: str):
@@ -212,6 +224,83 @@ def gc_batch_info(batch: int) -> dict:
 
 def gc_batch_destroy(batch: int) -> None:
     _check(_lib.gc_batch_destroy(batch), "gc_batch_destroy")
+
+
+def gc_server_create(ctx: int, hbm_budget: int, host_budget: int, max_channels: int,
+                     max_receivers: int, max_dumps: int, n_streams: int = 2,
+                     max_batch_rx: int = 256, flags: int = 0) -> int:
+    h = C.c_void_p()
+    _check(_lib.gc_server_create(ctx, hbm_budget, host_budget, max_channels, max_receivers,
+                                 max_dumps, n_streams, max_batch_rx, flags, C.byref(h)),
+           "gc_server_create")
+    return h.value
+
+
+def gc_server_open_rx(server: int, fmt: int, cfg: np.ndarray, state0: np.ndarray) -> int:
+    cfg = np.ascontiguousarray(cfg, dtype=CHAN_CFG)
+    state0 = np.ascontiguousarray(state0, dtype=CHAN_STATE)
+    assert len(cfg) == len(state0)
+    r = C.c_int32()
+    _check(_lib.gc_server_open_rx(server, fmt, cfg.ctypes.data, state0.ctypes.data, len(cfg),
+                                  C.byref(r)), "gc_server_open_rx")
+    return r.value
+
+
+def gc_server_submit(server: int, rx_id: int, samples: np.ndarray, n_samples: int):
+    """Returns the request id, or None when admission is refused (GC_EBUSY)."""
+    samples = np.ascontiguousarray(samples, dtype=np.uint8)
+    rid = C.c_uint64()
+    rc = _lib.gc_server_submit(server, rx_id, samples.ctypes.data, n_samples, C.byref(rid))
+    if rc == GC_EBUSY:
+        return None
+    _check(rc, "gc_server_submit")
+    return rid.value
+
+
+def gc_server_hold(server: int, hold: bool) -> None:
+    _check(_lib.gc_server_hold(server, int(bool(hold))), "gc_server_hold")
+
+
+def gc_server_poll(server: int, max_n: int = 4096) -> np.ndarray:
+    ids = np.zeros(max_n, np.uint64)
+    n = C.c_int32()
+    _check(_lib.gc_server_poll(server, ids.ctypes.data, max_n, C.byref(n)), "gc_server_poll")
+    return ids[: n.value]
+
+
+def gc_server_result(server: int, req_id: int, n_chan: int, max_dumps: int):
+    """(out, dump_n, n_dumps, status, service_s) of a finished request, or
+    None when it is not finished (GC_EAGAIN)."""
+    out = np.zeros((n_chan, max_dumps, 4, 2), np.int32)
+    dump_n = np.zeros((n_chan, max_dumps), np.uint32)
+    n_dumps = np.zeros(n_chan, np.uint32)
+    status = np.zeros(n_chan, np.int32)
+    svc = np.zeros(1, np.float64)
+    rc = _lib.gc_server_result(server, req_id, out.ctypes.data, dump_n.ctypes.data,
+                               n_dumps.ctypes.data, status.ctypes.data, svc.ctypes.data)
+    if rc == GC_EAGAIN:
+        return None
+    _check(rc, "gc_server_result")
+    return out, dump_n, n_dumps, status, float(svc[0])
+
+
+def gc_server_state(server: int, rx_id: int, n_chan: int) -> np.ndarray:
+    st = np.zeros(n_chan, CHAN_STATE)
+    _check(_lib.gc_server_state(server, rx_id, st.ctypes.data), "gc_server_state")
+    return st
+
+
+def gc_server_info(server: int) -> dict:
+    md, ts, fl = C.c_uint32(), C.c_int32(), C.c_int32()
+    hb, ln, lr = C.c_uint64(), C.c_uint64(), C.c_uint64()
+    _check(_lib.gc_server_info(server, C.byref(md), C.byref(ts), C.byref(fl), C.byref(hb),
+                               C.byref(ln), C.byref(lr)), "gc_server_info")
+    return {"max_dumps": md.value, "tap_stride": ts.value, "in_flight": fl.value,
+            "hbm_in_use": hb.value, "launches": ln.value, "launched_requests": lr.value}
+
+
+def gc_server_destroy(server: int) -> None:
+    _check(_lib.gc_server_destroy(server), "gc_server_destroy")
 
 
 def _stream_ptr(stream):

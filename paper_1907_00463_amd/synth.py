@@ -257,3 +257,99 @@ def workload_multicorrelator(seconds: float = 2.0, seed: int = 1004, n_chan: int
                          code_phase0=float(rng.uniform(0.0, 1023.0)), taps_chips=taps)
         chans.append(ch)
     return st, chans, rng
+
+
+def workload_batched(seconds: float = 1.0, seed: int = 1003, n_rx: int = 64):
+    """64 receivers x U{8..14} channels, one satellite per channel; fs uniform
+    over {4.092, 8.184, 16.368} MHz with IF = fs/4; int8 or 2-bit real; the
+    integration of each channel uniform over {1, 4, 20} periods; 1 s each.
+    Receiver r draws from its own generator default_rng([seed, r]): rate,
+    format, channel count, PRNs, Dopplers, code phases, C/N0, periods, then
+    the satellites' carrier phases and navigation bits, then (in
+    synth_batched) its samples.  Returns [(Stream, [Channel], rng_r)]."""
+    rates = np.array([4.092e6, 8.184e6, 16.368e6])
+    out = []
+    for r in range(n_rx):
+        rng = np.random.default_rng([seed, r])
+        fs = float(rng.choice(rates))
+        fmt = int(rng.choice([I8_REAL, I2_REAL]))
+        n = int(round(seconds * fs))
+        n -= n % 4
+        k = int(rng.integers(8, 15))
+        prns = rng.choice(np.arange(1, 33), size=k, replace=False)
+        dop = rng.uniform(-5000.0, 5000.0, size=k)
+        p0 = rng.uniform(0.0, 1023.0, size=k)
+        cn0 = rng.uniform(35.0, 50.0, size=k)
+        periods = rng.choice(np.array([1, 4, 20]), size=k)
+        sats = [make_sat(rng, fs, n, int(prns[i]), float(dop[i]), float(p0[i]), float(cn0[i]))
+                for i in range(k)]
+        st = Stream(fs, fs / 4, fmt, n, sats, seed)
+        out.append((st, [channel_for(sats[i], fs / 4, int_periods=int(periods[i]))
+                         for i in range(k)], rng))
+    return out
+
+
+def synth_batched(workload, threads: Optional[int] = None):
+    """Sample buffers of every receiver of workload_batched, receivers in
+    parallel (each from its own generator, so the result does not depend on
+    the thread count)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    nthr = threads or min(16, (os.cpu_count() or 1))
+    with ThreadPoolExecutor(max_workers=nthr) as pool:
+        return list(pool.map(lambda w: synth_samples(w[0], w[2], threads=1), workload))
+
+
+def workload_serving(seed: int = 1005, n_rx: int = 500, stream_ms: float = 24.0):
+    """500 receivers x U{4..14} channels, drawn as in workload_batched (rate
+    over {4.092, 8.184, 16.368} MHz with IF = fs/4, int8 or 2-bit real,
+    integrations over {1, 4, 20} periods) from default_rng([seed, r]); each
+    receiver has stream_ms of samples that its requests slice (see
+    serving_schedule).  Returns [(Stream, [Channel], rng_r)]."""
+    rates = np.array([4.092e6, 8.184e6, 16.368e6])
+    out = []
+    for r in range(n_rx):
+        rng = np.random.default_rng([seed, r])
+        fs = float(rng.choice(rates))
+        fmt = int(rng.choice([I8_REAL, I2_REAL]))
+        n = int(round(stream_ms * 1e-3 * fs))
+        n -= n % 4
+        k = int(rng.integers(4, 15))
+        prns = rng.choice(np.arange(1, 33), size=k, replace=False)
+        dop = rng.uniform(-5000.0, 5000.0, size=k)
+        p0 = rng.uniform(0.0, 1023.0, size=k)
+        cn0 = rng.uniform(35.0, 50.0, size=k)
+        periods = rng.choice(np.array([1, 4, 20]), size=k)
+        sats = [make_sat(rng, fs, n, int(prns[i]), float(dop[i]), float(p0[i]), float(cn0[i]))
+                for i in range(k)]
+        st = Stream(fs, fs / 4, fmt, n, sats, seed)
+        out.append((st, [channel_for(sats[i], fs / 4, int_periods=int(periods[i]))
+                         for i in range(k)], rng))
+    return out
+
+
+def serving_schedule(workload, rate_hz: float = 2000.0, seconds: float = 10.0,
+                     seed: int = 1006):
+    """Poisson arrivals at rate_hz over `seconds`: exponential gaps, each
+    request for a receiver drawn uniformly, lasting U{1..20} ms of its
+    samples.  A receiver's requests take consecutive slices of its stream
+    (offsets are multiples of 4 samples, wrapping to the start when the next
+    slice would not fit), so its channels see a continuing signal up to the
+    wrap.  Returns arrays (t_arrival s, receiver, offset, n_samples)."""
+    rng = np.random.default_rng(seed)
+    n_req = int(rng.poisson(rate_hz * seconds))
+    t = np.sort(rng.uniform(0.0, seconds, size=n_req))
+    rx = rng.integers(0, len(workload), size=n_req)
+    dur = rng.integers(1, 21, size=n_req)
+    off = np.zeros(n_req, np.int64)
+    ns = np.zeros(n_req, np.int64)
+    cur = np.zeros(len(workload), np.int64)
+    for i in range(n_req):
+        st = workload[int(rx[i])][0]
+        n = int(round(int(dur[i]) * 1e-3 * st.fs))
+        n -= n % 4
+        if cur[rx[i]] + n > st.n:
+            cur[rx[i]] = 0
+        off[i], ns[i] = cur[rx[i]], n
+        cur[rx[i]] += n
+    return t, rx, off, ns

@@ -49,16 +49,20 @@ int main(void) {
          offsetof(gc_chan_state, acc));
   printf("%zu %zu %zu\n", offsetof(gc_chan_state, acc_f), offsetof(gc_chan_state, acc_n),
          offsetof(gc_chan_state, carr_step));
+  printf("%zu %zu %zu %zu\n", sizeof(gc_rx_desc), offsetof(gc_rx_desc, n_samples),
+         offsetof(gc_rx_desc, fmt), offsetof(gc_rx_desc, reserved));
   return 0;
 }
 ''')
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)])
     vals = [int(v) for v in subprocess.check_output([str(exe)]).split()]
-    cfg, st = gnsscorr.CHAN_CFG, gnsscorr.CHAN_STATE
+    cfg, st, rx = gnsscorr.CHAN_CFG, gnsscorr.CHAN_STATE, gnsscorr.RX_DESC
     assert vals == [cfg.itemsize, st.itemsize, cfg.fields["tap_q32"][1],
                     st.fields["carr_phase_f"][1], st.fields["acc"][1],
-                    st.fields["acc_f"][1], st.fields["acc_n"][1], st.fields["carr_step"][1]]
+                    st.fields["acc_f"][1], st.fields["acc_n"][1], st.fields["carr_step"][1],
+                    rx.itemsize, rx.fields["n_samples"][1], rx.fields["fmt"][1],
+                    rx.fields["reserved"][1]]
 
 
 def test_host_validation_without_a_device():
@@ -68,6 +72,15 @@ def test_host_validation_without_a_device():
     assert g._lib.gc_destroy(None) == g.GC_EINVAL
     assert g._lib.gc_plan_destroy(None) == g.GC_EINVAL
     assert g._lib.gc_code_table(None, 1, None) == g.GC_EINVAL
+    assert g._lib.gc_batch_create(None, None, 1, None, None, 1, None, None, None, None, None,
+                                  1, None) == g.GC_EINVAL
+    assert g._lib.gc_batch_destroy(None) == g.GC_EINVAL
+    assert g._lib.gc_server_create(None, 1 << 20, 1 << 20, 1, 1, 8, 1, 1, 0,
+                                   None) == g.GC_EINVAL
+    assert g._lib.gc_server_submit(None, 0, None, 0, None) == g.GC_EINVAL
+    assert g._lib.gc_server_poll(None, None, 0, None) == g.GC_EINVAL
+    assert g._lib.gc_server_result(None, 1, None, None, None, None, None) == g.GC_EINVAL
+    assert g._lib.gc_server_destroy(None) == g.GC_EINVAL
     assert g.gc_version() == (1, 0)
     for s in (0, -1, -2, -3, -4, -5, -6, -7):
         assert len(g.gc_strerror(s)) > 0

@@ -1,0 +1,234 @@
+"""GPU parity of the serving loop against the CPU oracle, through the C ABI.
+
+Consecutive requests of several receivers, admitted under an HBM budget and
+batched as they arrive, give every receiver the dumps, sample counts and
+final NCO state of the oracle run over the same blocks in order, bit for
+bit; a request gives the same results alone and in a mix; the plain
+per-channel mode gives the same results; admission refuses what does not
+fit the budget."""
+import time
+
+import numpy as np
+import pytest
+
+from gpu_util import block_bytes, run_oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+EPL = [1 << 31, 0, -(1 << 31)]
+MAX_DUMPS = 40
+
+
+@pytest.fixture(scope="module")
+def g():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1907_00463_amd import gnsscorr
+    return gnsscorr
+
+
+@pytest.fixture(scope="module")
+def ctx(g):
+    c = g.gc_create(0)
+    yield c
+    g.gc_destroy(c)
+
+
+def _receivers(g, seed, n_rx=6, n_req=3):
+    """Receivers (fmt, cfgs, states0) and their request blocks [(buf, n)]."""
+    rng = np.random.default_rng(seed)
+    rates = [4.092e6, 8.184e6, 16.368e6]
+    out = []
+    for r in range(n_rx):
+        fs = rates[r % 3]
+        fmt = (0, 2)[(r // 3) % 2]
+        cfgs, states = [], []
+        for c in range(int(rng.integers(1, 5))):
+            T = int(rng.choice([1, 4, 20]))
+            taps = EPL if (r, c) != (1, 0) else [0, 1 << 30]  # one 2-tap channel
+            cfgs.append(g.make_cfg(int(rng.integers(1, 33)), taps, T))
+            fd = float(rng.uniform(-5000, 5000))
+            states.append(g.gc_nco_init(fs, fs / 4 + fd, float(rng.random()),
+                                        1.023e6 * (1 + fd / 1575.42e6),
+                                        float(rng.uniform(0, 1023 * T)), T))
+        reqs = []
+        for k in range(n_req):
+            # one empty request, otherwise 1 .. 20 ms of samples
+            n = 0 if (r, k) == (2, 1) else int(rng.integers(2_000, int(fs * 0.02)))
+            reqs.append((rng.integers(0, 256, size=block_bytes(fmt, n), dtype=np.uint8), n))
+        out.append((fmt, np.array(cfgs, g.CHAN_CFG), np.array(states, g.CHAN_STATE), reqs))
+    return out
+
+
+def _expect(rxs):
+    """Oracle results per receiver: per request [(dumps, dns)], final states."""
+    res = []
+    for fmt, cfgs, states, reqs in rxs:
+        r, s = run_oracle(fmt, cfgs, states, [b for b, _ in reqs], [n for _, n in reqs])
+        res.append((r, s))
+    return res
+
+
+def _server(g, ctx, rxs, flags=0, n_streams=2, hbm=64 << 20):
+    n_chan = sum(len(c) for _, c, _, _ in rxs)
+    s = g.gc_server_create(ctx, hbm, 64 << 20, n_chan, len(rxs), MAX_DUMPS, n_streams, 64,
+                           flags)
+    ids = [g.gc_server_open_rx(s, fmt, cfgs, states) for fmt, cfgs, states, _ in rxs]
+    assert ids == list(range(len(rxs)))
+    return s
+
+
+def _wait(g, s, req_ids, timeout=60.0):
+    want, t0 = set(req_ids), time.time()
+    while want:
+        for i in g.gc_server_poll(s):
+            want.discard(int(i))
+        assert time.time() - t0 < timeout, "requests did not finish"
+        time.sleep(1e-4)
+
+
+def _submit_all(g, s, rxs, wait_each=False):
+    """Submit request k of every receiver for k = 0, 1, ...; returns ids[r][k]."""
+    ids = [[None] * len(rxs[0][3]) for _ in rxs]
+    for k in range(len(rxs[0][3])):
+        for r, (_, _, _, reqs) in enumerate(rxs):
+            buf, n = reqs[k]
+            rid = g.gc_server_submit(s, r, buf, n)
+            assert rid is not None
+            ids[r][k] = rid
+            if wait_each:
+                _wait(g, s, [rid])
+    return ids
+
+
+def _collect(g, s, rxs, ids):
+    res = []
+    for r, (_, cfgs, _, _) in enumerate(rxs):
+        rr = []
+        for rid in ids[r]:
+            x = g.gc_server_result(s, rid, len(cfgs), MAX_DUMPS)
+            assert x is not None
+            rr.append(x)
+        res.append(rr)
+    return res
+
+
+def _check_oracle(g, s, rxs, got, expect):
+    for r, (_, cfgs, _, _) in enumerate(rxs):
+        orc_res, orc_st = expect[r]
+        for (out, dump_n, n_dumps, status, svc), (dumps, dns) in zip(got[r], orc_res):
+            assert np.all(status == 0), (r, status)
+            assert svc > 0
+            for i, c in enumerate(cfgs):
+                K = int(c["n_taps"])
+                nd = int(n_dumps[i])
+                assert nd == len(dumps[i]), (r, i, nd, len(dumps[i]))
+                assert np.array_equal(out[i, :nd, :K].astype(np.int64), dumps[i]), (r, i)
+                assert np.array_equal(dump_n[i, :nd], dns[i]), (r, i)
+        st = g.gc_server_state(s, r, len(cfgs))
+        for i, c in enumerate(cfgs):
+            K = int(c["n_taps"])
+            o = orc_st[i]
+            assert int(st[i]["code_phase"]) == o.code_phase, (r, i)
+            assert int(st[i]["carr_phase"]) == o.carr_phase, (r, i)
+            assert int(st[i]["acc_n"]) == o.acc_n, (r, i)
+            assert np.array_equal(st[i]["acc"][:K].reshape(-1).astype(np.int64), o.acc), (r, i)
+
+
+def _same(a, b, rxs):
+    for r, (_, cfgs, _, _) in enumerate(rxs):
+        for (o1, d1, n1, s1, _), (o2, d2, n2, s2, _) in zip(a[r], b[r]):
+            assert np.array_equal(n1, n2) and np.array_equal(s1, s2), r
+            for i, c in enumerate(cfgs):
+                K, nd = int(c["n_taps"]), int(n1[i])
+                assert np.array_equal(o1[i, :nd, :K], o2[i, :nd, :K]), (r, i)
+                assert np.array_equal(d1[i, :nd], d2[i, :nd]), (r, i)
+
+
+@pytest.fixture(scope="module")
+def workload(g):
+    rxs = _receivers(g, 1201)
+    return rxs, _expect(rxs)
+
+
+def test_server_bit_exact_batched(g, ctx, workload):
+    rxs, expect = workload
+    s = _server(g, ctx, rxs)
+    try:
+        # hold launches until every request is queued: request k of all six
+        # receivers then runs as one launch
+        g.gc_server_hold(s, True)
+        ids = _submit_all(g, s, rxs)
+        info = g.gc_server_info(s)
+        assert info["in_flight"] == 18 and info["launches"] == 0 and info["hbm_in_use"] > 0
+        g.gc_server_hold(s, False)
+        _wait(g, s, [i for row in ids for i in row])
+        info = g.gc_server_info(s)
+        assert info["launches"] == 3 and info["launched_requests"] == 18, info
+        assert info["in_flight"] == 0 and info["hbm_in_use"] == 0
+        _check_oracle(g, s, rxs, _collect(g, s, rxs, ids), expect)
+    finally:
+        g.gc_server_destroy(s)
+
+
+def test_server_alone_equals_mixed(g, ctx, workload):
+    rxs, expect = workload
+    runs = []
+    for wait_each in (True, False):
+        s = _server(g, ctx, rxs)
+        try:
+            ids = _submit_all(g, s, rxs, wait_each=wait_each)
+            _wait(g, s, [i for row in ids for i in row])
+            info = g.gc_server_info(s)
+            if wait_each:   # every launch carried exactly one request
+                assert info["launches"] == 18 == info["launched_requests"], info
+            runs.append(_collect(g, s, rxs, ids))
+            if wait_each:
+                _check_oracle(g, s, rxs, runs[-1], expect)
+        finally:
+            g.gc_server_destroy(s)
+    _same(runs[0], runs[1], rxs)
+
+
+def test_server_plain_mode(g, ctx, workload):
+    rxs, expect = workload
+    s = _server(g, ctx, rxs, flags=g.GC_SERVER_PLAIN, n_streams=1)
+    try:
+        ids = _submit_all(g, s, rxs)
+        _wait(g, s, [i for row in ids for i in row])
+        _check_oracle(g, s, rxs, _collect(g, s, rxs, ids), expect)
+    finally:
+        g.gc_server_destroy(s)
+
+
+def test_server_admission_budget(g, ctx):
+    rxs = _receivers(g, 1202, n_rx=1, n_req=1)
+    fmt, cfgs, states, _ = rxs[0]
+    s = _server(g, ctx, rxs, hbm=4096)
+    try:
+        rng = np.random.default_rng(5)
+        nb = lambda n: block_bytes(fmt, n)     # noqa: E731
+        n_big = 5000 * (4 if fmt == 2 else 1)  # 5000 bytes: over the whole budget
+        assert g.gc_server_submit(s, 0, rng.integers(0, 256, nb(n_big), np.uint8), n_big) is None
+        g.gc_server_hold(s, True)
+        n = 3000 * (4 if fmt == 2 else 1)      # 3000 bytes: one fits, two do not
+        blocks = [rng.integers(0, 256, nb(n), np.uint8) for _ in range(2)]
+        a = g.gc_server_submit(s, 0, blocks[0], n)
+        assert a is not None
+        assert g.gc_server_submit(s, 0, blocks[1], n) is None
+        assert g.gc_server_info(s)["in_flight"] == 1
+        g.gc_server_hold(s, False)
+        _wait(g, s, [a])
+        b = g.gc_server_submit(s, 0, blocks[1], n)
+        assert b is not None
+        _wait(g, s, [b])
+        got = [[g.gc_server_result(s, a, len(cfgs), MAX_DUMPS),
+                g.gc_server_result(s, b, len(cfgs), MAX_DUMPS)]]
+        rxs2 = [(fmt, cfgs, states, [(blocks[0], n), (blocks[1], n)])]
+        _check_oracle(g, s, rxs2, got, _expect(rxs2))
+        # a collected id is gone; an unknown receiver is refused
+        assert g._lib.gc_server_result(s, a, None, None, None, None, None) == g.GC_EINVAL
+        with pytest.raises(g.GcError):
+            g.gc_server_submit(s, 7, blocks[0], n)
+    finally:
+        g.gc_server_destroy(s)
