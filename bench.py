@@ -41,6 +41,7 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12     # 32-bit lane-ops/s, T
 INT8_MFMA_PEAK_TOPS = 5000.0                 # dense int8 MFMA, T ops/s (2 ops per MAC)
 OPS_PER_SAMPLE_CHANNEL = 6
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
 KERNEL_SETS = {"auto": None, "binned": 2, "direct": 0}
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_pbin_i2_12ch_10s_counters.md")
 
@@ -94,9 +95,9 @@ def build_inputs(workload: str, seconds: float):
     return st, chans, buf, cfgs, states
 
 
-def cpu_baseline(st, buf, cfgs, states, seconds: float = 10.0):
+def cpu_baseline(st, buf, cfgs, states, seconds: float = 10.0, f64: bool = False):
     """The oracle as it stands, host threads over channels, on the first
-    `seconds` of the same stream."""
+    `seconds` of the same stream (its FP64 form for the FP32-carrier runs)."""
     from concurrent.futures import ThreadPoolExecutor
 
     import oracle
@@ -106,16 +107,22 @@ def cpu_baseline(st, buf, cfgs, states, seconds: float = 10.0):
     n -= n % 4
     n = min(n, st.n)
     sub = buf[: int(np.ceil(n * bytes_per))]
-    threads = min(len(cfgs), os.cpu_count() or 1)
+    threads = min(len(cfgs), host_threads())
 
     def one(i):
         s = states[i]
         os_ = oracle.OracleState(int(s["carr_phase"]), int(s["carr_step"]), int(s["code_phase"]),
-                                 int(s["code_step"]), int(cfgs[i]["n_taps"]))
+                                 int(s["code_step"]), int(cfgs[i]["n_taps"]),
+                                 carr_phase_f=float(s["carr_phase_f"]),
+                                 carr_freq_f=float(s["carr_freq_f"]))
         K = int(cfgs[i]["n_taps"])
-        return oracle.correlate_lut(st.fmt, sub, n, int(cfgs[i]["prn"]), cfgs[i]["tap_q32"][:K],
-                                    int(cfgs[i]["int_periods"]), os_)
+        f = oracle.correlate_f64 if f64 else oracle.correlate_lut
+        return f(st.fmt, sub, n, int(cfgs[i]["prn"]), cfgs[i]["tap_q32"][:K],
+                 int(cfgs[i]["int_periods"]), os_)
 
+    t0 = time.perf_counter()
+    one(0)
+    dt1 = time.perf_counter() - t0
     t0 = time.perf_counter()
     with ThreadPoolExecutor(max_workers=threads) as ex:
         list(ex.map(one, range(len(cfgs))))
@@ -123,10 +130,32 @@ def cpu_baseline(st, buf, cfgs, states, seconds: float = 10.0):
     taps = int(cfgs["n_taps"].sum())
     return {"value": n * taps / dt / 1e9, "unit": "G sample·taps/s", "cores": threads,
             "kind": "oracle",
+            "single_thread_value": n * int(cfgs[0]["n_taps"]) / dt1 / 1e9,
+            "host": host_cpu(),
             "sample": "first %.3f s (%d samples) of the same stream, all %d channels, "
-                      "%d threads over channels; %.2f s wall; real-time channels %.1f"
+                      "%d threads over channels; %.2f s wall; real-time channels %.1f "
+                      "(single thread: channel 0 alone, %.2f s)"
                       % (n / st.fs, n, len(cfgs), threads, dt,
-                         realtime_channels(len(cfgs), n / st.fs, dt))}
+                         realtime_channels(len(cfgs), n / st.fs, dt), dt1)}
+
+
+def host_threads() -> int:
+    """Host threads for the oracle: the cores this process may use, at most 16."""
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def host_cpu() -> str:
+    """CPU model and the number of cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return "%s, %d usable cores" % (model, len(os.sched_getaffinity(0)))
 
 
 def kernel_source_tag(name: str = "gc_pbin.hip") -> str:
@@ -316,7 +345,7 @@ def main_batched(args, wl, seconds, cpu_seconds):
 
         import oracle
         sel = [i for i in range(len(cfgs)) if chan_rx[i] < 8]
-        threads = min(len(sel), os.cpu_count() or 1)
+        threads = min(len(sel), host_threads())
 
         def one(i):
             r = int(chan_rx[i])
@@ -356,9 +385,15 @@ def serve_schedule(g, server, sched, payload, n_chan, deadline_s=1e-3):
     status = np.zeros(max(n_chan), np.int32)
     ids = np.zeros(4096, np.uint64)
     rid, nd = C.c_uint64(), C.c_int32()
+    svc_s = np.full(n_req, np.nan)
     pending = {}
     refused = bad = i = done = 0
     t_done_last = 0.0
+    # the client's own pauses would count as latency: no garbage collection
+    # while the schedule runs
+    import gc
+    gc.collect()
+    gc.disable()
     t0 = time.perf_counter() + 0.02
     while done < n_req:
         now = time.perf_counter() - t0
@@ -384,16 +419,23 @@ def serve_schedule(g, server, sched, payload, n_chan, deadline_s=1e-3):
                                           status.ctypes.data, svc.ctypes.data)
                 if rc != g.GC_OK:
                     raise g.GcError(rc, "gc_server_result")
+                svc_s[j] = svc[0]
                 bad += int(np.any(status[: n_chan[int(rx[j])]] != 0))
             done += nd.value
             t_done_last = t
+    gc.enable()
     ms = lat * 1e3
-    return {"requests": n_req, "p50_ms": round(float(np.percentile(ms, 50)), 4),
+    worst = np.argsort(ms)[-5:][::-1]
+    return {"requests": n_req,
+            "worst": [[round(float(t_arr[j]), 4), round(float(ms[j]), 3),
+                       round(float(svc_s[j]) * 1e3, 3), int(rx[j]), int(ns[j])] for j in worst], "p50_ms": round(float(np.percentile(ms, 50)), 4),
             "p99_ms": round(float(np.percentile(ms, 99)), 4),
             "p999_ms": round(float(np.percentile(ms, 99.9)), 4),
             "max_ms": round(float(ms.max()), 4),
             "deadline_ms": deadline_s * 1e3,
             "deadline_miss_frac": round(float(np.mean(lat > deadline_s)), 5),
+            "server_p50_ms": round(float(np.percentile(svc_s, 50)) * 1e3, 4),
+            "server_p99_ms": round(float(np.percentile(svc_s, 99)) * 1e3, 4),
             "admission_retries": refused, "channel_errors": bad,
             "makespan_s": round(t_done_last, 4)}
 
@@ -416,11 +458,16 @@ def main_serving(args, wl, seconds):
     sched = synth.serving_schedule(work, seconds=seconds)
     t_arr, rx, off, ns = sched
     per = {0: 1, 2: 4}     # samples per byte
-    payload = []
-    for r, o, n in zip(rx, off, ns):
-        st = work[int(r)][0]
-        b = bufs[int(r)]
-        payload.append((b.ctypes.data + int(o) // per[st.fmt], int(n)))
+
+    def payload_of(sc):
+        return [(bufs[int(r)].ctypes.data + int(o) // per[work[int(r)][0].fmt], int(n))
+                for r, o, n in zip(sc[1], sc[2], sc[3])]
+
+    payload = payload_of(sched)
+    # the same receivers under 10x the load for 1 s (continuous batching
+    # against one launch per channel when requests queue up)
+    stress = synth.serving_schedule(work, rate_hz=10 * 2000.0, seconds=1.0, seed=1007)
+    stress_payload = payload_of(stress)
     cfgs, states = [], []
     for st, chans, _ in work:
         cfgs.append(np.array([g.make_cfg(ch.prn, synth.taps_to_q32(ch.taps_chips),
@@ -458,6 +505,16 @@ def main_serving(args, wl, seconds):
         stats["launches"] = info["launches"]
         stats["requests_per_launch"] = round(info["launched_requests"] / max(1, info["launches"]),
                                              3)
+        print("bench: %s at 10x load, %d requests over 1 s" % (mode, len(stress[0])),
+              file=sys.stderr, flush=True)
+        st10 = serve_schedule(g, srv, stress, stress_payload, n_chan)
+        info2 = g.gc_server_info(srv)
+        st10["launches"] = info2["launches"] - info["launches"]
+        st10["requests_per_launch"] = round(
+            (info2["launched_requests"] - info["launched_requests"]) / max(1, st10["launches"]), 3)
+        sc10 = int(sum(int(n) * n_chan[int(r)] for r, n in zip(stress[1], stress[3])))
+        st10["value"] = round(3 * sc10 / st10["makespan_s"] / 1e9, 3)
+        stats["at_10x_load"] = st10
         g.gc_server_destroy(srv)
         print("bench: %s p50 %.3f ms p99 %.3f ms" % (mode, stats["p50_ms"], stats["p99_ms"]),
               file=sys.stderr, flush=True)
@@ -494,7 +551,7 @@ def main_serving(args, wl, seconds):
 
         import oracle
         k_req = min(2000, len(t_arr))
-        threads = min(16, os.cpu_count() or 1)
+        threads = host_threads()
 
         def one(k):
             r, p = int(rx[k]), per[work[int(rx[k])][0].fmt]
@@ -530,6 +587,8 @@ def main():
     ap.add_argument("--seconds", type=float, default=None, help="data per step")
     ap.add_argument("--kernels", choices=list(KERNEL_SETS), default="auto",
                     help="kernel families the plan may use (auto: all)")
+    ap.add_argument("--carrier", choices=["lut", "f32"], default="lut",
+                    help="integer NCO + table (exact) or the FP32 sin/cos variant")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-channel launch baseline")
     ap.add_argument("--cpu-seconds", type=float, default=None)
@@ -562,7 +621,8 @@ def main():
     st, chans, buf, cfgs, states = build_inputs(args.workload, seconds)
     n = st.n
     ctx = g.gc_create(0)
-    plan = g.Plan(ctx, st.fmt, g.GC_CARRIER_LUT, cfgs)
+    f32 = args.carrier == "f32"
+    plan = g.Plan(ctx, st.fmt, g.GC_CARRIER_F32 if f32 else g.GC_CARRIER_LUT, cfgs)
     if KERNEL_SETS[args.kernels] is not None:
         g.gc_plan_set_kernels(plan.handle, KERNEL_SETS[args.kernels])
     samples = torch.from_numpy(buf).to(dev)
@@ -637,7 +697,18 @@ def main():
                      "kernel_ms": round(k_s * 1e3, 4),
                      "ops_per_sample_channel": wl["ops"]},
     }
-    if args.workload == "multicorrelator" and args.kernels == "auto":
+    if f32:
+        # the direct form with an FP32 carrier: per sample one sin/cos pair,
+        # per sample and tap two FP32 multiply-adds (I and Q) = 4 FLOPs
+        tflops = 4 * sample_taps / k_s / 1e12
+        res["dtype"] = "f32"
+        res["config"]["carrier"] = "f32"
+        res["roofline"] = {"bound": "alu", "achieved": round(tflops, 3),
+                           "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": round(tflops / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                           "kernel_ms": round(k_s * 1e3, 4),
+                           "note": "4 FLOPs per sample·tap (two FP32 multiply-adds)"}
+    elif args.workload == "multicorrelator" and args.kernels == "auto":
         # stage 2: 128 rows (I/Q x lo/hi x 32 cells) x 16 shifts per chip
         chips = n * float(np.mean(states["code_step"].astype(np.float64))) / 2 ** 32
         macs = 128 * 16 * chips * len(cfgs)
@@ -648,7 +719,7 @@ def main():
                                   "macs": round(macs),
                                   "note": "int8 MFMA work over the whole kernel time "
                                           "(stage 1 dominates)"}
-    if not args.no_plain:
+    if not args.no_plain and not f32:
         print("bench: plain per-channel launches", file=sys.stderr, flush=True)
         psteps = 1 if args.workload == "multicorrelator" else max(1, min(args.steps, 5))
         dt = plain_baseline(torch, g, ctx, st, cfgs, states, samples, n, max_dumps, stream,
@@ -659,7 +730,7 @@ def main():
                         "speedup": round(dt / (wall / args.steps), 2)}
     if not args.no_cpu_baseline:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
-        res["cpu_baseline"] = cpu_baseline(st, buf, cfgs, states, cpu_seconds)
+        res["cpu_baseline"] = cpu_baseline(st, buf, cfgs, states, cpu_seconds, f64=f32)
     plan.close()
     g.gc_destroy(ctx)
     print(json.dumps(res), flush=True)

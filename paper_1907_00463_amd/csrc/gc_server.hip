@@ -408,6 +408,12 @@ gc_status gc_server_create(gc_ctx* ctx, uint64_t hbm_budget_bytes, uint64_t host
         if (e == hipSuccess)
             e = hipHostMalloc(&sl.h_list, sizeof(int32_t) * 2 * C, hipHostMallocDefault);
     }
+    // touch every stream once with a device operation (clearing the status
+    // words), so that no request pays for the runtime's first use of a queue
+    for (SrvSlot& sl : s->slots)
+        if (e == hipSuccess) e = hipMemsetAsync(s->d_status, 0, 4 * C, sl.s);
+    if (e == hipSuccess) e = hipMemsetAsync(s->d_n_dumps, 0, 4 * C, s->up);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         s->stop = true;
         gc_server_destroy(s);

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import TWO32, assert_exact, block_bytes, run_library, run_oracle
+from gpu_util import TWO32, assert_exact, block_bytes, c10_check, run_library, run_oracle
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -70,6 +70,35 @@ def test_mfma_path_equals_direct_path(g, ctx):
     assert np.array_equal(a[0][0], b[0][0])
     assert np.array_equal(a[0][1], b[0][1])
     assert np.array_equal(sa.view(np.uint8), sb.view(np.uint8))
+
+
+def test_fp32_carrier_128_taps_within_tolerance(g, ctx):
+    # the FP32-carrier variant of the multi-correlator (complex int8, 128
+    # taps at 1/32 chip) against the FP64 oracle, every tap to the |P| bound
+    rng = np.random.default_rng(720)
+    cfgs, states = _channels(g, rng, 20.46e6, 3, TAPS_128, periods=(1, 4, 1))
+    states["code_phase"] %= np.uint64(1023 * TWO32)
+    lens = [44_000, 20_460]
+    blocks = _blocks(rng, 1, lens)
+    lib, lst = run_library(torch, ctx, 1, g.GC_CARRIER_F32, cfgs, states, blocks, lens)
+    orc, ost = run_oracle(1, cfgs, states, blocks, lens, f64=True)
+    worst = 0.0
+    for (out, dump_n, n_dumps, status), (dumps, dns) in zip(lib, orc):
+        assert np.all(status == 0)
+        for i in range(len(cfgs)):
+            nd = int(n_dumps[i])
+            assert nd == len(dumps[i])
+            assert np.array_equal(dump_n[i, :nd], dns[i])
+            if nd == 0:
+                continue
+            sigma = np.sqrt(dns[i].astype(np.float64) * (2 * 128 ** 2 / 3) / 2)[:, None]
+            ok, w = c10_check(out[i, :nd, :128].astype(np.float64), dumps[i], sigma)
+            assert ok.all(), w
+            worst = max(worst, w)
+    for i in range(len(cfgs)):
+        assert int(lst[i]["code_phase"]) == ost[i].code_phase
+        assert abs(float(lst[i]["carr_phase_f"]) - ost[i].carr_phase_f) < 1e-9
+    print("worst relative |P| error", worst)
 
 
 def test_epl_columns_equal_the_three_tap_correlator(g, ctx):
