@@ -288,14 +288,22 @@ def main_batched(args, wl, seconds, cpu_seconds):
                    "channels": len(cfgs), "samples": int(sum(ns)),
                    "sample_channels": int(sample_ch), "kernels": "batch",
                    "shape": info["shape"], "grid": info["grid"], "work_items": info["n_items"],
+                   "periodic_chunk": info["periodic_chunk"],
+                   "periodic_items": info["periodic_items"],
                    "tuned_ms": round(info["tuned_ms"], 4),
                    "realtime_channels": round(data_s / wall, 1)},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                      "peak": round(VALU_PEAK_TOPS, 2), "unit": "T lane-ops/s",
                      "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
                      "kernel_ms": round(graph_ms, 4), "ops_per_sample_channel": wl["ops"],
-                     "note": "kernel_ms is the whole graph (set-up, rows, batch kernel)"},
+                     "note": "kernel_ms is the whole graph (set-up, rows, periodic and "
+                             "chip-by-chip batch kernels)"},
     }
+    # the same batch with the periodic kernel off (every channel chip by chip)
+    batch.configure(info["shape"], info["grid"], -1)
+    dt = time_steps(torch, step, max(1, min(args.steps, 5)), 1)
+    res["chip_by_chip_only"] = {"value": round(sample_taps / dt / 1e9, 3),
+                                "ms_per_step": round(dt * 1e3, 4)}
     # one plan per receiver (all kernel families), launched one after another
     plans = []
     for r, (st, _, _) in enumerate(work):

@@ -237,9 +237,12 @@ gc_status gc_plan_kernel_ms(gc_plan* plan, int32_t slot, float* ms);
  * A batch binds the sample blocks of n_rx receivers (each with its own
  * format and length) and the channels that track them (Sec. 3.5: channels
  * are independent given their receiver's samples), and correlates all of
- * them with one launch of the chip-by-chip E/P/L kernel whose blocks walk
- * every (receiver, tile) work item; the per-call set-up and that launch are
- * captured once into a HIP graph and replayed by gc_batch_launch.  Results
+ * them with two persistent launches: the periodic-bin E/P/L kernel over
+ * (receiver, channel group, tile chunk) work items for channels whose half
+ * chips span a fixed 2, 4, 8 or 10 samples, then the chip-by-chip kernel over
+ * (receiver, tile) work items for the others; the per-call set-up and both
+ * launches are captured once into a HIP graph and replayed by
+ * gc_batch_launch.  Results
  * are those of gc_correlate on one plan per receiver, bit for bit.
  * ------------------------------------------------------------------------ */
 typedef struct gc_batch gc_batch;
@@ -272,14 +275,19 @@ gc_status gc_batch_create(gc_ctx* ctx, const gc_rx_desc* rx, int32_t n_rx,
                           uint32_t* n_dumps, int32_t* status, uint32_t max_dumps,
                           gc_batch** out_batch);
 
-/* Choose the block shape (0 .. n_shapes-1, see gc_batch_info) and the number
- * of persistent blocks (0: one per compute unit).  Drops the captured graph.
+/* Choose the chip-by-chip kernel's block shape (0 .. n_shapes-1, see
+ * gc_batch_info) and number of persistent blocks (0: one per compute unit),
+ * and the periodic kernel's work-item size in sample tiles (0: the default
+ * of 4, -1: periodic kernel off, every channel on the chip-by-chip kernel;
+ * values below 2 are raised to 2).  Drops the captured graph.
  * Errors: GC_EINVAL, GC_EDEVICE. */
-gc_status gc_batch_configure(gc_batch* b, int32_t shape, int32_t grid);
+gc_status gc_batch_configure(gc_batch* b, int32_t shape, int32_t grid, int32_t periodic_chunk);
 
-/* Autotune: time every shape with 1x and 2x one block per compute unit,
- * `reps` launches each, restoring the bound channel states before every
- * launch (the states are left as they were), and keep the fastest.
+/* Autotune: time every shape of the chip-by-chip kernel with 1x and 2x one
+ * block per compute unit, then (unless the periodic kernel is off) periodic
+ * work items of 2, 4 and 8 tiles, `reps` launches each, restoring the bound
+ * channel states before every launch (the states are left as they were),
+ * and keep the fastest.
  * Synchronous.  Errors: GC_EINVAL (reps outside 1..100), GC_ENOMEM,
  * GC_EDEVICE. */
 gc_status gc_batch_tune(gc_batch* b, int32_t reps);
@@ -289,11 +297,13 @@ gc_status gc_batch_tune(gc_batch* b, int32_t reps);
  * when needed.  Errors: GC_EDEVICE. */
 gc_status gc_batch_launch(gc_batch* b, void* stream);
 
-/* Query: shape, grid, work items of the current configuration, the number of
- * shapes, and the best time per launch measured by gc_batch_tune (ms, 0 when
- * not tuned).  Any output pointer may be NULL. */
+/* Query: shape, grid and work items of the chip-by-chip kernel, the number
+ * of shapes, the best time per launch measured by gc_batch_tune (ms, 0 when
+ * not tuned), and the periodic kernel's tiles per work item (-1: off) and
+ * work items.  Any output pointer may be NULL. */
 gc_status gc_batch_info(const gc_batch* b, int32_t* shape, int32_t* grid, int32_t* n_items,
-                        int32_t* n_shapes, float* tuned_ms);
+                        int32_t* n_shapes, float* tuned_ms, int32_t* periodic_chunk,
+                        int32_t* periodic_items);
 
 /* Release a batch (waits for the device). */
 gc_status gc_batch_destroy(gc_batch* b);

@@ -12,13 +12,17 @@ constexpr int kTabLut = 64;   // 256 words: (cos low 16 | sin high 16), int16 ea
 constexpr int kTabExpand = 320;  // 512 words: packed 2-bit byte -> its 4 samples as int16 (2 words)
 constexpr int kTabSign = 832;    // 32 PRNs x kSignLen words: chip i -> (s, s) int16, s = +-1
 
-// Periodic form (half chips of exactly 8 or 10 samples): tile length, and
-// the most 64-bin steps one lane makes in a tile (at most tile/8 + 2 bins).
+// Periodic form (half chips of exactly L = 2, 4, 8 or 10 samples): tile
+// length, the most 64-bin steps one lane makes in a tile (at most tile/L + 2
+// bins), and the most steps whose code signs are fetched ahead of use.
 constexpr int kPbinTileSamples = 23552;
-constexpr int kPbinMaxSteps = (kPbinTileSamples / 8 + 2 + 63) / 64;
+constexpr int kPbinMinBinLen = 2;
+constexpr int kPbinMaxSteps = (kPbinTileSamples / kPbinMinBinLen + 2 + 63) / 64;
+constexpr int kPbinMaxAhead = 8;
 // chip index 0..1022 followed by a wrapped copy long enough for a run of
-// periodic steps (32 chips per step, read one step ahead) from any chip
-constexpr int kSignLen = 1023 + 32 * (kPbinMaxSteps + 2);
+// periodic steps (32 chips per step, read up to kPbinMaxAhead steps ahead)
+// from any chip
+constexpr int kSignLen = 1023 + 32 * (kPbinMaxSteps + kPbinMaxAhead + 1);
 // 32 PRNs x 2 x kCodePairWords words: word i holds the int8 pair (C, 64*C)
 // of chip i mod 1023 in its low half-word, then the same pairs in the upper
 // half-words (multi-tap MFMA operands).
@@ -84,12 +88,13 @@ __device__ __forceinline__ bool binned_ok(int fmt, uint64_t dp) {
     return (q + 1) * maxw <= 32767ull;
 }
 
-// Periodic form: half chips of exactly L samples (L = 8 or 10), with at most
-// one one-sample slip of the bin grid per tile of kPbinTileSamples samples.
+// Periodic form: half chips of exactly L samples (L = 2, 4, 8 or 10), with
+// at most one one-sample slip of the bin grid per tile of kPbinTileSamples
+// samples.
 __device__ __forceinline__ int periodic_bin_len(int fmt, uint64_t dp) {
     if (dp == 0 || dp >= (1ull << 31)) return 0;
     const uint64_t L = ((1ull << 31) + dp / 2) / dp;  // nearest integer to 2^31 / dp
-    if (L != 8 && L != 10) return 0;
+    if (L != 2 && L != 4 && L != 8 && L != 10) return 0;
     const uint64_t maxw = fmt == GC_I8_REAL ? 128ull * GC_LUT_AMP : 3ull * GC_LUT_AMP;
     if (L * maxw > 32767ull) return 0;
     const int64_t D = (int64_t)(L * dp) - (int64_t)(1ull << 31);

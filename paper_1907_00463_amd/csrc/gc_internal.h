@@ -88,6 +88,17 @@ struct DevRx {
     uint32_t tile_begin;   // first work item of this receiver
 };
 
+// A work item of the batched periodic kernel: tiles [tile_begin, tile_end)
+// of receiver rx for its channels [chan_begin, chan_begin + n_chan), at most
+// 16 of them.
+struct PbinItem {
+    int32_t rx;
+    int32_t chan_begin;
+    int32_t n_chan;
+    uint32_t tile_begin;
+    uint32_t tile_end;
+};
+
 constexpr int32_t kPathDirect = 0;
 constexpr int32_t kPathBinned = 1;
 constexpr int32_t kPathPeriodic = 2;
@@ -115,16 +126,26 @@ hipError_t launch_setup(const DevChan* chans, DevMeta* meta, gc_chan_state* stat
 // batched chip-by-chip kernel (shape 0 .. epl_batch_shapes()-1)
 int epl_batch_shapes();
 uint32_t epl_batch_tile(int shape);
+// (n_items_dev: when not null, a device word holding the number of items
+// of `order` to run, at most n_items)
 hipError_t launch_epl_batch(int shape, int grid, const DevRx* rx, int n_rx,
-                            const uint32_t* order, uint32_t n_items, const DevChan* chans,
-                            const DevMeta* meta, gc_chan_state* state, int32_t* out,
-                            int tap_stride, uint32_t max_dumps, const uint32_t* tables,
-                            hipStream_t s);
+                            const uint32_t* order, uint32_t n_items, const uint32_t* n_items_dev,
+                            const DevChan* chans, const DevMeta* meta, gc_chan_state* state,
+                            int32_t* out, int tap_stride, uint32_t max_dumps,
+                            const uint32_t* tables, hipStream_t s);
+// The items of k_epl_batch with work (receivers with a channel that is not
+// refused and not periodic) into order[0 .. *count), one block.
+hipError_t launch_epl_select(const DevRx* rx, int n_rx, uint32_t n_items, const DevMeta* meta,
+                             uint32_t* order, uint32_t* count, hipStream_t s);
 hipError_t launch_pbin(const uint8_t* samples, uint64_t n_samples, int fmt, const DevChan* chans,
                        const DevMeta* meta, gc_chan_state* state, int n_chan, int32_t* out,
                        int tap_stride, uint32_t max_dumps, const uint32_t* d_tables, int grid,
                        hipStream_t s);
 int pbin_tile_samples();
+hipError_t launch_pbin_batch(int grid, const DevRx* rx, const PbinItem* items, uint32_t n_items,
+                             const DevChan* chans, const DevMeta* meta, gc_chan_state* state,
+                             int32_t* out, int tap_stride, uint32_t max_dumps,
+                             const uint32_t* tables, hipStream_t s);
 hipError_t launch_mtap(const uint8_t* samples, uint64_t n_samples, int fmt, const DevChan* chans,
                        const DevMeta* meta, gc_chan_state* state, int n_chan, int32_t* out,
                        int tap_stride, uint32_t max_dumps, const uint32_t* d_tables, int grid,

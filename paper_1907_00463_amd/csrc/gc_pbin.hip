@@ -2,8 +2,9 @@
 // bins are periodic in the sample stream (integer carrier path, real int8
 // and 2-bit samples).
 //
-// When fs is close to an integer multiple L of twice the code rate (L = 8 at
-// 16.368 MHz, 10 at 20.46 MHz), every half chip of code phase covers exactly
+// When fs is close to an integer multiple L of twice the code rate (L = 2 at
+// 4.092 MHz, 4 at 8.184, 8 at 16.368, 10 at 20.46), every half chip of code
+// phase covers exactly
 // L samples, give or take one sample every |dp / (L*dp - 2^31)| bins (the
 // code Doppler "slip").  Bin k of a run then starts at sample s_0 + k*L, so
 // consecutive lanes can take consecutive bins with fixed per-lane offsets:
@@ -22,8 +23,11 @@
 //     early or its late sign, fixed for a lane over a run;
 //   * with L = 8, bins start 4 dwords apart, so the lanes of each 8-lane
 //     group read the dwords of their bin in a rotated order and one read
-//     instruction touches 64 distinct LDS banks (L = 10: 5 dwords apart,
-//     distinct banks already);
+//     instruction touches 64 distinct LDS banks; with L = 4 (2 dwords apart)
+//     lanes 16-47 read their second dword first; with L = 2 or 10 (1 or 5
+//     dwords apart) the banks are distinct already;
+//   * short bins take more steps per loop iteration (8 at L = 2, 4 at L = 4,
+//     2 otherwise), their code signs fetched one iteration ahead;
 //   * the step at which a dump closes is found per wave in advance; only that
 //     step (and the ragged last step of a run) carries per-lane checks;
 //   * a tile in which the bin grid slips by one sample is split into two
@@ -48,10 +52,20 @@ constexpr int kXB = kXA + kXBytes;             // copy B: B[i] = x[t0 + i + 1]
 constexpr int kLdsBytes = kXB + kXBytes;
 constexpr int kMaxWaves = 16;                  // one channel per wave
 constexpr uint32_t kPermSel = 0x0C0C0700u;     // byte1 = phase[31:24], byte0 = lane*4
-static_assert(kPbinMaxSteps * 3 * GC_LUT_AMP * 8 <= 32767, "2-bit int16 sums, L = 8");
-static_assert((kTile / 10 + 2 + 63) / 64 * 3 * GC_LUT_AMP * 10 <= 32767, "2-bit int16 sums, L = 10");
-static_assert(kCodeLen - 1 + 32 * (kPbinMaxSteps + 1) + 2 <= kSignLen, "sign table padding");
+// most 64-bin steps of one lane in a tile, and steps per loop iteration
+constexpr int max_steps(int L) { return (kTile / L + 2 + 63) / 64; }
+constexpr int unroll(int L) { return L <= 2 ? 8 : (L <= 4 ? 4 : 2); }
+static_assert(max_steps(2) * 3 * GC_LUT_AMP * 2 <= 32767, "2-bit int16 sums, L = 2");
+static_assert(max_steps(4) * 3 * GC_LUT_AMP * 4 <= 32767, "2-bit int16 sums, L = 4");
+static_assert(max_steps(8) * 3 * GC_LUT_AMP * 8 <= 32767, "2-bit int16 sums, L = 8");
+static_assert(max_steps(10) * 3 * GC_LUT_AMP * 10 <= 32767, "2-bit int16 sums, L = 10");
+static_assert(max_steps(kPbinMinBinLen) <= kPbinMaxSteps && unroll(2) <= kPbinMaxAhead,
+              "sign table sizes");
+// sign words read: start chip <= 1022, then up to 32*(steps + ahead - 1) + 1 more
+static_assert(kCodeLen - 1 + 32 * (kPbinMaxSteps + kPbinMaxAhead - 1) + 2 <= kSignLen,
+              "sign table padding");
 static_assert(kLdsBytes + 4 * (kMaxWaves + 1) <= 160 * 1024, "LDS per block");
+static_assert((kTile / kPbinMinBinLen + 2) * kMaxWaves < (1 << 30), "32-bit bin shares");
 
 typedef short short2_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ short2_t as_s2(uint32_t v) { return __builtin_bit_cast(short2_t, v); }
@@ -78,7 +92,7 @@ struct Dest {
 // its prompt sign equals its early sign (first half) or its late sign
 // (second half): a run accumulates only E and L, and fold() adds the one of
 // them that matches the lane's half to P.  For 2-bit input the run sums are
-// packed int16 (at most kPbinMaxSteps bins of |sum| <= 3*24*L per lane).
+// packed int16 (at most max_steps(L) bins of |sum| <= 3*24*L per lane).
 struct Slot {
     int v[6];              // E I, E Q, P I, P Q, L I, L Q
     short2_t e16, l16;     // run sums, 2-bit input
@@ -167,15 +181,22 @@ __device__ __forceinline__ void periodic_run(Slot& S, const uint8_t* lds, uint32
                                              const Dest& d) {
     if (ke <= kb) return;
     constexpr int B = L / 2;               // dwords per bin
-    constexpr bool kRot = (B % 2) == 0;    // bin starts share bank classes (B = 4)
-    static_assert(!kRot || B == 4, "rotation is laid out for 4-dword bins");
-    const uint32_t c8 = lane >> 3;
-    const uint32_t g = kRot ? ((c8 ^ (c8 >> 2)) & 3u) : 0u;
+    constexpr int U = unroll(L);           // steps per loop iteration
+    static_assert(L % 2 == 0 && (B % 2 == 1 || B == 2 || B == 4), "bank layout");
+    // rotation of the dword order so that one read instruction of the wave
+    // hits distinct banks (bins 2 or 4 dwords apart share bank classes)
+    uint32_t g = 0;
+    if constexpr (B == 4) {
+        const uint32_t c8 = lane >> 3;
+        g = (c8 ^ (c8 >> 2)) & 3u;
+    } else if constexpr (B == 2) {
+        g = ((lane >> 4) ^ (lane >> 5)) & 1u;
+    }
     uint32_t roff[B];
     uint32_t poff[L];
 #pragma unroll
     for (int j = 0; j < B; ++j) {
-        const uint32_t jr = kRot ? ((j + g) & 3u) : (uint32_t)j;
+        const uint32_t jr = (B == 4 || B == 2) ? ((j + g) & (uint32_t)(B - 1)) : (uint32_t)j;
         roff[j] = 4u * jr;
         poff[2 * j] = 2u * jr * m.dphi;
         poff[2 * j + 1] = (2u * jr + 1u) * m.dphi;
@@ -194,9 +215,10 @@ __device__ __forceinline__ void periodic_run(Slot& S, const uint8_t* lds, uint32
     // table repeats the code so that the offset only grows within a run
     uint32_t soff = 4u * (((hk0 >> 1) + par + kCodeLen - 1) % kCodeLen);
     const uint8_t* sgb = reinterpret_cast<const uint8_t*>(sgn_prn);
-    // signs of steps j and j + 1 (fetched two steps ahead of their use)
-    uint2 sg0 = *reinterpret_cast<const uint2*>(sgb + soff);
-    uint2 sg1 = *reinterpret_cast<const uint2*>(sgb + soff + 128u);
+    // signs of steps j .. j + U - 1 (fetched one iteration ahead of their use)
+    uint2 sg[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) sg[u] = *reinterpret_cast<const uint2*>(sgb + soff + 128u * u);
 
     constexpr uint32_t dx = 64u * 2u * L;
     const uint32_t dph = (uint32_t)(64 * L) * m.dphi;
@@ -209,26 +231,29 @@ __device__ __forceinline__ void periodic_run(Slot& S, const uint8_t* lds, uint32
         const uint32_t h_cross = 2u * S.wnext;
         const uint32_t jx = h_cross > hfirst + 63u ? (h_cross - hfirst - 63u + 63u) / 64u : 0u;
         const uint32_t jend = min(max(jx, j), full);
-        for (; j + 2 <= jend; j += 2) {
-            const short2_t a0 = bin_sum<L>(lds, xaddr, ph, roff, poff, lane4);
-            const short2_t a1 = bin_sum<L>(lds, xaddr + dx, ph + dph, roff, poff, lane4);
-            add_bin<FMT>(S, a0, sg0);
-            add_bin<FMT>(S, a1, sg1);
-            sg0 = *reinterpret_cast<const uint2*>(sgb + soff + 256u);
-            sg1 = *reinterpret_cast<const uint2*>(sgb + soff + 384u);
-            soff += 256u;
-            xaddr += 2u * dx;
-            ph += 2u * dph;
+        for (; j + U <= jend; j += U) {
+            short2_t a[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                a[u] = bin_sum<L>(lds, xaddr + u * dx, ph + (uint32_t)u * dph, roff, poff, lane4);
+#pragma unroll
+            for (int u = 0; u < U; ++u) add_bin<FMT>(S, a[u], sg[u]);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                sg[u] = *reinterpret_cast<const uint2*>(sgb + soff + 128u * (U + u));
+            soff += 128u * U;
+            xaddr += U * dx;
+            ph += (uint32_t)U * dph;
         }
-        if (j < jend) {
+        for (; j < jend; ++j) {
             const short2_t a0 = bin_sum<L>(lds, xaddr, ph, roff, poff, lane4);
-            add_bin<FMT>(S, a0, sg0);
-            sg0 = sg1;
-            sg1 = *reinterpret_cast<const uint2*>(sgb + soff + 256u);
+            add_bin<FMT>(S, a0, sg[0]);
+#pragma unroll
+            for (int u = 0; u + 1 < U; ++u) sg[u] = sg[u + 1];
+            sg[U - 1] = *reinterpret_cast<const uint2*>(sgb + soff + 128u * U);
             soff += 128u;
             xaddr += dx;
             ph += dph;
-            ++j;
         }
         if (j >= steps) break;
         // a step with a dump boundary, or the ragged last step
@@ -239,7 +264,7 @@ __device__ __forceinline__ void periodic_run(Slot& S, const uint8_t* lds, uint32
             const bool ahead = valid && c >= S.wnext;
             short2_t a = bin_sum<L>(lds, valid ? xaddr : (uint32_t)kXA, ph, roff, poff, lane4);
             if (!valid) a = short2_t{0, 0};
-            if (valid && !ahead) add_bin<FMT>(S, a, sg0);
+            if (valid && !ahead) add_bin<FMT>(S, a, sg[0]);
             if (__ballot(ahead) != 0) {
                 fold<FMT>(S, par);
                 wave_flush(S, d, ch);
@@ -247,10 +272,11 @@ __device__ __forceinline__ void periodic_run(Slot& S, const uint8_t* lds, uint32
                 for (int q = 0; q < 6; ++q) S.v[q] = 0;
                 S.w += 1;
                 S.wnext += span;
-                if (ahead) add_bin<FMT>(S, a, sg0);
+                if (ahead) add_bin<FMT>(S, a, sg[0]);
             }
-            sg0 = sg1;
-            sg1 = *reinterpret_cast<const uint2*>(sgb + soff + 256u);
+#pragma unroll
+            for (int u = 0; u + 1 < U; ++u) sg[u] = sg[u + 1];
+            sg[U - 1] = *reinterpret_cast<const uint2*>(sgb + soff + 128u * U);
             soff += 128u;
             xaddr += dx;
             ph += dph;
@@ -422,18 +448,35 @@ __device__ __forceinline__ void bin_start(uint64_t h, uint64_t u0, uint32_t dp, 
     e_out = nr * dp - D;
 }
 
+// Bins [kb, ke) of a run clipped to this wave's share [pb, pe).
+template <int FMT, int L>
+__device__ __forceinline__ void clipped_run(Slot& S, const uint8_t* lds, uint32_t lane,
+                                            uint32_t lane4, int64_t base, uint32_t h_a,
+                                            uint32_t kb, uint32_t ke, uint32_t pb, uint32_t pe,
+                                            uint64_t t0, const DevMeta& m, const DevChan& ch,
+                                            const uint32_t* __restrict__ sgn_prn, uint32_t span,
+                                            const Dest& d) {
+    periodic_run<FMT, L>(S, lds, lane, lane4, base, h_a, max(kb, pb), min(ke, pe), t0, m, ch,
+                         sgn_prn, span, d);
+}
+
+// One channel on the staged tile [t0, t1), by wave `sub` of the R waves
+// that share the channel: the tile's whole-chip bins are cut into R
+// contiguous shares (multiples of 64 bins) and the wave takes share `sub`;
+// wave 0 also takes the direct samples at the block ends and the slip seam.
 template <int FMT, int L>
 __device__ __forceinline__ void channel_tile(Slot& S, const uint8_t* lds, uint32_t lane,
                                              uint32_t lane4, uint64_t t0, uint64_t t1,
                                              const DevMeta& m, const DevChan& ch,
-                                             const uint32_t* __restrict__ sgn_prn, const Dest& d) {
+                                             const uint32_t* __restrict__ sgn_prn, const Dest& d,
+                                             uint32_t sub, uint32_t R) {
     const uint32_t span = (uint32_t)(m.window >> 32);
     const uint32_t tl = (uint32_t)(t1 - t0);
     // samples of chips cut by the ends of the block
-    if (m.head_end > t0)
+    if (sub == 0 && m.head_end > t0)
         direct_epl(lds, lane4, t0, 0, (uint32_t)(min((uint64_t)m.head_end, t1) - t0), m, ch,
                    sgn_prn, d);
-    if (t1 > m.tail_beg)
+    if (sub == 0 && t1 > m.tail_beg)
         direct_epl(lds, lane4, t0, (uint32_t)(max((uint64_t)m.tail_beg, t0) - t0), tl, m, ch,
                    sgn_prn, d);
     // bins of whole chips whose code phase starts in [u(t0), u(t1))
@@ -445,22 +488,36 @@ __device__ __forceinline__ void channel_tile(Slot& S, const uint8_t* lds, uint32
     if (hb > 2 * m.c_full1) hb = 2 * m.c_full1;
     if (hb <= ha) return;
     const uint32_t nb = (uint32_t)(hb - ha);
+    // this wave's share of the bins (nb < 2^15, so 32-bit products)
+    const uint32_t pb = sub == 0 ? 0u : min(nb, ((nb * sub) / R + 63u) & ~63u);
+    const uint32_t pe = sub + 1 == R ? nb : min(nb, ((nb * (sub + 1)) / R + 63u) & ~63u);
+    // the open dump becomes the one of the share's first bin (the shares of
+    // the other waves lie in between): flush what is open if that is later
+    if (pb < pe) {
+        const uint32_t c_first = (uint32_t)((ha + pb) >> 1);
+        if (!S.init || c_first >= S.wnext) {
+            const uint32_t w_first = c_first / span;
+            if (S.init) {
+                wave_flush(S, d, ch);
+#pragma unroll
+                for (int q = 0; q < 6; ++q) S.v[q] = 0;
+            }
+            S.init = true;
+            S.w = w_first;
+            S.wnext = (w_first + 1) * span;
+        }
+    }
     const uint32_t dp = (uint32_t)m.dp;
     uint64_t na, ea;
     bin_start(ha, u0, dp, 1.0f / (float)dp, na, ea);
-    if (!S.init) {  // dump of the first bin this wave sees for the channel
-        S.init = true;
-        S.w = (uint32_t)((ha >> 1) / span);
-        S.wnext = (S.w + 1) * span;
-    }
     // bin k starts at na + k*L while e_k = ea + k*D stays in [0, dp); bins
     // 0 .. nb-1 all hold L samples when that holds up to k = nb (the start of
     // the first bin of the next tile)
     const int64_t D = (int64_t)L * (int64_t)dp - (int64_t(1) << 31);
     const int64_t elast = (int64_t)ea + (int64_t)nb * D;
     if (elast >= 0 && elast < (int64_t)dp) {
-        periodic_run<FMT, L>(S, lds, lane, lane4, (int64_t)na, (uint32_t)ha, 0, nb, t0, m, ch,
-                             sgn_prn, span, d);
+        clipped_run<FMT, L>(S, lds, lane, lane4, (int64_t)na, (uint32_t)ha, 0, nb, pb, pe, t0, m,
+                            ch, sgn_prn, span, d);
         return;
     }
     // one slip: first k (1 <= ks <= nb) whose bin starts one sample earlier
@@ -474,15 +531,86 @@ __device__ __forceinline__ void channel_tile(Slot& S, const uint8_t* lds, uint32
         ks = (uint32_t)((int64_t)ea / (-D) + 1);
         sigma = 1;
     }
-    periodic_run<FMT, L>(S, lds, lane, lane4, (int64_t)na, (uint32_t)ha, 0, ks, t0, m, ch, sgn_prn,
-                         span, d);
-    periodic_run<FMT, L>(S, lds, lane, lane4, (int64_t)na + sigma, (uint32_t)ha, ks, nb, t0, m, ch,
-                         sgn_prn, span, d);
+    clipped_run<FMT, L>(S, lds, lane, lane4, (int64_t)na, (uint32_t)ha, 0, ks, pb, pe, t0, m, ch,
+                        sgn_prn, span, d);
+    clipped_run<FMT, L>(S, lds, lane, lane4, (int64_t)na + sigma, (uint32_t)ha, ks, nb, pb, pe, t0,
+                        m, ch, sgn_prn, span, d);
     // bin ks-1 really ends at na + ks*L + sigma: the sample between the two
     // grids was counted twice (sigma = -1) or not at all (sigma = +1)
-    if (lane == 0) {
+    if (sub == 0 && lane == 0) {
         const int64_t off = (int64_t)na + (int64_t)ks * L + (sigma < 0 ? -1 : 0);
         seam_sample(lds, lane4, t0, off, ha + ks - 1, sigma < 0 ? -1 : 1, m, ch, sgn_prn, span, d);
+    }
+}
+
+// Tiles [tb0, tb1) of one sample block for the block's channel list
+// s_list[0 .. nlist), R waves per channel (nlist * R <= kMaxWaves); each
+// wave keeps its channel's sums in registers across the tiles and flushes
+// the dump still open at the end.
+template <int FMT>
+__device__ __forceinline__ void pbin_chunk(uint8_t* s_lds, const int* s_list, int nlist, int R,
+                                           const uint8_t* __restrict__ samples, uint64_t n,
+                                           uint32_t tb0, uint32_t tb1,
+                                           const DevChan* __restrict__ chans,
+                                           const DevMeta* __restrict__ metas,
+                                           gc_chan_state* __restrict__ state,
+                                           int32_t* __restrict__ out, int tap_stride,
+                                           uint32_t max_dumps,
+                                           const uint32_t* __restrict__ tables) {
+    const int tid = threadIdx.x;
+    const int nthreads = blockDim.x;
+    const int wave = tid / 64;
+    const uint32_t lane = tid & 63;
+    const uint32_t lane4 = lane * 4;
+    Slot S;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) S.v[q] = 0;
+    S.e16 = S.l16 = short2_t{0, 0};
+    S.r[0] = S.r[1] = S.r[2] = S.r[3] = 0;
+    S.w = 0;
+    S.wnext = 0;
+    S.init = false;
+    const int slot = wave / R;
+    const uint32_t sub = (uint32_t)(wave - slot * R);
+    const bool active = slot < nlist;
+    const int chn = __builtin_amdgcn_readfirstlane(active ? s_list[slot] : s_list[0]);
+    const DevChan& ch = chans[chn];
+    const uint32_t* sgn_prn = tables + kTabSign + (ch.prn - 1) * kSignLen;
+    const DevMeta m = metas[chn];
+    const Dest d{out, state + chn, (uint64_t)chn * max_dumps, tap_stride, m.m_close};
+    for (uint32_t tile = tb0; tile < tb1; ++tile) {
+        const uint64_t t0 = (uint64_t)tile * kTile;
+        const uint64_t t1 = min(n, t0 + kTile);
+        __syncthreads();
+        stage_tile<FMT>(samples, n, t0, s_lds, nthreads);
+        __syncthreads();
+        if (active) {
+            switch (m.bin_len) {
+                case 2: channel_tile<FMT, 2>(S, s_lds, lane, lane4, t0, t1, m, ch, sgn_prn, d, sub, R); break;
+                case 4: channel_tile<FMT, 4>(S, s_lds, lane, lane4, t0, t1, m, ch, sgn_prn, d, sub, R); break;
+                case 8: channel_tile<FMT, 8>(S, s_lds, lane, lane4, t0, t1, m, ch, sgn_prn, d, sub, R); break;
+                default: channel_tile<FMT, 10>(S, s_lds, lane, lane4, t0, t1, m, ch, sgn_prn, d, sub, R); break;
+            }
+        }
+    }
+    // the dump still open at the end of the chunk
+    if (active && S.init) wave_flush(S, d, ch);
+}
+
+// Periodic channels first .. of [c_begin, c_end) into s_list (at most
+// `cap`), their number into s_list[kMaxWaves]; by thread 0.
+__device__ __forceinline__ void list_periodic(int* s_list, const DevMeta* __restrict__ metas,
+                                              int c_begin, int c_end, int first, int cap) {
+    if (threadIdx.x == 0) {
+        int k = 0, seen = 0;
+        for (int c = c_begin; c < c_end && k < cap; ++c) {
+            const DevMeta& m = metas[c];
+            if (m.status == GC_OK && m.path == kPathPeriodic) {
+                if (seen >= first) s_list[k++] = c;
+                ++seen;
+            }
+        }
+        s_list[kMaxWaves] = k;
     }
 }
 
@@ -495,69 +623,59 @@ __global__ __launch_bounds__(kMaxWaves * 64) void k_pbin(const uint8_t* __restri
                                                          int32_t* __restrict__ out, int tap_stride,
                                                          uint32_t max_dumps,
                                                          const uint32_t* __restrict__ tables,
-                                                         int n_chan, uint32_t n_tiles) {
+                                                         int n_chan, uint32_t n_tiles,
+                                                         int per_block) {
     // one LDS block: the per-lane carrier tables at offset 0 (the v_perm
     // result is the address itself), the two staged copies, the channel list
     __shared__ __attribute__((aligned(16))) uint8_t s_lds[kLdsBytes + 4 * (kMaxWaves + 1)];
     uint32_t* s_lut = reinterpret_cast<uint32_t*>(s_lds);
     int* s_list = reinterpret_cast<int*>(s_lds + kLdsBytes);
-    const int tid = threadIdx.x;
-    const int nthreads = blockDim.x;
-    const int wave = tid / 64;
-    const uint32_t lane = tid & 63;
-    const uint32_t lane4 = lane * 4;
-
-    // this block's channel group: periodic channels 16*blockIdx.y ...
-    if (tid == 0) {
-        const int first = (int)blockIdx.y * kMaxWaves;
-        int k = 0, seen = 0;
-        for (int c = 0; c < n_chan && k < kMaxWaves; ++c) {
-            const DevMeta& m = metas[c];
-            if (m.status == GC_OK && m.path == kPathPeriodic) {
-                if (seen >= first) s_list[k++] = c;
-                ++seen;
-            }
-        }
-        s_list[kMaxWaves] = k;
-    }
+    // this block's channel group: periodic channels of ranks
+    // per_block*blockIdx.y ..; with fewer channels than kMaxWaves, several
+    // waves share a channel (R per channel, nlist*R <= blockDim.x/64)
+    list_periodic(s_list, metas, 0, n_chan, (int)blockIdx.y * per_block, per_block);
     __syncthreads();
     const int nlist = s_list[kMaxWaves];
     if (nlist == 0) return;
-    for (int i = tid; i < kLutWords; i += nthreads) s_lut[i] = tables[kTabLut + (i >> 6)];
-
-    Slot S;
-#pragma unroll
-    for (int q = 0; q < 6; ++q) S.v[q] = 0;
-    S.e16 = S.l16 = short2_t{0, 0};
-    S.r[0] = S.r[1] = S.r[2] = S.r[3] = 0;
-    S.w = 0;
-    S.wnext = 0;
-    S.init = false;
-    const bool active = wave < nlist;
-    const int chn = __builtin_amdgcn_readfirstlane(active ? s_list[wave] : 0);
-    const DevChan& ch = chans[chn];
-    const uint32_t* sgn_prn = tables + kTabSign + (ch.prn - 1) * kSignLen;
-    const DevMeta m = metas[chn];
-    const Dest d{out, state + chn, (uint64_t)chn * max_dumps, tap_stride, m.m_close};
+    const int R = (int)(blockDim.x / 64) / nlist;
+    for (int i = threadIdx.x; i < kLutWords; i += blockDim.x) s_lut[i] = tables[kTabLut + (i >> 6)];
     // contiguous chunk of tiles for this block
     const uint32_t tb0 = (uint32_t)(((uint64_t)blockIdx.x * n_tiles) / gridDim.x);
     const uint32_t tb1 = (uint32_t)(((uint64_t)(blockIdx.x + 1) * n_tiles) / gridDim.x);
-    for (uint32_t tile = tb0; tile < tb1; ++tile) {
-        const uint64_t t0 = (uint64_t)tile * kTile;
-        const uint64_t t1 = min(n, t0 + kTile);
+    pbin_chunk<FMT>(s_lds, s_list, nlist, R, samples, n, tb0, tb1, chans, metas, state, out,
+                    tap_stride, max_dumps, tables);
+}
+
+// Many receivers in one persistent launch: item i is a chunk of tiles of
+// one receiver for a group of at most kMaxWaves of its channels; the block
+// lists the group's periodic channels, one wave each (R = 1), or R =
+// kMaxWaves / nlist waves each when that is 2 or more.
+__global__ __launch_bounds__(kMaxWaves * 64) void k_pbin_batch(
+    const DevRx* __restrict__ rx, const PbinItem* __restrict__ items, uint32_t n_items,
+    const DevChan* __restrict__ chans, const DevMeta* __restrict__ metas,
+    gc_chan_state* __restrict__ state, int32_t* __restrict__ out, int tap_stride,
+    uint32_t max_dumps, const uint32_t* __restrict__ tables) {
+    __shared__ __attribute__((aligned(16))) uint8_t s_lds[kLdsBytes + 4 * (kMaxWaves + 1)];
+    uint32_t* s_lut = reinterpret_cast<uint32_t*>(s_lds);
+    int* s_list = reinterpret_cast<int*>(s_lds + kLdsBytes);
+    for (int i = threadIdx.x; i < kLutWords; i += blockDim.x) s_lut[i] = tables[kTabLut + (i >> 6)];
+    for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const PbinItem I = items[it];
+        __syncthreads();   // the previous item is done with s_list and the tile
+        list_periodic(s_list, metas, I.chan_begin, I.chan_begin + I.n_chan, 0, kMaxWaves);
         __syncthreads();
-        stage_tile<FMT>(samples, n, t0, s_lds, nthreads);
-        __syncthreads();
-        if (active) {
-            if (m.bin_len == 8)
-                channel_tile<FMT, 8>(S, s_lds, lane, lane4, t0, t1, m, ch, sgn_prn, d);
-            else
-                channel_tile<FMT, 10>(S, s_lds, lane, lane4, t0, t1, m, ch, sgn_prn, d);
-        }
-    }
-    // the dump still open at the end of the chunk
-    if (active && S.init) {
-        wave_flush(S, d, ch);
+        const int nlist = s_list[kMaxWaves];
+        if (nlist == 0) continue;
+        const int R = kMaxWaves / nlist;
+        const DevRx& X = rx[I.rx];
+        if (X.fmt == GC_I2_REAL)
+            pbin_chunk<GC_I2_REAL>(s_lds, s_list, nlist, R, X.samples, X.n, I.tile_begin,
+                                   I.tile_end, chans, metas, state, out, tap_stride, max_dumps,
+                                   tables);
+        else
+            pbin_chunk<GC_I8_REAL>(s_lds, s_list, nlist, R, X.samples, X.n, I.tile_begin,
+                                   I.tile_end, chans, metas, state, out, tap_stride, max_dumps,
+                                   tables);
     }
 }
 
@@ -567,15 +685,32 @@ void launch_one(const uint8_t* samples, uint64_t n, const DevChan* chans, const 
                 const uint32_t* tables, int grid, hipStream_t s) {
     const uint32_t n_tiles = (uint32_t)((n + kTile - 1) / kTile);
     const int g = (int)min((uint32_t)grid, n_tiles);
-    const int waves = min(n_chan, kMaxWaves);
-    const int groups = (n_chan + kMaxWaves - 1) / kMaxWaves;
-    hipLaunchKernelGGL((k_pbin<FMT>), dim3(g, groups), dim3(64 * waves), 0, s, samples, n, chans,
-                       meta, state, out, tap_stride, max_dumps, tables, n_chan, n_tiles);
+    // up to kMaxWaves channels per block, one wave each; a plan with fewer
+    // channels lets R = kMaxWaves / n_chan waves share each channel (more
+    // waves for a small plan; with many channels sharing costs more than
+    // it gains)
+    const int per_block = min(n_chan, kMaxWaves);
+    const int R = kMaxWaves / per_block;
+    const int groups = (n_chan + per_block - 1) / per_block;
+    hipLaunchKernelGGL((k_pbin<FMT>), dim3(g, groups), dim3(64 * per_block * R), 0, s, samples, n,
+                       chans, meta, state, out, tap_stride, max_dumps, tables, n_chan, n_tiles,
+                       per_block);
 }
 
 }  // namespace
 
 int pbin_tile_samples() { return kTile; }
+
+hipError_t launch_pbin_batch(int grid, const DevRx* rx, const PbinItem* items, uint32_t n_items,
+                             const DevChan* chans, const DevMeta* meta, gc_chan_state* state,
+                             int32_t* out, int tap_stride, uint32_t max_dumps,
+                             const uint32_t* tables, hipStream_t s) {
+    if (n_items == 0) return hipSuccess;
+    const int g = (int)min((uint32_t)grid, n_items);
+    hipLaunchKernelGGL(k_pbin_batch, dim3(g), dim3(64 * kMaxWaves), 0, s, rx, items, n_items,
+                       chans, meta, state, out, tap_stride, max_dumps, tables);
+    return hipGetLastError();
+}
 
 hipError_t launch_pbin(const uint8_t* samples, uint64_t n, int fmt, const DevChan* chans,
                        const DevMeta* meta, gc_chan_state* state, int n_chan, int32_t* out,

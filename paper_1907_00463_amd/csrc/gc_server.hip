@@ -267,7 +267,7 @@ hipError_t launch_batch(const gc_server* s, SrvSlot& sl, const std::vector<Job>&
                                  s->d_n_dumps, s->d_status, gc::kAllowBinned, sl.d_rx, sl.d_list,
                                  sl.d_list + s->cap_chan, sl.s);
         if (e == hipSuccess)
-            e = gc::launch_epl_batch(0, s->cus, sl.d_rx, nr, nullptr, items, s->d_chans,
+            e = gc::launch_epl_batch(0, s->cus, sl.d_rx, nr, nullptr, items, nullptr, s->d_chans,
                                      s->d_meta, s->d_state, s->d_out, kTapStride, s->max_dumps,
                                      s->ctx->d_tables, sl.s);
         for (int i = 0; i < nr && e == hipSuccess; ++i) e = copy_results(s, jobs[(size_t)i], sl.s);

@@ -65,10 +65,10 @@ def _load():
         "gc_plan_kernel_ms": ([P, I32, P], I32),
         "gc_plan_set_kernels": ([P, I32], I32),
         "gc_batch_create": ([P, P, I32, P, P, I32, P, P, P, P, P, U32, P], I32),
-        "gc_batch_configure": ([P, I32, I32], I32),
+        "gc_batch_configure": ([P, I32, I32, I32], I32),
         "gc_batch_tune": ([P, I32], I32),
         "gc_batch_launch": ([P, P], I32),
-        "gc_batch_info": ([P, P, P, P, P, P], I32),
+        "gc_batch_info": ([P, P, P, P, P, P, P, P], I32),
         "gc_batch_destroy": ([P], I32),
         "gc_server_create": ([P, U64, U64, I32, I32, U32, I32, I32, I32, P], I32),
         "gc_server_open_rx": ([P, I32, P, P, I32, P], I32),
@@ -201,8 +201,8 @@ def gc_batch_create(ctx: int, rx: np.ndarray, cfg: np.ndarray, chan_rx: np.ndarr
     return h.value
 
 
-def gc_batch_configure(batch: int, shape: int, grid: int = 0) -> None:
-    _check(_lib.gc_batch_configure(batch, shape, grid), "gc_batch_configure")
+def gc_batch_configure(batch: int, shape: int, grid: int = 0, periodic_chunk: int = 0) -> None:
+    _check(_lib.gc_batch_configure(batch, shape, grid, periodic_chunk), "gc_batch_configure")
 
 
 def gc_batch_tune(batch: int, reps: int = 3) -> None:
@@ -215,11 +215,12 @@ def gc_batch_launch(batch: int, stream=None) -> None:
 
 def gc_batch_info(batch: int) -> dict:
     a, b, c, d = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    pc, pi = C.c_int32(), C.c_int32()
     ms = C.c_float()
-    _check(_lib.gc_batch_info(batch, C.byref(a), C.byref(b), C.byref(c), C.byref(d), C.byref(ms)),
-           "gc_batch_info")
+    _check(_lib.gc_batch_info(batch, C.byref(a), C.byref(b), C.byref(c), C.byref(d), C.byref(ms),
+                              C.byref(pc), C.byref(pi)), "gc_batch_info")
     return {"shape": a.value, "grid": b.value, "n_items": c.value, "n_shapes": d.value,
-            "tuned_ms": ms.value}
+            "tuned_ms": ms.value, "periodic_chunk": pc.value, "periodic_items": pi.value}
 
 
 def gc_batch_destroy(batch: int) -> None:
@@ -408,8 +409,8 @@ class Batch:
         self.handle = gc_batch_create(ctx, rx, self.cfgs, chan_rx, self.state, self.out,
                                       self.dump_n, self.n_dumps, self.status, max_dumps)
 
-    def configure(self, shape: int, grid: int = 0):
-        gc_batch_configure(self.handle, shape, grid)
+    def configure(self, shape: int, grid: int = 0, periodic_chunk: int = 0):
+        gc_batch_configure(self.handle, shape, grid, periodic_chunk)
 
     def tune(self, reps: int = 3):
         gc_batch_tune(self.handle, reps)

@@ -119,8 +119,8 @@ def test_batch_every_shape_and_the_tuner(g, ctx):
     try:
         s0 = b.state.clone()
         for shape in range(b.info()["n_shapes"]):
-            for grid in (0, 7):
-                b.configure(shape, grid)
+            for grid, chunk in ((0, 0), (7, -1), (0, 2), (7, 8)):
+                b.configure(shape, grid, chunk)
                 b.state.copy_(s0)
                 b.launch()
                 _check(b, cfgs, expect)

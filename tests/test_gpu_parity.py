@@ -253,7 +253,7 @@ def _epl_channels_at(g, rng, fs, n_chan, ratios, periods=(1, 4, 20)):
     return cfgs, states
 
 
-@pytest.mark.parametrize("fs", [16.368e6, 20.46e6])
+@pytest.mark.parametrize("fs", [4.092e6, 8.184e6, 16.368e6, 20.46e6])
 @pytest.mark.parametrize("fmt", [0, 2])
 def test_periodic_bins_with_frequent_grid_slips(g, ctx, fs, fmt):
     # code-rate offsets up to 5e-5 (bin-grid slips about every tile, both
