@@ -509,6 +509,8 @@ def main_serving(args, wl, seconds):
         print("bench: serving (%s), %d requests over %g s" % (mode, len(t_arr), seconds),
               file=sys.stderr, flush=True)
         stats = serve_schedule(g, srv, sched, payload, n_chan)
+        stats["server_timing"] = {k: (round(v, 4) if isinstance(v, float) else v)
+                                  for k, v in g.gc_server_stats(srv).items()}
         info = g.gc_server_info(srv)
         stats["launches"] = info["launches"]
         stats["requests_per_launch"] = round(info["launched_requests"] / max(1, info["launches"]),

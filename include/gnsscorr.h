@@ -402,6 +402,24 @@ gc_status gc_server_info(gc_server* s, uint32_t* max_dumps, int32_t* tap_stride,
                          int32_t* in_flight, uint64_t* hbm_in_use, uint64_t* launches,
                          uint64_t* launched_requests);
 
+/* Host-side timing of the serving loop since creation (for latency
+ * diagnostics): per launch, the time the dispatcher spent enqueueing it
+ * (copies and kernel launches) and the time from the end of that enqueue to
+ * the dispatcher seeing it complete; and the longest HIP-call time of a
+ * submission (the sample upload).  Layout fixed: 56 bytes. */
+typedef struct {
+    uint64_t launches;
+    uint64_t launched_requests;
+    double enqueue_mean_ms;
+    double enqueue_max_ms;
+    double device_mean_ms;
+    double device_max_ms;
+    double submit_max_ms;
+} gc_server_timing;
+
+/* Errors: GC_EINVAL. */
+gc_status gc_server_stats(gc_server* s, gc_server_timing* out);
+
 /* Stop the dispatcher, wait for the device and release everything
  * (unfetched results are dropped). */
 gc_status gc_server_destroy(gc_server* s);

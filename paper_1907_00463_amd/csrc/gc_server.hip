@@ -15,6 +15,7 @@
 // request runs alone, one direct-kernel launch per channel (the baseline).
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -101,16 +102,93 @@ struct SrvReq {
     Clock::time_point t_submit, t_done;
 };
 
+// Where one request's results go: its channels in the server arrays and
+// its result area in the pinned host arena (device-visible pointers).
+struct ExportDesc {
+    int32_t cb, n_chan;
+    int32_t* out;
+    uint32_t* dump_n;
+    uint32_t* n_dumps;
+    int32_t* status;
+};
+
+// A launch's tables, laid out the same in pinned host memory (written by
+// the dispatcher) and in device memory (copied there by a kernel at the
+// start of the launch): the compact receiver table, the channel list, each
+// listed channel's receiver index, the export descriptors.
+struct LaunchLayout {
+    size_t off_rx, off_list, off_lrx, off_exp, bytes;
+    void init(int max_rx, int cap_chan) {
+        auto up16 = [](size_t v) { return (v + 15) & ~size_t(15); };
+        off_rx = 0;
+        off_list = up16(off_rx + sizeof(gc::DevRx) * (size_t)max_rx);
+        off_lrx = up16(off_list + sizeof(int32_t) * (size_t)cap_chan);
+        off_exp = up16(off_lrx + sizeof(int32_t) * (size_t)cap_chan);
+        bytes = up16(off_exp + sizeof(ExportDesc) * (size_t)max_rx);
+    }
+};
+
 struct SrvSlot {
     hipStream_t s = nullptr;
     hipEvent_t done = nullptr;
     bool busy = false;
     std::vector<uint64_t> reqs;
-    gc::DevRx* d_rx = nullptr;     // compact receiver table of the launch
-    int32_t* d_list = nullptr;     // channels, then their receiver index
-    gc::DevRx* h_rx = nullptr;     // pinned mirrors
-    int32_t* h_list = nullptr;
+    uint8_t* h_tab = nullptr;      // pinned launch tables (host view)
+    uint8_t* h_tab_dev = nullptr;  // the same memory, device view
+    uint8_t* d_tab = nullptr;      // device copy
+    Clock::time_point t_enq;       // end of the current launch's enqueue
 };
+
+// n bytes from src to dst (16-byte aligned starts; either side may be
+// pinned host memory seen from the device): 16-byte moves, then the tail.
+__global__ __launch_bounds__(256) void k_copy(uint8_t* __restrict__ dst,
+                                              const uint8_t* __restrict__ src, uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t n16 = n / 16;
+    for (uint64_t i = t; i < n16; i += stride)
+        reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(src)[i];
+    for (uint64_t i = n16 * 16 + t; i < n; i += stride) dst[i] = src[i];
+}
+
+// The used parts of a launch's tables: range blockIdx.y of (offset,
+// length) pairs, both multiples of 16 bytes, from pinned host memory to the
+// device copy.
+struct Ranges {
+    uint32_t off[4], len[4];
+};
+__global__ __launch_bounds__(256) void k_copy_ranges(uint8_t* __restrict__ dst,
+                                                     const uint8_t* __restrict__ src, Ranges r) {
+    const uint32_t o = r.off[blockIdx.y], n16 = r.len[blockIdx.y] / 16;
+    const uint4* sp = reinterpret_cast<const uint4*>(src + o);
+    uint4* dp = reinterpret_cast<uint4*>(dst + o);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += gridDim.x * blockDim.x)
+        dp[i] = sp[i];
+}
+
+// Results of request blockIdx.y into its pinned result area.
+__global__ __launch_bounds__(256) void k_export(const ExportDesc* __restrict__ ds,
+                                                const int32_t* __restrict__ d_out,
+                                                const uint32_t* __restrict__ d_dump_n,
+                                                const uint32_t* __restrict__ d_n_dumps,
+                                                const int32_t* __restrict__ d_status,
+                                                uint32_t max_dumps, int tap_stride) {
+    const ExportDesc D = ds[blockIdx.y];
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t rows = (uint64_t)D.n_chan * max_dumps;
+    // rows of tap_stride * 2 words (tap_stride * 8 bytes, a multiple of 16)
+    const uint64_t n16 = rows * (uint64_t)tap_stride / 2;
+    const uint4* so = reinterpret_cast<const uint4*>(d_out + (uint64_t)D.cb * max_dumps * tap_stride * 2);
+    uint4* dout = reinterpret_cast<uint4*>(D.out);
+    for (uint64_t i = t; i < n16; i += stride) dout[i] = so[i];
+    const uint32_t* sd = d_dump_n + (uint64_t)D.cb * max_dumps;
+    for (uint64_t i = t; i < rows; i += stride) D.dump_n[i] = sd[i];
+    for (uint64_t i = t; i < (uint64_t)D.n_chan; i += stride) {
+        D.n_dumps[i] = d_n_dumps[D.cb + i];
+        D.status[i] = d_status[D.cb + i];
+    }
+}
 
 }  // namespace
 
@@ -130,7 +208,9 @@ struct gc_server {
     uint8_t* d_arena;
     Arena dev;
     uint8_t* h_arena;
+    uint8_t* h_arena_dev;          // the pinned arena seen from the device
     Arena host;
+    LaunchLayout lay;
     hipStream_t up;
     int cus;
     std::vector<SrvRx> rx;
@@ -145,6 +225,9 @@ struct gc_server {
     uint64_t next_id;
     size_t rr;                     // round-robin start over receivers
     uint64_t launches, launched_reqs;
+    // host-side timing: enqueue of a launch, enqueue end to completion seen,
+    // HIP calls of a submission (seconds)
+    double enq_sum, enq_max, dev_sum, dev_max, sub_max;
     hipError_t err;                // first device error seen by the dispatcher
 };
 
@@ -185,33 +268,65 @@ struct Job {
     uint64_t n;
     int fmt, cb, n_chan;
     hipEvent_t uploaded;
-    ResPtr res;
+    ResPtr res;                    // device view of the result area
 };
 
-// Copies of one request's rows, sample counts, dump counts and statuses.
-hipError_t copy_results(const gc_server* s, const Job& j, hipStream_t st) {
-    const uint64_t rows = (uint64_t)j.n_chan * s->max_dumps;
-    hipError_t e = hipMemcpyAsync(j.res.out,
-                                  s->d_out + (uint64_t)j.cb * s->max_dumps * kTapStride * 2,
-                                  rows * kTapStride * 2 * 4, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(j.res.dump_n, s->d_dump_n + (uint64_t)j.cb * s->max_dumps, rows * 4,
-                           hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(j.res.n_dumps, s->d_n_dumps + j.cb, (size_t)j.n_chan * 4,
-                           hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(j.res.status, s->d_status + j.cb, (size_t)j.n_chan * 4,
-                           hipMemcpyDeviceToHost, st);
-    return e;
+// Device view of a pointer into the pinned host arena.
+template <class T>
+T* dev_view(const gc_server* s, T* host_ptr) {
+    return reinterpret_cast<T*>(s->h_arena_dev + (reinterpret_cast<uint8_t*>(host_ptr) - s->h_arena));
 }
 
-// One launch of the given requests (distinct receivers) on a slot.
+// One launch of the given requests (distinct receivers) on a slot: the
+// launch tables copied to the device, the correlation, the results written
+// into each request's pinned result area -- every step a kernel on the
+// slot's stream.
 hipError_t launch_batch(const gc_server* s, SrvSlot& sl, const std::vector<Job>& jobs) {
     const int nr = (int)jobs.size();
+    const LaunchLayout& L = s->lay;
+    gc::DevRx* h_rx = reinterpret_cast<gc::DevRx*>(sl.h_tab + L.off_rx);
+    int32_t* h_list = reinterpret_cast<int32_t*>(sl.h_tab + L.off_list);
+    int32_t* h_lrx = reinterpret_cast<int32_t*>(sl.h_tab + L.off_lrx);
+    ExportDesc* h_exp = reinterpret_cast<ExportDesc*>(sl.h_tab + L.off_exp);
+    const gc::DevRx* d_rx = reinterpret_cast<const gc::DevRx*>(sl.d_tab + L.off_rx);
+    const int32_t* d_list = reinterpret_cast<const int32_t*>(sl.d_tab + L.off_list);
+    const int32_t* d_lrx = reinterpret_cast<const int32_t*>(sl.d_tab + L.off_lrx);
+    const ExportDesc* d_exp = reinterpret_cast<const ExportDesc*>(sl.d_tab + L.off_exp);
+    const uint32_t tile = gc::epl_batch_tile(0);
+    uint32_t items = 0;
+    int nl = 0;
+    for (int i = 0; i < nr; ++i) {
+        const Job& j = jobs[(size_t)i];
+        gc::DevRx& d = h_rx[i];
+        d.samples = j.samples;
+        d.n = j.n;
+        d.fmt = j.fmt;
+        d.chan_begin = j.cb;
+        d.chan_end = j.cb + j.n_chan;
+        d.tile_begin = items;
+        items += (uint32_t)((j.n + tile - 1) / tile);
+        for (int c = 0; c < j.n_chan; ++c) {
+            h_list[nl] = j.cb + c;
+            h_lrx[nl] = i;
+            ++nl;
+        }
+        h_exp[i] = ExportDesc{j.cb, j.n_chan, j.res.out, j.res.dump_n, j.res.n_dumps,
+                              j.res.status};
+    }
     hipError_t e = hipSuccess;
     for (const Job& j : jobs)
         if (e == hipSuccess) e = hipStreamWaitEvent(sl.s, j.uploaded, 0);
+    if (e == hipSuccess) {
+        auto up16 = [](size_t v) { return (uint32_t)((v + 15) & ~size_t(15)); };
+        Ranges r;
+        r.off[0] = (uint32_t)L.off_rx;   r.len[0] = up16(sizeof(gc::DevRx) * (size_t)nr);
+        r.off[1] = (uint32_t)L.off_list; r.len[1] = up16(sizeof(int32_t) * (size_t)nl);
+        r.off[2] = (uint32_t)L.off_lrx;  r.len[2] = up16(sizeof(int32_t) * (size_t)nl);
+        r.off[3] = (uint32_t)L.off_exp;  r.len[3] = up16(sizeof(ExportDesc) * (size_t)nr);
+        hipLaunchKernelGGL(k_copy_ranges, dim3(2, 4), dim3(256), 0, sl.s, sl.d_tab, sl.h_tab_dev,
+                           r);
+        e = hipGetLastError();
+    }
     if (s->plain) {
         // every channel alone: its set-up and a direct-kernel launch
         for (int i = 0; i < nr && e == hipSuccess; ++i) {
@@ -230,47 +345,22 @@ hipError_t launch_batch(const gc_server* s, SrvSlot& sl, const std::vector<Job>&
                                            kTapStride, out, kTapStride, s->max_dumps,
                                            s->ctx->d_tables, 0, sl.s);
             }
-            if (e == hipSuccess) e = copy_results(s, j, sl.s);
         }
     } else {
-        const uint32_t tile = gc::epl_batch_tile(0);
-        uint32_t items = 0;
-        int nl = 0;
-        for (int i = 0; i < nr; ++i) {
-            const Job& j = jobs[(size_t)i];
-            gc::DevRx& d = sl.h_rx[i];
-            d.samples = j.samples;
-            d.n = j.n;
-            d.fmt = j.fmt;
-            d.chan_begin = j.cb;
-            d.chan_end = j.cb + j.n_chan;
-            d.tile_begin = items;
-            items += (uint32_t)((j.n + tile - 1) / tile);
-            for (int c = 0; c < j.n_chan; ++c) {
-                sl.h_list[nl] = j.cb + c;
-                sl.h_list[s->cap_chan + nl] = i;
-                ++nl;
-            }
-        }
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(sl.d_rx, sl.h_rx, sizeof(gc::DevRx) * (size_t)nr,
-                               hipMemcpyHostToDevice, sl.s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(sl.d_list, sl.h_list, sizeof(int32_t) * (size_t)nl,
-                               hipMemcpyHostToDevice, sl.s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(sl.d_list + s->cap_chan, sl.h_list + s->cap_chan,
-                               sizeof(int32_t) * (size_t)nl, hipMemcpyHostToDevice, sl.s);
         if (e == hipSuccess)
             e = gc::launch_setup(s->d_chans, s->d_meta, s->d_state, nl, 0, GC_I8_REAL,
                                  GC_CARRIER_LUT, s->max_dumps, s->d_out, kTapStride, s->d_dump_n,
-                                 s->d_n_dumps, s->d_status, gc::kAllowBinned, sl.d_rx, sl.d_list,
-                                 sl.d_list + s->cap_chan, sl.s);
+                                 s->d_n_dumps, s->d_status, gc::kAllowBinned, d_rx, d_list, d_lrx,
+                                 sl.s);
         if (e == hipSuccess)
-            e = gc::launch_epl_batch(0, s->cus, sl.d_rx, nr, nullptr, items, nullptr, s->d_chans,
+            e = gc::launch_epl_batch(0, s->cus, d_rx, nr, nullptr, items, nullptr, s->d_chans,
                                      s->d_meta, s->d_state, s->d_out, kTapStride, s->max_dumps,
                                      s->ctx->d_tables, sl.s);
-        for (int i = 0; i < nr && e == hipSuccess; ++i) e = copy_results(s, jobs[(size_t)i], sl.s);
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_export, dim3(4, nr), dim3(256), 0, sl.s, d_exp, s->d_out,
+                           s->d_dump_n, s->d_n_dumps, s->d_status, s->max_dumps, kTapStride);
+        e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipEventRecord(sl.done, sl.s);
     return e;
@@ -297,6 +387,9 @@ void dispatcher(gc_server* s) {
         for (size_t k = 0; k < s->slots.size(); ++k) {
             SrvSlot& sl = s->slots[k];
             if (!finished[k]) continue;
+            const double dev = std::chrono::duration<double>(now - sl.t_enq).count();
+            s->dev_sum += dev;
+            s->dev_max = std::max(s->dev_max, dev);
             for (uint64_t id : sl.reqs) {
                 SrvReq& q = s->reqs[id];
                 q.state = 2;
@@ -324,8 +417,13 @@ void dispatcher(gc_server* s) {
                 SrvReq& q = s->reqs[id];
                 q.state = 1;
                 sl.reqs.push_back(id);
+                ResPtr rp = res_ptr(s, q);
+                rp.out = dev_view(s, rp.out);
+                rp.dump_n = dev_view(s, rp.dump_n);
+                rp.n_dumps = dev_view(s, rp.n_dumps);
+                rp.status = dev_view(s, rp.status);
                 jobs.push_back(Job{s->d_arena + q.dev_off, q.n, R.fmt, R.cb, R.n_chan,
-                                   q.uploaded, res_ptr(s, q)});
+                                   q.uploaded, rp});
             }
             if (sl.reqs.empty()) break;
             s->rr = (s->rr + 1) % (nrx ? nrx : 1);
@@ -333,8 +431,13 @@ void dispatcher(gc_server* s) {
             s->launches += 1;
             s->launched_reqs += sl.reqs.size();
             lk.unlock();
+            const Clock::time_point t0 = Clock::now();
             const hipError_t e = launch_batch(s, sl, jobs);
+            sl.t_enq = Clock::now();
             lk.lock();
+            const double enq = std::chrono::duration<double>(sl.t_enq - t0).count();
+            s->enq_sum += enq;
+            s->enq_max = std::max(s->enq_max, enq);
             if (e != hipSuccess && s->err == hipSuccess) s->err = e;
             progress = true;
         }
@@ -381,6 +484,7 @@ gc_status gc_server_create(gc_ctx* ctx, uint64_t hbm_budget_bytes, uint64_t host
     s->next_id = 1;
     s->rr = 0;
     s->launches = s->launched_reqs = 0;
+    s->enq_sum = s->enq_max = s->dev_sum = s->dev_max = s->sub_max = 0.0;
     s->err = hipSuccess;
     s->cus = gc::epl_blocks_per_device(ctx->device);
     const size_t C = (size_t)max_channels;
@@ -393,6 +497,8 @@ gc_status gc_server_create(gc_ctx* ctx, uint64_t hbm_budget_bytes, uint64_t host
     if (e == hipSuccess) e = hipMalloc(&s->d_status, 4 * C);
     if (e == hipSuccess) e = hipMalloc(&s->d_arena, hbm_budget_bytes);
     if (e == hipSuccess) e = hipHostMalloc(&s->h_arena, host_budget_bytes, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&s->h_arena_dev, s->h_arena, 0);
+    s->lay.init(max_batch_rx, max_channels);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->up, hipStreamNonBlocking);
     s->dev.init(hbm_budget_bytes);
     s->host.init(host_budget_bytes);
@@ -400,13 +506,9 @@ gc_status gc_server_create(gc_ctx* ctx, uint64_t hbm_budget_bytes, uint64_t host
     for (SrvSlot& sl : s->slots) {
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipMalloc(&sl.d_rx, sizeof(gc::DevRx) * (size_t)max_batch_rx);
-        if (e == hipSuccess) e = hipMalloc(&sl.d_list, sizeof(int32_t) * 2 * C);
-        if (e == hipSuccess)
-            e = hipHostMalloc(&sl.h_rx, sizeof(gc::DevRx) * (size_t)max_batch_rx,
-                              hipHostMallocDefault);
-        if (e == hipSuccess)
-            e = hipHostMalloc(&sl.h_list, sizeof(int32_t) * 2 * C, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipMalloc(&sl.d_tab, s->lay.bytes);
+        if (e == hipSuccess) e = hipHostMalloc(&sl.h_tab, s->lay.bytes, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&sl.h_tab_dev, sl.h_tab, 0);
     }
     // touch every stream once with a device operation (clearing the status
     // words), so that no request pays for the runtime's first use of a queue
@@ -477,11 +579,16 @@ gc_status gc_server_submit(gc_server* s, int32_t rx_id, const void* host_samples
         return GC_EBUSY;
     }
     memcpy(s->h_arena + q.host_off, host_samples, q.dev_bytes);
+    const Clock::time_point t0 = Clock::now();
     hipError_t e = hipEventCreateWithFlags(&q.uploaded, hipEventDisableTiming);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(s->d_arena + q.dev_off, s->h_arena + q.host_off, q.dev_bytes,
-                           hipMemcpyHostToDevice, s->up);
+    if (e == hipSuccess && q.dev_bytes > 0) {
+        const uint32_t blocks = (uint32_t)std::min<uint64_t>(64, (q.dev_bytes + 4095) / 4096);
+        hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, s->up, s->d_arena + q.dev_off,
+                           s->h_arena_dev + q.host_off, q.dev_bytes);
+        e = hipGetLastError();
+    }
     if (e == hipSuccess) e = hipEventRecord(q.uploaded, s->up);
+    s->sub_max = std::max(s->sub_max, std::chrono::duration<double>(Clock::now() - t0).count());
     if (e != hipSuccess) {
         s->dev.release(q.dev_off, q.dev_bytes);
         s->host.release(q.host_off, q.host_bytes);
@@ -580,6 +687,20 @@ gc_status gc_server_info(gc_server* s, uint32_t* max_dumps, int32_t* tap_stride,
     return GC_OK;
 }
 
+gc_status gc_server_stats(gc_server* s, gc_server_timing* out) {
+    if (!s || !out) return GC_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    const double n = s->launches ? (double)s->launches : 1.0;
+    out->launches = s->launches;
+    out->launched_requests = s->launched_reqs;
+    out->enqueue_mean_ms = 1e3 * s->enq_sum / n;
+    out->enqueue_max_ms = 1e3 * s->enq_max;
+    out->device_mean_ms = 1e3 * s->dev_sum / n;
+    out->device_max_ms = 1e3 * s->dev_max;
+    out->submit_max_ms = 1e3 * s->sub_max;
+    return GC_OK;
+}
+
 gc_status gc_server_destroy(gc_server* s) {
     if (!s) return GC_EINVAL;
     {
@@ -595,10 +716,8 @@ gc_status gc_server_destroy(gc_server* s) {
     for (SrvSlot& sl : s->slots) {
         if (sl.s) (void)hipStreamDestroy(sl.s);
         if (sl.done) (void)hipEventDestroy(sl.done);
-        if (sl.d_rx) (void)hipFree(sl.d_rx);
-        if (sl.d_list) (void)hipFree(sl.d_list);
-        if (sl.h_rx) (void)hipHostFree(sl.h_rx);
-        if (sl.h_list) (void)hipHostFree(sl.h_list);
+        if (sl.d_tab) (void)hipFree(sl.d_tab);
+        if (sl.h_tab) (void)hipHostFree(sl.h_tab);
     }
     if (s->up) (void)hipStreamDestroy(s->up);
     if (s->d_chans) (void)hipFree(s->d_chans);

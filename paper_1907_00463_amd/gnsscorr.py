@@ -35,7 +35,12 @@ CHAN_STATE = np.dtype([("code_phase", "<u8"), ("code_step", "<u8"), ("carr_phase
                        ("acc", "<i4", (GC_MAX_TAPS, 2)), ("acc_f", "<f4", (GC_MAX_TAPS, 2))])
 RX_DESC = np.dtype([("samples", "<u8"), ("n_samples", "<u8"), ("fmt", "<i4"),
                     ("reserved", "<i4")])
+SERVER_TIMING = np.dtype([("launches", "<u8"), ("launched_requests", "<u8"),
+                          ("enqueue_mean_ms", "<f8"), ("enqueue_max_ms", "<f8"),
+                          ("device_mean_ms", "<f8"), ("device_max_ms", "<f8"),
+                          ("submit_max_ms", "<f8")])
 assert CHAN_CFG.itemsize == 1040 and CHAN_STATE.itemsize == 2096 and RX_DESC.itemsize == 24
+assert SERVER_TIMING.itemsize == 56
 
 
 class GcError(RuntimeError):
@@ -79,6 +84,7 @@ def _load():
         "gc_server_state": ([P, I32, P], I32),
         "gc_server_info": ([P, P, P, P, P, P, P], I32),
         "gc_server_destroy": ([P], I32),
+        "gc_server_stats": ([P, P], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -94,7 +100,7 @@ EXPORTED = ("gc_strerror", "gc_version", "gc_create", "gc_destroy", "gc_nco_init
             "gc_batch_create", "gc_batch_configure", "gc_batch_tune", "gc_batch_launch",
             "gc_batch_info", "gc_batch_destroy", "gc_server_create", "gc_server_open_rx",
             "gc_server_submit", "gc_server_hold", "gc_server_poll", "gc_server_result", "gc_server_state",
-            "gc_server_info", "gc_server_destroy")
+            "gc_server_info", "gc_server_destroy", "gc_server_stats")
 
 
 def _check(rc: int, where: str):
@@ -298,6 +304,12 @@ def gc_server_info(server: int) -> dict:
                                C.byref(ln), C.byref(lr)), "gc_server_info")
     return {"max_dumps": md.value, "tap_stride": ts.value, "in_flight": fl.value,
             "hbm_in_use": hb.value, "launches": ln.value, "launched_requests": lr.value}
+
+
+def gc_server_stats(server: int) -> dict:
+    t = np.zeros(1, SERVER_TIMING)
+    _check(_lib.gc_server_stats(server, t.ctypes.data), "gc_server_stats")
+    return {k: t[0][k].item() for k in SERVER_TIMING.names}
 
 
 def gc_server_destroy(server: int) -> None:

@@ -51,6 +51,8 @@ int main(void) {
          offsetof(gc_chan_state, carr_step));
   printf("%zu %zu %zu %zu\n", sizeof(gc_rx_desc), offsetof(gc_rx_desc, n_samples),
          offsetof(gc_rx_desc, fmt), offsetof(gc_rx_desc, reserved));
+  printf("%zu %zu %zu\n", sizeof(gc_server_timing), offsetof(gc_server_timing, enqueue_mean_ms),
+         offsetof(gc_server_timing, submit_max_ms));
   return 0;
 }
 ''')
@@ -62,7 +64,9 @@ int main(void) {
                     st.fields["carr_phase_f"][1], st.fields["acc"][1],
                     st.fields["acc_f"][1], st.fields["acc_n"][1], st.fields["carr_step"][1],
                     rx.itemsize, rx.fields["n_samples"][1], rx.fields["fmt"][1],
-                    rx.fields["reserved"][1]]
+                    rx.fields["reserved"][1], gnsscorr.SERVER_TIMING.itemsize,
+                    gnsscorr.SERVER_TIMING.fields["enqueue_mean_ms"][1],
+                    gnsscorr.SERVER_TIMING.fields["submit_max_ms"][1]]
 
 
 def test_host_validation_without_a_device():
@@ -81,6 +85,7 @@ def test_host_validation_without_a_device():
     assert g._lib.gc_server_poll(None, None, 0, None) == g.GC_EINVAL
     assert g._lib.gc_server_result(None, 1, None, None, None, None, None) == g.GC_EINVAL
     assert g._lib.gc_server_destroy(None) == g.GC_EINVAL
+    assert g._lib.gc_server_stats(None, None) == g.GC_EINVAL
     assert g.gc_version() == (1, 0)
     for s in (0, -1, -2, -3, -4, -5, -6, -7):
         assert len(g.gc_strerror(s)) > 0
