@@ -148,37 +148,79 @@ __device__ __forceinline__ void chunk_next(Chunk& k, uint64_t span, uint64_t dp,
 }
 
 // Tile samples [t0, t0 + kXSamples) as two int16 pairs each: (xI, xQ) and
-// (xQ, -xI) (real input: (x, 0) and (0, -x)); zero past the block.
+// (xQ, -xI) (real input: (x, 0) and (0, -x)); zero past the block.  Each
+// thread takes units of 8 samples: one 16-byte (complex int8), 8-byte (real
+// int8) or 2-byte (2-bit) load, four 16-byte LDS stores.
 template <int FMT>
 __device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, uint64_t n,
                                            uint64_t t0, uint8_t* lds, int nthreads) {
+    static_assert(kXSamples % 8 == 0, "staging unit");
     uint4* dst = reinterpret_cast<uint4*>(lds + kOffX);
     const uint32_t avail = (uint32_t)min(n - t0, (uint64_t)kXSamples);
-    // two samples (16 bytes of LDS) per thread and pass
-    for (int i = threadIdx.x; i < kXSamples / 2; i += nthreads) {
-        const uint32_t s = 2u * i;
-        int xi[2] = {0, 0}, xq[2] = {0, 0};
+    for (int u = threadIdx.x; u < kXSamples / 8; u += nthreads) {
+        const uint32_t s0 = 8u * (uint32_t)u;
+        const bool whole = s0 + 8 <= avail;
+        int xi[8], xq[8];
+        if constexpr (FMT == GC_I8_IQ) {
+            const uint8_t* src = samples + 2 * (t0 + s0);
+            uint32_t w[4] = {0, 0, 0, 0};
+            if (whole) {
+                const uint4 q = *reinterpret_cast<const uint4*>(src);
+                w[0] = q.x; w[1] = q.y; w[2] = q.z; w[3] = q.w;
+            } else {
+                for (uint32_t b = 0; b < 16; ++b)
+                    if (s0 + b / 2 < avail) w[b / 4] |= (uint32_t)src[b] << (8 * (b % 4));
+            }
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            if (s + u < avail) {
-                const uint64_t g = t0 + s + u;
-                if constexpr (FMT == GC_I8_IQ) {
-                    const uint16_t v = *reinterpret_cast<const uint16_t*>(samples + 2 * g);
-                    xi[u] = (int)(int8_t)(v & 0xFF);
-                    xq[u] = (int)(int8_t)(v >> 8);
-                } else if constexpr (FMT == GC_I8_REAL) {
-                    xi[u] = (int)(int8_t)samples[g];
-                } else {
-                    xi[u] = 2 * (int)((samples[g >> 2] >> (2 * (g & 3))) & 3u) - 3;
-                }
+            for (int k = 0; k < 8; ++k) {
+                const uint32_t v = w[k / 2] >> (16 * (k % 2));
+                xi[k] = (int)(int8_t)(v & 0xFF);
+                xq[k] = (int)(int8_t)((v >> 8) & 0xFF);
+            }
+        } else if constexpr (FMT == GC_I8_REAL) {
+            const uint8_t* src = samples + t0 + s0;
+            uint32_t w[2] = {0, 0};
+            if (whole) {
+                const uint2 q = *reinterpret_cast<const uint2*>(src);
+                w[0] = q.x; w[1] = q.y;
+            } else {
+                for (uint32_t b = 0; b < 8; ++b)
+                    if (s0 + b < avail) w[b / 4] |= (uint32_t)src[b] << (8 * (b % 4));
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                xi[k] = (int)(int8_t)((w[k / 4] >> (8 * (k % 4))) & 0xFF);
+                xq[k] = 0;
+            }
+        } else {
+            const uint8_t* src = samples + (t0 + s0) / 4;
+            uint32_t w = 0;
+            if (whole) {
+                w = *reinterpret_cast<const uint16_t*>(src);
+            } else {
+                for (uint32_t b = 0; b < 2; ++b)
+                    if (s0 + 4 * b < avail) w |= (uint32_t)src[b] << (8 * b);
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                xi[k] = s0 + k < avail ? 2 * (int)((w >> (2 * k)) & 3u) - 3 : 0;
+                xq[k] = 0;
             }
         }
-        uint4 o;
-        o.x = (uint32_t)(uint16_t)xi[0] | ((uint32_t)(uint16_t)xq[0] << 16);
-        o.y = (uint32_t)(uint16_t)xq[0] | ((uint32_t)(uint16_t)(-xi[0]) << 16);
-        o.z = (uint32_t)(uint16_t)xi[1] | ((uint32_t)(uint16_t)xq[1] << 16);
-        o.w = (uint32_t)(uint16_t)xq[1] | ((uint32_t)(uint16_t)(-xi[1]) << 16);
-        dst[i] = o;
+        if (!whole) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (s0 + k >= avail) xi[k] = xq[k] = 0;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; k += 2) {
+            uint4 o;
+            o.x = (uint32_t)(uint16_t)xi[k] | ((uint32_t)(uint16_t)xq[k] << 16);
+            o.y = (uint32_t)(uint16_t)xq[k] | ((uint32_t)(uint16_t)(-xi[k]) << 16);
+            o.z = (uint32_t)(uint16_t)xi[k + 1] | ((uint32_t)(uint16_t)xq[k + 1] << 16);
+            o.w = (uint32_t)(uint16_t)xq[k + 1] | ((uint32_t)(uint16_t)(-xi[k + 1]) << 16);
+            dst[(s0 + k) / 2] = o;
+        }
     }
 }
 
@@ -346,6 +388,15 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
     if (T0 > 0 && k.sa < T0) k = chunk_of(k.ce, span, m.p0, m.dp, n);
     bool seen_first = k.first;  // this wave holds the dump from its first chunk
     bool open = false;          // acc holds part of dump k.m
+    // replica operand of a chunk (chips from cmod), loaded one chunk ahead
+    auto load_b = [&](uint32_t cmod, int4_t (&b)[2]) {
+        uint32_t o = cmod + b_off;
+        if (o >= kCodeLen) o -= kCodeLen;
+        b[0] = *reinterpret_cast<const int4_t*>(cpl + o);
+        b[1] = *reinterpret_cast<const int4_t*>(cpl + o + 16);
+    };
+    int4_t bop[2];
+    if (active) load_b(k.cmod, bop);
 
     for (uint32_t tile = tb0; tile < tb1; ++tile) {
         const uint64_t t0 = (uint64_t)tile * kTile;
@@ -384,18 +435,21 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
             // stage 2: two 16-row tiles x two 16-chip K steps x 16 columns
             {
                 const uint32_t j = lane & 15, g = lane >> 4;
-                uint32_t o = k.cmod + b_off;
-                if (o >= kCodeLen) o -= kCodeLen;
+                const int4_t b_cur[2] = {bop[0], bop[1]};
+                // the next chunk starts at chip offset cmod + 32, or at a
+                // code epoch (offset 0) after the last chunk of a dump
+                uint32_t cnext = k.cmod + kChunkChips;
+                if (cnext >= kCodeLen) cnext -= kCodeLen;
+                load_b(k.last ? 0u : cnext, bop);
 #pragma unroll
                 for (int ks = 0; ks < 2; ++ks) {
-                    const int4_t b = *reinterpret_cast<const int4_t*>(cpl + o + 16 * ks);
 #pragma unroll
                     for (int t = 0; t < 2; ++t) {
                         const uint8_t* ap = s_lds + s_base + (16 * t + j) * kRowBytes + 64 * ks + 16 * g;
                         const int2_t a0 = *reinterpret_cast<const int2_t*>(ap);
                         const int2_t a1 = *reinterpret_cast<const int2_t*>(ap + 8);
                         const int4_t a = int4_t{a0.x, a0.y, a1.x, a1.y};
-                        acc[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc[t], 0, 0, 0);
+                        acc[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b_cur[ks], acc[t], 0, 0, 0);
                     }
                 }
             }
