@@ -390,3 +390,231 @@ int orc_correlate_f64(int fmt, const uint8_t* buf, uint64_t n_samples,
     *n_dumps = nd;
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Closed tracking loops (Table 3): a 2nd-order DLL with the normalised     */
+/* early-minus-late envelope discriminator and carrier aiding, and a        */
+/* 2nd-order PLL (atan discriminator) assisted by a 1st-order FLL (atan2    */
+/* discriminator).  The paper names the loop types only; the filter form   */
+/* and its coefficients follow the softGNSS receiver it builds on:          */
+/*   Wn = B * 8 z / (4 z^2 + 1),  tau1 = k / Wn^2,  tau2 = 2 z / Wn,          */
+/*   nco += (tau2 / tau1) (e - e_prev) + e (T / tau1),                        */
+/* with B the noise bandwidth (Hz), z the damping ratio, k the loop gain and */
+/* T the dump length (int_periods ms).  The FLL is first order with gain    */
+/* 4 B_f T on the frequency basis.  Angles come from a vectoring CORDIC on  */
+/* the integer dumps (Volder, 1959), so that every step is exact integer    */
+/* arithmetic or a correctly rounded double operation.                      */
+/* ------------------------------------------------------------------------ */
+#define ORC_CORDIC_N 31
+#define ORC_Q30 1073741824.0
+
+/* atan2(y, x) for x >= 0, in units of 2^-30 rad: the vector is scaled into */
+/* [2^39, 2^40) by shifts, then rotated towards the x axis by +-atan(2^-i). */
+static int64_t orc_cordic_tab[ORC_CORDIC_N];  /* round(atan(2^-i) * 2^30) */
+
+__attribute__((constructor)) static void orc_cordic_init(void)
+{
+    for (int i = 0; i < ORC_CORDIC_N; ++i)
+        orc_cordic_tab[i] = llround(atan(ldexp(1.0, -i)) * ORC_Q30);
+}
+
+static int64_t orc_atan2_q30(int64_t y, int64_t x)
+{
+    const int64_t* tab = orc_cordic_tab;
+    if (x == 0 && y == 0) return 0;
+    const int64_t hi = (int64_t)1 << 40, lo = (int64_t)1 << 39;
+    while (llabs(x) >= hi || llabs(y) >= hi) { x >>= 1; y >>= 1; }
+    while (llabs(x) < lo && llabs(y) < lo) { x *= 2; y *= 2; }
+    int64_t z = 0;
+    for (int i = 0; i < ORC_CORDIC_N; ++i) {
+        const int64_t xs = x >> i, ys = y >> i;
+        if (y > 0) { x += ys; y -= xs; z += tab[i]; }
+        else       { x -= ys; y += xs; z -= tab[i]; }
+    }
+    return z;
+}
+
+int orc_cordic_table(int64_t* out)
+{
+    if (!out) return ORC_EINVAL;
+    for (int i = 0; i < ORC_CORDIC_N; ++i) out[i] = orc_cordic_tab[i];
+    return ORC_OK;
+}
+
+int orc_cordic_atan2(int64_t y, int64_t x, int64_t* out)
+{
+    if (!out || x < 0) return ORC_EINVAL;
+    *out = orc_atan2_q30(y, x);
+    return ORC_OK;
+}
+
+/* Loop coefficients (tau1, tau2) of a loop with noise bandwidth B, damping */
+/* z and gain k. */
+static void orc_loop_coef(double B, double z, double k, double* tau1, double* tau2)
+{
+    const double wn = B * 8.0 * z / (4.0 * z * z + 1.0);
+    *tau1 = k / (wn * wn);
+    *tau2 = 2.0 * z / wn;
+}
+
+int orc_loop_coefficients(double B, double z, double k, double* out2)
+{
+    if (!out2 || !(B > 0.0) || !(z > 0.0) || !(k > 0.0)) return ORC_EINVAL;
+    orc_loop_coef(B, z, k, &out2[0], &out2[1]);
+    return ORC_OK;
+}
+
+/* Halve all four values until each magnitude is below 2^30 (products and */
+/* their sums then stay inside int64). */
+static void orc_shrink4(int64_t* a, int64_t* b, int64_t* c, int64_t* d)
+{
+    const int64_t lim = (int64_t)1 << 30;
+    while (llabs(*a) >= lim || llabs(*b) >= lim || llabs(*c) >= lim || llabs(*d) >= lim) {
+        *a >>= 1; *b >>= 1; *c >>= 1; *d >>= 1;
+    }
+}
+
+/*
+ * Loop update at the close of a dump.
+ *   prm[9]  = fs, IF, DLL (B, z, k), PLL (B, z, k), FLL B        (Hz, -, -)
+ *   ls[7]   = carr_freq (Hz), code_freq (chips/s), FLL basis (Hz),
+ *             PLL nco (Hz), previous PLL error (cycles), DLL nco (chips/s),
+ *             previous DLL error
+ *   is[3]   = previous prompt I, Q, and whether they are set
+ *   d[6]    = E I, E Q, P I, P Q, L I, L Q of the closed dump
+ * PLL error = atan(Q_P / I_P) / (2 pi) cycles; FLL error = atan2(cross,
+ * dot) / (2 pi T) Hz with cross = I'Q - Q'I, dot = I'I + Q'Q of the previous
+ * (') and current prompts, the dot product's sign removed (a navigation-bit
+ * flip between dumps turns the prompt by pi, not the frequency); DLL error =
+ * (|E| - |L|) / (|E| + |L|).  Carrier frequency = FLL basis + PLL nco; code
+ * frequency = 1.023 MHz (1 + (carrier - IF) / 1575.42 MHz) + DLL nco.  The
+ * new NCO steps are round_half_even(f / fs * 2^32).  Returns ORC_ERANGE when
+ * the code step leaves [1, 2^31).
+ */
+static int orc_loop_update(const double* prm, int int_periods, const int64_t* d, double* ls,
+                           int32_t* is, uint32_t* carr_step, uint64_t* code_step)
+{
+    const double T = (double)int_periods * 1e-3;
+    double t1c, t2c, t1d, t2d;
+    orc_loop_coef(prm[5], prm[6], prm[7], &t1c, &t2c);
+    orc_loop_coef(prm[2], prm[3], prm[4], &t1d, &t2d);
+    const int64_t ie = d[0], qe = d[1], ip = d[2], qp = d[3], il = d[4], ql = d[5];
+    /* PLL */
+    const int64_t a = ip >= 0 ? orc_atan2_q30(qp, ip) : orc_atan2_q30(-qp, -ip);
+    const double carr_err = ((double)a / ORC_Q30) / (2.0 * M_PI);
+    /* FLL */
+    if (is[2]) {
+        int64_t i0 = is[0], q0 = is[1], i1 = ip, q1 = qp;
+        orc_shrink4(&i0, &q0, &i1, &q1);
+        const int64_t dot = i0 * i1 + q0 * q1;
+        const int64_t cross = i0 * q1 - q0 * i1;
+        const int64_t f = dot >= 0 ? orc_atan2_q30(cross, dot) : orc_atan2_q30(-cross, -dot);
+        const double f_err = ((double)f / ORC_Q30) / (2.0 * M_PI * T);
+        ls[2] = ls[2] + (4.0 * prm[8] * T) * f_err;
+    }
+    is[0] = (int32_t)ip;
+    is[1] = (int32_t)qp;
+    is[2] = 1;
+    /* PLL filter */
+    {
+        const double u1 = (t2c / t1c) * (carr_err - ls[4]);
+        const double u2 = carr_err * (T / t1c);
+        ls[3] = ls[3] + (u1 + u2);
+        ls[4] = carr_err;
+    }
+    ls[0] = ls[2] + ls[3];
+    /* DLL */
+    {
+        const double fe = (double)ie, ge = (double)qe, fl = (double)il, gl = (double)ql;
+        const double E = sqrt(fe * fe + ge * ge), L = sqrt(fl * fl + gl * gl);
+        const double code_err = (E + L) > 0.0 ? (E - L) / (E + L) : 0.0;
+        const double u1 = (t2d / t1d) * (code_err - ls[6]);
+        const double u2 = code_err * (T / t1d);
+        ls[5] = ls[5] + (u1 + u2);
+        ls[6] = code_err;
+    }
+    ls[1] = 1.023e6 * (1.0 + (ls[0] - prm[1]) / 1575.42e6) + ls[5];
+    const double cs = nearbyint(ls[0] / prm[0] * ORC_TWO32);
+    *carr_step = (uint32_t)(uint64_t)(int64_t)cs;
+    const double ks = nearbyint(ls[1] / prm[0] * ORC_TWO32);
+    if (!(ks >= 1.0) || !(ks < 2147483648.0)) return ORC_ERANGE;
+    *code_step = (uint64_t)ks;
+    return ORC_OK;
+}
+
+/*
+ * Closed-loop tracking of one E/P/L channel (taps +1/2, 0, -1/2 chip) over
+ * one block.  Per sample the correlation is that of orc_correlate_lut with
+ * the code phase kept inside the window: before sample n, a phase that has
+ * reached W closes the dump (its sums, its sample count and the NCO steps
+ * used for it are emitted, the loops update the steps) and the phase drops
+ * by W; the end of the block closes a dump whose phase has reached W as
+ * well.  rows[] receives per closed dump the six sums followed by the
+ * carrier and code steps used, as int32 (the steps' bit patterns).
+ */
+int orc_track(int fmt, const uint8_t* buf, uint64_t n_samples, int prn, int int_periods,
+              const double* prm, uint32_t* carr_phase, uint32_t* carr_step,
+              uint64_t* code_phase, uint64_t* code_step, int64_t* acc, uint32_t* acc_n,
+              double* ls, int32_t* is, int32_t* rows, uint32_t* dump_n, uint32_t max_dumps,
+              uint32_t* n_dumps)
+{
+    if (fmt < 0 || fmt > 2 || int_periods < 1 || !prm || !acc || !acc_n || !ls || !is ||
+        !n_dumps || !carr_phase || !carr_step || !code_phase || !code_step)
+        return ORC_EINVAL;
+    int8_t code[ORC_CODE_LEN], lc[ORC_LUT_SIZE], ls8[ORC_LUT_SIZE];
+    if (orc_ca_code(prn, code)) return ORC_EINVAL;
+    orc_lut(lc, ls8);
+    const int64_t taps[3] = {(int64_t)1 << 31, 0, -((int64_t)1 << 31)};
+    const uint64_t W = (uint64_t)int_periods * ORC_CODE_LEN * 4294967296ULL;
+    uint32_t phi = *carr_phase, dphi = *carr_step;
+    uint64_t p = *code_phase, dp = *code_step;
+    if (p >= W) return ORC_EINVAL;
+    uint32_t nd = 0;
+    int rc = ORC_OK;
+    for (uint64_t n = 0; n <= n_samples; ++n) {
+        if (p >= W) {
+            if (nd >= max_dumps || !rows || !dump_n) return ORC_ENOSPC;
+            for (int k = 0; k < 6; ++k) {
+                if (!orc_fits_i32(acc[k])) rc = ORC_ERANGE;
+                rows[(uint64_t)nd * 8 + k] = (int32_t)acc[k];
+            }
+            rows[(uint64_t)nd * 8 + 6] = (int32_t)dphi;
+            rows[(uint64_t)nd * 8 + 7] = (int32_t)(uint32_t)dp;
+            dump_n[nd++] = *acc_n;
+            const int u = orc_loop_update(prm, int_periods, acc, ls, is, &dphi, &dp);
+            if (u != ORC_OK) return u;
+            for (int k = 0; k < 6; ++k) acc[k] = 0;
+            *acc_n = 0;
+            p -= W;
+        }
+        if (n == n_samples) break;
+        const int l = (int)(phi >> 24);
+        const int c = lc[l], s = ls8[l];
+        int xi, xq;
+        orc_sample(fmt, buf, n, &xi, &xq);
+        int64_t wi, wq;
+        if (fmt == ORC_I8_IQ) {
+            wi = (int64_t)xi * c + (int64_t)xq * s;
+            wq = (int64_t)xq * c - (int64_t)xi * s;
+        } else {
+            wi = (int64_t)xi * c;
+            wq = -(int64_t)xi * s;
+        }
+        for (int k = 0; k < 3; ++k) {
+            const int64_t chip = orc_mod(orc_floor_div_2_32((int64_t)p + taps[k]), ORC_CODE_LEN);
+            acc[2 * k] += wi * code[chip];
+            acc[2 * k + 1] += wq * code[chip];
+        }
+        *acc_n += 1;
+        phi += dphi;
+        p += dp;
+    }
+    for (int k = 0; k < 6; ++k)
+        if (!orc_fits_i32(acc[k])) rc = ORC_ERANGE;
+    *carr_phase = phi;
+    *carr_step = dphi;
+    *code_phase = p;
+    *code_step = dp;
+    *n_dumps = nd;
+    return rc;
+}

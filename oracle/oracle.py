@@ -30,7 +30,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc into oracle/liboracle.so."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-Wall",
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-Wall", "-ffp-contract=off",
                                "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -56,6 +56,11 @@ def _load():
         lib.orc_correlate_f64.argtypes = [C.c_int, P, C.c_uint64, C.c_int, C.c_int, P, C.c_int,
                                           P, C.c_double, P, C.c_uint64, P, P, P, P,
                                           C.c_uint32, P]
+        lib.orc_cordic_table.argtypes = [P]
+        lib.orc_cordic_atan2.argtypes = [C.c_int64, C.c_int64, P]
+        lib.orc_loop_coefficients.argtypes = [C.c_double, C.c_double, C.c_double, P]
+        lib.orc_track.argtypes = [C.c_int, P, C.c_uint64, C.c_int, C.c_int, P, P, P, P, P, P, P,
+                                  P, P, P, P, C.c_uint32, P]
         _lib = lib
     return _lib
 
@@ -193,3 +198,100 @@ def correlate_f64(fmt, buf, n, prn, taps_q32, T, st: OracleState):
     st.carr_phase_f, st.code_phase, st.acc, st.acc_n = float(cp[0]), int(kp[0]), acc, int(an[0])
     d = int(nd[0])
     return dumps[:d], dump_n[:d]
+
+
+# ---------------------------------------------------------------- closed loops
+@dataclasses.dataclass
+class LoopParams:
+    """Tracking-loop parameters (Table 3 names the loop types; the bandwidths,
+    damping ratios and gains are this library's defaults, those of softGNSS
+    for the DLL and PLL)."""
+    fs: float
+    if_hz: float
+    dll_bw: float = 2.0
+    dll_zeta: float = 0.7
+    dll_k: float = 1.0
+    pll_bw: float = 25.0
+    pll_zeta: float = 0.7
+    pll_k: float = 0.25
+    fll_bw: float = 10.0
+
+    def array(self) -> np.ndarray:
+        return np.array([self.fs, self.if_hz, self.dll_bw, self.dll_zeta, self.dll_k,
+                         self.pll_bw, self.pll_zeta, self.pll_k, self.fll_bw], np.float64)
+
+
+@dataclasses.dataclass
+class TrackState:
+    """A tracked channel: NCO words and open dump (``words``, 3 taps), loop
+    state ``ls`` = (carrier Hz, code chips/s, FLL basis Hz, PLL nco Hz, PLL
+    error cycles, DLL nco chips/s, DLL error) and ``is_`` = (previous prompt
+    I, Q, set)."""
+    words: OracleState
+    ls: np.ndarray
+    is_: np.ndarray
+
+    def copy(self):
+        return TrackState(self.words.copy(), self.ls.copy(), self.is_.copy())
+
+
+def track_state(words: OracleState, carr_hz: float, code_rate: float) -> TrackState:
+    ls = np.array([carr_hz, code_rate, carr_hz, 0.0, 0.0, 0.0, 0.0], np.float64)
+    return TrackState(words, ls, np.zeros(3, np.int32))
+
+
+def cordic_table() -> np.ndarray:
+    out = np.zeros(31, np.int64)
+    _load().orc_cordic_table(_p(out))
+    return out
+
+
+def cordic_atan2(y: int, x: int) -> int:
+    """atan2(y, x), x >= 0, in units of 2^-30 rad."""
+    out = np.zeros(1, np.int64)
+    if _load().orc_cordic_atan2(int(y), int(x), _p(out)):
+        raise ValueError("x must be >= 0")
+    return int(out[0])
+
+
+def loop_coefficients(bw, zeta, k):
+    out = np.zeros(2, np.float64)
+    if _load().orc_loop_coefficients(bw, zeta, k, _p(out)):
+        raise ValueError("bad loop parameters")
+    return float(out[0]), float(out[1])
+
+
+def track(fmt, buf, n, prn, T, params: LoopParams, st: TrackState):
+    """Closed-loop E/P/L tracking of one channel over one block; returns
+    (rows int32 [D, 8]: E I, E Q, P I, P Q, L I, L Q, carrier step, code step
+    used; dump_n [D]).  ``st`` is updated in place."""
+    lib = _load()
+    buf = np.ascontiguousarray(buf, dtype=np.uint8)
+    w = st.words
+    if w.acc is None:
+        w.acc = np.zeros(6, np.int64)
+    md = n // (T * 2046) + 2              # code steps stay below 2^31
+    rows = np.zeros((md, 8), np.int32)
+    dump_n = np.zeros(md, np.uint32)
+    cp = np.array([w.carr_phase], np.uint32)
+    cs = np.array([w.carr_step], np.uint32)
+    kp = np.array([w.code_phase], np.uint64)
+    ks = np.array([w.code_step], np.uint64)
+    an = np.array([w.acc_n], np.uint32)
+    nd = np.zeros(1, np.uint32)
+    acc = np.ascontiguousarray(w.acc, dtype=np.int64)
+    ls = np.ascontiguousarray(st.ls, dtype=np.float64)
+    is_ = np.ascontiguousarray(st.is_, dtype=np.int32)
+    prm = params.array()
+    rc = lib.orc_track(fmt, _p(buf), n, prn, T, _p(prm), _p(cp), _p(cs), _p(kp), _p(ks),
+                       _p(acc), _p(an), _p(ls), _p(is_), _p(rows), _p(dump_n), md, _p(nd))
+    if rc == ERANGE:
+        raise OverflowError("accumulation leaves int32 or a code step leaves [1, 2^31)")
+    if rc:
+        raise RuntimeError("oracle error %d" % rc)
+    w.carr_phase, w.carr_step = int(cp[0]), int(cs[0])
+    w.code_phase, w.code_step = int(kp[0]), int(ks[0])
+    w.acc, w.acc_n = acc, int(an[0])
+    st.ls, st.is_ = ls, is_
+    d = int(nd[0])
+    return rows[:d], dump_n[:d]
