@@ -232,6 +232,81 @@ gc_status gc_plan_timing(gc_plan* plan, int32_t n_slots);
 gc_status gc_plan_kernel_ms(gc_plan* plan, int32_t slot, float* ms);
 
 /* ------------------------------------------------------------------------
+ * Closed tracking loops (Table 3).
+ *
+ * gc_track runs the E/P/L correlator dump by dump and closes the tracking
+ * loops of every channel after each dump: a 2nd-order DLL with the
+ * normalised early-minus-late envelope discriminator (|E| - |L|) / (|E| +
+ * |L|) and carrier aiding, and a 2nd-order PLL with the atan(Q_P / I_P)
+ * discriminator assisted by a 1st-order FLL with an atan2 discriminator on
+ * consecutive prompts (cross and dot products, the dot product's sign
+ * removed so that navigation-bit flips do not count as frequency).  Loop
+ * filter (softGNSS form): wn = B 8 z / (4 z^2 + 1), tau1 = k / wn^2, tau2 =
+ * 2 z / wn, nco += (tau2 / tau1)(e - e_prev) + e T / tau1 with T the dump
+ * length; the FLL adds 4 B_f T times its error (Hz) to the frequency basis.
+ * Carrier = basis + PLL nco; code = 1.023 MHz (1 + (carrier - IF) /
+ * 1575.42 MHz) + DLL nco; the new steps are round_half_even(f / fs 2^32)
+ * and apply from the next dump.  Angles come from a 31-step vectoring
+ * CORDIC on the integer dumps in units of 2^-30 rad; every other step is a
+ * correctly rounded double operation, so results are reproducible bit for
+ * bit.  A dump closes when the code phase reaches the window end, before
+ * the next sample or at the end of the block, so any split of a stream into
+ * blocks gives the same dumps and loop states.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    double fs_hz;      /* sample rate */
+    double if_hz;      /* carrier frequency of zero Doppler */
+    double dll_bw_hz;  /* DLL noise bandwidth, damping ratio, gain (2, 0.7, 1) */
+    double dll_zeta;
+    double dll_gain;
+    double pll_bw_hz;  /* PLL noise bandwidth, damping ratio, gain (25, 0.7, 0.25) */
+    double pll_zeta;
+    double pll_gain;
+    double fll_bw_hz;  /* FLL noise bandwidth (10) */
+} gc_loop_params;
+
+/* Per-channel loop state, in/out for every gc_track call (device memory).
+ * Layout fixed: 72 bytes. */
+typedef struct {
+    double carr_hz;        /* carrier NCO frequency */
+    double code_cps;       /* code NCO rate, chips/s */
+    double fll_basis_hz;   /* FLL frequency basis */
+    double pll_nco_hz;     /* PLL filter output */
+    double pll_err_prev;   /* previous PLL error, cycles */
+    double dll_nco_cps;    /* DLL filter output, chips/s */
+    double dll_err_prev;   /* previous DLL error */
+    int32_t prompt_i_prev; /* prompt of the previous closed dump */
+    int32_t prompt_q_prev;
+    int32_t have_prev;     /* 1 once a dump has closed */
+    int32_t reserved;      /* 0 */
+} gc_loop_state;
+
+/* Host helper: a loop state starting at carrier carr_hz and code rate
+ * code_cps (the same values gc_nco_init turned into the channel's NCO
+ * words), filters at rest.  Errors: GC_EINVAL (null out). */
+gc_status gc_loop_init(double carr_hz, double code_cps, gc_loop_state* out);
+
+/* Track one block: like gc_correlate for the plan's channels, each an E/P/L
+ * channel (3 taps at +1/2, 0, -1/2 chip; others get GC_EINVAL), with the
+ * loops closed after every dump.
+ *   params  host, the loop parameters (by value at the call)
+ *   state   device, gc_chan_state[n_chan] in/out (NCO words, open dump)
+ *   loop    device, gc_loop_state[n_chan] in/out
+ *   rows    device, int32 [n_chan][max_dumps][8]: per closed dump E I, E Q,
+ *           P I, P Q, L I, L Q and the carrier and code steps used for it
+ *           (their bit patterns)
+ *   dump_n, n_dumps, status, max_dumps: as for gc_correlate
+ * Per-channel status: GC_OK; GC_EINVAL (not an E/P/L channel, phase outside
+ * the window); GC_ERANGE (a code step, given or set by the loops, outside
+ * 1 .. 2^31-1 or letting a dump leave int32); GC_ENOSPC.  A channel with an
+ * error keeps its state and loop state.  The plan must use GC_CARRIER_LUT.
+ * Errors returned directly: GC_EINVAL, GC_EDEVICE. */
+gc_status gc_track(gc_plan* plan, const void* samples, uint64_t n_samples,
+                   const gc_loop_params* params, gc_chan_state* state, gc_loop_state* loop,
+                   int32_t* rows, uint32_t* dump_n, uint32_t* n_dumps, int32_t* status,
+                   uint32_t max_dumps, void* stream);
+
+/* ------------------------------------------------------------------------
  * Batches: many receivers in one persistent launch.
  *
  * A batch binds the sample blocks of n_rx receivers (each with its own

@@ -491,6 +491,31 @@ static void orc_shrink4(int64_t* a, int64_t* b, int64_t* c, int64_t* d)
  * new NCO steps are round_half_even(f / fs * 2^32).  Returns ORC_ERANGE when
  * the code step leaves [1, 2^31).
  */
+/* The largest |wipe-off| of one sample: 128 * 24 (int8 real), 128 * the   */
+/* largest |cos| + |sin| of the table (int8 I/Q), 3 * 24 (2-bit). */
+static int64_t orc_max_w(int fmt)
+{
+    if (fmt == ORC_I8_REAL) return 128 * 24;
+    if (fmt == ORC_I2_REAL) return 3 * 24;
+    int8_t c[ORC_LUT_SIZE], s[ORC_LUT_SIZE];
+    orc_lut(c, s);
+    int m = 0;
+    for (int l = 0; l < ORC_LUT_SIZE; ++l) {
+        const int v = abs(c[l]) + abs(s[l]);
+        if (v > m) m = v;
+    }
+    return 128 * (int64_t)m;
+}
+
+/* A code step keeps every dump inside int32 when a window of W holds at   */
+/* most floor((W - 1) / dp) + 1 samples of at most max|w| each.            */
+static int orc_step_in_range(uint64_t dp, uint64_t W, int fmt)
+{
+    if (dp < 1 || dp >= ((uint64_t)1 << 31)) return 0;
+    const uint64_t cnt = (W - 1) / dp + 1;
+    return cnt * (uint64_t)orc_max_w(fmt) < ((uint64_t)1 << 31);
+}
+
 static int orc_loop_update(const double* prm, int int_periods, const int64_t* d, double* ls,
                            int32_t* is, uint32_t* carr_step, uint64_t* code_step)
 {
@@ -550,7 +575,9 @@ static int orc_loop_update(const double* prm, int int_periods, const int64_t* d,
  * used for it are emitted, the loops update the steps) and the phase drops
  * by W; the end of the block closes a dump whose phase has reached W as
  * well.  rows[] receives per closed dump the six sums followed by the
- * carrier and code steps used, as int32 (the steps' bit patterns).
+ * carrier and code steps used, as int32 (the steps' bit patterns).  The
+ * code step, at the start and after every update, must keep a window's sums
+ * inside int32 (the bound of orc_step_in_range), else ORC_ERANGE.
  */
 int orc_track(int fmt, const uint8_t* buf, uint64_t n_samples, int prn, int int_periods,
               const double* prm, uint32_t* carr_phase, uint32_t* carr_step,
@@ -569,6 +596,7 @@ int orc_track(int fmt, const uint8_t* buf, uint64_t n_samples, int prn, int int_
     uint32_t phi = *carr_phase, dphi = *carr_step;
     uint64_t p = *code_phase, dp = *code_step;
     if (p >= W) return ORC_EINVAL;
+    if (!orc_step_in_range(dp, W, fmt)) return ORC_ERANGE;
     uint32_t nd = 0;
     int rc = ORC_OK;
     for (uint64_t n = 0; n <= n_samples; ++n) {
@@ -583,6 +611,7 @@ int orc_track(int fmt, const uint8_t* buf, uint64_t n_samples, int prn, int int_
             dump_n[nd++] = *acc_n;
             const int u = orc_loop_update(prm, int_periods, acc, ls, is, &dphi, &dp);
             if (u != ORC_OK) return u;
+            if (!orc_step_in_range(dp, W, fmt)) return ORC_ERANGE;
             for (int k = 0; k < 6; ++k) acc[k] = 0;
             *acc_n = 0;
             p -= W;

@@ -109,6 +109,17 @@ constexpr int32_t kAllowBinned = 1;
 constexpr int32_t kAllowPeriodic = 2;
 constexpr int32_t kAllowMtap = 4;
 
+// Loop constants of gc_track, passed by value: the loop parameters and the
+// CORDIC angles round(atan(2^-i) * 2^30), i = 0 .. kCordicSteps - 1.
+constexpr int kCordicSteps = 31;
+struct TrackConsts {
+    double fs, if_hz;
+    double dll_bw, dll_zeta, dll_k;
+    double pll_bw, pll_zeta, pll_k;
+    double fll_bw;
+    int64_t tab[kCordicSteps];
+};
+
 // Validated device form of a channel configuration (host side).
 gc_status fill_devchan(const gc_chan_cfg& c, DevChan& d);
 
@@ -155,6 +166,11 @@ hipError_t launch_epl(const uint8_t* samples, uint64_t n_samples, int fmt, const
                       int tap_stride, uint32_t max_dumps, const uint32_t* d_tables, int grid,
                       hipStream_t s);
 int epl_blocks_per_device(int device);
+hipError_t launch_track(const uint8_t* samples, uint64_t n, int fmt, const DevChan* chans,
+                        gc_chan_state* state, gc_loop_state* loop, const TrackConsts& consts,
+                        int n_chan, int32_t* rows, uint32_t* dump_n, uint32_t* n_dumps,
+                        int32_t* status, uint32_t max_dumps, const uint32_t* tables,
+                        hipStream_t s);
 hipError_t launch_generic(const uint8_t* samples, uint64_t n_samples, int fmt, int carrier,
                           const DevChan* chans, const DevMeta* meta, gc_chan_state* state,
                           int n_chan, int max_taps, void* out, int tap_stride,

@@ -307,6 +307,48 @@ gc_status gc_plan_info(const gc_plan* plan, int32_t* tap_stride, int32_t* n_chan
     return GC_OK;
 }
 
+gc_status gc_loop_init(double carr_hz, double code_cps, gc_loop_state* out) {
+    if (!out) return GC_EINVAL;
+    memset(out, 0, sizeof(*out));
+    out->carr_hz = carr_hz;
+    out->code_cps = code_cps;
+    out->fll_basis_hz = carr_hz;
+    return GC_OK;
+}
+
+gc_status gc_track(gc_plan* plan, const void* samples, uint64_t n_samples,
+                   const gc_loop_params* params, gc_chan_state* state, gc_loop_state* loop,
+                   int32_t* rows, uint32_t* dump_n, uint32_t* n_dumps, int32_t* status,
+                   uint32_t max_dumps, void* stream) {
+    if (!plan || !params || !state || !loop || !rows || !dump_n || !n_dumps || !status)
+        return GC_EINVAL;
+    if (n_samples >= (1ull << 31) || max_dumps == 0 || (n_samples > 0 && !samples))
+        return GC_EINVAL;
+    if (plan->carrier != GC_CARRIER_LUT) return GC_EINVAL;
+    const gc_loop_params& q = *params;
+    if (!(q.fs_hz > 0.0) || !(q.dll_bw_hz > 0.0) || !(q.dll_zeta > 0.0) || !(q.dll_gain > 0.0) ||
+        !(q.pll_bw_hz > 0.0) || !(q.pll_zeta > 0.0) || !(q.pll_gain > 0.0) || !(q.fll_bw_hz >= 0.0))
+        return GC_EINVAL;
+    gc::TrackConsts c;
+    c.fs = q.fs_hz;
+    c.if_hz = q.if_hz;
+    c.dll_bw = q.dll_bw_hz;
+    c.dll_zeta = q.dll_zeta;
+    c.dll_k = q.dll_gain;
+    c.pll_bw = q.pll_bw_hz;
+    c.pll_zeta = q.pll_zeta;
+    c.pll_k = q.pll_gain;
+    c.fll_bw = q.fll_bw_hz;
+    // the CORDIC angles atan(2^-i) in units of 2^-30 rad, rounded to nearest
+    for (int i = 0; i < gc::kCordicSteps; ++i)
+        c.tab[i] = llround(atan(ldexp(1.0, -i)) * 1073741824.0);
+    DeviceGuard g(plan->ctx->device);
+    if (!g.ok) return GC_EDEVICE;
+    return from_hip(gc::launch_track((const uint8_t*)samples, n_samples, plan->fmt, plan->d_chans,
+                                     state, loop, c, plan->n_chan, rows, dump_n, n_dumps, status,
+                                     max_dumps, plan->ctx->d_tables, (hipStream_t)stream));
+}
+
 gc_status gc_correlate(gc_plan* plan, const void* samples, uint64_t n_samples,
                        gc_chan_state* state, void* out, uint32_t* dump_n, uint32_t* n_dumps,
                        int32_t* status, uint32_t max_dumps, void* stream) {

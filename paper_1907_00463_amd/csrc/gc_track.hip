@@ -1,0 +1,315 @@
+// gc_track.hip -- closed tracking loops on the device (Table 3): per channel,
+// the E/P/L correlation of one dump, then the DLL / PLL / FLL update that
+// sets the NCO steps of the next dump.
+//
+// One block per channel walks the block of samples dump by dump.  For a dump
+// the block's threads take its samples with a stride (carrier phase and code
+// phase of sample i are phi + i*dphi and p + i*dp), sum the six products in
+// int32 (a code step that keeps the window's sums inside int32 is enforced),
+// and reduce them with DPP and LDS; thread 0 adds them to the open dump and,
+// when the code phase has reached the window end, emits the dump and runs
+// the loop update.  The loop update uses a vectoring CORDIC on the integer
+// dumps for the angles and only correctly rounded double operations
+// (contraction off) elsewhere, so the loop state is reproducible bit for bit.
+#include "gc_internal.h"
+#include "gc_device.h"
+
+namespace gc {
+
+namespace {
+
+constexpr int kThreads = 512;
+constexpr int kWaves = kThreads / 64;
+constexpr double kQ30 = 1073741824.0;
+
+__device__ __forceinline__ int64_t iabs64(int64_t v) { return v < 0 ? -v : v; }
+
+// atan2(y, x), x >= 0, in units of 2^-30 rad: scale the vector into
+// [2^39, 2^40), then rotate it towards the x axis by -+atan(2^-i).
+__device__ int64_t atan2_q30(int64_t y, int64_t x, const int64_t* tab) {
+    if (x == 0 && y == 0) return 0;
+    const int64_t hi = int64_t(1) << 40, lo = int64_t(1) << 39;
+    while (iabs64(x) >= hi || iabs64(y) >= hi) {
+        x >>= 1;
+        y >>= 1;
+    }
+    while (iabs64(x) < lo && iabs64(y) < lo) {
+        x *= 2;
+        y *= 2;
+    }
+    int64_t z = 0;
+    for (int i = 0; i < kCordicSteps; ++i) {
+        const int64_t xs = x >> i, ys = y >> i;
+        if (y > 0) {
+            x += ys;
+            y -= xs;
+            z += tab[i];
+        } else {
+            x -= ys;
+            y += xs;
+            z -= tab[i];
+        }
+    }
+    return z;
+}
+
+__device__ void loop_coef(double B, double z, double k, double& tau1, double& tau2) {
+#pragma clang fp contract(off)
+    const double wn = B * 8.0 * z / (4.0 * z * z + 1.0);
+    tau1 = k / (wn * wn);
+    tau2 = 2.0 * z / wn;
+}
+
+// Largest |wipe-off| of one sample of the format.
+__device__ __forceinline__ uint64_t max_w(int fmt) {
+    return fmt == GC_I8_REAL ? 128ull * GC_LUT_AMP
+                             : (fmt == GC_I2_REAL ? 3ull * GC_LUT_AMP : 128ull * kLutAbsSumMax);
+}
+
+// The code step keeps a window's sums inside int32.
+__device__ __forceinline__ bool step_ok(uint64_t dp, uint64_t W, int fmt) {
+    if (dp < 1 || dp >= (1ull << 31)) return false;
+    return ((W - 1) / dp + 1) * max_w(fmt) < (1ull << 31);
+}
+
+// Loop update at the close of a dump with sums d (E I, E Q, P I, P Q, L I,
+// L Q): new carrier and code steps; false when the code step leaves
+// 1 .. 2^31-1.
+__device__ bool loop_update(const TrackConsts& P, int int_periods, const int64_t* d,
+                            gc_loop_state& L, uint32_t& carr_step, uint64_t& code_step) {
+#pragma clang fp contract(off)
+    const double T = (double)int_periods * 1e-3;
+    double t1c, t2c, t1d, t2d;
+    loop_coef(P.pll_bw, P.pll_zeta, P.pll_k, t1c, t2c);
+    loop_coef(P.dll_bw, P.dll_zeta, P.dll_k, t1d, t2d);
+    const int64_t ie = d[0], qe = d[1], ip = d[2], qp = d[3], il = d[4], ql = d[5];
+    // PLL: atan(Q / I) in cycles
+    const int64_t a = ip >= 0 ? atan2_q30(qp, ip, P.tab) : atan2_q30(-qp, -ip, P.tab);
+    const double carr_err = ((double)a / kQ30) / (2.0 * M_PI);
+    // FLL: angle between consecutive prompts, the dot product's sign removed
+    if (L.have_prev) {
+        int64_t i0 = L.prompt_i_prev, q0 = L.prompt_q_prev, i1 = ip, q1 = qp;
+        const int64_t lim = int64_t(1) << 30;
+        while (iabs64(i0) >= lim || iabs64(q0) >= lim || iabs64(i1) >= lim || iabs64(q1) >= lim) {
+            i0 >>= 1;
+            q0 >>= 1;
+            i1 >>= 1;
+            q1 >>= 1;
+        }
+        const int64_t dot = i0 * i1 + q0 * q1;
+        const int64_t cross = i0 * q1 - q0 * i1;
+        const int64_t f = dot >= 0 ? atan2_q30(cross, dot, P.tab) : atan2_q30(-cross, -dot, P.tab);
+        const double f_err = ((double)f / kQ30) / (2.0 * M_PI * T);
+        L.fll_basis_hz = L.fll_basis_hz + (4.0 * P.fll_bw * T) * f_err;
+    }
+    L.prompt_i_prev = (int32_t)ip;
+    L.prompt_q_prev = (int32_t)qp;
+    L.have_prev = 1;
+    {
+        const double u1 = (t2c / t1c) * (carr_err - L.pll_err_prev);
+        const double u2 = carr_err * (T / t1c);
+        L.pll_nco_hz = L.pll_nco_hz + (u1 + u2);
+        L.pll_err_prev = carr_err;
+    }
+    L.carr_hz = L.fll_basis_hz + L.pll_nco_hz;
+    {
+        const double fe = (double)ie, ge = (double)qe, fl = (double)il, gl = (double)ql;
+        const double E = __builtin_sqrt(fe * fe + ge * ge), Lm = __builtin_sqrt(fl * fl + gl * gl);
+        const double code_err = (E + Lm) > 0.0 ? (E - Lm) / (E + Lm) : 0.0;
+        const double u1 = (t2d / t1d) * (code_err - L.dll_err_prev);
+        const double u2 = code_err * (T / t1d);
+        L.dll_nco_cps = L.dll_nco_cps + (u1 + u2);
+        L.dll_err_prev = code_err;
+    }
+    L.code_cps = 1.023e6 * (1.0 + (L.carr_hz - P.if_hz) / 1575.42e6) + L.dll_nco_cps;
+    const double cs = __builtin_rint(L.carr_hz / P.fs * 4294967296.0);
+    carr_step = (uint32_t)(uint64_t)(int64_t)cs;
+    const double ks = __builtin_rint(L.code_cps / P.fs * 4294967296.0);
+    if (!(ks >= 1.0) || !(ks < 2147483648.0)) return false;
+    code_step = (uint64_t)ks;
+    return true;
+}
+
+// Chip index of the code phase v (Q32 chips, may be below 0 by less than a
+// chip), modulo 1023.
+__device__ __forceinline__ int chip_of(int64_t v) {
+    const int64_t c = v >> 32;
+    return c < 0 ? (int)(c + kCodeLen) : (int)(c % kCodeLen);
+}
+
+// Control block of a channel, shared by the block's threads.
+struct Ctl {
+    uint64_t p, dp, s;
+    uint32_t phi, dphi;
+    uint32_t acc_n, nd;
+    int32_t status;
+    int32_t done;
+    int64_t acc[6];
+};
+
+template <int FMT>
+__global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ samples,
+                                                    uint64_t n, const DevChan* __restrict__ chans,
+                                                    gc_chan_state* __restrict__ states,
+                                                    gc_loop_state* __restrict__ loops,
+                                                    TrackConsts P, int32_t* __restrict__ rows,
+                                                    uint32_t* __restrict__ dump_n,
+                                                    uint32_t* __restrict__ n_dumps,
+                                                    int32_t* __restrict__ status,
+                                                    uint32_t max_dumps,
+                                                    const uint32_t* __restrict__ tables) {
+    __shared__ uint32_t s_lut[256];
+    __shared__ int8_t s_code[kCodeLen + 1];
+    __shared__ int32_t s_red[6][kWaves];
+    __shared__ Ctl ctl;
+    const int tid = threadIdx.x;
+    const int chn = blockIdx.x;
+    const DevChan& ch = chans[chn];
+    for (int i = tid; i < 256; i += kThreads) s_lut[i] = tables[kTabLut + i];
+    const uint32_t* sgn = tables + kTabSign + (ch.prn - 1) * kSignLen;
+    for (int i = tid; i < kCodeLen; i += kThreads) s_code[i] = (int8_t)(int16_t)(sgn[i] & 0xFFFF);
+    const uint64_t W = ch.window;
+    gc_chan_state* st = states + chn;
+    gc_loop_state L;   // thread 0's copy
+    if (tid == 0) {
+        ctl.status = GC_OK;
+        ctl.done = 0;
+        ctl.s = 0;
+        ctl.nd = 0;
+        ctl.p = st->code_phase;
+        ctl.dp = st->code_step;
+        ctl.phi = st->carr_phase;
+        ctl.dphi = st->carr_step;
+        ctl.acc_n = st->acc_n;
+        if (ch.n_taps != 3 || !ch.epl || ctl.p >= W) {
+            ctl.status = GC_EINVAL;
+        } else if (!step_ok(ctl.dp, W, FMT)) {
+            ctl.status = GC_ERANGE;
+        } else {
+            const int sl[3] = {ch.slot_e, ch.slot_p, ch.slot_l};
+            for (int k = 0; k < 3; ++k) {
+                ctl.acc[2 * k] = st->acc[sl[k]][0];
+                ctl.acc[2 * k + 1] = st->acc[sl[k]][1];
+            }
+            L = loops[chn];
+        }
+    }
+    __syncthreads();
+    if (ctl.status != GC_OK) {
+        if (tid == 0) {
+            status[chn] = ctl.status;
+            n_dumps[chn] = 0;
+        }
+        return;
+    }
+    const int64_t half = int64_t(1) << 31;
+    while (true) {
+        const uint64_t p = ctl.p, dp = ctl.dp, s0 = ctl.s;
+        const uint32_t phi = ctl.phi, dphi = ctl.dphi;
+        const uint64_t need = (W - p + dp - 1) / dp;     // samples until the phase reaches W
+        const uint64_t take = min(need, n - s0);
+        int32_t a[6] = {0, 0, 0, 0, 0, 0};
+        for (uint64_t i = tid; i < take; i += kThreads) {
+            int xi, xq;
+            load_sample<FMT>(samples, s0 + i, xi, xq);
+            int c, sn;
+            lut_cs(s_lut[(phi + (uint32_t)i * dphi) >> 24], c, sn);
+            int wi, wq;
+            wipe<FMT>(xi, xq, c, sn, wi, wq);
+            const int64_t u = (int64_t)(p + i * dp);
+            const int re = s_code[chip_of(u + half)];
+            const int rp = s_code[chip_of(u)];
+            const int rl = s_code[chip_of(u - half)];
+            a[0] += wi * re;
+            a[1] += wq * re;
+            a[2] += wi * rp;
+            a[3] += wq * rp;
+            a[4] += wi * rl;
+            a[5] += wq * rl;
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const int t = wave_total_dpp(a[k]);
+            if ((tid & 63) == 63) s_red[k][tid >> 6] = t;
+        }
+        __syncthreads();
+        if (tid == 0) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                int64_t t = 0;
+                for (int w = 0; w < kWaves; ++w) t += s_red[k][w];
+                ctl.acc[k] += t;
+            }
+            ctl.acc_n += (uint32_t)take;
+            ctl.phi = phi + (uint32_t)take * dphi;
+            ctl.p = p + take * dp;
+            ctl.s = s0 + take;
+            if (ctl.p >= W) {  // the dump closes
+                if (ctl.nd >= max_dumps) {
+                    ctl.status = GC_ENOSPC;
+                } else {
+                    int32_t* r = rows + ((uint64_t)chn * max_dumps + ctl.nd) * 8;
+                    for (int k = 0; k < 6; ++k) r[k] = (int32_t)ctl.acc[k];
+                    r[6] = (int32_t)ctl.dphi;
+                    r[7] = (int32_t)(uint32_t)ctl.dp;
+                    dump_n[(uint64_t)chn * max_dumps + ctl.nd] = ctl.acc_n;
+                    ctl.nd += 1;
+                    uint32_t ncs;
+                    uint64_t nks;
+                    if (!loop_update(P, ch.int_periods, ctl.acc, L, ncs, nks) ||
+                        !step_ok(nks, W, FMT)) {
+                        ctl.status = GC_ERANGE;
+                    } else {
+                        ctl.dphi = ncs;
+                        ctl.dp = nks;
+                    }
+                    for (int k = 0; k < 6; ++k) ctl.acc[k] = 0;
+                    ctl.acc_n = 0;
+                    ctl.p -= W;
+                }
+            }
+            ctl.done = ctl.status != GC_OK || (ctl.s >= n && ctl.p < W);
+        }
+        __syncthreads();
+        if (ctl.done) break;
+    }
+    if (tid == 0) {
+        status[chn] = ctl.status;
+        if (ctl.status == GC_OK) {
+            n_dumps[chn] = ctl.nd;
+            st->code_phase = ctl.p;
+            st->code_step = ctl.dp;
+            st->carr_phase = ctl.phi;
+            st->carr_step = ctl.dphi;
+            st->acc_n = ctl.acc_n;
+            const int sl[3] = {ch.slot_e, ch.slot_p, ch.slot_l};
+            for (int k = 0; k < 3; ++k) {
+                st->acc[sl[k]][0] = (int32_t)ctl.acc[2 * k];
+                st->acc[sl[k]][1] = (int32_t)ctl.acc[2 * k + 1];
+            }
+            loops[chn] = L;
+        } else {
+            n_dumps[chn] = 0;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_track(const uint8_t* samples, uint64_t n, int fmt, const DevChan* chans,
+                        gc_chan_state* state, gc_loop_state* loop, const TrackConsts& consts,
+                        int n_chan, int32_t* rows, uint32_t* dump_n, uint32_t* n_dumps,
+                        int32_t* status, uint32_t max_dumps, const uint32_t* tables,
+                        hipStream_t s) {
+#define GC_T(F)                                                                             \
+    hipLaunchKernelGGL((k_track<F>), dim3(n_chan), dim3(kThreads), 0, s, samples, n, chans, \
+                       state, loop, consts, rows, dump_n, n_dumps, status, max_dumps, tables)
+    if (fmt == GC_I8_REAL) GC_T(GC_I8_REAL);
+    else if (fmt == GC_I8_IQ) GC_T(GC_I8_IQ);
+    else if (fmt == GC_I2_REAL) GC_T(GC_I2_REAL);
+    else return hipErrorInvalidValue;
+#undef GC_T
+    return hipGetLastError();
+}
+
+}  // namespace gc

@@ -41,6 +41,14 @@ SERVER_TIMING = np.dtype([("launches", "<u8"), ("launched_requests", "<u8"),
                           ("submit_max_ms", "<f8")])
 assert CHAN_CFG.itemsize == 1040 and CHAN_STATE.itemsize == 2096 and RX_DESC.itemsize == 24
 assert SERVER_TIMING.itemsize == 56
+LOOP_PARAMS = np.dtype([("fs_hz", "<f8"), ("if_hz", "<f8"), ("dll_bw_hz", "<f8"),
+                        ("dll_zeta", "<f8"), ("dll_gain", "<f8"), ("pll_bw_hz", "<f8"),
+                        ("pll_zeta", "<f8"), ("pll_gain", "<f8"), ("fll_bw_hz", "<f8")])
+LOOP_STATE = np.dtype([("carr_hz", "<f8"), ("code_cps", "<f8"), ("fll_basis_hz", "<f8"),
+                       ("pll_nco_hz", "<f8"), ("pll_err_prev", "<f8"), ("dll_nco_cps", "<f8"),
+                       ("dll_err_prev", "<f8"), ("prompt_i_prev", "<i4"),
+                       ("prompt_q_prev", "<i4"), ("have_prev", "<i4"), ("reserved", "<i4")])
+assert LOOP_PARAMS.itemsize == 72 and LOOP_STATE.itemsize == 72
 
 
 class GcError(RuntimeError):
@@ -85,6 +93,8 @@ def _load():
         "gc_server_info": ([P, P, P, P, P, P, P], I32),
         "gc_server_destroy": ([P], I32),
         "gc_server_stats": ([P, P], I32),
+        "gc_loop_init": ([D, D, P], I32),
+        "gc_track": ([P, P, U64, P, P, P, P, P, P, P, U32, P], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -100,7 +110,8 @@ EXPORTED = ("gc_strerror", "gc_version", "gc_create", "gc_destroy", "gc_nco_init
             "gc_batch_create", "gc_batch_configure", "gc_batch_tune", "gc_batch_launch",
             "gc_batch_info", "gc_batch_destroy", "gc_server_create", "gc_server_open_rx",
             "gc_server_submit", "gc_server_hold", "gc_server_poll", "gc_server_result", "gc_server_state",
-            "gc_server_info", "gc_server_destroy", "gc_server_stats")
+            "gc_server_info", "gc_server_destroy", "gc_server_stats", "gc_loop_init",
+            "gc_track")
 
 
 def _check(rc: int, where: str):
@@ -314,6 +325,28 @@ def gc_server_stats(server: int) -> dict:
 
 def gc_server_destroy(server: int) -> None:
     _check(_lib.gc_server_destroy(server), "gc_server_destroy")
+
+
+def loop_params(fs_hz, if_hz, dll_bw_hz=2.0, dll_zeta=0.7, dll_gain=1.0, pll_bw_hz=25.0,
+                pll_zeta=0.7, pll_gain=0.25, fll_bw_hz=10.0) -> np.ndarray:
+    p = np.zeros(1, LOOP_PARAMS)
+    p[0] = (fs_hz, if_hz, dll_bw_hz, dll_zeta, dll_gain, pll_bw_hz, pll_zeta, pll_gain, fll_bw_hz)
+    return p
+
+
+def gc_loop_init(carr_hz: float, code_cps: float) -> np.ndarray:
+    st = np.zeros(1, LOOP_STATE)
+    _check(_lib.gc_loop_init(carr_hz, code_cps, st.ctypes.data), "gc_loop_init")
+    return st[0]
+
+
+def gc_track(plan: int, samples, n_samples: int, params: np.ndarray, state, loop, rows, dump_n,
+             n_dumps, status, max_dumps: int, stream=None) -> int:
+    """Enqueue closed-loop tracking of one block; returns the gc_status of the call."""
+    params = np.ascontiguousarray(params, dtype=LOOP_PARAMS)
+    return _lib.gc_track(plan, _ptr(samples), n_samples, params.ctypes.data, _ptr(state),
+                         _ptr(loop), _ptr(rows), _ptr(dump_n), _ptr(n_dumps), _ptr(status),
+                         max_dumps, _stream_ptr(stream))
 
 
 def _stream_ptr(stream):

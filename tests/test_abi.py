@@ -53,6 +53,9 @@ int main(void) {
          offsetof(gc_rx_desc, fmt), offsetof(gc_rx_desc, reserved));
   printf("%zu %zu %zu\n", sizeof(gc_server_timing), offsetof(gc_server_timing, enqueue_mean_ms),
          offsetof(gc_server_timing, submit_max_ms));
+  printf("%zu %zu %zu %zu %zu\n", sizeof(gc_loop_params), offsetof(gc_loop_params, fll_bw_hz),
+         sizeof(gc_loop_state), offsetof(gc_loop_state, prompt_i_prev),
+         offsetof(gc_loop_state, have_prev));
   return 0;
 }
 ''')
@@ -66,7 +69,10 @@ int main(void) {
                     rx.itemsize, rx.fields["n_samples"][1], rx.fields["fmt"][1],
                     rx.fields["reserved"][1], gnsscorr.SERVER_TIMING.itemsize,
                     gnsscorr.SERVER_TIMING.fields["enqueue_mean_ms"][1],
-                    gnsscorr.SERVER_TIMING.fields["submit_max_ms"][1]]
+                    gnsscorr.SERVER_TIMING.fields["submit_max_ms"][1],
+                    gnsscorr.LOOP_PARAMS.itemsize, gnsscorr.LOOP_PARAMS.fields["fll_bw_hz"][1],
+                    gnsscorr.LOOP_STATE.itemsize, gnsscorr.LOOP_STATE.fields["prompt_i_prev"][1],
+                    gnsscorr.LOOP_STATE.fields["have_prev"][1]]
 
 
 def test_host_validation_without_a_device():
@@ -86,6 +92,11 @@ def test_host_validation_without_a_device():
     assert g._lib.gc_server_result(None, 1, None, None, None, None, None) == g.GC_EINVAL
     assert g._lib.gc_server_destroy(None) == g.GC_EINVAL
     assert g._lib.gc_server_stats(None, None) == g.GC_EINVAL
+    assert g._lib.gc_loop_init(1.0, 1.0, None) == g.GC_EINVAL
+    assert g._lib.gc_track(None, None, 0, None, None, None, None, None, None, None, 1,
+                           None) == g.GC_EINVAL
+    ls = g.gc_loop_init(4.0e6, 1.023e6)
+    assert ls["carr_hz"] == 4.0e6 and ls["fll_basis_hz"] == 4.0e6 and ls["have_prev"] == 0
     assert g.gc_version() == (1, 0)
     for s in (0, -1, -2, -3, -4, -5, -6, -7):
         assert len(g.gc_strerror(s)) > 0
