@@ -70,6 +70,10 @@ WORKLOADS = {
         describe="256 channels x 128 taps (-2 + k/32 chips), complex int8, fs 20.46 MHz, IF 0, "
                  "%g s, 1 ms dumps", seconds=2.0, ops=14, fmt_name="i8_iq",
         cpu_seconds=0.05),
+    "tracking": dict(
+        describe="12 channels, 2-bit real, fs 16.368 MHz, IF 4.092 MHz, %g s, 1 ms dumps, E/P/L at "
+                 "+-1/2 chip, closed DLL/PLL/FLL loops started 30 Hz and 0.1 chip off",
+        seconds=10.0, ops=6, fmt_name="i2_real", cpu_seconds=1.0),
     "serving": dict(
         describe="500 receivers x 4-14 channels (fs 4.092/8.184/16.368 MHz, IF fs/4, int8 or "
                  "2-bit real, 1/4/20 ms dumps, E/P/L at +-1/2 chip), Poisson arrivals at 2000 "
@@ -588,6 +592,107 @@ def main_serving(args, wl, seconds):
     print(json.dumps(res), flush=True)
 
 
+def main_tracking(args, wl, seconds, cpu_seconds):
+    """Workload "tracking": the 12-channel stream with the loops closed after
+    every dump (gc_track), each step from the same initial NCO and loop
+    states (started 30 Hz and 0.1 chip off the true values)."""
+    import torch
+
+    from paper_1907_00463_amd import gnsscorr as g
+    from paper_1907_00463_amd import synth
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    print("bench: generating %.3f s of the tracking workload" % seconds, file=sys.stderr,
+          flush=True)
+    st, chans, rng = synth.workload_twelve_channels(seconds=seconds)
+    buf = synth.synth_samples(st, rng)
+    n = st.n
+    cfgs = np.zeros(len(chans), g.CHAN_CFG)
+    states = np.zeros(len(chans), g.CHAN_STATE)
+    loops = np.zeros(len(chans), g.LOOP_STATE)
+    for i, ch in enumerate(chans):
+        cfgs[i] = g.make_cfg(ch.prn, synth.taps_to_q32(ch.taps_chips), ch.int_periods)
+        states[i] = g.gc_nco_init(st.fs, ch.carr_hz + 30.0, ch.carr_phase0, ch.code_rate,
+                                  ch.code_phase0 + 0.1, ch.int_periods)
+        loops[i] = g.gc_loop_init(ch.carr_hz + 30.0, ch.code_rate)
+    params = g.loop_params(st.fs, st.if_hz)
+    ctx = g.gc_create(0)
+    plan = g.Plan(ctx, st.fmt, g.GC_CARRIER_LUT, cfgs)
+    samples = torch.from_numpy(buf).to(dev)
+    s0 = plan.states_to_device(states)
+    l0 = torch.from_numpy(loops.view(np.uint8).copy()).to(dev)
+    s1, l1 = s0.clone(), l0.clone()
+    max_dumps = int(seconds * 1000) + 2
+    rows = torch.zeros((len(chans), max_dumps, 8), dtype=torch.int32, device=dev)
+    dn = torch.zeros((len(chans), max_dumps), dtype=torch.int32, device=dev)
+    nd = torch.zeros(len(chans), dtype=torch.int32, device=dev)
+    stt = torch.zeros(len(chans), dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def step():
+        s1.copy_(s0)
+        l1.copy_(l0)
+        rc = g.gc_track(plan.handle, samples, n, params, s1, l1, rows, dn, nd, stt, max_dumps,
+                        stream)
+        assert rc == g.GC_OK
+
+    dt = time_steps(torch, step, args.steps, args.warmup)
+    assert int(stt.abs().sum()) == 0, "channel refused"
+    lf = l1.cpu().numpy().view(g.LOOP_STATE)
+    carr_err = [float(lf[i]["carr_hz"]) - ch.carr_hz for i, ch in enumerate(chans)]
+    sample_taps = n * 3 * len(chans)
+    achieved = wl["ops"] * n * len(chans) / dt / 1e12
+    res = {
+        "metric": METRIC, "value": round(sample_taps / dt / 1e9, 3), "unit": "G sample·taps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": wl["describe"] % seconds, "channels": len(chans), "samples": n,
+                   "format": wl["fmt_name"], "kernels": "track",
+                   "dumps_per_channel": int(nd.cpu().numpy().max()),
+                   "realtime_channels": round(realtime_channels(len(chans), n / st.fs, dt), 1),
+                   "final_carrier_error_hz_max": round(max(abs(e) for e in carr_err), 3)},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 4),
+                     "peak": round(VALU_PEAK_TOPS, 2), "unit": "T lane-ops/s",
+                     "frac": round(achieved / VALU_PEAK_TOPS, 5), "traffic": None,
+                     "kernel_ms": round(dt * 1e3, 4),
+                     "note": "one block per channel walks the dumps in order (each dump's NCO "
+                             "steps come from the previous dump's loop update): 12 of 256 "
+                             "compute units, latency bound"},
+    }
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline", file=sys.stderr, flush=True)
+        from concurrent.futures import ThreadPoolExecutor
+
+        import oracle
+        m = min(n, int(round(cpu_seconds * st.fs)) // 4 * 4)
+        op = oracle.LoopParams(fs=st.fs, if_hz=st.if_hz)
+
+        def one(i):
+            s_ = states[i]
+            w = oracle.OracleState(int(s_["carr_phase"]), int(s_["carr_step"]),
+                                   int(s_["code_phase"]), int(s_["code_step"]), 3)
+            ts = oracle.track_state(w, float(loops[i]["carr_hz"]), float(loops[i]["code_cps"]))
+            oracle.track(st.fmt, buf, m, int(cfgs[i]["prn"]), 1, op, ts)
+
+        threads = min(len(chans), host_threads())
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            list(ex.map(one, range(len(chans))))
+        dtc = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": m * 3 * len(chans) / dtc / 1e9,
+                               "unit": "G sample·taps/s", "cores": threads, "kind": "oracle",
+                               "host": host_cpu(),
+                               "sample": "first %.3f s of the same stream, all 12 channels, "
+                                         "threads over channels; %.2f s wall; real-time "
+                                         "channels %.1f" % (m / st.fs, dtc,
+                                                            realtime_channels(12, m / st.fs, dtc))}
+    plan.close()
+    g.gc_destroy(ctx)
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -618,6 +723,8 @@ def main():
         return main_batched(args, wl, seconds, cpu_seconds)
     if args.workload == "serving":
         return main_serving(args, wl, seconds)
+    if args.workload == "tracking":
+        return main_tracking(args, wl, seconds, cpu_seconds)
 
     import torch
 

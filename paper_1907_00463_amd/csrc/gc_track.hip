@@ -18,7 +18,7 @@ namespace gc {
 
 namespace {
 
-constexpr int kThreads = 512;
+constexpr int kThreads = 1024;
 constexpr int kWaves = kThreads / 64;
 constexpr double kQ30 = 1073741824.0;
 
@@ -26,16 +26,33 @@ __device__ __forceinline__ int64_t iabs64(int64_t v) { return v < 0 ? -v : v; }
 
 // atan2(y, x), x >= 0, in units of 2^-30 rad: scale the vector into
 // [2^39, 2^40), then rotate it towards the x axis by -+atan(2^-i).
+__device__ __forceinline__ int bitlen64(uint64_t m) { return m ? 64 - __builtin_clzll(m) : 0; }
+
 __device__ int64_t atan2_q30(int64_t y, int64_t x, const int64_t* tab) {
     if (x == 0 && y == 0) return 0;
-    const int64_t hi = int64_t(1) << 40, lo = int64_t(1) << 39;
-    while (iabs64(x) >= hi || iabs64(y) >= hi) {
-        x >>= 1;
-        y >>= 1;
+    const int64_t hi = int64_t(1) << 40;
+    // halving while a magnitude is >= 2^40: one shift that cannot overshoot
+    // (arithmetic shifts compose), then the last one or two steps
+    {
+        const uint64_t m = (uint64_t)max(iabs64(x), iabs64(y));
+        const int s = bitlen64(m) - 42;
+        if (s > 0) {
+            x >>= s;
+            y >>= s;
+        }
+        while (iabs64(x) >= hi || iabs64(y) >= hi) {
+            x >>= 1;
+            y >>= 1;
+        }
     }
-    while (iabs64(x) < lo && iabs64(y) < lo) {
-        x *= 2;
-        y *= 2;
+    // doubling while both magnitudes are below 2^39 is one exact shift
+    {
+        const uint64_t m = (uint64_t)max(iabs64(x), iabs64(y));
+        const int s = 40 - bitlen64(m);
+        if (s > 0) {
+            x *= int64_t(1) << s;
+            y *= int64_t(1) << s;
+        }
     }
     int64_t z = 0;
     for (int i = 0; i < kCordicSteps; ++i) {
@@ -75,13 +92,14 @@ __device__ __forceinline__ bool step_ok(uint64_t dp, uint64_t W, int fmt) {
 // Loop update at the close of a dump with sums d (E I, E Q, P I, P Q, L I,
 // L Q): new carrier and code steps; false when the code step leaves
 // 1 .. 2^31-1.
-__device__ bool loop_update(const TrackConsts& P, int int_periods, const int64_t* d,
+struct Coefs {
+    double T, t1c, t2c, t1d, t2d;
+};
+
+__device__ bool loop_update(const TrackConsts& P, const Coefs& K, const int64_t* d,
                             gc_loop_state& L, uint32_t& carr_step, uint64_t& code_step) {
 #pragma clang fp contract(off)
-    const double T = (double)int_periods * 1e-3;
-    double t1c, t2c, t1d, t2d;
-    loop_coef(P.pll_bw, P.pll_zeta, P.pll_k, t1c, t2c);
-    loop_coef(P.dll_bw, P.dll_zeta, P.dll_k, t1d, t2d);
+    const double T = K.T, t1c = K.t1c, t2c = K.t2c, t1d = K.t1d, t2d = K.t2d;
     const int64_t ie = d[0], qe = d[1], ip = d[2], qp = d[3], il = d[4], ql = d[5];
     // PLL: atan(Q / I) in cycles
     const int64_t a = ip >= 0 ? atan2_q30(qp, ip, P.tab) : atan2_q30(-qp, -ip, P.tab);
@@ -130,12 +148,7 @@ __device__ bool loop_update(const TrackConsts& P, int int_periods, const int64_t
     return true;
 }
 
-// Chip index of the code phase v (Q32 chips, may be below 0 by less than a
-// chip), modulo 1023.
-__device__ __forceinline__ int chip_of(int64_t v) {
-    const int64_t c = v >> 32;
-    return c < 0 ? (int)(c + kCodeLen) : (int)(c % kCodeLen);
-}
+
 
 // Control block of a channel, shared by the block's threads.
 struct Ctl {
@@ -171,7 +184,11 @@ __global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ 
     const uint64_t W = ch.window;
     gc_chan_state* st = states + chn;
     gc_loop_state L;   // thread 0's copy
+    Coefs K;
     if (tid == 0) {
+        K.T = (double)ch.int_periods * 1e-3;
+        loop_coef(P.pll_bw, P.pll_zeta, P.pll_k, K.t1c, K.t2c);
+        loop_coef(P.dll_bw, P.dll_zeta, P.dll_k, K.t1d, K.t2d);
         ctl.status = GC_OK;
         ctl.done = 0;
         ctl.s = 0;
@@ -202,7 +219,6 @@ __global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ 
         }
         return;
     }
-    const int64_t half = int64_t(1) << 31;
     while (true) {
         const uint64_t p = ctl.p, dp = ctl.dp, s0 = ctl.s;
         const uint32_t phi = ctl.phi, dphi = ctl.dphi;
@@ -216,10 +232,17 @@ __global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ 
             lut_cs(s_lut[(phi + (uint32_t)i * dphi) >> 24], c, sn);
             int wi, wq;
             wipe<FMT>(xi, xq, c, sn, wi, wq);
-            const int64_t u = (int64_t)(p + i * dp);
-            const int re = s_code[chip_of(u + half)];
-            const int rp = s_code[chip_of(u)];
-            const int rl = s_code[chip_of(u - half)];
+            // prompt chip floor(u / 2^32) mod 1023; the early (late) chip is
+            // the next (previous) one when u's fraction is at or above
+            // (below) one half chip
+            const uint64_t u = p + i * dp;
+            const uint32_t cp = (uint32_t)((u >> 32) % kCodeLen);
+            const bool upper = (uint32_t)u >= (1u << 31);
+            const uint32_t ce = upper ? (cp + 1 == kCodeLen ? 0u : cp + 1) : cp;
+            const uint32_t cl = upper ? cp : (cp == 0 ? kCodeLen - 1 : cp - 1);
+            const int re = s_code[ce];
+            const int rp = s_code[cp];
+            const int rl = s_code[cl];
             a[0] += wi * re;
             a[1] += wq * re;
             a[2] += wi * rp;
@@ -256,7 +279,7 @@ __global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ 
                     ctl.nd += 1;
                     uint32_t ncs;
                     uint64_t nks;
-                    if (!loop_update(P, ch.int_periods, ctl.acc, L, ncs, nks) ||
+                    if (!loop_update(P, K, ctl.acc, L, ncs, nks) ||
                         !step_ok(nks, W, FMT)) {
                         ctl.status = GC_ERANGE;
                     } else {
