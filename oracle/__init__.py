@@ -13,4 +13,5 @@ from .oracle import (  # noqa: F401
     build, ca_bits, ca_code, g2_bits, g2i_bits, lut, nco_words,
     correlate_lut, correlate_f64, advance_words,
     LoopParams, TrackState, track_state, cordic_table, cordic_atan2, loop_coefficients, track,
+    lock_metrics,
 )

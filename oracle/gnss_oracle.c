@@ -647,3 +647,80 @@ int orc_track(int fmt, const uint8_t* buf, uint64_t n_samples, int prn, int int_
     *n_dumps = nd;
     return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Lock metrics and bit synchronisation over a channel's closed dumps       */
+/* (the Channel Health indicators of Sec. 3.6 and the 20-period navigation */
+/* bits of Sec. 3.1).  prompt[k] = (I_k, Q_k) of dump k, k = 0 .. n-1.       */
+/*                                                                          */
+/* C/N0 per window of K consecutive dumps, by the moments (M2M4) estimator  */
+/* of Pauluzzi and Beaulieu (2000): with P_k = I_k^2 + Q_k^2,               */
+/*   M2 = mean P_k,  M4 = mean P_k^2,  A = sqrt(2 M2^2 - M4) (signal power), */
+/*   SNR = A / (M2 - A),  C/N0 = 10 log10(SNR / T)  (dB-Hz, T in seconds);  */
+/* a window whose 2 M2^2 - M4 <= 0 or M2 - A <= 0 gets NaN.                  */
+/* Carrier lock ratio per window, the estimate of cos(2 phase error):       */
+/*   sum (I_k^2 - Q_k^2) / sum (I_k^2 + Q_k^2)  (0 for an all-zero window). */
+/* A window is a lock failure when its ratio is below lock_min.             */
+/* Bit edge: for each k >= 1 whose prompt I changes sign from dump k-1 to    */
+/* k (zero counts as positive), position (k + phase) mod 20 gets one count; */
+/* the edge is the position with the most counts (the lowest on ties).      */
+/* With the edge e, bit j sums I over dumps k with (k + phase - e) mod 20    */
+/* = 0 .. 19 of the j-th whole period after the edge, and is 1 when the sum */
+/* is negative (logic 1 -> -1, as for the code chips).                      */
+/* ------------------------------------------------------------------------ */
+int orc_lock_metrics(const int32_t* prompt, uint32_t n, uint32_t K, double T, double lock_min,
+                     uint32_t phase, double* cn0, double* lock, uint32_t* n_windows,
+                     uint32_t* lock_fails, uint32_t* hist, uint32_t* edge, uint8_t* bits,
+                     uint32_t max_bits, uint32_t* n_bits)
+{
+    if (!prompt && n) return ORC_EINVAL;
+    if (K < 2 || !(T > 0.0) || !n_windows || !lock_fails || !hist || !edge || !n_bits)
+        return ORC_EINVAL;
+    const uint32_t nw = n / K;
+    uint32_t fails = 0;
+    for (uint32_t w = 0; w < nw; ++w) {
+        double m2 = 0.0, m4 = 0.0, ii = 0.0, qq = 0.0;
+        for (uint32_t k = w * K; k < (w + 1) * K; ++k) {
+            const double i = (double)prompt[2 * k], q = (double)prompt[2 * k + 1];
+            const double p = i * i + q * q;
+            m2 += p;
+            m4 += p * p;
+            ii += i * i;
+            qq += q * q;
+        }
+        m2 = m2 / (double)K;
+        m4 = m4 / (double)K;
+        const double d = 2.0 * m2 * m2 - m4;
+        double c = NAN;
+        if (d > 0.0) {
+            const double a = sqrt(d);
+            if (m2 - a > 0.0) c = 10.0 * log10((a / (m2 - a)) / T);
+        }
+        const double r = (ii + qq) > 0.0 ? (ii - qq) / (ii + qq) : 0.0;
+        if (cn0) cn0[w] = c;
+        if (lock) lock[w] = r;
+        if (r < lock_min) ++fails;
+    }
+    *n_windows = nw;
+    *lock_fails = fails;
+    for (int j = 0; j < 20; ++j) hist[j] = 0;
+    for (uint32_t k = 1; k < n; ++k) {
+        const int a = prompt[2 * (k - 1)] < 0, b = prompt[2 * k] < 0;
+        if (a != b) hist[(k + phase) % 20] += 1;
+    }
+    uint32_t e = 0;
+    for (uint32_t j = 1; j < 20; ++j)
+        if (hist[j] > hist[e]) e = j;
+    *edge = e;
+    /* first dump of the first whole bit: smallest k with (k + phase) % 20 == e */
+    const uint32_t k0 = (e + 20 - phase % 20) % 20;
+    uint32_t nb = 0;
+    for (uint64_t k = k0; k + 20 <= n; k += 20) {
+        int64_t s = 0;
+        for (uint32_t t = 0; t < 20; ++t) s += prompt[2 * (k + t)];
+        if (nb < max_bits && bits) bits[nb] = (uint8_t)(s < 0);
+        ++nb;
+    }
+    *n_bits = nb < max_bits ? nb : max_bits;
+    return ORC_OK;
+}

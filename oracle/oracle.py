@@ -61,6 +61,8 @@ def _load():
         lib.orc_loop_coefficients.argtypes = [C.c_double, C.c_double, C.c_double, P]
         lib.orc_track.argtypes = [C.c_int, P, C.c_uint64, C.c_int, C.c_int, P, P, P, P, P, P, P,
                                   P, P, P, P, C.c_uint32, P]
+        lib.orc_lock_metrics.argtypes = [P, C.c_uint32, C.c_uint32, C.c_double, C.c_double,
+                                         C.c_uint32, P, P, P, P, P, P, P, C.c_uint32, P]
         _lib = lib
     return _lib
 
@@ -295,3 +297,30 @@ def track(fmt, buf, n, prn, T, params: LoopParams, st: TrackState):
     st.ls, st.is_ = ls, is_
     d = int(nd[0])
     return rows[:d], dump_n[:d]
+
+
+def lock_metrics(prompt, K=20, T=1e-3, lock_min=0.5, phase=0):
+    """C/N0 (dB-Hz) and lock ratio per window of K dumps, lock failures, the
+    20-position bit-transition histogram, the bit edge and the navigation
+    bits, from prompts int32 [n, 2] (I, Q) of consecutive dumps; ``phase``
+    is the position of dump 0 in the 20-dump cycle."""
+    lib = _load()
+    prompt = np.ascontiguousarray(prompt, dtype=np.int32).reshape(-1, 2)
+    n = len(prompt)
+    nw_max = max(1, n // K)
+    cn0 = np.zeros(nw_max, np.float64)
+    lock = np.zeros(nw_max, np.float64)
+    nw = np.zeros(1, np.uint32)
+    fails = np.zeros(1, np.uint32)
+    hist = np.zeros(20, np.uint32)
+    edge = np.zeros(1, np.uint32)
+    max_bits = n // 20 + 1
+    bits = np.zeros(max_bits, np.uint8)
+    nb = np.zeros(1, np.uint32)
+    rc = lib.orc_lock_metrics(_p(prompt), n, K, T, lock_min, phase, _p(cn0), _p(lock), _p(nw),
+                              _p(fails), _p(hist), _p(edge), _p(bits), max_bits, _p(nb))
+    if rc:
+        raise ValueError("bad lock-metric arguments")
+    w = int(nw[0])
+    return {"cn0": cn0[:w], "lock": lock[:w], "lock_fails": int(fails[0]), "hist": hist,
+            "edge": int(edge[0]), "bits": bits[:int(nb[0])]}
