@@ -307,6 +307,55 @@ gc_status gc_track(gc_plan* plan, const void* samples, uint64_t n_samples,
                    uint32_t max_dumps, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Lock metrics and bit synchronisation (Sec. 3.6, channel health; Sec. 3.1,
+ * 20 code periods per navigation bit), over the closed dumps of channels.
+ *
+ * Channel c's dump k has its prompt I and Q at
+ *   rows[(c * max_dumps + k) * row_stride + prompt_col]  and  [... + 1],
+ * k = 0 .. min(n_dumps[c], max_dumps) - 1, one code period per dump (so
+ * gc_track's rows with row_stride 8, prompt_col 2, or gc_correlate's out with
+ * row_stride 2 * tap_stride and prompt_col 2 * the prompt tap).
+ *
+ * C/N0 per window of `window` consecutive dumps by the moments (M2M4)
+ * estimator: with P = I^2 + Q^2, M2 = mean P, M4 = mean P^2, A = sqrt(2 M2^2
+ * - M4), C/N0 = 10 log10(A / (M2 - A) / dump_s) dB-Hz, NaN where 2 M2^2 - M4
+ * <= 0 or M2 <= A.  Carrier lock ratio per window (the estimate of cos 2x
+ * the phase error): sum(I^2 - Q^2) / sum(I^2 + Q^2), 0 for an all-zero
+ * window; a window below lock_min counts as a lock failure.  Bit edge: each
+ * sign change of prompt I from dump k-1 to dump k (zero counts as positive)
+ * adds one to histogram position (k + phase[c]) mod 20; the edge is the
+ * position with the most counts, the lowest on ties.  Bit j sums I over the
+ * 20 dumps of the j-th whole period that starts at an edge position and is
+ * 1 when the sum is negative.
+ *
+ *   rows, n_dumps         device, as above
+ *   phase                 device, uint32 [n_chan], position of dump 0 in the
+ *                         20-dump cycle, or NULL for 0
+ *   cn0, lock             device, double [n_chan][max_windows] (may be NULL
+ *                         when max_windows is 0)
+ *   n_windows             device, uint32 [n_chan]: windows written,
+ *                         min(n / window, max_windows)
+ *   lock_fails            device, uint32 [n_chan]: failures over all n /
+ *                         window windows
+ *   hist                  device, uint32 [n_chan][20]
+ *   edge                  device, uint32 [n_chan]
+ *   bits                  device, uint8 [n_chan][max_bits] (0 or 1)
+ *   n_bits                device, uint32 [n_chan]: bits written (at most
+ *                         max_bits)
+ * Sums are fp64 in dump order, so results match a sequential double
+ * evaluation exactly apart from the last bits of log10.  Errors: GC_EINVAL
+ * (null pointers, n_chan outside 1 .. GC_MAX_CHANNELS, window < 2, dump_s
+ * <= 0, prompt_col + 1 >= row_stride), GC_EDEVICE.
+ * ------------------------------------------------------------------------ */
+gc_status gc_lock_metrics(gc_ctx* ctx, const int32_t* rows, int32_t row_stride,
+                          int32_t prompt_col, const uint32_t* n_dumps, int32_t n_chan,
+                          uint32_t max_dumps, uint32_t window, double dump_s, double lock_min,
+                          const uint32_t* phase, double* cn0, double* lock, uint32_t max_windows,
+                          uint32_t* n_windows, uint32_t* lock_fails, uint32_t* hist,
+                          uint32_t* edge, uint8_t* bits, uint32_t max_bits, uint32_t* n_bits,
+                          void* stream);
+
+/* ------------------------------------------------------------------------
  * Batches: many receivers in one persistent launch.
  *
  * A batch binds the sample blocks of n_rx receivers (each with its own

@@ -166,6 +166,12 @@ hipError_t launch_epl(const uint8_t* samples, uint64_t n_samples, int fmt, const
                       int tap_stride, uint32_t max_dumps, const uint32_t* d_tables, int grid,
                       hipStream_t s);
 int epl_blocks_per_device(int device);
+hipError_t launch_lock_metrics(const int32_t* rows, int stride, int col, const uint32_t* n_dumps,
+                               int n_chan, uint32_t max_dumps, uint32_t K, double T,
+                               double lock_min, const uint32_t* phase, double* cn0, double* lock,
+                               uint32_t max_windows, uint32_t* n_windows, uint32_t* lock_fails,
+                               uint32_t* hist, uint32_t* edge, uint8_t* bits, uint32_t max_bits,
+                               uint32_t* n_bits, hipStream_t s);
 hipError_t launch_track(const uint8_t* samples, uint64_t n, int fmt, const DevChan* chans,
                         gc_chan_state* state, gc_loop_state* loop, const TrackConsts& consts,
                         int n_chan, int32_t* rows, uint32_t* dump_n, uint32_t* n_dumps,

@@ -349,6 +349,27 @@ gc_status gc_track(gc_plan* plan, const void* samples, uint64_t n_samples,
                                      max_dumps, plan->ctx->d_tables, (hipStream_t)stream));
 }
 
+gc_status gc_lock_metrics(gc_ctx* ctx, const int32_t* rows, int32_t row_stride,
+                          int32_t prompt_col, const uint32_t* n_dumps, int32_t n_chan,
+                          uint32_t max_dumps, uint32_t window, double dump_s, double lock_min,
+                          const uint32_t* phase, double* cn0, double* lock, uint32_t max_windows,
+                          uint32_t* n_windows, uint32_t* lock_fails, uint32_t* hist,
+                          uint32_t* edge, uint8_t* bits, uint32_t max_bits, uint32_t* n_bits,
+                          void* stream) {
+    if (!ctx || !rows || !n_dumps || !n_windows || !lock_fails || !hist || !edge || !n_bits)
+        return GC_EINVAL;
+    if (n_chan < 1 || n_chan > GC_MAX_CHANNELS || max_dumps == 0 || window < 2 ||
+        !(dump_s > 0.0) || row_stride < 2 || prompt_col < 0 || prompt_col + 1 >= row_stride ||
+        (max_windows > 0 && (!cn0 || !lock)) || (max_bits > 0 && !bits))
+        return GC_EINVAL;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return GC_EDEVICE;
+    return from_hip(gc::launch_lock_metrics(rows, row_stride, prompt_col, n_dumps, n_chan,
+                                            max_dumps, window, dump_s, lock_min, phase, cn0,
+                                            lock, max_windows, n_windows, lock_fails, hist, edge,
+                                            bits, max_bits, n_bits, (hipStream_t)stream));
+}
+
 gc_status gc_correlate(gc_plan* plan, const void* samples, uint64_t n_samples,
                        gc_chan_state* state, void* out, uint32_t* dump_n, uint32_t* n_dumps,
                        int32_t* status, uint32_t max_dumps, void* stream) {

@@ -317,7 +317,94 @@ __global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ 
     }
 }
 
+// Lock metrics and bit synchronisation of channel blockIdx.x over its
+// closed dumps: prompt I and Q of dump k at rows[(ch * max_dumps + k) *
+// stride + col] and [... + col + 1].  One thread per window (C/N0 by the
+// moments estimator, lock ratio), per bit-period start (navigation bits),
+// and a block-wide histogram of prompt sign changes.
+__global__ __launch_bounds__(256) void k_lock_metrics(
+    const int32_t* __restrict__ rows, int stride, int col, const uint32_t* __restrict__ n_dumps,
+    uint32_t max_dumps, uint32_t K, double T, double lock_min,
+    const uint32_t* __restrict__ phase, double* __restrict__ cn0, double* __restrict__ lock,
+    uint32_t max_windows, uint32_t* __restrict__ n_windows, uint32_t* __restrict__ lock_fails,
+    uint32_t* __restrict__ hist, uint32_t* __restrict__ edge, uint8_t* __restrict__ bits,
+    uint32_t max_bits, uint32_t* __restrict__ n_bits) {
+#pragma clang fp contract(off)
+    __shared__ uint32_t s_hist[20];
+    __shared__ uint32_t s_fails;
+    __shared__ uint32_t s_edge;
+    const int ch = blockIdx.x, tid = threadIdx.x;
+    const uint32_t n = min(n_dumps[ch], max_dumps);
+    const int32_t* r = rows + (uint64_t)ch * max_dumps * stride + col;
+    const uint32_t ph = phase ? phase[ch] % 20 : 0;
+    if (tid < 20) s_hist[tid] = 0;
+    if (tid == 0) s_fails = 0;
+    __syncthreads();
+    const uint32_t nw = n / K;
+    for (uint32_t w = tid; w < nw; w += blockDim.x) {
+        double m2 = 0.0, m4 = 0.0, ii = 0.0, qq = 0.0;
+        for (uint32_t k = w * K; k < (w + 1) * K; ++k) {
+            const double i = (double)r[(uint64_t)k * stride], q = (double)r[(uint64_t)k * stride + 1];
+            const double p = i * i + q * q;
+            m2 += p;
+            m4 += p * p;
+            ii += i * i;
+            qq += q * q;
+        }
+        m2 = m2 / (double)K;
+        m4 = m4 / (double)K;
+        const double d = 2.0 * m2 * m2 - m4;
+        double c = __builtin_nan("");
+        if (d > 0.0) {
+            const double a = __builtin_sqrt(d);
+            if (m2 - a > 0.0) c = 10.0 * log10((a / (m2 - a)) / T);
+        }
+        const double ratio = (ii + qq) > 0.0 ? (ii - qq) / (ii + qq) : 0.0;
+        if (w < max_windows) {
+            cn0[(uint64_t)ch * max_windows + w] = c;
+            lock[(uint64_t)ch * max_windows + w] = ratio;
+        }
+        if (ratio < lock_min) atomicAdd(&s_fails, 1u);
+    }
+    for (uint32_t k = 1 + tid; k < n; k += blockDim.x) {
+        const bool a = r[(uint64_t)(k - 1) * stride] < 0, b = r[(uint64_t)k * stride] < 0;
+        if (a != b) atomicAdd(&s_hist[(k + ph) % 20], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t e = 0;
+        for (uint32_t j = 1; j < 20; ++j)
+            if (s_hist[j] > s_hist[e]) e = j;
+        s_edge = e;
+        for (int j = 0; j < 20; ++j) hist[ch * 20 + j] = s_hist[j];
+        edge[ch] = e;
+        n_windows[ch] = min(nw, max_windows);
+        lock_fails[ch] = s_fails;
+    }
+    __syncthreads();
+    const uint32_t k0 = (s_edge + 20 - ph) % 20;
+    const uint32_t nb = n >= k0 + 20 ? (n - k0) / 20 : 0;
+    for (uint32_t j = tid; j < nb && j < max_bits; j += blockDim.x) {
+        int64_t sum = 0;
+        for (uint32_t t = 0; t < 20; ++t) sum += r[(uint64_t)(k0 + 20 * j + t) * stride];
+        bits[(uint64_t)ch * max_bits + j] = (uint8_t)(sum < 0);
+    }
+    if (tid == 0) n_bits[ch] = min(nb, max_bits);
+}
+
 }  // namespace
+
+hipError_t launch_lock_metrics(const int32_t* rows, int stride, int col, const uint32_t* n_dumps,
+                               int n_chan, uint32_t max_dumps, uint32_t K, double T,
+                               double lock_min, const uint32_t* phase, double* cn0, double* lock,
+                               uint32_t max_windows, uint32_t* n_windows, uint32_t* lock_fails,
+                               uint32_t* hist, uint32_t* edge, uint8_t* bits, uint32_t max_bits,
+                               uint32_t* n_bits, hipStream_t s) {
+    hipLaunchKernelGGL(k_lock_metrics, dim3(n_chan), dim3(256), 0, s, rows, stride, col, n_dumps,
+                       max_dumps, K, T, lock_min, phase, cn0, lock, max_windows, n_windows,
+                       lock_fails, hist, edge, bits, max_bits, n_bits);
+    return hipGetLastError();
+}
 
 hipError_t launch_track(const uint8_t* samples, uint64_t n, int fmt, const DevChan* chans,
                         gc_chan_state* state, gc_loop_state* loop, const TrackConsts& consts,

@@ -95,6 +95,8 @@ def _load():
         "gc_server_stats": ([P, P], I32),
         "gc_loop_init": ([D, D, P], I32),
         "gc_track": ([P, P, U64, P, P, P, P, P, P, P, U32, P], I32),
+        "gc_lock_metrics": ([P, P, I32, I32, P, I32, U32, U32, D, D, P, P, P, U32, P, P, P, P,
+                             P, U32, P, P], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -111,7 +113,7 @@ EXPORTED = ("gc_strerror", "gc_version", "gc_create", "gc_destroy", "gc_nco_init
             "gc_batch_info", "gc_batch_destroy", "gc_server_create", "gc_server_open_rx",
             "gc_server_submit", "gc_server_hold", "gc_server_poll", "gc_server_result", "gc_server_state",
             "gc_server_info", "gc_server_destroy", "gc_server_stats", "gc_loop_init",
-            "gc_track")
+            "gc_track", "gc_lock_metrics")
 
 
 def _check(rc: int, where: str):
@@ -347,6 +349,18 @@ def gc_track(plan: int, samples, n_samples: int, params: np.ndarray, state, loop
     return _lib.gc_track(plan, _ptr(samples), n_samples, params.ctypes.data, _ptr(state),
                          _ptr(loop), _ptr(rows), _ptr(dump_n), _ptr(n_dumps), _ptr(status),
                          max_dumps, _stream_ptr(stream))
+
+
+def gc_lock_metrics(ctx: int, rows, row_stride: int, prompt_col: int, n_dumps, n_chan: int,
+                    max_dumps: int, window: int, dump_s: float, lock_min: float, phase, cn0, lock,
+                    max_windows: int, n_windows, lock_fails, hist, edge, bits, max_bits: int,
+                    n_bits, stream=None) -> int:
+    """Enqueue lock metrics and bit synchronisation; returns the gc_status of the call."""
+    return _lib.gc_lock_metrics(ctx, _ptr(rows), row_stride, prompt_col, _ptr(n_dumps), n_chan,
+                                max_dumps, window, dump_s, lock_min, _ptr(phase), _ptr(cn0),
+                                _ptr(lock), max_windows, _ptr(n_windows), _ptr(lock_fails),
+                                _ptr(hist), _ptr(edge), _ptr(bits), max_bits, _ptr(n_bits),
+                                _stream_ptr(stream))
 
 
 def _stream_ptr(stream):

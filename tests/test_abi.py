@@ -95,6 +95,9 @@ def test_host_validation_without_a_device():
     assert g._lib.gc_loop_init(1.0, 1.0, None) == g.GC_EINVAL
     assert g._lib.gc_track(None, None, 0, None, None, None, None, None, None, None, 1,
                            None) == g.GC_EINVAL
+    assert g._lib.gc_lock_metrics(None, None, 8, 2, None, 1, 1, 20, 1e-3, 0.5, None, None,
+                                  None, 0, None, None, None, None, None, 0, None,
+                                  None) == g.GC_EINVAL
     ls = g.gc_loop_init(4.0e6, 1.023e6)
     assert ls["carr_hz"] == 4.0e6 and ls["fll_basis_hz"] == 4.0e6 and ls["have_prev"] == 0
     assert g.gc_version() == (1, 0)

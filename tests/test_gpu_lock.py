@@ -1,0 +1,213 @@
+"""GPU parity of the lock metrics and bit synchronisation (gc_lock_metrics)
+against the CPU oracle, through the C ABI: histograms, edges, bits, window
+and failure counts bit for bit, lock ratios bit for bit, C/N0 to the last
+bits of log10; on random prompts with ragged dump counts, on clipped
+outputs, and on the rows the GPU tracking loops write for a synthetic
+signal, whose navigation bits come back."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+EPL = [1 << 31, 0, -(1 << 31)]
+
+
+@pytest.fixture(scope="module")
+def g():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1907_00463_amd import gnsscorr
+    return gnsscorr
+
+
+@pytest.fixture(scope="module")
+def ctx(g):
+    c = g.gc_create(0)
+    yield c
+    g.gc_destroy(c)
+
+
+def _gpu(g, ctx, rows, stride, col, n_dumps, K, T, lock_min, phase, max_windows, max_bits,
+         dev_rows=None):
+    """Run gc_lock_metrics on rows (numpy [n_chan, max_dumps, stride] or, with
+    dev_rows, a device tensor of that shape); returns per-channel dicts."""
+    n_chan, max_dumps = rows.shape[0], rows.shape[1]
+    cu = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")   # noqa: E731
+    r = dev_rows if dev_rows is not None else cu(rows)
+    nd = cu(np.asarray(n_dumps, np.int32))
+    ph = None if phase is None else cu(np.asarray(phase, np.int32))
+    mw = max(max_windows, 1)
+    mb = max(max_bits, 1)
+    cn0 = torch.full((n_chan, mw), -1.0, dtype=torch.float64, device="cuda")
+    lock = torch.full((n_chan, mw), -1.0, dtype=torch.float64, device="cuda")
+    nw = torch.zeros(n_chan, dtype=torch.int32, device="cuda")
+    fails = torch.zeros(n_chan, dtype=torch.int32, device="cuda")
+    hist = torch.full((n_chan, 20), 7, dtype=torch.int32, device="cuda")
+    edge = torch.zeros(n_chan, dtype=torch.int32, device="cuda")
+    bits = torch.full((n_chan, mb), 9, dtype=torch.uint8, device="cuda")
+    nb = torch.zeros(n_chan, dtype=torch.int32, device="cuda")
+    rc = g.gc_lock_metrics(ctx, r, stride, col, nd, n_chan, max_dumps, K, T, lock_min, ph, cn0,
+                           lock, max_windows, nw, fails, hist, edge, bits, max_bits, nb,
+                           torch.cuda.current_stream())
+    assert rc == g.GC_OK
+    torch.cuda.synchronize()
+    out = []
+    for c in range(n_chan):
+        w, b = int(nw[c]), int(nb[c])
+        out.append({"cn0": cn0[c, :w].cpu().numpy(), "lock": lock[c, :w].cpu().numpy(),
+                    "lock_fails": int(fails[c]), "hist": hist[c].cpu().numpy().astype(np.uint32),
+                    "edge": int(edge[c]), "bits": bits[c, :b].cpu().numpy()})
+    return out
+
+
+def _same(got, want, max_windows=None, max_bits=None):
+    w = len(want["cn0"]) if max_windows is None else min(len(want["cn0"]), max_windows)
+    assert len(got["cn0"]) == w
+    assert got["lock"].tobytes() == want["lock"][:w].tobytes()
+    a, b = got["cn0"], want["cn0"][:w]
+    assert np.array_equal(np.isnan(a), np.isnan(b))
+    f = ~np.isnan(b)
+    assert np.allclose(a[f], b[f], rtol=1e-14, atol=0.0)
+    assert got["lock_fails"] == want["lock_fails"]
+    assert np.array_equal(got["hist"], want["hist"])
+    assert got["edge"] == want["edge"]
+    nb = len(want["bits"]) if max_bits is None else min(len(want["bits"]), max_bits)
+    assert np.array_equal(got["bits"], want["bits"][:nb])
+
+
+def _random_rows(rng, n_chan, max_dumps, stride, col):
+    rows = rng.integers(-2 ** 31, 2 ** 31, size=(n_chan, max_dumps, stride), dtype=np.int64)
+    for c in range(n_chan):
+        # prompts of a signal with bits, noise and a phase, at scales from a few
+        # counts to near the int32 limit
+        A = float(10 ** rng.uniform(0.5, 9.0))
+        k = np.arange(max_dumps)
+        e = int(rng.integers(0, 20))
+        b = rng.choice([-1, 1], max_dumps // 20 + 2)[(k + 20 - e) // 20]
+        ph = rng.uniform(-0.6, 0.6)
+        s = A * float(rng.uniform(0.05, 1.0))
+        i = np.clip(np.rint(A * b * math.cos(ph) + rng.normal(0, s, max_dumps)), -2 ** 31, 2 ** 31 - 1)
+        q = np.clip(np.rint(A * b * math.sin(ph) + rng.normal(0, s, max_dumps)), -2 ** 31, 2 ** 31 - 1)
+        rows[c, :, col] = i
+        rows[c, :, col + 1] = q
+    return rows.astype(np.int32)
+
+
+@pytest.mark.parametrize("stride,col,K", [(8, 2, 20), (2, 0, 50), (10, 7, 2)])
+def test_lock_metrics_random_prompts(g, ctx, stride, col, K):
+    rng = np.random.default_rng(stride * 100 + col)
+    max_dumps = 1200
+    n_dumps = [0, 1, 19, 20, 21, 57, 400, 1000, 1200, 5000, 333, 2]   # 5000: clipped to 1200
+    n_chan = len(n_dumps)
+    rows = _random_rows(rng, n_chan, max_dumps, stride, col)
+    phase = rng.integers(0, 1000, n_chan)
+    T, lock_min = 1e-3 * float(rng.integers(1, 5)), 0.6
+    mw, mb = max_dumps // K, max_dumps // 20 + 1
+    got = _gpu(g, ctx, rows, stride, col, n_dumps, K, T, lock_min, phase, mw, mb)
+    for c in range(n_chan):
+        n = min(n_dumps[c], max_dumps)
+        want = oracle.lock_metrics(rows[c, :n, col:col + 2], K=K, T=T, lock_min=lock_min,
+                                   phase=int(phase[c]))
+        _same(got[c], want)
+    # without a phase array every channel's dump 0 is position 0
+    got = _gpu(g, ctx, rows, stride, col, n_dumps, K, T, lock_min, None, mw, mb)
+    for c in range(n_chan):
+        n = min(n_dumps[c], max_dumps)
+        _same(got[c], oracle.lock_metrics(rows[c, :n, col:col + 2], K=K, T=T,
+                                          lock_min=lock_min))
+
+
+def test_lock_metrics_clipped_outputs(g, ctx):
+    # fewer window and bit slots than the dumps fill: the first ones are
+    # written and counted; lock failures still count every window
+    rng = np.random.default_rng(5)
+    rows = _random_rows(rng, 3, 900, 8, 2)
+    n_dumps = [900, 640, 77]
+    got = _gpu(g, ctx, rows, 8, 2, n_dumps, 20, 1e-3, 0.99, [0, 3, 19], 5, 4)
+    for c in range(3):
+        want = oracle.lock_metrics(rows[c, :n_dumps[c], 2:4], K=20, T=1e-3, lock_min=0.99,
+                                   phase=[0, 3, 19][c])
+        _same(got[c], want, max_windows=5, max_bits=4)
+    # no window or bit slots at all: counts, histogram and edge only
+    got = _gpu(g, ctx, rows, 8, 2, n_dumps, 20, 1e-3, 0.99, None, 0, 0)
+    for c in range(3):
+        want = oracle.lock_metrics(rows[c, :n_dumps[c], 2:4], K=20, T=1e-3, lock_min=0.99)
+        _same(got[c], want, max_windows=0, max_bits=0)
+
+
+def test_lock_metrics_on_tracked_rows(g, ctx):
+    # PRN 7 at 45 dB-Hz, tracked on the GPU for 2 s from a 30 Hz and 0.2 chip
+    # offset; the metrics run on the device rows in place and equal the
+    # oracle's on the oracle's own tracking rows; the bits after the loops
+    # settle are the transmitted ones up to the PLL's sign
+    from paper_1907_00463_amd import synth
+    st, chans, rng = synth.workload_single_channel(seconds=2.0, seed=1001)
+    ch = chans[0]
+    buf = synth.synth_samples(st, rng)
+    cfgs = np.zeros(1, g.CHAN_CFG)
+    cfgs[0] = g.make_cfg(ch.prn, EPL, 1)
+    states = np.zeros(1, g.CHAN_STATE)
+    states[0] = g.gc_nco_init(st.fs, ch.carr_hz + 30.0, ch.carr_phase0, ch.code_rate,
+                              ch.code_phase0 + 0.2, 1)
+    loops = np.zeros(1, g.LOOP_STATE)
+    loops[0] = g.gc_loop_init(ch.carr_hz + 30.0, ch.code_rate)
+    params = g.loop_params(st.fs, st.if_hz)
+    max_dumps = 2100
+    plan = g.Plan(ctx, st.fmt, g.GC_CARRIER_LUT, cfgs)
+    try:
+        sd = plan.states_to_device(states)
+        lp = torch.from_numpy(loops.view(np.uint8).copy()).to("cuda")
+        rows = torch.zeros((1, max_dumps, 8), dtype=torch.int32, device="cuda")
+        dn = torch.zeros((1, max_dumps), dtype=torch.int32, device="cuda")
+        nd = torch.zeros(1, dtype=torch.int32, device="cuda")
+        stt = torch.zeros(1, dtype=torch.int32, device="cuda")
+        x = torch.from_numpy(buf).to("cuda")
+        assert g.gc_track(plan.handle, x, st.n, params, sd, lp, rows, dn, nd, stt, max_dumps,
+                          torch.cuda.current_stream()) == g.GC_OK
+        torch.cuda.synchronize()
+        assert int(stt[0]) == 0
+        n = int(nd[0])
+        got = _gpu(g, ctx, np.zeros((1, max_dumps, 8), np.int32), 8, 2, [n], 20, 1e-3, 0.8,
+                   None, 200, 200, dev_rows=rows)[0]
+    finally:
+        plan.close()
+    ts = oracle.track_state(
+        oracle.OracleState(*oracle.nco_words(st.fs, ch.carr_hz + 30.0, ch.carr_phase0,
+                                             ch.code_rate, ch.code_phase0 + 0.2, 1), 3),
+        ch.carr_hz + 30.0, ch.code_rate)
+    orows, _ = oracle.track(st.fmt, buf, st.n, ch.prn, 1,
+                            oracle.LoopParams(fs=st.fs, if_hz=st.if_hz), ts)
+    assert n == len(orows)
+    want = oracle.lock_metrics(orows[:, 2:4], K=20, T=1e-3, lock_min=0.8)
+    _same(got, want)
+    assert got["edge"] == 0
+    nav = (st.sats[0].nav_bits[:len(got["bits"])] < 0).astype(np.uint8)
+    agree = np.mean(got["bits"][25:] == nav[25:])
+    assert agree in (0.0, 1.0)
+
+
+def test_lock_metrics_argument_errors(g, ctx):
+    rows = torch.zeros((2, 40, 8), dtype=torch.int32, device="cuda")
+    nd = torch.full((2,), 40, dtype=torch.int32, device="cuda")
+    u = lambda n: torch.zeros(n, dtype=torch.int32, device="cuda")   # noqa: E731
+    d = torch.zeros((2, 2), dtype=torch.float64, device="cuda")
+    b = torch.zeros((2, 3), dtype=torch.uint8, device="cuda")
+
+    def call(stride=8, col=2, n_chan=2, K=20, T=1e-3, cn0=d, bits=b, ndp=nd):
+        return g.gc_lock_metrics(ctx, rows, stride, col, ndp, n_chan, 40, K, T, 0.5, None, cn0,
+                                 d, 2, u(2), u(2), u(40), u(2), bits, 3, u(2))
+
+    assert call() == g.GC_OK
+    assert call(K=1) == g.GC_EINVAL
+    assert call(T=0.0) == g.GC_EINVAL
+    assert call(col=7) == g.GC_EINVAL
+    assert call(stride=1, col=0) == g.GC_EINVAL
+    assert call(n_chan=0) == g.GC_EINVAL
+    assert call(cn0=None) == g.GC_EINVAL
+    assert call(bits=None) == g.GC_EINVAL
+    assert call(ndp=None) == g.GC_EINVAL
+    torch.cuda.synchronize()
