@@ -6,7 +6,8 @@ path (``paper_1907_00463_amd``) never imports it and shares no code with it.
 
 ``gnss_oracle.c`` holds the definition (plain C loops, int64 / fp64);
 ``oracle.py`` loads it with ctypes; ``brute.py`` is an independent numpy
-matrix-form brute force for tiny inputs, used as one of the pins.
+matrix-form brute force for tiny inputs, used as one of the pins;
+``acquire.py`` is the FFT-based parallel code-phase search (numpy, fp64).
 """
 from .oracle import (  # noqa: F401
     I8_REAL, I8_IQ, I2_REAL, EPL_TAPS_Q32, OracleState,
@@ -15,3 +16,4 @@ from .oracle import (  # noqa: F401
     LoopParams, TrackState, track_state, cordic_table, cordic_atan2, loop_coefficients, track,
     lock_metrics,
 )
+from . import acquire  # noqa: F401,E402
