@@ -356,6 +356,80 @@ gc_status gc_lock_metrics(gc_ctx* ctx, const int32_t* rows, int32_t row_stride,
                           void* stream);
 
 /* ------------------------------------------------------------------------
+ * Acquisition (Sec. 3.6: the ACQ module searches a buffer of whole code
+ * periods for the satellites to track; Sec. 3.7: FFT-based search).
+ *
+ * A parallel code-phase search over Doppler bins and PRNs, computed exactly
+ * in integers.  The buffer holds `blocks` blocks of `coherent_periods` code
+ * periods at R = samples_per_chip samples per chip (fs = R * 1.023 MHz, N =
+ * 1023 R samples per period).  Bin d has the carrier frequency if_hz +
+ * (f_lo_hz + d * f_step_hz) and the NCO step round_half_even(f / fs * 2^32)
+ * mod 2^32.  Its phase is 0 at sample 0 of the buffer and runs on across
+ * blocks.  The wipe-off uses the correlator's carrier table.  At code phase
+ * tau (0 <= tau < N samples), sample n meets chip floor((n + tau) / R) mod
+ * 1023 of the PRN's code.  For each block the kernel forms the complex sum
+ * Y of wiped-off sample times chip over the block, and the power is
+ *   P[p][d][tau] = sum over blocks of (Y_I^2 + Y_Q^2)     (uint64, exact).
+ * Detection per PRN: the peak is the largest P; ties go to the lower bin,
+ * then the lower tau.  The second peak is the largest P in the peak's bin
+ * over the chips floor(tau / R) at least two chips (circularly) from the
+ * peak's chip.  metric = peak / second in double (+inf when second is 0),
+ * and the PRN counts as acquired when metric >= threshold.
+ * ------------------------------------------------------------------------ */
+#define GC_ACQ_MAX_SPC 32     /* samples per chip */
+#define GC_ACQ_MAX_BINS 1024
+#define GC_ACQ_MAX_PRNS 1024
+
+typedef struct gc_acq gc_acq;
+
+/* One PRN's detection (device memory, written by gc_acquire).  Layout
+ * fixed: 56 bytes. */
+typedef struct {
+    int32_t prn;
+    int32_t bin;              /* Doppler bin of the peak */
+    int32_t tau;              /* code phase of the peak, samples */
+    int32_t acquired;         /* 1 when metric >= threshold */
+    uint64_t peak;            /* P at the peak */
+    uint64_t second;          /* second peak (see above) */
+    double doppler_hz;        /* f_lo_hz + bin * f_step_hz */
+    double code_phase_chips;  /* tau / R: code phase at sample 0 of the buffer */
+    double metric;            /* peak / second */
+} gc_acq_result;
+
+/* A search plan: validates the bounds, computes the bin steps and allocates
+ * the device scratch (gc_acq_info reports its size).
+ *   fmt                  sample format of the buffer
+ *   samples_per_chip     R, 1 .. GC_ACQ_MAX_SPC
+ *   prns                 host, n_prn PRN numbers 1..32 (repeats allowed)
+ *   coherent_periods     Mc, 1 .. 1000
+ *   blocks               Knc, 1 .. 1000 (non-coherent sum)
+ * The bounds on the exact integer arithmetic: Mc * R * max|w| < 2^28, where
+ * max|w| is 72 for 2-bit, 3072 for int8 real and 4352 for int8 I/Q, and
+ * Knc * 2 * (Mc * N * max|w|)^2 < 1.8e19.
+ * Errors: GC_EINVAL (null pointers, values out of range, bounds),
+ * GC_ENOMEM, GC_EDEVICE. */
+gc_status gc_acq_create(gc_ctx* ctx, gc_format fmt, int32_t samples_per_chip, double if_hz,
+                        double f_lo_hz, double f_step_hz, int32_t n_bins, const int32_t* prns,
+                        int32_t n_prn, int32_t coherent_periods, int32_t blocks, gc_acq** out);
+
+/* Run the search on the first Knc * Mc * N samples of a device buffer.
+ *   samples    device, at least that many samples
+ *   surface    device, uint64 [n_prn][n_bins][N] power, or NULL
+ *   results    device, gc_acq_result[n_prn]
+ * Calls on one plan share its scratch: run them in one stream.
+ * Errors: GC_EINVAL (null, too few samples), GC_EDEVICE. */
+gc_status gc_acquire(gc_acq* acq, const void* samples, uint64_t n_samples, double threshold,
+                     uint64_t* surface, gc_acq_result* results, void* stream);
+
+/* Query (any pointer may be NULL): int8 digits per box sum (2 or 4), device
+ * scratch bytes, samples a call reads.  Errors: GC_EINVAL. */
+gc_status gc_acq_info(gc_acq* acq, int32_t* digits, uint64_t* scratch_bytes,
+                      uint64_t* samples_needed);
+
+/* Free a plan (after its last call has finished).  Errors: GC_EINVAL. */
+gc_status gc_acq_destroy(gc_acq* acq);
+
+/* ------------------------------------------------------------------------
  * Batches: many receivers in one persistent launch.
  *
  * A batch binds the sample blocks of n_rx receivers (each with its own

@@ -49,6 +49,10 @@ LOOP_STATE = np.dtype([("carr_hz", "<f8"), ("code_cps", "<f8"), ("fll_basis_hz",
                        ("dll_err_prev", "<f8"), ("prompt_i_prev", "<i4"),
                        ("prompt_q_prev", "<i4"), ("have_prev", "<i4"), ("reserved", "<i4")])
 assert LOOP_PARAMS.itemsize == 72 and LOOP_STATE.itemsize == 72
+ACQ_RESULT = np.dtype([("prn", "<i4"), ("bin", "<i4"), ("tau", "<i4"), ("acquired", "<i4"),
+                       ("peak", "<u8"), ("second", "<u8"), ("doppler_hz", "<f8"),
+                       ("code_phase_chips", "<f8"), ("metric", "<f8")])
+assert ACQ_RESULT.itemsize == 56
 
 
 class GcError(RuntimeError):
@@ -95,6 +99,10 @@ def _load():
         "gc_server_stats": ([P, P], I32),
         "gc_loop_init": ([D, D, P], I32),
         "gc_track": ([P, P, U64, P, P, P, P, P, P, P, U32, P], I32),
+        "gc_acq_create": ([P, I32, I32, D, D, D, I32, P, I32, I32, I32, P], I32),
+        "gc_acquire": ([P, P, U64, D, P, P, P], I32),
+        "gc_acq_info": ([P, P, P, P], I32),
+        "gc_acq_destroy": ([P], I32),
         "gc_lock_metrics": ([P, P, I32, I32, P, I32, U32, U32, D, D, P, P, P, U32, P, P, P, P,
                              P, U32, P, P], I32),
     }
@@ -113,7 +121,8 @@ EXPORTED = ("gc_strerror", "gc_version", "gc_create", "gc_destroy", "gc_nco_init
             "gc_batch_info", "gc_batch_destroy", "gc_server_create", "gc_server_open_rx",
             "gc_server_submit", "gc_server_hold", "gc_server_poll", "gc_server_result", "gc_server_state",
             "gc_server_info", "gc_server_destroy", "gc_server_stats", "gc_loop_init",
-            "gc_track", "gc_lock_metrics")
+            "gc_track", "gc_lock_metrics", "gc_acq_create", "gc_acquire", "gc_acq_info",
+            "gc_acq_destroy")
 
 
 def _check(rc: int, where: str):
@@ -361,6 +370,35 @@ def gc_lock_metrics(ctx: int, rows, row_stride: int, prompt_col: int, n_dumps, n
                                 _ptr(lock), max_windows, _ptr(n_windows), _ptr(lock_fails),
                                 _ptr(hist), _ptr(edge), _ptr(bits), max_bits, _ptr(n_bits),
                                 _stream_ptr(stream))
+
+
+def gc_acq_create(ctx: int, fmt: int, samples_per_chip: int, if_hz: float, f_lo_hz: float,
+                  f_step_hz: float, n_bins: int, prns, coherent_periods: int, blocks: int) -> int:
+    prns = np.ascontiguousarray(prns, dtype=np.int32)
+    h = C.c_void_p()
+    _check(_lib.gc_acq_create(ctx, fmt, samples_per_chip, if_hz, f_lo_hz, f_step_hz, n_bins,
+                              prns.ctypes.data, len(prns), coherent_periods, blocks, C.byref(h)),
+           "gc_acq_create")
+    return h.value
+
+
+def gc_acquire(acq: int, samples, n_samples: int, threshold: float, surface, results,
+               stream=None) -> int:
+    """Enqueue one search; returns the gc_status of the call."""
+    return _lib.gc_acquire(acq, _ptr(samples), n_samples, threshold, _ptr(surface),
+                           _ptr(results), _stream_ptr(stream))
+
+
+def gc_acq_info(acq: int) -> dict:
+    dg = C.c_int32()
+    sb = C.c_uint64()
+    ns = C.c_uint64()
+    _check(_lib.gc_acq_info(acq, C.byref(dg), C.byref(sb), C.byref(ns)), "gc_acq_info")
+    return {"digits": dg.value, "scratch_bytes": sb.value, "samples_needed": ns.value}
+
+
+def gc_acq_destroy(acq: int) -> None:
+    _check(_lib.gc_acq_destroy(acq), "gc_acq_destroy")
 
 
 def _stream_ptr(stream):

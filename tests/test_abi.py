@@ -1,5 +1,6 @@
 """The C ABI: exports, struct layouts, host-side validation and the host NCO
 helper.  No compute call is made here (no GPU needed)."""
+import ctypes as C
 import os
 import re
 import subprocess
@@ -56,6 +57,8 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu\n", sizeof(gc_loop_params), offsetof(gc_loop_params, fll_bw_hz),
          sizeof(gc_loop_state), offsetof(gc_loop_state, prompt_i_prev),
          offsetof(gc_loop_state, have_prev));
+  printf("%zu %zu %zu %zu\n", sizeof(gc_acq_result), offsetof(gc_acq_result, peak),
+         offsetof(gc_acq_result, doppler_hz), offsetof(gc_acq_result, metric));
   return 0;
 }
 ''')
@@ -72,7 +75,10 @@ int main(void) {
                     gnsscorr.SERVER_TIMING.fields["submit_max_ms"][1],
                     gnsscorr.LOOP_PARAMS.itemsize, gnsscorr.LOOP_PARAMS.fields["fll_bw_hz"][1],
                     gnsscorr.LOOP_STATE.itemsize, gnsscorr.LOOP_STATE.fields["prompt_i_prev"][1],
-                    gnsscorr.LOOP_STATE.fields["have_prev"][1]]
+                    gnsscorr.LOOP_STATE.fields["have_prev"][1],
+                    gnsscorr.ACQ_RESULT.itemsize, gnsscorr.ACQ_RESULT.fields["peak"][1],
+                    gnsscorr.ACQ_RESULT.fields["doppler_hz"][1],
+                    gnsscorr.ACQ_RESULT.fields["metric"][1]]
 
 
 def test_host_validation_without_a_device():
@@ -98,6 +104,11 @@ def test_host_validation_without_a_device():
     assert g._lib.gc_lock_metrics(None, None, 8, 2, None, 1, 1, 20, 1e-3, 0.5, None, None,
                                   None, 0, None, None, None, None, None, 0, None,
                                   None) == g.GC_EINVAL
+    prns = (C.c_int32 * 1)(1)
+    assert g._lib.gc_acq_create(None, 0, 4, 0.0, 0.0, 1.0, 1, prns, 1, 1, 1, None) == g.GC_EINVAL
+    assert g._lib.gc_acquire(None, None, 0, 2.5, None, None, None) == g.GC_EINVAL
+    assert g._lib.gc_acq_info(None, None, None, None) == g.GC_EINVAL
+    assert g._lib.gc_acq_destroy(None) == g.GC_EINVAL
     ls = g.gc_loop_init(4.0e6, 1.023e6)
     assert ls["carr_hz"] == 4.0e6 and ls["fll_basis_hz"] == 4.0e6 and ls["have_prev"] == 0
     assert g.gc_version() == (1, 0)
