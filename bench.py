@@ -11,7 +11,8 @@ HBM.  Other workloads: "single" (1 channel, int8 real at 4.092 MHz, 1 s),
 "batched" (64 receivers of 8-14 channels, mixed rates, formats and dump
 lengths, 1 s each, one graph-captured persistent launch) and
 "multicorrelator" (256 channels x 128 taps at 1/32 chip, complex int8 at
-20.46 MHz, 2 s).
+20.46 MHz, 2 s), "tracking" (closed loops plus lock metrics), "serving"
+(continuous batching) and "acquisition" (a 32-PRN x 41-bin cold start).
 
 Prints ONE JSON line.  ``value`` is G sample*taps/s (one sample correlated
 against one tap, I and Q counted together).  ``roofline`` prices the main
@@ -74,6 +75,11 @@ WORKLOADS = {
         describe="12 channels, 2-bit real, fs 16.368 MHz, IF 4.092 MHz, %g s, 1 ms dumps, E/P/L at "
                  "+-1/2 chip, closed DLL/PLL/FLL loops started 30 Hz and 0.1 chip off",
         seconds=10.0, ops=6, fmt_name="i2_real", cpu_seconds=1.0),
+    "acquisition": dict(
+        describe="cold-start acquisition on the 12-channel stream (2-bit real, fs 16.368 MHz = 16 "
+                 "samples per chip, IF 4.092 MHz): 32 PRNs x 41 Doppler bins (+-10 kHz, 500 Hz) x "
+                 "16368 code phases, 1 ms coherent, %d non-coherent blocks",
+        seconds=0.010, ops=0, fmt_name="i2_real", cpu_seconds=0.004),
     "serving": dict(
         describe="500 receivers x 4-14 channels (fs 4.092/8.184/16.368 MHz, IF fs/4, int8 or "
                  "2-bit real, 1/4/20 ms dumps, E/P/L at +-1/2 chip), Poisson arrivals at 2000 "
@@ -629,6 +635,20 @@ def main_tracking(args, wl, seconds, cpu_seconds):
     nd = torch.zeros(len(chans), dtype=torch.int32, device=dev)
     stt = torch.zeros(len(chans), dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream(dev)
+    nc = len(chans)
+    # lock metrics over windows of 20 dumps and navigation bits
+    max_win = max_dumps // 20 + 1
+    u32 = lambda *shape: torch.zeros(shape, dtype=torch.int32, device=dev)   # noqa: E731
+    cn0 = torch.zeros((nc, max_win), dtype=torch.float64, device=dev)
+    lock = torch.zeros((nc, max_win), dtype=torch.float64, device=dev)
+    nwin, fails, hist, edge, nbits = u32(nc), u32(nc), u32(nc, 20), u32(nc), u32(nc)
+    bits = torch.zeros((nc, max_win), dtype=torch.uint8, device=dev)
+
+    def metrics():
+        rc = g.gc_lock_metrics(ctx, rows, 8, 2, nd, nc, max_dumps, 20, 1e-3, 0.8, None, cn0,
+                               lock, max_win, nwin, fails, hist, edge, bits, max_win, nbits,
+                               stream)
+        assert rc == g.GC_OK
 
     def step():
         s1.copy_(s0)
@@ -636,11 +656,24 @@ def main_tracking(args, wl, seconds, cpu_seconds):
         rc = g.gc_track(plan.handle, samples, n, params, s1, l1, rows, dn, nd, stt, max_dumps,
                         stream)
         assert rc == g.GC_OK
+        metrics()
 
     dt = time_steps(torch, step, args.steps, args.warmup)
+    dt_lock = time_steps(torch, metrics, args.steps, args.warmup)
     assert int(stt.abs().sum()) == 0, "channel refused"
     lf = l1.cpu().numpy().view(g.LOOP_STATE)
     carr_err = [float(lf[i]["carr_hz"]) - ch.carr_hz for i, ch in enumerate(chans)]
+    # decoded bits after the first second against the transmitted ones (up to
+    # the sign the PLL locks with), and the C/N0 estimate against the truth
+    agree, cn0_err = [], []
+    for i, sat in enumerate(st.sats):
+        b = bits[i, :int(nbits[i])].cpu().numpy().astype(np.int64)
+        t = (sat.nav_bits[:len(b)] < 0).astype(np.int64)
+        a = float(np.mean(b[50:] == t[50:])) if len(b) > 60 else float("nan")
+        agree.append(max(a, 1.0 - a))
+        c = cn0[i, 50:int(nwin[i])].cpu().numpy()
+        cn0_err.append(float(np.median(c[np.isfinite(c)])) - sat.cn0_dbhz if len(c) else
+                       float("nan"))
     sample_taps = n * 3 * len(chans)
     achieved = wl["ops"] * n * len(chans) / dt / 1e12
     res = {
@@ -649,10 +682,13 @@ def main_tracking(args, wl, seconds, cpu_seconds):
         "ms_per_step": round(dt * 1e3, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": wl["describe"] % seconds, "channels": len(chans), "samples": n,
-                   "format": wl["fmt_name"], "kernels": "track",
+                   "format": wl["fmt_name"], "kernels": "track + lock metrics",
                    "dumps_per_channel": int(nd.cpu().numpy().max()),
                    "realtime_channels": round(realtime_channels(len(chans), n / st.fs, dt), 1),
-                   "final_carrier_error_hz_max": round(max(abs(e) for e in carr_err), 3)},
+                   "final_carrier_error_hz_max": round(max(abs(e) for e in carr_err), 3),
+                   "lock_metrics_ms": round(dt_lock * 1e3, 4),
+                   "nav_bit_agreement_min": round(min(agree), 4),
+                   "cn0_error_db": [round(e, 2) for e in cn0_err]},
         "roofline": {"bound": "alu", "achieved": round(achieved, 4),
                      "peak": round(VALU_PEAK_TOPS, 2), "unit": "T lane-ops/s",
                      "frac": round(achieved / VALU_PEAK_TOPS, 5), "traffic": None,
@@ -693,6 +729,106 @@ def main_tracking(args, wl, seconds, cpu_seconds):
     print(json.dumps(res), flush=True)
 
 
+def main_acquisition(args, wl, seconds, cpu_seconds):
+    """Workload "acquisition": one parallel code-phase search (gc_acquire) of
+    all 32 PRNs over 41 bins on Knc = seconds / 1 ms blocks of the 12-channel
+    stream.  ``value`` counts every (code phase, bin, PRN) hypothesis as one
+    tap correlated against every sample of the buffer."""
+    import torch
+
+    from paper_1907_00463_amd import gnsscorr as g
+    from paper_1907_00463_amd import synth
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    knc = max(1, int(round(seconds * 1000)))
+    R, bins, f_lo, f_step = 16, 41, -10000.0, 500.0
+    prns = list(range(1, 33))
+    print("bench: generating %d ms of the acquisition workload" % knc, file=sys.stderr, flush=True)
+    st, chans, rng = synth.workload_twelve_channels(seconds=knc * 1e-3 + 1e-4)
+    buf = synth.synth_samples(st, rng)
+    N = 1023 * R
+    n = knc * N
+    ctx = g.gc_create(0)
+    acq = g.gc_acq_create(ctx, st.fmt, R, st.if_hz, f_lo, f_step, bins, prns, 1, knc)
+    info = g.gc_acq_info(acq)
+    samples = torch.from_numpy(buf).to(dev)
+    res = torch.zeros(len(prns) * g.ACQ_RESULT.itemsize, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def step():
+        assert g.gc_acquire(acq, samples, st.n, 2.5, None, res, stream) == g.GC_OK
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    g.gc_acq_timing(acq, args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    kms = np.array([g.gc_acq_kernel_ms(acq, i) for i in range(args.steps)])
+    g.gc_acq_timing(acq, 0)
+    stage = kms.mean(axis=0)
+    r = res.cpu().numpy().view(g.ACQ_RESULT)
+    found = [int(x["prn"]) for x in r if x["acquired"]]
+    truth = {s.prn: s for s in st.sats}
+    correct = [p for p in found if p in truth and
+               abs(float(r[p - 1]["doppler_hz"]) - truth[p].doppler_hz) < 500.0]
+    # algorithmic contraction: rows (bin, r, I/Q) x 1023 chips x 1023 shifts per PRN and block
+    alg_ops = 2.0 * (2 * bins * R) * 1023 * 1023 * len(prns) * knc
+    exe_ops = 2.0 * (2 * info["digits"] * bins * R) * 1024 * 1024 * len(prns) * knc
+    k_s = stage[1] / 1e3
+    tops = alg_ops / k_s / 1e12
+    sample_taps = float(n) * N * bins * len(prns)
+    out = {
+        "metric": METRIC, "value": round(sample_taps / wall / 1e9, 1), "unit": "G sample·taps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int8/int32", "data": "synthetic",
+        "config": {"workload": wl["describe"] % knc, "prns": len(prns), "bins": bins,
+                   "code_phases": N, "samples": n, "format": wl["fmt_name"],
+                   "digits": info["digits"], "scratch_mib": round(info["scratch_bytes"] / 2 ** 20, 1),
+                   "kernel_ms": {"sums": round(float(stage[0]), 4),
+                                 "contraction": round(float(stage[1]), 4),
+                                 "reduce": round(float(stage[2]), 4),
+                                 "detect": round(float(stage[3]), 4)},
+                   "acquired": found,
+                   "acquired_in_stream_at_true_doppler": len(correct),
+                   "satellites_in_stream": len(st.sats),
+                   "tap": "one (code phase, Doppler bin, PRN) hypothesis against every sample"},
+        "roofline": {"bound": "mfma", "achieved": round(tops, 2), "peak": INT8_MFMA_PEAK_TOPS,
+                     "unit": "T int8 ops/s", "frac": round(tops / INT8_MFMA_PEAK_TOPS, 4),
+                     "traffic": None, "kernel_ms": round(float(stage[1]), 4),
+                     "executed_frac": round(exe_ops / k_s / 1e12 / INT8_MFMA_PEAK_TOPS, 4),
+                     "note": "algorithmic ops = 2 x (2 x bins x R rows) x 1023 x 1023 per PRN "
+                             "and block; the kernel runs %d int8 digit rows per value and pads "
+                             "to 1024 (executed_frac)" % info["digits"]},
+    }
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline", file=sys.stderr, flush=True)
+        from concurrent.futures import ThreadPoolExecutor
+
+        from oracle import acquire as A
+        kc = max(1, int(round(cpu_seconds * 1000)))
+        threads = host_threads()
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            list(ex.map(lambda p: A.search(st.fmt, buf, R, st.if_hz, f_lo, f_step, bins, [p], 1,
+                                           kc), prns))
+        dtc = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": round(float(kc * N) * N * bins * len(prns) / dtc / 1e9, 1),
+            "unit": "G sample·taps/s", "cores": threads, "kind": "oracle", "host": host_cpu(),
+            "sample": "the same search on %d blocks (fp64 FFT per PRN and bin), threads over "
+                      "PRNs; %.2f s wall" % (kc, dtc)}
+    g.gc_acq_destroy(acq)
+    g.gc_destroy(ctx)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -725,6 +861,8 @@ def main():
         return main_serving(args, wl, seconds)
     if args.workload == "tracking":
         return main_tracking(args, wl, seconds, cpu_seconds)
+    if args.workload == "acquisition":
+        return main_acquisition(args, wl, seconds, cpu_seconds)
 
     import torch
 

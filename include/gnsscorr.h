@@ -426,6 +426,18 @@ gc_status gc_acquire(gc_acq* acq, const void* samples, uint64_t n_samples, doubl
 gc_status gc_acq_info(gc_acq* acq, int32_t* digits, uint64_t* scratch_bytes,
                       uint64_t* samples_needed);
 
+/* Per-kernel timing of gc_acquire: with n_slots > 0 every later call records
+ * HIP events on its stream before and after each of its four kernels (box
+ * sums, contraction, chip reduction, detection) into slot (call index mod
+ * n_slots); 0 turns timing off.  At most 4096 slots.  Errors: GC_EINVAL,
+ * GC_ENOMEM, GC_EDEVICE. */
+gc_status gc_acq_timing(gc_acq* acq, int32_t n_slots);
+
+/* The four kernel durations (ms) of `slot`; waits for its last event.
+ * Errors: GC_EINVAL (timing off, slot out of range or never recorded),
+ * GC_EDEVICE. */
+gc_status gc_acq_kernel_ms(gc_acq* acq, int32_t slot, float* ms4);
+
 /* Free a plan (after its last call has finished).  Errors: GC_EINVAL. */
 gc_status gc_acq_destroy(gc_acq* acq);
 

@@ -60,6 +60,10 @@ struct gc_acq {
     uint8_t* d_chiparg;   // [n_prn][n_bins][1024]
     uint64_t* d_binmax;   // [n_prn][n_bins]
     uint32_t* d_binarg;   // [n_prn][n_bins]
+    // timing slots (empty: off): events before the four kernels and after the last
+    std::vector<hipEvent_t> ev;  // [slot][5]
+    std::vector<uint8_t> ev_used;
+    uint64_t calls = 0;
 };
 
 namespace gc {
@@ -404,13 +408,14 @@ hipError_t launch_sums(const gc_acq* a, const void* samples, hipStream_t s) {
 }
 
 template <int ND>
-hipError_t launch_acq_nd(const gc_acq* a, const void* samples, hipStream_t s) {
+hipError_t launch_acq_nd(const gc_acq* a, const void* samples, hipStream_t s, hipEvent_t* ev) {
     hipError_t e;
     switch (a->fmt) {
         case GC_I8_REAL: e = launch_sums<GC_I8_REAL, ND>(a, samples, s); break;
         case GC_I8_IQ: e = launch_sums<GC_I8_IQ, ND>(a, samples, s); break;
         default: e = launch_sums<GC_I2_REAL, ND>(a, samples, s); break;
     }
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[1], s);
     if (e != hipSuccess) return e;
     const int n_tiles = a->rows_pad / kAcqRows;
     const int gx = (n_tiles + a->tiles_per_wg - 1) / a->tiles_per_wg;
@@ -530,19 +535,28 @@ gc_status gc_acquire(gc_acq* a, const void* samples, uint64_t n_samples, double 
     DeviceGuard g(a->device);
     if (!g.ok) return GC_EDEVICE;
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = a->nd == 2 ? launch_acq_nd<2>(a, samples, s) : launch_acq_nd<4>(a, samples, s);
+    const size_t n_slots = a->ev_used.size();
+    hipEvent_t* ev = n_slots ? &a->ev[5 * (size_t)(a->calls % n_slots)] : nullptr;
+    if (ev) a->ev_used[(size_t)(a->calls % n_slots)] = 1;
+    ++a->calls;
+    hipError_t e = ev ? hipEventRecord(ev[0], s) : hipSuccess;
+    if (e == hipSuccess)
+        e = a->nd == 2 ? launch_acq_nd<2>(a, samples, s, ev) : launch_acq_nd<4>(a, samples, s, ev);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[2], s);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_acq_reduce, dim3(a->n_bins, a->n_prn), dim3(256), 0, s, a->d_pw, a->R,
                            a->n_x, a->n_bins, a->d_chipmax, a->d_chiparg, a->d_binmax, a->d_binarg,
                            surface);
         e = hipGetLastError();
     }
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[3], s);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_acq_detect, dim3(a->n_prn), dim3(256), 0, s, a->d_chipmax, a->d_chiparg,
                            a->d_binmax, a->d_binarg, a->d_prns, a->n_bins, a->R, a->f_lo, a->f_step,
                            threshold, results);
         e = hipGetLastError();
     }
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[4], s);
     return from_hip(e);
 }
 
@@ -554,9 +568,46 @@ gc_status gc_acq_info(gc_acq* a, int32_t* digits, uint64_t* scratch_bytes, uint6
     return GC_OK;
 }
 
+static void acq_drop_timing(gc_acq* a) {
+    for (auto e : a->ev) (void)hipEventDestroy(e);
+    a->ev.clear();
+    a->ev_used.clear();
+}
+
+gc_status gc_acq_timing(gc_acq* a, int32_t n_slots) {
+    if (!a || n_slots < 0 || n_slots > 4096) return GC_EINVAL;
+    DeviceGuard g(a->device);
+    if (!g.ok) return GC_EDEVICE;
+    acq_drop_timing(a);
+    for (int i = 0; i < 5 * n_slots; ++i) {
+        hipEvent_t e;
+        const hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) {
+            acq_drop_timing(a);
+            return from_hip(r);
+        }
+        a->ev.push_back(e);
+    }
+    a->ev_used.assign((size_t)n_slots, 0);
+    a->calls = 0;
+    return GC_OK;
+}
+
+gc_status gc_acq_kernel_ms(gc_acq* a, int32_t slot, float* ms) {
+    if (!a || !ms || slot < 0 || (size_t)slot >= a->ev_used.size() || !a->ev_used[(size_t)slot])
+        return GC_EINVAL;
+    DeviceGuard g(a->device);
+    if (!g.ok) return GC_EDEVICE;
+    const hipEvent_t* ev = &a->ev[5 * (size_t)slot];
+    hipError_t e = hipEventSynchronize(ev[4]);
+    for (int k = 0; k < 4 && e == hipSuccess; ++k) e = hipEventElapsedTime(&ms[k], ev[k], ev[k + 1]);
+    return from_hip(e);
+}
+
 gc_status gc_acq_destroy(gc_acq* a) {
     if (!a) return GC_EINVAL;
     DeviceGuard g(a->device);
+    acq_drop_timing(a);
     void* ptrs[] = {a->d_sd, a->d_codes, a->d_steps, a->d_prns, a->d_pw,
                     a->d_chipmax, a->d_chiparg, a->d_binmax, a->d_binarg};
     for (void* p : ptrs)

@@ -103,6 +103,8 @@ def _load():
         "gc_acquire": ([P, P, U64, D, P, P, P], I32),
         "gc_acq_info": ([P, P, P, P], I32),
         "gc_acq_destroy": ([P], I32),
+        "gc_acq_timing": ([P, I32], I32),
+        "gc_acq_kernel_ms": ([P, I32, P], I32),
         "gc_lock_metrics": ([P, P, I32, I32, P, I32, U32, U32, D, D, P, P, P, U32, P, P, P, P,
                              P, U32, P, P], I32),
     }
@@ -122,7 +124,7 @@ EXPORTED = ("gc_strerror", "gc_version", "gc_create", "gc_destroy", "gc_nco_init
             "gc_server_submit", "gc_server_hold", "gc_server_poll", "gc_server_result", "gc_server_state",
             "gc_server_info", "gc_server_destroy", "gc_server_stats", "gc_loop_init",
             "gc_track", "gc_lock_metrics", "gc_acq_create", "gc_acquire", "gc_acq_info",
-            "gc_acq_destroy")
+            "gc_acq_destroy", "gc_acq_timing", "gc_acq_kernel_ms")
 
 
 def _check(rc: int, where: str):
@@ -395,6 +397,18 @@ def gc_acq_info(acq: int) -> dict:
     ns = C.c_uint64()
     _check(_lib.gc_acq_info(acq, C.byref(dg), C.byref(sb), C.byref(ns)), "gc_acq_info")
     return {"digits": dg.value, "scratch_bytes": sb.value, "samples_needed": ns.value}
+
+
+def gc_acq_timing(acq: int, n_slots: int) -> None:
+    _check(_lib.gc_acq_timing(acq, n_slots), "gc_acq_timing")
+
+
+def gc_acq_kernel_ms(acq: int, slot: int):
+    """Durations (ms) of the four kernels of a timed call: sums, contraction,
+    reduction, detection."""
+    ms = (C.c_float * 4)()
+    _check(_lib.gc_acq_kernel_ms(acq, slot, ms), "gc_acq_kernel_ms")
+    return [float(v) for v in ms]
 
 
 def gc_acq_destroy(acq: int) -> None:
