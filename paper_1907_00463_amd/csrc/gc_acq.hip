@@ -49,10 +49,9 @@ struct gc_acq {
     double f_lo, f_step;
     int n_x;          // bins * R
     int rows_pad;     // operand rows, padded to the row tile
-    int tiles_per_wg;
     uint64_t scratch;
     int8_t* d_sd;     // [Knc][rows_pad][1024] digit rows
-    int8_t* d_codes;  // [n_prn][1024] code chips +-1
+    int8_t* d_codes;  // [n_prn][16][2064] byte-shifted code copies
     uint32_t* d_steps;
     int32_t* d_prns;
     uint64_t* d_pw;       // [n_prn][n_x][1024] power per (bin, r) row and chip column
@@ -76,6 +75,7 @@ constexpr int kAcqCols = 256;        // columns per block (64 per wave)
 constexpr int kAcqKc = 128;          // contraction chunk staged per step
 constexpr int kAcqARow = 144;        // staged row stride: 8 rows of one read hit distinct banks
 constexpr int kAcqK = 1024;          // chips, padded (chip 1023 of every row is 0)
+constexpr int kAcqTabBytes = 16 * kAcqTabStride;  // one PRN's code copies
 static_assert(kAcqTabStride % 16 == 0 && kAcqTabStride >= 2032, "aligned reads up to chip 2046");
 static_assert(kAcqARow % 16 == 0, "aligned row reads");
 
@@ -161,121 +161,154 @@ __global__ __launch_bounds__(kSumThreads) void k_acq_sums(const uint8_t* __restr
     }
 }
 
+// Work item of block L when blocks are dealt to the 8 XCDs in turn (block L
+// runs on XCD L mod 8): XCD x takes the x-th contiguous range of items in
+// (row tile, PRN, column block) order, so the blocks that read one row tile
+// of the operand share an L2.
+__device__ __forceinline__ int xcd_item(int L, int G) {
+    const int x = L & 7, k = L >> 3;
+    int start = 0;
+    for (int y = 0; y < x; ++y) start += (G - y + 7) >> 3;
+    return start + k;
+}
+
+// One block: a 128-row tile of the operand against 256 columns of one PRN;
+// wave w takes columns 64 w .. 64 w + 63 of all 128 rows (4 x 2 MFMA
+// blocks).  Row chunks (128 rows x 128 chips) are staged through two LDS
+// buffers with the next chunk's global loads in flight during the current
+// chunk's MFMAs.
 template <int ND>
 __global__ __launch_bounds__(256) void k_acq_corr(const int8_t* __restrict__ sd,
                                                   const int8_t* __restrict__ codes,
                                                   uint64_t* __restrict__ pw, int rows_pad, int n_x,
-                                                  int knc, int tiles_per_wg) {
-    __shared__ __align__(16) int8_t s_tab[16 * kAcqTabStride];
-    __shared__ __align__(16) int8_t s_a[kAcqRows * kAcqARow];
+                                                  int n_prn, int knc) {
+    __shared__ __align__(16) int8_t s_tab[kAcqTabBytes];
+    __shared__ __align__(16) int8_t s_a[2][kAcqRows * kAcqARow];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int l32 = lane & 31, h = lane >> 5;
-    const int p = blockIdx.z;
-    const int colw = blockIdx.y * kAcqCols + 64 * wave;
-    const int8_t* code = codes + (uint64_t)p * kAcqK;
-    // copy a, byte i = code[(i + a) mod 1023]: a lane's chips o .. o+15 are
-    // bytes (o & ~15) .. +15 of copy (o & 15)
-    for (int idx = tid; idx < 16 * kAcqTabStride / 4; idx += 256) {
-        const int a = idx / (kAcqTabStride / 4);
-        const int i = 4 * (idx - a * (kAcqTabStride / 4)) + a;
-        uint32_t v = 0;
+    constexpr int kColBlocks = kAcqK / kAcqCols;
+    const int item = xcd_item(blockIdx.x, gridDim.x);
+    const int cb = item % kColBlocks;
+    const int p = (item / kColBlocks) % n_prn;
+    const int tile = item / (kColBlocks * n_prn);
+    const int row0 = tile * kAcqRows;
+    const int colw = cb * kAcqCols + 64 * wave;
+    {
+        // the PRN's 16 byte-shifted code copies (copy a, byte i = chip
+        // (i + a) mod 1023), prepared at plan creation: a lane's chips
+        // o .. o + 15 are bytes (o & ~15) .. + 15 of copy (o & 15)
+        const int4v* src = reinterpret_cast<const int4v*>(codes + (uint64_t)p * kAcqTabBytes);
+        int4v* dst = reinterpret_cast<int4v*>(s_tab);
+        constexpr int kPieces = kAcqTabBytes / 16, kPer = (kPieces + 255) / 256;
+        int4v v[kPer];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) v |= (uint32_t)(uint8_t)code[(i + k) % kCodeLen] << (8 * k);
-        reinterpret_cast<uint32_t*>(s_tab)[idx] = v;
+        for (int e = 0; e < kPer; ++e)
+            if (tid + 256 * e < kPieces) v[e] = src[tid + 256 * e];
+#pragma unroll
+        for (int e = 0; e < kPer; ++e)
+            if (tid + 256 * e < kPieces) dst[tid + 256 * e] = v[e];
     }
     constexpr int NP = ND == 2 ? 4 : 2;  // powers per lane per 32x32 block
-    const int n_tiles = rows_pad / kAcqRows;
-    const int t_end = min(n_tiles, (int)(blockIdx.x + 1) * tiles_per_wg);
-    for (int tile = blockIdx.x * tiles_per_wg; tile < t_end; ++tile) {
-        const int row0 = tile * kAcqRows;
-        uint64_t pacc[4][2][NP];
+    constexpr int kChunks = kAcqK / kAcqKc;
+    static_assert(kChunks % 2 == 0, "buffer parity follows the chunk index within a block");
+    uint64_t pacc[4][2][NP];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int q = 0; q < NP; ++q) pacc[t][ct][q] = 0;
+    // chunk g = b * kChunks + kc of the row tile: 128 rows x 128 bytes, one
+    // 16-byte piece per thread and step
+    auto load = [&](int gch, int4v* st) {
+        const int b = gch / kChunks, kc = (gch % kChunks) * kAcqKc;
+        const int8_t* src = sd + ((uint64_t)b * rows_pad + row0) * kAcqK + kc;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int idx = tid + 256 * e;
+            st[e] = *reinterpret_cast<const int4v*>(src + (uint64_t)(idx >> 3) * kAcqK + 16 * (idx & 7));
+        }
+    };
+    int4v stage[4];
+    load(0, stage);
+    for (int b = 0; b < knc; ++b) {
+        int16v acc[4][2];
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
             for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
-                for (int q = 0; q < NP; ++q) pacc[t][ct][q] = 0;
-        for (int b = 0; b < knc; ++b) {
-            int16v acc[4][2];
+                for (int e = 0; e < 16; ++e) acc[t][ct][e] = 0;
+        for (int kq = 0; kq < kChunks; ++kq) {
+            const int kc = kq * kAcqKc;
+            int8_t* buf = s_a[kq & 1];
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
-#pragma unroll
-                for (int ct = 0; ct < 2; ++ct)
-#pragma unroll
-                    for (int e = 0; e < 16; ++e) acc[t][ct][e] = 0;
-            const int8_t* src = sd + ((uint64_t)b * rows_pad + row0) * kAcqK;
-            for (int kc = 0; kc < kAcqK; kc += kAcqKc) {
-                int4v stage[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int idx = tid + 256 * e;  // 128 rows x 8 pieces of 16 bytes
-                    stage[e] = *reinterpret_cast<const int4v*>(src + (uint64_t)(idx >> 3) * kAcqK + kc +
-                                                               16 * (idx & 7));
-                }
-                __syncthreads();  // the previous chunk's readers are done
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int idx = tid + 256 * e;
-                    *reinterpret_cast<int4v*>(s_a + (idx >> 3) * kAcqARow + 16 * (idx & 7)) = stage[e];
-                }
-                __syncthreads();
-#pragma unroll
-                for (int ks = 0; ks < kAcqKc / 32; ++ks) {
-                    int4v bf[2], af[4];
-#pragma unroll
-                    for (int ct = 0; ct < 2; ++ct) {
-                        const int o = kc + 32 * ks + 16 * h + colw + 32 * ct + l32;
-                        bf[ct] = *reinterpret_cast<const int4v*>(s_tab + (o & 15) * kAcqTabStride + (o & ~15));
-                    }
-#pragma unroll
-                    for (int t = 0; t < 4; ++t)
-                        af[t] = *reinterpret_cast<const int4v*>(s_a + (32 * t + l32) * kAcqARow + 32 * ks + 16 * h);
-#pragma unroll
-                    for (int t = 0; t < 4; ++t)
-#pragma unroll
-                        for (int ct = 0; ct < 2; ++ct)
-                            acc[t][ct] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[t], bf[ct], acc[t][ct], 0, 0, 0);
-                }
+            for (int e = 0; e < 4; ++e) {
+                const int idx = tid + 256 * e;
+                *reinterpret_cast<int4v*>(buf + (idx >> 3) * kAcqARow + 16 * (idx & 7)) = stage[e];
             }
-            // block done: recombine digits and add |Y|^2.  Element e of a
-            // 32x32 block holds row 8 (e / 4) + 4 h + e % 4, column l32.
+            // one barrier per chunk: the buffer written next was last read
+            // two chunks ago, before every wave passed this barrier (the
+            // first also publishes the code copies)
+            __syncthreads();
+            const int gnext = b * kChunks + kq + 1;
+            if (gnext < knc * kChunks) load(gnext, stage);
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
+            for (int ks = 0; ks < kAcqKc / 32; ++ks) {
+                int4v bf[2], af[4];
 #pragma unroll
-                for (int ct = 0; ct < 2; ++ct)
+                for (int ct = 0; ct < 2; ++ct) {
+                    const int o = kc + 32 * ks + 16 * h + colw + 32 * ct + l32;
+                    bf[ct] = *reinterpret_cast<const int4v*>(s_tab + (o & 15) * kAcqTabStride + (o & ~15));
+                }
 #pragma unroll
-                    for (int q = 0; q < NP; ++q) {
-                        int64_t yi, yq;
-                        if constexpr (ND == 2) {
-                            yi = (int64_t)acc[t][ct][4 * q] + 128 * (int64_t)acc[t][ct][4 * q + 1];
-                            yq = (int64_t)acc[t][ct][4 * q + 2] + 128 * (int64_t)acc[t][ct][4 * q + 3];
-                        } else {
-                            yi = 0;
-                            yq = 0;
+                for (int t = 0; t < 4; ++t)
+                    af[t] = *reinterpret_cast<const int4v*>(buf + (32 * t + l32) * kAcqARow + 32 * ks + 16 * h);
 #pragma unroll
-                            for (int s = 3; s >= 0; --s) {
-                                yi = yi * 128 + (int64_t)acc[t][ct][8 * q + s];
-                                yq = yq * 128 + (int64_t)acc[t][ct][8 * q + 4 + s];
-                            }
-                        }
-                        pacc[t][ct][q] += (uint64_t)(yi * yi) + (uint64_t)(yq * yq);
-                    }
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int ct = 0; ct < 2; ++ct)
+                        acc[t][ct] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[t], bf[ct], acc[t][ct], 0, 0, 0);
+            }
         }
+        // block done: recombine digits and add |Y|^2.  Element e of a 32x32
+        // block holds row 8 (e / 4) + 4 h + e % 4, column l32.
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
             for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
                 for (int q = 0; q < NP; ++q) {
-                    // two digits: X = (row0 + 32 t + 8 q + 4 h) / 4; four
-                    // digits: X = (row0 + 32 t) / 8 + 2 q + h
-                    const int X = ND == 2 ? (row0 + 32 * t + 8 * q + 4 * h) / 4
-                                          : (row0 + 32 * t) / 8 + 2 * q + h;
-                    const int col = colw + 32 * ct + l32;
-                    if (X < n_x && col < kCodeLen)
-                        pw[((uint64_t)p * n_x + X) * kAcqK + col] = pacc[t][ct][q];
+                    int64_t yi, yq;
+                    if constexpr (ND == 2) {
+                        yi = (int64_t)acc[t][ct][4 * q] + 128 * (int64_t)acc[t][ct][4 * q + 1];
+                        yq = (int64_t)acc[t][ct][4 * q + 2] + 128 * (int64_t)acc[t][ct][4 * q + 3];
+                    } else {
+                        yi = 0;
+                        yq = 0;
+#pragma unroll
+                        for (int s = 3; s >= 0; --s) {
+                            yi = yi * 128 + (int64_t)acc[t][ct][8 * q + s];
+                            yq = yq * 128 + (int64_t)acc[t][ct][8 * q + 4 + s];
+                        }
+                    }
+                    pacc[t][ct][q] += (uint64_t)(yi * yi) + (uint64_t)(yq * yq);
                 }
     }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                // two digits: X = (row0 + 32 t + 8 q + 4 h) / 4; four
+                // digits: X = (row0 + 32 t) / 8 + 2 q + h
+                const int X = ND == 2 ? (row0 + 32 * t + 8 * q + 4 * h) / 4
+                                      : (row0 + 32 * t) / 8 + 2 * q + h;
+                const int col = colw + 32 * ct + l32;
+                if (X < n_x && col < kCodeLen)
+                    pw[((uint64_t)p * n_x + X) * kAcqK + col] = pacc[t][ct][q];
+            }
 }
 
 // Largest value and lowest index on ties, over a 256-thread block.
@@ -389,14 +422,16 @@ __global__ __launch_bounds__(256) void k_acq_detect(const uint64_t* __restrict__
     }
 }
 
-// Code chips of each searched PRN as int8 +-1 (chip 1023: 0), from the
-// context's sign table.
+// The 16 byte-shifted copies of each searched PRN's code (copy a, byte i =
+// chip (i + a) mod 1023 as int8 +-1), from the context's sign table.
 __global__ void k_acq_codes(const uint32_t* __restrict__ tables, const int32_t* __restrict__ prns,
-                            int8_t* __restrict__ codes) {
+                            int8_t* __restrict__ tabs) {
     const int p = blockIdx.x;
     const uint32_t* sign = tables + kTabSign + (uint64_t)(prns[p] - 1) * kSignLen;
-    for (int i = threadIdx.x; i < kAcqK; i += blockDim.x)
-        codes[(uint64_t)p * kAcqK + i] = i < kCodeLen ? (int8_t)(int16_t)(sign[i] & 0xFFFF) : 0;
+    for (int idx = threadIdx.x; idx < kAcqTabBytes; idx += blockDim.x) {
+        const int a = idx / kAcqTabStride, i = idx - a * kAcqTabStride;
+        tabs[(uint64_t)p * kAcqTabBytes + idx] = (int8_t)(int16_t)(sign[(i + a) % kCodeLen] & 0xFFFF);
+    }
 }
 
 template <int FMT, int ND>
@@ -417,10 +452,9 @@ hipError_t launch_acq_nd(const gc_acq* a, const void* samples, hipStream_t s, hi
     }
     if (e == hipSuccess && ev) e = hipEventRecord(ev[1], s);
     if (e != hipSuccess) return e;
-    const int n_tiles = a->rows_pad / kAcqRows;
-    const int gx = (n_tiles + a->tiles_per_wg - 1) / a->tiles_per_wg;
-    hipLaunchKernelGGL((k_acq_corr<ND>), dim3(gx, kAcqK / kAcqCols, a->n_prn), dim3(256), 0, s,
-                       a->d_sd, a->d_codes, a->d_pw, a->rows_pad, a->n_x, a->Knc, a->tiles_per_wg);
+    const int n_items = a->rows_pad / kAcqRows * (kAcqK / kAcqCols) * a->n_prn;
+    hipLaunchKernelGGL((k_acq_corr<ND>), dim3(n_items), dim3(256), 0, s, a->d_sd, a->d_codes,
+                       a->d_pw, a->rows_pad, a->n_x, a->n_prn, a->Knc);
     return hipGetLastError();
 }
 
@@ -474,9 +508,6 @@ gc_status gc_acq_create(gc_ctx* ctx, gc_format fmt, int32_t samples_per_chip, do
     a->n_x = n_bins * R;
     const int rows = nd == 2 ? 4 * a->n_x : 16 * ((a->n_x + 1) / 2);
     a->rows_pad = (rows + kAcqRows - 1) / kAcqRows * kAcqRows;
-    const int n_tiles = a->rows_pad / kAcqRows;
-    // about four blocks per compute unit, each walking whole row tiles
-    a->tiles_per_wg = std::max(1, n_tiles * (kAcqK / kAcqCols) * n_prn / 1024);
 
     std::vector<uint32_t> steps((size_t)n_bins);
     const double fs = (double)R * 1.023e6;
@@ -492,14 +523,14 @@ gc_status gc_acq_create(gc_ctx* ctx, gc_format fmt, int32_t samples_per_chip, do
     const uint64_t sd_bytes = (uint64_t)Knc * a->rows_pad * kAcqK;
     const uint64_t pw_bytes = (uint64_t)n_prn * a->n_x * kAcqK * 8;
     const uint64_t pb = (uint64_t)n_prn * n_bins;
-    a->scratch = sd_bytes + pw_bytes + pb * kAcqK * 9 + pb * 12 + (uint64_t)n_prn * (kAcqK + 4) +
+    a->scratch = sd_bytes + pw_bytes + pb * kAcqK * 9 + pb * 12 + (uint64_t)n_prn * (kAcqTabBytes + 4) +
                  4ull * n_bins;
     hipError_t e = hipSuccess;
     auto alloc = [&](void** p, uint64_t bytes) {
         if (e == hipSuccess) e = hipMalloc(p, bytes);
     };
     alloc((void**)&a->d_sd, sd_bytes);
-    alloc((void**)&a->d_codes, (uint64_t)n_prn * kAcqK);
+    alloc((void**)&a->d_codes, (uint64_t)n_prn * kAcqTabBytes);
     alloc((void**)&a->d_steps, 4ull * n_bins);
     alloc((void**)&a->d_prns, 4ull * n_prn);
     alloc((void**)&a->d_pw, pw_bytes);
