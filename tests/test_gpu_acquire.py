@@ -84,6 +84,24 @@ def test_acquire_random_bytes_bit_exact(g, ctx, fmt, R, Mc, Knc, bins, digits):
     _same_detection(r, A.detect(want, R, -3000.0, 750.0, 2.5), prns)
 
 
+@pytest.mark.parametrize("fmt,R,Mc,Knc,bins,digits", [
+    (1, 20, 1, 2, 3, 4),    # complex int8 at 20.46 MHz: 4 digits
+    (2, 32, 1, 1, 2, 2),    # the largest samples-per-chip, 2-bit
+    (2, 32, 7, 1, 1, 2),    # 7 periods at R = 32: |S| <= 16128, still 2 digits
+])
+def test_acquire_large_rates(g, ctx, fmt, R, Mc, Knc, bins, digits):
+    rng = np.random.default_rng(7 * R + fmt)
+    n = Knc * Mc * 1023 * R
+    buf = rng.integers(0, 256, _bytes(fmt, n), dtype=np.uint8)
+    if_hz = 0.0 if fmt == 1 else 0.25 * R * 1.023e6
+    prns = [11, 28]
+    P, r, info = _gpu(g, ctx, fmt, buf, n, R, if_hz, -2500.0, 2500.0, bins, prns, Mc, Knc)
+    assert info["digits"] == digits
+    want = A.search(fmt, buf, R, if_hz, -2500.0, 2500.0, bins, prns, Mc, Knc)
+    assert np.array_equal(P, want)
+    _same_detection(r, A.detect(want, R, -2500.0, 2500.0, 2.5), prns)
+
+
 def test_acquire_single_channel_signal(g, ctx):
     # PRN 7 at +1.5 kHz, 300.25 chips, 45 dB-Hz, int8 at 4.092 MHz; a search
     # of 8 PRNs over +-5 kHz in 500 Hz bins, 1 ms coherent, 4 blocks
