@@ -405,7 +405,7 @@ typedef struct {
  *   blocks               Knc, 1 .. 1000 (non-coherent sum)
  * The bounds on the exact integer arithmetic: Mc * R * max|w| < 2^28, where
  * max|w| is 72 for 2-bit, 3072 for int8 real and 4352 for int8 I/Q, and
- * Knc * 2 * (Mc * N * max|w|)^2 < 1.8e19.
+ * Knc * 2 * (Mc * N * max|w|)^2 < 9.0e18.
  * Errors: GC_EINVAL (null pointers, values out of range, bounds),
  * GC_ENOMEM, GC_EDEVICE. */
 gc_status gc_acq_create(gc_ctx* ctx, gc_format fmt, int32_t samples_per_chip, double if_hz,

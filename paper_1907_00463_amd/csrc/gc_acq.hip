@@ -211,7 +211,7 @@ __global__ __launch_bounds__(256) void k_acq_corr(const int8_t* __restrict__ sd,
     constexpr int NP = ND == 2 ? 4 : 2;  // powers per lane per 32x32 block
     constexpr int kChunks = kAcqK / kAcqKc;
     static_assert(kChunks % 2 == 0, "buffer parity follows the chunk index within a block");
-    uint64_t pacc[4][2][NP];
+    int64_t pacc[4][2][NP];  // below 2^63 by the plan's bound
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -279,20 +279,20 @@ __global__ __launch_bounds__(256) void k_acq_corr(const int8_t* __restrict__ sd,
             for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
                 for (int q = 0; q < NP; ++q) {
-                    int64_t yi, yq;
                     if constexpr (ND == 2) {
-                        yi = (int64_t)acc[t][ct][4 * q] + 128 * (int64_t)acc[t][ct][4 * q + 1];
-                        yq = (int64_t)acc[t][ct][4 * q + 2] + 128 * (int64_t)acc[t][ct][4 * q + 3];
+                        // |Y| <= 1023 * 2^14: int32, and one 32x32+64 multiply-add per square
+                        const int32_t yi = acc[t][ct][4 * q] + 128 * acc[t][ct][4 * q + 1];
+                        const int32_t yq = acc[t][ct][4 * q + 2] + 128 * acc[t][ct][4 * q + 3];
+                        pacc[t][ct][q] += (int64_t)yi * yi + (int64_t)yq * yq;
                     } else {
-                        yi = 0;
-                        yq = 0;
+                        int64_t yi = 0, yq = 0;
 #pragma unroll
                         for (int s = 3; s >= 0; --s) {
                             yi = yi * 128 + (int64_t)acc[t][ct][8 * q + s];
                             yq = yq * 128 + (int64_t)acc[t][ct][8 * q + 4 + s];
                         }
+                        pacc[t][ct][q] += yi * yi + yq * yq;
                     }
-                    pacc[t][ct][q] += (uint64_t)(yi * yi) + (uint64_t)(yq * yq);
                 }
     }
 #pragma unroll
@@ -307,7 +307,7 @@ __global__ __launch_bounds__(256) void k_acq_corr(const int8_t* __restrict__ sd,
                                       : (row0 + 32 * t) / 8 + 2 * q + h;
                 const int col = colw + 32 * ct + l32;
                 if (X < n_x && col < kCodeLen)
-                    pw[((uint64_t)p * n_x + X) * kAcqK + col] = pacc[t][ct][q];
+                    pw[((uint64_t)p * n_x + X) * kAcqK + col] = (uint64_t)pacc[t][ct][q];
             }
 }
 
@@ -489,7 +489,7 @@ gc_status gc_acq_create(gc_ctx* ctx, gc_format fmt, int32_t samples_per_chip, do
     else if (smax < 268435456.0) nd = 4;
     else return GC_EINVAL;
     const double ymax = (double)Mc * kCodeLen * R * maxw;
-    if (2.0 * ymax * ymax * (double)Knc >= 1.8e19) return GC_EINVAL;
+    if (2.0 * ymax * ymax * (double)Knc >= 9.0e18) return GC_EINVAL;  // power sums below 2^63
 
     DeviceGuard g(ctx->device);
     if (!g.ok) return GC_EDEVICE;
