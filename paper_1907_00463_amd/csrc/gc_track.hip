@@ -20,6 +20,10 @@ namespace {
 
 constexpr int kThreads = 1024;
 constexpr int kWaves = kThreads / 64;
+constexpr int kStageBytes = 32768;             // LDS sample window per step
+constexpr int kStagePieces = kStageBytes / 16;
+static_assert(kStagePieces % kThreads == 0, "whole 16-byte pieces per thread");
+typedef int int4v __attribute__((ext_vector_type(4)));
 constexpr double kQ30 = 1073741824.0;
 
 __device__ __forceinline__ int64_t iabs64(int64_t v) { return v < 0 ? -v : v; }
@@ -172,15 +176,19 @@ __global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ 
                                                     uint32_t max_dumps,
                                                     const uint32_t* __restrict__ tables) {
     __shared__ uint32_t s_lut[256];
-    __shared__ int8_t s_code[kCodeLen + 1];
+    __shared__ uint32_t s_code3[kCodeLen];  // chip c: bytes C[c-1], C[c], C[c+1]
     __shared__ int32_t s_red[6][kWaves];
     __shared__ Ctl ctl;
+    __shared__ __align__(16) uint8_t s_stage[kStageBytes];
     const int tid = threadIdx.x;
     const int chn = blockIdx.x;
     const DevChan& ch = chans[chn];
     for (int i = tid; i < 256; i += kThreads) s_lut[i] = tables[kTabLut + i];
     const uint32_t* sgn = tables + kTabSign + (ch.prn - 1) * kSignLen;
-    for (int i = tid; i < kCodeLen; i += kThreads) s_code[i] = (int8_t)(int16_t)(sgn[i] & 0xFFFF);
+    for (int i = tid; i < kCodeLen; i += kThreads) {
+        const int im = i == 0 ? kCodeLen - 1 : i - 1, ip = i + 1 == kCodeLen ? 0 : i + 1;
+        s_code3[i] = (sgn[im] & 0xFFu) | (sgn[i] & 0xFFu) << 8 | (sgn[ip] & 0xFFu) << 16;
+    }
     const uint64_t W = ch.window;
     gc_chan_state* st = states + chn;
     gc_loop_state L;   // thread 0's copy
@@ -219,30 +227,75 @@ __global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ 
         }
         return;
     }
+    // The samples pass through LDS in windows of kStageBytes bytes that start
+    // at the 16-byte boundary below the first sample of a step; the window of
+    // the next step (which starts where this one ends) is loaded into
+    // registers while this step is summed and the loops are updated.
+    // samples whose bytes fit a window from any start (at most 15 bytes of
+    // alignment before the first)
+    constexpr uint32_t kStageSamples = FMT == GC_I2_REAL ? 4 * (kStageBytes - 17)
+                                       : FMT == GC_I8_IQ ? (kStageBytes - 16) / 2
+                                                         : kStageBytes - 16;
+    const uint64_t nbytes = FMT == GC_I2_REAL ? (n + 3) / 4 : FMT == GC_I8_IQ ? 2 * n : n;
+    auto byte_of = [](uint64_t smp) -> uint64_t {
+        return FMT == GC_I2_REAL ? smp >> 2 : FMT == GC_I8_IQ ? 2 * smp : smp;
+    };
+    int4v pf[kStagePieces / kThreads];
+    auto load_window = [&](uint64_t first) {
+        const uint64_t b0 = byte_of(first) & ~(uint64_t)15;
+#pragma unroll
+        for (int e = 0; e < kStagePieces / kThreads; ++e) {
+            const uint64_t b = b0 + 16 * (uint64_t)(tid + kThreads * e);
+            if (b + 16 <= nbytes) {
+                pf[e] = *reinterpret_cast<const int4v*>(samples + b);
+            } else {
+                uint32_t w[4] = {0, 0, 0, 0};
+                for (int k = 0; k < 16 && b + k < nbytes; ++k) w[k >> 2] |= (uint32_t)samples[b + k] << (8 * (k & 3));
+                pf[e] = int4v{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
+            }
+        }
+    };
+    load_window(0);
     while (true) {
         const uint64_t p = ctl.p, dp = ctl.dp, s0 = ctl.s;
         const uint32_t phi = ctl.phi, dphi = ctl.dphi;
         const uint64_t need = (W - p + dp - 1) / dp;     // samples until the phase reaches W
-        const uint64_t take = min(need, n - s0);
+        const uint64_t take = min(min(need, n - s0), (uint64_t)kStageSamples);
+#pragma unroll
+        for (int e = 0; e < kStagePieces / kThreads; ++e)
+            reinterpret_cast<int4v*>(s_stage)[tid + kThreads * e] = pf[e];
+        __syncthreads();
+        load_window(s0 + take);
+        const uint64_t b0 = byte_of(s0) & ~(uint64_t)15;
         int32_t a[6] = {0, 0, 0, 0, 0, 0};
-        for (uint64_t i = tid; i < take; i += kThreads) {
+        for (uint32_t i = tid; i < (uint32_t)take; i += kThreads) {
             int xi, xq;
-            load_sample<FMT>(samples, s0 + i, xi, xq);
+            const uint64_t smp = s0 + i;
+            const uint32_t off = (uint32_t)(byte_of(smp) - b0);
+            if constexpr (FMT == GC_I8_REAL) {
+                xi = (int)(int8_t)s_stage[off];
+                xq = 0;
+            } else if constexpr (FMT == GC_I8_IQ) {
+                xi = (int)(int8_t)s_stage[off];
+                xq = (int)(int8_t)s_stage[off + 1];
+            } else {
+                xi = 2 * (int)((s_stage[off] >> (2 * (smp & 3))) & 3) - 3;
+                xq = 0;
+            }
             int c, sn;
-            lut_cs(s_lut[(phi + (uint32_t)i * dphi) >> 24], c, sn);
+            lut_cs(s_lut[(phi + i * dphi) >> 24], c, sn);
             int wi, wq;
             wipe<FMT>(xi, xq, c, sn, wi, wq);
             // prompt chip floor(u / 2^32) mod 1023; the early (late) chip is
             // the next (previous) one when u's fraction is at or above
             // (below) one half chip
-            const uint64_t u = p + i * dp;
+            const uint64_t u = p + (uint64_t)i * dp;
             const uint32_t cp = (uint32_t)((u >> 32) % kCodeLen);
-            const bool upper = (uint32_t)u >= (1u << 31);
-            const uint32_t ce = upper ? (cp + 1 == kCodeLen ? 0u : cp + 1) : cp;
-            const uint32_t cl = upper ? cp : (cp == 0 ? kCodeLen - 1 : cp - 1);
-            const int re = s_code[ce];
-            const int rp = s_code[cp];
-            const int rl = s_code[cl];
+            const int sh = (uint32_t)u >= (1u << 31) ? 8 : 0;
+            const uint32_t c3 = s_code3[cp];
+            const int re = (int)(int8_t)(c3 >> (8 + sh));
+            const int rp = (int)(int8_t)(c3 >> 8);
+            const int rl = (int)(int8_t)(c3 >> sh);
             a[0] += wi * re;
             a[1] += wq * re;
             a[2] += wi * rp;
