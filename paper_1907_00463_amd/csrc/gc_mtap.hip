@@ -233,16 +233,21 @@ __device__ __forceinline__ void scatter_step(uint8_t* lds, uint32_t xaddr, uint3
     if (CHECK && !valid) return;
     const uint2 xw = *reinterpret_cast<const uint2*>(lds + xaddr);
     const uint32_t cs = *reinterpret_cast<const uint32_t*>(lds + lut_base + ((ph >> 24) << 2));
-    const int wi = __builtin_amdgcn_sdot2(as_s2(xw.x), as_s2(cs), 0, false);
-    const int wq = __builtin_amdgcn_sdot2(as_s2(xw.y), as_s2(cs), 0, false);
-    // low 16 bits of wi and wq (|w| < 2^15), then per half: bits 0-5 stay,
-    // bits 6-13 move to the upper byte (w >> 6 as a two's complement byte)
-    const uint32_t h = __builtin_amdgcn_perm((uint32_t)wq, (uint32_t)wi, 0x05040100u);
+    // (wI, wQ) = (xI, xQ) c + (xQ, -xI) s as int16 pairs: every product and
+    // sum stays below 2^15 in magnitude (|x c| <= 3072, |w| <= 4352), so the
+    // 16-bit lanes hold the exact values
+    const short2_t c2 = as_s2(cs);
+    const short2_t cc = __builtin_shufflevector(c2, c2, 0, 0);
+    const short2_t ss = __builtin_shufflevector(c2, c2, 1, 1);
+    const short2_t w2 = as_s2(xw.x) * cc + as_s2(xw.y) * ss;
+    // per half: bits 0-5 stay, bits 6-13 move to the upper byte (w >> 6 as a
+    // two's complement byte)
+    const uint32_t h = __builtin_bit_cast(uint32_t, w2);
     const uint32_t cell = ((h << 2) & 0xFF00FF00u) | (h & 0x003F003Fu);
     // row q, column chip - cs: cbase = s_base - 4*cs (mod 2^32)
-    const uint2 u2 = __builtin_bit_cast(uint2, U);
-    const uint32_t q = u2.x >> 27;
-    const uint32_t a = __umul24(q, kRowBytes) + ((u2.y << 2) + cbase);
+    const uint32_t lo = (uint32_t)U, hi = (uint32_t)(U >> 32);
+    const uint32_t q = lo >> 27;
+    const uint32_t a = __umul24(q, kRowBytes) + (hi * 4u + cbase);
     *reinterpret_cast<uint32_t*>(lds + a) = cell;
 }
 
