@@ -422,9 +422,11 @@ gc_status gc_acquire(gc_acq* acq, const void* samples, uint64_t n_samples, doubl
                      uint64_t* surface, gc_acq_result* results, void* stream);
 
 /* Query (any pointer may be NULL): int8 digits per box sum (2 or 4), device
- * scratch bytes, samples a call reads.  Errors: GC_EINVAL. */
+ * scratch bytes, samples a call reads, operand rows per block of the
+ * contraction (96 or 128, chosen at creation for the fewest rows in the
+ * last round of blocks).  Errors: GC_EINVAL. */
 gc_status gc_acq_info(gc_acq* acq, int32_t* digits, uint64_t* scratch_bytes,
-                      uint64_t* samples_needed);
+                      uint64_t* samples_needed, int32_t* row_tile);
 
 /* Per-kernel timing of gc_acquire: with n_slots > 0 every later call records
  * HIP events on its stream before and after each of its four kernels (box

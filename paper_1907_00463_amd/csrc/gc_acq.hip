@@ -48,6 +48,7 @@ struct gc_acq {
     int fmt, R, n_bins, n_prn, Mc, Knc, nd;
     double f_lo, f_step;
     int n_x;          // bins * R
+    int nt;           // MFMA row blocks per tile (3 or 4)
     int rows_pad;     // operand rows, padded to the row tile
     uint64_t scratch;
     int8_t* d_sd;     // [Knc][rows_pad][1024] digit rows
@@ -70,7 +71,6 @@ namespace gc {
 namespace {
 
 constexpr int kAcqTabStride = 2064;  // bytes per code copy; = 16 mod 128 spreads the copies over banks
-constexpr int kAcqRows = 128;        // operand rows per tile (4 MFMA row blocks)
 constexpr int kAcqCols = 256;        // columns per block (64 per wave)
 constexpr int kAcqKc = 128;          // contraction chunk staged per step
 constexpr int kAcqARow = 144;        // staged row stride: 8 rows of one read hit distinct banks
@@ -172,18 +172,19 @@ __device__ __forceinline__ int xcd_item(int L, int G) {
     return start + k;
 }
 
-// One block: a 128-row tile of the operand against 256 columns of one PRN;
-// wave w takes columns 64 w .. 64 w + 63 of all 128 rows (4 x 2 MFMA
-// blocks).  Row chunks (128 rows x 128 chips) are staged through two LDS
+// One block: a tile of 32 NT operand rows against 256 columns of one PRN;
+// wave w takes columns 64 w .. 64 w + 63 of all the tile's rows (NT x 2
+// MFMA blocks).  Row chunks (128 rows x 128 chips) are staged through two LDS
 // buffers with the next chunk's global loads in flight during the current
 // chunk's MFMAs.
-template <int ND>
+template <int ND, int NT>
 __global__ __launch_bounds__(256) void k_acq_corr(const int8_t* __restrict__ sd,
                                                   const int8_t* __restrict__ codes,
                                                   uint64_t* __restrict__ pw, int rows_pad, int n_x,
                                                   int n_prn, int knc) {
     __shared__ __align__(16) int8_t s_tab[kAcqTabBytes];
-    __shared__ __align__(16) int8_t s_a[2][kAcqRows * kAcqARow];
+    constexpr int kRows = 32 * NT;  // operand rows of a tile (NT MFMA row blocks)
+    __shared__ __align__(16) int8_t s_a[2][kRows * kAcqARow];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int l32 = lane & 31, h = lane >> 5;
     constexpr int kColBlocks = kAcqK / kAcqCols;
@@ -191,7 +192,7 @@ __global__ __launch_bounds__(256) void k_acq_corr(const int8_t* __restrict__ sd,
     const int cb = item % kColBlocks;
     const int p = (item / kColBlocks) % n_prn;
     const int tile = item / (kColBlocks * n_prn);
-    const int row0 = tile * kAcqRows;
+    const int row0 = tile * kRows;
     const int colw = cb * kAcqCols + 64 * wave;
     {
         // the PRN's 16 byte-shifted code copies (copy a, byte i = chip
@@ -211,30 +212,30 @@ __global__ __launch_bounds__(256) void k_acq_corr(const int8_t* __restrict__ sd,
     constexpr int NP = ND == 2 ? 4 : 2;  // powers per lane per 32x32 block
     constexpr int kChunks = kAcqK / kAcqKc;
     static_assert(kChunks % 2 == 0, "buffer parity follows the chunk index within a block");
-    int64_t pacc[4][2][NP];  // below 2^63 by the plan's bound
+    int64_t pacc[NT][2][NP];  // below 2^63 by the plan's bound
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
             for (int q = 0; q < NP; ++q) pacc[t][ct][q] = 0;
-    // chunk g = b * kChunks + kc of the row tile: 128 rows x 128 bytes, one
-    // 16-byte piece per thread and step
+    // chunk g = b * kChunks + kc of the row tile: kRows rows x 128 bytes,
+    // NT 16-byte pieces per thread
     auto load = [&](int gch, int4v* st) {
         const int b = gch / kChunks, kc = (gch % kChunks) * kAcqKc;
         const int8_t* src = sd + ((uint64_t)b * rows_pad + row0) * kAcqK + kc;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < NT; ++e) {
             const int idx = tid + 256 * e;
             st[e] = *reinterpret_cast<const int4v*>(src + (uint64_t)(idx >> 3) * kAcqK + 16 * (idx & 7));
         }
     };
-    int4v stage[4];
+    int4v stage[NT];
     load(0, stage);
     for (int b = 0; b < knc; ++b) {
-        int16v acc[4][2];
+        int16v acc[NT][2];
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
+        for (int t = 0; t < NT; ++t)
 #pragma unroll
             for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
@@ -243,7 +244,7 @@ __global__ __launch_bounds__(256) void k_acq_corr(const int8_t* __restrict__ sd,
             const int kc = kq * kAcqKc;
             int8_t* buf = s_a[kq & 1];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
+            for (int e = 0; e < NT; ++e) {
                 const int idx = tid + 256 * e;
                 *reinterpret_cast<int4v*>(buf + (idx >> 3) * kAcqARow + 16 * (idx & 7)) = stage[e];
             }
@@ -255,17 +256,17 @@ __global__ __launch_bounds__(256) void k_acq_corr(const int8_t* __restrict__ sd,
             if (gnext < knc * kChunks) load(gnext, stage);
 #pragma unroll
             for (int ks = 0; ks < kAcqKc / 32; ++ks) {
-                int4v bf[2], af[4];
+                int4v bf[2], af[NT];
 #pragma unroll
                 for (int ct = 0; ct < 2; ++ct) {
                     const int o = kc + 32 * ks + 16 * h + colw + 32 * ct + l32;
                     bf[ct] = *reinterpret_cast<const int4v*>(s_tab + (o & 15) * kAcqTabStride + (o & ~15));
                 }
 #pragma unroll
-                for (int t = 0; t < 4; ++t)
+                for (int t = 0; t < NT; ++t)
                     af[t] = *reinterpret_cast<const int4v*>(buf + (32 * t + l32) * kAcqARow + 32 * ks + 16 * h);
 #pragma unroll
-                for (int t = 0; t < 4; ++t)
+                for (int t = 0; t < NT; ++t)
 #pragma unroll
                     for (int ct = 0; ct < 2; ++ct)
                         acc[t][ct] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[t], bf[ct], acc[t][ct], 0, 0, 0);
@@ -274,7 +275,7 @@ __global__ __launch_bounds__(256) void k_acq_corr(const int8_t* __restrict__ sd,
         // block done: recombine digits and add |Y|^2.  Element e of a 32x32
         // block holds row 8 (e / 4) + 4 h + e % 4, column l32.
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
+        for (int t = 0; t < NT; ++t)
 #pragma unroll
             for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
@@ -296,7 +297,7 @@ __global__ __launch_bounds__(256) void k_acq_corr(const int8_t* __restrict__ sd,
                 }
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
@@ -442,6 +443,14 @@ hipError_t launch_sums(const gc_acq* a, const void* samples, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int ND, int NT>
+hipError_t launch_corr(const gc_acq* a, hipStream_t s) {
+    const int n_items = a->rows_pad / (32 * NT) * (kAcqK / kAcqCols) * a->n_prn;
+    hipLaunchKernelGGL((k_acq_corr<ND, NT>), dim3(n_items), dim3(256), 0, s, a->d_sd, a->d_codes,
+                       a->d_pw, a->rows_pad, a->n_x, a->n_prn, a->Knc);
+    return hipGetLastError();
+}
+
 template <int ND>
 hipError_t launch_acq_nd(const gc_acq* a, const void* samples, hipStream_t s, hipEvent_t* ev) {
     hipError_t e;
@@ -452,10 +461,7 @@ hipError_t launch_acq_nd(const gc_acq* a, const void* samples, hipStream_t s, hi
     }
     if (e == hipSuccess && ev) e = hipEventRecord(ev[1], s);
     if (e != hipSuccess) return e;
-    const int n_items = a->rows_pad / kAcqRows * (kAcqK / kAcqCols) * a->n_prn;
-    hipLaunchKernelGGL((k_acq_corr<ND>), dim3(n_items), dim3(256), 0, s, a->d_sd, a->d_codes,
-                       a->d_pw, a->rows_pad, a->n_x, a->n_prn, a->Knc);
-    return hipGetLastError();
+    return a->nt == 3 ? launch_corr<ND, 3>(a, s) : launch_corr<ND, 4>(a, s);
 }
 
 }  // namespace
@@ -507,7 +513,23 @@ gc_status gc_acq_create(gc_ctx* ctx, gc_format fmt, int32_t samples_per_chip, do
     a->f_step = f_step_hz;
     a->n_x = n_bins * R;
     const int rows = nd == 2 ? 4 * a->n_x : 16 * ((a->n_x + 1) / 2);
-    a->rows_pad = (rows + kAcqRows - 1) / kAcqRows * kAcqRows;
+    // row tile of 96 or 128 rows: the one with fewer tile-rows in its last
+    // round of blocks (two blocks per compute unit run at once)
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess ||
+        cus < 1)
+        cus = 256;
+    int64_t best = -1;
+    for (int nt = 4; nt >= 3; --nt) {
+        const int64_t tiles = (rows + 32 * nt - 1) / (32 * nt);
+        const int64_t items = tiles * (kAcqK / kAcqCols) * n_prn;
+        const int64_t cost = (items + 2 * cus - 1) / (2 * cus) * nt;
+        if (best < 0 || cost < best) {
+            best = cost;
+            a->nt = nt;
+        }
+    }
+    a->rows_pad = (rows + 32 * a->nt - 1) / (32 * a->nt) * (32 * a->nt);
 
     std::vector<uint32_t> steps((size_t)n_bins);
     const double fs = (double)R * 1.023e6;
@@ -591,9 +613,11 @@ gc_status gc_acquire(gc_acq* a, const void* samples, uint64_t n_samples, double 
     return from_hip(e);
 }
 
-gc_status gc_acq_info(gc_acq* a, int32_t* digits, uint64_t* scratch_bytes, uint64_t* samples_needed) {
+gc_status gc_acq_info(gc_acq* a, int32_t* digits, uint64_t* scratch_bytes, uint64_t* samples_needed,
+                      int32_t* row_tile) {
     if (!a) return GC_EINVAL;
     if (digits) *digits = a->nd;
+    if (row_tile) *row_tile = 32 * a->nt;
     if (scratch_bytes) *scratch_bytes = a->scratch;
     if (samples_needed) *samples_needed = (uint64_t)a->Knc * a->Mc * kCodeLen * a->R;
     return GC_OK;

@@ -101,7 +101,7 @@ def _load():
         "gc_track": ([P, P, U64, P, P, P, P, P, P, P, U32, P], I32),
         "gc_acq_create": ([P, I32, I32, D, D, D, I32, P, I32, I32, I32, P], I32),
         "gc_acquire": ([P, P, U64, D, P, P, P], I32),
-        "gc_acq_info": ([P, P, P, P], I32),
+        "gc_acq_info": ([P, P, P, P, P], I32),
         "gc_acq_destroy": ([P], I32),
         "gc_acq_timing": ([P, I32], I32),
         "gc_acq_kernel_ms": ([P, I32, P], I32),
@@ -395,8 +395,11 @@ def gc_acq_info(acq: int) -> dict:
     dg = C.c_int32()
     sb = C.c_uint64()
     ns = C.c_uint64()
-    _check(_lib.gc_acq_info(acq, C.byref(dg), C.byref(sb), C.byref(ns)), "gc_acq_info")
-    return {"digits": dg.value, "scratch_bytes": sb.value, "samples_needed": ns.value}
+    rt = C.c_int32()
+    _check(_lib.gc_acq_info(acq, C.byref(dg), C.byref(sb), C.byref(ns), C.byref(rt)),
+           "gc_acq_info")
+    return {"digits": dg.value, "scratch_bytes": sb.value, "samples_needed": ns.value,
+            "row_tile": rt.value}
 
 
 def gc_acq_timing(acq: int, n_slots: int) -> None:

@@ -107,7 +107,7 @@ def test_host_validation_without_a_device():
     prns = (C.c_int32 * 1)(1)
     assert g._lib.gc_acq_create(None, 0, 4, 0.0, 0.0, 1.0, 1, prns, 1, 1, 1, None) == g.GC_EINVAL
     assert g._lib.gc_acquire(None, None, 0, 2.5, None, None, None) == g.GC_EINVAL
-    assert g._lib.gc_acq_info(None, None, None, None) == g.GC_EINVAL
+    assert g._lib.gc_acq_info(None, None, None, None, None) == g.GC_EINVAL
     assert g._lib.gc_acq_destroy(None) == g.GC_EINVAL
     ls = g.gc_loop_init(4.0e6, 1.023e6)
     assert ls["carr_hz"] == 4.0e6 and ls["fll_basis_hz"] == 4.0e6 and ls["have_prev"] == 0

@@ -102,6 +102,25 @@ def test_acquire_large_rates(g, ctx, fmt, R, Mc, Knc, bins, digits):
     _same_detection(r, A.detect(want, R, -2500.0, 2500.0, 2.5), prns)
 
 
+def test_acquire_128_row_tiles(g, ctx):
+    # 32 bins x 4 samples per chip x 4 rows = 512 rows, 32 PRNs: 4 tiles of
+    # 128 rows give 512 blocks (one round on 256 compute units), where 6
+    # tiles of 96 would need two; both digit counts
+    rng = np.random.default_rng(128)
+    prns = list(range(1, 33))
+    for fmt, Mc, digits in ((2, 1, 2), (1, 1, 4)):
+        n = Mc * 1023 * 4
+        buf = rng.integers(0, 256, _bytes(fmt, n), dtype=np.uint8)
+        if_hz = 0.0 if fmt == 1 else 1.023e6
+        P, r, info = _gpu(g, ctx, fmt, buf, n, 4, if_hz, -8000.0, 500.0, 32, prns, Mc, 1)
+        assert info["digits"] == digits
+        if torch.cuda.get_device_properties(0).multi_processor_count == 256 and digits == 2:
+            assert info["row_tile"] == 128
+        want = A.search(fmt, buf, 4, if_hz, -8000.0, 500.0, 32, prns, Mc, 1)
+        assert np.array_equal(P, want)
+        _same_detection(r, A.detect(want, 4, -8000.0, 500.0, 2.5), prns)
+
+
 def test_acquire_single_channel_signal(g, ctx):
     # PRN 7 at +1.5 kHz, 300.25 chips, 45 dB-Hz, int8 at 4.092 MHz; a search
     # of 8 PRNs over +-5 kHz in 500 Hz bins, 1 ms coherent, 4 blocks
@@ -129,6 +148,10 @@ def test_acquire_twelve_channel_cold_start(g, ctx):
     prns = list(range(1, 33))
     P, r, info = _gpu(g, ctx, st.fmt, buf, st.n, 16, st.if_hz, -10000.0, 500.0, 41, prns, 1, 2)
     assert info["digits"] == 2
+    # 2624 rows: 28 tiles of 96 x 4 x 32 = 3584 blocks fill 7 rounds of 512
+    # exactly, where 21 tiles of 128 would leave a quarter round
+    assert info["row_tile"] == (96 if torch.cuda.get_device_properties(0).multi_processor_count == 256
+                                else info["row_tile"])
     want = A.search(st.fmt, buf, 16, st.if_hz, -10000.0, 500.0, 41, prns, 1, 2)
     sel = np.random.default_rng(3).integers(0, 32 * 41, 64)
     for s in sel:
