@@ -168,6 +168,39 @@ def test_acquire_twelve_channel_cold_start(g, ctx):
     assert not any(r[p - 1]["acquired"] for p in absent)
 
 
+def test_acquire_bench_configuration(g, ctx):
+    # the benchmark's search (32 PRNs x 41 bins x 16368 phases, 10 blocks of
+    # 1 ms on the 12-channel stream): sampled (PRN, bin) rows against the
+    # oracle, one bin at a time; every detection against the GPU's own full
+    # surface (peak, its place, the second peak's chip rule) and, for the
+    # PRNs whose peak row was sampled, against the oracle's row
+    from paper_1907_00463_amd import synth
+    st, chans, rng = synth.workload_twelve_channels(seconds=0.0101)
+    buf = synth.synth_samples(st, rng)
+    prns = list(range(1, 33))
+    R, f_lo, f_step, bins, knc = 16, -10000.0, 500.0, 41, 10
+    P, r, info = _gpu(g, ctx, st.fmt, buf, st.n, R, st.if_hz, f_lo, f_step, bins, prns, 1, knc)
+    assert info["samples_needed"] == knc * 16368
+    pick = np.random.default_rng(11).integers(0, 32 * bins, 10).tolist()
+    pick += [(int(x["prn"]) - 1) * bins + int(x["bin"]) for x in r if x["acquired"]][:4]
+    for sidx in pick:
+        p, d = divmod(int(sidx), bins)
+        row = A.search(st.fmt, buf, R, st.if_hz, f_lo + float(d) * f_step, f_step, 1, [p + 1], 1,
+                       knc)
+        assert np.array_equal(P[p, d], row[0, 0]), (p, d)
+    N = 16368
+    chips = np.arange(N) // R
+    for k, x in enumerate(r):
+        flat = int(np.argmax(P[k].reshape(-1)))
+        d, tau = divmod(flat, N)
+        assert (int(x["bin"]), int(x["tau"]), int(x["peak"])) == (d, tau, int(P[k, d, tau]))
+        j = tau // R
+        dist = np.minimum((chips - j) % 1023, (j - chips) % 1023)
+        assert int(x["second"]) == int(P[k, d][dist >= 2].max())
+        assert float(x["metric"]) == float(int(x["peak"])) / float(int(x["second"]))
+    assert sum(int(x["acquired"]) for x in r) >= 10
+
+
 def test_acquire_without_surface_and_repeated(g, ctx):
     # no surface requested: the same detections; a plan runs again on new data
     rng = np.random.default_rng(8)

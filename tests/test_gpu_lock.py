@@ -190,6 +190,58 @@ def test_lock_metrics_on_tracked_rows(g, ctx):
     assert agree in (0.0, 1.0)
 
 
+def test_lock_metrics_on_twelve_channel_tracking(g, ctx):
+    # the tracking benchmark's launch configuration on 2 s of the 12-channel
+    # 2-bit 16.368 MHz stream (channels started 30 Hz and 0.1 chip off):
+    # the lock metrics of every channel's GPU rows equal the oracle's on the
+    # same rows; the strong channels decode their bits and read their C/N0
+    from paper_1907_00463_amd import synth
+    st, chans, rng = synth.workload_twelve_channels(seconds=2.0)
+    buf = synth.synth_samples(st, rng)
+    nc = len(chans)
+    cfgs = np.zeros(nc, g.CHAN_CFG)
+    states = np.zeros(nc, g.CHAN_STATE)
+    loops = np.zeros(nc, g.LOOP_STATE)
+    for i, ch in enumerate(chans):
+        cfgs[i] = g.make_cfg(ch.prn, EPL, 1)
+        states[i] = g.gc_nco_init(st.fs, ch.carr_hz + 30.0, ch.carr_phase0, ch.code_rate,
+                                  ch.code_phase0 + 0.1, 1)
+        loops[i] = g.gc_loop_init(ch.carr_hz + 30.0, ch.code_rate)
+    params = g.loop_params(st.fs, st.if_hz)
+    max_dumps = 2002
+    plan = g.Plan(ctx, st.fmt, g.GC_CARRIER_LUT, cfgs)
+    try:
+        sd = plan.states_to_device(states)
+        lp = torch.from_numpy(loops.view(np.uint8).copy()).to("cuda")
+        rows = torch.zeros((nc, max_dumps, 8), dtype=torch.int32, device="cuda")
+        dn = torch.zeros((nc, max_dumps), dtype=torch.int32, device="cuda")
+        nd = torch.zeros(nc, dtype=torch.int32, device="cuda")
+        stt = torch.zeros(nc, dtype=torch.int32, device="cuda")
+        x = torch.from_numpy(buf).to("cuda")
+        assert g.gc_track(plan.handle, x, st.n, params, sd, lp, rows, dn, nd, stt, max_dumps,
+                          torch.cuda.current_stream()) == g.GC_OK
+        torch.cuda.synchronize()
+        assert not np.any(stt.cpu().numpy())
+        n_d = nd.cpu().numpy()
+        got = _gpu(g, ctx, np.zeros((nc, max_dumps, 8), np.int32), 8, 2, n_d, 20, 1e-3, 0.8,
+                   None, max_dumps // 20, max_dumps // 20 + 1, dev_rows=rows)
+        host_rows = rows.cpu().numpy()
+    finally:
+        plan.close()
+    for i in range(nc):
+        want = oracle.lock_metrics(host_rows[i, :int(n_d[i]), 2:4], K=20, T=1e-3, lock_min=0.8)
+        _same(got[i], want)
+    for i, s_ in enumerate(st.sats):
+        if s_.cn0_dbhz < 44.0:
+            continue
+        b = got[i]["bits"][25:].astype(np.int64)
+        t = (s_.nav_bits[25:25 + len(b)] < 0).astype(np.int64)
+        a = float(np.mean(b == t))
+        assert max(a, 1.0 - a) == 1.0, (s_.prn, a)
+        c = got[i]["cn0"][50:]
+        assert abs(float(np.median(c[np.isfinite(c)])) - s_.cn0_dbhz) < 2.0, s_.prn
+
+
 def test_lock_metrics_argument_errors(g, ctx):
     rows = torch.zeros((2, 40, 8), dtype=torch.int32, device="cuda")
     nd = torch.full((2,), 40, dtype=torch.int32, device="cuda")
