@@ -93,34 +93,50 @@ __device__ __forceinline__ bool step_ok(uint64_t dp, uint64_t W, int fmt) {
     return ((W - 1) / dp + 1) * max_w(fmt) < (1ull << 31);
 }
 
-// Loop update at the close of a dump with sums d (E I, E Q, P I, P Q, L I,
-// L Q): new carrier and code steps; false when the code step leaves
-// 1 .. 2^31-1.
+// Loop filter coefficients; new carrier and code steps come from
+// loop_update, which is false when the code step leaves 1 .. 2^31-1.
 struct Coefs {
     double T, t1c, t2c, t1d, t2d;
 };
 
-__device__ bool loop_update(const TrackConsts& P, const Coefs& K, const int64_t* d,
-                            gc_loop_state& L, uint32_t& carr_step, uint64_t& code_step) {
+// The vector whose angle (units of 2^-30 rad) is a discriminator of the
+// closing dump: which = 0, the PLL's atan(Q / I) of the prompt; which = 1,
+// the FLL's angle between the previous and this prompt, the dot product's
+// sign removed.  Two lanes form one vector each and then run the same
+// CORDIC side by side.
+__device__ __forceinline__ void loop_angle_args(int which, int64_t ip, int64_t qp, int32_t prev_i,
+                                                int32_t prev_q, int64_t& y, int64_t& x) {
+    if (which == 0) {
+        y = ip >= 0 ? qp : -qp;
+        x = ip >= 0 ? ip : -ip;
+        return;
+    }
+    int64_t i0 = prev_i, q0 = prev_q, i1 = ip, q1 = qp;
+    const int64_t lim = int64_t(1) << 30;
+    while (iabs64(i0) >= lim || iabs64(q0) >= lim || iabs64(i1) >= lim || iabs64(q1) >= lim) {
+        i0 >>= 1;
+        q0 >>= 1;
+        i1 >>= 1;
+        q1 >>= 1;
+    }
+    const int64_t dot = i0 * i1 + q0 * q1;
+    const int64_t cross = i0 * q1 - q0 * i1;
+    y = dot >= 0 ? cross : -cross;
+    x = dot >= 0 ? dot : -dot;
+}
+
+// Loop update at the close of a dump with sums d (E I, E Q, P I, P Q, L I,
+// L Q) and the discriminator angles a (PLL) and f (FLL).
+__device__ bool loop_update(const TrackConsts& P, const Coefs& K, const int64_t* d, int64_t a,
+                            int64_t f, gc_loop_state& L, uint32_t& carr_step,
+                            uint64_t& code_step) {
 #pragma clang fp contract(off)
     const double T = K.T, t1c = K.t1c, t2c = K.t2c, t1d = K.t1d, t2d = K.t2d;
     const int64_t ie = d[0], qe = d[1], ip = d[2], qp = d[3], il = d[4], ql = d[5];
     // PLL: atan(Q / I) in cycles
-    const int64_t a = ip >= 0 ? atan2_q30(qp, ip, P.tab) : atan2_q30(-qp, -ip, P.tab);
     const double carr_err = ((double)a / kQ30) / (2.0 * M_PI);
     // FLL: angle between consecutive prompts, the dot product's sign removed
     if (L.have_prev) {
-        int64_t i0 = L.prompt_i_prev, q0 = L.prompt_q_prev, i1 = ip, q1 = qp;
-        const int64_t lim = int64_t(1) << 30;
-        while (iabs64(i0) >= lim || iabs64(q0) >= lim || iabs64(i1) >= lim || iabs64(q1) >= lim) {
-            i0 >>= 1;
-            q0 >>= 1;
-            i1 >>= 1;
-            q1 >>= 1;
-        }
-        const int64_t dot = i0 * i1 + q0 * q1;
-        const int64_t cross = i0 * q1 - q0 * i1;
-        const int64_t f = dot >= 0 ? atan2_q30(cross, dot, P.tab) : atan2_q30(-cross, -dot, P.tab);
         const double f_err = ((double)f / kQ30) / (2.0 * M_PI * T);
         L.fll_basis_hz = L.fll_basis_hz + (4.0 * P.fll_bw * T) * f_err;
     }
@@ -154,6 +170,12 @@ __device__ bool loop_update(const TrackConsts& P, const Coefs& K, const int64_t*
 
 
 
+// Orders the LDS accesses of one wave's lanes around this point.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // Control block of a channel, shared by the block's threads.
 struct Ctl {
     uint64_t p, dp, s;
@@ -162,7 +184,18 @@ struct Ctl {
     int32_t status;
     int32_t done;
     int64_t acc[6];
+    int32_t prev_i, prev_q, have_prev;  // the loop state's previous prompt
+    int32_t closes;                     // the step closes a dump
+    int64_t ang[2];                     // PLL and FLL angles of the closing dump
 };
+
+// ceil(num / d) for num < 2^53, d >= 1: a double estimate made exact.
+__device__ __forceinline__ uint64_t ceil_div53(uint64_t num, uint64_t d) {
+    uint64_t q = (uint64_t)((double)num / (double)d);
+    while (q * d < num) ++q;
+    while (q > 0 && (q - 1) * d >= num) --q;
+    return q;
+}
 
 template <int FMT>
 __global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ samples,
@@ -217,6 +250,9 @@ __global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ 
                 ctl.acc[2 * k + 1] = st->acc[sl[k]][1];
             }
             L = loops[chn];
+            ctl.prev_i = L.prompt_i_prev;
+            ctl.prev_q = L.prompt_q_prev;
+            ctl.have_prev = L.have_prev;
         }
     }
     __syncthreads();
@@ -259,7 +295,7 @@ __global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ 
     while (true) {
         const uint64_t p = ctl.p, dp = ctl.dp, s0 = ctl.s;
         const uint32_t phi = ctl.phi, dphi = ctl.dphi;
-        const uint64_t need = (W - p + dp - 1) / dp;     // samples until the phase reaches W
+        const uint64_t need = ceil_div53(W - p, dp);     // samples until the phase reaches W
         const uint64_t take = min(min(need, n - s0), (uint64_t)kStageSamples);
 #pragma unroll
         for (int e = 0; e < kStagePieces / kThreads; ++e)
@@ -309,21 +345,30 @@ __global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ 
             if ((tid & 63) == 63) s_red[k][tid >> 6] = t;
         }
         __syncthreads();
-        if (tid == 0) {
-#pragma unroll
-            for (int k = 0; k < 6; ++k) {
+        if (tid < 64) {  // wave 0 closes the step
+            if (tid < 6) {  // the six sums in parallel, one lane each
                 int64_t t = 0;
-                for (int w = 0; w < kWaves; ++w) t += s_red[k][w];
-                ctl.acc[k] += t;
+#pragma unroll
+                for (int w = 0; w < kWaves; ++w) t += s_red[tid][w];
+                ctl.acc[tid] += t;
             }
-            ctl.acc_n += (uint32_t)take;
-            ctl.phi = phi + (uint32_t)take * dphi;
-            ctl.p = p + take * dp;
-            ctl.s = s0 + take;
-            if (ctl.p >= W) {  // the dump closes
-                if (ctl.nd >= max_dumps) {
-                    ctl.status = GC_ENOSPC;
-                } else {
+            if (tid == 0) {
+                ctl.acc_n += (uint32_t)take;
+                ctl.phi = phi + (uint32_t)take * dphi;
+                ctl.p = p + take * dp;
+                ctl.s = s0 + take;
+                ctl.closes = ctl.p >= W && ctl.nd < max_dumps;
+                if (ctl.p >= W && ctl.nd >= max_dumps) ctl.status = GC_ENOSPC;
+            }
+            wave_sync();
+            if (ctl.closes) {  // the dump closes: both angles side by side, then the update
+                if (tid < 2 && (tid == 0 || ctl.have_prev)) {
+                    int64_t y, x;
+                    loop_angle_args(tid, ctl.acc[2], ctl.acc[3], ctl.prev_i, ctl.prev_q, y, x);
+                    ctl.ang[tid] = atan2_q30(y, x, P.tab);
+                }
+                wave_sync();
+                if (tid == 0) {
                     int32_t* r = rows + ((uint64_t)chn * max_dumps + ctl.nd) * 8;
                     for (int k = 0; k < 6; ++k) r[k] = (int32_t)ctl.acc[k];
                     r[6] = (int32_t)ctl.dphi;
@@ -332,19 +377,22 @@ __global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ 
                     ctl.nd += 1;
                     uint32_t ncs;
                     uint64_t nks;
-                    if (!loop_update(P, K, ctl.acc, L, ncs, nks) ||
+                    if (!loop_update(P, K, ctl.acc, ctl.ang[0], ctl.ang[1], L, ncs, nks) ||
                         !step_ok(nks, W, FMT)) {
                         ctl.status = GC_ERANGE;
                     } else {
                         ctl.dphi = ncs;
                         ctl.dp = nks;
                     }
+                    ctl.prev_i = L.prompt_i_prev;
+                    ctl.prev_q = L.prompt_q_prev;
+                    ctl.have_prev = L.have_prev;
                     for (int k = 0; k < 6; ++k) ctl.acc[k] = 0;
                     ctl.acc_n = 0;
                     ctl.p -= W;
                 }
             }
-            ctl.done = ctl.status != GC_OK || (ctl.s >= n && ctl.p < W);
+            if (tid == 0) ctl.done = ctl.status != GC_OK || (ctl.s >= n && ctl.p < W);
         }
         __syncthreads();
         if (ctl.done) break;
