@@ -24,6 +24,8 @@ constexpr int kStageBytes = 32768;             // LDS sample window per step
 constexpr int kStagePieces = kStageBytes / 16;
 static_assert(kStagePieces % kThreads == 0, "whole 16-byte pieces per thread");
 typedef int int4v __attribute__((ext_vector_type(4)));
+typedef short short2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ short2_t as_s2(uint32_t v) { return __builtin_bit_cast(short2_t, v); }
 constexpr double kQ30 = 1073741824.0;
 
 __device__ __forceinline__ int64_t iabs64(int64_t v) { return v < 0 ? -v : v; }
@@ -32,7 +34,7 @@ __device__ __forceinline__ int64_t iabs64(int64_t v) { return v < 0 ? -v : v; }
 // [2^39, 2^40), then rotate it towards the x axis by -+atan(2^-i).
 __device__ __forceinline__ int bitlen64(uint64_t m) { return m ? 64 - __builtin_clzll(m) : 0; }
 
-__device__ int64_t atan2_q30(int64_t y, int64_t x, const int64_t* tab) {
+__device__ int64_t atan2_q30(int64_t y, int64_t x, const int32_t* tab) {
     if (x == 0 && y == 0) return 0;
     const int64_t hi = int64_t(1) << 40;
     // halving while a magnitude is >= 2^40: one shift that cannot overshoot
@@ -58,20 +60,19 @@ __device__ int64_t atan2_q30(int64_t y, int64_t x, const int64_t* tab) {
             y *= int64_t(1) << s;
         }
     }
-    int64_t z = 0;
+    // the rotations, branch-free (two lanes run them side by side); the
+    // angle sum stays within the sum of the table, below 2^31
+    int32_t z = 0;
+#pragma unroll
     for (int i = 0; i < kCordicSteps; ++i) {
         const int64_t xs = x >> i, ys = y >> i;
-        if (y > 0) {
-            x += ys;
-            y -= xs;
-            z += tab[i];
-        } else {
-            x -= ys;
-            y += xs;
-            z -= tab[i];
-        }
+        const bool pos = y > 0;
+        const int32_t t = tab[i];
+        x = pos ? x + ys : x - ys;
+        y = pos ? y - xs : y + xs;
+        z = pos ? z + t : z - t;
     }
-    return z;
+    return (int64_t)z;
 }
 
 __device__ void loop_coef(double B, double z, double k, double& tau1, double& tau2) {
@@ -210,6 +211,11 @@ __global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ 
                                                     const uint32_t* __restrict__ tables) {
     __shared__ uint32_t s_lut[256];
     __shared__ uint32_t s_code3[kCodeLen];  // chip c: bytes C[c-1], C[c], C[c+1]
+    __shared__ int32_t s_cordic[kCordicSteps];  // round(atan(2^-i) 2^30), all below 2^30
+    // 2-bit: (c, -s) int16 pairs of the carrier table, and per chip the
+    // sign pairs (C, C) of chips c - 1, c, c + 1
+    __shared__ uint32_t s_lut2[FMT == GC_I2_REAL ? 256 : 1];
+    __shared__ uint4 s_code4[FMT == GC_I2_REAL ? kCodeLen : 1];
     __shared__ int32_t s_red[6][kWaves];
     __shared__ Ctl ctl;
     __shared__ __align__(16) uint8_t s_stage[kStageBytes];
@@ -217,10 +223,19 @@ __global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ 
     const int chn = blockIdx.x;
     const DevChan& ch = chans[chn];
     for (int i = tid; i < 256; i += kThreads) s_lut[i] = tables[kTabLut + i];
+    if (tid < kCordicSteps) s_cordic[tid] = (int32_t)P.tab[tid];
     const uint32_t* sgn = tables + kTabSign + (ch.prn - 1) * kSignLen;
     for (int i = tid; i < kCodeLen; i += kThreads) {
         const int im = i == 0 ? kCodeLen - 1 : i - 1, ip = i + 1 == kCodeLen ? 0 : i + 1;
         s_code3[i] = (sgn[im] & 0xFFu) | (sgn[i] & 0xFFu) << 8 | (sgn[ip] & 0xFFu) << 16;
+        if constexpr (FMT == GC_I2_REAL) s_code4[i] = uint4{sgn[im], sgn[i], sgn[ip], 0u};
+    }
+    if constexpr (FMT == GC_I2_REAL) {
+        for (int i = tid; i < 256; i += kThreads) {
+            const uint32_t e = tables[kTabLut + i];
+            const uint32_t c = e & 0xFFFFu, sn = e >> 16;
+            s_lut2[i] = c | ((uint32_t)(uint16_t)(-(int16_t)sn) << 16);
+        }
     }
     const uint64_t W = ch.window;
     gc_chan_state* st = states + chn;
@@ -304,10 +319,43 @@ __global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ 
         load_window(s0 + take);
         const uint64_t b0 = byte_of(s0) & ~(uint64_t)15;
         int32_t a[6] = {0, 0, 0, 0, 0, 0};
-        for (uint32_t i = tid; i < (uint32_t)take; i += kThreads) {
+        // this thread's samples i = tid + kThreads k: offsets, carrier and
+        // code phases advance by fixed amounts from one to the next
+        uint32_t off = (uint32_t)(byte_of(s0 + tid) - b0);
+        const uint32_t sh2 = 2u * (uint32_t)((s0 + tid) & 3);   // 2-bit: bit offset in the byte
+        uint32_t ph = phi + (uint32_t)tid * dphi;
+        uint64_t u = p + (uint64_t)tid * dp;
+        const uint32_t dph = (uint32_t)kThreads * dphi;
+        const uint64_t du = (uint64_t)kThreads * dp;
+        constexpr uint32_t doff = FMT == GC_I2_REAL ? kThreads / 4 : FMT == GC_I8_IQ ? 2 * kThreads : kThreads;
+        if constexpr (FMT == GC_I2_REAL) {
+            // 2-bit samples in int16 pairs: (wI, wQ) = x (c, -s) in one packed
+            // multiply, then E, P and L by packed multiply-adds with the
+            // chips' sign pairs; a thread's partial sums stay below
+            // (kStageSamples / kThreads + 1) * 72 < 2^15
+            short2_t sE = {0, 0}, sP = {0, 0}, sL = {0, 0};
+            for (uint32_t i = tid; i < (uint32_t)take; i += kThreads, off += doff, ph += dph, u += du) {
+                const int xi = 2 * (int)((s_stage[off] >> sh2) & 3) - 3;
+                const short2_t x2 = as_s2((uint32_t)(uint16_t)xi * 0x10001u);
+                const short2_t w2 = x2 * as_s2(s_lut2[ph >> 24]);
+                const uint32_t cp = (uint32_t)((u >> 32) % kCodeLen);
+                const bool upper = (uint32_t)u >= (1u << 31);
+                const uint4 c4 = s_code4[cp];
+                const short2_t e2 = as_s2(upper ? c4.z : c4.y);
+                const short2_t l2 = as_s2(upper ? c4.y : c4.x);
+                sE = w2 * e2 + sE;
+                sP = w2 * as_s2(c4.y) + sP;
+                sL = w2 * l2 + sL;
+            }
+            a[0] = sE.x;
+            a[1] = sE.y;
+            a[2] = sP.x;
+            a[3] = sP.y;
+            a[4] = sL.x;
+            a[5] = sL.y;
+        } else
+        for (uint32_t i = tid; i < (uint32_t)take; i += kThreads, off += doff, ph += dph, u += du) {
             int xi, xq;
-            const uint64_t smp = s0 + i;
-            const uint32_t off = (uint32_t)(byte_of(smp) - b0);
             if constexpr (FMT == GC_I8_REAL) {
                 xi = (int)(int8_t)s_stage[off];
                 xq = 0;
@@ -315,17 +363,16 @@ __global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ 
                 xi = (int)(int8_t)s_stage[off];
                 xq = (int)(int8_t)s_stage[off + 1];
             } else {
-                xi = 2 * (int)((s_stage[off] >> (2 * (smp & 3))) & 3) - 3;
+                xi = 2 * (int)((s_stage[off] >> sh2) & 3) - 3;
                 xq = 0;
             }
             int c, sn;
-            lut_cs(s_lut[(phi + i * dphi) >> 24], c, sn);
+            lut_cs(s_lut[ph >> 24], c, sn);
             int wi, wq;
             wipe<FMT>(xi, xq, c, sn, wi, wq);
             // prompt chip floor(u / 2^32) mod 1023; the early (late) chip is
             // the next (previous) one when u's fraction is at or above
             // (below) one half chip
-            const uint64_t u = p + (uint64_t)i * dp;
             const uint32_t cp = (uint32_t)((u >> 32) % kCodeLen);
             const int sh = (uint32_t)u >= (1u << 31) ? 8 : 0;
             const uint32_t c3 = s_code3[cp];
@@ -365,7 +412,7 @@ __global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ 
                 if (tid < 2 && (tid == 0 || ctl.have_prev)) {
                     int64_t y, x;
                     loop_angle_args(tid, ctl.acc[2], ctl.acc[3], ctl.prev_i, ctl.prev_q, y, x);
-                    ctl.ang[tid] = atan2_q30(y, x, P.tab);
+                    ctl.ang[tid] = atan2_q30(y, x, s_cordic);
                 }
                 wave_sync();
                 if (tid == 0) {
