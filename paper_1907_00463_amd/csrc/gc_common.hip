@@ -55,14 +55,13 @@ __global__ void k_init_tables(uint32_t* tables) {
         const int i = (idx % kSignLen) % kCodeLen;
         tables[kTabSign + idx] = ca_chip(tables, c_g2_delay_dev[prn - 1], i) < 0 ? 0xFFFFFFFFu : 0x00010001u;
     }
-    // int8 code pairs (C, 64*C) per chip for the multi-tap MFMA operands
-    for (int idx = t; idx < 32 * 2 * kCodePairWords; idx += blockDim.x) {
-        const int prn = idx / (2 * kCodePairWords) + 1;
-        const int hi = (idx / kCodePairWords) % 2;
-        const int i = (idx % kCodePairWords) % kCodeLen;
+    // the multi-tap replica operand: chip x mod 1023 as an int8 in byte b
+    for (int idx = t; idx < 32 * 4 * kMtapCodeWords; idx += blockDim.x) {
+        const int prn = idx / (4 * kMtapCodeWords) + 1;
+        const int b = (idx / kMtapCodeWords) % 4;
+        const int i = (idx % kMtapCodeWords) % kCodeLen;
         const int c = ca_chip(tables, c_g2_delay_dev[prn - 1], i);
-        const uint32_t pair = (uint32_t)(uint8_t)(int8_t)c | ((uint32_t)(uint8_t)(int8_t)(64 * c) << 8);
-        tables[kTabCodePair + idx] = pair << (16 * hi);
+        tables[kTabMtapCode + idx] = (uint32_t)(uint8_t)(int8_t)c << (8 * b);
     }
     if (t < 256) {
         double ang = 6.283185307179586476925286766559 * ((double)t + 0.5) / 256.0;

@@ -23,12 +23,12 @@ constexpr int kPbinMaxAhead = 8;
 // periodic steps (32 chips per step, read up to kPbinMaxAhead steps ahead)
 // from any chip
 constexpr int kSignLen = 1023 + 32 * (kPbinMaxSteps + kPbinMaxAhead + 1);
-// 32 PRNs x 2 x kCodePairWords words: word i holds the int8 pair (C, 64*C)
-// of chip i mod 1023 in its low half-word, then the same pairs in the upper
-// half-words (multi-tap MFMA operands).
-constexpr int kCodePairWords = 1060;
-constexpr int kTabCodePair = kTabSign + 32 * kSignLen;
-constexpr int kTabWords = kTabCodePair + 32 * 2 * kCodePairWords;
+// Multi-tap replica operand: 32 PRNs x 4 byte positions x kMtapCodeWords
+// words; word x of byte position b holds chip x mod 1023 of the PRN as an
+// int8 in byte b and zeros in the other bytes.
+constexpr int kMtapCodeWords = 2080;
+constexpr int kTabMtapCode = kTabSign + 32 * kSignLen;
+constexpr int kTabWords = kTabMtapCode + 32 * 4 * kMtapCodeWords;
 constexpr int kLutAbsSumMax = 34;  // max over l of |cos_l| + |sin_l| at amplitude 24
 
 // Chip i of the C/A code whose G2 delay is d: G1[i] XOR G2[(i - d) mod 1023],

@@ -9,23 +9,26 @@
 // (at most one sample per cell when a chip spans <= 32 samples):
 //     T[q][j] = sum_c S[q][c] * C[(c + j) mod 1023]      (stage 2, MFMA)
 //     Y_k     = sum_q T[q][floor((q + d_k) / 32)]         (stage 3)
-// Stage 1 scatters the samples into S, one 32-chip chunk at a time, in LDS.
+// Stage 1 scatters the samples into S, one window of 32 chips at a time, in
+// LDS.  Windows are aligned to multiples of 32 chips, so a cell's address is
+// a bit field of U: (U >> 25) & 0xFFC = 128 * (c mod 32) + 4 * q.  A window
+// that holds the end of a dump is taken twice, once for each dump.
 // A cell holds four int8: the wiped-off I and Q (|w| <= 128*34) each split
-// as w = 64*hi + lo with lo = w & 63 in [0, 63] and hi = w >> 6 in [-68, 68].
-// The contraction index runs over (chip, byte of the cell); the replica
-// operand holds (C, 64*C, 0, 0) per chip in its I columns and (0, 0, C, 64*C)
-// in its Q columns (8 chip shifts each), so one v_mfma_i32_16x16x64_i8 over
-// 16 chips yields exact int32 T for I and Q at once.  T accumulates over the
-// chunks of a dump; at the dump's end prefix sums over q turn every tap into
-// two range sums (stage 3), and the dump is stored.
+// as w = lo + 256*hi with lo in [-128, 127]: the 16-bit (w + 128) XOR 0x80
+// holds lo in its low and hi in its high byte, so the pack is one XOR (the
+// +128 rides in the wipe-off's multiply-add).  The contraction index runs
+// over (chip, byte of the cell) and the 32 columns are (byte b, shift j):
+// the replica operand of column (b, j) holds C in byte b of each chip word.
+// One v_mfma_i32_32x32x32_i8 per 8 chips gives exact int32 T for the four
+// bytes of 8 shifts; at the dump's end I = T_0 + 256 T_1, Q = T_2 + 256 T_3,
+// prefix sums over q turn every tap into two range sums (stage 3), and the
+// dump is stored.
 //
 // One wave per channel (16 per block), blocks take contiguous chunks of
 // sample tiles; the tile (8 B per sample: (xI, xQ) and (xQ, -xI) as int16)
 // and a 16-copy carrier table are shared by the block's waves.  The complex
-// wipe-off is two v_dot2 per sample; lanes take consecutive samples, so
-// sample and table reads are conflict-free, and a row stride of 34 dwords
-// keeps the cells one instruction writes in distinct banks (rows q differ
-// by less than 32) as well as the 8-byte operand reads of 16 rows.
+// wipe-off is two packed int16 multiply-adds per sample; lanes take
+// consecutive samples.  The window walk runs on uniform (scalar) values.
 #include "gc_device.h"
 
 namespace gc {
@@ -33,28 +36,29 @@ namespace gc {
 namespace {
 
 constexpr int kWaves = 16;
-constexpr int kChunkChips = 32;                  // chips per chunk (two MFMA K steps)
-constexpr int kRows = 32;                        // q
-constexpr int kRowBytes = 136;                   // 32 chips x 4 B + 8 pad (34 dwords)
-constexpr int kSBytes = kRows * kRowBytes;       // 4352 per wave
+constexpr int kChunkChips = 32;                   // chips per window (4 MFMA K steps of 8)
+constexpr int kRows = 32;                         // q
+constexpr int kSBytes = kChunkChips * kRows * 4;  // 4096 per wave, cell (p, q) at 128 p + 4 q
 constexpr int kLutCopies = 16;
-constexpr int kLutStride = 257;                  // words between copies
+constexpr int kLutStride = 257;                   // words between copies
 constexpr int kLutBytes = kLutCopies * kLutStride * 4;
-constexpr int kTile = 8576;                      // samples per tile
-constexpr int kMargin = kChunkChips * 32 + 64;   // a chunk spans <= 32 chips of <= 32 samples
+constexpr int kTile = 8576;                       // samples per tile
+constexpr int kMargin = kChunkChips * 32 + 64 + 128;  // <= 32 chips of <= 32 samples, + one pair read ahead
 constexpr int kXSamples = kTile + kMargin;
-constexpr int kOffS = kLutBytes;
-constexpr int kOffX = kOffS + kWaves * kSBytes;
+constexpr int kOffS = 0;                          // S areas first: bases are multiples of 4096
+constexpr int kOffLut = kOffS + kWaves * kSBytes;
+constexpr int kOffX = kOffLut + kLutBytes;
 constexpr int kOffList = kOffX + kXSamples * 8;
 constexpr int kLdsBytes = kOffList + 4 * (kWaves + 1);
 static_assert(kLdsBytes <= 160 * 1024, "LDS per block");
+static_assert(kOffS % 4096 == 0 && kSBytes == 4096, "cell offset = (U >> 25) & 0xFFC | wave base");
 static_assert(kTile % 16 == 0 && kXSamples % 16 == 0, "staging granule");
-static_assert(2 * 8 * 33 * 4 <= kSBytes, "stage-3 prefix sums fit the wave's S area");
-static_assert(kOffS % 8 == 0 && kSBytes % 8 == 0 && kRowBytes % 8 == 0, "8-byte operand reads");
+static_assert(16 * 33 * 4 <= kSBytes, "stage-3 prefix sums fit the wave's S area");
+static_assert(kMtapCodeWords >= 1023 + 1023 + 4 + 24 + 4, "replica operand reads stay in the table");
 
 typedef short short2_t __attribute__((ext_vector_type(2)));
 typedef int int4_t __attribute__((ext_vector_type(4)));
-typedef int int2_t __attribute__((ext_vector_type(2)));
+typedef int i32x16 __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ short2_t as_s2(uint32_t v) { return __builtin_bit_cast(short2_t, v); }
 
@@ -63,26 +67,42 @@ __device__ __forceinline__ void wave_fence() {
     __builtin_amdgcn_wave_barrier();
 }
 
-// ceil(num / d), d in [2^27, 2^31): a double estimate made exact.
+__device__ __forceinline__ uint64_t uni64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// a uniform value computed on the VALU, moved to an SGPR: the empty asm
+// keeps the conversion before the read-first-lane (the compiler otherwise
+// hoists the read above it and leaves the rest of the window walk in VGPRs)
+__device__ __forceinline__ uint32_t to_sgpr(uint32_t v) {
+    asm("" : "+v"(v));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// ceil(num / d), d in [2^27, 2^31): a double estimate (within one of the
+// quotient) made exact by a bounded correction.
 __device__ __forceinline__ uint64_t ceil_div(uint64_t num, uint64_t d) {
     uint64_t q = (uint64_t)((double)num / (double)d);
-    while (q * d < num) ++q;
-    while (q > 0 && (q - 1) * d >= num) --q;
+    for (int i = 0; i < 4 && q * d < num; ++i) ++q;
+    for (int i = 0; i < 4 && q > 0 && (q - 1) * d >= num; ++i) --q;
     return q;
 }
 
-// One 32-chip chunk of a dump: chips [cs, ce), samples [sa, sb).  Chunks
-// are walked in order; the first sample of the next chunk follows from the
-// overshoot of this one (e = sb*dp - (ce*2^32 - p0), in [0, dp)) without a
-// division by the code step.
+// One chunk: the chips [cs, ce) of dump m inside the aligned window
+// [w0, w0 + 32), samples [sa, sb).  Chunks are walked in order; the first
+// sample of the next chunk follows from the overshoot of this one
+// (e = sb*dp - (ce*2^32 - p0), in [0, dp)) without a division by the code step.
 struct Chunk {
     uint64_t cs, ce;   // chips [cs, ce)
+    uint64_t w0;       // window start, a multiple of 32
     uint64_t d0;       // first chip of the dump (span * m)
     uint64_t sa, sb;   // samples [sa, sb), clipped to [0, n]
     uint64_t fb;       // first sample of chip ce (unclipped)
     uint64_t eb;       // its overshoot
     uint32_t m;        // dump (window) index
-    uint32_t cmod;     // cs mod 1023
+    uint32_t wmod;     // w0 mod 1023: the code chip of window position 0
     bool first, last;  // first / last chunk of its dump
 };
 
@@ -100,17 +120,19 @@ __device__ __forceinline__ void chip_first(uint64_t c, uint64_t p0, uint64_t dp,
     e = f * dp - (ph - p0);
 }
 
-// The chunk of chip c: chips [span*m + 32a, min(+32, span*(m+1))).
+// The chunk of chip c.  A dump spans a whole number of code periods, so the
+// code chip of chip c is c mod 1023 whatever the dump.
 __device__ __forceinline__ Chunk chunk_of(uint64_t c, uint64_t span, uint64_t p0, uint64_t dp,
                                           uint64_t n) {
     Chunk k;
     k.m = (uint32_t)(c / span);
     k.d0 = (uint64_t)k.m * span;
-    k.cs = k.d0 + ((c - k.d0) / kChunkChips) * kChunkChips;
-    k.ce = min(k.cs + kChunkChips, k.d0 + span);
+    k.w0 = c & ~(uint64_t)(kChunkChips - 1);
+    k.cs = max(k.d0, k.w0);
+    k.ce = min(k.w0 + kChunkChips, k.d0 + span);
     k.first = k.cs == k.d0;
     k.last = k.ce == k.d0 + span;
-    k.cmod = (uint32_t)((k.cs - k.d0) % kCodeLen);
+    k.wmod = (uint32_t)(k.w0 % kCodeLen);
     uint64_t fa, ea;
     chip_first(k.cs, p0, dp, fa, ea);
     chip_first(k.ce, p0, dp, k.fb, k.eb);
@@ -121,27 +143,53 @@ __device__ __forceinline__ Chunk chunk_of(uint64_t c, uint64_t span, uint64_t p0
 
 // The chunk after k: its first sample is k's end; its end advances by
 // ceil(((ce' - ce)*2^32 - eb) / dp) samples (one or two candidates around a
-// float estimate, checked exactly).
+// float estimate two below the quotient, stepped up exactly; the float
+// error is far below one sample, so a few steps always suffice).
+// For a full 32-chip chunk after a full one the sample count is
+// ceil((32*2^32 - eb)/dp) with eb in [0, dp): qhi = ceil(32*2^32/dp) or
+// qhi - 1, the latter exactly when the numerator is at most (qhi - 1)*dp.
+struct FullStep {
+    uint64_t qhi, p1, pq;  // qhi, (qhi - 1)*dp, qhi*dp
+};
+
 __device__ __forceinline__ void chunk_next(Chunk& k, uint64_t span, uint64_t dp, float inv_dp,
-                                           uint64_t n) {
+                                           uint64_t n, const FullStep& fs) {
+    if (!k.last && k.ce + kChunkChips <= k.d0 + span) {  // a full window after a full window
+        k.cs = k.ce;
+        k.w0 = k.ce;
+        k.wmod += kChunkChips;
+        if (k.wmod >= kCodeLen) k.wmod -= kCodeLen;
+        k.ce += kChunkChips;
+        k.first = false;
+        k.last = k.ce == k.d0 + span;
+        k.sa = k.sb;
+        const uint64_t num = ((uint64_t)kChunkChips << 32) - k.eb;
+        const bool hiq = num > fs.p1;
+        k.fb += hiq ? fs.qhi : fs.qhi - 1;
+        k.eb = (hiq ? fs.pq : fs.p1) - num;
+        k.sb = min(n, k.fb);
+        return;
+    }
     if (k.last) {
         k.m += 1;
         k.d0 += span;
-        k.cmod = 0;  // a dump starts on a code epoch
-    } else {
-        k.cmod += kChunkChips;
-        if (k.cmod >= kCodeLen) k.cmod -= kCodeLen;
+    }
+    const uint64_t w0 = k.ce & ~(uint64_t)(kChunkChips - 1);
+    if (w0 != k.w0) {
+        k.wmod += kChunkChips;
+        if (k.wmod >= kCodeLen) k.wmod -= kCodeLen;
+        k.w0 = w0;
     }
     k.cs = k.ce;
-    k.ce = min(k.cs + kChunkChips, k.d0 + span);
+    k.ce = min(k.w0 + kChunkChips, k.d0 + span);
     k.first = k.cs == k.d0;
     k.last = k.ce == k.d0 + span;
     k.sa = k.sb;
     const uint32_t nch = (uint32_t)(k.ce - k.cs);          // 1 .. 32
     const uint64_t num = ((uint64_t)nch << 32) - k.eb;      // > 0
     const float est = ((float)nch * 4294967296.0f - (float)(uint32_t)k.eb) * inv_dp;
-    uint64_t q = (uint64_t)(uint32_t)max(0.0f, est - 2.0f);
-    while (q * dp < num) ++q;
+    uint64_t q = to_sgpr((uint32_t)max(0.0f, est - 2.0f));
+    for (int i = 0; i < 8 && q * dp < num; ++i) ++q;
     k.fb += q;
     k.eb = q * dp - num;
     k.sb = min(n, k.fb);
@@ -224,31 +272,27 @@ __device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, 
     }
 }
 
-// Stage 1, one sample per lane: wipe-off, split into the four int8 of the
-// cell, one dword store into row q, column (chip - cs).
-template <bool CHECK>
-__device__ __forceinline__ void scatter_step(uint8_t* lds, uint32_t xaddr, uint32_t ph,
-                                             uint32_t lut_base, uint64_t U, uint32_t cbase,
-                                             bool valid) {
-    if (CHECK && !valid) return;
-    const uint2 xw = *reinterpret_cast<const uint2*>(lds + xaddr);
-    const uint32_t cs = *reinterpret_cast<const uint32_t*>(lds + lut_base + ((ph >> 24) << 2));
-    // (wI, wQ) = (xI, xQ) c + (xQ, -xI) s as int16 pairs: every product and
-    // sum stays below 2^15 in magnitude (|x c| <= 3072, |w| <= 4352), so the
-    // 16-bit lanes hold the exact values
+// Stage 1 for one sample: the wiped-off (wI, wQ) + 128 as int16 pairs,
+// (xI, xQ) c + ((xQ, -xI) s + 128): every product and sum stays below 2^15
+// in magnitude (|x c| <= 3072, |w| <= 4352), so the 16-bit lanes hold the
+// exact values; XOR 0x80 per half gives the cell bytes (lo, hi).  The empty
+// asm keeps the +128 inside the first packed multiply-add (the compiler
+// would otherwise add it separately after both products).
+__device__ __forceinline__ uint32_t cell_of(uint2 xw, uint32_t cs, short2_t k128) {
     const short2_t c2 = as_s2(cs);
     const short2_t cc = __builtin_shufflevector(c2, c2, 0, 0);
     const short2_t ss = __builtin_shufflevector(c2, c2, 1, 1);
-    const short2_t w2 = as_s2(xw.x) * cc + as_s2(xw.y) * ss;
-    // per half: bits 0-5 stay, bits 6-13 move to the upper byte (w >> 6 as a
-    // two's complement byte)
-    const uint32_t h = __builtin_bit_cast(uint32_t, w2);
-    const uint32_t cell = ((h << 2) & 0xFF00FF00u) | (h & 0x003F003Fu);
-    // row q, column chip - cs: cbase = s_base - 4*cs (mod 2^32)
-    const uint32_t lo = (uint32_t)U, hi = (uint32_t)(U >> 32);
-    const uint32_t q = lo >> 27;
-    const uint32_t a = __umul24(q, kRowBytes) + (hi * 4u + cbase);
-    *reinterpret_cast<uint32_t*>(lds + a) = cell;
+    short2_t p = as_s2(xw.y) * ss + k128;
+    asm("" : "+v"(p));
+    const short2_t w2 = as_s2(xw.x) * cc + p;
+    return __builtin_bit_cast(uint32_t, w2) ^ 0x00800080u;
+}
+
+// offset of the cell of code phase U in the wave's S area; s_base_v (a
+// multiple of 4096 from the start of the block's LDS) is a value whose bits
+// the compiler does not see, so the OR stays one v_and_or_b32
+__device__ __forceinline__ uint32_t cell_addr(uint64_t U, uint32_t s_base_v) {
+    return ((uint32_t)(U >> 25) & 0xFFCu) | s_base_v;
 }
 
 struct Dest {
@@ -259,18 +303,23 @@ struct Dest {
     uint32_t m_close;
 };
 
-// Stage 3 for the dump held in acc (T[q][col]: col < 8 the I sums of shift
-// jmin + col, col >= 8 the Q sums of shift jmin + col - 8): prefix sums over q
-// in the wave's S area, two range sums per tap, stored (plain or atomic).
-__device__ __forceinline__ void finish_dump(int4_t (&acc)[2], uint8_t* lds, uint32_t s_base,
+// Stage 3 for the dump held in acc (column l32 = 8 b + j: byte b of shift
+// jmin + j; element e is row q = 8 (e / 4) + 4 h + e % 4): I and Q of each
+// (q, j) from the lo and hi bytes (lane + 8 holds the hi byte), prefix sums
+// over q in the wave's S area, two range sums per tap, stored (plain or
+// atomic).
+__device__ __forceinline__ void finish_dump(i32x16& acc, uint8_t* lds, uint32_t s_base,
                                             uint32_t lane, const DevChan& ch, int jmin,
                                             uint32_t m, bool plain, const Dest& d) {
-    int32_t* P = reinterpret_cast<int32_t*>(lds + s_base);  // [plane][j][33]
-    const uint32_t col = lane & 15, g = lane >> 4;
+    int32_t* P = reinterpret_cast<int32_t*>(lds + s_base);  // [plane * 8 + j][33]
+    const uint32_t l32 = lane & 31, h = lane >> 5;
+    const uint32_t seq = (l32 >> 4) * 8 + (l32 & 7);
+    const bool lo_lane = (l32 & 8) == 0;
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) P[col * 33 + 16 * t + 4 * g + v] = acc[t][v];
+    for (int e = 0; e < 16; ++e) {
+        const int hi = __builtin_amdgcn_update_dpp(0, acc[e], 0x108, 0xf, 0xf, false);  // row_shl:8
+        const int v = acc[e] + 256 * hi;
+        if (lo_lane) P[seq * 33 + 8 * (e / 4) + 4 * h + (e % 4)] = v;
     }
     wave_fence();
     if (lane < 16) {  // exclusive prefix over q of sequence (plane, j) = (lane/8, lane%8)
@@ -316,8 +365,8 @@ __device__ __forceinline__ void finish_dump(int4_t (&acc)[2], uint8_t* lds, uint
         }
     }
     wave_fence();
-    acc[0] = int4_t{0, 0, 0, 0};
-    acc[1] = int4_t{0, 0, 0, 0};
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[e] = 0;
 }
 
 template <int FMT>
@@ -334,7 +383,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
     int* s_list = reinterpret_cast<int*>(s_lds + kOffList);
     const int tid = threadIdx.x;
     const int nthreads = blockDim.x;
-    const int wave = tid / 64;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
     const uint32_t lane = tid & 63;
 
     if (tid == 0) {  // this block's channel group
@@ -350,10 +399,10 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
         s_list[kWaves] = k;
     }
     __syncthreads();
-    const int nlist = s_list[kWaves];
+    const int nlist = __builtin_amdgcn_readfirstlane(s_list[kWaves]);
     if (nlist == 0) return;
     {
-        uint32_t* lut = reinterpret_cast<uint32_t*>(s_lds);
+        uint32_t* lut = reinterpret_cast<uint32_t*>(s_lds + kOffLut);
         for (int i = tid; i < kLutCopies * kLutStride; i += nthreads) {
             const int e = i % kLutStride;
             lut[i] = e < 256 ? tables[kTabLut + e] : 0u;
@@ -366,42 +415,70 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
     const DevMeta m = metas[chn];
     const Dest d{out, state + chn, (uint64_t)chn * max_dumps, tap_stride, m.m_close};
     const uint64_t span = m.window >> 32;
-    const uint32_t s_base = kOffS + wave * kSBytes;
-    const uint32_t lut_base = (lane & (kLutCopies - 1)) * kLutStride * 4;
+    const uint32_t s_base = kOffS + (uint32_t)wave * kSBytes;  // offset from s_lds
+    uint32_t s_base_v = s_base;
+    asm("" : "+v"(s_base_v));
+    const short2_t k128 = {128, 128};
+    const uint32_t lut_base = kOffLut + (lane & (kLutCopies - 1)) * kLutStride * 4;
     const int jmin = ch.mt_jmin;
     const float inv_dp = 1.0f / (float)m.dp;
-    // lane's operand columns: chips 4g.. of each 16-chip K step, shift
-    // jmin + (lane & 7), as an offset in [0, 1023) from the chunk's first
-    // chip; lanes 8..15 of a row group read the Q table (pairs in the upper
-    // half-word)
-    const uint32_t b_off = (uint32_t)(4 * (int)(lane >> 4) + (int)(lane & 7) + 2 * kCodeLen + jmin) %
-                           kCodeLen;
-    // replica operand source: (C, 64*C) int8 pairs of this PRN, one word per
-    // chip, then the same pairs in the upper half-words
-    const uint32_t* cpair = tables + kTabCodePair + (ch.prn - 1) * 2 * kCodePairWords;
-    const uint32_t* cpl = cpair + ((lane & 8) ? kCodePairWords : 0);
+    FullStep fs;
+    fs.qhi = uni64(ceil_div((uint64_t)kChunkChips << 32, m.dp));
+    fs.p1 = (fs.qhi - 1) * m.dp;
+    fs.pq = fs.qhi * m.dp;
+    const uint32_t l32 = lane & 31, h = lane >> 5;
+    // replica operand: column l32 = 8 b + j takes the byte-b table of the
+    // PRN at chip (window chip + shift jmin + j); K step ks, lane half h
+    // covers window positions 8 ks + 4 h .. + 3
+    const int jsh = (int)(((int64_t)jmin + (int64_t)(l32 & 7)) % kCodeLen);
+    const uint32_t b_lane = (uint32_t)(jsh < 0 ? jsh + kCodeLen : jsh) + 4u * h;
+    const uint32_t* btab =
+        tables + kTabMtapCode + ((ch.prn - 1) * 4 + (int)(l32 >> 3)) * kMtapCodeWords + b_lane;
+    // per-lane parts of the sample walk
+    const uint64_t lane_dU = (uint64_t)lane * m.dp;
+    const uint32_t lane_dph = lane * m.dphi;
+    const uint64_t dU = 64ull * m.dp;
+    const uint32_t dph = 64u * m.dphi;
+    // the step increments as VGPR values: the compiler then adds them
+    // directly instead of keeping scalar running offsets
+    uint64_t dUv = dU, dU2v = 2 * dU;
+    uint32_t dph2v = 2 * dph;
+    asm("" : "+v"(dUv));
+    asm("" : "+v"(dU2v));
+    asm("" : "+v"(dph2v));
+    // A fragment of K step ks: window positions 8 ks + 4 h + i, row l32
+    const uint32_t a_base = s_base + 128u * 4u * h + 4u * l32;
 
     // contiguous chunk of tiles for this block; chunks belong to the tile
     // holding their first sample
     const uint32_t tb0 = (uint32_t)(((uint64_t)blockIdx.x * n_tiles) / gridDim.x);
     const uint32_t tb1 = (uint32_t)(((uint64_t)(blockIdx.x + 1) * n_tiles) / gridDim.x);
     const uint64_t T0 = (uint64_t)tb0 * kTile;
-    const uint64_t T1 = min(n, (uint64_t)tb1 * kTile);
 
-    int4_t acc[2] = {int4_t{0, 0, 0, 0}, int4_t{0, 0, 0, 0}};
+    // two accumulators (even and odd K steps) halve the dependent MFMA chain
+    i32x16 acc0, acc1;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc0[e] = acc1[e] = 0;
     Chunk k = chunk_of((m.p0 + T0 * m.dp) >> 32, span, m.p0, m.dp, n);
     if (T0 > 0 && k.sa < T0) k = chunk_of(k.ce, span, m.p0, m.dp, n);
     bool seen_first = k.first;  // this wave holds the dump from its first chunk
-    bool open = false;          // acc holds part of dump k.m
-    // replica operand of a chunk (chips from cmod), loaded one chunk ahead
-    auto load_b = [&](uint32_t cmod, int4_t (&b)[2]) {
-        uint32_t o = cmod + b_off;
-        if (o >= kCodeLen) o -= kCodeLen;
-        b[0] = *reinterpret_cast<const int4_t*>(cpl + o);
-        b[1] = *reinterpret_cast<const int4_t*>(cpl + o + 16);
+    bool open = false;          // acc0 + acc1 hold part of dump k.m
+    // the lane's sample sa + lane of the current chunk: code phase, carrier
+    // phase, and tile address (relative to the tile being worked on); each
+    // chunk advances them by its sample count
+    uint64_t Ul;
+    uint32_t phl, xl;
+    {
+        const uint64_t sa = uni64(k.sa);
+        Ul = m.p0 + sa * m.dp + lane_dU;
+        phl = m.phi0 + (uint32_t)sa * m.dphi + lane_dph;
+        xl = kOffX + (uint32_t)(sa - T0) * 8u + lane * 8u;
+    }
+    auto x_at = [&](uint32_t a) { return *reinterpret_cast<const uint2*>(s_lds + a); };
+    auto lut_at = [&](uint32_t phase) {
+        return *reinterpret_cast<const uint32_t*>(s_lds + lut_base + ((phase >> 24) << 2));
     };
-    int4_t bop[2];
-    if (active) load_b(k.cmod, bop);
+    auto cell_store = [&](uint32_t a, uint32_t v) { *reinterpret_cast<uint32_t*>(s_lds + a) = v; };
 
     for (uint32_t tile = tb0; tile < tb1; ++tile) {
         const uint64_t t0 = (uint64_t)tile * kTile;
@@ -410,66 +487,112 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
         stage_tile<FMT>(samples, n, t0, s_lds, nthreads);
         __syncthreads();
         if (!active) continue;
+        if (tile > tb0) xl -= 8u * kTile;
         while (k.sa < t1 && k.sa < k.sb) {
-            // stage 1: clear S (32 rows of 32 cells), scatter the chunk's samples
+            // the window's replica operand, in flight during stage 1
+            int4_t bop[4];
             {
-                uint2* z = reinterpret_cast<uint2*>(s_lds + s_base + (lane >> 1) * kRowBytes +
-                                                    64 * (lane & 1));
+                const uint32_t* bp = btab + k.wmod;
 #pragma unroll
-                for (int c = 0; c < 8; ++c) z[c] = uint2{0u, 0u};
+                for (int ks = 0; ks < 4; ++ks) bop[ks] = *reinterpret_cast<const int4_t*>(bp + 8 * ks);
+            }
+            // stage 1: clear S (32 x 32 cells), scatter the chunk's samples
+            {
+                uint4* z = reinterpret_cast<uint4*>(s_lds + s_base) + lane;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) z[64 * c] = uint4{0u, 0u, 0u, 0u};
             }
             wave_fence();
-            const uint64_t n0 = k.sa + lane;
-            uint64_t U = m.p0 + n0 * m.dp;
-            uint32_t ph = m.phi0 + (uint32_t)n0 * m.dphi;
-            uint32_t xaddr = kOffX + (uint32_t)(n0 - t0) * 8u;
-            const uint64_t dU = 64ull * m.dp;
-            const uint32_t dph = 64u * m.dphi;
-            const uint32_t cbase = s_base - 4u * (uint32_t)k.cs;
-            const uint32_t cnt = __builtin_amdgcn_readfirstlane((uint32_t)(k.sb - k.sa));
-            const uint32_t full = cnt / 64;
-            for (uint32_t j = 0; j < full; ++j) {
-                scatter_step<false>(s_lds, xaddr, ph, lut_base, U, cbase, true);
-                U += dU;
-                ph += dph;
-                xaddr += 512u;
-            }
-            if (cnt % 64)
-                scatter_step<true>(s_lds, xaddr, ph, lut_base, U, cbase, lane < cnt % 64);
-            wave_fence();
-            // stage 2: two 16-row tiles x two 16-chip K steps x 16 columns
-            {
-                const uint32_t j = lane & 15, g = lane >> 4;
-                const int4_t b_cur[2] = {bop[0], bop[1]};
-                // the next chunk starts at chip offset cmod + 32, or at a
-                // code epoch (offset 0) after the last chunk of a dump
-                uint32_t cnext = k.cmod + kChunkChips;
-                if (cnext >= kCodeLen) cnext -= kCodeLen;
-                load_b(k.last ? 0u : cnext, bop);
-#pragma unroll
-                for (int ks = 0; ks < 2; ++ks) {
-#pragma unroll
-                    for (int t = 0; t < 2; ++t) {
-                        const uint8_t* ap = s_lds + s_base + (16 * t + j) * kRowBytes + 64 * ks + 16 * g;
-                        const int2_t a0 = *reinterpret_cast<const int2_t*>(ap);
-                        const int2_t a1 = *reinterpret_cast<const int2_t*>(ap + 8);
-                        const int4_t a = int4_t{a0.x, a0.y, a1.x, a1.y};
-                        acc[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b_cur[ks], acc[t], 0, 0, 0);
+            const uint32_t adv = __builtin_amdgcn_readfirstlane((uint32_t)(k.sb - k.sa));
+            // at most 32 chips of at most 32 samples, inside the staged tile
+            const uint32_t cnt = min(adv, (uint32_t)(kXSamples - (uint32_t)(k.sa - t0)));
+            uint64_t U = Ul;
+            uint32_t ph = phl, xa = xl;
+            // pairs of full steps, software-pipelined over two register
+            // sets: the reads of the next pair (unconditional: the staged
+            // tile extends one pair past any chunk) are issued before the
+            // stores of the current one
+            uint32_t pairs = __builtin_amdgcn_readfirstlane(cnt / 128);
+            if (pairs > 0) {
+                uint2 xa0 = x_at(xa), xa1 = x_at(xa + 512u);
+                uint32_t ca0 = lut_at(ph), ca1 = lut_at(ph + dph);
+                uint2 xb0, xb1;
+                uint32_t cb0, cb1;
+                for (;;) {
+                    {
+                        const uint32_t v0 = cell_of(xa0, ca0, k128), v1 = cell_of(xa1, ca1, k128);
+                        const uint32_t a0 = cell_addr(U, s_base_v), a1 = cell_addr(U + dUv, s_base_v);
+                        U += dU2v;
+                        ph += dph2v;
+                        xa += 1024u;
+                        xb0 = x_at(xa);
+                        xb1 = x_at(xa + 512u);
+                        cb0 = lut_at(ph);
+                        cb1 = lut_at(ph + dph);
+                        cell_store(a0, v0);
+                        cell_store(a1, v1);
+                        if (--pairs == 0) break;
+                    }
+                    {
+                        const uint32_t v0 = cell_of(xb0, cb0, k128), v1 = cell_of(xb1, cb1, k128);
+                        const uint32_t a0 = cell_addr(U, s_base_v), a1 = cell_addr(U + dUv, s_base_v);
+                        U += dU2v;
+                        ph += dph2v;
+                        xa += 1024u;
+                        xa0 = x_at(xa);
+                        xa1 = x_at(xa + 512u);
+                        ca0 = lut_at(ph);
+                        ca1 = lut_at(ph + dph);
+                        cell_store(a0, v0);
+                        cell_store(a1, v1);
+                        if (--pairs == 0) break;
                     }
                 }
             }
+            // the last 0 .. 127 samples: one pair with masked stores
+            const uint32_t rest = cnt % 128;
+            if (rest > 0) {
+                const uint32_t v0 = cell_of(x_at(xa), lut_at(ph), k128);
+                const uint32_t v1 = cell_of(x_at(xa + 512u), lut_at(ph + dph), k128);
+                const uint32_t a0 = cell_addr(U, s_base_v), a1 = cell_addr(U + dUv, s_base_v);
+                if (lane < rest) cell_store(a0, v0);
+                if (lane + 64 < rest) cell_store(a1, v1);
+            }
+            wave_fence();
+            // stage 2: four K steps of 8 chips, 32 rows q x 32 columns
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                const uint8_t* ap = s_lds + a_base + 1024u * ks;
+                const int4_t a = int4_t{*reinterpret_cast<const int*>(ap),
+                                        *reinterpret_cast<const int*>(ap + 128),
+                                        *reinterpret_cast<const int*>(ap + 256),
+                                        *reinterpret_cast<const int*>(ap + 384)};
+                if (ks % 2 == 0)
+                    acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, bop[ks], acc0, 0, 0, 0);
+                else
+                    acc1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, bop[ks], acc1, 0, 0, 0);
+            }
             open = true;
             if (k.last) {
-                finish_dump(acc, s_lds, s_base, lane, ch, jmin, k.m, seen_first && k.m > 0, d);
+                acc0 += acc1;
+                finish_dump(acc0, s_lds, s_base, lane, ch, jmin, k.m, seen_first && k.m > 0, d);
+#pragma unroll
+                for (int e = 0; e < 16; ++e) acc1[e] = 0;
                 open = false;
             }
+            Ul += (uint64_t)adv * m.dp;
+            phl += adv * m.dphi;
+            xl += 8u * adv;
             const bool was_last = k.last;
-            chunk_next(k, span, m.dp, inv_dp, n);
+            chunk_next(k, span, m.dp, inv_dp, n, fs);
             if (was_last) seen_first = true;
         }
     }
     // the dump still open at the end of this block's range
-    if (active && open) finish_dump(acc, s_lds, s_base, lane, ch, jmin, k.m, false, d);
+    if (active && open) {
+        acc0 += acc1;
+        finish_dump(acc0, s_lds, s_base, lane, ch, jmin, k.m, false, d);
+    }
 }
 
 template <int FMT>
