@@ -964,14 +964,17 @@ def main():
                            "kernel_ms": round(k_s * 1e3, 4),
                            "note": "4 FLOPs per sample·tap (two FP32 multiply-adds)"}
     elif args.workload == "multicorrelator" and args.kernels == "auto":
-        # stage 2: 128 rows (I/Q x lo/hi x 32 cells) x 16 shifts per chip
+        # stage 2, algorithmic: per chip and channel 32 cells x 8 chip shifts
+        # x I/Q x two int8 digits = 1024 MAC; the kernel executes 4096 per
+        # chip (32 rows x 32 columns x 4 bytes: three of a column's four
+        # bytes are zero), a little more where a window holds a dump end
         chips = n * float(np.mean(states["code_step"].astype(np.float64))) / 2 ** 32
-        macs = 128 * 16 * chips * len(cfgs)
+        macs = 1024 * chips * len(cfgs)
         tops = 2 * macs / k_s / 1e12
         res["roofline_stage2"] = {"bound": "mfma", "achieved": round(tops, 3),
                                   "peak": INT8_MFMA_PEAK_TOPS, "unit": "T int8 ops/s",
                                   "frac": round(tops / INT8_MFMA_PEAK_TOPS, 5),
-                                  "macs": round(macs),
+                                  "macs": round(macs), "executed_macs": round(4 * macs),
                                   "note": "int8 MFMA work over the whole kernel time "
                                           "(stage 1 dominates)"}
     if not args.no_plain and not f32:

@@ -55,11 +55,12 @@ __global__ void k_init_tables(uint32_t* tables) {
         const int i = (idx % kSignLen) % kCodeLen;
         tables[kTabSign + idx] = ca_chip(tables, c_g2_delay_dev[prn - 1], i) < 0 ? 0xFFFFFFFFu : 0x00010001u;
     }
-    // the multi-tap replica operand: chip x mod 1023 as an int8 in byte b
+    // the multi-tap replica operand: chip (2y + r) mod 1023 as an int8 in byte b
     for (int idx = t; idx < 32 * 4 * kMtapCodeWords; idx += blockDim.x) {
         const int prn = idx / (4 * kMtapCodeWords) + 1;
         const int b = (idx / kMtapCodeWords) % 4;
-        const int i = (idx % kMtapCodeWords) % kCodeLen;
+        const int r = (idx / kMtapHalfWords) % 2;
+        const int i = (2 * (idx % kMtapHalfWords) + r) % kCodeLen;
         const int c = ca_chip(tables, c_g2_delay_dev[prn - 1], i);
         tables[kTabMtapCode + idx] = (uint32_t)(uint8_t)(int8_t)c << (8 * b);
     }

@@ -23,10 +23,12 @@ constexpr int kPbinMaxAhead = 8;
 // periodic steps (32 chips per step, read up to kPbinMaxAhead steps ahead)
 // from any chip
 constexpr int kSignLen = 1023 + 32 * (kPbinMaxSteps + kPbinMaxAhead + 1);
-// Multi-tap replica operand: 32 PRNs x 4 byte positions x kMtapCodeWords
-// words; word x of byte position b holds chip x mod 1023 of the PRN as an
-// int8 in byte b and zeros in the other bytes.
-constexpr int kMtapCodeWords = 2080;
+// Multi-tap replica operand: 32 PRNs x 4 byte positions x 2 parities x
+// kMtapHalfWords words; word y of parity r of byte position b holds chip
+// (2y + r) mod 1023 of the PRN as an int8 in byte b and zeros in the other
+// bytes (so four chips two apart are one 16-byte read).
+constexpr int kMtapHalfWords = 1040;
+constexpr int kMtapCodeWords = 2 * kMtapHalfWords;
 constexpr int kTabMtapCode = kTabSign + 32 * kSignLen;
 constexpr int kTabWords = kTabMtapCode + 32 * 4 * kMtapCodeWords;
 constexpr int kLutAbsSumMax = 34;  // max over l of |cos_l| + |sin_l| at amplitude 24

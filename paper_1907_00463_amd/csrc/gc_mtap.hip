@@ -19,7 +19,8 @@
 // +128 rides in the wipe-off's multiply-add).  The contraction index runs
 // over (chip, byte of the cell) and the 32 columns are (byte b, shift j):
 // the replica operand of column (b, j) holds C in byte b of each chip word.
-// One v_mfma_i32_32x32x32_i8 per 8 chips gives exact int32 T for the four
+// One v_mfma_i32_32x32x32_i8 per 8 chips (each lane half taking every
+// other chip) gives exact int32 T for the four
 // bytes of 8 shifts; at the dump's end I = T_0 + 256 T_1, Q = T_2 + 256 T_3,
 // prefix sums over q turn every tap into two range sums (stage 3), and the
 // dump is stored.
@@ -54,7 +55,7 @@ static_assert(kLdsBytes <= 160 * 1024, "LDS per block");
 static_assert(kOffS % 4096 == 0 && kSBytes == 4096, "cell offset = (U >> 25) & 0xFFC | wave base");
 static_assert(kTile % 16 == 0 && kXSamples % 16 == 0, "staging granule");
 static_assert(16 * 33 * 4 <= kSBytes, "stage-3 prefix sums fit the wave's S area");
-static_assert(kMtapCodeWords >= 1023 + 1023 + 4 + 24 + 4, "replica operand reads stay in the table");
+static_assert(2 * kMtapHalfWords >= 1022 + 1022 + 1 + 24 + 8, "replica operand reads stay in the table");
 
 typedef short short2_t __attribute__((ext_vector_type(2)));
 typedef int int4_t __attribute__((ext_vector_type(4)));
@@ -419,7 +420,14 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
     uint32_t s_base_v = s_base;
     asm("" : "+v"(s_base_v));
     const short2_t k128 = {128, 128};
-    const uint32_t lut_base = kOffLut + (lane & (kLutCopies - 1)) * kLutStride * 4;
+    // carrier table reads: a slow carrier (the 64 lanes of a step span fewer
+    // than 32 consecutive entries, e.g. complex baseband with Doppler) reads
+    // one copy, where lanes on one entry are a broadcast and distinct entries
+    // fall in distinct banks; a fast one (IF input) spreads the lanes over
+    // the 16 copies so that entries a multiple of 32 apart do not collide
+    const uint32_t adphi = (int32_t)m.dphi < 0 ? 0u - m.dphi : m.dphi;
+    const bool one_copy = (uint64_t)adphi * 64 <= (31ull << 24);
+    const uint32_t lut_base = kOffLut + (one_copy ? 0u : (lane & (kLutCopies - 1)) * kLutStride * 4);
     const int jmin = ch.mt_jmin;
     const float inv_dp = 1.0f / (float)m.dp;
     FullStep fs;
@@ -428,12 +436,12 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
     fs.pq = fs.qhi * m.dp;
     const uint32_t l32 = lane & 31, h = lane >> 5;
     // replica operand: column l32 = 8 b + j takes the byte-b table of the
-    // PRN at chip (window chip + shift jmin + j); K step ks, lane half h
-    // covers window positions 8 ks + 4 h .. + 3
+    // PRN at chip (window chip + shift jmin + j); in K step ks lane half h
+    // covers window positions 8 ks + h + 2 i (i = 0..3), four chips two
+    // apart: one 16-byte read from the table of their parity
     const int jsh = (int)(((int64_t)jmin + (int64_t)(l32 & 7)) % kCodeLen);
-    const uint32_t b_lane = (uint32_t)(jsh < 0 ? jsh + kCodeLen : jsh) + 4u * h;
-    const uint32_t* btab =
-        tables + kTabMtapCode + ((ch.prn - 1) * 4 + (int)(l32 >> 3)) * kMtapCodeWords + b_lane;
+    const uint32_t b_lane = (uint32_t)(jsh < 0 ? jsh + kCodeLen : jsh) + h;
+    const uint32_t* btab = tables + kTabMtapCode + ((ch.prn - 1) * 4 + (int)(l32 >> 3)) * kMtapCodeWords;
     // per-lane parts of the sample walk
     const uint64_t lane_dU = (uint64_t)lane * m.dp;
     const uint32_t lane_dph = lane * m.dphi;
@@ -446,8 +454,9 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
     asm("" : "+v"(dUv));
     asm("" : "+v"(dU2v));
     asm("" : "+v"(dph2v));
-    // A fragment of K step ks: window positions 8 ks + 4 h + i, row l32
-    const uint32_t a_base = s_base + 128u * 4u * h + 4u * l32;
+    // A fragment of K step ks: window positions 8 ks + h + 2 i, row l32
+    // (the two lane halves read chips one apart: distinct banks)
+    const uint32_t a_base = s_base + 128u * h + 4u * l32;
 
     // contiguous chunk of tiles for this block; chunks belong to the tile
     // holding their first sample
@@ -492,9 +501,10 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
             // the window's replica operand, in flight during stage 1
             int4_t bop[4];
             {
-                const uint32_t* bp = btab + k.wmod;
+                const uint32_t x = k.wmod + b_lane;  // chip of position h (i = 0, ks = 0)
+                const uint32_t* bp = btab + (x & 1u) * kMtapHalfWords + (x >> 1);
 #pragma unroll
-                for (int ks = 0; ks < 4; ++ks) bop[ks] = *reinterpret_cast<const int4_t*>(bp + 8 * ks);
+                for (int ks = 0; ks < 4; ++ks) bop[ks] = *reinterpret_cast<const int4_t*>(bp + 4 * ks);
             }
             // stage 1: clear S (32 x 32 cells), scatter the chunk's samples
             {
@@ -564,9 +574,9 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
             for (int ks = 0; ks < 4; ++ks) {
                 const uint8_t* ap = s_lds + a_base + 1024u * ks;
                 const int4_t a = int4_t{*reinterpret_cast<const int*>(ap),
-                                        *reinterpret_cast<const int*>(ap + 128),
                                         *reinterpret_cast<const int*>(ap + 256),
-                                        *reinterpret_cast<const int*>(ap + 384)};
+                                        *reinterpret_cast<const int*>(ap + 512),
+                                        *reinterpret_cast<const int*>(ap + 768)};
                 if (ks % 2 == 0)
                     acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, bop[ks], acc0, 0, 0, 0);
                 else
