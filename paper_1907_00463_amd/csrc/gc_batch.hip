@@ -34,7 +34,7 @@ struct gc_batch {
     gc::PbinItem* d_pitems;
     uint32_t n_pitems, max_pitems;
     uint32_t* d_order;         // chip-by-chip items with work (written on the device)
-    uint32_t* d_count;         // their number
+    uint32_t* d_count;         // their number, then the periodic kernel's queue counter
     int cus;
     float tuned_ms;
     hipStream_t cap;           // private stream for graph capture
@@ -99,6 +99,12 @@ hipError_t upload_pitems(gc_batch* b, int chunk) {
                 h.push_back(gc::PbinItem{r, cb + first, std::min(kGroup, nc - first), t,
                                          std::min(nt, t + (uint32_t)chunk)});
     }
+    // the queue hands out larger items (more channels, more tiles) first, so
+    // that the last items to finish are small ones
+    std::stable_sort(h.begin(), h.end(), [](const gc::PbinItem& a, const gc::PbinItem& c) {
+        return (uint64_t)a.n_chan * (a.tile_end - a.tile_begin) >
+               (uint64_t)c.n_chan * (c.tile_end - c.tile_begin);
+    });
     if (h.size() > b->max_pitems) return hipErrorInvalidValue;
     b->n_pitems = (uint32_t)h.size();
     if (h.empty()) return hipSuccess;
@@ -112,9 +118,9 @@ hipError_t enqueue(gc_batch* b, hipStream_t s) {
                                     GC_CARRIER_LUT, b->max_dumps, b->out, b->max_taps, b->dump_n,
                                     b->n_dumps, b->status, allow, b->d_rx, nullptr, nullptr, s);
     if (e == hipSuccess && b->pchunk > 0)
-        e = gc::launch_pbin_batch(b->cus, b->d_rx, b->d_pitems, b->n_pitems, b->d_chans,
-                                  b->d_meta, b->state, (int32_t*)b->out, b->max_taps,
-                                  b->max_dumps, b->ctx->d_tables, s);
+        e = gc::launch_pbin_batch(b->cus, b->d_rx, b->d_pitems, b->n_pitems, b->d_count + 1,
+                                  b->d_chans, b->d_meta, b->state, (int32_t*)b->out,
+                                  b->max_taps, b->max_dumps, b->ctx->d_tables, s);
     // with the periodic kernel on, the chip-by-chip kernel runs only the
     // tiles of receivers that still have work, selected on the device
     const bool sel = b->pchunk > 0;
@@ -217,7 +223,7 @@ gc_status gc_batch_create(gc_ctx* ctx, const gc_rx_desc* rx, int32_t n_rx,
     if (e == hipSuccess)
         e = hipMalloc(&b->d_pitems, sizeof(gc::PbinItem) * (size_t)std::max(1u, b->max_pitems));
     if (e == hipSuccess) e = hipMalloc(&b->d_order, sizeof(uint32_t) * (size_t)max_items);
-    if (e == hipSuccess) e = hipMalloc(&b->d_count, sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&b->d_count, 2 * sizeof(uint32_t));
     if (e == hipSuccess)
         e = hipMemcpy(b->d_chans, h.data(), sizeof(gc::DevChan) * (size_t)n_chan,
                       hipMemcpyHostToDevice);

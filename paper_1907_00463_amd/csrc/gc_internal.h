@@ -153,10 +153,11 @@ hipError_t launch_pbin(const uint8_t* samples, uint64_t n_samples, int fmt, cons
                        int tap_stride, uint32_t max_dumps, const uint32_t* d_tables, int grid,
                        hipStream_t s);
 int pbin_tile_samples();
+// counter: one device word, the items' queue (reset on the stream first)
 hipError_t launch_pbin_batch(int grid, const DevRx* rx, const PbinItem* items, uint32_t n_items,
-                             const DevChan* chans, const DevMeta* meta, gc_chan_state* state,
-                             int32_t* out, int tap_stride, uint32_t max_dumps,
-                             const uint32_t* tables, hipStream_t s);
+                             uint32_t* counter, const DevChan* chans, const DevMeta* meta,
+                             gc_chan_state* state, int32_t* out, int tap_stride,
+                             uint32_t max_dumps, const uint32_t* tables, hipStream_t s);
 hipError_t launch_mtap(const uint8_t* samples, uint64_t n_samples, int fmt, const DevChan* chans,
                        const DevMeta* meta, gc_chan_state* state, int n_chan, int32_t* out,
                        int tap_stride, uint32_t max_dumps, const uint32_t* d_tables, int grid,

@@ -460,23 +460,24 @@ __device__ __forceinline__ void clipped_run(Slot& S, const uint8_t* lds, uint32_
                          sgn_prn, span, d);
 }
 
-// One channel on the staged tile [t0, t1), by wave `sub` of the R waves
-// that share the channel: the tile's whole-chip bins are cut into R
-// contiguous shares (multiples of 64 bins) and the wave takes share `sub`;
-// wave 0 also takes the direct samples at the block ends and the slip seam.
+// One channel on the staged tile [t0, t1), share [n0, n1) of W: the tile's
+// whole-chip bins are cut at multiples of 64 bins near nb*n/W and the wave
+// takes the bins between the cuts at n0 and n1; the share starting at 0
+// also takes the direct samples at the block ends and the slip seam.
 template <int FMT, int L>
 __device__ __forceinline__ void channel_tile(Slot& S, const uint8_t* lds, uint32_t lane,
                                              uint32_t lane4, uint64_t t0, uint64_t t1,
                                              const DevMeta& m, const DevChan& ch,
                                              const uint32_t* __restrict__ sgn_prn, const Dest& d,
-                                             uint32_t sub, uint32_t R) {
+                                             uint32_t n0, uint32_t n1, uint32_t W) {
     const uint32_t span = (uint32_t)(m.window >> 32);
     const uint32_t tl = (uint32_t)(t1 - t0);
     // samples of chips cut by the ends of the block
-    if (sub == 0 && m.head_end > t0)
+    const bool lead = n0 == 0;
+    if (lead && m.head_end > t0)
         direct_epl(lds, lane4, t0, 0, (uint32_t)(min((uint64_t)m.head_end, t1) - t0), m, ch,
                    sgn_prn, d);
-    if (sub == 0 && t1 > m.tail_beg)
+    if (lead && t1 > m.tail_beg)
         direct_epl(lds, lane4, t0, (uint32_t)(max((uint64_t)m.tail_beg, t0) - t0), tl, m, ch,
                    sgn_prn, d);
     // bins of whole chips whose code phase starts in [u(t0), u(t1))
@@ -489,8 +490,8 @@ __device__ __forceinline__ void channel_tile(Slot& S, const uint8_t* lds, uint32
     if (hb <= ha) return;
     const uint32_t nb = (uint32_t)(hb - ha);
     // this wave's share of the bins (nb < 2^15, so 32-bit products)
-    const uint32_t pb = sub == 0 ? 0u : min(nb, ((nb * sub) / R + 63u) & ~63u);
-    const uint32_t pe = sub + 1 == R ? nb : min(nb, ((nb * (sub + 1)) / R + 63u) & ~63u);
+    const uint32_t pb = n0 == 0 ? 0u : min(nb, ((nb * n0) / W + 63u) & ~63u);
+    const uint32_t pe = n1 == W ? nb : min(nb, ((nb * n1) / W + 63u) & ~63u);
     // the open dump becomes the one of the share's first bin (the shares of
     // the other waves lie in between): flush what is open if that is later
     if (pb < pe) {
@@ -537,18 +538,22 @@ __device__ __forceinline__ void channel_tile(Slot& S, const uint8_t* lds, uint32
                         m, ch, sgn_prn, span, d);
     // bin ks-1 really ends at na + ks*L + sigma: the sample between the two
     // grids was counted twice (sigma = -1) or not at all (sigma = +1)
-    if (sub == 0 && lane == 0) {
+    if (lead && lane == 0) {
         const int64_t off = (int64_t)na + (int64_t)ks * L + (sigma < 0 ? -1 : 0);
         seam_sample(lds, lane4, t0, off, ha + ks - 1, sigma < 0 ? -1 : 1, m, ch, sgn_prn, span, d);
     }
 }
 
 // Tiles [tb0, tb1) of one sample block for the block's channel list
-// s_list[0 .. nlist), R waves per channel (nlist * R <= kMaxWaves); each
-// wave keeps its channel's sums in registers across the tiles and flushes
-// the dump still open at the end.
+// s_list[0 .. nlist), nlist <= W = blockDim.x / 64.  The channels' bins are
+// shared evenly among the W waves: wave w takes positions [w*nlist,
+// (w+1)*nlist) of nlist*W, channel c holding [c*W, (c+1)*W), so each wave
+// has one channel piece (when nlist divides W) or at most two.  A wave with
+// one piece keeps its channel's sums in registers across the tiles and
+// flushes the dump still open at the end; a wave with two flushes each
+// piece after every tile.
 template <int FMT>
-__device__ __forceinline__ void pbin_chunk(uint8_t* s_lds, const int* s_list, int nlist, int R,
+__device__ __forceinline__ void pbin_chunk(uint8_t* s_lds, const int* s_list, int nlist,
                                            const uint8_t* __restrict__ samples, uint64_t n,
                                            uint32_t tb0, uint32_t tb1,
                                            const DevChan* __restrict__ chans,
@@ -559,42 +564,63 @@ __device__ __forceinline__ void pbin_chunk(uint8_t* s_lds, const int* s_list, in
                                            const uint32_t* __restrict__ tables) {
     const int tid = threadIdx.x;
     const int nthreads = blockDim.x;
-    const int wave = tid / 64;
+    const uint32_t W = __builtin_amdgcn_readfirstlane((uint32_t)nthreads / 64);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane((uint32_t)tid / 64);
     const uint32_t lane = tid & 63;
     const uint32_t lane4 = lane * 4;
     Slot S;
+    auto reset = [&]() {
 #pragma unroll
-    for (int q = 0; q < 6; ++q) S.v[q] = 0;
-    S.e16 = S.l16 = short2_t{0, 0};
-    S.r[0] = S.r[1] = S.r[2] = S.r[3] = 0;
-    S.w = 0;
-    S.wnext = 0;
-    S.init = false;
-    const int slot = wave / R;
-    const uint32_t sub = (uint32_t)(wave - slot * R);
-    const bool active = slot < nlist;
-    const int chn = __builtin_amdgcn_readfirstlane(active ? s_list[slot] : s_list[0]);
-    const DevChan& ch = chans[chn];
-    const uint32_t* sgn_prn = tables + kTabSign + (ch.prn - 1) * kSignLen;
-    const DevMeta m = metas[chn];
-    const Dest d{out, state + chn, (uint64_t)chn * max_dumps, tap_stride, m.m_close};
+        for (int q = 0; q < 6; ++q) S.v[q] = 0;
+        S.e16 = S.l16 = short2_t{0, 0};
+        S.r[0] = S.r[1] = S.r[2] = S.r[3] = 0;
+        S.w = 0;
+        S.wnext = 0;
+        S.init = false;
+    };
+    reset();
+    // this wave's pieces: positions [x0, x1) of nlist * W
+    const uint32_t x0 = wave * (uint32_t)nlist, x1 = x0 + (uint32_t)nlist;
+    const uint32_t cA = x0 / W, cB = (x1 - 1) / W;
+    const bool two = cB != cA;
+    const uint32_t aN0 = x0 - cA * W, aN1 = two ? W : x1 - cA * W;
+    const uint32_t bN1 = x1 - cB * W;
+    auto piece = [&](uint32_t slot, uint32_t p0, uint32_t p1, uint64_t t0, uint64_t t1) {
+        const int chn = __builtin_amdgcn_readfirstlane(s_list[slot]);
+        const DevChan& ch = chans[chn];
+        const uint32_t* sgn_prn = tables + kTabSign + (ch.prn - 1) * kSignLen;
+        const DevMeta m = metas[chn];
+        const Dest d{out, state + chn, (uint64_t)chn * max_dumps, tap_stride, m.m_close};
+        switch (m.bin_len) {
+            case 2: channel_tile<FMT, 2>(S, s_lds, lane, lane4, t0, t1, m, ch, sgn_prn, d, p0, p1, W); break;
+            case 4: channel_tile<FMT, 4>(S, s_lds, lane, lane4, t0, t1, m, ch, sgn_prn, d, p0, p1, W); break;
+            case 8: channel_tile<FMT, 8>(S, s_lds, lane, lane4, t0, t1, m, ch, sgn_prn, d, p0, p1, W); break;
+            default: channel_tile<FMT, 10>(S, s_lds, lane, lane4, t0, t1, m, ch, sgn_prn, d, p0, p1, W); break;
+        }
+    };
+    auto flush = [&](uint32_t slot) {
+        if (S.init) {
+            const int chn = __builtin_amdgcn_readfirstlane(s_list[slot]);
+            const Dest d{out, state + chn, (uint64_t)chn * max_dumps, tap_stride,
+                         metas[chn].m_close};
+            wave_flush(S, d, chans[chn]);
+        }
+        reset();
+    };
     for (uint32_t tile = tb0; tile < tb1; ++tile) {
         const uint64_t t0 = (uint64_t)tile * kTile;
         const uint64_t t1 = min(n, t0 + kTile);
         __syncthreads();
         stage_tile<FMT>(samples, n, t0, s_lds, nthreads);
         __syncthreads();
-        if (active) {
-            switch (m.bin_len) {
-                case 2: channel_tile<FMT, 2>(S, s_lds, lane, lane4, t0, t1, m, ch, sgn_prn, d, sub, R); break;
-                case 4: channel_tile<FMT, 4>(S, s_lds, lane, lane4, t0, t1, m, ch, sgn_prn, d, sub, R); break;
-                case 8: channel_tile<FMT, 8>(S, s_lds, lane, lane4, t0, t1, m, ch, sgn_prn, d, sub, R); break;
-                default: channel_tile<FMT, 10>(S, s_lds, lane, lane4, t0, t1, m, ch, sgn_prn, d, sub, R); break;
-            }
+        for (uint32_t j = 0; j < (two ? 2u : 1u); ++j) {
+            const uint32_t slot = j ? cB : cA;
+            piece(slot, j ? 0u : aN0, j ? bN1 : aN1, t0, t1);
+            if (two) flush(slot);
         }
     }
     // the dump still open at the end of the chunk
-    if (active && S.init) wave_flush(S, d, ch);
+    if (!two) flush(cA);
 }
 
 // Periodic channels first .. of [c_begin, c_end) into s_list (at most
@@ -637,43 +663,53 @@ __global__ __launch_bounds__(kMaxWaves * 64) void k_pbin(const uint8_t* __restri
     __syncthreads();
     const int nlist = s_list[kMaxWaves];
     if (nlist == 0) return;
-    const int R = (int)(blockDim.x / 64) / nlist;
     for (int i = threadIdx.x; i < kLutWords; i += blockDim.x) s_lut[i] = tables[kTabLut + (i >> 6)];
     // contiguous chunk of tiles for this block
     const uint32_t tb0 = (uint32_t)(((uint64_t)blockIdx.x * n_tiles) / gridDim.x);
     const uint32_t tb1 = (uint32_t)(((uint64_t)(blockIdx.x + 1) * n_tiles) / gridDim.x);
-    pbin_chunk<FMT>(s_lds, s_list, nlist, R, samples, n, tb0, tb1, chans, metas, state, out,
+    pbin_chunk<FMT>(s_lds, s_list, nlist, samples, n, tb0, tb1, chans, metas, state, out,
                     tap_stride, max_dumps, tables);
 }
 
 // Many receivers in one persistent launch: item i is a chunk of tiles of
 // one receiver for a group of at most kMaxWaves of its channels; the block
-// lists the group's periodic channels, one wave each (R = 1), or R =
-// kMaxWaves / nlist waves each when that is 2 or more.
+// lists the group's periodic channels and shares their bins evenly among
+// its kMaxWaves waves.  Blocks take items from a queue (an atomic counter,
+// zeroed by k_queue_reset just before), so that items of unequal cost
+// (channel count, samples per chip) even out across the compute units.
+__global__ void k_queue_reset(uint32_t* __restrict__ counter) {
+    if (threadIdx.x == 0) *counter = 0;
+}
+
 __global__ __launch_bounds__(kMaxWaves * 64) void k_pbin_batch(
     const DevRx* __restrict__ rx, const PbinItem* __restrict__ items, uint32_t n_items,
-    const DevChan* __restrict__ chans, const DevMeta* __restrict__ metas,
-    gc_chan_state* __restrict__ state, int32_t* __restrict__ out, int tap_stride,
-    uint32_t max_dumps, const uint32_t* __restrict__ tables) {
-    __shared__ __attribute__((aligned(16))) uint8_t s_lds[kLdsBytes + 4 * (kMaxWaves + 1)];
+    uint32_t* __restrict__ counter, const DevChan* __restrict__ chans,
+    const DevMeta* __restrict__ metas, gc_chan_state* __restrict__ state,
+    int32_t* __restrict__ out, int tap_stride, uint32_t max_dumps,
+    const uint32_t* __restrict__ tables) {
+    __shared__ __attribute__((aligned(16))) uint8_t s_lds[kLdsBytes + 4 * (kMaxWaves + 2)];
     uint32_t* s_lut = reinterpret_cast<uint32_t*>(s_lds);
     int* s_list = reinterpret_cast<int*>(s_lds + kLdsBytes);
+    uint32_t* s_item = reinterpret_cast<uint32_t*>(s_lds + kLdsBytes) + kMaxWaves + 1;
     for (int i = threadIdx.x; i < kLutWords; i += blockDim.x) s_lut[i] = tables[kTabLut + (i >> 6)];
-    for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+    for (;;) {
+        __syncthreads();   // the previous item is done with s_list, s_item and the tile
+        if (threadIdx.x == 0) *s_item = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t it = *s_item;
+        if (it >= n_items) break;   // every block ends on its first ticket past the end
         const PbinItem I = items[it];
-        __syncthreads();   // the previous item is done with s_list and the tile
         list_periodic(s_list, metas, I.chan_begin, I.chan_begin + I.n_chan, 0, kMaxWaves);
         __syncthreads();
         const int nlist = s_list[kMaxWaves];
         if (nlist == 0) continue;
-        const int R = kMaxWaves / nlist;
         const DevRx& X = rx[I.rx];
         if (X.fmt == GC_I2_REAL)
-            pbin_chunk<GC_I2_REAL>(s_lds, s_list, nlist, R, X.samples, X.n, I.tile_begin,
+            pbin_chunk<GC_I2_REAL>(s_lds, s_list, nlist, X.samples, X.n, I.tile_begin,
                                    I.tile_end, chans, metas, state, out, tap_stride, max_dumps,
                                    tables);
         else
-            pbin_chunk<GC_I8_REAL>(s_lds, s_list, nlist, R, X.samples, X.n, I.tile_begin,
+            pbin_chunk<GC_I8_REAL>(s_lds, s_list, nlist, X.samples, X.n, I.tile_begin,
                                    I.tile_end, chans, metas, state, out, tap_stride, max_dumps,
                                    tables);
     }
@@ -702,13 +738,14 @@ void launch_one(const uint8_t* samples, uint64_t n, const DevChan* chans, const 
 int pbin_tile_samples() { return kTile; }
 
 hipError_t launch_pbin_batch(int grid, const DevRx* rx, const PbinItem* items, uint32_t n_items,
-                             const DevChan* chans, const DevMeta* meta, gc_chan_state* state,
-                             int32_t* out, int tap_stride, uint32_t max_dumps,
-                             const uint32_t* tables, hipStream_t s) {
+                             uint32_t* counter, const DevChan* chans, const DevMeta* meta,
+                             gc_chan_state* state, int32_t* out, int tap_stride,
+                             uint32_t max_dumps, const uint32_t* tables, hipStream_t s) {
     if (n_items == 0) return hipSuccess;
     const int g = (int)min((uint32_t)grid, n_items);
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, counter);
     hipLaunchKernelGGL(k_pbin_batch, dim3(g), dim3(64 * kMaxWaves), 0, s, rx, items, n_items,
-                       chans, meta, state, out, tap_stride, max_dumps, tables);
+                       counter, chans, meta, state, out, tap_stride, max_dumps, tables);
     return hipGetLastError();
 }
 
