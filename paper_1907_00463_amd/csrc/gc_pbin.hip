@@ -545,8 +545,8 @@ __device__ __forceinline__ void channel_tile(Slot& S, const uint8_t* lds, uint32
 }
 
 // Tiles [tb0, tb1) of one sample block for the block's channel list
-// s_list[0 .. nlist), nlist <= W = blockDim.x / 64.  The channels' bins are
-// shared evenly among the W waves: wave w takes positions [w*nlist,
+// s_list[0 .. nlist), nlist <= blockDim.x / 64.  The channels' bins are
+// shared evenly among W waves (W below): wave w takes positions [w*nlist,
 // (w+1)*nlist) of nlist*W, channel c holding [c*W, (c+1)*W), so each wave
 // has one channel piece (when nlist divides W) or at most two.  A wave with
 // one piece keeps its channel's sums in registers across the tiles and
@@ -564,8 +564,14 @@ __device__ __forceinline__ void pbin_chunk(uint8_t* s_lds, const int* s_list, in
                                            const uint32_t* __restrict__ tables) {
     const int tid = threadIdx.x;
     const int nthreads = blockDim.x;
-    const uint32_t W = __builtin_amdgcn_readfirstlane((uint32_t)nthreads / 64);
+    // waves used: all of the block's, unless the channels already fill three
+    // quarters of them; then one wave per channel (sharing a channel between
+    // waves costs a cut of its bins and a flush per tile, more than the
+    // remaining idle waves would gain)
+    const uint32_t Wb = __builtin_amdgcn_readfirstlane((uint32_t)nthreads / 64);
+    const uint32_t W = 4u * (uint32_t)nlist >= 3u * Wb ? (uint32_t)nlist : Wb;
     const uint32_t wave = __builtin_amdgcn_readfirstlane((uint32_t)tid / 64);
+    const bool busy = wave < W;
     const uint32_t lane = tid & 63;
     const uint32_t lane4 = lane * 4;
     Slot S;
@@ -580,7 +586,7 @@ __device__ __forceinline__ void pbin_chunk(uint8_t* s_lds, const int* s_list, in
     };
     reset();
     // this wave's pieces: positions [x0, x1) of nlist * W
-    const uint32_t x0 = wave * (uint32_t)nlist, x1 = x0 + (uint32_t)nlist;
+    const uint32_t x0 = (busy ? wave : 0u) * (uint32_t)nlist, x1 = x0 + (uint32_t)nlist;
     const uint32_t cA = x0 / W, cB = (x1 - 1) / W;
     const bool two = cB != cA;
     const uint32_t aN0 = x0 - cA * W, aN1 = two ? W : x1 - cA * W;
@@ -613,14 +619,14 @@ __device__ __forceinline__ void pbin_chunk(uint8_t* s_lds, const int* s_list, in
         __syncthreads();
         stage_tile<FMT>(samples, n, t0, s_lds, nthreads);
         __syncthreads();
-        for (uint32_t j = 0; j < (two ? 2u : 1u); ++j) {
+        for (uint32_t j = 0; j < (busy ? (two ? 2u : 1u) : 0u); ++j) {
             const uint32_t slot = j ? cB : cA;
             piece(slot, j ? 0u : aN0, j ? bN1 : aN1, t0, t1);
             if (two) flush(slot);
         }
     }
     // the dump still open at the end of the chunk
-    if (!two) flush(cA);
+    if (busy && !two) flush(cA);
 }
 
 // Periodic channels first .. of [c_begin, c_end) into s_list (at most
