@@ -157,3 +157,36 @@ def test_batch_equals_plans(g, ctx):
                 assert np.array_equal(out[i, :nd, :K], o[j, :nd, :K]), i
     finally:
         b.close()
+
+
+def test_batch_wide_receivers_share_waves(g, ctx):
+    # receivers of 9, 11, 12, 14, 16 and 17 channels: groups below three
+    # quarters of a block's 16 waves share their channels' bins over all 16
+    # (two channel pieces for some waves), fuller groups run one wave per
+    # channel; the 17-channel receiver spans two groups; items come from the
+    # device queue in size order.  Every channel bit-exact against the oracle.
+    rng = np.random.default_rng(905)
+    rates = [16.368e6, 8.184e6, 4.092e6, 16.368e6, 8.184e6, 16.368e6]
+    counts = [9, 11, 12, 14, 16, 17]
+    rx, cfgs, states, chan_rx = [], [], [], []
+    for r, (fs, nc) in enumerate(zip(rates, counts)):
+        fmt = (2, 0)[r % 2]
+        n = int(rng.integers(120_000, 260_000))
+        rx.append((fmt, n, rng.integers(0, 256, size=block_bytes(fmt, n), dtype=np.uint8)))
+        for c in range(nc):
+            T = int(rng.choice([1, 4, 20]))
+            cfgs.append(g.make_cfg(int(rng.integers(1, 33)), EPL, T))
+            fd = float(rng.uniform(-5000, 5000))
+            states.append(g.gc_nco_init(fs, fs / 4 + fd, float(rng.random()),
+                                        1.023e6 * (1 + fd / 1575.42e6),
+                                        float(rng.uniform(0, 1023 * T)), T))
+            chan_rx.append(r)
+    cfgs = np.array(cfgs, g.CHAN_CFG)
+    states = np.array(states, g.CHAN_STATE)
+    chan_rx = np.array(chan_rx)
+    b = _make_batch(g, ctx, rx, cfgs, states, chan_rx)
+    try:
+        b.launch()
+        _check(b, cfgs, _oracle_all(rx, cfgs, states, chan_rx))
+    finally:
+        b.close()

@@ -186,3 +186,20 @@ def test_multicorrelator_workload_sampled_channels(g, ctx):
             assert int(lst[i]["code_phase"]) == s.code_phase
             assert int(lst[i]["acc_n"]) == s.acc_n
             assert np.array_equal(lst[i]["acc"].reshape(-1).astype(np.int64), s.acc)
+
+
+@pytest.mark.parametrize("rate_scale", [1.0, 1.0 + 2e-6])
+def test_32_samples_per_chip_edge(g, ctx, rate_scale):
+    # code step exactly 2^27 (32 samples per chip: every cell row of a chip
+    # written, 1,024-sample windows) and just above it, complex int8 at
+    # 32.736 MHz; 128 taps, dumps of 1 and 4 periods
+    rng = np.random.default_rng(730)
+    fs = 32.736e6
+    rates = (1.023e6 * rate_scale,)
+    cfgs, states = _channels(g, rng, fs, 3, TAPS_128, periods=(1, 4, 1), rates=rates)
+    assert int(states["code_step"].min()) >= 1 << 27
+    lens = [70_000, 33_000]
+    blocks = _blocks(rng, 1, lens)
+    lib, lst = run_library(torch, ctx, 1, g.GC_CARRIER_LUT, cfgs, states, blocks, lens)
+    orc, ost = run_oracle(1, cfgs, states, blocks, lens)
+    assert_exact(lib, lst, orc, ost, cfgs)
