@@ -177,17 +177,12 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-// Control block of a channel, shared by the block's threads.
-struct Ctl {
+// What every wave needs of a step: the phases and steps at its first
+// sample, its sample count, and whether the walk is over.
+struct StepCtl {
     uint64_t p, dp, s;
-    uint32_t phi, dphi;
-    uint32_t acc_n, nd;
-    int32_t status;
-    int32_t done;
-    int64_t acc[6];
-    int32_t prev_i, prev_q, have_prev;  // the loop state's previous prompt
-    int32_t closes;                     // the step closes a dump
-    int64_t ang[2];                     // PLL and FLL angles of the closing dump
+    uint32_t phi, dphi, take;
+    int32_t status, done;
 };
 
 // ceil(num / d) for num < 2^53, d >= 1: a double estimate made exact.
@@ -215,9 +210,16 @@ __global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ 
     // 2-bit: (c, -s) int16 pairs of the carrier table, and per chip the
     // sign pairs (C, C) of chips c - 1, c, c + 1
     __shared__ uint32_t s_lut2[FMT == GC_I2_REAL ? 256 : 1];
-    __shared__ uint4 s_code4[FMT == GC_I2_REAL ? kCodeLen : 1];
+    // 2-bit: entry 2 (c + 2) + u for chip c = -2 .. 1022 (mod 1023) and half
+    // u of the chip: the (L, E, P) sign pairs, u = 0 (first half) (C[c-1],
+    // C[c], C[c]), u = 1 (second half) (C[c], C[c+1], C[c]); and per byte
+    // value its four samples as (x, x) int16 pairs
+    __shared__ uint4 s_codeh[FMT == GC_I2_REAL ? 2 * (kCodeLen + 2) : 1];
+    __shared__ uint4 s_x4[FMT == GC_I2_REAL ? 256 : 1];
     __shared__ int32_t s_red[6][kWaves];
-    __shared__ Ctl ctl;
+    __shared__ StepCtl sc;
+    __shared__ gc_loop_state s_loop;  // the loop state and filter coefficients, read and
+    __shared__ Coefs s_coef;          // written by wave 0 at each dump close
     __shared__ __align__(16) uint8_t s_stage[kStageBytes];
     const int tid = threadIdx.x;
     const int chn = blockIdx.x;
@@ -228,9 +230,25 @@ __global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ 
     for (int i = tid; i < kCodeLen; i += kThreads) {
         const int im = i == 0 ? kCodeLen - 1 : i - 1, ip = i + 1 == kCodeLen ? 0 : i + 1;
         s_code3[i] = (sgn[im] & 0xFFu) | (sgn[i] & 0xFFu) << 8 | (sgn[ip] & 0xFFu) << 16;
-        if constexpr (FMT == GC_I2_REAL) s_code4[i] = uint4{sgn[im], sgn[i], sgn[ip], 0u};
+        if constexpr (FMT == GC_I2_REAL) {
+            s_codeh[2 * (i + 2)] = uint4{sgn[im], sgn[i], sgn[i], 0u};
+            s_codeh[2 * (i + 2) + 1] = uint4{sgn[i], sgn[ip], sgn[i], 0u};
+            if (i >= kCodeLen - 2) {  // chips -2 and -1 are chips 1021 and 1022
+                const int sl = i - (kCodeLen - 2);
+                s_codeh[2 * sl] = uint4{sgn[im], sgn[i], sgn[i], 0u};
+                s_codeh[2 * sl + 1] = uint4{sgn[i], sgn[ip], sgn[i], 0u};
+            }
+        }
     }
     if constexpr (FMT == GC_I2_REAL) {
+        for (int i = tid; i < 256; i += kThreads) {
+            uint32_t v[4];
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t x = (uint32_t)(uint16_t)(2 * (int)((i >> (2 * j)) & 3) - 3);
+                v[j] = x | x << 16;
+            }
+            s_x4[i] = uint4{v[0], v[1], v[2], v[3]};
+        }
         for (int i = tid; i < 256; i += kThreads) {
             const uint32_t e = tables[kTabLut + i];
             const uint32_t c = e & 0xFFFFu, sn = e >> 16;
@@ -239,61 +257,99 @@ __global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ 
     }
     const uint64_t W = ch.window;
     gc_chan_state* st = states + chn;
-    gc_loop_state L;   // thread 0's copy
-    Coefs K;
-    if (tid == 0) {
-        K.T = (double)ch.int_periods * 1e-3;
-        loop_coef(P.pll_bw, P.pll_zeta, P.pll_k, K.t1c, K.t2c);
-        loop_coef(P.dll_bw, P.dll_zeta, P.dll_k, K.t1d, K.t2d);
-        ctl.status = GC_OK;
-        ctl.done = 0;
-        ctl.s = 0;
-        ctl.nd = 0;
-        ctl.p = st->code_phase;
-        ctl.dp = st->code_step;
-        ctl.phi = st->carr_phase;
-        ctl.dphi = st->carr_step;
-        ctl.acc_n = st->acc_n;
-        if (ch.n_taps != 3 || !ch.epl || ctl.p >= W) {
-            ctl.status = GC_EINVAL;
-        } else if (!step_ok(ctl.dp, W, FMT)) {
-            ctl.status = GC_ERANGE;
-        } else {
-            const int sl[3] = {ch.slot_e, ch.slot_p, ch.slot_l};
-            for (int k = 0; k < 3; ++k) {
-                ctl.acc[2 * k] = st->acc[sl[k]][0];
-                ctl.acc[2 * k + 1] = st->acc[sl[k]][1];
-            }
-            L = loops[chn];
-            ctl.prev_i = L.prompt_i_prev;
-            ctl.prev_q = L.prompt_q_prev;
-            ctl.have_prev = L.have_prev;
-        }
-    }
-    __syncthreads();
-    if (ctl.status != GC_OK) {
-        if (tid == 0) {
-            status[chn] = ctl.status;
-            n_dumps[chn] = 0;
-        }
-        return;
-    }
-    // The samples pass through LDS in windows of kStageBytes bytes that start
-    // at the 16-byte boundary below the first sample of a step; the window of
-    // the next step (which starts where this one ends) is loaded into
-    // registers while this step is summed and the loops are updated.
+    // The control state lives in wave 0's registers, the same in every lane
+    // of the wave: the lanes run the dump close together (the loop update
+    // redundantly, on equal inputs), so no control value makes an LDS round
+    // trip.  The other waves see each step's phases, steps and sample count
+    // in `sc`, written by lane 0 before the step's barrier.
+    const bool w0 = tid < 64;
+    int64_t acc[6] = {0, 0, 0, 0, 0, 0};
+    uint64_t p = 0, dp = 0, s = 0;
+    uint32_t phi = 0, dphi = 0, acc_n = 0, nd = 0;
+    int32_t status_w = GC_OK;
+    int32_t prev_i = 0, prev_q = 0, have_prev = 0;
     // samples whose bytes fit a window from any start (at most 15 bytes of
     // alignment before the first)
     constexpr uint32_t kStageSamples = FMT == GC_I2_REAL ? 4 * (kStageBytes - 17)
                                        : FMT == GC_I8_IQ ? (kStageBytes - 16) / 2
                                                          : kStageBytes - 16;
+    // samples of the next step: up to the window end, the block end or the
+    // stage size
+    auto step_take = [&]() -> uint32_t {
+        const uint64_t need = ceil_div53(W - p, dp);     // samples until the phase reaches W
+        return (uint32_t)min(min(need, n - s), (uint64_t)kStageSamples);
+    };
+    if (w0) {
+        if (tid == 0) {
+            Coefs K;
+            K.T = (double)ch.int_periods * 1e-3;
+            loop_coef(P.pll_bw, P.pll_zeta, P.pll_k, K.t1c, K.t2c);
+            loop_coef(P.dll_bw, P.dll_zeta, P.dll_k, K.t1d, K.t2d);
+            s_coef = K;
+        }
+        p = st->code_phase;
+        dp = st->code_step;
+        phi = st->carr_phase;
+        dphi = st->carr_step;
+        acc_n = st->acc_n;
+        if (ch.n_taps != 3 || !ch.epl || p >= W) {
+            status_w = GC_EINVAL;
+        } else if (!step_ok(dp, W, FMT)) {
+            status_w = GC_ERANGE;
+        } else {
+            const int sl[3] = {ch.slot_e, ch.slot_p, ch.slot_l};
+            for (int k = 0; k < 3; ++k) {
+                acc[2 * k] = st->acc[sl[k]][0];
+                acc[2 * k + 1] = st->acc[sl[k]][1];
+            }
+            const gc_loop_state L = loops[chn];
+            if (tid == 0) s_loop = L;
+            prev_i = L.prompt_i_prev;
+            prev_q = L.prompt_q_prev;
+            have_prev = L.have_prev;
+        }
+        const uint32_t take0 = status_w == GC_OK ? step_take() : 0u;
+        if (tid == 0) {
+            sc.p = p;
+            sc.dp = dp;
+            sc.s = s;
+            sc.phi = phi;
+            sc.dphi = dphi;
+            sc.take = take0;
+            sc.status = status_w;
+            sc.done = status_w != GC_OK;
+        }
+    }
+    __syncthreads();
+    if (sc.status != GC_OK) {
+        if (tid == 0) {
+            status[chn] = sc.status;
+            n_dumps[chn] = 0;
+        }
+        return;
+    }
+    // The samples pass through LDS in windows of kStageBytes bytes that start
+    // at the 16-byte boundary below the first sample of a step.  The window
+    // of the next step (which starts where this one ends) is loaded into
+    // registers while this step is summed, and stored to LDS once every wave
+    // is past this step's sums, while wave 0 closes the step.
     const uint64_t nbytes = FMT == GC_I2_REAL ? (n + 3) / 4 : FMT == GC_I8_IQ ? 2 * n : n;
     auto byte_of = [](uint64_t smp) -> uint64_t {
         return FMT == GC_I2_REAL ? smp >> 2 : FMT == GC_I8_IQ ? 2 * smp : smp;
     };
     int4v pf[kStagePieces / kThreads];
+    // A window wholly inside the block is plain 16-byte loads, left in
+    // flight until the window is stored (a per-piece choice between these
+    // and the byte-wise tail made every load wait at once); only the last
+    // window of a block takes the per-piece path.
     auto load_window = [&](uint64_t first) {
         const uint64_t b0 = byte_of(first) & ~(uint64_t)15;
+        if (b0 + kStageBytes <= nbytes) {
+#pragma unroll
+            for (int e = 0; e < kStagePieces / kThreads; ++e)
+                pf[e] = *reinterpret_cast<const int4v*>(samples + b0 + 16 * (uint64_t)(tid + kThreads * e));
+            return;
+        }
 #pragma unroll
         for (int e = 0; e < kStagePieces / kThreads; ++e) {
             const uint64_t b = b0 + 16 * (uint64_t)(tid + kThreads * e);
@@ -306,16 +362,22 @@ __global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ 
             }
         }
     };
-    load_window(0);
-    while (true) {
-        const uint64_t p = ctl.p, dp = ctl.dp, s0 = ctl.s;
-        const uint32_t phi = ctl.phi, dphi = ctl.dphi;
-        const uint64_t need = ceil_div53(W - p, dp);     // samples until the phase reaches W
-        const uint64_t take = min(min(need, n - s0), (uint64_t)kStageSamples);
+    auto readlane64 = [](int64_t v, int l) -> int64_t {
+        const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, l);
+        const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+        return (int64_t)(((uint64_t)hi << 32) | lo);
+    };
+    auto store_window = [&]() {
 #pragma unroll
         for (int e = 0; e < kStagePieces / kThreads; ++e)
             reinterpret_cast<int4v*>(s_stage)[tid + kThreads * e] = pf[e];
-        __syncthreads();
+    };
+    load_window(0);
+    store_window();
+    __syncthreads();
+    while (true) {
+        const uint64_t p0 = sc.p, dp0 = sc.dp, s0 = sc.s;
+        const uint32_t phi0 = sc.phi, dphi0 = sc.dphi, take = sc.take;
         load_window(s0 + take);
         const uint64_t b0 = byte_of(s0) & ~(uint64_t)15;
         int32_t a[6] = {0, 0, 0, 0, 0, 0};
@@ -323,29 +385,62 @@ __global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ 
         // code phases advance by fixed amounts from one to the next
         uint32_t off = (uint32_t)(byte_of(s0 + tid) - b0);
         const uint32_t sh2 = 2u * (uint32_t)((s0 + tid) & 3);   // 2-bit: bit offset in the byte
-        uint32_t ph = phi + (uint32_t)tid * dphi;
-        uint64_t u = p + (uint64_t)tid * dp;
-        const uint32_t dph = (uint32_t)kThreads * dphi;
-        const uint64_t du = (uint64_t)kThreads * dp;
+        uint32_t ph = phi0 + (uint32_t)tid * dphi0;
+        uint64_t u = p0 + (uint64_t)tid * dp0;
+        const uint32_t dph = (uint32_t)kThreads * dphi0;
+        const uint64_t du = (uint64_t)kThreads * dp0;
         constexpr uint32_t doff = FMT == GC_I2_REAL ? kThreads / 4 : FMT == GC_I8_IQ ? 2 * kThreads : kThreads;
         if constexpr (FMT == GC_I2_REAL) {
-            // 2-bit samples in int16 pairs: (wI, wQ) = x (c, -s) in one packed
-            // multiply, then E, P and L by packed multiply-adds with the
-            // chips' sign pairs; a thread's partial sums stay below
-            // (kStageSamples / kThreads + 1) * 72 < 2^15
+            // 2-bit samples, four consecutive ones per thread and pass:
+            // thread t takes the byte Bs + t + kThreads k (Bs = s0 / 4) and
+            // its samples 4 B + j, j = 0..3, expanded by s_x4 into (x, x)
+            // int16 pairs.  (wI, wQ) = x (c, -s) in one packed multiply, then
+            // E, P and L by packed multiply-adds with the sign pairs.  The
+            // chip of the byte's last sample is reduced mod 1023 once; its
+            // four samples, at most two chips back, index s_codeh by their
+            // half-chip count less that of that chip's start.  Samples outside
+            // [s0, s0 + take), in the first and last byte, count as 0 (their
+            // table index is kept in range).  The reference chip is that of
+            // the byte's last sample, never before s0, so no code phase of a
+            // counted sample wraps below 0.  A
+            // thread's partial sums stay below (kStageSamples / kThreads +
+            // 4) * 72 < 2^15.
             short2_t sE = {0, 0}, sP = {0, 0}, sL = {0, 0};
-            for (uint32_t i = tid; i < (uint32_t)take; i += kThreads, off += doff, ph += dph, u += du) {
-                const int xi = 2 * (int)((s_stage[off] >> sh2) & 3) - 3;
-                const short2_t x2 = as_s2((uint32_t)(uint16_t)xi * 0x10001u);
-                const short2_t w2 = x2 * as_s2(s_lut2[ph >> 24]);
-                const uint32_t cp = (uint32_t)((u >> 32) % kCodeLen);
-                const bool upper = (uint32_t)u >= (1u << 31);
-                const uint4 c4 = s_code4[cp];
-                const short2_t e2 = as_s2(upper ? c4.z : c4.y);
-                const short2_t l2 = as_s2(upper ? c4.y : c4.x);
-                sE = w2 * e2 + sE;
-                sP = w2 * as_s2(c4.y) + sP;
-                sL = w2 * l2 + sL;
+            const uint64_t Bs = s0 >> 2, send = s0 + take;
+            const uint32_t nb = (uint32_t)(((send - 1) >> 2) - Bs + 1);  // bytes of the step
+            const uint32_t npass = (nb + kThreads - 1) / kThreads;
+            const uint32_t r0 = 4u * (uint32_t)tid - (uint32_t)(s0 & 3);  // offset of sample j = 0
+            uint32_t ph4 = phi0 + r0 * dphi0;
+            uint64_t u4 = p0 + (uint64_t)(int64_t)(int32_t)r0 * dp0;  // wraps where r0 < 0 (masked)
+            const uint32_t dph4 = 4u * kThreads * dphi0;
+            const uint64_t du4 = 4ull * kThreads * dp0;
+            const uint64_t dpj[4] = {0, dp0, 2 * dp0, 3 * dp0};
+            const uint32_t dphj[4] = {0, dphi0, 2 * dphi0, 3 * dphi0};
+            uint32_t offb = (uint32_t)(Bs - b0) + (uint32_t)tid;
+            for (uint32_t k = 0; k < npass; ++k, offb += kThreads, ph4 += dph4, u4 += du4) {
+                const bool edge = k == 0 || k + 1 == npass;  // uniform
+                const uint4 xs = s_x4[s_stage[edge ? min(offb, (uint32_t)kStageBytes - 1) : offb]];
+                uint32_t xv[4] = {xs.x, xs.y, xs.z, xs.w};
+                if (edge) {
+                    const uint64_t sb = 4 * (Bs + (uint64_t)tid + (uint64_t)kThreads * k);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (sb + j < s0 || sb + j >= send) xv[j] = 0;
+                }
+                const uint64_t uref = u4 + dpj[3];
+                const uint32_t cp = (uint32_t)((uref >> 32) % kCodeLen);
+                const uint32_t base = ((uint32_t)(uref >> 31) & ~1u) - 2u * (cp + 2u);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint64_t uj = u4 + dpj[j];
+                    const short2_t w2 = as_s2(xv[j]) * as_s2(s_lut2[(ph4 + dphj[j]) >> 24]);
+                    uint32_t ci = (uint32_t)(uj >> 31) - base;
+                    if (edge) ci = min(ci, (uint32_t)(2 * (kCodeLen + 2) - 1));
+                    const uint4 c = s_codeh[ci];
+                    sE = w2 * as_s2(c.y) + sE;
+                    sP = w2 * as_s2(c.z) + sP;
+                    sL = w2 * as_s2(c.x) + sL;
+                }
             }
             a[0] = sE.x;
             a[1] = sE.y;
@@ -392,73 +487,90 @@ __global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ 
             if ((tid & 63) == 63) s_red[k][tid >> 6] = t;
         }
         __syncthreads();
-        if (tid < 64) {  // wave 0 closes the step
-            if (tid < 6) {  // the six sums in parallel, one lane each
-                int64_t t = 0;
+        if (!w0) store_window();  // every wave is done with this step's window
+        if (w0) {  // wave 0 closes the step
+            int64_t t = 0;  // the six sums in parallel, one lane each
+            if (tid < 6) {
 #pragma unroll
                 for (int w = 0; w < kWaves; ++w) t += s_red[tid][w];
-                ctl.acc[tid] += t;
             }
-            if (tid == 0) {
-                ctl.acc_n += (uint32_t)take;
-                ctl.phi = phi + (uint32_t)take * dphi;
-                ctl.p = p + take * dp;
-                ctl.s = s0 + take;
-                ctl.closes = ctl.p >= W && ctl.nd < max_dumps;
-                if (ctl.p >= W && ctl.nd >= max_dumps) ctl.status = GC_ENOSPC;
-            }
-            wave_sync();
-            if (ctl.closes) {  // the dump closes: both angles side by side, then the update
-                if (tid < 2 && (tid == 0 || ctl.have_prev)) {
+            store_window();  // after the sums' reads, ahead of the close
+#pragma unroll
+            for (int k = 0; k < 6; ++k) acc[k] += readlane64(t, k);
+            acc_n += take;
+            phi = phi0 + take * dphi0;
+            p = p0 + (uint64_t)take * dp0;
+            s = s0 + take;
+            const bool closes = p >= W && nd < max_dumps;
+            if (p >= W && nd >= max_dumps) status_w = GC_ENOSPC;
+            if (closes) {  // the dump closes: both angles side by side, then the update
+                int64_t ang = 0;
+                if (tid < 2 && (tid == 0 || have_prev)) {
                     int64_t y, x;
-                    loop_angle_args(tid, ctl.acc[2], ctl.acc[3], ctl.prev_i, ctl.prev_q, y, x);
-                    ctl.ang[tid] = atan2_q30(y, x, s_cordic);
+                    loop_angle_args((int)tid, acc[2], acc[3], prev_i, prev_q, y, x);
+                    ang = atan2_q30(y, x, s_cordic);
                 }
-                wave_sync();
-                if (tid == 0) {
-                    int32_t* r = rows + ((uint64_t)chn * max_dumps + ctl.nd) * 8;
-                    for (int k = 0; k < 6; ++k) r[k] = (int32_t)ctl.acc[k];
-                    r[6] = (int32_t)ctl.dphi;
-                    r[7] = (int32_t)(uint32_t)ctl.dp;
-                    dump_n[(uint64_t)chn * max_dumps + ctl.nd] = ctl.acc_n;
-                    ctl.nd += 1;
-                    uint32_t ncs;
-                    uint64_t nks;
-                    if (!loop_update(P, K, ctl.acc, ctl.ang[0], ctl.ang[1], L, ncs, nks) ||
-                        !step_ok(nks, W, FMT)) {
-                        ctl.status = GC_ERANGE;
-                    } else {
-                        ctl.dphi = ncs;
-                        ctl.dp = nks;
-                    }
-                    ctl.prev_i = L.prompt_i_prev;
-                    ctl.prev_q = L.prompt_q_prev;
-                    ctl.have_prev = L.have_prev;
-                    for (int k = 0; k < 6; ++k) ctl.acc[k] = 0;
-                    ctl.acc_n = 0;
-                    ctl.p -= W;
+                const int64_t a_pll = readlane64(ang, 0), a_fll = readlane64(ang, 1);
+                if (tid < 8) {  // the row: six sums, then the NCO steps of the dump
+                    int32_t v = (int32_t)(uint32_t)dp;
+                    v = tid == 6 ? (int32_t)dphi : v;
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) v = tid == (uint32_t)k ? (int32_t)acc[k] : v;
+                    rows[((uint64_t)chn * max_dumps + nd) * 8 + tid] = v;
                 }
+                if (tid == 0) dump_n[(uint64_t)chn * max_dumps + nd] = acc_n;
+                nd += 1;
+                uint32_t ncs;
+                uint64_t nks;
+                gc_loop_state L = s_loop;
+                const Coefs K = s_coef;
+                const bool ok = loop_update(P, K, acc, a_pll, a_fll, L, ncs, nks);
+                if (tid == 0) s_loop = L;
+                if (!ok || !step_ok(nks, W, FMT)) {
+                    status_w = GC_ERANGE;
+                } else {
+                    dphi = ncs;
+                    dp = nks;
+                }
+                prev_i = L.prompt_i_prev;
+                prev_q = L.prompt_q_prev;
+                have_prev = L.have_prev;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) acc[k] = 0;
+                acc_n = 0;
+                p -= W;
             }
-            if (tid == 0) ctl.done = ctl.status != GC_OK || (ctl.s >= n && ctl.p < W);
+            const bool done = status_w != GC_OK || (s >= n && p < W);
+            const uint32_t take_n = done ? 0u : step_take();
+            if (tid == 0) {
+                sc.p = p;
+                sc.dp = dp;
+                sc.s = s;
+                sc.phi = phi;
+                sc.dphi = dphi;
+                sc.take = take_n;
+                sc.status = status_w;
+                sc.done = done;
+            }
         }
         __syncthreads();
-        if (ctl.done) break;
+        if (sc.done) break;
     }
     if (tid == 0) {
-        status[chn] = ctl.status;
-        if (ctl.status == GC_OK) {
-            n_dumps[chn] = ctl.nd;
-            st->code_phase = ctl.p;
-            st->code_step = ctl.dp;
-            st->carr_phase = ctl.phi;
-            st->carr_step = ctl.dphi;
-            st->acc_n = ctl.acc_n;
+        status[chn] = status_w;
+        if (status_w == GC_OK) {
+            n_dumps[chn] = nd;
+            st->code_phase = p;
+            st->code_step = dp;
+            st->carr_phase = phi;
+            st->carr_step = dphi;
+            st->acc_n = acc_n;
             const int sl[3] = {ch.slot_e, ch.slot_p, ch.slot_l};
             for (int k = 0; k < 3; ++k) {
-                st->acc[sl[k]][0] = (int32_t)ctl.acc[2 * k];
-                st->acc[sl[k]][1] = (int32_t)ctl.acc[2 * k + 1];
+                st->acc[sl[k]][0] = (int32_t)acc[2 * k];
+                st->acc[sl[k]][1] = (int32_t)acc[2 * k + 1];
             }
-            loops[chn] = L;
+            loops[chn] = s_loop;
         } else {
             n_dumps[chn] = 0;
         }
