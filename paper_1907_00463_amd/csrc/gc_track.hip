@@ -210,12 +210,10 @@ __global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ 
     // 2-bit: (c, -s) int16 pairs of the carrier table, and per chip the
     // sign pairs (C, C) of chips c - 1, c, c + 1
     __shared__ uint32_t s_lut2[FMT == GC_I2_REAL ? 256 : 1];
-    // 2-bit: entry 2 (c + 2) + u for chip c = -2 .. 1022 (mod 1023) and half
-    // u of the chip: the (L, E, P) sign pairs, u = 0 (first half) (C[c-1],
-    // C[c], C[c]), u = 1 (second half) (C[c], C[c+1], C[c]); and per byte
-    // value its four samples as (x, x) int16 pairs
-    __shared__ uint4 s_codeh[FMT == GC_I2_REAL ? 2 * (kCodeLen + 2) : 1];
-    __shared__ uint4 s_x4[FMT == GC_I2_REAL ? 256 : 1];
+    // 2-bit: entry 2 c + u for chip c and half u of the chip: the (L, E, P)
+    // sign pairs, u = 0 (first half) (C[c-1], C[c], C[c]), u = 1 (second
+    // half) (C[c], C[c+1], C[c])
+    __shared__ uint4 s_codeh[FMT == GC_I2_REAL ? 2 * kCodeLen : 1];
     __shared__ int32_t s_red[6][kWaves];
     __shared__ StepCtl sc;
     __shared__ gc_loop_state s_loop;  // the loop state and filter coefficients, read and
@@ -231,24 +229,11 @@ __global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ 
         const int im = i == 0 ? kCodeLen - 1 : i - 1, ip = i + 1 == kCodeLen ? 0 : i + 1;
         s_code3[i] = (sgn[im] & 0xFFu) | (sgn[i] & 0xFFu) << 8 | (sgn[ip] & 0xFFu) << 16;
         if constexpr (FMT == GC_I2_REAL) {
-            s_codeh[2 * (i + 2)] = uint4{sgn[im], sgn[i], sgn[i], 0u};
-            s_codeh[2 * (i + 2) + 1] = uint4{sgn[i], sgn[ip], sgn[i], 0u};
-            if (i >= kCodeLen - 2) {  // chips -2 and -1 are chips 1021 and 1022
-                const int sl = i - (kCodeLen - 2);
-                s_codeh[2 * sl] = uint4{sgn[im], sgn[i], sgn[i], 0u};
-                s_codeh[2 * sl + 1] = uint4{sgn[i], sgn[ip], sgn[i], 0u};
-            }
+            s_codeh[2 * i] = uint4{sgn[im], sgn[i], sgn[i], 0u};
+            s_codeh[2 * i + 1] = uint4{sgn[i], sgn[ip], sgn[i], 0u};
         }
     }
     if constexpr (FMT == GC_I2_REAL) {
-        for (int i = tid; i < 256; i += kThreads) {
-            uint32_t v[4];
-            for (int j = 0; j < 4; ++j) {
-                const uint32_t x = (uint32_t)(uint16_t)(2 * (int)((i >> (2 * j)) & 3) - 3);
-                v[j] = x | x << 16;
-            }
-            s_x4[i] = uint4{v[0], v[1], v[2], v[3]};
-        }
         for (int i = tid; i < 256; i += kThreads) {
             const uint32_t e = tables[kTabLut + i];
             const uint32_t c = e & 0xFFFFu, sn = e >> 16;
@@ -391,56 +376,22 @@ __global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ 
         const uint64_t du = (uint64_t)kThreads * dp0;
         constexpr uint32_t doff = FMT == GC_I2_REAL ? kThreads / 4 : FMT == GC_I8_IQ ? 2 * kThreads : kThreads;
         if constexpr (FMT == GC_I2_REAL) {
-            // 2-bit samples, four consecutive ones per thread and pass:
-            // thread t takes the byte Bs + t + kThreads k (Bs = s0 / 4) and
-            // its samples 4 B + j, j = 0..3, expanded by s_x4 into (x, x)
-            // int16 pairs.  (wI, wQ) = x (c, -s) in one packed multiply, then
-            // E, P and L by packed multiply-adds with the sign pairs.  The
-            // chip of the byte's last sample is reduced mod 1023 once; its
-            // four samples, at most two chips back, index s_codeh by their
-            // half-chip count less that of that chip's start.  Samples outside
-            // [s0, s0 + take), in the first and last byte, count as 0 (their
-            // table index is kept in range).  The reference chip is that of
-            // the byte's last sample, never before s0, so no code phase of a
-            // counted sample wraps below 0.  A
-            // thread's partial sums stay below (kStageSamples / kThreads +
-            // 4) * 72 < 2^15.
+            // 2-bit samples: x as an (x, x) int16 pair, (wI, wQ) = x (c, -s)
+            // in one packed multiply, then E, P and L by packed
+            // multiply-adds with the sign pairs of the sample's half-chip.
+            // A thread's partial sums stay below
+            // (kStageSamples / kThreads) * 72 < 2^15.
             short2_t sE = {0, 0}, sP = {0, 0}, sL = {0, 0};
-            const uint64_t Bs = s0 >> 2, send = s0 + take;
-            const uint32_t nb = (uint32_t)(((send - 1) >> 2) - Bs + 1);  // bytes of the step
-            const uint32_t npass = (nb + kThreads - 1) / kThreads;
-            const uint32_t r0 = 4u * (uint32_t)tid - (uint32_t)(s0 & 3);  // offset of sample j = 0
-            uint32_t ph4 = phi0 + r0 * dphi0;
-            uint64_t u4 = p0 + (uint64_t)(int64_t)(int32_t)r0 * dp0;  // wraps where r0 < 0 (masked)
-            const uint32_t dph4 = 4u * kThreads * dphi0;
-            const uint64_t du4 = 4ull * kThreads * dp0;
-            const uint64_t dpj[4] = {0, dp0, 2 * dp0, 3 * dp0};
-            const uint32_t dphj[4] = {0, dphi0, 2 * dphi0, 3 * dphi0};
-            uint32_t offb = (uint32_t)(Bs - b0) + (uint32_t)tid;
-            for (uint32_t k = 0; k < npass; ++k, offb += kThreads, ph4 += dph4, u4 += du4) {
-                const bool edge = k == 0 || k + 1 == npass;  // uniform
-                const uint4 xs = s_x4[s_stage[edge ? min(offb, (uint32_t)kStageBytes - 1) : offb]];
-                uint32_t xv[4] = {xs.x, xs.y, xs.z, xs.w};
-                if (edge) {
-                    const uint64_t sb = 4 * (Bs + (uint64_t)tid + (uint64_t)kThreads * k);
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        if (sb + j < s0 || sb + j >= send) xv[j] = 0;
-                }
-                const uint64_t uref = u4 + dpj[3];
-                const uint32_t cp = (uint32_t)((uref >> 32) % kCodeLen);
-                const uint32_t base = ((uint32_t)(uref >> 31) & ~1u) - 2u * (cp + 2u);
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const uint64_t uj = u4 + dpj[j];
-                    const short2_t w2 = as_s2(xv[j]) * as_s2(s_lut2[(ph4 + dphj[j]) >> 24]);
-                    uint32_t ci = (uint32_t)(uj >> 31) - base;
-                    if (edge) ci = min(ci, (uint32_t)(2 * (kCodeLen + 2) - 1));
-                    const uint4 c = s_codeh[ci];
-                    sE = w2 * as_s2(c.y) + sE;
-                    sP = w2 * as_s2(c.z) + sP;
-                    sL = w2 * as_s2(c.x) + sL;
-                }
+            for (uint32_t i = tid; i < (uint32_t)take; i += kThreads, off += doff, ph += dph, u += du) {
+                const int xi = 2 * (int)((s_stage[off] >> sh2) & 3) - 3;
+                const short2_t x2 = as_s2((uint32_t)(uint16_t)xi * 0x10001u);
+                const short2_t w2 = x2 * as_s2(s_lut2[ph >> 24]);
+                const uint32_t cp = (uint32_t)((u >> 32) % kCodeLen);
+                const bool upper = (uint32_t)u >= (1u << 31);
+                const uint4 c = s_codeh[2 * cp + (upper ? 1u : 0u)];
+                sE = w2 * as_s2(c.y) + sE;
+                sP = w2 * as_s2(c.z) + sP;
+                sL = w2 * as_s2(c.x) + sL;
             }
             a[0] = sE.x;
             a[1] = sE.y;
