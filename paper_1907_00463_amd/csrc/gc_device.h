@@ -122,6 +122,37 @@ __device__ __forceinline__ int wave_total_dpp(int v) {
     return __builtin_amdgcn_readlane(v, 63);
 }
 
+// Six wavefront sums at once (all 64 lanes active).  The six values (two
+// zeros pad them to eight) are halved over lane pairs three times, lane
+// l ^ 7, then l ^ 2, then l ^ 1: each lane keeps the half its lane bit picks
+// and adds the partner's copy of that half, so that afterwards lane l holds
+// value l & 7 summed over its group of eight lanes.  That one value is then
+// summed over the row (l ^ 8) and over the four rows (l ^ 16, l ^ 32).
+// Lanes 0-5 (and 8-13, ...) return the totals of v[0] .. v[5].
+__device__ __forceinline__ int wave_total6(const int (&v)[6]) {
+    const uint32_t lane = threadIdx.x & 63;
+    const bool b2 = (lane & 4) != 0, b1 = (lane & 2) != 0, b0 = (lane & 1) != 0;
+    int u[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int lo = v[k], hi = k + 4 < 6 ? v[k + 4] : 0;
+        const int send = b2 ? lo : hi;
+        u[k] = (b2 ? hi : lo) + __builtin_amdgcn_update_dpp(0, send, 0x141, 0xf, 0xf, false);  // row_half_mirror
+    }
+    int w[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int send = b1 ? u[k] : u[k + 2];
+        w[k] = (b1 ? u[k + 2] : u[k]) + __builtin_amdgcn_update_dpp(0, send, 0x4E, 0xf, 0xf, false);  // quad_perm [2,3,0,1]
+    }
+    int t = (b0 ? w[1] : w[0]) +
+            __builtin_amdgcn_update_dpp(0, b0 ? w[0] : w[1], 0xB1, 0xf, 0xf, false);  // quad_perm [1,0,3,2]
+    t += __builtin_amdgcn_update_dpp(0, t, 0x128, 0xf, 0xf, false);  // row_ror:8
+    t += __shfl_xor(t, 16, 64);
+    t += __shfl_xor(t, 32, 64);
+    return t;
+}
+
 // Wavefront sum (64 lanes) with DPP-backed cross-lane moves.
 __device__ __forceinline__ int wave_sum(int v) {
 #pragma unroll

@@ -119,15 +119,16 @@ __device__ __forceinline__ void fold(Slot& s, uint32_t par) {
     }
 }
 
-// Sum of the open dump over the wave's 64 lanes (all lanes active), one
-// atomic per output word from lane 0; Q is negated here (wipe-off Q = -x*s).
+// Sum of the open dump over the wave's 64 lanes (all lanes active): lanes
+// 0-5 receive the six totals (E I, E Q, P I, P Q, L I, L Q) and one atomic
+// instruction adds them to their output words; Q is negated here (wipe-off
+// Q = -x*s).
 __device__ __forceinline__ void wave_flush(const Slot& s, const Dest& d, const DevChan& ch) {
-    const int slot[3] = {ch.slot_e, ch.slot_p, ch.slot_l};
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        const int t = wave_total_dpp(s.v[k]);
-        if ((threadIdx.x & 63) == 0 && t != 0)
-            atomicAdd(d.at(s.w, slot[k >> 1], k & 1), (k & 1) ? -t : t);
+    const uint32_t lane = threadIdx.x & 63;
+    const int t = wave_total6(s.v);
+    if (lane < 6 && t != 0) {
+        const int slot = lane < 2 ? ch.slot_e : (lane < 4 ? ch.slot_p : ch.slot_l);
+        atomicAdd(d.at(s.w, slot, (int)(lane & 1)), (lane & 1) ? -t : t);
     }
 }
 
