@@ -379,19 +379,28 @@ __global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ 
             // 2-bit samples: x as an (x, x) int16 pair, (wI, wQ) = x (c, -s)
             // in one packed multiply, then E, P and L by packed
             // multiply-adds with the sign pairs of the sample's half-chip.
-            // A thread's partial sums stay below
+            // The code phase is kept as its fraction and its chip mod 1023:
+            // a thread's phase advances by du = kThreads dp < 2^41 per
+            // sample, so the chip moves by under 512 (plus the fraction's
+            // carry) and one conditional subtract keeps it below 1023.  A
+            // thread's partial sums stay below
             // (kStageSamples / kThreads) * 72 < 2^15.
             short2_t sE = {0, 0}, sP = {0, 0}, sL = {0, 0};
-            for (uint32_t i = tid; i < (uint32_t)take; i += kThreads, off += doff, ph += dph, u += du) {
-                const int xi = 2 * (int)((s_stage[off] >> sh2) & 3) - 3;
-                const short2_t x2 = as_s2((uint32_t)(uint16_t)xi * 0x10001u);
-                const short2_t w2 = x2 * as_s2(s_lut2[ph >> 24]);
-                const uint32_t cp = (uint32_t)((u >> 32) % kCodeLen);
-                const bool upper = (uint32_t)u >= (1u << 31);
-                const uint4 c = s_codeh[2 * cp + (upper ? 1u : 0u)];
+            uint32_t uf = (uint32_t)u;
+            uint32_t cp = (uint32_t)((u >> 32) % kCodeLen);
+            const uint32_t dfr = (uint32_t)du, dch = (uint32_t)(du >> 32);
+            for (uint32_t i = tid; i < (uint32_t)take; i += kThreads, off += doff, ph += dph) {
+                const uint32_t v = __builtin_amdgcn_ubfe((uint32_t)s_stage[off], sh2, 2u);
+                const uint32_t x16 = (2u * v + 0xFFFDu) & 0xFFFFu;  // 2 v - 3 in the low half
+                const short2_t w2 = as_s2(x16 * 0x10001u) * as_s2(s_lut2[ph >> 24]);
+                const uint4 c = s_codeh[2 * cp + (uf >> 31)];
                 sE = w2 * as_s2(c.y) + sE;
                 sP = w2 * as_s2(c.z) + sP;
                 sL = w2 * as_s2(c.x) + sL;
+                const uint32_t nf = uf + dfr;
+                cp += dch + (nf < uf ? 1u : 0u);
+                uf = nf;
+                cp = min(cp, cp - (uint32_t)kCodeLen);
             }
             a[0] = sE.x;
             a[1] = sE.y;
