@@ -441,10 +441,9 @@ __global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ 
             a[4] += wi * rl;
             a[5] += wq * rl;
         }
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            const int t = wave_total_dpp(a[k]);
-            if ((tid & 63) == 63) s_red[k][tid >> 6] = t;
+        {  // the wave's six sums land in lanes 0-5, one store
+            const int t = wave_total6(a);
+            if ((tid & 63) < 6) s_red[tid & 63][tid >> 6] = t;
         }
         __syncthreads();
         if (!w0) store_window();  // every wave is done with this step's window
