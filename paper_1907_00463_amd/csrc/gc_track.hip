@@ -389,7 +389,7 @@ __global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ 
             uint32_t uf = (uint32_t)u;
             uint32_t cp = (uint32_t)((u >> 32) % kCodeLen);
             const uint32_t dfr = (uint32_t)du, dch = (uint32_t)(du >> 32);
-            for (uint32_t i = tid; i < (uint32_t)take; i += kThreads, off += doff, ph += dph) {
+            auto one = [&]() {
                 const uint32_t v = __builtin_amdgcn_ubfe((uint32_t)s_stage[off], sh2, 2u);
                 const uint32_t x16 = (2u * v + 0xFFFDu) & 0xFFFFu;  // 2 v - 3 in the low half
                 const short2_t w2 = as_s2(x16 * 0x10001u) * as_s2(s_lut2[ph >> 24]);
@@ -401,7 +401,14 @@ __global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ 
                 cp += dch + (nf < uf ? 1u : 0u);
                 uf = nf;
                 cp = min(cp, cp - (uint32_t)kCodeLen);
-            }
+                off += doff;
+                ph += dph;
+            };
+            // passes in which every thread has a sample run on a uniform
+            // count; the last, partial pass is guarded per thread
+            const uint32_t nfull = (uint32_t)take / kThreads;
+            for (uint32_t k = 0; k < nfull; ++k) one();
+            if ((uint32_t)tid < (uint32_t)take - nfull * kThreads) one();
             a[0] = sE.x;
             a[1] = sE.y;
             a[2] = sP.x;
