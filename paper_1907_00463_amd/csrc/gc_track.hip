@@ -415,38 +415,49 @@ __global__ __launch_bounds__(kThreads) void k_track(const uint8_t* __restrict__ 
             a[3] = sP.y;
             a[4] = sL.x;
             a[5] = sL.y;
-        } else
-        for (uint32_t i = tid; i < (uint32_t)take; i += kThreads, off += doff, ph += dph, u += du) {
-            int xi, xq;
-            if constexpr (FMT == GC_I8_REAL) {
-                xi = (int)(int8_t)s_stage[off];
-                xq = 0;
-            } else if constexpr (FMT == GC_I8_IQ) {
-                xi = (int)(int8_t)s_stage[off];
-                xq = (int)(int8_t)s_stage[off + 1];
-            } else {
-                xi = 2 * (int)((s_stage[off] >> sh2) & 3) - 3;
-                xq = 0;
-            }
-            int c, sn;
-            lut_cs(s_lut[ph >> 24], c, sn);
-            int wi, wq;
-            wipe<FMT>(xi, xq, c, sn, wi, wq);
-            // prompt chip floor(u / 2^32) mod 1023; the early (late) chip is
-            // the next (previous) one when u's fraction is at or above
-            // (below) one half chip
-            const uint32_t cp = (uint32_t)((u >> 32) % kCodeLen);
-            const int sh = (uint32_t)u >= (1u << 31) ? 8 : 0;
-            const uint32_t c3 = s_code3[cp];
-            const int re = (int)(int8_t)(c3 >> (8 + sh));
-            const int rp = (int)(int8_t)(c3 >> 8);
-            const int rl = (int)(int8_t)(c3 >> sh);
-            a[0] += wi * re;
-            a[1] += wq * re;
-            a[2] += wi * rp;
-            a[3] += wq * rp;
-            a[4] += wi * rl;
-            a[5] += wq * rl;
+        } else {
+            // int8 samples: the same pass split, and the chip carried as in
+            // the 2-bit loop
+            uint32_t uf = (uint32_t)u;
+            uint32_t cp = (uint32_t)((u >> 32) % kCodeLen);
+            const uint32_t dfr = (uint32_t)du, dch = (uint32_t)(du >> 32);
+            auto one = [&]() {
+                int xi, xq;
+                if constexpr (FMT == GC_I8_IQ) {
+                    xi = (int)(int8_t)s_stage[off];
+                    xq = (int)(int8_t)s_stage[off + 1];
+                } else {
+                    xi = (int)(int8_t)s_stage[off];
+                    xq = 0;
+                }
+                int c, sn;
+                lut_cs(s_lut[ph >> 24], c, sn);
+                int wi, wq;
+                wipe<FMT>(xi, xq, c, sn, wi, wq);
+                // prompt chip floor(u / 2^32) mod 1023; the early (late) chip
+                // is the next (previous) one when u's fraction is at or above
+                // (below) one half chip
+                const int sh = uf >= (1u << 31) ? 8 : 0;
+                const uint32_t c3 = s_code3[cp];
+                const int re = (int)(int8_t)(c3 >> (8 + sh));
+                const int rp = (int)(int8_t)(c3 >> 8);
+                const int rl = (int)(int8_t)(c3 >> sh);
+                a[0] += wi * re;
+                a[1] += wq * re;
+                a[2] += wi * rp;
+                a[3] += wq * rp;
+                a[4] += wi * rl;
+                a[5] += wq * rl;
+                const uint32_t nf = uf + dfr;
+                cp += dch + (nf < uf ? 1u : 0u);
+                uf = nf;
+                cp = min(cp, cp - (uint32_t)kCodeLen);
+                off += doff;
+                ph += dph;
+            };
+            const uint32_t nfull = (uint32_t)take / kThreads;
+            for (uint32_t k = 0; k < nfull; ++k) one();
+            if ((uint32_t)tid < (uint32_t)take - nfull * kThreads) one();
         }
         {  // the wave's six sums land in lanes 0-5, one store
             const int t = wave_total6(a);
