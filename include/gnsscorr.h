@@ -356,7 +356,7 @@ gc_status gc_lock_metrics(gc_ctx* ctx, const int32_t* rows, int32_t row_stride,
                           void* stream);
 
 /* ------------------------------------------------------------------------
- * Acquisition (Sec. 3.6: the ACQ module searches a buffer of whole code
+ * Acquisition (Sec. 3.3: the ACQ module searches a buffer of whole code
  * periods for the satellites to track; Sec. 3.7: FFT-based search).
  *
  * A parallel code-phase search over Doppler bins and PRNs, computed exactly

@@ -1,5 +1,5 @@
 """Oracle of the acquisition search: parallel code-phase search (PCS) over
-Doppler bins and PRNs (Sec. 3.6: the ACQ module searches a buffer of whole
+Doppler bins and PRNs (Sec. 3.3: the ACQ module searches a buffer of whole
 code periods before tracking starts; Sec. 3.7: FFT-based search).
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).

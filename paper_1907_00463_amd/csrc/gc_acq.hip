@@ -1,5 +1,5 @@
 // gc_acq.hip -- acquisition search (parallel code-phase search over Doppler
-// bins and PRNs, Sec. 3.6 and 3.7) as an exact int8 contraction on the
+// bins and PRNs, Sec. 3.3 and 3.7) as an exact int8 contraction on the
 // matrix cores.
 //
 // The search computes, for Knc blocks of Mc code periods at R samples per
