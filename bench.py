@@ -16,13 +16,22 @@ lengths, 1 s each, one graph-captured persistent launch) and
 
 Prints ONE JSON line.  ``value`` is G sample*taps/s (one sample correlated
 against one tap, I and Q counted together).  ``roofline`` prices the main
-kernel's algorithmic work against the VALU peak (256 CUs * 64 lanes *
-2.4 GHz): 6 32-bit lane-ops per sample per channel for E/P/L (carrier NCO
-add, table lookup, two multiplies, two adds), 14 for the first stage of the
-multi-tap form; the kernel duration comes from HIP events the library
-records around that kernel on the launch stream.  ``cpu_baseline`` is the
-CPU oracle on a bounded sample of the same stream; ``plain`` is one plan and
-one direct-kernel launch per channel on the same GPU.
+kernel's algorithmic integer operations against MI355X's published vector
+peak, 157.3 T ops/s (256 CUs x 64 lanes x 2.4 GHz x 4: a packed two-wide
+multiply-add is four operations per lane and clock, the most any
+instruction of these kernels performs), so ``frac`` cannot exceed 1: 6 ops
+per sample per channel for E/P/L on real input (carrier NCO add, table
+lookup, two multiplies, two adds), 10 on complex input, 14 for the first
+stage of the multi-tap form.  ``valu_issue_frac`` is the measured share of
+VALU issue cycles (SQ_INSTS_VALU x 4 clocks over 1024 SIMDs) from the
+committed counter summary, while that summary matches the kernel source.
+The kernel duration comes from HIP events the library records around that
+kernel on the launch stream.  ``cpu_baseline`` is the CPU oracle on a
+bounded sample of the same stream; ``plain`` is one plan and one
+direct-kernel launch per channel on the same GPU.  The default line also
+carries ``served``: a 2 s slice of the serving schedule through the
+continuous-batching server and the plain server, p50/p99 latency against
+the 1 ms deadline.
 """
 from __future__ import annotations
 
@@ -38,13 +47,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "G sample·taps/s E/P/L correlation vs plain; real-time channels; served p99 latency"
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12     # 32-bit lane-ops/s, T
+VALU_ISSUE_TSLOTS = 256 * 4 * 2.4e9 / 4 * 64 / 1e12  # lane-instruction slots/s, T (39.32)
+VALU_PEAK_TOPS = 157.3                       # published vector peak, T ops/s (4 per lane-clock)
 INT8_MFMA_PEAK_TOPS = 5000.0                 # dense int8 MFMA, T ops/s (2 ops per MAC)
-OPS_PER_SAMPLE_CHANNEL = 6
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 KERNEL_SETS = {"auto": None, "binned": 2, "direct": 0}
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_pbin_i2_12ch_10s_counters.md")
+
+
+def alu_roofline(ops_per_unit: float, units: float, kernel_s: float, **extra) -> dict:
+    """Algorithmic integer ops of one launch over its duration, against the
+    published vector peak (frac <= 1 by construction)."""
+    achieved = ops_per_unit * units / kernel_s / 1e12
+    r = {"bound": "alu", "achieved": round(achieved, 4), "peak": VALU_PEAK_TOPS,
+         "unit": "T ops/s", "frac": round(achieved / VALU_PEAK_TOPS, 5), "traffic": None,
+         "kernel_ms": round(kernel_s * 1e3, 4), "ops_per_sample_channel": ops_per_unit}
+    r.update(extra)
+    return r
 
 
 def realtime_channels(channels: int, data_seconds: float, wall_seconds: float) -> float:
@@ -67,6 +87,10 @@ WORKLOADS = {
         describe="64 receivers x 8-14 channels, fs 4.092/8.184/16.368 MHz (IF fs/4), int8 or "
                  "2-bit real, 1/4/20 ms dumps per channel, %g s each, E/P/L at +-1/2 chip",
         seconds=1.0, ops=6, fmt_name="i8_real+i2_real", cpu_seconds=1.0),
+    "paper": dict(
+        describe="12 channels, complex int8 (I then Q), fs 5 MHz, IF 0, %g s, 1 ms dumps, E/P/L "
+                 "at +-1/2 chip (the paper's offline configuration)", seconds=10.0, ops=10,
+        fmt_name="i8_iq", cpu_seconds=10.0),
     "multicorrelator": dict(
         describe="256 channels x 128 taps (-2 + k/32 chips), complex int8, fs 20.46 MHz, IF 0, "
                  "%g s, 1 ms dumps", seconds=2.0, ops=14, fmt_name="i8_iq",
@@ -93,6 +117,7 @@ def build_inputs(workload: str, seconds: float):
     from paper_1907_00463_amd import synth
 
     make = {"twelve": synth.workload_twelve_channels, "single": synth.workload_single_channel,
+            "paper": synth.workload_paper,
             "multicorrelator": synth.workload_multicorrelator}[workload]
     st, chans, rng = make(seconds=seconds)
     buf = synth.synth_samples(st, rng)
@@ -106,8 +131,11 @@ def build_inputs(workload: str, seconds: float):
 
 
 def cpu_baseline(st, buf, cfgs, states, seconds: float = 10.0, f64: bool = False):
-    """The oracle as it stands, host threads over channels, on the first
-    `seconds` of the same stream (its FP64 form for the FP32-carrier runs)."""
+    """The oracle as it stands on the first `seconds` of the same stream (its
+    FP64 form for the FP32-carrier runs), on every host core: each channel's
+    block is cut into equal time pieces (a multiple of 4 samples), each piece
+    started from the channel's NCO words advanced to its first sample (the
+    NCOs have closed forms), and the channel-pieces run on a thread pool."""
     from concurrent.futures import ThreadPoolExecutor
 
     import oracle
@@ -116,36 +144,44 @@ def cpu_baseline(st, buf, cfgs, states, seconds: float = 10.0, f64: bool = False
     n = int(round(seconds * st.fs))
     n -= n % 4
     n = min(n, st.n)
-    sub = buf[: int(np.ceil(n * bytes_per))]
-    threads = min(len(cfgs), host_threads())
+    threads = host_threads()
+    pieces = threads
+    cuts = [(n * k // pieces) // 4 * 4 for k in range(pieces)] + [n]
 
-    def one(i):
+    def one(job):
+        i, k = job
+        a, b = cuts[k], cuts[k + 1]
         s = states[i]
-        os_ = oracle.OracleState(int(s["carr_phase"]), int(s["carr_step"]), int(s["code_phase"]),
-                                 int(s["code_step"]), int(cfgs[i]["n_taps"]),
-                                 carr_phase_f=float(s["carr_phase_f"]),
-                                 carr_freq_f=float(s["carr_freq_f"]))
         K = int(cfgs[i]["n_taps"])
+        T = int(cfgs[i]["int_periods"])
+        cp, kp = oracle.advance_words(int(s["carr_phase"]), int(s["carr_step"]),
+                                      int(s["code_phase"]), int(s["code_step"]), T, a)
+        ph = float(s["carr_phase_f"]) + a * float(s["carr_freq_f"])
+        os_ = oracle.OracleState(cp, int(s["carr_step"]), kp, int(s["code_step"]), K,
+                                 carr_phase_f=ph - np.floor(ph),
+                                 carr_freq_f=float(s["carr_freq_f"]))
         f = oracle.correlate_f64 if f64 else oracle.correlate_lut
-        return f(st.fmt, sub, n, int(cfgs[i]["prn"]), cfgs[i]["tap_q32"][:K],
-                 int(cfgs[i]["int_periods"]), os_)
+        sub = buf[int(a * bytes_per): int(np.ceil(b * bytes_per))]
+        return f(st.fmt, sub, b - a, int(cfgs[i]["prn"]), cfgs[i]["tap_q32"][:K], T, os_)
 
     t0 = time.perf_counter()
-    one(0)
+    for k in range(pieces):
+        one((0, k))
     dt1 = time.perf_counter() - t0
+    jobs = [(i, k) for i in range(len(cfgs)) for k in range(pieces)]
     t0 = time.perf_counter()
     with ThreadPoolExecutor(max_workers=threads) as ex:
-        list(ex.map(one, range(len(cfgs))))
+        list(ex.map(one, jobs))
     dt = time.perf_counter() - t0
     taps = int(cfgs["n_taps"].sum())
     return {"value": n * taps / dt / 1e9, "unit": "G sample·taps/s", "cores": threads,
             "kind": "oracle",
             "single_thread_value": n * int(cfgs[0]["n_taps"]) / dt1 / 1e9,
             "host": host_cpu(),
-            "sample": "first %.3f s (%d samples) of the same stream, all %d channels, "
-                      "%d threads over channels; %.2f s wall; real-time channels %.1f "
-                      "(single thread: channel 0 alone, %.2f s)"
-                      % (n / st.fs, n, len(cfgs), threads, dt,
+            "sample": "first %.3f s (%d samples) of the same stream, all %d channels, each cut "
+                      "into %d time pieces, %d threads over the channel-pieces; %.2f s wall; "
+                      "real-time channels %.1f (single thread: channel 0 alone, %.2f s)"
+                      % (n / st.fs, n, len(cfgs), pieces, threads, dt,
                          realtime_channels(len(cfgs), n / st.fs, dt), dt1)}
 
 
@@ -173,6 +209,24 @@ def kernel_source_tag(name: str = "gc_pbin.hip") -> str:
     src = os.path.join(ROOT, "paper_1907_00463_amd", "csrc", name)
     with open(src, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def recorded_counters():
+    """Fields of the committed counter summary of the periodic kernel, or {}
+    when the kernel source has changed since those counters were taken."""
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            text = f.read()
+    except OSError:
+        return {}
+    fields = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    if fields.get("kernel_source_sha256_16") != kernel_source_tag():
+        return {}
+    return fields
 
 
 def recorded_traffic():
@@ -288,7 +342,6 @@ def main_batched(args, wl, seconds, cpu_seconds):
     sample_taps = 3 * sample_ch
     data_s = sum(int((chan_rx == r).sum()) * n / st.fs for r, (n, (st, _, _)) in
                  enumerate(zip(ns, work)))
-    achieved = wl["ops"] * sample_ch / (graph_ms / 1e3) / 1e12
     res = {
         "metric": METRIC, "value": round(sample_taps / wall / 1e9, 3),
         "unit": "G sample·taps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -302,12 +355,9 @@ def main_batched(args, wl, seconds, cpu_seconds):
                    "periodic_items": info["periodic_items"],
                    "tuned_ms": round(info["tuned_ms"], 4),
                    "realtime_channels": round(data_s / wall, 1)},
-        "roofline": {"bound": "alu", "achieved": round(achieved, 3),
-                     "peak": round(VALU_PEAK_TOPS, 2), "unit": "T lane-ops/s",
-                     "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
-                     "kernel_ms": round(graph_ms, 4), "ops_per_sample_channel": wl["ops"],
-                     "note": "kernel_ms is the whole graph (set-up, rows, periodic and "
-                             "chip-by-chip batch kernels)"},
+        "roofline": alu_roofline(wl["ops"], sample_ch, graph_ms / 1e3,
+                                 note="kernel_ms is the whole graph (set-up, rows, periodic and "
+                                      "chip-by-chip batch kernels)"),
     }
     # the same batch with the periodic kernel off (every channel chip by chip)
     batch.configure(info["shape"], info["grid"], -1)
@@ -458,11 +508,115 @@ def serve_schedule(g, server, sched, payload, n_chan, deadline_s=1e-3):
             "makespan_s": round(t_done_last, 4)}
 
 
+class ServingSetup:
+    """The serving workload's receivers, sample streams, channel
+    configurations and initial states, and a Poisson schedule over them."""
+
+    def __init__(self, g, synth, seconds: float):
+        self.work = synth.workload_serving()
+        self.bufs = synth.synth_batched(self.work)
+        self.per = {0: 1.0, 1: 0.5, 2: 4.0}     # samples per byte
+        self.sched = synth.serving_schedule(self.work, seconds=seconds)
+        self.cfgs, self.states = [], []
+        for st, chans, _ in self.work:
+            self.cfgs.append(np.array([g.make_cfg(ch.prn, synth.taps_to_q32(ch.taps_chips),
+                                                  ch.int_periods) for ch in chans], g.CHAN_CFG))
+            self.states.append(np.array([g.gc_nco_init(st.fs, ch.carr_hz, ch.carr_phase0,
+                                                       ch.code_rate, ch.code_phase0,
+                                                       ch.int_periods) for ch in chans],
+                                        g.CHAN_STATE))
+        self.n_chan = [len(c) for c in self.cfgs]
+        step_max = max(int(x["code_step"].max()) for x in self.states)
+        self.max_dumps = g.max_dumps_for(int(self.sched[3].max()), step_max, 1)
+
+    def byte_range(self, r: int, off: int, n: int):
+        p = self.per[self.work[r][0].fmt]
+        return int(off / p), int((off + n) / p)
+
+    def payload_of(self, sc):
+        out = []
+        for r, o, n in zip(sc[1], sc[2], sc[3]):
+            a, _ = self.byte_range(int(r), int(o), int(n))
+            out.append((self.bufs[int(r)].ctypes.data + a, int(n)))
+        return out
+
+    def sample_channels(self, sc) -> int:
+        return int(sum(int(n) * self.n_chan[int(r)] for r, n in zip(sc[1], sc[3])))
+
+
+def serve_mode(g, ctx, S: ServingSetup, mode: str, warmup: int, stress=None):
+    """One server (continuous batching, or plain: every request alone with one
+    set-up and direct-kernel launch per channel) over the schedule, after
+    `warmup` requests one after another; with `stress`, a second schedule
+    follows on the same server."""
+    t_arr, rx, off, ns = S.sched
+    flags = g.GC_SERVER_PLAIN if mode == "plain" else 0
+    srv = g.gc_server_create(ctx, 256 << 20, 1 << 30, sum(S.n_chan), len(S.work), S.max_dumps,
+                             n_streams=2, max_batch_rx=len(S.work), flags=flags)
+    for (st, _, _), c, s0 in zip(S.work, S.cfgs, S.states):
+        g.gc_server_open_rx(srv, st.fmt, c, s0)
+    # warm-up: the first requests of the schedule, one after another (they
+    # advance those receivers' states; results are not used)
+    for k in range(min(warmup, len(t_arr))):
+        r = int(rx[k])
+        a, b = S.byte_range(r, int(off[k]), int(ns[k]))
+        q = g.gc_server_submit(srv, r, S.bufs[r][a:b], int(ns[k]))
+        while not len(g.gc_server_poll(srv)):
+            time.sleep(1e-4)
+        g.gc_server_result(srv, q, S.n_chan[r], S.max_dumps)
+    print("bench: serving (%s), %d requests over %.3g s" % (mode, len(t_arr), t_arr[-1]),
+          file=sys.stderr, flush=True)
+    stats = serve_schedule(g, srv, S.sched, S.payload_of(S.sched), S.n_chan)
+    stats["server_timing"] = {k: (round(v, 4) if isinstance(v, float) else v)
+                              for k, v in g.gc_server_stats(srv).items()}
+    info = g.gc_server_info(srv)
+    stats["launches"] = info["launches"]
+    stats["requests_per_launch"] = round(info["launched_requests"] / max(1, info["launches"]), 3)
+    stats["value"] = round(3 * S.sample_channels(S.sched) / stats["makespan_s"] / 1e9, 3)
+    if stress is not None:
+        print("bench: %s at 10x load, %d requests over 1 s" % (mode, len(stress[0])),
+              file=sys.stderr, flush=True)
+        st10 = serve_schedule(g, srv, stress, S.payload_of(stress), S.n_chan)
+        info2 = g.gc_server_info(srv)
+        st10["launches"] = info2["launches"] - info["launches"]
+        st10["requests_per_launch"] = round(
+            (info2["launched_requests"] - info["launched_requests"]) / max(1, st10["launches"]),
+            3)
+        st10["value"] = round(3 * S.sample_channels(stress) / st10["makespan_s"] / 1e9, 3)
+        stats["at_10x_load"] = st10
+    g.gc_server_destroy(srv)
+    print("bench: %s p50 %.3f ms p99 %.3f ms" % (mode, stats["p50_ms"], stats["p99_ms"]),
+          file=sys.stderr, flush=True)
+    return stats
+
+
+def served_slice(g, ctx, seconds: float = 2.0, warmup: int = 3) -> dict:
+    """A bounded slice of the serving schedule (the first `seconds` of the
+    2,000 requests/s Poisson arrivals over the 500 receivers) through the
+    continuous-batching server and the plain server: the metric's latency
+    leg, carried by the default benchmark line."""
+    from paper_1907_00463_amd import synth
+    print("bench: generating the serving workload (%g s slice)" % seconds, file=sys.stderr,
+          flush=True)
+    S = ServingSetup(g, synth, seconds)
+    b = serve_mode(g, ctx, S, "batched", warmup)
+    p = serve_mode(g, ctx, S, "plain", warmup)
+    return {"schedule": "first %g s of the serving schedule: %d requests, 500 receivers, "
+                        "Poisson 2,000 requests/s, U{1..20} ms each" % (seconds, len(S.sched[0])),
+            "p50_ms": b["p50_ms"], "p99_ms": b["p99_ms"], "max_ms": b["max_ms"],
+            "deadline_ms": b["deadline_ms"], "deadline_misses": int(round(
+                b["deadline_miss_frac"] * b["requests"])),
+            "requests_per_launch": b["requests_per_launch"],
+            "plain_p50_ms": p["p50_ms"], "plain_p99_ms": p["p99_ms"], "plain_max_ms": p["max_ms"],
+            "plain_deadline_misses": int(round(p["deadline_miss_frac"] * p["requests"])),
+            "channel_errors": b["channel_errors"] + p["channel_errors"]}
+
+
 def main_serving(args, wl, seconds):
     """Workload "serving": the open-loop Poisson schedule through the
     continuous-batching server, then through the same server in plain mode
     (every request alone, one set-up and one direct-kernel launch per
-    channel)."""
+    channel); each then takes 10x the load for 1 s."""
     import torch
 
     from paper_1907_00463_amd import gnsscorr as g
@@ -471,99 +625,35 @@ def main_serving(args, wl, seconds):
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     print("bench: generating the serving workload", file=sys.stderr, flush=True)
-    work = synth.workload_serving()
-    bufs = synth.synth_batched(work)
-    sched = synth.serving_schedule(work, seconds=seconds)
-    t_arr, rx, off, ns = sched
-    per = {0: 1, 2: 4}     # samples per byte
-
-    def payload_of(sc):
-        return [(bufs[int(r)].ctypes.data + int(o) // per[work[int(r)][0].fmt], int(n))
-                for r, o, n in zip(sc[1], sc[2], sc[3])]
-
-    payload = payload_of(sched)
+    S = ServingSetup(g, synth, seconds)
+    t_arr, rx, off, ns = S.sched
     # the same receivers under 10x the load for 1 s (continuous batching
     # against one launch per channel when requests queue up)
-    stress = synth.serving_schedule(work, rate_hz=10 * 2000.0, seconds=1.0, seed=1007)
-    stress_payload = payload_of(stress)
-    cfgs, states = [], []
-    for st, chans, _ in work:
-        cfgs.append(np.array([g.make_cfg(ch.prn, synth.taps_to_q32(ch.taps_chips),
-                                         ch.int_periods) for ch in chans], g.CHAN_CFG))
-        states.append(np.array([g.gc_nco_init(st.fs, ch.carr_hz, ch.carr_phase0, ch.code_rate,
-                                              ch.code_phase0, ch.int_periods) for ch in chans],
-                               g.CHAN_STATE))
-    n_chan = [len(c) for c in cfgs]
-    step_max = max(int(s["code_step"].max()) for s in states)
-    max_dumps = g.max_dumps_for(int(ns.max()), step_max, 1)
-    sample_ch = int(sum(int(n) * n_chan[int(r)] for r, n in zip(rx, ns)))
+    stress = synth.serving_schedule(S.work, rate_hz=10 * 2000.0, seconds=1.0, seed=1007)
+    sample_ch = S.sample_channels(S.sched)
     ctx = g.gc_create(0)
-    res = None
-    for mode in ("batched", "plain"):
-        if mode == "plain" and args.no_plain:
-            continue
-        flags = g.GC_SERVER_PLAIN if mode == "plain" else 0
-        srv = g.gc_server_create(ctx, 256 << 20, 1 << 30, sum(n_chan), len(work), max_dumps,
-                                 n_streams=2, max_batch_rx=len(work), flags=flags)
-        for (st, _, _), c, s0 in zip(work, cfgs, states):
-            g.gc_server_open_rx(srv, st.fmt, c, s0)
-        # warm-up: the first requests of the schedule, one after another
-        # (they advance those receivers' states; results are not used)
-        for k in range(min(args.warmup, len(t_arr))):
-            r, p = int(rx[k]), per[work[int(rx[k])][0].fmt]
-            q = g.gc_server_submit(srv, r, bufs[r][int(off[k]) // p: (int(off[k]) + int(ns[k]))
-                                                  // p], int(ns[k]))
-            while not len(g.gc_server_poll(srv)):
-                time.sleep(1e-4)
-            g.gc_server_result(srv, q, n_chan[int(rx[k])], max_dumps)
-        print("bench: serving (%s), %d requests over %g s" % (mode, len(t_arr), seconds),
-              file=sys.stderr, flush=True)
-        stats = serve_schedule(g, srv, sched, payload, n_chan)
-        stats["server_timing"] = {k: (round(v, 4) if isinstance(v, float) else v)
-                                  for k, v in g.gc_server_stats(srv).items()}
-        info = g.gc_server_info(srv)
-        stats["launches"] = info["launches"]
-        stats["requests_per_launch"] = round(info["launched_requests"] / max(1, info["launches"]),
-                                             3)
-        print("bench: %s at 10x load, %d requests over 1 s" % (mode, len(stress[0])),
-              file=sys.stderr, flush=True)
-        st10 = serve_schedule(g, srv, stress, stress_payload, n_chan)
-        info2 = g.gc_server_info(srv)
-        st10["launches"] = info2["launches"] - info["launches"]
-        st10["requests_per_launch"] = round(
-            (info2["launched_requests"] - info["launched_requests"]) / max(1, st10["launches"]), 3)
-        sc10 = int(sum(int(n) * n_chan[int(r)] for r, n in zip(stress[1], stress[3])))
-        st10["value"] = round(3 * sc10 / st10["makespan_s"] / 1e9, 3)
-        stats["at_10x_load"] = st10
-        g.gc_server_destroy(srv)
-        print("bench: %s p50 %.3f ms p99 %.3f ms" % (mode, stats["p50_ms"], stats["p99_ms"]),
-              file=sys.stderr, flush=True)
-        tput = 3 * sample_ch / stats["makespan_s"] / 1e9
-        if mode == "batched":
-            achieved = wl["ops"] * sample_ch / stats["makespan_s"] / 1e12
-            res = {
-                "metric": METRIC, "value": round(tput, 3), "unit": "G sample·taps/s",
-                "n_gpus": 1, "steps": len(t_arr), "warmup": 0,
-                "ms_per_step": round(stats["makespan_s"] * 1e3 / len(t_arr), 4),
-                "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-                "dtype": "int32", "data": "synthetic",
-                "config": {"workload": wl["describe"] % seconds, "receivers": len(work),
-                           "channels": sum(n_chan), "requests": len(t_arr),
-                           "sample_channels": sample_ch, "max_dumps": max_dumps,
-                           "streams": 2, "kernels": "server"},
-                "serving": stats,
-                "roofline": {"bound": "alu", "achieved": round(achieved, 4),
-                             "peak": round(VALU_PEAK_TOPS, 2), "unit": "T lane-ops/s",
-                             "frac": round(achieved / VALU_PEAK_TOPS, 5), "traffic": None,
-                             "note": "offered-load bound: the value is the offered rate once "
-                                     "the server keeps up; the kernel's own fraction is that of "
-                                     "the batched workload"},
-            }
-        else:
-            stats["value"] = round(tput, 3)
-            stats["kind"] = "same server, every request alone, one set-up and one direct-kernel " \
-                            "launch per channel"
-            res["plain"] = stats
+    stats = serve_mode(g, ctx, S, "batched", args.warmup, stress)
+    res = {
+        "metric": METRIC, "value": stats["value"], "unit": "G sample·taps/s",
+        "n_gpus": 1, "steps": len(t_arr), "warmup": 0,
+        "ms_per_step": round(stats["makespan_s"] * 1e3 / len(t_arr), 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": wl["describe"] % seconds, "receivers": len(S.work),
+                   "channels": sum(S.n_chan), "requests": len(t_arr),
+                   "sample_channels": sample_ch, "max_dumps": S.max_dumps,
+                   "streams": 2, "kernels": "server"},
+        "serving": stats,
+        "roofline": alu_roofline(
+            wl["ops"], sample_ch, stats["makespan_s"],
+            note="offered-load bound: the value is the offered rate once the server keeps up; "
+                 "the kernel's own fraction is that of the batched workload"),
+    }
+    if not args.no_plain:
+        p = serve_mode(g, ctx, S, "plain", args.warmup, stress)
+        p["kind"] = "same server, every request alone, one set-up and one direct-kernel " \
+                    "launch per channel"
+        res["plain"] = p
     if not args.no_cpu_baseline:
         # the oracle over the first 2000 requests of the schedule, each from
         # its receiver's initial states, threads over requests
@@ -574,23 +664,24 @@ def main_serving(args, wl, seconds):
         threads = host_threads()
 
         def one(k):
-            r, p = int(rx[k]), per[work[int(rx[k])][0].fmt]
-            blk = bufs[r][int(off[k]) // p: (int(off[k]) + int(ns[k])) // p]
-            for i in range(n_chan[r]):
-                s_ = states[r][i]
-                c = cfgs[r][i]
+            r = int(rx[k])
+            a, b = S.byte_range(r, int(off[k]), int(ns[k]))
+            blk = S.bufs[r][a:b]
+            for i in range(S.n_chan[r]):
+                s_ = S.states[r][i]
+                c = S.cfgs[r][i]
                 os_ = oracle.OracleState(int(s_["carr_phase"]), int(s_["carr_step"]),
                                          int(s_["code_phase"]), int(s_["code_step"]), 3)
-                oracle.correlate_lut(work[r][0].fmt, blk, int(ns[k]), int(c["prn"]),
+                oracle.correlate_lut(S.work[r][0].fmt, blk, int(ns[k]), int(c["prn"]),
                                      c["tap_q32"][:3], int(c["int_periods"]), os_)
 
         t0 = time.perf_counter()
         with ThreadPoolExecutor(max_workers=threads) as ex:
             list(ex.map(one, range(k_req)))
         dt = time.perf_counter() - t0
-        st_k = 3 * sum(int(ns[k]) * n_chan[int(rx[k])] for k in range(k_req))
+        st_k = 3 * sum(int(ns[k]) * S.n_chan[int(rx[k])] for k in range(k_req))
         res["cpu_baseline"] = {"value": st_k / dt / 1e9, "unit": "G sample·taps/s",
-                               "cores": threads, "kind": "oracle",
+                               "cores": threads, "kind": "oracle", "host": host_cpu(),
                                "sample": "the first %d requests of the schedule, all their "
                                          "channels, threads over requests; %.2f s wall"
                                          % (k_req, dt)}
@@ -675,7 +766,6 @@ def main_tracking(args, wl, seconds, cpu_seconds):
         cn0_err.append(float(np.median(c[np.isfinite(c)])) - sat.cn0_dbhz if len(c) else
                        float("nan"))
     sample_taps = n * 3 * len(chans)
-    achieved = wl["ops"] * n * len(chans) / dt / 1e12
     res = {
         "metric": METRIC, "value": round(sample_taps / dt / 1e9, 3), "unit": "G sample·taps/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -689,13 +779,11 @@ def main_tracking(args, wl, seconds, cpu_seconds):
                    "lock_metrics_ms": round(dt_lock * 1e3, 4),
                    "nav_bit_agreement_min": round(min(agree), 4),
                    "cn0_error_db": [round(e, 2) for e in cn0_err]},
-        "roofline": {"bound": "alu", "achieved": round(achieved, 4),
-                     "peak": round(VALU_PEAK_TOPS, 2), "unit": "T lane-ops/s",
-                     "frac": round(achieved / VALU_PEAK_TOPS, 5), "traffic": None,
-                     "kernel_ms": round(dt * 1e3, 4),
-                     "note": "one block per channel walks the dumps in order (each dump's NCO "
-                             "steps come from the previous dump's loop update): 12 of 256 "
-                             "compute units, latency bound"},
+        "roofline": alu_roofline(
+            wl["ops"], n * len(chans), dt,
+            note="one block per channel walks the dumps in order (each dump's NCO steps come "
+                 "from the previous dump's loop update): 12 of 256 compute units, latency "
+                 "bound"),
     }
     if not args.no_cpu_baseline:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
@@ -842,6 +930,8 @@ def main():
                     help="integer NCO + table (exact) or the FP32 sin/cos variant")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-channel launch baseline")
+    ap.add_argument("--no-served", action="store_true",
+                    help="skip the serving slice of the default workload")
     ap.add_argument("--cpu-seconds", type=float, default=None)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before timing, copy a buffer of this many MiB once (a kernel of known "
@@ -922,7 +1012,6 @@ def main():
     sample_taps = n * taps
     value = sample_taps / (wall / args.steps) / 1e9
     k_s = float(np.mean(kern_ms)) / 1e3
-    achieved = wl["ops"] * n * len(cfgs) / k_s / 1e12
     taps_per = sorted(set(int(t) for t in cfgs["n_taps"]))
     res = {
         "metric": METRIC,
@@ -944,14 +1033,17 @@ def main():
                    "dumps_per_channel": int(nd.max()),
                    "realtime_channels": round(realtime_channels(len(cfgs), n / st.fs,
                                                                 wall / args.steps), 1)},
-        "roofline": {"bound": "alu", "achieved": round(achieved, 3),
-                     "peak": round(VALU_PEAK_TOPS, 2), "unit": "T lane-ops/s",
-                     "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                     "traffic": recorded_traffic()
-                     if (args.kernels == "auto" and args.workload == "twelve") else None,
-                     "kernel_ms": round(k_s * 1e3, 4),
-                     "ops_per_sample_channel": wl["ops"]},
+        "roofline": alu_roofline(wl["ops"], n * len(cfgs), k_s),
     }
+    if args.kernels == "auto" and args.workload == "twelve":
+        res["roofline"]["traffic"] = recorded_traffic()
+        ctr = recorded_counters()
+        if "sq_insts_valu_per_launch" in ctr:
+            # wave-instructions x 4 clocks over 1024 SIMDs at 2.4 GHz
+            busy = int(ctr["sq_insts_valu_per_launch"]) * 4 / (1024 * 2.4e9)
+            res["roofline"]["valu_issue_frac"] = round(busy / k_s, 4)
+        else:
+            res["roofline"]["valu_issue_frac"] = None
     if f32:
         # the direct form with an FP32 carrier: per sample one sin/cos pair,
         # per sample and tap two FP32 multiply-adds (I and Q) = 4 FLOPs
@@ -986,6 +1078,8 @@ def main():
                         "ms_per_step": round(dt * 1e3, 4),
                         "kind": "one plan and one direct-kernel launch per channel",
                         "speedup": round(dt / (wall / args.steps), 2)}
+    if args.workload == "twelve" and not f32 and not args.no_served:
+        res["served"] = served_slice(g, ctx)
     if not args.no_cpu_baseline:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(st, buf, cfgs, states, cpu_seconds, f64=f32)

@@ -165,14 +165,14 @@ gc_status gc_plan_destroy(gc_plan* plan);
 /* Kernel families a plan may use for its E/P/L channels (bit mask).  Every
  * family computes the same integer sums (the definition of Eqs. (1)-(3)
  * with the table carrier); the choice only changes speed.
- *   GC_KERNEL_PERIODIC  half chips of exactly 8 or 10 samples with a bounded
- *                       grid slip (fs an integer multiple of twice the code
- *                       rate)
+ *   GC_KERNEL_PERIODIC  half chips of exactly 2, 4, 8 or 10 samples with a
+ *                       bounded grid slip (fs an integer multiple of twice the
+ *                       code rate)
  *   GC_KERNEL_BINNED    any rate of >= 2^32/127 code step, chip by chip
- *   GC_KERNEL_MTAP      plans with more than 4 taps or complex input: channels
- *                       whose taps are all multiples of 2^27 (1/32 chip)
- *                       spanning at most 8 chip shifts, at <= 32 samples per
- *                       chip (two-stage int8 MFMA form, table carrier)
+ *   GC_KERNEL_MTAP      plans with more than 4 taps: channels whose taps are
+ *                       all multiples of 2^27 (1/32 chip) spanning at most 8
+ *                       chip shifts, at <= 32 samples per chip (two-stage
+ *                       int8 MFMA form, table carrier)
  * Channels that no allowed family takes, and every channel of a plan with
  * the float carrier, use the direct per-sample kernel.  Default: all bits
  * set.  Takes effect at the next gc_correlate.
@@ -462,7 +462,7 @@ typedef struct gc_batch gc_batch;
 typedef struct {
     const void* samples;  /* device, the receiver's block in its format */
     uint64_t n_samples;   /* 0 .. 2^31-1 */
-    int32_t fmt;          /* GC_I8_REAL or GC_I2_REAL */
+    int32_t fmt;          /* GC_I8_REAL, GC_I8_IQ or GC_I2_REAL */
     int32_t reserved;     /* must be 0 */
 } gc_rx_desc;
 
@@ -563,7 +563,7 @@ gc_status gc_server_create(gc_ctx* ctx, uint64_t hbm_budget_bytes, uint64_t host
                            int32_t n_streams, int32_t max_batch_rx, int32_t flags,
                            gc_server** out);
 
-/* Register a receiver: sample format (GC_I8_REAL or GC_I2_REAL), n_chan
+/* Register a receiver: sample format (GC_I8_REAL, GC_I8_IQ or GC_I2_REAL), n_chan
  * channel configurations with at most 4 taps each, and their initial NCO
  * states (host arrays, copied).  Its id, counted from 0, goes to *rx_id.
  * Synchronous.  Errors: GC_EINVAL (null, fmt, a configuration), GC_ENOMEM

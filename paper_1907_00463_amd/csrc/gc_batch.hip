@@ -161,7 +161,7 @@ gc_status gc_batch_create(gc_ctx* ctx, const gc_rx_desc* rx, int32_t n_rx,
         return GC_EINVAL;
     for (int r = 0; r < n_rx; ++r) {
         const gc_rx_desc& d = rx[r];
-        if ((d.fmt != GC_I8_REAL && d.fmt != GC_I2_REAL) || d.reserved != 0 ||
+        if ((d.fmt != GC_I8_REAL && d.fmt != GC_I8_IQ && d.fmt != GC_I2_REAL) || d.reserved != 0 ||
             d.n_samples >= (1ull << 31) || (d.n_samples > 0 && !d.samples))
             return GC_EINVAL;
     }

@@ -164,9 +164,8 @@ __global__ __launch_bounds__(64) void k_setup(const DevChan* __restrict__ chans,
             m.tail_beg = (uint32_t)tb;
             m.path = kPathDirect;
             m.bin_len = 0;
-            const bool epl_ok = c.epl && carrier == GC_CARRIER_LUT && m.c_full1 > m.c_full0 &&
-                                (fmt == GC_I8_REAL || fmt == GC_I2_REAL);
-            if (epl_ok && (allow & kAllowPeriodic)) {
+            const bool epl_ok = c.epl && carrier == GC_CARRIER_LUT && m.c_full1 > m.c_full0;
+            if (epl_ok && (allow & kAllowPeriodic) && fmt != GC_I8_IQ) {
                 m.bin_len = periodic_bin_len(fmt, m.dp);
                 if (m.bin_len) m.path = kPathPeriodic;
             }

@@ -78,6 +78,13 @@ __device__ __forceinline__ void wipe(T xi, T xq, T c, T s, T& wi, T& wq) {
     }
 }
 
+// Largest |term| of one sample in a packed int16 bin sum: x*c or x*s (real
+// input), and for complex input each of the two planes (xI, xQ)*c and
+// (xQ, xI)*s that the kernels sum separately.
+__device__ __forceinline__ uint64_t bin_plane_max(int fmt) {
+    return fmt == GC_I2_REAL ? 3ull * GC_LUT_AMP : 128ull * GC_LUT_AMP;
+}
+
 // Binned E/P/L form: tile geometry and the per-channel condition on the code
 // step.  A chip must fit in the staged margin, and a half-chip bin sum must
 // fit int16 (bin length <= q + 1 samples, q = floor(2^31 / dp)).
@@ -86,8 +93,7 @@ __device__ __forceinline__ bool binned_ok(int fmt, uint64_t dp) {
     if (dp == 0 || dp >= (1ull << 31)) return false;
     if (dp * (kEplMarginSamples - 1) < (1ull << 32)) return false;
     const uint64_t q = (1ull << 31) / dp;
-    const uint64_t maxw = fmt == GC_I8_REAL ? 128ull * GC_LUT_AMP : 3ull * GC_LUT_AMP;
-    return (q + 1) * maxw <= 32767ull;
+    return (q + 1) * bin_plane_max(fmt) <= 32767ull;
 }
 
 // Periodic form: half chips of exactly L samples (L = 2, 4, 8 or 10), with
@@ -97,8 +103,7 @@ __device__ __forceinline__ int periodic_bin_len(int fmt, uint64_t dp) {
     if (dp == 0 || dp >= (1ull << 31)) return 0;
     const uint64_t L = ((1ull << 31) + dp / 2) / dp;  // nearest integer to 2^31 / dp
     if (L != 2 && L != 4 && L != 8 && L != 10) return 0;
-    const uint64_t maxw = fmt == GC_I8_REAL ? 128ull * GC_LUT_AMP : 3ull * GC_LUT_AMP;
-    if (L * maxw > 32767ull) return 0;
+    if (L * bin_plane_max(fmt) > 32767ull) return 0;
     const int64_t D = (int64_t)(L * dp) - (int64_t)(1ull << 31);
     const uint64_t drift = (uint64_t)(D < 0 ? -D : D) * (kPbinTileSamples / L + 2);
     return drift < dp ? (int)L : 0;

@@ -1,5 +1,5 @@
-// gc_epl.hip -- binned early/prompt/late correlator for real int8 and 2-bit
-// sample streams (integer carrier path).
+// gc_epl.hip -- binned early/prompt/late correlator for real int8, 2-bit and
+// complex int8 (I then Q) sample streams (integer carrier path).
 //
 // The replicas of E, P and L (offsets +1/2, 0, -1/2 chip) are constant over
 // each half chip of code phase, so the kernel first sums the wiped-off
@@ -14,7 +14,10 @@
 //   * a tile of kTile samples is staged once in LDS as int16 (2-bit codes
 //     expanded) and read by every channel of the plan; a packed multiply
 //     picks either sample of a dword through its operand select, so samples
-//     need no unpacking;
+//     need no unpacking.  Complex samples are staged as (xI, xQ) int16 pairs,
+//     one dword each, in two half tiles; per sample two packed multiply-adds
+//     form the planes (xI, xQ)*c and (xQ, xI)*s, and the bin's wiped-off
+//     sum is (xI c + xQ s, xQ c - xI s) from their halves;
 //   * per channel, the chips whose first sample lies in the tile are split
 //     into 512 runs of consecutive whole chips, one per lane (~90 samples,
 //     an odd number of LDS dwords apart, so lanes hit different banks);
@@ -46,8 +49,14 @@ struct Shape {
     static constexpr int kRun = RUN;
     static constexpr int kTile = THREADS * RUN;                 // samples per tile
     static constexpr int kXSamples = kTile + kMargin;           // staged as int16
-    static constexpr int kLdsBytes = kLutWords * 4 + kXSamples * 2;  // table at LDS offset 0
+    // complex input: half tiles of kTile / 2 samples (+ margin), one dword each
+    static constexpr int kHalf = kTile / 2;
+    static constexpr int kXSamplesIQ = kHalf + kMargin;
+    static constexpr int kXBytes = kXSamples * 2 > kXSamplesIQ * 4 ? kXSamples * 2
+                                                                   : kXSamplesIQ * 4;
+    static constexpr int kLdsBytes = kLutWords * 4 + kXBytes;   // table at LDS offset 0
     static_assert((RUN / 2) % 2 == 1, "odd dword stride between lanes");
+    static_assert(kTile % 8 == 0, "half tiles start on a multiple of 4 samples");
     static_assert(kLdsBytes <= 160 * 1024, "LDS per block");
 };
 using ShapePlan = Shape<512, 90>;             // single-receiver plans: 46080-sample tiles
@@ -87,6 +96,38 @@ __device__ __forceinline__ short2_t bin_sum(const short* __restrict__ xs, uint32
         for (uint32_t j = 0; j < len; ++j) a = mac_sample(a, xs[j], phi + j * dphi, lane4, lut);
     }
     return a;
+}
+
+// Complex sample (xI, xQ) at phase phi: a += (xI, xQ)*c, b += (xQ, xI)*s
+// (operand selects swap and broadcast the halves).
+__device__ __forceinline__ void mac_iq(short2_t& a, short2_t& b, uint32_t xw, uint32_t phi,
+                                       uint32_t lane4, const uint8_t* lut_bytes) {
+    const uint32_t off = __builtin_amdgcn_perm(phi, lane4, kPermSel);
+    const short2_t cs = as_s2(*reinterpret_cast<const uint32_t*>(lut_bytes + off));
+    const short2_t x = as_s2(xw);
+    const short2_t xs = __builtin_shufflevector(x, x, 1, 0);
+    a = x * __builtin_shufflevector(cs, cs, 0, 0) + a;
+    b = xs * __builtin_shufflevector(cs, cs, 1, 1) + b;
+}
+
+// Complex bin of len samples (as bin_sum): the planes a = sum (xI, xQ)*c and
+// b = sum (xQ, xI)*s, each within int16 (len * 128 * 24 <= 32767).
+template <int Q>
+__device__ __forceinline__ void bin_sum_iq(const uint32_t* __restrict__ xs, uint32_t phi,
+                                           uint32_t dphi, uint32_t lane4, const uint8_t* lut,
+                                           uint32_t len, short2_t& a, short2_t& b) {
+    a = short2_t{0, 0};
+    b = short2_t{0, 0};
+    if constexpr (Q > 0) {
+#pragma unroll
+        for (int j = 0; j < Q - 1; ++j) mac_iq(a, b, xs[j], phi + j * dphi, lane4, lut);
+        const uint32_t x1 = len >= (uint32_t)Q ? xs[Q - 1] : 0u;
+        mac_iq(a, b, x1, phi + (Q - 1) * dphi, lane4, lut);
+        const uint32_t x2 = len > (uint32_t)Q ? xs[Q] : 0u;
+        mac_iq(a, b, x2, phi + Q * dphi, lane4, lut);
+    } else {
+        for (uint32_t j = 0; j < len; ++j) mac_iq(a, b, xs[j], phi + j * dphi, lane4, lut);
+    }
 }
 
 struct Dest {
@@ -148,6 +189,29 @@ struct EplAcc<GC_I8_REAL> {
     }
 };
 
+// Complex input: the bin's wiped-off sums wi = aI + bI and nq = -(aQ - bQ)
+// (Q kept negated like the real forms' +x*s) in int32.
+template <>
+struct EplAcc<GC_I8_IQ> {
+    int ei, eq, pi, pq, li, lq;
+    __device__ __forceinline__ void zero() { ei = eq = pi = pq = li = lq = 0; }
+    __device__ __forceinline__ void fold0(int wi, int nq, uint32_t mp, uint32_t mc) {
+        const int sc = (int)(short)(mc & 0xFFFF), sp = (int)(short)(mp & 0xFFFF);
+        ei += wi * sc; eq += nq * sc;
+        pi += wi * sc; pq += nq * sc;
+        li += wi * sp; lq += nq * sp;
+    }
+    __device__ __forceinline__ void fold1(int wi, int nq, uint32_t mc, uint32_t mn) {
+        const int sc = (int)(short)(mc & 0xFFFF), sn = (int)(short)(mn & 0xFFFF);
+        ei += wi * sn; eq += nq * sn;
+        pi += wi * sc; pq += nq * sc;
+        li += wi * sc; lq += nq * sc;
+    }
+    __device__ __forceinline__ void get(int v[6]) const {
+        v[0] = ei; v[1] = eq; v[2] = pi; v[3] = pq; v[4] = li; v[5] = lq;
+    }
+};
+
 // Lane-private atomics of one run's sums (dump boundary inside a run).
 template <int FMT>
 __device__ __forceinline__ void flush_lane(const EplAcc<FMT>& acc, const Dest& d, uint32_t w,
@@ -165,7 +229,7 @@ __device__ __forceinline__ void flush_lane(const EplAcc<FMT>& acc, const Dest& d
 // Binned run of one lane over chips [c, c + K) whose samples start at tile
 // offset nb with code-phase overshoot e past the chip start.
 template <int FMT, int Q>
-__device__ __forceinline__ void epl_run(const short* __restrict__ sx, const uint8_t* lut,
+__device__ __forceinline__ void epl_run(const void* __restrict__ sx, const uint8_t* lut,
                                      uint32_t lane4, uint32_t nb, uint32_t phi, uint32_t dphi,
                                      uint32_t e, uint32_t dp, uint32_t q, uint32_t r, uint32_t c,
                                      uint32_t K, uint32_t Kmax, uint32_t span,
@@ -192,18 +256,34 @@ __device__ __forceinline__ void epl_run(const short* __restrict__ sx, const uint
             bool lt = e < r;
             uint32_t len = q + (lt ? 1u : 0u);
             e = lt ? e + dp - r : e - r;
-            short2_t a = bin_sum<Q>(sx + nb, phi, dphi, lane4, lut, len);
+            if constexpr (FMT == GC_I8_IQ) {
+                short2_t a, b;
+                bin_sum_iq<Q>(static_cast<const uint32_t*>(sx) + nb, phi, dphi, lane4, lut, len,
+                              a, b);
+                acc.fold0((int)a.x + (int)b.x, (int)b.y - (int)a.y, mp, mc);
+            } else {
+                const short2_t a =
+                    bin_sum<Q>(static_cast<const short*>(sx) + nb, phi, dphi, lane4, lut, len);
+                acc.fold0(a, mp, mc, mn);
+            }
             nb += len;
             phi += len * dphi;
-            acc.fold0(a, mp, mc, mn);
             // bin 1: phase [c + 1/2, c + 1)
             lt = e < r;
             len = q + (lt ? 1u : 0u);
             e = lt ? e + dp - r : e - r;
-            a = bin_sum<Q>(sx + nb, phi, dphi, lane4, lut, len);
+            if constexpr (FMT == GC_I8_IQ) {
+                short2_t a, b;
+                bin_sum_iq<Q>(static_cast<const uint32_t*>(sx) + nb, phi, dphi, lane4, lut, len,
+                              a, b);
+                acc.fold1((int)a.x + (int)b.x, (int)b.y - (int)a.y, mc, mn);
+            } else {
+                const short2_t a =
+                    bin_sum<Q>(static_cast<const short*>(sx) + nb, phi, dphi, lane4, lut, len);
+                acc.fold1(a, mp, mc, mn);
+            }
             nb += len;
             phi += len * dphi;
-            acc.fold1(a, mp, mc, mn);
             mp = mc;
             mc = mn;
             mn = mnn;
@@ -232,8 +312,8 @@ __device__ __forceinline__ void epl_run(const short* __restrict__ sx, const uint
 
 // Direct per-sample form over tile offsets [lo, hi) for up to 4 taps (chips
 // cut by the block ends, and channels the binned form does not cover).
-template <int kThreads>
-__device__ __forceinline__ void direct_range(const short* __restrict__ sx, const uint8_t* lut,
+template <int FMT, int kThreads>
+__device__ __forceinline__ void direct_range(const void* __restrict__ sx, const uint8_t* lut,
                                              uint32_t lane4, uint64_t t0, uint32_t lo, uint32_t hi,
                                              const DevMeta& m, const DevChan& ch,
                                              const uint32_t* __restrict__ sgn_prn, const Dest d) {
@@ -255,8 +335,15 @@ __device__ __forceinline__ void direct_range(const short* __restrict__ sx, const
             const uint32_t e = *reinterpret_cast<const uint32_t*>(lut + off);
             int c, s;
             lut_cs(e, c, s);
-            const int x = sx[i];
-            const int wi = x * c, wq = -(x * s);
+            int wi, wq;
+            if constexpr (FMT == GC_I8_IQ) {
+                const uint32_t xw = static_cast<const uint32_t*>(sx)[i];
+                const int xi = (int)(short)(xw & 0xFFFF), xq = (int)(short)(xw >> 16);
+                wipe<GC_I8_IQ, int>(xi, xq, c, s, wi, wq);
+            } else {
+                const int x = static_cast<const short*>(sx)[i];
+                wipe<GC_I8_REAL, int>(x, 0, c, s, wi, wq);
+            }
             const uint64_t u = m.p0 + n * m.dp;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -279,9 +366,27 @@ __device__ __forceinline__ void direct_range(const short* __restrict__ sx, const
 
 template <int FMT, int kThreads, int kXSamples>
 __device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, uint64_t n,
-                                           uint64_t t0, short* sx, const uint32_t* tables) {
-    uint2* dst = reinterpret_cast<uint2*>(sx);  // 4 samples per 8 bytes
-    if constexpr (FMT == GC_I2_REAL) {
+                                           uint64_t t0, void* sx, const uint32_t* tables) {
+    uint2* dst = reinterpret_cast<uint2*>(sx);  // 4 samples per 8 bytes (2 for complex)
+    if constexpr (FMT == GC_I8_IQ) {
+        // kXSamples complex samples from t0 (a multiple of 4): the 4 bytes of
+        // two samples give two (xI, xQ) int16 dwords
+        for (int i = threadIdx.x; i < kXSamples / 2; i += kThreads) {
+            const uint64_t smp = t0 + 2ull * i;
+            uint32_t v = 0;
+            if (smp + 2 <= n) {
+                v = *reinterpret_cast<const uint32_t*>(samples + 2 * smp);
+            } else if (smp < n) {
+                v = *reinterpret_cast<const uint16_t*>(samples + 2 * smp);
+            }
+            uint2 o;
+            o.x = ((uint32_t)(uint16_t)(int16_t)(int8_t)(v & 0xFF)) |
+                  ((uint32_t)(uint16_t)(int16_t)(int8_t)((v >> 8) & 0xFF) << 16);
+            o.y = ((uint32_t)(uint16_t)(int16_t)(int8_t)((v >> 16) & 0xFF)) |
+                  ((uint32_t)(uint16_t)(int16_t)(int8_t)(v >> 24) << 16);
+            dst[i] = o;
+        }
+    } else if constexpr (FMT == GC_I2_REAL) {
         // t0 is a multiple of 4: byte t0/4 + i holds tile samples 4i .. 4i+3
         const uint64_t nbytes = (n + 3) / 4;
         const uint64_t b0 = t0 / 4;
@@ -317,7 +422,7 @@ __device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, 
 
 // Channels [c_begin, c_end) of one receiver on its staged tile [t0, t1).
 template <int FMT, class SH>
-__device__ __forceinline__ void epl_tile(const short* __restrict__ s_x, const uint8_t* lut,
+__device__ __forceinline__ void epl_tile(const void* __restrict__ s_x, const uint8_t* lut,
                                          uint64_t t0, uint64_t t1, int c_begin, int c_end,
                                          const DevChan* __restrict__ chans,
                                          const DevMeta* __restrict__ metas,
@@ -335,17 +440,17 @@ __device__ __forceinline__ void epl_tile(const short* __restrict__ s_x, const ui
         const uint32_t* sgn_prn = tables + kTabSign + (ch.prn - 1) * kSignLen;
         const uint32_t tl = (uint32_t)(t1 - t0);
         if (m.path != kPathBinned) {
-            direct_range<kThreads>(s_x, lut, lane4, t0, 0, tl, m, ch, sgn_prn, d);
+            direct_range<FMT, kThreads>(s_x, lut, lane4, t0, 0, tl, m, ch, sgn_prn, d);
             continue;
         }
         // block-edge samples outside whole chips
         {
             const uint64_t he = m.head_end, tb = m.tail_beg;
             if (he > t0)
-                direct_range<kThreads>(s_x, lut, lane4, t0, 0, (uint32_t)min(he, t1) - (uint32_t)t0,
+                direct_range<FMT, kThreads>(s_x, lut, lane4, t0, 0, (uint32_t)min(he, t1) - (uint32_t)t0,
                                        m, ch, sgn_prn, d);
             if (t1 > tb)
-                direct_range<kThreads>(s_x, lut, lane4, t0, (uint32_t)(max(tb, t0) - t0), tl, m,
+                direct_range<FMT, kThreads>(s_x, lut, lane4, t0, (uint32_t)(max(tb, t0) - t0), tl, m,
                                        ch, sgn_prn, d);
         }
         // whole chips whose first sample lies in [t0, t1)
@@ -399,6 +504,34 @@ __device__ __forceinline__ void epl_tile(const short* __restrict__ s_x, const ui
     }
 }
 
+// One tile [t0, t0 + kTile) of a block of n samples for channels [c_begin,
+// c_end): staged and correlated whole (real input) or as two half tiles
+// (complex input, one dword per sample).
+template <int FMT, class SH>
+__device__ __forceinline__ void tile_pass(const uint8_t* __restrict__ samples, uint64_t n,
+                                          uint64_t t0, void* s_x, const uint8_t* lut,
+                                          int c_begin, int c_end,
+                                          const DevChan* __restrict__ chans,
+                                          const DevMeta* __restrict__ metas,
+                                          gc_chan_state* __restrict__ state,
+                                          int32_t* __restrict__ out, int tap_stride,
+                                          uint32_t max_dumps, const uint32_t* __restrict__ tables) {
+    constexpr int kParts = FMT == GC_I8_IQ ? 2 : 1;
+    constexpr int kPart = SH::kTile / kParts;
+    constexpr int kStaged = FMT == GC_I8_IQ ? SH::kXSamplesIQ : SH::kXSamples;
+#pragma unroll
+    for (int h = 0; h < kParts; ++h) {
+        const uint64_t a = t0 + (uint64_t)h * kPart;
+        if (a >= n) break;
+        const uint64_t b = min(n, a + kPart);
+        __syncthreads();
+        stage_tile<FMT, SH::kThreads, kStaged>(samples, n, a, s_x, tables);
+        __syncthreads();
+        epl_tile<FMT, SH>(s_x, lut, a, b, c_begin, c_end, chans, metas, state, out, tap_stride,
+                          max_dumps, tables);
+    }
+}
+
 template <int FMT>
 __global__ __launch_bounds__(ShapePlan::kThreads) void k_epl(
     const uint8_t* __restrict__ samples, uint64_t n, const DevChan* __restrict__ chans,
@@ -410,7 +543,7 @@ __global__ __launch_bounds__(ShapePlan::kThreads) void k_epl(
     // result is the address itself), then the staged samples
     __shared__ __attribute__((aligned(16))) uint8_t s_lds[SH::kLdsBytes];
     uint32_t* s_lut = reinterpret_cast<uint32_t*>(s_lds);
-    short* s_x = reinterpret_cast<short*>(s_lds + kLutWords * 4);
+    void* s_x = s_lds + kLutWords * 4;
     const int tid = threadIdx.x;
     // channels left to this kernel: not refused and not on the periodic path
     {
@@ -423,12 +556,8 @@ __global__ __launch_bounds__(ShapePlan::kThreads) void k_epl(
 
     for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const uint64_t t0 = (uint64_t)tile * SH::kTile;
-        const uint64_t t1 = min(n, t0 + SH::kTile);
-        __syncthreads();
-        stage_tile<FMT, SH::kThreads, SH::kXSamples>(samples, n, t0, s_x, tables);
-        __syncthreads();
-        epl_tile<FMT, SH>(s_x, s_lds, t0, t1, 0, n_chan, chans, metas, state, out, tap_stride,
-                          max_dumps, tables);
+        tile_pass<FMT, SH>(samples, n, t0, s_x, s_lds, 0, n_chan, chans, metas, state, out,
+                           tap_stride, max_dumps, tables);
     }
 }
 
@@ -445,7 +574,7 @@ __global__ __launch_bounds__(SH::kThreads) void k_epl_batch(
     uint32_t max_dumps, const uint32_t* __restrict__ tables) {
     __shared__ __attribute__((aligned(16))) uint8_t s_lds[SH::kLdsBytes];
     uint32_t* s_lut = reinterpret_cast<uint32_t*>(s_lds);
-    short* s_x = reinterpret_cast<short*>(s_lds + kLutWords * 4);
+    void* s_x = s_lds + kLutWords * 4;
     const int tid = threadIdx.x;
     // the item count written by k_epl_select, when given
     if (n_items_dev) n_items = min(n_items, *n_items_dev);
@@ -467,19 +596,15 @@ __global__ __launch_bounds__(SH::kThreads) void k_epl_batch(
             mine |= metas[c].status == GC_OK && metas[c].path != kPathPeriodic;
         if (!mine) continue;
         const uint64_t t0 = (uint64_t)(item - R.tile_begin) * SH::kTile;
-        const uint64_t t1 = min(R.n, t0 + SH::kTile);
-        __syncthreads();
         if (R.fmt == GC_I2_REAL)
-            stage_tile<GC_I2_REAL, SH::kThreads, SH::kXSamples>(R.samples, R.n, t0, s_x, tables);
+            tile_pass<GC_I2_REAL, SH>(R.samples, R.n, t0, s_x, s_lds, R.chan_begin, R.chan_end,
+                                      chans, metas, state, out, tap_stride, max_dumps, tables);
+        else if (R.fmt == GC_I8_IQ)
+            tile_pass<GC_I8_IQ, SH>(R.samples, R.n, t0, s_x, s_lds, R.chan_begin, R.chan_end,
+                                    chans, metas, state, out, tap_stride, max_dumps, tables);
         else
-            stage_tile<GC_I8_REAL, SH::kThreads, SH::kXSamples>(R.samples, R.n, t0, s_x, tables);
-        __syncthreads();
-        if (R.fmt == GC_I2_REAL)
-            epl_tile<GC_I2_REAL, SH>(s_x, s_lds, t0, t1, R.chan_begin, R.chan_end, chans, metas,
-                                     state, out, tap_stride, max_dumps, tables);
-        else
-            epl_tile<GC_I8_REAL, SH>(s_x, s_lds, t0, t1, R.chan_begin, R.chan_end, chans, metas,
-                                     state, out, tap_stride, max_dumps, tables);
+            tile_pass<GC_I8_REAL, SH>(R.samples, R.n, t0, s_x, s_lds, R.chan_begin, R.chan_end,
+                                      chans, metas, state, out, tap_stride, max_dumps, tables);
     }
 }
 
@@ -554,6 +679,9 @@ hipError_t launch_epl(const uint8_t* samples, uint64_t n, int fmt, const DevChan
                            meta, state, out, tap_stride, max_dumps, tables, n_chan, n_tiles);
     } else if (fmt == GC_I8_REAL) {
         hipLaunchKernelGGL((k_epl<GC_I8_REAL>), dim3(g), dim3(SH::kThreads), 0, s, samples, n, chans,
+                           meta, state, out, tap_stride, max_dumps, tables, n_chan, n_tiles);
+    } else if (fmt == GC_I8_IQ) {
+        hipLaunchKernelGGL((k_epl<GC_I8_IQ>), dim3(g), dim3(SH::kThreads), 0, s, samples, n, chans,
                            meta, state, out, tap_stride, max_dumps, tables, n_chan, n_tiles);
     } else {
         return hipErrorInvalidValue;

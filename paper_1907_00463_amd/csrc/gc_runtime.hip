@@ -22,7 +22,7 @@ struct gc_plan {
     int max_taps;
     gc::DevChan* d_chans;
     gc::DevMeta* d_meta;
-    int use_epl;      // all channels <= 4 taps, real int8 / 2-bit, integer carrier
+    int use_epl;      // all channels <= 4 taps, integer carrier
     int use_mtap;     // table carrier and some channel has dense 1/32-chip taps
     int kernels;      // GC_KERNEL_* mask
     int epl_grid;     // persistent blocks of the binned kernel
@@ -214,8 +214,7 @@ gc_status gc_plan_create(gc_ctx* ctx, gc_format fmt, gc_carrier carrier, const g
     p->d_chans = nullptr;
     p->d_meta = nullptr;
     p->calls = 0;
-    p->use_epl = carrier == GC_CARRIER_LUT && (fmt == GC_I8_REAL || fmt == GC_I2_REAL) &&
-                 max_taps <= 4;
+    p->use_epl = carrier == GC_CARRIER_LUT && max_taps <= 4;
     p->use_mtap = 0;
     if (carrier == GC_CARRIER_LUT && !p->use_epl)
         for (int i = 0; i < n_chan; ++i) p->use_mtap |= h[(size_t)i].mt_ok;
@@ -379,7 +378,8 @@ gc_status gc_correlate(gc_plan* plan, const void* samples, uint64_t n_samples,
     DeviceGuard g(plan->ctx->device);
     if (!g.ok) return GC_EDEVICE;
     hipStream_t s = (hipStream_t)stream;
-    const bool periodic = plan->use_epl && (plan->kernels & GC_KERNEL_PERIODIC);
+    const bool periodic = plan->use_epl && (plan->kernels & GC_KERNEL_PERIODIC) &&
+                          plan->fmt != GC_I8_IQ;
     const bool binned = plan->use_epl && (plan->kernels & GC_KERNEL_BINNED);
     const bool mtap = plan->use_mtap && (plan->kernels & GC_KERNEL_MTAP);
     const int32_t allow = (periodic ? gc::kAllowPeriodic : 0) | (binned ? gc::kAllowBinned : 0) |

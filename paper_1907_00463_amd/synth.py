@@ -228,6 +228,25 @@ def workload_twelve_channels(seconds: float = 10.0, seed: int = 1002):
     return st, [channel_for(s, if_hz) for s in sats], rng
 
 
+def workload_paper(seconds: float = 10.0, seed: int = 1010):
+    """The paper's offline configuration (Sec. 4): complex int8, I then Q, at
+    fs 5 MHz from a direct-conversion front end (IF 0, Sec. 2.2), 12 satellites
+    in view, 1 ms integrations.  PRNs, Dopplers ~ U(-5, 5) kHz, code phases
+    and C/N0 ~ U(35, 50) dB-Hz are drawn as for the 12-channel workload."""
+    rng = np.random.default_rng(seed)
+    fs, if_hz = 5.0e6, 0.0
+    n = int(round(seconds * fs))
+    n -= n % 4
+    prns = rng.choice(np.arange(1, 33), size=12, replace=False)
+    dop = rng.uniform(-5000.0, 5000.0, size=12)
+    p0 = rng.uniform(0.0, 1023.0, size=12)
+    cn0 = rng.uniform(35.0, 50.0, size=12)
+    sats = [make_sat(rng, fs, n, int(prns[i]), float(dop[i]), float(p0[i]), float(cn0[i]))
+            for i in range(12)]
+    st = Stream(fs, if_hz, I8_IQ, n, sats, seed)
+    return st, [channel_for(s, if_hz) for s in sats], rng
+
+
 def workload_multicorrelator(seconds: float = 2.0, seed: int = 1004, n_chan: int = 256):
     """Complex int8 at 20.46 MHz, IF 0; 12 satellites in the stream; 256 channels =
     32 PRNs x 8 (Doppler, code) hypotheses; 128 taps at -2 + k/32 chips."""

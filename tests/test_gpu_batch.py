@@ -33,7 +33,7 @@ def _receivers(g, seed, n_rx=6):
     rx, cfgs, states, chan_rx = [], [], [], []
     for r in range(n_rx):
         fs = rates[r % 3]
-        fmt = (0, 2)[(r // 3) % 2]
+        fmt = (0, 2, 1)[(r + r // 3) % 3]   # real int8, 2-bit and complex int8
         n = int(rng.integers(50_000, 400_000))
         buf = rng.integers(0, 256, size=block_bytes(fmt, n), dtype=np.uint8)
         rx.append((fmt, n, buf))

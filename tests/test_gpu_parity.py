@@ -217,7 +217,7 @@ KERNEL_SETS = {"default": None, "binned": 2, "direct": 0}
 
 @pytest.mark.parametrize("kernels", list(KERNEL_SETS))
 @pytest.mark.parametrize("fs", [4.092e6, 8.184e6, 16.368e6, 20.46e6, 5e6])
-@pytest.mark.parametrize("fmt", [0, 2])
+@pytest.mark.parametrize("fmt", [0, 1, 2])
 def test_binned_epl_rates_bit_exact(g, ctx, fs, fmt, kernels):
     # E/P/L channels at the workloads' sample rates, several tiles per block,
     # dumps of 1, 4 and 20 periods, Doppler of either sign
@@ -303,6 +303,31 @@ def test_twelve_channel_workload_full_size_bit_exact(g, ctx):
         parts = list(ex.map(one, range(len(cfgs))))
     orc = [([p[0] for p in parts], [p[1] for p in parts])]
     assert int(lib[0][2].min()) == 10000
+    assert_exact(lib, lst, orc, sts, cfgs)
+
+
+def test_paper_workload_full_size_bit_exact(g, ctx):
+    # the paper's offline configuration (complex int8 at 5 MHz, 12 satellites,
+    # 1 ms dumps, Sec. 4) over 10 s in the benchmark's launch configuration:
+    # every dump of every channel against the oracle
+    from concurrent.futures import ThreadPoolExecutor
+
+    from paper_1907_00463_amd import synth
+    st, chans, rng = synth.workload_paper()
+    buf = synth.synth_samples(st, rng)
+    cfgs, states = _cfgs_states_for(g, st, chans)
+    lib, lst = run_library(torch, ctx, st.fmt, g.GC_CARRIER_LUT, cfgs, states, [buf], [st.n])
+    sts = [None] * len(cfgs)
+
+    def one(i):
+        r, s = run_oracle(st.fmt, cfgs[i: i + 1], states[i: i + 1], [buf], [st.n])
+        sts[i] = s[0]
+        return r[0][0][0], r[0][1][0]
+
+    with ThreadPoolExecutor(max_workers=12) as ex:
+        parts = list(ex.map(one, range(len(cfgs))))
+    orc = [([p[0] for p in parts], [p[1] for p in parts])]
+    assert int(lib[0][2].min()) >= 9999
     assert_exact(lib, lst, orc, sts, cfgs)
 
 
