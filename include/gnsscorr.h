@@ -216,6 +216,41 @@ gc_status gc_correlate(gc_plan* plan, const void* samples, uint64_t n_samples,
                        uint32_t* n_dumps, int32_t* status, uint32_t max_dumps,
                        void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * correlation as gc_correlate without a plan.  The per-channel kernel
+ * records and the per-call set-up values that a plan keeps in its own
+ * device buffers live instead in one fixed array of the library, one per
+ * GPU, reserved when the library is loaded and held until the process ends
+ * (GC_NOALLOC_MAX_CHANNELS channels); this call allocates nothing, on the
+ * device or the host.
+ *
+ *   cfg        DEVICE, gc_chan_cfg[n_chan] (the caller's copy; read by the
+ *              call's first kernel, so it may be reused once the stream has
+ *              passed the call)
+ *   n_chan     1 .. GC_NOALLOC_MAX_CHANNELS
+ *   tap_stride taps per output row, 1 .. GC_MAX_TAPS; it also picks the
+ *              kernels as a plan's largest n_taps does (<= 4 with the table
+ *              carrier: the E/P/L kernels; more: the multi-tap and direct
+ *              kernels; float carrier: the direct kernel)
+ *   the rest   as for gc_correlate, with the plan's format and carrier given
+ *              here
+ * A channel whose cfg a plan would refuse (PRN, n_taps, int_periods,
+ * reserved, tap offsets) or with n_taps > tap_stride gets status GC_EINVAL
+ * and is left untouched, like a channel with a bad state.  Every call on
+ * one GPU shares that GPU's array: calls that overlap on the device (two
+ * streams, or two host threads) race and give wrong results; calls ordered
+ * on one stream are safe, each rewrites what it uses.
+ * Errors returned directly: GC_EINVAL (null pointers, fmt, carrier, n_chan
+ * above GC_NOALLOC_MAX_CHANNELS or below 1, tap_stride, n_samples,
+ * max_dumps == 0), GC_EDEVICE. */
+#define GC_NOALLOC_MAX_CHANNELS 1024
+gc_status gc_correlate_noalloc(gc_ctx* ctx, gc_format fmt, gc_carrier carrier,
+                               const gc_chan_cfg* cfg, int32_t n_chan, int32_t tap_stride,
+                               const void* samples, uint64_t n_samples, gc_chan_state* state,
+                               void* out, uint32_t* dump_n, uint32_t* n_dumps, int32_t* status,
+                               uint32_t max_dumps, void* stream);
+
 /* Per-launch timing of the plan's main correlation kernel (the paper reports
  * tracking time per epoch per channel, Sec. 4, Table 5).  A call runs up to
  * two correlation kernels after its set-up (which one takes a channel is

@@ -83,6 +83,80 @@ hipError_t launch_make_tables(uint32_t* d_tables, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Channel records from device-resident configurations, one thread per
+// channel: the checks and derived fields of the host's fill_devchan (E/P/L
+// tap slots, the 1/32-chip grid test), plus n_taps <= tap_stride.  A
+// configuration that fails a check leaves an all-zero record (prn 0), which
+// k_setup refuses with GC_EINVAL.
+__global__ __launch_bounds__(64) void k_fill_chans(const gc_chan_cfg* __restrict__ cfg,
+                                                    int n_chan, int tap_stride,
+                                                    DevChan* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_chan) return;
+    const gc_chan_cfg& c = cfg[i];
+    DevChan d;
+    d.prn = 0;
+    d.n_taps = 0;
+    d.int_periods = 0;
+    d.g2_delay = 0;
+    d.window = 0;
+    d.epl = 0;
+    d.slot_e = d.slot_p = d.slot_l = -1;
+    d.mt_ok = 0;
+    d.mt_jmin = 0;
+    d.mt_nj = 0;
+    d.rx = 0;
+    for (int k = 0; k < GC_MAX_TAPS; ++k) d.taps[k] = 0;
+    bool ok = c.prn >= 1 && c.prn <= 32 && c.n_taps >= 1 && c.n_taps <= tap_stride &&
+              c.int_periods >= 1 && c.int_periods <= 1000 && c.reserved == 0;
+    const int K = ok ? c.n_taps : 0;
+    const int64_t lim = int64_t(1) << 40;
+    bool grid = true;
+    int64_t dmin = 0, dmax = 0;
+    for (int k = 0; k < K; ++k) {
+        const int64_t t = c.tap_q32[k];
+        if (t <= -lim || t >= lim) ok = false;
+        d.taps[k] = t;
+        if (t & ((int64_t(1) << 27) - 1)) grid = false;
+        const int64_t dk = t >> 27;
+        if (k == 0 || dk < dmin) dmin = dk;
+        if (k == 0 || dk > dmax) dmax = dk;
+    }
+    if (ok) {
+        d.prn = c.prn;
+        d.n_taps = c.n_taps;
+        d.int_periods = c.int_periods;
+        d.g2_delay = c_g2_delay_dev[c.prn - 1];
+        d.window = (uint64_t)c.int_periods * kCodeLen * kTwo32;
+        if (K == 3) {
+            const int64_t h = int64_t(1) << 31;
+            for (int k = 0; k < 3; ++k) {
+                if (c.tap_q32[k] == h) d.slot_e = k;
+                else if (c.tap_q32[k] == 0) d.slot_p = k;
+                else if (c.tap_q32[k] == -h) d.slot_l = k;
+            }
+            d.epl = d.slot_e >= 0 && d.slot_p >= 0 && d.slot_l >= 0;
+        }
+        // floor division by 32 of the 1/32-chip indices
+        const int64_t jmin = dmin >= 0 ? dmin / 32 : -((31 - dmin) / 32);
+        const int64_t hi = dmax + 31;
+        const int64_t jmax = hi >= 0 ? hi / 32 : -((31 - hi) / 32);
+        d.mt_ok = grid && jmax - jmin + 1 <= 8;
+        d.mt_jmin = (int32_t)jmin;
+        d.mt_nj = (int32_t)(jmax - jmin + 1);
+    } else {
+        for (int k = 0; k < GC_MAX_TAPS; ++k) d.taps[k] = 0;
+    }
+    out[i] = d;
+}
+
+hipError_t launch_fill_chans(const gc_chan_cfg* cfg, int n_chan, int tap_stride, DevChan* out,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_chans, dim3((n_chan + 63) / 64), dim3(64), 0, s, cfg, n_chan,
+                       tap_stride, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_code_table(const uint32_t* d_tables, int g2_delay, int8_t* d_out, hipStream_t s) {
     hipLaunchKernelGGL(k_code_table, dim3(1), dim3(256), 0, s, d_tables, g2_delay, d_out);
     return hipGetLastError();
@@ -137,7 +211,7 @@ __global__ __launch_bounds__(64) void k_setup(const DevChan* __restrict__ chans,
         m.bin_len = 0;
         m.pad2 = 0;
         int32_t s = GC_OK;
-        if (m.dp == 0 || m.dp >= (1ull << 31) || m.p0 >= m.window) {
+        if (c.prn < 1 || m.dp == 0 || m.dp >= (1ull << 31) || m.p0 >= m.window) {
             s = GC_EINVAL;
         } else {
             const uint64_t u_end = m.p0 + n * m.dp;

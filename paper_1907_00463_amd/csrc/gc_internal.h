@@ -12,6 +12,8 @@ struct gc_ctx {
     int device;
     uint32_t* d_tables;  // G1, G2, carrier table, sign and code tables (gc::kTabWords words)
     hipStream_t stream;  // context-private stream for synchronous helpers
+    int n_cu;            // compute units of the device (persistent grids)
+    uint8_t* d_scratch;  // this device's copy of the fixed array of gc_correlate_noalloc
 };
 
 namespace gc {
@@ -125,6 +127,9 @@ gc_status fill_devchan(const gc_chan_cfg& c, DevChan& d);
 
 // Kernel launch entry points (defined in the .hip files, called by the runtime).
 hipError_t launch_make_tables(uint32_t* d_tables, hipStream_t s);
+// channel records from device-resident configurations (gc_correlate_noalloc)
+hipError_t launch_fill_chans(const gc_chan_cfg* cfg, int n_chan, int tap_stride, DevChan* out,
+                             hipStream_t s);
 hipError_t launch_code_table(const uint32_t* d_tables, int g2_delay, int8_t* d_out, hipStream_t s);
 hipError_t launch_setup(const DevChan* chans, DevMeta* meta, gc_chan_state* state, int n_chan,
                         uint64_t n_samples, int fmt, int carrier, uint32_t max_dumps,

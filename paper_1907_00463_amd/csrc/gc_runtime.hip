@@ -35,6 +35,22 @@ struct gc_plan {
 
 namespace {
 
+// The fixed device array of gc_correlate_noalloc: GC_NOALLOC_MAX_CHANNELS
+// channel records (DevChan) followed by as many per-call set-up records
+// (DevMeta).  Each GPU holds its own copy from the library's load to the end
+// of the process; host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device (gc_create keeps it in
+// the context), never through the array's name.
+constexpr size_t kNoallocChanBytes = sizeof(gc::DevChan) * GC_NOALLOC_MAX_CHANNELS;
+constexpr size_t kNoallocBytes = kNoallocChanBytes + sizeof(gc::DevMeta) * GC_NOALLOC_MAX_CHANNELS;
+static_assert(kNoallocChanBytes % 256 == 0, "set-up records start 256-byte aligned");
+
+}  // namespace
+
+static __device__ __align__(256) uint8_t scratch[kNoallocBytes];
+
+namespace {
+
 // G2 delay in chips of PRN 1..32 (IS-GPS-200, Table 3-Ia).
 const int32_t kG2Delay[32] = {5,   6,   7,   8,   17,  18,  139, 140, 141, 251, 252,
                               254, 255, 256, 257, 258, 469, 470, 471, 472, 473, 474,
@@ -92,6 +108,68 @@ gc_status fill_devchan(const gc_chan_cfg& c, DevChan& d) {
 
 }  // namespace gc
 
+namespace {
+
+// What one correlation call launches, from a plan or from the fixed array.
+struct Launches {
+    int fmt, carrier, n_chan, tap_stride;
+    bool periodic, binned, mtap;
+    int grid;
+    gc::DevChan* chans;
+    gc::DevMeta* meta;
+    const uint32_t* tables;
+    hipEvent_t ev_start = nullptr, ev_mid = nullptr, ev_stop = nullptr;  // null: untimed
+};
+
+// Set-up, then two correlation kernels; which one does the work is decided
+// on the device per channel.  Periodic plans: the periodic kernel, then the
+// chip-by-chip kernel for the E/P/L channels it leaves.  Multi-tap plans:
+// the MFMA kernel, then the direct kernel (one block per channel and tap
+// group looping over the tiles) for channels off the 1/32-chip grid or
+// above 32 samples per chip.  A kernel with no channel returns at once.
+// Timing events (when given) go before, between and after the two; the
+// kernel time is the longer of the two intervals.
+hipError_t run_correlation(const Launches& L, const void* samples, uint64_t n_samples,
+                           gc_chan_state* state, void* out, uint32_t* dump_n,
+                           uint32_t* n_dumps, int32_t* status, uint32_t max_dumps,
+                           hipStream_t s) {
+    const int32_t allow = (L.periodic ? gc::kAllowPeriodic : 0) |
+                          (L.binned ? gc::kAllowBinned : 0) | (L.mtap ? gc::kAllowMtap : 0);
+    hipError_t e = gc::launch_setup(L.chans, L.meta, state, L.n_chan, n_samples, L.fmt,
+                                    L.carrier, max_dumps, out, L.tap_stride, dump_n, n_dumps,
+                                    status, allow, nullptr, nullptr, nullptr, s);
+    const uint8_t* x = (const uint8_t*)samples;
+    int32_t* o = (int32_t*)out;
+    if (e == hipSuccess && L.ev_start) e = hipEventRecord(L.ev_start, s);
+    if (e == hipSuccess) {
+        if (L.mtap)
+            e = gc::launch_mtap(x, n_samples, L.fmt, L.chans, L.meta, state, L.n_chan, o,
+                                L.tap_stride, max_dumps, L.tables, L.grid, s);
+        else if (L.periodic)
+            e = gc::launch_pbin(x, n_samples, L.fmt, L.chans, L.meta, state, L.n_chan, o,
+                                L.tap_stride, max_dumps, L.tables, L.grid, s);
+        else if (L.binned)
+            e = gc::launch_epl(x, n_samples, L.fmt, L.chans, L.meta, state, L.n_chan, o,
+                               L.tap_stride, max_dumps, L.tables, L.grid, s);
+        else
+            e = gc::launch_generic(x, n_samples, L.fmt, L.carrier, L.chans, L.meta, state,
+                                   L.n_chan, L.tap_stride, out, L.tap_stride, max_dumps,
+                                   L.tables, 0, s);
+    }
+    if (e == hipSuccess && L.ev_mid) e = hipEventRecord(L.ev_mid, s);
+    if (e == hipSuccess && L.periodic)
+        e = gc::launch_epl(x, n_samples, L.fmt, L.chans, L.meta, state, L.n_chan, o,
+                           L.tap_stride, max_dumps, L.tables, L.grid, s);
+    if (e == hipSuccess && L.mtap)
+        e = gc::launch_generic(x, n_samples, L.fmt, L.carrier, L.chans, L.meta, state,
+                               L.n_chan, L.tap_stride, out, L.tap_stride, max_dumps,
+                               L.tables, 1, s);
+    if (e == hipSuccess && L.ev_stop) e = hipEventRecord(L.ev_stop, s);
+    return e;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* gc_strerror(gc_status s) {
@@ -128,7 +206,12 @@ gc_status gc_create(gc_ctx** out, int32_t device) {
     c->device = device;
     c->d_tables = nullptr;
     c->stream = nullptr;
-    hipError_t e = hipMalloc(&c->d_tables, gc::kTabWords * sizeof(uint32_t));
+    c->n_cu = gc::epl_blocks_per_device(device);
+    c->d_scratch = nullptr;
+    // this device's copy of the fixed array (the device is current here)
+    hipError_t e = hipGetSymbolAddress((void**)&c->d_scratch, HIP_SYMBOL(scratch));
+    if (e == hipSuccess && !c->d_scratch) e = hipErrorInvalidSymbol;
+    if (e == hipSuccess) e = hipMalloc(&c->d_tables, gc::kTabWords * sizeof(uint32_t));
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = gc::launch_make_tables(c->d_tables, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -219,7 +302,7 @@ gc_status gc_plan_create(gc_ctx* ctx, gc_format fmt, gc_carrier carrier, const g
     if (carrier == GC_CARRIER_LUT && !p->use_epl)
         for (int i = 0; i < n_chan; ++i) p->use_mtap |= h[(size_t)i].mt_ok;
     p->kernels = GC_KERNEL_PERIODIC | GC_KERNEL_BINNED | GC_KERNEL_MTAP;
-    p->epl_grid = gc::epl_blocks_per_device(ctx->device);
+    p->epl_grid = ctx->n_cu;
     hipError_t e = hipMalloc(&p->d_chans, sizeof(gc::DevChan) * (size_t)n_chan);
     if (e == hipSuccess) e = hipMalloc(&p->d_meta, sizeof(gc::DevMeta) * (size_t)n_chan);
     if (e == hipSuccess)
@@ -377,60 +460,65 @@ gc_status gc_correlate(gc_plan* plan, const void* samples, uint64_t n_samples,
     if (n_samples > 0 && !samples) return GC_EINVAL;
     DeviceGuard g(plan->ctx->device);
     if (!g.ok) return GC_EDEVICE;
-    hipStream_t s = (hipStream_t)stream;
-    const bool periodic = plan->use_epl && (plan->kernels & GC_KERNEL_PERIODIC) &&
-                          plan->fmt != GC_I8_IQ;
-    const bool binned = plan->use_epl && (plan->kernels & GC_KERNEL_BINNED);
-    const bool mtap = plan->use_mtap && (plan->kernels & GC_KERNEL_MTAP);
-    const int32_t allow = (periodic ? gc::kAllowPeriodic : 0) | (binned ? gc::kAllowBinned : 0) |
-                          (mtap ? gc::kAllowMtap : 0);
-    hipError_t e = gc::launch_setup(plan->d_chans, plan->d_meta, state, plan->n_chan, n_samples,
-                                    plan->fmt, plan->carrier, max_dumps, out, plan->max_taps,
-                                    dump_n, n_dumps, status, allow, nullptr, nullptr, nullptr, s);
-    const uint8_t* x = (const uint8_t*)samples;
     const size_t slot = plan->ev_stop.empty() ? 0 : (size_t)(plan->calls % plan->ev_stop.size());
     const bool timed = !plan->ev_start.empty();
-    // Two correlation kernels per call; which one does the work is decided on
-    // the device per channel.  Periodic plans: the periodic kernel, then the
-    // chip-by-chip kernel for the E/P/L channels it leaves.  Multi-tap plans:
-    // the MFMA kernel, then the direct kernel (one block per channel and tap
-    // group looping over the tiles) for channels off the 1/32-chip grid or
-    // above 32 samples per chip.  A kernel with no channel returns at once.
-    // The timing slot records events before, between and after the two; the
-    // plan's kernel time is the longer of the two intervals.
-    if (e == hipSuccess && timed) e = hipEventRecord(plan->ev_start[slot], s);
-    if (e == hipSuccess) {
-        if (mtap)
-            e = gc::launch_mtap(x, n_samples, plan->fmt, plan->d_chans, plan->d_meta, state,
-                                plan->n_chan, (int32_t*)out, plan->max_taps, max_dumps,
-                                plan->ctx->d_tables, plan->epl_grid, s);
-        else if (periodic)
-            e = gc::launch_pbin(x, n_samples, plan->fmt, plan->d_chans, plan->d_meta, state,
-                                plan->n_chan, (int32_t*)out, plan->max_taps, max_dumps,
-                                plan->ctx->d_tables, plan->epl_grid, s);
-        else if (binned)
-            e = gc::launch_epl(x, n_samples, plan->fmt, plan->d_chans, plan->d_meta, state,
-                               plan->n_chan, (int32_t*)out, plan->max_taps, max_dumps,
-                               plan->ctx->d_tables, plan->epl_grid, s);
-        else
-            e = gc::launch_generic(x, n_samples, plan->fmt, plan->carrier, plan->d_chans,
-                                   plan->d_meta, state, plan->n_chan, plan->max_taps, out,
-                                   plan->max_taps, max_dumps, plan->ctx->d_tables, 0, s);
-    }
-    if (e == hipSuccess && timed) e = hipEventRecord(plan->ev_mid[slot], s);
-    if (e == hipSuccess && periodic)
-        e = gc::launch_epl(x, n_samples, plan->fmt, plan->d_chans, plan->d_meta, state,
-                           plan->n_chan, (int32_t*)out, plan->max_taps, max_dumps,
-                           plan->ctx->d_tables, plan->epl_grid, s);
-    if (e == hipSuccess && mtap)
-        e = gc::launch_generic(x, n_samples, plan->fmt, plan->carrier, plan->d_chans,
-                               plan->d_meta, state, plan->n_chan, plan->max_taps, out,
-                               plan->max_taps, max_dumps, plan->ctx->d_tables, 1, s);
-    if (e == hipSuccess && timed) {
-        e = hipEventRecord(plan->ev_stop[slot], s);
-        plan->ev_used[slot] = 1;
-    }
+    Launches L{};
+    L.fmt = plan->fmt;
+    L.carrier = plan->carrier;
+    L.n_chan = plan->n_chan;
+    L.tap_stride = plan->max_taps;
+    L.periodic = plan->use_epl && (plan->kernels & GC_KERNEL_PERIODIC) && plan->fmt != GC_I8_IQ;
+    L.binned = plan->use_epl && (plan->kernels & GC_KERNEL_BINNED);
+    L.mtap = plan->use_mtap && (plan->kernels & GC_KERNEL_MTAP);
+    L.grid = plan->epl_grid;
+    L.chans = plan->d_chans;
+    L.meta = plan->d_meta;
+    L.tables = plan->ctx->d_tables;
+    L.ev_start = timed ? plan->ev_start[slot] : nullptr;
+    L.ev_mid = timed ? plan->ev_mid[slot] : nullptr;
+    L.ev_stop = timed ? plan->ev_stop[slot] : nullptr;
+    const hipError_t e = run_correlation(L, samples, n_samples, state, out, dump_n, n_dumps,
+                                         status, max_dumps, (hipStream_t)stream);
+    if (e == hipSuccess && timed) plan->ev_used[slot] = 1;
     plan->calls++;
+    return from_hip(e);
+}
+
+gc_status gc_correlate_noalloc(gc_ctx* ctx, gc_format fmt, gc_carrier carrier,
+                               const gc_chan_cfg* cfg, int32_t n_chan, int32_t tap_stride,
+                               const void* samples, uint64_t n_samples, gc_chan_state* state,
+                               void* out, uint32_t* dump_n, uint32_t* n_dumps, int32_t* status,
+                               uint32_t max_dumps, void* stream) {
+    if (!ctx || !cfg || !state || !out || !dump_n || !n_dumps || !status) return GC_EINVAL;
+    if (fmt != GC_I8_REAL && fmt != GC_I8_IQ && fmt != GC_I2_REAL) return GC_EINVAL;
+    if (carrier != GC_CARRIER_LUT && carrier != GC_CARRIER_F32) return GC_EINVAL;
+    if (n_chan < 1 || n_chan > GC_NOALLOC_MAX_CHANNELS) return GC_EINVAL;
+    if (tap_stride < 1 || tap_stride > GC_MAX_TAPS) return GC_EINVAL;
+    if (n_samples >= (1ull << 31) || max_dumps == 0) return GC_EINVAL;
+    if (n_samples > 0 && !samples) return GC_EINVAL;
+    if (!ctx->d_scratch) return GC_EDEVICE;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return GC_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    // the kernel families a plan with these channels would use: tap_stride
+    // stands for the plan's largest n_taps
+    const bool use_epl = carrier == GC_CARRIER_LUT && tap_stride <= 4;
+    Launches L{};
+    L.fmt = fmt;
+    L.carrier = carrier;
+    L.n_chan = n_chan;
+    L.tap_stride = tap_stride;
+    L.periodic = use_epl && fmt != GC_I8_IQ;
+    L.binned = use_epl;
+    L.mtap = carrier == GC_CARRIER_LUT && !use_epl;
+    L.grid = ctx->n_cu;
+    L.chans = reinterpret_cast<gc::DevChan*>(ctx->d_scratch);
+    L.meta = reinterpret_cast<gc::DevMeta*>(ctx->d_scratch + kNoallocChanBytes);
+    L.tables = ctx->d_tables;
+    hipError_t e = gc::launch_fill_chans(cfg, n_chan, tap_stride, L.chans, s);
+    if (e == hipSuccess)
+        e = run_correlation(L, samples, n_samples, state, out, dump_n, n_dumps, status,
+                            max_dumps, s);
     return from_hip(e);
 }
 

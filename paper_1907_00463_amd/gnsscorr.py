@@ -23,6 +23,7 @@ GC_CARRIER_LUT, GC_CARRIER_F32 = 0, 1
 GC_KERNEL_PERIODIC, GC_KERNEL_BINNED, GC_KERNEL_MTAP = 1, 2, 4
 GC_SERVER_PLAIN = 1
 GC_MAX_TAPS = 128
+GC_NOALLOC_MAX_CHANNELS = 1024
 GC_LUT_AMP = 24
 TWO32 = 1 << 32
 
@@ -78,6 +79,7 @@ def _load():
         "gc_plan_destroy": ([P], I32),
         "gc_plan_info": ([P, P, P], I32),
         "gc_correlate": ([P, P, U64, P, P, P, P, P, U32, P], I32),
+        "gc_correlate_noalloc": ([P, I32, I32, P, I32, I32, P, U64, P, P, P, P, P, U32, P], I32),
         "gc_plan_timing": ([P, I32], I32),
         "gc_plan_kernel_ms": ([P, I32, P], I32),
         "gc_plan_set_kernels": ([P, I32], I32),
@@ -118,7 +120,7 @@ def _load():
 _lib = _load()
 EXPORTED = ("gc_strerror", "gc_version", "gc_create", "gc_destroy", "gc_nco_init",
             "gc_code_table", "gc_plan_create", "gc_plan_destroy", "gc_plan_info",
-            "gc_correlate", "gc_plan_timing", "gc_plan_kernel_ms", "gc_plan_set_kernels",
+            "gc_correlate", "gc_correlate_noalloc", "gc_plan_timing", "gc_plan_kernel_ms", "gc_plan_set_kernels",
             "gc_batch_create", "gc_batch_configure", "gc_batch_tune", "gc_batch_launch",
             "gc_batch_info", "gc_batch_destroy", "gc_server_create", "gc_server_open_rx",
             "gc_server_submit", "gc_server_hold", "gc_server_poll", "gc_server_result", "gc_server_state",
@@ -206,6 +208,17 @@ def gc_correlate(plan: int, samples, n_samples: int, state, out, dump_n, n_dumps
     return _lib.gc_correlate(plan, _ptr(samples), n_samples, _ptr(state), _ptr(out),
                              _ptr(dump_n), _ptr(n_dumps), _ptr(status), max_dumps,
                              _stream_ptr(stream))
+
+
+def gc_correlate_noalloc(ctx: int, fmt: int, carrier: int, cfg, n_chan: int, tap_stride: int,
+                         samples, n_samples: int, state, out, dump_n, n_dumps, status,
+                         max_dumps: int, stream=None) -> int:
+    """Enqueue one block without a plan (``cfg`` in device memory); returns the
+    gc_status of the call (per-channel status in ``status``)."""
+    return _lib.gc_correlate_noalloc(ctx, fmt, carrier, _ptr(cfg), n_chan, tap_stride,
+                                     _ptr(samples), n_samples, _ptr(state), _ptr(out),
+                                     _ptr(dump_n), _ptr(n_dumps), _ptr(status), max_dumps,
+                                     _stream_ptr(stream))
 
 
 def gc_plan_timing(plan: int, n_slots: int) -> None:

@@ -86,6 +86,9 @@ def test_host_validation_without_a_device():
     assert g._lib.gc_plan_create(None, 0, 0, None, 1, None) == g.GC_EINVAL
     assert g._lib.gc_correlate(None, None, 0, None, None, None, None, None, 1, None) == g.GC_EINVAL
     assert g._lib.gc_destroy(None) == g.GC_EINVAL
+    # the allocation-free entry point: null context, then sizes past the fixed array
+    assert g._lib.gc_correlate_noalloc(None, 0, 0, None, 1, 3, None, 0, None, None, None, None,
+                                       None, 1, None) == g.GC_EINVAL
     assert g._lib.gc_plan_destroy(None) == g.GC_EINVAL
     assert g._lib.gc_code_table(None, 1, None) == g.GC_EINVAL
     assert g._lib.gc_batch_create(None, None, 1, None, None, 1, None, None, None, None, None,
