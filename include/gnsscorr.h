@@ -148,6 +148,20 @@ gc_status gc_nco_init(double fs_hz, double carr_hz, double carr_phase_cyc,
  * Synchronous.  Errors: GC_EINVAL (prn, null), GC_EDEVICE. */
 gc_status gc_code_table(gc_ctx* ctx, int32_t prn, int8_t* host_out);
 
+/* The stated error of the float carrier (GC_CARRIER_F32).  Its kernels
+ * compute each sample's phase in cycles in fp32, reduced to [0, 1), from a
+ * start phase computed in fp64, and take cos and sin of 2*pi*phase with the
+ * GPU's sine and cosine instructions (argument in revolutions).  This call
+ * evaluates that same sin/cos routine on the GPU for every fp32 phase whose
+ * bit pattern lies in first_bits .. first_bits + count - 1 and returns the
+ * largest absolute error against cos and sin in double precision:
+ * host_err[0] for cos, host_err[1] for sin.  All 1,065,353,216 fp32 values
+ * in [0, 1) are bit patterns 0 .. 0x3F7FFFFF.  Synchronous.
+ * Errors: GC_EINVAL (null, count 0, a bit pattern at or above that of 1.0f),
+ * GC_ENOMEM, GC_EDEVICE. */
+gc_status gc_carrier_f32_error(gc_ctx* ctx, uint32_t first_bits, uint32_t count,
+                               double* host_err);
+
 /* Build a plan for a fixed set of channels that share one sample stream
  * (one receiver; channels run independently as in Sec. 3.5).  Validates
  * every cfg on the host, uploads them to device memory (synchronous) and

@@ -66,6 +66,15 @@ __device__ __forceinline__ void lut_cs(uint32_t e, int& c, int& s) {
     s = (int)(int16_t)(e >> 16);
 }
 
+// Float carrier: (cos, sin)(2*pi*ph) for a phase ph in cycles, 0 <= ph < 1,
+// by the VALU's sine and cosine instructions (their argument is in
+// revolutions).  Every float-carrier kernel calls this one function, and
+// gc_carrier_f32_error measures it against double precision.
+__device__ __forceinline__ void carrier_f32(float ph, float& c, float& s) {
+    c = __builtin_amdgcn_cosf(ph);
+    s = __builtin_amdgcn_sinf(ph);
+}
+
 // Wipe-off by exp(-j*theta): real (x*c, -x*s); complex (xi*c + xq*s, xq*c - xi*s).
 template <int FMT, typename T>
 __device__ __forceinline__ void wipe(T xi, T xq, T c, T s, T& wi, T& wq) {

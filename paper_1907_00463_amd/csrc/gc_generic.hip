@@ -86,8 +86,8 @@ __global__ __launch_bounds__(kThreads) void k_generic(const uint8_t* __restrict_
                 lut_cs(s_lut[phi >> 24], c, s);
                 wipe<FMT, int>(xi, xq, c, s, wi, wq);
             } else {
-                const float c = __builtin_amdgcn_cosf(ph);
-                const float s = __builtin_amdgcn_sinf(ph);
+                float c, s;
+                carrier_f32(ph, c, s);
                 wipe<FMT, float>((float)xi, (float)xq, c, s, wi, wq);
                 ph += dph;
                 ph -= floorf(ph);
@@ -144,7 +144,43 @@ void launch_one(const uint8_t* samples, uint64_t n, const DevChan* chans, const 
                        meta, state, out, tap_stride, max_dumps, tables);
 }
 
+// Largest |error| of carrier_f32 over the fp32 phases with bit patterns
+// first .. first + count - 1 (all in [0, 1)), against cos and sin of
+// 2*pi*phase in double precision: out[0] cos, out[1] sin, as the bit
+// patterns of non-negative doubles (which order like the integers).
+__global__ __launch_bounds__(256) void k_carrier_sweep(uint32_t first, uint32_t count,
+                                                        unsigned long long* __restrict__ out) {
+    double ec = 0.0, es = 0.0;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+        const float ph = __uint_as_float(first + i);
+        float c, s;
+        carrier_f32(ph, c, s);
+        double sd, cd;
+        sincos(6.283185307179586476925286766559 * (double)ph, &sd, &cd);
+        ec = fmax(ec, fabs((double)c - cd));
+        es = fmax(es, fabs((double)s - sd));
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        ec = fmax(ec, __shfl_xor(ec, o, 64));
+        es = fmax(es, __shfl_xor(es, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(out, (unsigned long long)__double_as_longlong(ec));
+        atomicMax(out + 1, (unsigned long long)__double_as_longlong(es));
+    }
+}
+
 }  // namespace
+
+hipError_t launch_carrier_sweep(uint32_t first, uint32_t count, unsigned long long* out,
+                                hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    const uint32_t blocks = min((count + 255u) / 256u, 8192u);
+    hipLaunchKernelGGL(k_carrier_sweep, dim3(blocks), dim3(256), 0, s, first, count, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_generic(const uint8_t* samples, uint64_t n, int fmt, int carrier,
                           const DevChan* chans, const DevMeta* meta, gc_chan_state* state,

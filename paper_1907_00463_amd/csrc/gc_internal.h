@@ -183,6 +183,10 @@ hipError_t launch_track(const uint8_t* samples, uint64_t n, int fmt, const DevCh
                         int n_chan, int32_t* rows, uint32_t* dump_n, uint32_t* n_dumps,
                         int32_t* status, uint32_t max_dumps, const uint32_t* tables,
                         hipStream_t s);
+// largest errors of the float carrier's sin/cos over a range of fp32 phases
+// (two zeroed device words in, double bit patterns out)
+hipError_t launch_carrier_sweep(uint32_t first, uint32_t count, unsigned long long* out,
+                                hipStream_t s);
 hipError_t launch_generic(const uint8_t* samples, uint64_t n_samples, int fmt, int carrier,
                           const DevChan* chans, const DevMeta* meta, gc_chan_state* state,
                           int n_chan, int max_taps, void* out, int tap_stride,

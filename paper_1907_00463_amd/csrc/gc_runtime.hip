@@ -271,6 +271,28 @@ gc_status gc_code_table(gc_ctx* ctx, int32_t prn, int8_t* host_out) {
     return from_hip(e);
 }
 
+gc_status gc_carrier_f32_error(gc_ctx* ctx, uint32_t first_bits, uint32_t count,
+                               double* host_err) {
+    if (!ctx || !host_err || count == 0) return GC_EINVAL;
+    // every phase in [0, 1): bit patterns below that of 1.0f
+    if (first_bits >= 0x3F800000u || count > 0x3F800000u - first_bits) return GC_EINVAL;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return GC_EDEVICE;
+    unsigned long long* d = nullptr;
+    unsigned long long h[2] = {0, 0};
+    hipError_t e = hipMalloc(&d, sizeof(h));
+    if (e == hipSuccess) e = hipMemsetAsync(d, 0, sizeof(h), ctx->stream);
+    if (e == hipSuccess) e = gc::launch_carrier_sweep(first_bits, count, d, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (d) (void)hipFree(d);
+    if (e == hipSuccess) {
+        memcpy(&host_err[0], &h[0], sizeof(double));
+        memcpy(&host_err[1], &h[1], sizeof(double));
+    }
+    return from_hip(e);
+}
+
 gc_status gc_plan_create(gc_ctx* ctx, gc_format fmt, gc_carrier carrier, const gc_chan_cfg* cfg,
                          int32_t n_chan, gc_plan** out) {
     if (!ctx || !cfg || !out) return GC_EINVAL;

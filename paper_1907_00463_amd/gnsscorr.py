@@ -75,6 +75,7 @@ def _load():
         "gc_destroy": ([P], I32),
         "gc_nco_init": ([D, D, D, D, D, I32, P], I32),
         "gc_code_table": ([P, I32, P], I32),
+        "gc_carrier_f32_error": ([P, U32, U32, P], I32),
         "gc_plan_create": ([P, I32, I32, P, I32, P], I32),
         "gc_plan_destroy": ([P], I32),
         "gc_plan_info": ([P, P, P], I32),
@@ -119,7 +120,7 @@ def _load():
 
 _lib = _load()
 EXPORTED = ("gc_strerror", "gc_version", "gc_create", "gc_destroy", "gc_nco_init",
-            "gc_code_table", "gc_plan_create", "gc_plan_destroy", "gc_plan_info",
+            "gc_code_table", "gc_carrier_f32_error", "gc_plan_create", "gc_plan_destroy", "gc_plan_info",
             "gc_correlate", "gc_correlate_noalloc", "gc_plan_timing", "gc_plan_kernel_ms", "gc_plan_set_kernels",
             "gc_batch_create", "gc_batch_configure", "gc_batch_tune", "gc_batch_launch",
             "gc_batch_info", "gc_batch_destroy", "gc_server_create", "gc_server_open_rx",
@@ -178,6 +179,15 @@ def gc_code_table(ctx: int, prn: int) -> np.ndarray:
     out = np.zeros(1023, np.int8)
     _check(_lib.gc_code_table(ctx, prn, out.ctypes.data), "gc_code_table")
     return out
+
+
+def gc_carrier_f32_error(ctx: int, first_bits: int = 0, count: int = 0x3F800000):
+    """Largest |error| (cos, sin) of the float carrier's sin/cos over fp32 phases
+    with bit patterns first_bits .. first_bits + count - 1, against fp64."""
+    out = np.zeros(2, np.float64)
+    _check(_lib.gc_carrier_f32_error(ctx, first_bits, count, out.ctypes.data),
+           "gc_carrier_f32_error")
+    return float(out[0]), float(out[1])
 
 
 def gc_plan_create(ctx: int, fmt: int, carrier: int, cfg: np.ndarray) -> int:

@@ -86,6 +86,7 @@ def test_host_validation_without_a_device():
     assert g._lib.gc_plan_create(None, 0, 0, None, 1, None) == g.GC_EINVAL
     assert g._lib.gc_correlate(None, None, 0, None, None, None, None, None, 1, None) == g.GC_EINVAL
     assert g._lib.gc_destroy(None) == g.GC_EINVAL
+    assert g._lib.gc_carrier_f32_error(None, 0, 1, None) == g.GC_EINVAL
     # the allocation-free entry point: null context, then sizes past the fixed array
     assert g._lib.gc_correlate_noalloc(None, 0, 0, None, 1, 3, None, 0, None, None, None, None,
                                        None, 1, None) == g.GC_EINVAL

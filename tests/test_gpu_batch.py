@@ -190,3 +190,78 @@ def test_batch_wide_receivers_share_waves(g, ctx):
         _check(b, cfgs, _oracle_all(rx, cfgs, states, chan_rx))
     finally:
         b.close()
+
+
+def test_batch_full_workload_sampled(g, ctx):
+    # The 64-receiver batched workload at full size (708 channels, 1 s per
+    # receiver at 4.092/8.184/16.368 MHz, int8 and 2-bit, 1/4/20-period dumps)
+    # in the launch configuration the benchmark times: one batch, tuned, the
+    # graph launched once.  The receivers' channels and NCO words are the
+    # workload's; the sample bytes are uniform random (bit-exactness does not
+    # depend on the signal, and this keeps the test fast).  Checked against
+    # the oracle: one channel of every (rate, format, period) class, the first
+    # and last channel of the widest receiver, and the receivers' last
+    # channels, which close the work queue's items.
+    from paper_1907_00463_amd import synth
+    work = synth.workload_batched(seconds=1.0)
+    rng = np.random.default_rng(1303)
+    rx, cfgs, states, chan_rx = [], [], [], []
+    for r, (st, chans, _) in enumerate(work):
+        rx.append((st.fmt, st.n, rng.integers(0, 256, size=block_bytes(st.fmt, st.n),
+                                              dtype=np.uint8)))
+        for ch in chans:
+            cfgs.append(g.make_cfg(ch.prn, synth.taps_to_q32(ch.taps_chips), ch.int_periods))
+            states.append(g.gc_nco_init(st.fs, ch.carr_hz, ch.carr_phase0, ch.code_rate,
+                                        ch.code_phase0, ch.int_periods))
+            chan_rx.append(r)
+    cfgs = np.array(cfgs, g.CHAN_CFG)
+    states = np.array(states, g.CHAN_STATE)
+    chan_rx = np.array(chan_rx)
+    assert len(work) == 64 and len(cfgs) == 708
+    pick = {}
+    for i in range(len(cfgs)):
+        st = work[int(chan_rx[i])][0]
+        pick.setdefault((st.fs, st.fmt, int(cfgs[i]["int_periods"])), i)
+    assert len(pick) == 18
+    sel = set(pick.values())
+    widest = max(range(64), key=lambda r: int(np.sum(chan_rx == r)))
+    idx = np.nonzero(chan_rx == widest)[0]
+    sel |= {int(idx[0]), int(idx[-1])}
+    for r in range(0, 64, 9):
+        sel.add(int(np.nonzero(chan_rx == r)[0][-1]))
+    sel = sorted(sel)
+    b = _make_batch(g, ctx, rx, cfgs, states, chan_rx)
+    try:
+        s0 = b.state.clone()
+        b.tune(reps=1)
+        assert torch.equal(b.state, s0)
+        b.launch()
+        torch.cuda.synchronize()
+        out = b.out.cpu().numpy()
+        dump_n = b.dump_n.cpu().numpy().astype(np.uint32)
+        n_dumps = b.n_dumps.cpu().numpy()
+        status = b.status.cpu().numpy()
+        st_fin = b.states()
+        assert np.all(status == 0)
+        for i in sel:
+            fmt, n, buf = rx[int(chan_rx[i])]
+            r, s = run_oracle(fmt, cfgs[i: i + 1], states[i: i + 1], [buf], [n])
+            dumps, dns, so = r[0][0][0], r[0][1][0], s[0]
+            nd = int(n_dumps[i])
+            assert nd == len(dumps), (i, nd, len(dumps))
+            assert np.array_equal(out[i, :nd, :3].astype(np.int64), dumps), i
+            assert np.array_equal(dump_n[i, :nd], dns), i
+            assert int(st_fin[i]["code_phase"]) == so.code_phase, i
+            assert int(st_fin[i]["carr_phase"]) == so.carr_phase, i
+            assert int(st_fin[i]["acc_n"]) == so.acc_n, i
+            assert np.array_equal(st_fin[i]["acc"][:3].reshape(-1).astype(np.int64), so.acc), i
+        # every channel: dump counts and sample counts follow from the NCO words alone
+        for i in range(len(cfgs)):
+            n = rx[int(chan_rx[i])][1]
+            W = int(cfgs[i]["int_periods"]) * 1023 << 32
+            u_end = int(states[i]["code_phase"]) + n * int(states[i]["code_step"])
+            assert int(n_dumps[i]) == u_end // W, i
+            nd = int(n_dumps[i])
+            assert int(dump_n[i, :nd].astype(np.int64).sum()) + int(st_fin[i]["acc_n"]) == n, i
+    finally:
+        b.close()
