@@ -636,7 +636,7 @@ gc_status gc_acq_timing(gc_acq* a, int32_t n_slots) {
     acq_drop_timing(a);
     for (int i = 0; i < 5 * n_slots; ++i) {
         hipEvent_t e;
-        const hipError_t r = hipEventCreate(&e);
+        const hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
         if (r != hipSuccess) {
             acq_drop_timing(a);
             return from_hip(r);

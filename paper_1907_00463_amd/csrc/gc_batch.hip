@@ -274,8 +274,8 @@ gc_status gc_batch_tune(gc_batch* b, int32_t reps) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipMalloc(&snap, sbytes);
     if (e == hipSuccess) e = hipMemcpyAsync(snap, b->state, sbytes, hipMemcpyDeviceToDevice, b->cap);
-    if (e == hipSuccess) e = hipEventCreate(&e0);
-    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&e0, hipEventDisableSystemFence);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&e1, hipEventDisableSystemFence);
     // mean time of `reps` launches of the current configuration (after one
     // warm-up), the bound states restored before each
     auto time_config = [&](float* mean) {

@@ -358,7 +358,7 @@ gc_status gc_plan_timing(gc_plan* plan, int32_t n_slots) {
     for (int i = 0; i < n_slots; ++i) {
         hipEvent_t ev[3];
         for (int k = 0; k < 3; ++k) {
-            if (hipEventCreate(&ev[k]) != hipSuccess) {
+            if (hipEventCreateWithFlags(&ev[k], hipEventDisableSystemFence) != hipSuccess) {
                 for (int j = 0; j < k; ++j) (void)hipEventDestroy(ev[j]);
                 drop_timing(plan);
                 return GC_EDEVICE;
