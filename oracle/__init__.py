@@ -10,7 +10,7 @@ matrix-form brute force for tiny inputs, used as one of the pins;
 ``acquire.py`` is the FFT-based parallel code-phase search (numpy, fp64).
 """
 from .oracle import (  # noqa: F401
-    I8_REAL, I8_IQ, I2_REAL, EPL_TAPS_Q32, OracleState,
+    I8_REAL, I8_IQ, I2_REAL, I2_IQ, EPL_TAPS_Q32, OracleState,
     build, ca_bits, ca_code, g2_bits, g2i_bits, lut, nco_words,
     correlate_lut, correlate_f64, advance_words,
     LoopParams, TrackState, track_state, cordic_table, cordic_atan2, loop_coefficients, track,

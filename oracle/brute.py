@@ -26,9 +26,15 @@ def unpack(fmt: int, buf: np.ndarray, n: int) -> np.ndarray:
     if fmt == 1:
         v = buf[: 2 * n].view(np.int8).astype(np.int64)
         return v[0::2] + 1j * v[1::2]
-    idx = np.arange(n)
-    codes = (buf[idx // 4] >> (2 * (idx % 4))) & 3
-    return (2 * codes.astype(np.int64) - 3) + 0j
+    if fmt == 2:
+        idx = np.arange(n)
+        codes = (buf[idx // 4] >> (2 * (idx % 4))) & 3
+        return (2 * codes.astype(np.int64) - 3) + 0j
+    # 2-bit complex: the 2-bit real packing of the interleaved stream I0 Q0 I1 Q1 ...
+    bits = np.unpackbits(buf[: (n + 1) // 2], bitorder="little").reshape(-1, 2)
+    codes = bits[:, 0].astype(np.int64) + 2 * bits[:, 1]           # value codes, stream order
+    vals = (2 * codes - 3)[: 2 * n]
+    return vals[0::2] + 1j * vals[1::2]
 
 
 def correlate(fmt, buf, n, code_pm1, taps_q32, T, carr_phase, carr_step, code_phase, code_step,

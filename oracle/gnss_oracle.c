@@ -38,7 +38,10 @@
 #define ORC_TWO32 4294967296.0
 
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ERANGE = -4, ORC_ENOSPC = -7 };
-enum { ORC_I8_REAL = 0, ORC_I8_IQ = 1, ORC_I2_REAL = 2 };
+enum { ORC_I8_REAL = 0, ORC_I8_IQ = 1, ORC_I2_REAL = 2, ORC_I2_IQ = 3 };
+
+/* Complex formats: the wipe-off multiplies (xI + j xQ) by exp(-j*theta). */
+static int orc_is_complex(int fmt) { return fmt == ORC_I8_IQ || fmt == ORC_I2_IQ; }
 
 /* ------------------------------------------------------------------------ */
 /* C/A Gold code, IS-GPS-200 Sec. 3.2.1.3.                                   */
@@ -189,9 +192,12 @@ static int64_t orc_mod(int64_t a, int64_t m)
     return r < 0 ? r + m : r;
 }
 
-/* One sample, unpacked: real formats set xq = 0 and is_complex = 0.
+/* One sample, unpacked: real formats set xq = 0.
  * 2-bit real: value codes 0,1,2,3 -> -3,-1,+1,+3, four samples per byte,
- * sample j of a byte in bits [2j, 2j+1] (least significant pair first). */
+ * sample j of a byte in bits [2j, 2j+1] (least significant pair first).
+ * 2-bit complex: the 2-bit real packing of the interleaved stream I0 Q0 I1
+ * Q1 ..., so two samples per byte, sample j's I in bits [4j, 4j+1] and its
+ * Q in bits [4j+2, 4j+3], same value codes. */
 static void orc_sample(int fmt, const uint8_t* buf, uint64_t n, int* xi, int* xq)
 {
     if (fmt == ORC_I8_REAL) {
@@ -200,10 +206,14 @@ static void orc_sample(int fmt, const uint8_t* buf, uint64_t n, int* xi, int* xq
     } else if (fmt == ORC_I8_IQ) {
         *xi = (int)(int8_t)buf[2 * n];
         *xq = (int)(int8_t)buf[2 * n + 1];
-    } else {
+    } else if (fmt == ORC_I2_REAL) {
         int code = (buf[n >> 2] >> (2 * (n & 3))) & 3;
         *xi = 2 * code - 3;
         *xq = 0;
+    } else {
+        const int byte = buf[n >> 1], sh = 4 * (int)(n & 1);
+        *xi = 2 * ((byte >> sh) & 3) - 3;
+        *xq = 2 * ((byte >> (sh + 2)) & 3) - 3;
     }
 }
 
@@ -239,7 +249,7 @@ int orc_correlate_lut(int fmt, const uint8_t* buf, uint64_t n_samples,
                       int64_t* dumps, uint32_t* dump_n, uint32_t max_dumps,
                       uint32_t* n_dumps)
 {
-    if (fmt < 0 || fmt > 2 || n_taps < 1 || int_periods < 1 || !acc || !acc_n || !n_dumps)
+    if (fmt < 0 || fmt > 3 || n_taps < 1 || int_periods < 1 || !acc || !acc_n || !n_dumps)
         return ORC_EINVAL;
     int8_t code[ORC_CODE_LEN], lc[ORC_LUT_SIZE], ls[ORC_LUT_SIZE];
     if (orc_ca_code(prn, code)) return ORC_EINVAL;
@@ -260,7 +270,7 @@ int orc_correlate_lut(int fmt, const uint8_t* buf, uint64_t n_samples,
         int xi, xq;
         orc_sample(fmt, buf, n, &xi, &xq);
         int64_t wi, wq;
-        if (fmt == ORC_I8_IQ) {
+        if (orc_is_complex(fmt)) {
             wi = (int64_t)xi * c + (int64_t)xq * s;
             wq = (int64_t)xq * c - (int64_t)xi * s;
         } else {
@@ -326,7 +336,7 @@ int orc_correlate_f64(int fmt, const uint8_t* buf, uint64_t n_samples,
                       double* dumps, uint32_t* dump_n, uint32_t max_dumps,
                       uint32_t* n_dumps)
 {
-    if (fmt < 0 || fmt > 2 || n_taps < 1 || int_periods < 1 || !acc || !acc_n || !n_dumps)
+    if (fmt < 0 || fmt > 3 || n_taps < 1 || int_periods < 1 || !acc || !acc_n || !n_dumps)
         return ORC_EINVAL;
     int8_t code[ORC_CODE_LEN];
     if (orc_ca_code(prn, code)) return ORC_EINVAL;
@@ -344,7 +354,7 @@ int orc_correlate_f64(int fmt, const uint8_t* buf, uint64_t n_samples,
         int xi, xq;
         orc_sample(fmt, buf, n, &xi, &xq);
         double wi, wq;
-        if (fmt == ORC_I8_IQ) {
+        if (orc_is_complex(fmt)) {
             wi = xi * c + xq * s;
             wq = xq * c - xi * s;
         } else {
@@ -492,7 +502,8 @@ static void orc_shrink4(int64_t* a, int64_t* b, int64_t* c, int64_t* d)
  * the code step leaves [1, 2^31).
  */
 /* The largest |wipe-off| of one sample: 128 * 24 (int8 real), 128 * the   */
-/* largest |cos| + |sin| of the table (int8 I/Q), 3 * 24 (2-bit). */
+/* largest |cos| + |sin| of the table (int8 I/Q), 3 * 24 (2-bit real), 3 * */
+/* the largest |cos| + |sin| (2-bit I/Q). */
 static int64_t orc_max_w(int fmt)
 {
     if (fmt == ORC_I8_REAL) return 128 * 24;
@@ -504,7 +515,7 @@ static int64_t orc_max_w(int fmt)
         const int v = abs(c[l]) + abs(s[l]);
         if (v > m) m = v;
     }
-    return 128 * (int64_t)m;
+    return (fmt == ORC_I2_IQ ? 3 : 128) * (int64_t)m;
 }
 
 /* A code step keeps every dump inside int32 when a window of W holds at   */
@@ -585,7 +596,7 @@ int orc_track(int fmt, const uint8_t* buf, uint64_t n_samples, int prn, int int_
               double* ls, int32_t* is, int32_t* rows, uint32_t* dump_n, uint32_t max_dumps,
               uint32_t* n_dumps)
 {
-    if (fmt < 0 || fmt > 2 || int_periods < 1 || !prm || !acc || !acc_n || !ls || !is ||
+    if (fmt < 0 || fmt > 3 || int_periods < 1 || !prm || !acc || !acc_n || !ls || !is ||
         !n_dumps || !carr_phase || !carr_step || !code_phase || !code_step)
         return ORC_EINVAL;
     int8_t code[ORC_CODE_LEN], lc[ORC_LUT_SIZE], ls8[ORC_LUT_SIZE];
@@ -622,7 +633,7 @@ int orc_track(int fmt, const uint8_t* buf, uint64_t n_samples, int prn, int int_
         int xi, xq;
         orc_sample(fmt, buf, n, &xi, &xq);
         int64_t wi, wq;
-        if (fmt == ORC_I8_IQ) {
+        if (orc_is_complex(fmt)) {
             wi = (int64_t)xi * c + (int64_t)xq * s;
             wq = (int64_t)xq * c - (int64_t)xi * s;
         } else {

@@ -12,7 +12,7 @@ import subprocess
 
 import numpy as np
 
-I8_REAL, I8_IQ, I2_REAL = 0, 1, 2
+I8_REAL, I8_IQ, I2_REAL, I2_IQ = 0, 1, 2, 3
 ERANGE, ENOSPC = -4, -7
 TWO32 = 1 << 32
 

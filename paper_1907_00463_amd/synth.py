@@ -32,8 +32,8 @@ import numpy as np
 
 F_L1 = 1575.42e6
 CHIP_RATE = 1.023e6
-I8_REAL, I8_IQ, I2_REAL = 0, 1, 2
-FMT_NAMES = {I8_REAL: "i8_real", I8_IQ: "i8_iq", I2_REAL: "i2_real"}
+I8_REAL, I8_IQ, I2_REAL, I2_IQ = 0, 1, 2, 3
+FMT_NAMES = {I8_REAL: "i8_real", I8_IQ: "i8_iq", I2_REAL: "i2_real", I2_IQ: "i2_iq"}
 
 # G2 delay in chips for PRN 1..32 (IS-GPS-200, Table 3-Ia, "G2 delay" column).
 _G2_DELAY = [5, 6, 7, 8, 17, 18, 139, 140, 141, 251, 252, 254, 255, 256, 257, 258,
@@ -124,11 +124,14 @@ def synth_samples(st: Stream, rng: np.random.Generator, chunk: int = 1 << 20,
     so the result does not depend on the thread count."""
     from concurrent.futures import ThreadPoolExecutor
 
-    complex_ = st.fmt == I8_IQ
+    complex_ = st.fmt in (I8_IQ, I2_IQ)
     codes = {s.prn: ca_chips(s.prn).astype(np.float64) for s in st.sats}
     if st.fmt == I2_REAL:
         assert st.n % 4 == 0
         out = np.empty(st.n // 4, np.uint8)
+    elif st.fmt == I2_IQ:
+        assert st.n % 2 == 0
+        out = np.empty(st.n // 2, np.uint8)
     elif complex_:
         out = np.empty(2 * st.n, np.uint8)
     else:
@@ -148,6 +151,15 @@ def synth_samples(st: Stream, rng: np.random.Generator, chunk: int = 1 << 20,
             if st.fmt == I2_REAL:
                 q = ((x >= -1.0).astype(np.uint8) + (x >= 0.0) + (x >= 1.0)).reshape(-1, 4)
                 out[c0 // 4: (c0 + m) // 4] = q[:, 0] | (q[:, 1] << 2) | (q[:, 2] << 4) | (q[:, 3] << 6)
+            elif st.fmt == I2_IQ:
+                # each component against 0 and +-1 sigma (sigma = sqrt(1/2)),
+                # packed as the interleaved stream I0 Q0 I1 Q1 of value codes
+                t = math.sqrt(0.5)
+                comp = np.empty(2 * m)
+                comp[0::2] = x.real
+                comp[1::2] = x.imag
+                q = ((comp >= -t).astype(np.uint8) + (comp >= 0.0) + (comp >= t)).reshape(-1, 4)
+                out[c0 // 2: (c0 + m) // 2] = q[:, 0] | (q[:, 1] << 2) | (q[:, 2] << 4) | (q[:, 3] << 6)
             elif complex_:
                 sc = 8.0 / math.sqrt(0.5)
                 inter = np.empty(2 * m, np.int8)
@@ -244,6 +256,44 @@ def workload_paper(seconds: float = 10.0, seed: int = 1010):
     sats = [make_sat(rng, fs, n, int(prns[i]), float(dop[i]), float(p0[i]), float(cn0[i]))
             for i in range(12)]
     st = Stream(fs, if_hz, I8_IQ, n, sats, seed)
+    return st, [channel_for(s, if_hz) for s in sats], rng
+
+
+def workload_iq2(seconds: float = 10.0, seed: int = 1011):
+    """2-bit complex baseband (I then Q codes interleaved, two samples per
+    byte) at fs 8.184 MHz from a zero-IF front end, 12 satellites, 1 ms
+    integrations; PRNs, Dopplers ~ U(-5, 5) kHz, code phases and C/N0 ~
+    U(35, 50) dB-Hz drawn as for the 12-channel workload."""
+    rng = np.random.default_rng(seed)
+    fs, if_hz = 8.184e6, 0.0
+    n = int(round(seconds * fs))
+    n -= n % 4
+    prns = rng.choice(np.arange(1, 33), size=12, replace=False)
+    dop = rng.uniform(-5000.0, 5000.0, size=12)
+    p0 = rng.uniform(0.0, 1023.0, size=12)
+    cn0 = rng.uniform(35.0, 50.0, size=12)
+    sats = [make_sat(rng, fs, n, int(prns[i]), float(dop[i]), float(p0[i]), float(cn0[i]))
+            for i in range(12)]
+    st = Stream(fs, if_hz, I2_IQ, n, sats, seed)
+    return st, [channel_for(s, if_hz) for s in sats], rng
+
+
+def workload_if_recording(seconds: float = 10.0, seed: int = 1012):
+    """A recording of the GN3S kind (offline mode's IF files): real samples
+    at fs 16.3676 MHz with IF 4.1304 MHz, stored one int8 per sample, 12
+    satellites, 1 ms integrations.  At 16.0 samples per chip less a little,
+    the half chips are not a whole number of samples long."""
+    rng = np.random.default_rng(seed)
+    fs, if_hz = 16.3676e6, 4.1304e6
+    n = int(round(seconds * fs))
+    n -= n % 4
+    prns = rng.choice(np.arange(1, 33), size=12, replace=False)
+    dop = rng.uniform(-5000.0, 5000.0, size=12)
+    p0 = rng.uniform(0.0, 1023.0, size=12)
+    cn0 = rng.uniform(35.0, 50.0, size=12)
+    sats = [make_sat(rng, fs, n, int(prns[i]), float(dop[i]), float(p0[i]), float(cn0[i]))
+            for i in range(12)]
+    st = Stream(fs, if_hz, I8_REAL, n, sats, seed)
     return st, [channel_for(s, if_hz) for s in sats], rng
 
 

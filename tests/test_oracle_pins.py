@@ -152,8 +152,17 @@ def _fresh(carr_phase, carr_step, code_phase, code_step, K):
 
 
 def _rand_buf(rng, fmt, n):
-    nb = {0: n, 1: 2 * n, 2: (n + 3) // 4}[fmt]
+    nb = {0: n, 1: 2 * n, 2: (n + 3) // 4, 3: (n + 1) // 2}[fmt]
     return rng.integers(0, 256, size=nb, dtype=np.uint8)
+
+
+def _i2iq_as_i8iq(buf, n):
+    """A 2-bit complex block rewritten as int8 complex: the interleaved
+    stream I0 Q0 I1 Q1 ... of 2-bit value codes (four per byte, lowest bit
+    pair first), each code c as the int8 2c - 3."""
+    b = np.asarray(buf, np.uint8)[: (n + 1) // 2].astype(np.int64)
+    codes = np.stack([(b >> s) & 3 for s in (0, 2, 4, 6)], axis=1).reshape(-1)[: 2 * n]
+    return (2 * codes - 3).astype(np.int8).view(np.uint8)
 
 
 # ---------------------------------------------------------------- correlator
@@ -186,7 +195,74 @@ def test_brute_force_matches_oracle(seed):
     assert st.carr_phase == bcp and st.code_phase == bkp
 
 
-@pytest.mark.parametrize("fmt", [0, 1, 2])
+@pytest.mark.parametrize("seed", range(4))
+def test_brute_force_matches_oracle_i2iq(seed):
+    # 2-bit complex: the matrix-form brute force unpacks through numpy's bit
+    # unpacking, the oracle through shifts of each byte
+    rng = np.random.default_rng(500 + seed)
+    n = int(rng.integers(1, 160))
+    T = int(rng.integers(1, 3))
+    W = T * 1023 * TWO32
+    code_step = int(rng.integers(TWO32 // 20, TWO32 // 2))
+    code_phase = int(W - rng.integers(0, n * code_step + 1)) % W
+    carr_phase = int(rng.integers(0, TWO32))
+    carr_step = int(rng.integers(0, TWO32))
+    K = int(rng.integers(1, 7))
+    taps = rng.integers(-3 * TWO32, 3 * TWO32, size=K, dtype=np.int64)
+    prn = int(rng.integers(1, 33))
+    buf = _rand_buf(rng, 3, n)
+    lc, ls = oracle.lut()
+    bd, bn, bopen, bopen_n, bcp, bkp = brute.correlate(3, buf, n, oracle.ca_code(prn), taps, T,
+                                                       carr_phase, carr_step, code_phase,
+                                                       code_step, lc, ls)
+    st = _fresh(carr_phase, carr_step, code_phase, code_step, K)
+    od, on = oracle.correlate_lut(3, buf, n, prn, taps, T, st)
+    assert np.array_equal(od, bd) and np.array_equal(on, bn)
+    assert np.array_equal(st.acc.reshape(K, 2), bopen) and st.acc_n == bopen_n
+    assert st.carr_phase == bcp and st.code_phase == bkp
+
+
+@pytest.mark.parametrize("f64", [False, True])
+def test_i2iq_equals_i8iq_on_expanded_stream(f64):
+    # the same complex values given as 2-bit codes and as int8 give the same
+    # dumps, open dump and NCO words (integer and FP64 carrier)
+    rng = np.random.default_rng(520 + f64)
+    n = 60001
+    buf2 = _rand_buf(rng, 3, n)
+    buf8 = _i2iq_as_i8iq(buf2, n)
+    assert buf8.size == 2 * n and set(np.unique(buf8.view(np.int8))) <= {-3, -1, 1, 3}
+    for T, taps in ((1, oracle.EPL_TAPS_Q32), (4, np.array([5 << 27, -(3 << 29)], np.int64))):
+        a = _fresh(0x12345678, 0x3F00ABCD, 700 * TWO32 + 99, TWO32 // 7, len(taps))
+        a.carr_phase_f, a.carr_freq_f = 0.3125, 0.2471
+        b = a.copy()
+        if f64:
+            da, na = oracle.correlate_f64(3, buf2, n, 9, taps, T, a)
+            db, nb = oracle.correlate_f64(1, buf8, n, 9, taps, T, b)
+        else:
+            da, na = oracle.correlate_lut(3, buf2, n, 9, taps, T, a)
+            db, nb = oracle.correlate_lut(1, buf8, n, 9, taps, T, b)
+        assert len(da) >= 2
+        assert np.array_equal(da, db) and np.array_equal(na, nb)
+        assert np.array_equal(a.acc, b.acc) and a.acc_n == b.acc_n
+        assert a.code_phase == b.code_phase and a.carr_phase == b.carr_phase
+
+
+def test_i2iq_bit_layout_by_hand():
+    # byte 0b11_10_01_00 holds I0 = code 0, Q0 = code 1, I1 = code 2, Q1 =
+    # code 3: samples (-3, -1) and (+1, +3).  With a carrier of phase 0 and
+    # step 0 (table entry 0: c = cL[0], s = sL[0]) and one prompt tap on a
+    # zero code phase, each sample adds (xI c + xQ s, xQ c - xI s) * C[0].
+    lc, ls = oracle.lut()
+    c, s = int(lc[0]), int(ls[0])
+    r = int(oracle.ca_code(3)[0])
+    st = _fresh(0, 0, 0, 1 << 28, 1)
+    oracle.correlate_lut(3, np.array([0b11100100], np.uint8), 2, 3, np.array([0], np.int64), 1, st)
+    want_i = ((-3) * c + (-1) * s + 1 * c + 3 * s) * r
+    want_q = ((-1) * c - (-3) * s + 3 * c - 1 * s) * r
+    assert list(st.acc) == [want_i, want_q] and st.acc_n == 2
+
+
+@pytest.mark.parametrize("fmt", [0, 1, 2, 3])
 def test_chunking_invariance(fmt):
     rng = np.random.default_rng(100 + fmt)
     n = 40000
@@ -201,7 +277,7 @@ def test_chunking_invariance(fmt):
     st = st0.copy()
     ds, ns = [], []
     for a, b in zip(cuts[:-1], cuts[1:]):
-        nb = {0: (a, b), 1: (2 * a, 2 * b), 2: (a // 4, b // 4)}[fmt]
+        nb = {0: (a, b), 1: (2 * a, 2 * b), 2: (a // 4, b // 4), 3: (a // 2, b // 2)}[fmt]
         d, dn = oracle.correlate_lut(fmt, buf[nb[0]:nb[1]], b - a, 5, oracle.EPL_TAPS_Q32, T, st)
         ds.append(d)
         ns.append(dn)

@@ -36,6 +36,23 @@ def test_two_bit_packing_and_levels():
     assert abs(frac[0] - frac[3]) < 0.01
 
 
+def test_two_bit_complex_packing_and_levels():
+    st, chans, rng = synth.workload_iq2(seconds=0.01)
+    buf = synth.synth_samples(st, rng)
+    assert st.fmt == synth.I2_IQ and buf.size == st.n // 2
+    codes = np.stack([(buf >> (2 * j)) & 3 for j in range(4)], axis=1).ravel()
+    # each component is noise of variance 1/2 plus half of the satellites'
+    # power (complex amplitude sqrt(C/N0 / fs) each), against 0 and
+    # +-sqrt(1/2): P(|x| > sqrt(1/2)) = erfc(sqrt(1/2) / (sqrt(2) sigma))
+    p_sig = sum(10 ** (s.cn0_dbhz / 10) / st.fs for s in st.sats)
+    sigma = math.sqrt(0.5 + p_sig / 2)
+    want = math.erfc(math.sqrt(0.5) / (math.sqrt(2) * sigma))
+    for comp in (codes[0::2], codes[1::2]):  # I codes, Q codes
+        frac = np.bincount(comp, minlength=4) / comp.size
+        assert abs(frac[0] + frac[3] - want) < 0.006
+        assert abs(frac[0] - frac[3]) < 0.01
+
+
 def test_cn0_recovered_from_prompt_dumps():
     # single-channel workload: 45 dB-Hz, 1000 one-millisecond dumps
     st, chans, rng = synth.workload_single_channel(seconds=1.0)
