@@ -91,6 +91,14 @@ WORKLOADS = {
         describe="12 channels, complex int8 (I then Q), fs 5 MHz, IF 0, %g s, 1 ms dumps, E/P/L "
                  "at +-1/2 chip (the paper's offline configuration)", seconds=10.0, ops=10,
         fmt_name="i8_iq", cpu_seconds=10.0),
+    "iq2": dict(
+        describe="12 channels, 2-bit complex (I then Q codes), fs 8.184 MHz, IF 0, %g s, 1 ms "
+                 "dumps, E/P/L at +-1/2 chip", seconds=10.0, ops=10, fmt_name="i2_iq",
+        cpu_seconds=10.0),
+    "if_recording": dict(
+        describe="12 channels, GN3S-style IF recording: int8 real, fs 16.3676 MHz, IF 4.1304 MHz, "
+                 "%g s, 1 ms dumps, E/P/L at +-1/2 chip", seconds=10.0, ops=6,
+        fmt_name="i8_real", cpu_seconds=10.0),
     "multicorrelator": dict(
         describe="256 channels x 128 taps (-2 + k/32 chips), complex int8, fs 20.46 MHz, IF 0, "
                  "%g s, 1 ms dumps", seconds=2.0, ops=14, fmt_name="i8_iq",
@@ -117,7 +125,8 @@ def build_inputs(workload: str, seconds: float):
     from paper_1907_00463_amd import synth
 
     make = {"twelve": synth.workload_twelve_channels, "single": synth.workload_single_channel,
-            "paper": synth.workload_paper,
+            "paper": synth.workload_paper, "iq2": synth.workload_iq2,
+            "if_recording": synth.workload_if_recording,
             "multicorrelator": synth.workload_multicorrelator}[workload]
     st, chans, rng = make(seconds=seconds)
     buf = synth.synth_samples(st, rng)

@@ -39,7 +39,10 @@
  *     dumps.
  *   - Sample formats: GC_I8_REAL one int8 per sample; GC_I8_IQ int8 I then
  *     Q; GC_I2_REAL four samples per byte, sample j in bits [2j, 2j+1],
- *     value codes 0,1,2,3 -> -3,-1,+1,+3.
+ *     value codes 0,1,2,3 -> -3,-1,+1,+3; GC_I2_IQ the same packing of the
+ *     interleaved stream I0 Q0 I1 Q1 ..., two samples per byte, sample j's
+ *     I in bits [4j, 4j+1] and its Q in bits [4j+2, 4j+3] (offline mode's
+ *     recordings of I or I-Q samples, Sec. 3).
  *   - Integer path results are exact int32; a channel whose dump could
  *     leave int32 is refused (GC_ERANGE), never wrapped.
  *
@@ -77,7 +80,7 @@ typedef enum {
     GC_ENOSPC = -7   /* more dumps close in this block than max_dumps */
 } gc_status;
 
-typedef enum { GC_I8_REAL = 0, GC_I8_IQ = 1, GC_I2_REAL = 2 } gc_format;
+typedef enum { GC_I8_REAL = 0, GC_I8_IQ = 1, GC_I2_REAL = 2, GC_I2_IQ = 3 } gc_format;
 
 typedef enum {
     GC_CARRIER_LUT = 0, /* integer NCO + sin/cos table, exact int32 results */
@@ -203,7 +206,8 @@ gc_status gc_plan_info(const gc_plan* plan, int32_t* tap_stride, int32_t* n_chan
 /* Correlate one block of samples for every channel of the plan.
  *
  *   samples   device, the block in the plan's format; n_samples samples
- *             (n_samples bytes, 2*n_samples bytes, or ceil(n_samples/4) bytes)
+ *             (n_samples bytes, 2*n_samples bytes, ceil(n_samples/4) bytes or
+ *             ceil(n_samples/2) bytes)
  *   n_samples 0 .. 2^31-1
  *   state     device, gc_chan_state[n_chan], read and updated in place:
  *             NCO phases advance by n_samples, the open dump is carried
@@ -216,7 +220,7 @@ gc_status gc_plan_info(const gc_plan* plan, int32_t* tap_stride, int32_t* n_chan
  *             (state out of range: code_phase >= W or code_step not in
  *             1..2^31-1), GC_ENOSPC (more than max_dumps would close),
  *             GC_ERANGE (int32 bound: (floor((W-1)/code_step)+1) * max|w| must
- *             stay below 2^31, max|w| = 24*max|x| real, 34*128 complex);
+ *             stay below 2^31, max|w| = 24*max|x| real, 34*max|x| complex);
  *             a refused channel's state and outputs are left untouched and
  *             its n_dumps is 0
  *   max_dumps rows per channel in out and dump_n
@@ -348,7 +352,8 @@ gc_status gc_loop_init(double carr_hz, double code_cps, gc_loop_state* out);
  * Per-channel status: GC_OK; GC_EINVAL (not an E/P/L channel, phase outside
  * the window); GC_ERANGE (a code step, given or set by the loops, outside
  * 1 .. 2^31-1 or letting a dump leave int32); GC_ENOSPC.  A channel with an
- * error keeps its state and loop state.  The plan must use GC_CARRIER_LUT.
+ * error keeps its state and loop state.  The plan must use GC_CARRIER_LUT
+ * and a format other than GC_I2_IQ (GC_EINVAL).
  * Errors returned directly: GC_EINVAL, GC_EDEVICE. */
 gc_status gc_track(gc_plan* plan, const void* samples, uint64_t n_samples,
                    const gc_loop_params* params, gc_chan_state* state, gc_loop_state* loop,
@@ -447,7 +452,7 @@ typedef struct {
 
 /* A search plan: validates the bounds, computes the bin steps and allocates
  * the device scratch (gc_acq_info reports its size).
- *   fmt                  sample format of the buffer
+ *   fmt                  sample format of the buffer (GC_I2_IQ is refused)
  *   samples_per_chip     R, 1 .. GC_ACQ_MAX_SPC
  *   prns                 host, n_prn PRN numbers 1..32 (repeats allowed)
  *   coherent_periods     Mc, 1 .. 1000

@@ -73,12 +73,14 @@ uint32_t tiles(uint64_t n, uint32_t tile) { return (uint32_t)((n + tile - 1) / t
 // Work items of the periodic kernel: per receiver, groups of at most kGroup
 // channels times chunks of `chunk` tiles.
 constexpr int kGroup = 16;
+// the periodic kernel takes real input only (complex receivers get no items)
+bool periodic_format(int fmt) { return fmt == GC_I8_REAL || fmt == GC_I2_REAL; }
 uint32_t count_pitems(const gc_batch* b, int chunk) {
     const uint32_t tile = (uint32_t)gc::pbin_tile_samples();
     uint64_t k = 0;
     for (int r = 0; r < b->n_rx; ++r) {
         const int nc = b->chan_end[(size_t)r] - b->chan_begin[(size_t)r];
-        if (nc <= 0) continue;
+        if (nc <= 0 || !periodic_format(b->rx[(size_t)r].fmt)) continue;
         k += (uint64_t)((nc + kGroup - 1) / kGroup) *
              ((tiles(b->rx[(size_t)r].n_samples, tile) + chunk - 1) / chunk);
     }
@@ -92,6 +94,7 @@ hipError_t upload_pitems(gc_batch* b, int chunk) {
     std::vector<gc::PbinItem> h;
     h.reserve(count_pitems(b, chunk));
     for (int r = 0; r < b->n_rx; ++r) {
+        if (!periodic_format(b->rx[(size_t)r].fmt)) continue;
         const int cb = b->chan_begin[(size_t)r], nc = b->chan_end[(size_t)r] - cb;
         const uint32_t nt = tiles(b->rx[(size_t)r].n_samples, tile);
         for (int first = 0; first < nc; first += kGroup)
@@ -161,7 +164,8 @@ gc_status gc_batch_create(gc_ctx* ctx, const gc_rx_desc* rx, int32_t n_rx,
         return GC_EINVAL;
     for (int r = 0; r < n_rx; ++r) {
         const gc_rx_desc& d = rx[r];
-        if ((d.fmt != GC_I8_REAL && d.fmt != GC_I8_IQ && d.fmt != GC_I2_REAL) || d.reserved != 0 ||
+        if ((d.fmt != GC_I8_REAL && d.fmt != GC_I8_IQ && d.fmt != GC_I2_REAL && d.fmt != GC_I2_IQ) ||
+            d.reserved != 0 ||
             d.n_samples >= (1ull << 31) || (d.n_samples > 0 && !d.samples))
             return GC_EINVAL;
     }

@@ -219,6 +219,7 @@ __global__ __launch_bounds__(64) void k_setup(const DevChan* __restrict__ chans,
             const uint64_t nmax = (m.window - 1) / m.dp + 1;
             const uint64_t maxw = fmt == GC_I8_REAL ? 128ull * GC_LUT_AMP
                                 : fmt == GC_I8_IQ   ? 128ull * kLutAbsSumMax
+                                : fmt == GC_I2_IQ   ? 3ull * kLutAbsSumMax
                                                     : 3ull * GC_LUT_AMP;
             if (carrier == GC_CARRIER_LUT && nmax * maxw > 2147483647ull) s = GC_ERANGE;
             else if (mc > max_dumps) s = GC_ENOSPC;
@@ -239,7 +240,7 @@ __global__ __launch_bounds__(64) void k_setup(const DevChan* __restrict__ chans,
             m.path = kPathDirect;
             m.bin_len = 0;
             const bool epl_ok = c.epl && carrier == GC_CARRIER_LUT && m.c_full1 > m.c_full0;
-            if (epl_ok && (allow & kAllowPeriodic) && fmt != GC_I8_IQ) {
+            if (epl_ok && (allow & kAllowPeriodic) && !fmt_complex(fmt)) {
                 m.bin_len = periodic_bin_len(fmt, m.dp);
                 if (m.bin_len) m.path = kPathPeriodic;
             }

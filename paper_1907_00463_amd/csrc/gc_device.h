@@ -43,6 +43,9 @@ __device__ __forceinline__ int8_t ca_chip(const uint32_t* tables, int d, int i) 
     return (b1 ^ b2) ? (int8_t)-1 : (int8_t)1;
 }
 
+// Complex sample formats (the wipe-off multiplies xI + j xQ by exp(-j*theta)).
+constexpr bool fmt_complex(int fmt) { return fmt == GC_I8_IQ || fmt == GC_I2_IQ; }
+
 // Unpacked sample: real formats leave q = 0.
 template <int FMT>
 __device__ __forceinline__ void load_sample(const uint8_t* __restrict__ s, uint64_t n, int& i, int& q) {
@@ -53,10 +56,14 @@ __device__ __forceinline__ void load_sample(const uint8_t* __restrict__ s, uint6
         const uint16_t v = *reinterpret_cast<const uint16_t*>(s + 2 * n);
         i = (int)(int8_t)(v & 0xFF);
         q = (int)(int8_t)(v >> 8);
-    } else {
+    } else if constexpr (FMT == GC_I2_REAL) {
         const int code = (s[n >> 2] >> (2 * (n & 3))) & 3;
         i = 2 * code - 3;
         q = 0;
+    } else {  // 2-bit complex: I then Q code of sample n in the nibble n & 1
+        const int nib = (s[n >> 1] >> (4 * (n & 1))) & 15;
+        i = 2 * (nib & 3) - 3;
+        q = 2 * (nib >> 2) - 3;
     }
 }
 
@@ -78,7 +85,7 @@ __device__ __forceinline__ void carrier_f32(float ph, float& c, float& s) {
 // Wipe-off by exp(-j*theta): real (x*c, -x*s); complex (xi*c + xq*s, xq*c - xi*s).
 template <int FMT, typename T>
 __device__ __forceinline__ void wipe(T xi, T xq, T c, T s, T& wi, T& wq) {
-    if constexpr (FMT == GC_I8_IQ) {
+    if constexpr (fmt_complex(FMT)) {
         wi = xi * c + xq * s;
         wq = xq * c - xi * s;
     } else {
@@ -91,7 +98,7 @@ __device__ __forceinline__ void wipe(T xi, T xq, T c, T s, T& wi, T& wq) {
 // input), and for complex input each of the two planes (xI, xQ)*c and
 // (xQ, xI)*s that the kernels sum separately.
 __device__ __forceinline__ uint64_t bin_plane_max(int fmt) {
-    return fmt == GC_I2_REAL ? 3ull * GC_LUT_AMP : 128ull * GC_LUT_AMP;
+    return (fmt == GC_I2_REAL || fmt == GC_I2_IQ) ? 3ull * GC_LUT_AMP : 128ull * GC_LUT_AMP;
 }
 
 // Binned E/P/L form: tile geometry and the per-channel condition on the code

@@ -212,6 +212,10 @@ struct EplAcc<GC_I8_IQ> {
     }
 };
 
+// 2-bit complex input: staged like int8 complex, the same sums.
+template <>
+struct EplAcc<GC_I2_IQ> : EplAcc<GC_I8_IQ> {};
+
 // Lane-private atomics of one run's sums (dump boundary inside a run).
 template <int FMT>
 __device__ __forceinline__ void flush_lane(const EplAcc<FMT>& acc, const Dest& d, uint32_t w,
@@ -256,7 +260,7 @@ __device__ __forceinline__ void epl_run(const void* __restrict__ sx, const uint8
             bool lt = e < r;
             uint32_t len = q + (lt ? 1u : 0u);
             e = lt ? e + dp - r : e - r;
-            if constexpr (FMT == GC_I8_IQ) {
+            if constexpr (fmt_complex(FMT)) {
                 short2_t a, b;
                 bin_sum_iq<Q>(static_cast<const uint32_t*>(sx) + nb, phi, dphi, lane4, lut, len,
                               a, b);
@@ -272,7 +276,7 @@ __device__ __forceinline__ void epl_run(const void* __restrict__ sx, const uint8
             lt = e < r;
             len = q + (lt ? 1u : 0u);
             e = lt ? e + dp - r : e - r;
-            if constexpr (FMT == GC_I8_IQ) {
+            if constexpr (fmt_complex(FMT)) {
                 short2_t a, b;
                 bin_sum_iq<Q>(static_cast<const uint32_t*>(sx) + nb, phi, dphi, lane4, lut, len,
                               a, b);
@@ -336,7 +340,7 @@ __device__ __forceinline__ void direct_range(const void* __restrict__ sx, const 
             int c, s;
             lut_cs(e, c, s);
             int wi, wq;
-            if constexpr (FMT == GC_I8_IQ) {
+            if constexpr (fmt_complex(FMT)) {
                 const uint32_t xw = static_cast<const uint32_t*>(sx)[i];
                 const int xi = (int)(short)(xw & 0xFFFF), xq = (int)(short)(xw >> 16);
                 wipe<GC_I8_IQ, int>(xi, xq, c, s, wi, wq);
@@ -384,6 +388,21 @@ __device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, 
                   ((uint32_t)(uint16_t)(int16_t)(int8_t)((v >> 8) & 0xFF) << 16);
             o.y = ((uint32_t)(uint16_t)(int16_t)(int8_t)((v >> 16) & 0xFF)) |
                   ((uint32_t)(uint16_t)(int16_t)(int8_t)(v >> 24) << 16);
+            dst[i] = o;
+        }
+    } else if constexpr (FMT == GC_I2_IQ) {
+        // t0 is even: byte t0/2 + i holds tile samples 2i and 2i+1, each a
+        // nibble of I then Q codes; samples past the block read as zero
+        for (int i = threadIdx.x; i < kXSamples / 2; i += kThreads) {
+            const uint64_t smp = t0 + 2ull * i;
+            const uint32_t v = smp < n ? samples[smp >> 1] : 0u;
+            const auto iq = [](uint32_t nib) {
+                return (uint32_t)(uint16_t)(int16_t)(2 * (int)(nib & 3u) - 3) |
+                       ((uint32_t)(uint16_t)(int16_t)(2 * (int)((nib >> 2) & 3u) - 3) << 16);
+            };
+            uint2 o;
+            o.x = smp < n ? iq(v & 15u) : 0u;
+            o.y = smp + 1 < n ? iq(v >> 4) : 0u;
             dst[i] = o;
         }
     } else if constexpr (FMT == GC_I2_REAL) {
@@ -516,9 +535,9 @@ __device__ __forceinline__ void tile_pass(const uint8_t* __restrict__ samples, u
                                           gc_chan_state* __restrict__ state,
                                           int32_t* __restrict__ out, int tap_stride,
                                           uint32_t max_dumps, const uint32_t* __restrict__ tables) {
-    constexpr int kParts = FMT == GC_I8_IQ ? 2 : 1;
+    constexpr int kParts = fmt_complex(FMT) ? 2 : 1;
     constexpr int kPart = SH::kTile / kParts;
-    constexpr int kStaged = FMT == GC_I8_IQ ? SH::kXSamplesIQ : SH::kXSamples;
+    constexpr int kStaged = fmt_complex(FMT) ? SH::kXSamplesIQ : SH::kXSamples;
 #pragma unroll
     for (int h = 0; h < kParts; ++h) {
         const uint64_t a = t0 + (uint64_t)h * kPart;
@@ -602,6 +621,9 @@ __global__ __launch_bounds__(SH::kThreads) void k_epl_batch(
         else if (R.fmt == GC_I8_IQ)
             tile_pass<GC_I8_IQ, SH>(R.samples, R.n, t0, s_x, s_lds, R.chan_begin, R.chan_end,
                                     chans, metas, state, out, tap_stride, max_dumps, tables);
+        else if (R.fmt == GC_I2_IQ)
+            tile_pass<GC_I2_IQ, SH>(R.samples, R.n, t0, s_x, s_lds, R.chan_begin, R.chan_end,
+                                    chans, metas, state, out, tap_stride, max_dumps, tables);
         else
             tile_pass<GC_I8_REAL, SH>(R.samples, R.n, t0, s_x, s_lds, R.chan_begin, R.chan_end,
                                       chans, metas, state, out, tap_stride, max_dumps, tables);
@@ -679,6 +701,9 @@ hipError_t launch_epl(const uint8_t* samples, uint64_t n, int fmt, const DevChan
                            meta, state, out, tap_stride, max_dumps, tables, n_chan, n_tiles);
     } else if (fmt == GC_I8_REAL) {
         hipLaunchKernelGGL((k_epl<GC_I8_REAL>), dim3(g), dim3(SH::kThreads), 0, s, samples, n, chans,
+                           meta, state, out, tap_stride, max_dumps, tables, n_chan, n_tiles);
+    } else if (fmt == GC_I2_IQ) {
+        hipLaunchKernelGGL((k_epl<GC_I2_IQ>), dim3(g), dim3(SH::kThreads), 0, s, samples, n, chans,
                            meta, state, out, tap_stride, max_dumps, tables, n_chan, n_tiles);
     } else if (fmt == GC_I8_IQ) {
         hipLaunchKernelGGL((k_epl<GC_I8_IQ>), dim3(g), dim3(SH::kThreads), 0, s, samples, n, chans,

@@ -197,9 +197,11 @@ hipError_t launch_generic(const uint8_t* samples, uint64_t n, int fmt, int carri
     GC_CASE(GC_I8_REAL, GC_CARRIER_LUT)
     GC_CASE(GC_I8_IQ, GC_CARRIER_LUT)
     GC_CASE(GC_I2_REAL, GC_CARRIER_LUT)
+    GC_CASE(GC_I2_IQ, GC_CARRIER_LUT)
     GC_CASE(GC_I8_REAL, GC_CARRIER_F32)
     GC_CASE(GC_I8_IQ, GC_CARRIER_F32)
     GC_CASE(GC_I2_REAL, GC_CARRIER_F32)
+    GC_CASE(GC_I2_IQ, GC_CARRIER_F32)
 #undef GC_CASE
     return hipErrorInvalidValue;
 }

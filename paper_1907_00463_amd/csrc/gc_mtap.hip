@@ -199,7 +199,8 @@ __device__ __forceinline__ void chunk_next(Chunk& k, uint64_t span, uint64_t dp,
 // Tile samples [t0, t0 + kXSamples) as two int16 pairs each: (xI, xQ) and
 // (xQ, -xI) (real input: (x, 0) and (0, -x)); zero past the block.  Each
 // thread takes units of 8 samples: one 16-byte (complex int8), 8-byte (real
-// int8) or 2-byte (2-bit) load, four 16-byte LDS stores.
+// int8), 4-byte (2-bit complex) or 2-byte (2-bit real) load, four 16-byte
+// LDS stores.
 template <int FMT>
 __device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, uint64_t n,
                                            uint64_t t0, uint8_t* lds, int nthreads) {
@@ -225,6 +226,22 @@ __device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, 
                 const uint32_t v = w[k / 2] >> (16 * (k % 2));
                 xi[k] = (int)(int8_t)(v & 0xFF);
                 xq[k] = (int)(int8_t)((v >> 8) & 0xFF);
+            }
+        } else if constexpr (FMT == GC_I2_IQ) {
+            // two samples per byte, I then Q code in each nibble
+            const uint8_t* src = samples + (t0 + s0) / 2;
+            uint32_t w = 0;
+            if (whole) {
+                w = *reinterpret_cast<const uint32_t*>(src);
+            } else {
+                for (uint32_t b = 0; b < 4; ++b)
+                    if (s0 + 2 * b < avail) w |= (uint32_t)src[b] << (8 * b);
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const uint32_t nib = (w >> (4 * k)) & 15u;
+                xi[k] = 2 * (int)(nib & 3u) - 3;
+                xq[k] = 2 * (int)(nib >> 2) - 3;
             }
         } else if constexpr (FMT == GC_I8_REAL) {
             const uint8_t* src = samples + t0 + s0;
@@ -630,6 +647,9 @@ hipError_t launch_mtap(const uint8_t* samples, uint64_t n, int fmt, const DevCha
     else if (fmt == GC_I8_REAL)
         launch_one<GC_I8_REAL>(samples, n, chans, meta, state, n_chan, out, tap_stride, max_dumps,
                                tables, grid, s);
+    else if (fmt == GC_I2_IQ)
+        launch_one<GC_I2_IQ>(samples, n, chans, meta, state, n_chan, out, tap_stride, max_dumps,
+                             tables, grid, s);
     else if (fmt == GC_I2_REAL)
         launch_one<GC_I2_REAL>(samples, n, chans, meta, state, n_chan, out, tap_stride, max_dumps,
                                tables, grid, s);

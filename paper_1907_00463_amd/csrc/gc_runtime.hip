@@ -298,7 +298,8 @@ gc_status gc_plan_create(gc_ctx* ctx, gc_format fmt, gc_carrier carrier, const g
     if (!ctx || !cfg || !out) return GC_EINVAL;
     *out = nullptr;
     if (n_chan < 1 || n_chan > GC_MAX_CHANNELS) return GC_EINVAL;
-    if (fmt != GC_I8_REAL && fmt != GC_I8_IQ && fmt != GC_I2_REAL) return GC_EINVAL;
+    if (fmt != GC_I8_REAL && fmt != GC_I8_IQ && fmt != GC_I2_REAL && fmt != GC_I2_IQ)
+        return GC_EINVAL;
     if (carrier != GC_CARRIER_LUT && carrier != GC_CARRIER_F32) return GC_EINVAL;
     std::vector<gc::DevChan> h((size_t)n_chan);
     int max_taps = 0;
@@ -428,7 +429,7 @@ gc_status gc_track(gc_plan* plan, const void* samples, uint64_t n_samples,
         return GC_EINVAL;
     if (n_samples >= (1ull << 31) || max_dumps == 0 || (n_samples > 0 && !samples))
         return GC_EINVAL;
-    if (plan->carrier != GC_CARRIER_LUT) return GC_EINVAL;
+    if (plan->carrier != GC_CARRIER_LUT || plan->fmt == GC_I2_IQ) return GC_EINVAL;
     const gc_loop_params& q = *params;
     if (!(q.fs_hz > 0.0) || !(q.dll_bw_hz > 0.0) || !(q.dll_zeta > 0.0) || !(q.dll_gain > 0.0) ||
         !(q.pll_bw_hz > 0.0) || !(q.pll_zeta > 0.0) || !(q.pll_gain > 0.0) || !(q.fll_bw_hz >= 0.0))
@@ -489,7 +490,7 @@ gc_status gc_correlate(gc_plan* plan, const void* samples, uint64_t n_samples,
     L.carrier = plan->carrier;
     L.n_chan = plan->n_chan;
     L.tap_stride = plan->max_taps;
-    L.periodic = plan->use_epl && (plan->kernels & GC_KERNEL_PERIODIC) && plan->fmt != GC_I8_IQ;
+    L.periodic = plan->use_epl && (plan->kernels & GC_KERNEL_PERIODIC) && !gc::fmt_complex(plan->fmt);
     L.binned = plan->use_epl && (plan->kernels & GC_KERNEL_BINNED);
     L.mtap = plan->use_mtap && (plan->kernels & GC_KERNEL_MTAP);
     L.grid = plan->epl_grid;
@@ -512,7 +513,8 @@ gc_status gc_correlate_noalloc(gc_ctx* ctx, gc_format fmt, gc_carrier carrier,
                                void* out, uint32_t* dump_n, uint32_t* n_dumps, int32_t* status,
                                uint32_t max_dumps, void* stream) {
     if (!ctx || !cfg || !state || !out || !dump_n || !n_dumps || !status) return GC_EINVAL;
-    if (fmt != GC_I8_REAL && fmt != GC_I8_IQ && fmt != GC_I2_REAL) return GC_EINVAL;
+    if (fmt != GC_I8_REAL && fmt != GC_I8_IQ && fmt != GC_I2_REAL && fmt != GC_I2_IQ)
+        return GC_EINVAL;
     if (carrier != GC_CARRIER_LUT && carrier != GC_CARRIER_F32) return GC_EINVAL;
     if (n_chan < 1 || n_chan > GC_NOALLOC_MAX_CHANNELS) return GC_EINVAL;
     if (tap_stride < 1 || tap_stride > GC_MAX_TAPS) return GC_EINVAL;
@@ -530,7 +532,7 @@ gc_status gc_correlate_noalloc(gc_ctx* ctx, gc_format fmt, gc_carrier carrier,
     L.carrier = carrier;
     L.n_chan = n_chan;
     L.tap_stride = tap_stride;
-    L.periodic = use_epl && fmt != GC_I8_IQ;
+    L.periodic = use_epl && !gc::fmt_complex(fmt);
     L.binned = use_epl;
     L.mtap = carrier == GC_CARRIER_LUT && !use_epl;
     L.grid = ctx->n_cu;

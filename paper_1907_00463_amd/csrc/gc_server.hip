@@ -234,7 +234,8 @@ struct gc_server {
 namespace {
 
 uint64_t sample_bytes(int fmt, uint64_t n) {
-    return fmt == GC_I2_REAL ? (n + 3) / 4 : fmt == GC_I8_IQ ? 2 * n : n;
+    return fmt == GC_I2_REAL ? (n + 3) / 4 : fmt == GC_I2_IQ ? (n + 1) / 2
+         : fmt == GC_I8_IQ ? 2 * n : n;
 }
 
 uint64_t result_bytes(int n_chan, uint32_t max_dumps) {
@@ -531,7 +532,8 @@ gc_status gc_server_create(gc_ctx* ctx, uint64_t hbm_budget_bytes, uint64_t host
 gc_status gc_server_open_rx(gc_server* s, int32_t fmt, const gc_chan_cfg* cfg,
                             const gc_chan_state* state0, int32_t n_chan, int32_t* rx_id) {
     if (!s || !cfg || !state0 || !rx_id || n_chan < 1) return GC_EINVAL;
-    if (fmt != GC_I8_REAL && fmt != GC_I8_IQ && fmt != GC_I2_REAL) return GC_EINVAL;
+    if (fmt != GC_I8_REAL && fmt != GC_I8_IQ && fmt != GC_I2_REAL && fmt != GC_I2_IQ)
+        return GC_EINVAL;
     std::vector<gc::DevChan> h((size_t)n_chan);
     for (int i = 0; i < n_chan; ++i) {
         const gc_status st = gc::fill_devchan(cfg[i], h[(size_t)i]);

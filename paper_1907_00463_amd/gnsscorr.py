@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libgnsscorr.so")
 
 GC_OK, GC_EINVAL, GC_ENOMEM, GC_EDEVICE, GC_ERANGE, GC_EBUSY, GC_EAGAIN, GC_ENOSPC = (
     0, -1, -2, -3, -4, -5, -6, -7)
-GC_I8_REAL, GC_I8_IQ, GC_I2_REAL = 0, 1, 2
+GC_I8_REAL, GC_I8_IQ, GC_I2_REAL, GC_I2_IQ = 0, 1, 2, 3
 GC_CARRIER_LUT, GC_CARRIER_F32 = 0, 1
 GC_KERNEL_PERIODIC, GC_KERNEL_BINNED, GC_KERNEL_MTAP = 1, 2, 4
 GC_SERVER_PLAIN = 1

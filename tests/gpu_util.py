@@ -10,7 +10,7 @@ TWO32 = 1 << 32
 
 
 def block_bytes(fmt: int, n: int) -> int:
-    return {0: n, 1: 2 * n, 2: (n + 3) // 4}[fmt]
+    return {0: n, 1: 2 * n, 2: (n + 3) // 4, 3: (n + 1) // 2}[fmt]
 
 
 def oracle_state(st_rec, K: int, f64: bool = False) -> oracle.OracleState:

@@ -33,7 +33,7 @@ def _receivers(g, seed, n_rx=6):
     rx, cfgs, states, chan_rx = [], [], [], []
     for r in range(n_rx):
         fs = rates[r % 3]
-        fmt = (0, 2, 1)[(r + r // 3) % 3]   # real int8, 2-bit and complex int8
+        fmt = (0, 2, 1, 3)[(r + r // 4) % 4]   # real int8, 2-bit, complex int8, complex 2-bit
         n = int(rng.integers(50_000, 400_000))
         buf = rng.integers(0, 256, size=block_bytes(fmt, n), dtype=np.uint8)
         rx.append((fmt, n, buf))

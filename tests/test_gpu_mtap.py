@@ -46,7 +46,7 @@ def _blocks(rng, fmt, lens):
     return [rng.integers(0, 256, size=block_bytes(fmt, n), dtype=np.uint8) for n in lens]
 
 
-@pytest.mark.parametrize("fmt", [1, 0, 2])
+@pytest.mark.parametrize("fmt", [1, 0, 2, 3])
 def test_128_taps_bit_exact(g, ctx, fmt):
     # 128 taps at -2 + k/32 chips, 20.46 MHz, dumps of 1/4/20 periods, blocks
     # that split chunks and dumps anywhere

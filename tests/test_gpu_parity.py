@@ -13,7 +13,7 @@ from gpu_util import (TWO32, assert_exact, block_bytes, c10_check, run_library, 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-MAXW = {0: 128 * 24, 1: 128 * 34, 2: 3 * 24}
+MAXW = {0: 128 * 24, 1: 128 * 34, 2: 3 * 24, 3: 3 * 34}
 
 
 @pytest.fixture(scope="module")
@@ -63,7 +63,7 @@ def test_code_tables_equal_oracle(g, ctx):
         assert np.array_equal(g.gc_code_table(ctx, prn), oracle.ca_code(prn)), prn
 
 
-@pytest.mark.parametrize("fmt", [0, 1, 2])
+@pytest.mark.parametrize("fmt", [0, 1, 2, 3])
 @pytest.mark.parametrize("seed", range(4))
 def test_random_blocks_bit_exact(g, ctx, fmt, seed):
     rng = np.random.default_rng(1000 * fmt + seed)
@@ -77,7 +77,7 @@ def test_random_blocks_bit_exact(g, ctx, fmt, seed):
     assert_exact(lib, lst, orc, ost, cfgs)
 
 
-@pytest.mark.parametrize("fmt", [0, 1, 2])
+@pytest.mark.parametrize("fmt", [0, 1, 2, 3])
 def test_epl_many_short_dumps_bit_exact(g, ctx, fmt):
     # T = 1, 2 samples per chip: many windows per tile, windows straddling tiles
     rng = np.random.default_rng(77 + fmt)
@@ -181,7 +181,7 @@ def test_single_channel_workload_bit_exact(g, ctx):
     assert_exact(lib, lst, orc, ost, cfgs)
 
 
-@pytest.mark.parametrize("fmt", [0, 1, 2])
+@pytest.mark.parametrize("fmt", [0, 1, 2, 3])
 def test_fp32_carrier_within_tolerance(g, ctx, fmt):
     rng = np.random.default_rng(400 + fmt)
     cfgs, states = _random_channels(g, rng, fmt, 3, taps_kind="epl")
@@ -200,7 +200,7 @@ def test_fp32_carrier_within_tolerance(g, ctx, fmt):
             assert np.array_equal(dump_n[i, :nd], dns[i])
             if nd == 0:
                 continue
-            ex2 = {0: 128 ** 2 / 3, 1: 2 * 128 ** 2 / 3, 2: 5.0}[fmt]  # E|x|^2 of uniform bytes
+            ex2 = {0: 128 ** 2 / 3, 1: 2 * 128 ** 2 / 3, 2: 5.0, 3: 10.0}[fmt]  # E|x|^2 of uniform bytes
             sigma = np.sqrt(dns[i].astype(np.float64) * ex2 / 2)[:, None]
             ok, w = c10_check(out[i, :nd, :3].astype(np.float64), dumps[i], sigma)
             assert ok.all(), w
@@ -285,7 +285,7 @@ KERNEL_SETS = {"default": None, "binned": 2, "direct": 0}
 
 @pytest.mark.parametrize("kernels", list(KERNEL_SETS))
 @pytest.mark.parametrize("fs", [4.092e6, 8.184e6, 16.368e6, 20.46e6, 5e6])
-@pytest.mark.parametrize("fmt", [0, 1, 2])
+@pytest.mark.parametrize("fmt", [0, 1, 2, 3])
 def test_binned_epl_rates_bit_exact(g, ctx, fs, fmt, kernels):
     # E/P/L channels at the workloads' sample rates, several tiles per block,
     # dumps of 1, 4 and 20 periods, Doppler of either sign
@@ -396,6 +396,34 @@ def test_paper_workload_full_size_bit_exact(g, ctx):
         parts = list(ex.map(one, range(len(cfgs))))
     orc = [([p[0] for p in parts], [p[1] for p in parts])]
     assert int(lib[0][2].min()) >= 9999
+    assert_exact(lib, lst, orc, sts, cfgs)
+
+
+@pytest.mark.parametrize("name", ["iq2", "if_recording"])
+def test_more_formats_workloads_bit_exact(g, ctx, name):
+    # 2-bit complex baseband at 8.184 MHz (chip-by-chip kernel) and a GN3S-style
+    # real IF recording at 16.3676 MHz, IF 4.1304 MHz (not a whole number of
+    # samples per half chip: chip-by-chip kernel), 12 satellites, 1 s each:
+    # every dump of every channel against the oracle
+    from concurrent.futures import ThreadPoolExecutor
+
+    from paper_1907_00463_amd import synth
+    make = {"iq2": synth.workload_iq2, "if_recording": synth.workload_if_recording}[name]
+    st, chans, rng = make(seconds=1.0)
+    buf = synth.synth_samples(st, rng)
+    cfgs, states = _cfgs_states_for(g, st, chans)
+    lib, lst = run_library(torch, ctx, st.fmt, g.GC_CARRIER_LUT, cfgs, states, [buf], [st.n])
+    sts = [None] * len(cfgs)
+
+    def one(i):
+        r, s = run_oracle(st.fmt, cfgs[i: i + 1], states[i: i + 1], [buf], [st.n])
+        sts[i] = s[0]
+        return r[0][0][0], r[0][1][0]
+
+    with ThreadPoolExecutor(max_workers=12) as ex:
+        parts = list(ex.map(one, range(len(cfgs))))
+    orc = [([p[0] for p in parts], [p[1] for p in parts])]
+    assert int(lib[0][2].min()) >= 999
     assert_exact(lib, lst, orc, sts, cfgs)
 
 

@@ -41,7 +41,7 @@ def _receivers(g, seed, n_rx=6, n_req=3):
     out = []
     for r in range(n_rx):
         fs = rates[r % 3]
-        fmt = (0, 2, 1)[(r + r // 3) % 3]   # real int8, 2-bit and complex int8
+        fmt = (0, 2, 1, 3)[(r + r // 4) % 4]   # real int8, 2-bit, complex int8, complex 2-bit
         cfgs, states = [], []
         for c in range(int(rng.integers(1, 5))):
             T = int(rng.choice([1, 4, 20]))

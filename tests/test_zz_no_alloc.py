@@ -196,7 +196,7 @@ def test_noalloc_refuses_bad_channels_and_sizes(g, ctx):
     p, ps, _ = _run_plan(g, ctx, 0, g.GC_CARRIER_LUT, good, states[[0, 3]], buf, n, md)
     sub = tuple(x[[0, 3]] for x in a)
     _compare(g, g.GC_CARRIER_LUT, sub, p, sa[[0, 3]], ps, good)
-    # sizes: one channel past the array, tap_stride 0, format 3
+    # sizes: one channel past the array, tap_stride 0, format 4 (none)
     big = np.repeat(cfgs[:1], g.GC_NOALLOC_MAX_CHANNELS + 1)
     o = _outputs(g, g.GC_CARRIER_LUT, 1, md, 3)
     dev = _dev(big)
@@ -205,6 +205,6 @@ def test_noalloc_refuses_bad_channels_and_sizes(g, ctx):
     assert g.gc_correlate_noalloc(ctx, 0, 0, dev, g.GC_NOALLOC_MAX_CHANNELS + 1, 3, sb, n, stt,
                                   *o, md) == g.GC_EINVAL
     assert g.gc_correlate_noalloc(ctx, 0, 0, dev, 1, 0, sb, n, stt, *o, md) == g.GC_EINVAL
-    assert g.gc_correlate_noalloc(ctx, 3, 0, dev, 1, 3, sb, n, stt, *o, md) == g.GC_EINVAL
+    assert g.gc_correlate_noalloc(ctx, 4, 0, dev, 1, 3, sb, n, stt, *o, md) == g.GC_EINVAL
     torch.cuda.synchronize()
     assert np.all(o[3].cpu().numpy() == 7)                  # nothing was enqueued
