@@ -59,7 +59,7 @@ struct Shape {
     static_assert(kTile % 8 == 0, "half tiles start on a multiple of 4 samples");
     static_assert(kLdsBytes <= 160 * 1024, "LDS per block");
 };
-using ShapePlan = Shape<512, 90>;             // single-receiver plans: 46080-sample tiles
+using ShapePlan = Shape<1024, 46>;            // single-receiver plans: 47104-sample tiles
 
 typedef short short2_t __attribute__((ext_vector_type(2)));
 
@@ -315,9 +315,11 @@ __device__ __forceinline__ void epl_run(const void* __restrict__ sx, const uint8
 }
 
 // Direct per-sample form over tile offsets [lo, hi) for up to 4 taps (chips
-// cut by the block ends, and channels the binned form does not cover).
-template <int FMT, int kThreads>
+// cut by the block ends, and channels the binned form does not cover), by
+// the nthr threads of a group (gtid = 0 .. nthr - 1, whole waves).
+template <int FMT>
 __device__ __forceinline__ void direct_range(const void* __restrict__ sx, const uint8_t* lut,
+                                             uint32_t gtid, uint32_t nthr,
                                              uint32_t lane4, uint64_t t0, uint32_t lo, uint32_t hi,
                                              const DevMeta& m, const DevChan& ch,
                                              const uint32_t* __restrict__ sgn_prn, const Dest d) {
@@ -332,7 +334,7 @@ __device__ __forceinline__ void direct_range(const void* __restrict__ sx, const 
         const uint32_t a = (uint32_t)max((uint64_t)lo, s_lo > t0 ? s_lo - t0 : 0);
         const uint32_t b = (uint32_t)min((uint64_t)hi, s_hi - t0);
         int acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        for (uint32_t i = a + threadIdx.x; i < b; i += kThreads) {
+        for (uint32_t i = a + gtid; i < b; i += nthr) {
             const uint64_t n = t0 + i;
             const uint32_t phi = m.phi0 + (uint32_t)n * m.dphi;
             const uint32_t off = __builtin_amdgcn_perm(phi, lane4, kPermSel);
@@ -439,37 +441,58 @@ __device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, 
     }
 }
 
-// Channels [c_begin, c_end) of one receiver on its staged tile [t0, t1).
+// Channels [c_begin, c_end) of one receiver on its staged tile [t0, t1);
+// n_act of them are left to this kernel (not refused, not periodic).
 template <int FMT, class SH>
 __device__ __forceinline__ void epl_tile(const void* __restrict__ s_x, const uint8_t* lut,
                                          uint64_t t0, uint64_t t1, int c_begin, int c_end,
+                                         int n_act,
                                          const DevChan* __restrict__ chans,
                                          const DevMeta* __restrict__ metas,
                                          gc_chan_state* __restrict__ state,
                                          int32_t* __restrict__ out, int tap_stride,
                                          uint32_t max_dumps, const uint32_t* __restrict__ tables) {
-    constexpr int kThreads = SH::kThreads;
+    // Groups of whole waves take different channels at once: G groups of
+    // kThreads / G threads, G the largest power of two up to the number of
+    // channels left to this kernel with at least 128 threads per group.  A
+    // lane's run of whole chips is then G times longer than with every
+    // thread on one channel, so the per-run set-up and the closing wave sums
+    // weigh less (at 5 MHz complex input, about 5 chips per run otherwise).
+    static_assert((SH::kThreads & (SH::kThreads - 1)) == 0, "power-of-two block");
+    int G = 1;
+    while (2 * G <= n_act && SH::kThreads / (2 * G) >= 128) G *= 2;
+    const uint32_t lg = (uint32_t)__builtin_ctz((uint32_t)(SH::kThreads / G));  // log2 group size
+    const uint32_t kGroup = 1u << lg;
     const int tid = threadIdx.x;
+    const uint32_t gtid = (uint32_t)tid & (kGroup - 1);
+    const int grp = __builtin_amdgcn_readfirstlane(tid >> lg);
     const uint32_t lane4 = (tid & 63) * 4;
-    for (int chn = c_begin; chn < c_end; ++chn) {
+    // the group's channels: every G-th of those left to this kernel (when
+    // that is all of them, every G-th channel, without reading the others)
+    const bool all = n_act == c_end - c_begin;
+    int seq = 0;   // rank of the channel among those left to this kernel
+    for (int chn = c_begin + (all ? grp : 0); chn < c_end; chn += all ? G : 1) {
+        if (!all) {
+            if (metas[chn].status != GC_OK || metas[chn].path == kPathPeriodic) continue;
+            if ((seq++ & (G - 1)) != grp) continue;
+        }
         const DevMeta m = metas[chn];
-        if (m.status != GC_OK || m.path == kPathPeriodic) continue;
         const DevChan& ch = chans[chn];
         const Dest d{out, state + chn, (uint64_t)chn * max_dumps, tap_stride, m.m_close};
         const uint32_t* sgn_prn = tables + kTabSign + (ch.prn - 1) * kSignLen;
         const uint32_t tl = (uint32_t)(t1 - t0);
         if (m.path != kPathBinned) {
-            direct_range<FMT, kThreads>(s_x, lut, lane4, t0, 0, tl, m, ch, sgn_prn, d);
+            direct_range<FMT>(s_x, lut, gtid, kGroup, lane4, t0, 0, tl, m, ch, sgn_prn, d);
             continue;
         }
         // block-edge samples outside whole chips
         {
             const uint64_t he = m.head_end, tb = m.tail_beg;
             if (he > t0)
-                direct_range<FMT, kThreads>(s_x, lut, lane4, t0, 0, (uint32_t)min(he, t1) - (uint32_t)t0,
+                direct_range<FMT>(s_x, lut, gtid, kGroup, lane4, t0, 0, (uint32_t)min(he, t1) - (uint32_t)t0,
                                        m, ch, sgn_prn, d);
             if (t1 > tb)
-                direct_range<FMT, kThreads>(s_x, lut, lane4, t0, (uint32_t)(max(tb, t0) - t0), tl, m,
+                direct_range<FMT>(s_x, lut, gtid, kGroup, lane4, t0, (uint32_t)(max(tb, t0) - t0), tl, m,
                                        ch, sgn_prn, d);
         }
         // whole chips whose first sample lies in [t0, t1)
@@ -481,10 +504,10 @@ __device__ __forceinline__ void epl_tile(const void* __restrict__ s_x, const uin
         if (cb > m.c_full1) cb = m.c_full1;
         if (cb <= ca) continue;
         const uint32_t N = (uint32_t)(cb - ca);
-        const uint32_t k0 = (uint32_t)(((uint64_t)tid * N) / kThreads);
-        const uint32_t k1 = (uint32_t)(((uint64_t)(tid + 1) * N) / kThreads);
+        const uint32_t k0 = (uint32_t)(((uint64_t)gtid * N) >> lg);
+        const uint32_t k1 = (uint32_t)(((uint64_t)(gtid + 1) * N) >> lg);
         const uint32_t K = k1 - k0;
-        const uint32_t Kmax = (N + kThreads - 1) / kThreads;
+        const uint32_t Kmax = (N + kGroup - 1) >> lg;
         const uint32_t c = (uint32_t)(ca + k0);
         const uint32_t dp = (uint32_t)m.dp;
         const float inv_dp = 1.0f / (float)dp;
@@ -529,7 +552,7 @@ __device__ __forceinline__ void epl_tile(const void* __restrict__ s_x, const uin
 template <int FMT, class SH>
 __device__ __forceinline__ void tile_pass(const uint8_t* __restrict__ samples, uint64_t n,
                                           uint64_t t0, void* s_x, const uint8_t* lut,
-                                          int c_begin, int c_end,
+                                          int c_begin, int c_end, int n_act,
                                           const DevChan* __restrict__ chans,
                                           const DevMeta* __restrict__ metas,
                                           gc_chan_state* __restrict__ state,
@@ -546,8 +569,8 @@ __device__ __forceinline__ void tile_pass(const uint8_t* __restrict__ samples, u
         __syncthreads();
         stage_tile<FMT, SH::kThreads, kStaged>(samples, n, a, s_x, tables);
         __syncthreads();
-        epl_tile<FMT, SH>(s_x, lut, a, b, c_begin, c_end, chans, metas, state, out, tap_stride,
-                          max_dumps, tables);
+        epl_tile<FMT, SH>(s_x, lut, a, b, c_begin, c_end, n_act, chans, metas, state, out,
+                          tap_stride, max_dumps, tables);
     }
 }
 
@@ -565,17 +588,15 @@ __global__ __launch_bounds__(ShapePlan::kThreads) void k_epl(
     void* s_x = s_lds + kLutWords * 4;
     const int tid = threadIdx.x;
     // channels left to this kernel: not refused and not on the periodic path
-    {
-        int mine = 0;
-        for (int c = 0; c < n_chan; ++c)
-            mine |= metas[c].status == GC_OK && metas[c].path != kPathPeriodic;
-        if (!mine) return;
-    }
+    int n_act = 0;
+    for (int c = 0; c < n_chan; ++c)
+        n_act += metas[c].status == GC_OK && metas[c].path != kPathPeriodic;
+    if (n_act == 0) return;
     for (int i = tid; i < kLutWords; i += SH::kThreads) s_lut[i] = tables[kTabLut + (i >> 6)];
 
     for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const uint64_t t0 = (uint64_t)tile * SH::kTile;
-        tile_pass<FMT, SH>(samples, n, t0, s_x, s_lds, 0, n_chan, chans, metas, state, out,
+        tile_pass<FMT, SH>(samples, n, t0, s_x, s_lds, 0, n_chan, n_act, chans, metas, state, out,
                            tap_stride, max_dumps, tables);
     }
 }
@@ -610,22 +631,22 @@ __global__ __launch_bounds__(SH::kThreads) void k_epl_batch(
         const DevRx& R = rx[lo];
         // nothing to do when every channel of the receiver is refused or on
         // the periodic path (uniform over the block)
-        bool mine = false;
+        int n_act = 0;
         for (int c = R.chan_begin; c < R.chan_end; ++c)
-            mine |= metas[c].status == GC_OK && metas[c].path != kPathPeriodic;
-        if (!mine) continue;
+            n_act += metas[c].status == GC_OK && metas[c].path != kPathPeriodic;
+        if (n_act == 0) continue;
         const uint64_t t0 = (uint64_t)(item - R.tile_begin) * SH::kTile;
         if (R.fmt == GC_I2_REAL)
-            tile_pass<GC_I2_REAL, SH>(R.samples, R.n, t0, s_x, s_lds, R.chan_begin, R.chan_end,
+            tile_pass<GC_I2_REAL, SH>(R.samples, R.n, t0, s_x, s_lds, R.chan_begin, R.chan_end, n_act,
                                       chans, metas, state, out, tap_stride, max_dumps, tables);
         else if (R.fmt == GC_I8_IQ)
-            tile_pass<GC_I8_IQ, SH>(R.samples, R.n, t0, s_x, s_lds, R.chan_begin, R.chan_end,
+            tile_pass<GC_I8_IQ, SH>(R.samples, R.n, t0, s_x, s_lds, R.chan_begin, R.chan_end, n_act,
                                     chans, metas, state, out, tap_stride, max_dumps, tables);
         else if (R.fmt == GC_I2_IQ)
-            tile_pass<GC_I2_IQ, SH>(R.samples, R.n, t0, s_x, s_lds, R.chan_begin, R.chan_end,
+            tile_pass<GC_I2_IQ, SH>(R.samples, R.n, t0, s_x, s_lds, R.chan_begin, R.chan_end, n_act,
                                     chans, metas, state, out, tap_stride, max_dumps, tables);
         else
-            tile_pass<GC_I8_REAL, SH>(R.samples, R.n, t0, s_x, s_lds, R.chan_begin, R.chan_end,
+            tile_pass<GC_I8_REAL, SH>(R.samples, R.n, t0, s_x, s_lds, R.chan_begin, R.chan_end, n_act,
                                       chans, metas, state, out, tap_stride, max_dumps, tables);
     }
 }
