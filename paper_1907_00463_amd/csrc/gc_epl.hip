@@ -18,9 +18,15 @@
 //     one dword each, in two half tiles; per sample two packed multiply-adds
 //     form the planes (xI, xQ)*c and (xQ, xI)*s, and the bin's wiped-off
 //     sum is (xI c + xQ s, xQ c - xI s) from their halves;
-//   * per channel, the chips whose first sample lies in the tile are split
-//     into 512 runs of consecutive whole chips, one per lane (~90 samples,
-//     an odd number of LDS dwords apart, so lanes hit different banks);
+//   * the block's lanes (1024 in a plan, 256 or 512 in the batch shapes)
+//     form G groups of whole waves (G a power of two, at most the number of
+//     channels with work, at least 128 lanes a group), and the groups take
+//     different channels at once; within a group the chips whose first
+//     sample lies in the tile are split into one run of consecutive whole
+//     chips per lane (tile / group lanes samples, e.g. 46 * G in a plan;
+//     neighbouring runs start an odd number of LDS dwords apart, so lanes
+//     hit different banks).  Longer runs amortise the per-run set-up
+//     (Bresenham start, code signs, flush) over more samples;
 //   * a lane walks its run sample by sample: the carrier phase advances by
 //     one add, the sin/cos entry comes from a per-lane copy of the table in
 //     LDS (address = one v_perm, no bank conflicts), and one packed int16
