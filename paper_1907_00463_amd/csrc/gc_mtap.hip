@@ -50,9 +50,14 @@ constexpr int kOffS = 0;                          // S areas first: bases are mu
 constexpr int kOffLut = kOffS + kWaves * kSBytes;
 constexpr int kOffX = kOffLut + kLutBytes;
 constexpr int kOffList = kOffX + kXSamples * 8;
-constexpr int kLdsBytes = kOffList + 4 * (kWaves + 1);
+// 256 zero words: the carrier table of direct-form lanes whose row holds no
+// sample (their cells come out 0 with no branch); offset by 32 banks from
+// the first table copy, so that the same entry of both is in different banks
+constexpr int kOffZero = ((kOffList + 4 * (kWaves + 1) + 255) & ~255) + (((kOffLut / 4 + 32) % 64) * 4);
+constexpr int kLdsBytes = kOffZero + 1024;
 static_assert(kLdsBytes <= 160 * 1024, "LDS per block");
 static_assert(kOffS % 4096 == 0 && kSBytes == 4096, "cell offset = (U >> 25) & 0xFFC | wave base");
+static_assert((kOffZero / 4 - kOffLut / 4) % 64 == 32, "zero table 32 banks from the first copy");
 static_assert(kTile % 16 == 0 && kXSamples % 16 == 0, "staging granule");
 static_assert(16 * 33 * 4 <= kSBytes, "stage-3 prefix sums fit the wave's S area");
 static_assert(2 * kMtapHalfWords >= 1022 + 1022 + 1 + 24 + 8, "replica operand reads stay in the table");
@@ -139,6 +144,12 @@ __device__ __forceinline__ Chunk chunk_of(uint64_t c, uint64_t span, uint64_t p0
     chip_first(k.ce, p0, dp, k.fb, k.eb);
     k.sa = min(n, fa);
     k.sb = min(n, k.fb);
+    // every field is uniform (the arguments are); keep them in scalar
+    // registers so that the walk stays on the scalar unit
+    k.fb = uni64(k.fb);
+    k.eb = uni64(k.eb);
+    k.sa = uni64(k.sa);
+    k.sb = uni64(k.sb);
     return k;
 }
 
@@ -425,6 +436,8 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
             const int e = i % kLutStride;
             lut[i] = e < 256 ? tables[kTabLut + e] : 0u;
         }
+        uint32_t* zero = reinterpret_cast<uint32_t*>(s_lds + kOffZero);
+        for (int i = tid; i < 256; i += nthreads) zero[i] = 0u;
     }
 
     const bool active = wave < nlist;
@@ -459,6 +472,11 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
     const int jsh = (int)(((int64_t)jmin + (int64_t)(l32 & 7)) % kCodeLen);
     const uint32_t b_lane = (uint32_t)(jsh < 0 ? jsh + kCodeLen : jsh) + h;
     const uint32_t* btab = tables + kTabMtapCode + ((ch.prn - 1) * 4 + (int)(l32 >> 3)) * kMtapCodeWords;
+    // word offsets of the lane's first chip in the parity tables, for an even
+    // and an odd window code chip wmod (the chip is wmod + b_lane: parity
+    // (wmod + b_lane) & 1, word (wmod + b_lane) >> 1)
+    const uint32_t boff_e = (b_lane & 1u) * kMtapHalfWords + (b_lane >> 1);
+    const uint32_t boff_o = ((b_lane + 1u) & 1u) * kMtapHalfWords + ((b_lane + 1u) >> 1);
     // per-lane parts of the sample walk
     const uint64_t lane_dU = (uint64_t)lane * m.dp;
     const uint32_t lane_dph = lane * m.dphi;
@@ -474,6 +492,22 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
     // A fragment of K step ks: window positions 8 ks + h + 2 i, row l32
     // (the two lane halves read chips one apart: distinct banks)
     const uint32_t a_base = s_base + 128u * h + 4u * l32;
+    // Direct-cell form (rates where two chips span close to a whole number
+    // D2 of samples): the sample of cell (q, c) is n = ceil(N / dp) with
+    // N = c 2^32 + q 2^27 - P, present when r = n dp - N < 2^27.  Two chips
+    // on, N grows by 2^33, so n grows by D2 and r by d2 = D2 dp - 2^33 as
+    // long as r stays in [0, dp); while it also stays on its side of 2^27
+    // for all 16 positions of a lane's half, the lane's cells are a fixed
+    // sample stride apart and the lane forms its MFMA operand in registers.
+    // (code steps below 2^30, so that r and its drift over a window stay in
+    // int32)
+    const uint64_t D2 = uni64((uint64_t)(8589934592.0 / (double)m.dp + 0.5));
+    const int64_t d2l = (int64_t)(D2 * m.dp) - (int64_t)(1ull << 33);
+    const bool direct_ok = m.dp < (1ull << 30) && d2l >= -(1ll << 18) && d2l <= (1ll << 18);
+    const int32_t d2 = (int32_t)d2l;
+    const uint32_t dp32 = (uint32_t)m.dp;
+    const uint32_t X2 = 8u * (uint32_t)D2;          // tile bytes per two chips
+    const uint32_t F2 = (uint32_t)D2 * m.dphi;      // carrier phase per two chips
 
     // contiguous chunk of tiles for this block; chunks belong to the tile
     // holding their first sample
@@ -481,24 +515,23 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
     const uint32_t tb1 = (uint32_t)(((uint64_t)(blockIdx.x + 1) * n_tiles) / gridDim.x);
     const uint64_t T0 = (uint64_t)tb0 * kTile;
 
-    // two accumulators (even and odd K steps) halve the dependent MFMA chain
-    i32x16 acc0, acc1;
+    i32x16 acc0;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc0[e] = acc1[e] = 0;
+    for (int e = 0; e < 16; ++e) acc0[e] = 0;
     Chunk k = chunk_of((m.p0 + T0 * m.dp) >> 32, span, m.p0, m.dp, n);
     if (T0 > 0 && k.sa < T0) k = chunk_of(k.ce, span, m.p0, m.dp, n);
     bool seen_first = k.first;  // this wave holds the dump from its first chunk
-    bool open = false;          // acc0 + acc1 hold part of dump k.m
-    // the lane's sample sa + lane of the current chunk: code phase, carrier
-    // phase, and tile address (relative to the tile being worked on); each
-    // chunk advances them by its sample count
-    uint64_t Ul;
-    uint32_t phl, xl;
+    bool open = false;          // acc0 holds part of dump k.m
+    // sample sa of the current chunk (uniform): code phase, carrier phase,
+    // and tile address (relative to the tile being worked on); each chunk
+    // advances them by its sample count
+    uint64_t Ua;
+    uint32_t pha, xsa;
     {
         const uint64_t sa = uni64(k.sa);
-        Ul = m.p0 + sa * m.dp + lane_dU;
-        phl = m.phi0 + (uint32_t)sa * m.dphi + lane_dph;
-        xl = kOffX + (uint32_t)(sa - T0) * 8u + lane * 8u;
+        Ua = m.p0 + sa * m.dp;
+        pha = m.phi0 + (uint32_t)sa * m.dphi;
+        xsa = kOffX + (uint32_t)(sa - T0) * 8u;
     }
     auto x_at = [&](uint32_t a) { return *reinterpret_cast<const uint2*>(s_lds + a); };
     auto lut_at = [&](uint32_t phase) {
@@ -506,6 +539,12 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
     };
     auto cell_store = [&](uint32_t a, uint32_t v) { *reinterpret_cast<uint32_t*>(s_lds + a) = v; };
 
+    // direct-form state of the lane's cell (l32, dw0 + h): its sample's tile
+    // address and carrier phase, and r; advanced by one window after every
+    // window, recomputed when the next window is not the one it refers to
+    uint32_t dx = 0, df = 0;
+    int32_t dr = 0;
+    uint64_t dw0 = ~0ull;
     for (uint32_t tile = tb0; tile < tb1; ++tile) {
         const uint64_t t0 = (uint64_t)tile * kTile;
         const uint64_t t1 = min(n, t0 + kTile);
@@ -513,103 +552,197 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
         stage_tile<FMT>(samples, n, t0, s_lds, nthreads);
         __syncthreads();
         if (!active) continue;
-        if (tile > tb0) xl -= 8u * kTile;
+        if (tile > tb0) {
+            xsa -= 8u * kTile;
+            dx -= 8u * kTile;
+        }
         while (k.sa < t1 && k.sa < k.sb) {
             // the window's replica operand, in flight during stage 1
             int4_t bop[4];
             {
-                const uint32_t x = k.wmod + b_lane;  // chip of position h (i = 0, ks = 0)
-                const uint32_t* bp = btab + (x & 1u) * kMtapHalfWords + (x >> 1);
+                const uint32_t* bp = btab + ((k.wmod & 1u) ? boff_o : boff_e) + (k.wmod >> 1);
 #pragma unroll
                 for (int ks = 0; ks < 4; ++ks) bop[ks] = *reinterpret_cast<const int4_t*>(bp + 4 * ks);
             }
-            // stage 1: clear S (32 x 32 cells), scatter the chunk's samples
-            {
-                uint4* z = reinterpret_cast<uint4*>(s_lds + s_base) + lane;
-#pragma unroll
-                for (int c = 0; c < 4; ++c) z[64 * c] = uint4{0u, 0u, 0u, 0u};
-            }
-            wave_fence();
             const uint32_t adv = __builtin_amdgcn_readfirstlane((uint32_t)(k.sb - k.sa));
-            // at most 32 chips of at most 32 samples, inside the staged tile
-            const uint32_t cnt = min(adv, (uint32_t)(kXSamples - (uint32_t)(k.sa - t0)));
-            uint64_t U = Ul;
-            uint32_t ph = phl, xa = xl;
-            // pairs of full steps, software-pipelined over two register
-            // sets: the reads of the next pair (unconditional: the staged
-            // tile extends one pair past any chunk) are issued before the
-            // stores of the current one
-            uint32_t pairs = __builtin_amdgcn_readfirstlane(cnt / 128);
-            if (pairs > 0) {
-                uint2 xa0 = x_at(xa), xa1 = x_at(xa + 512u);
-                uint32_t ca0 = lut_at(ph), ca1 = lut_at(ph + dph);
-                uint2 xb0, xb1;
-                uint32_t cb0, cb1;
-                for (;;) {
-                    {
-                        const uint32_t v0 = cell_of(xa0, ca0, k128), v1 = cell_of(xa1, ca1, k128);
-                        const uint32_t a0 = cell_addr(U, s_base_v), a1 = cell_addr(U + dUv, s_base_v);
-                        U += dU2v;
-                        ph += dph2v;
-                        xa += 1024u;
-                        xb0 = x_at(xa);
-                        xb1 = x_at(xa + 512u);
-                        cb0 = lut_at(ph);
-                        cb1 = lut_at(ph + dph);
-                        cell_store(a0, v0);
-                        cell_store(a1, v1);
-                        if (--pairs == 0) break;
+            // direct-cell form: a whole window inside the block, every lane's
+            // cells on one side of their row boundaries (decided per lane,
+            // taken only when every lane agrees)
+            bool direct = false;
+            uint32_t lutb = lut_base;
+            if (direct_ok && k.cs == k.w0 && k.ce == k.w0 + kChunkChips && k.fb <= n &&
+                (k.cs << 32) >= m.p0) {
+                if (dw0 != k.w0) {
+                    // exact: cell (l32, w0 + h) relative to sample sa, the
+                    // first sample of chip w0 (uniform: lane 0's walk values):
+                    // N = h 2^32 + l32 2^27 - (U_sa mod 2^32), n = ceil(N / dp)
+                    const uint32_t fsa = (uint32_t)Ua;
+                    const int64_t N0 = ((int64_t)h << 32) + ((int64_t)l32 << 27) - (int64_t)fsa;
+                    const float est =
+                        ((float)h * 4294967296.0f + (float)(l32 << 27) - (float)fsa) * inv_dp;
+                    int32_t n0 = (int32_t)ceilf(est);
+                    int64_t r = (int64_t)n0 * (int64_t)m.dp - N0;
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) {
+                        if (r < 0) { r += (int64_t)m.dp; ++n0; }
+                        if (r >= (int64_t)m.dp) { r -= (int64_t)m.dp; --n0; }
                     }
-                    {
-                        const uint32_t v0 = cell_of(xb0, cb0, k128), v1 = cell_of(xb1, cb1, k128);
-                        const uint32_t a0 = cell_addr(U, s_base_v), a1 = cell_addr(U + dUv, s_base_v);
-                        U += dU2v;
-                        ph += dph2v;
-                        xa += 1024u;
-                        xa0 = x_at(xa);
-                        xa1 = x_at(xa + 512u);
-                        ca0 = lut_at(ph);
-                        ca1 = lut_at(ph + dph);
-                        cell_store(a0, v0);
-                        cell_store(a1, v1);
-                        if (--pairs == 0) break;
+                    dr = (int32_t)r;
+                    dx = xsa + 8u * (uint32_t)n0;
+                    df = pha + (uint32_t)n0 * m.dphi;
+                    dw0 = k.w0;
+                }
+                // r at the lane's last position; the cells of the window
+                // follow the first one's pattern when r stays in [0, dp) on
+                // one side of 2^27 (r is linear in the position)
+                const int32_t rhi = dr + 15 * d2;
+                const bool occ = dr < (1 << 27);
+                const bool ok = (uint32_t)dr < dp32 && (uint32_t)rhi < dp32 && (rhi < (1 << 27)) == occ;
+                direct = __all(ok);
+                lutb = occ ? lut_base : (uint32_t)kOffZero;
+            }
+            if (!direct) dw0 = ~0ull;
+            // opaque, so that each cell is one add from these (not a
+            // multiply of its sample index)
+            uint32_t x0 = dx, f0 = df;
+            asm("" : "+v"(x0));
+            asm("" : "+v"(f0));
+            if (direct) {
+                // stage 1 in registers: dword i of K step ks is the cell of
+                // window position 8 ks + h + 2 i, row l32
+                // (one K step at a time, the next step's reads issued before
+                // this step's arithmetic; a lane whose row holds no sample
+                // reads the zero table and forms 0 cells)
+                uint2 xv[4];
+                uint32_t cv[4];
+                auto load_step = [&](int ks, uint2* xs, uint32_t* cs) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const uint32_t t = (uint32_t)(4 * ks + i);
+                        const uint32_t ph = f0 + t * F2;
+                        cs[i] = *reinterpret_cast<const uint32_t*>(s_lds + lutb + ((ph >> 24) << 2));
+                        xs[i] = x_at(x0 + t * X2);
+                    }
+                };
+                load_step(0, xv, cv);
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) {
+                    uint2 xn[4];
+                    uint32_t cn[4];
+                    if (ks < 3) load_step(ks + 1, xn, cn);
+                    // cell_of for four cells, the +128 kept inside the first
+                    // multiply-add of each
+                    short2_t pp[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const short2_t c2 = as_s2(cv[i]);
+                        pp[i] = as_s2(xv[i].y) * __builtin_shufflevector(c2, c2, 1, 1) + k128;
+                    }
+                    asm("" : "+v"(pp[0]), "+v"(pp[1]), "+v"(pp[2]), "+v"(pp[3]));
+                    int4_t a;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const short2_t c2 = as_s2(cv[i]);
+                        const short2_t w2 = as_s2(xv[i].x) * __builtin_shufflevector(c2, c2, 0, 0) + pp[i];
+                        a[i] = (int)(__builtin_bit_cast(uint32_t, w2) ^ 0x00800080u);
+                    }
+                    acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, bop[ks], acc0, 0, 0, 0);
+                    if (ks < 3) {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            xv[i] = xn[i];
+                            cv[i] = cn[i];
+                        }
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            } else {
+                // stage 1: clear S (32 x 32 cells), scatter the chunk's samples
+                {
+                    uint4* z = reinterpret_cast<uint4*>(s_lds + s_base) + lane;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) z[64 * c] = uint4{0u, 0u, 0u, 0u};
+                }
+                wave_fence();
+                // at most 32 chips of at most 32 samples, inside the staged tile
+                const uint32_t cnt = min(adv, (uint32_t)(kXSamples - (uint32_t)(k.sa - t0)));
+                uint64_t U = Ua + lane_dU;
+                uint32_t ph = pha + lane_dph, xa = xsa + lane * 8u;
+                // pairs of full steps, software-pipelined over two register
+                // sets: the reads of the next pair (unconditional: the staged
+                // tile extends one pair past any chunk) are issued before the
+                // stores of the current one
+                uint32_t pairs = __builtin_amdgcn_readfirstlane(cnt / 128);
+                if (pairs > 0) {
+                    uint2 xa0 = x_at(xa), xa1 = x_at(xa + 512u);
+                    uint32_t ca0 = lut_at(ph), ca1 = lut_at(ph + dph);
+                    uint2 xb0, xb1;
+                    uint32_t cb0, cb1;
+                    for (;;) {
+                        {
+                            const uint32_t v0 = cell_of(xa0, ca0, k128), v1 = cell_of(xa1, ca1, k128);
+                            const uint32_t a0 = cell_addr(U, s_base_v), a1 = cell_addr(U + dUv, s_base_v);
+                            U += dU2v;
+                            ph += dph2v;
+                            xa += 1024u;
+                            xb0 = x_at(xa);
+                            xb1 = x_at(xa + 512u);
+                            cb0 = lut_at(ph);
+                            cb1 = lut_at(ph + dph);
+                            cell_store(a0, v0);
+                            cell_store(a1, v1);
+                            if (--pairs == 0) break;
+                        }
+                        {
+                            const uint32_t v0 = cell_of(xb0, cb0, k128), v1 = cell_of(xb1, cb1, k128);
+                            const uint32_t a0 = cell_addr(U, s_base_v), a1 = cell_addr(U + dUv, s_base_v);
+                            U += dU2v;
+                            ph += dph2v;
+                            xa += 1024u;
+                            xa0 = x_at(xa);
+                            xa1 = x_at(xa + 512u);
+                            ca0 = lut_at(ph);
+                            ca1 = lut_at(ph + dph);
+                            cell_store(a0, v0);
+                            cell_store(a1, v1);
+                            if (--pairs == 0) break;
+                        }
                     }
                 }
-            }
-            // the last 0 .. 127 samples: one pair with masked stores
-            const uint32_t rest = cnt % 128;
-            if (rest > 0) {
-                const uint32_t v0 = cell_of(x_at(xa), lut_at(ph), k128);
-                const uint32_t v1 = cell_of(x_at(xa + 512u), lut_at(ph + dph), k128);
-                const uint32_t a0 = cell_addr(U, s_base_v), a1 = cell_addr(U + dUv, s_base_v);
-                if (lane < rest) cell_store(a0, v0);
-                if (lane + 64 < rest) cell_store(a1, v1);
-            }
-            wave_fence();
-            // stage 2: four K steps of 8 chips, 32 rows q x 32 columns
+                // the last 0 .. 127 samples: one pair with masked stores
+                const uint32_t rest = cnt % 128;
+                if (rest > 0) {
+                    const uint32_t v0 = cell_of(x_at(xa), lut_at(ph), k128);
+                    const uint32_t v1 = cell_of(x_at(xa + 512u), lut_at(ph + dph), k128);
+                    const uint32_t a0 = cell_addr(U, s_base_v), a1 = cell_addr(U + dUv, s_base_v);
+                    if (lane < rest) cell_store(a0, v0);
+                    if (lane + 64 < rest) cell_store(a1, v1);
+                }
+                wave_fence();
+                // stage 2: four K steps of 8 chips, 32 rows q x 32 columns
 #pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-                const uint8_t* ap = s_lds + a_base + 1024u * ks;
-                const int4_t a = int4_t{*reinterpret_cast<const int*>(ap),
-                                        *reinterpret_cast<const int*>(ap + 256),
-                                        *reinterpret_cast<const int*>(ap + 512),
-                                        *reinterpret_cast<const int*>(ap + 768)};
-                if (ks % 2 == 0)
+                for (int ks = 0; ks < 4; ++ks) {
+                    const uint8_t* ap = s_lds + a_base + 1024u * ks;
+                    const int4_t a = int4_t{*reinterpret_cast<const int*>(ap),
+                                            *reinterpret_cast<const int*>(ap + 256),
+                                            *reinterpret_cast<const int*>(ap + 512),
+                                            *reinterpret_cast<const int*>(ap + 768)};
                     acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, bop[ks], acc0, 0, 0, 0);
-                else
-                    acc1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, bop[ks], acc1, 0, 0, 0);
+                }
+
             }
+            dx += 16u * X2;
+            df += 16u * F2;
+            dr += 16 * d2;
+            dw0 += kChunkChips;
             open = true;
             if (k.last) {
-                acc0 += acc1;
                 finish_dump(acc0, s_lds, s_base, lane, ch, jmin, k.m, seen_first && k.m > 0, d);
-#pragma unroll
-                for (int e = 0; e < 16; ++e) acc1[e] = 0;
                 open = false;
             }
-            Ul += (uint64_t)adv * m.dp;
-            phl += adv * m.dphi;
-            xl += 8u * adv;
+            Ua += (uint64_t)adv * m.dp;
+            pha += adv * m.dphi;
+            xsa += 8u * adv;
             const bool was_last = k.last;
             chunk_next(k, span, m.dp, inv_dp, n, fs);
             if (was_last) seen_first = true;
@@ -617,7 +750,6 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
     }
     // the dump still open at the end of this block's range
     if (active && open) {
-        acc0 += acc1;
         finish_dump(acc0, s_lds, s_base, lane, ch, jmin, k.m, false, d);
     }
 }
