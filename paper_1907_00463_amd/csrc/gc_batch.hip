@@ -117,19 +117,27 @@ hipError_t upload_pitems(gc_batch* b, int chunk) {
 
 hipError_t enqueue(gc_batch* b, hipStream_t s) {
     const int32_t allow = gc::kAllowBinned | (b->pchunk > 0 ? gc::kAllowPeriodic : 0);
+    // with the periodic kernel on, the chip-by-chip kernel runs only the
+    // tiles of receivers that still have work, selected on the device by one
+    // more block of the set-up's row kernel (which also zeroes the periodic
+    // kernel's item queue)
+    const bool sel = b->pchunk > 0;
+    gc::SelectArgs sa;
+    sa.rx = b->d_rx;
+    sa.n_rx = b->n_rx;
+    sa.n_chan = b->n_chan;
+    sa.n_items = b->n_items;
+    sa.order = b->d_order;
+    sa.count = b->d_count;
+    sa.queue = b->d_count + 1;
     hipError_t e = gc::launch_setup(b->d_chans, b->d_meta, b->state, b->n_chan, 0, GC_I8_REAL,
                                     GC_CARRIER_LUT, b->max_dumps, b->out, b->max_taps, b->dump_n,
-                                    b->n_dumps, b->status, allow, b->d_rx, nullptr, nullptr, s);
+                                    b->n_dumps, b->status, allow, b->d_rx, nullptr, nullptr, s,
+                                    sel ? &sa : nullptr);
     if (e == hipSuccess && b->pchunk > 0)
         e = gc::launch_pbin_batch(b->cus, b->d_rx, b->d_pitems, b->n_pitems, b->d_count + 1,
                                   b->d_chans, b->d_meta, b->state, (int32_t*)b->out,
                                   b->max_taps, b->max_dumps, b->ctx->d_tables, s);
-    // with the periodic kernel on, the chip-by-chip kernel runs only the
-    // tiles of receivers that still have work, selected on the device
-    const bool sel = b->pchunk > 0;
-    if (e == hipSuccess && sel)
-        e = gc::launch_epl_select(b->d_rx, b->n_rx, b->n_items, b->d_meta, b->d_order,
-                                  b->d_count, s);
     if (e == hipSuccess)
         e = gc::launch_epl_batch(b->shape, b->grid > 0 ? b->grid : b->cus, b->d_rx, b->n_rx,
                                  sel ? b->d_order : nullptr, b->n_items,

@@ -296,33 +296,105 @@ __global__ __launch_bounds__(64) void k_setup(const DevChan* __restrict__ chans,
 
 // ceil(num / d) for d >= 1: a double estimate made exact with integer checks
 // (the estimate is within one of the quotient for d >= 2^20).
-__device__ __forceinline__ uint64_t udiv_ceil(uint64_t num, uint64_t d) {
-    if (d < (1ull << 20)) return (num + d - 1) / d;
-    uint64_t q = (uint64_t)((double)num / (double)d);
-    while (q * d < num) ++q;
-    while (q > 0 && (q - 1) * d >= num) --q;
+// ceil(num / d) for d >= 2^20 from inv = 1 / d in double: the estimate
+// num * inv is within one of the quotient (below 2^44, relative error a few
+// units in 2^-53), so two exact integer steps each way make it exact.
+__device__ __forceinline__ uint64_t udiv_ceil(uint64_t num, uint64_t d, double inv) {
+    uint64_t q = (uint64_t)((double)num * inv);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        if (q * d < num) ++q;
+        if (q > 0 && (q - 1) * d >= num) --q;
+    }
     return q;
+}
+
+// The items of the chip-by-chip batch kernel with work: receivers with a
+// channel that is neither refused nor periodic, their tiles in order, into
+// order[0 .. *count); also zeroes *queue (the periodic batch kernel's item
+// queue).  Run by one block of k_rows (any block size up to 256).
+__device__ void select_items(const SelectArgs& a, const DevChan* __restrict__ chans,
+                             const DevMeta* __restrict__ metas) {
+    __shared__ uint32_t s_part[256];
+    __shared__ uint32_t s_need[256];
+    __shared__ uint32_t s_base;
+    const int t = threadIdx.x, nt = blockDim.x;
+    if (t == 0) {
+        s_base = 0;
+        if (a.queue) *a.queue = 0;
+    }
+    for (int r0 = 0; r0 < a.n_rx; r0 += nt) {
+        const int r1 = min(a.n_rx, r0 + nt);
+        s_need[t] = 0;
+        __syncthreads();
+        for (int c = t; c < a.n_chan; c += nt) {
+            const int cr = chans[c].rx;
+            if (cr >= r0 && cr < r1 && metas[c].status == GC_OK && metas[c].path != kPathPeriodic)
+                s_need[cr - r0] = 1u;
+        }
+        __syncthreads();
+        const int r = r0 + t;
+        uint32_t cnt = 0;
+        if (r < r1 && s_need[t]) {
+            const uint32_t te = r + 1 < a.n_rx ? a.rx[r + 1].tile_begin : a.n_items;
+            cnt = te - a.rx[r].tile_begin;
+        }
+        s_part[t] = cnt;
+        __syncthreads();
+        for (int off = 1; off < nt; off <<= 1) {  // inclusive scan
+            const uint32_t v = t >= off ? s_part[t - off] : 0u;
+            __syncthreads();
+            s_part[t] += v;
+            __syncthreads();
+        }
+        // each needing receiver's items, written by the whole block
+        for (int i = 0; i < r1 - r0; ++i) {
+            const uint32_t end = s_part[i], beg = i > 0 ? s_part[i - 1] : 0u;
+            if (end == beg) continue;
+            const uint32_t tb = a.rx[r0 + i].tile_begin;
+            for (uint32_t j = (uint32_t)t; j < end - beg; j += (uint32_t)nt)
+                a.order[s_base + beg + j] = tb + j;
+        }
+        __syncthreads();
+        if (t == nt - 1) s_base += s_part[nt - 1];
+        __syncthreads();
+    }
+    if (t == 0) *a.count = s_base;
 }
 
 // Per-call output rows 1 .. M-1 of every channel: cleared (all tap_stride
 // taps of a row), and the sample count of each emitted dump (row 0 also holds
-// the samples carried in).
+// the samples carried in).  With a selection (sel.rx not null) the grid has
+// one more column of blocks, whose first block runs select_items.
 __global__ __launch_bounds__(256) void k_rows(const DevChan* __restrict__ chans,
                                               const DevMeta* __restrict__ metas, int carrier,
                                               uint32_t max_dumps, void* out, int tap_stride,
                                               uint32_t* __restrict__ dump_n,
-                                              const int32_t* __restrict__ list) {
+                                              const int32_t* __restrict__ list, SelectArgs sel) {
+    const uint32_t nx = sel.rx ? gridDim.x - 1 : gridDim.x;
+    if (blockIdx.x == nx) {
+        if (blockIdx.y == 0) select_items(sel, chans, metas);
+        return;
+    }
     const int ch = list ? list[blockIdx.y] : (int)blockIdx.y;
     const DevMeta m = metas[ch];
     if (m.status != GC_OK) return;
     const uint32_t M = m.m_close;
-    const int K = chans[ch].n_taps;
-    const uint32_t stride = gridDim.x * blockDim.x;
+    const uint32_t stride = nx * blockDim.x;
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    for (uint32_t r = t; r < M; r += stride) {
-        const uint64_t s0 = r == 0 ? 0 : udiv_ceil(r * m.window - m.p0, m.dp);
-        const uint64_t s1 = udiv_ceil((r + 1) * m.window - m.p0, m.dp);
-        dump_n[(uint64_t)ch * max_dumps + r] = (uint32_t)(s1 - s0) + (r == 0 ? m.acc_n0 : 0u);
+    if (m.dp >= (1ull << 20)) {
+        const double inv = 1.0 / (double)m.dp;
+        for (uint32_t r = t; r < M; r += stride) {
+            const uint64_t s0 = r == 0 ? 0 : udiv_ceil(r * m.window - m.p0, m.dp, inv);
+            const uint64_t s1 = udiv_ceil((r + 1) * m.window - m.p0, m.dp, inv);
+            dump_n[(uint64_t)ch * max_dumps + r] = (uint32_t)(s1 - s0) + (r == 0 ? m.acc_n0 : 0u);
+        }
+    } else {
+        for (uint32_t r = t; r < M; r += stride) {
+            const uint64_t s0 = r == 0 ? 0 : (r * m.window - m.p0 + m.dp - 1) / m.dp;
+            const uint64_t s1 = ((r + 1) * m.window - m.p0 + m.dp - 1) / m.dp;
+            dump_n[(uint64_t)ch * max_dumps + r] = (uint32_t)(s1 - s0) + (r == 0 ? m.acc_n0 : 0u);
+        }
     }
     // rows 1 .. M-1 are contiguous: clear their 4-byte words, 16 bytes per
     // store where the row block is aligned (carrier-independent: 0 and 0.0f
@@ -337,20 +409,20 @@ __global__ __launch_bounds__(256) void k_rows(const DevChan* __restrict__ chans,
     const uint64_t n4 = (words - head) / 4;
     for (uint64_t i = t; i < n4; i += stride) o4[i] = uint4{0u, 0u, 0u, 0u};
     for (uint64_t i = head + 4 * n4 + t; i < words; i += stride) o[i] = 0u;
-    (void)K;
 }
 
 hipError_t launch_setup(const DevChan* chans, DevMeta* meta, gc_chan_state* state, int n_chan,
                         uint64_t n_samples, int fmt, int carrier, uint32_t max_dumps, void* out,
                         int tap_stride, uint32_t* dump_n, uint32_t* n_dumps, int32_t* status,
                         int32_t allow, const DevRx* rx, const int32_t* list,
-                        const int32_t* list_rx, hipStream_t s) {
+                        const int32_t* list_rx, hipStream_t s, const SelectArgs* sel) {
     hipLaunchKernelGGL(k_setup, dim3(n_chan), dim3(64), 0, s, chans, meta, state, n_samples, fmt,
                        carrier, max_dumps, out, tap_stride, dump_n, n_dumps, status, allow, rx,
                        list, list_rx);
     const uint32_t gx = min((max_dumps + 255u) / 256u, 256u);
-    hipLaunchKernelGGL(k_rows, dim3(gx, n_chan), dim3(256), 0, s, chans, meta, carrier, max_dumps,
-                       out, tap_stride, dump_n, list);
+    const SelectArgs none{};
+    hipLaunchKernelGGL(k_rows, dim3(gx + (sel ? 1u : 0u), n_chan), dim3(256), 0, s, chans, meta,
+                       carrier, max_dumps, out, tap_stride, dump_n, list, sel ? *sel : none);
     return hipGetLastError();
 }
 

@@ -622,7 +622,7 @@ __global__ __launch_bounds__(SH::kThreads) void k_epl_batch(
     uint32_t* s_lut = reinterpret_cast<uint32_t*>(s_lds);
     void* s_x = s_lds + kLutWords * 4;
     const int tid = threadIdx.x;
-    // the item count written by k_epl_select, when given
+    // the item count written by the set-up's item selection, when given
     if (n_items_dev) n_items = min(n_items, *n_items_dev);
     if (blockIdx.x >= n_items) return;
     for (int i = tid; i < kLutWords; i += SH::kThreads) s_lut[i] = tables[kTabLut + (i >> 6)];
@@ -661,52 +661,7 @@ __global__ __launch_bounds__(SH::kThreads) void k_epl_batch(
 // with a channel that is neither refused nor on the periodic path, in
 // receiver order, into order[0 .. *count) (one block; a block-wide scan of
 // the receivers' tile counts gives each receiver its place).
-__global__ __launch_bounds__(1024) void k_epl_select(const DevRx* __restrict__ rx, int n_rx,
-                                                     uint32_t n_items,
-                                                     const DevMeta* __restrict__ metas,
-                                                     uint32_t* __restrict__ order,
-                                                     uint32_t* __restrict__ count) {
-    __shared__ uint32_t s_part[1024];
-    __shared__ uint32_t s_base;
-    const int t = threadIdx.x;
-    if (t == 0) s_base = 0;
-    __syncthreads();
-    for (int r0 = 0; r0 < n_rx; r0 += 1024) {
-        const int r = r0 + t;
-        uint32_t cnt = 0, tb = 0;
-        if (r < n_rx) {
-            bool need = false;
-            for (int c = rx[r].chan_begin; c < rx[r].chan_end; ++c)
-                need |= metas[c].status == GC_OK && metas[c].path != kPathPeriodic;
-            tb = rx[r].tile_begin;
-            const uint32_t te = r + 1 < n_rx ? rx[r + 1].tile_begin : n_items;
-            cnt = need ? te - tb : 0u;
-        }
-        s_part[t] = cnt;
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {  // inclusive scan
-            const uint32_t v = t >= off ? s_part[t - off] : 0u;
-            __syncthreads();
-            s_part[t] += v;
-            __syncthreads();
-        }
-        const uint32_t at = s_base + s_part[t] - cnt;
-        for (uint32_t i = 0; i < cnt; ++i) order[at + i] = tb + i;
-        __syncthreads();
-        if (t == 1023) s_base += s_part[1023];
-        __syncthreads();
-    }
-    if (t == 0) *count = s_base;
-}
-
 }  // namespace
-
-hipError_t launch_epl_select(const DevRx* rx, int n_rx, uint32_t n_items, const DevMeta* meta,
-                             uint32_t* order, uint32_t* count, hipStream_t s) {
-    hipLaunchKernelGGL(k_epl_select, dim3(1), dim3(1024), 0, s, rx, n_rx, n_items, meta, order,
-                       count);
-    return hipGetLastError();
-}
 
 int epl_blocks_per_device(int device) {
     int cus = 0;

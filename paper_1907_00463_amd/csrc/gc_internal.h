@@ -131,11 +131,26 @@ hipError_t launch_make_tables(uint32_t* d_tables, hipStream_t s);
 hipError_t launch_fill_chans(const gc_chan_cfg* cfg, int n_chan, int tap_stride, DevChan* out,
                              hipStream_t s);
 hipError_t launch_code_table(const uint32_t* d_tables, int g2_delay, int8_t* d_out, hipStream_t s);
+// The chip-by-chip batch kernel's item selection, run inside the set-up:
+// receivers rx[0 .. n_rx) (with tile_begin, n_items tiles in all), the
+// channels chans[0 .. n_chan) (with their receiver in DevChan.rx); order
+// (n_items words) and *count receive the items with work, *queue (when not
+// null) is zeroed.
+struct SelectArgs {
+    const DevRx* rx = nullptr;
+    int n_rx = 0;
+    int n_chan = 0;
+    uint32_t n_items = 0;
+    uint32_t* order = nullptr;
+    uint32_t* count = nullptr;
+    uint32_t* queue = nullptr;
+};
 hipError_t launch_setup(const DevChan* chans, DevMeta* meta, gc_chan_state* state, int n_chan,
                         uint64_t n_samples, int fmt, int carrier, uint32_t max_dumps,
                         void* out, int tap_stride, uint32_t* dump_n, uint32_t* n_dumps,
                         int32_t* status, int32_t allow, const DevRx* rx,
-                        const int32_t* list, const int32_t* list_rx, hipStream_t s);
+                        const int32_t* list, const int32_t* list_rx, hipStream_t s,
+                        const SelectArgs* sel = nullptr);
 // list: the channels to set up (null: 0 .. n_chan-1); rx: receiver table of a
 // batch (null: one block of n_samples in fmt), indexed by list_rx[i] when
 // given, else by the channel's rx field
@@ -149,16 +164,13 @@ hipError_t launch_epl_batch(int shape, int grid, const DevRx* rx, int n_rx,
                             const DevChan* chans, const DevMeta* meta, gc_chan_state* state,
                             int32_t* out, int tap_stride, uint32_t max_dumps,
                             const uint32_t* tables, hipStream_t s);
-// The items of k_epl_batch with work (receivers with a channel that is not
-// refused and not periodic) into order[0 .. *count), one block.
-hipError_t launch_epl_select(const DevRx* rx, int n_rx, uint32_t n_items, const DevMeta* meta,
-                             uint32_t* order, uint32_t* count, hipStream_t s);
 hipError_t launch_pbin(const uint8_t* samples, uint64_t n_samples, int fmt, const DevChan* chans,
                        const DevMeta* meta, gc_chan_state* state, int n_chan, int32_t* out,
                        int tap_stride, uint32_t max_dumps, const uint32_t* d_tables, int grid,
                        hipStream_t s);
 int pbin_tile_samples();
-// counter: one device word, the items' queue (reset on the stream first)
+// counter: one device word, the items' queue, zero when the kernel starts
+// (the set-up's item selection zeroes it)
 hipError_t launch_pbin_batch(int grid, const DevRx* rx, const PbinItem* items, uint32_t n_items,
                              uint32_t* counter, const DevChan* chans, const DevMeta* meta,
                              gc_chan_state* state, int32_t* out, int tap_stride,

@@ -682,11 +682,8 @@ __global__ __launch_bounds__(kMaxWaves * 64) void k_pbin(const uint8_t* __restri
 // one receiver for a group of at most kMaxWaves of its channels; the block
 // lists the group's periodic channels and shares their bins evenly among
 // its kMaxWaves waves.  Blocks take items from a queue (an atomic counter,
-// zeroed by k_queue_reset just before), so that items of unequal cost
-// (channel count, samples per chip) even out across the compute units.
-__global__ void k_queue_reset(uint32_t* __restrict__ counter) {
-    if (threadIdx.x == 0) *counter = 0;
-}
+// zero when the kernel starts), so that items of unequal cost (channel
+// count, samples per chip) even out across the compute units.
 
 __global__ __launch_bounds__(kMaxWaves * 64) void k_pbin_batch(
     const DevRx* __restrict__ rx, const PbinItem* __restrict__ items, uint32_t n_items,
@@ -750,7 +747,6 @@ hipError_t launch_pbin_batch(int grid, const DevRx* rx, const PbinItem* items, u
                              uint32_t max_dumps, const uint32_t* tables, hipStream_t s) {
     if (n_items == 0) return hipSuccess;
     const int g = (int)min((uint32_t)grid, n_items);
-    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, counter);
     hipLaunchKernelGGL(k_pbin_batch, dim3(g), dim3(64 * kMaxWaves), 0, s, rx, items, n_items,
                        counter, chans, meta, state, out, tap_stride, max_dumps, tables);
     return hipGetLastError();
