@@ -82,10 +82,10 @@ __device__ __forceinline__ short2_t mac_sample(short2_t a, short x, uint32_t phi
     return xx * cs + a;
 }
 
-// Sum over one bin of len samples starting at phase phi, len in {Q-1, Q, Q+1}
-// (Q > 0: straight-line code, the last two samples weighted by 0 or 1 so that
-// no branch splits the chip body), or any len (Q == 0).  The bin's phase
-// advance is len*dphi, applied by the caller.
+// Sum over one bin of len samples starting at phase phi, len in {Q, Q+1}
+// (Q > 0: straight-line code, the last sample weighted by 0 or 1 so that no
+// branch splits the chip body), or any len (Q == 0).  The bin's phase advance
+// is len*dphi, applied by the caller.
 template <int Q>
 __device__ __forceinline__ short2_t bin_sum(const short* __restrict__ xs, uint32_t phi,
                                             uint32_t dphi, uint32_t lane4, const uint8_t* lut,
@@ -93,9 +93,7 @@ __device__ __forceinline__ short2_t bin_sum(const short* __restrict__ xs, uint32
     short2_t a = {0, 0};
     if constexpr (Q > 0) {
 #pragma unroll
-        for (int j = 0; j < Q - 1; ++j) a = mac_sample(a, xs[j], phi + j * dphi, lane4, lut);
-        const short x1 = len >= (uint32_t)Q ? xs[Q - 1] : (short)0;
-        a = mac_sample(a, x1, phi + (Q - 1) * dphi, lane4, lut);
+        for (int j = 0; j < Q; ++j) a = mac_sample(a, xs[j], phi + j * dphi, lane4, lut);
         const short x2 = len > (uint32_t)Q ? xs[Q] : (short)0;
         a = mac_sample(a, x2, phi + Q * dphi, lane4, lut);
     } else {
@@ -126,9 +124,7 @@ __device__ __forceinline__ void bin_sum_iq(const uint32_t* __restrict__ xs, uint
     b = short2_t{0, 0};
     if constexpr (Q > 0) {
 #pragma unroll
-        for (int j = 0; j < Q - 1; ++j) mac_iq(a, b, xs[j], phi + j * dphi, lane4, lut);
-        const uint32_t x1 = len >= (uint32_t)Q ? xs[Q - 1] : 0u;
-        mac_iq(a, b, x1, phi + (Q - 1) * dphi, lane4, lut);
+        for (int j = 0; j < Q; ++j) mac_iq(a, b, xs[j], phi + j * dphi, lane4, lut);
         const uint32_t x2 = len > (uint32_t)Q ? xs[Q] : 0u;
         mac_iq(a, b, x2, phi + Q * dphi, lane4, lut);
     } else {
@@ -172,55 +168,52 @@ struct EplAcc<GC_I2_REAL> {
     }
 };
 
-template <>
-struct EplAcc<GC_I8_REAL> {
+// int32 sums folded a chip at a time: the chip's two bins paired per
+// component, (b0, b1), against the sign pairs of the taps, E (s_c, s_c+1),
+// P (s_c, s_c) and L (s_c-1, s_c), by a two-term int16 dot product into
+// int32 each.
+__device__ __forceinline__ uint32_t lo_pair(uint32_t x0, uint32_t x1) {
+    return __builtin_amdgcn_perm(x1, x0, 0x05040100u);   // (x0.lo, x1.lo)
+}
+__device__ __forceinline__ uint32_t hi_pair(uint32_t x0, uint32_t x1) {
+    return __builtin_amdgcn_perm(x1, x0, 0x07060302u);   // (x0.hi, x1.hi)
+}
+__device__ __forceinline__ int dot2(uint32_t x, uint32_t s, int acc) {
+    return __builtin_amdgcn_sdot2(as_s2(x), as_s2(s), acc, false);
+}
+
+struct EplAcc32 {
     int ei, eq, pi, pq, li, lq;
     __device__ __forceinline__ void zero() { ei = eq = pi = pq = li = lq = 0; }
-    __device__ __forceinline__ void fold0(short2_t a, uint32_t mp, uint32_t mc, uint32_t) {
-        const int ai = a.x, aq = a.y;
-        const int sc = (int)(short)(mc & 0xFFFF), sp = (int)(short)(mp & 0xFFFF);
-        ei += ai * sc; eq += aq * sc;
-        pi += ai * sc; pq += aq * sc;
-        li += ai * sp; lq += aq * sp;
-    }
-    __device__ __forceinline__ void fold1(short2_t a, uint32_t, uint32_t mc, uint32_t mn) {
-        const int ai = a.x, aq = a.y;
-        const int sc = (int)(short)(mc & 0xFFFF), sn = (int)(short)(mn & 0xFFFF);
-        ei += ai * sn; eq += aq * sn;
-        pi += ai * sc; pq += aq * sc;
-        li += ai * sc; lq += aq * sc;
+    // I of the two bins in xi, the kept (negated) Q in xq
+    __device__ __forceinline__ void fold_chip(uint32_t xi, uint32_t xq, uint32_t se, uint32_t sc,
+                                              uint32_t sl) {
+        ei = dot2(xi, se, ei); eq = dot2(xq, se, eq);
+        pi = dot2(xi, sc, pi); pq = dot2(xq, sc, pq);
+        li = dot2(xi, sl, li); lq = dot2(xq, sl, lq);
     }
     __device__ __forceinline__ void get(int v[6]) const {
         v[0] = ei; v[1] = eq; v[2] = pi; v[3] = pq; v[4] = li; v[5] = lq;
     }
 };
 
-// Complex input: the bin's wiped-off sums wi = aI + bI and nq = -(aQ - bQ)
-// (Q kept negated like the real forms' +x*s) in int32.
+// int8 real input: a bin is (sum x c, sum x s).
 template <>
-struct EplAcc<GC_I8_IQ> {
-    int ei, eq, pi, pq, li, lq;
-    __device__ __forceinline__ void zero() { ei = eq = pi = pq = li = lq = 0; }
-    __device__ __forceinline__ void fold0(int wi, int nq, uint32_t mp, uint32_t mc) {
-        const int sc = (int)(short)(mc & 0xFFFF), sp = (int)(short)(mp & 0xFFFF);
-        ei += wi * sc; eq += nq * sc;
-        pi += wi * sc; pq += nq * sc;
-        li += wi * sp; lq += nq * sp;
-    }
-    __device__ __forceinline__ void fold1(int wi, int nq, uint32_t mc, uint32_t mn) {
-        const int sc = (int)(short)(mc & 0xFFFF), sn = (int)(short)(mn & 0xFFFF);
-        ei += wi * sn; eq += nq * sn;
-        pi += wi * sc; pq += nq * sc;
-        li += wi * sc; lq += nq * sc;
-    }
-    __device__ __forceinline__ void get(int v[6]) const {
-        v[0] = ei; v[1] = eq; v[2] = pi; v[3] = pq; v[4] = li; v[5] = lq;
-    }
-};
+struct EplAcc<GC_I8_REAL> : EplAcc32 {};
 
-// 2-bit complex input: staged like int8 complex, the same sums.
+// Complex input: a bin's wiped-off sums are wi = aI + bI and nq = bQ - aQ
+// (Q kept negated like the real forms' +x*s), formed as the packed
+// a * (1, -1) + b while they fit int16 (bins of at most Q + 1 samples, each
+// |xI c + xQ s| <= max|x| * 34), else dotted plane by plane.
 template <>
-struct EplAcc<GC_I2_IQ> : EplAcc<GC_I8_IQ> {};
+struct EplAcc<GC_I8_IQ> : EplAcc32 {};
+template <>
+struct EplAcc<GC_I2_IQ> : EplAcc32 {};
+
+template <int FMT, int Q>
+__device__ __forceinline__ constexpr bool iq_packed_w() {
+    return Q > 0 && (uint64_t)(Q + 1) * (FMT == GC_I2_IQ ? 3u : 128u) * kLutAbsSumMax <= 32767u;
+}
 
 // Lane-private atomics of one run's sums (dump boundary inside a run).
 template <int FMT>
@@ -252,6 +245,7 @@ __device__ __forceinline__ void epl_run(const void* __restrict__ sx, const uint8
     while ((w + 1) * span <= c) ++w;
     uint32_t wnext = (w + 1) * span;
     uint32_t mp = sgn[0], mc = sgn[1], mn = sgn[2];
+    uint32_t sl = lo_pair(mp, mc);   // (s_c-1, s_c) of the chip
     const bool active = K > 0;
     for (uint32_t k = 0; k < Kmax; ++k) {
         if (k < K) {
@@ -266,15 +260,13 @@ __device__ __forceinline__ void epl_run(const void* __restrict__ sx, const uint8
             bool lt = e < r;
             uint32_t len = q + (lt ? 1u : 0u);
             e = lt ? e + dp - r : e - r;
+            short2_t a0, b0, a1, b1;
             if constexpr (fmt_complex(FMT)) {
-                short2_t a, b;
                 bin_sum_iq<Q>(static_cast<const uint32_t*>(sx) + nb, phi, dphi, lane4, lut, len,
-                              a, b);
-                acc.fold0((int)a.x + (int)b.x, (int)b.y - (int)a.y, mp, mc);
+                              a0, b0);
             } else {
-                const short2_t a =
-                    bin_sum<Q>(static_cast<const short*>(sx) + nb, phi, dphi, lane4, lut, len);
-                acc.fold0(a, mp, mc, mn);
+                a0 = bin_sum<Q>(static_cast<const short*>(sx) + nb, phi, dphi, lane4, lut, len);
+                if constexpr (FMT == GC_I2_REAL) acc.fold0(a0, mp, mc, mn);
             }
             nb += len;
             phi += len * dphi;
@@ -283,17 +275,35 @@ __device__ __forceinline__ void epl_run(const void* __restrict__ sx, const uint8
             len = q + (lt ? 1u : 0u);
             e = lt ? e + dp - r : e - r;
             if constexpr (fmt_complex(FMT)) {
-                short2_t a, b;
                 bin_sum_iq<Q>(static_cast<const uint32_t*>(sx) + nb, phi, dphi, lane4, lut, len,
-                              a, b);
-                acc.fold1((int)a.x + (int)b.x, (int)b.y - (int)a.y, mc, mn);
+                              a1, b1);
             } else {
-                const short2_t a =
-                    bin_sum<Q>(static_cast<const short*>(sx) + nb, phi, dphi, lane4, lut, len);
-                acc.fold1(a, mp, mc, mn);
+                a1 = bin_sum<Q>(static_cast<const short*>(sx) + nb, phi, dphi, lane4, lut, len);
+                if constexpr (FMT == GC_I2_REAL) acc.fold1(a1, mp, mc, mn);
             }
             nb += len;
             phi += len * dphi;
+            if constexpr (FMT != GC_I2_REAL) {
+                const uint32_t se = lo_pair(mc, mn);   // (s_c, s_c+1)
+                if constexpr (FMT == GC_I8_REAL) {
+                    const uint32_t x0 = as_u32(a0), x1 = as_u32(a1);
+                    acc.fold_chip(lo_pair(x0, x1), hi_pair(x0, x1), se, mc, sl);
+                } else if constexpr (iq_packed_w<FMT, Q>()) {
+                    const short2_t m1 = {1, -1};
+                    const uint32_t w0 = as_u32(a0 * m1 + b0), w1 = as_u32(a1 * m1 + b1);
+                    acc.fold_chip(lo_pair(w0, w1), hi_pair(w0, w1), se, mc, sl);
+                } else {
+                    // wi = aI + bI, nq = bQ - aQ: the b planes with the signs,
+                    // the a planes with the signs for I and negated for Q
+                    const uint32_t xa0 = as_u32(a0), xa1 = as_u32(a1);
+                    const uint32_t xb0 = as_u32(b0), xb1 = as_u32(b1);
+                    acc.fold_chip(lo_pair(xb0, xb1), hi_pair(xb0, xb1), se, mc, sl);
+                    const uint32_t ai = lo_pair(xa0, xa1), aq = hi_pair(xa0, xa1);
+                    const uint32_t naq = as_u32(short2_t{0, 0} - as_s2(aq));
+                    acc.fold_chip(ai, naq, se, mc, sl);
+                }
+                sl = se;
+            }
             mp = mc;
             mc = mn;
             mn = mnn;
@@ -537,15 +547,15 @@ __device__ __forceinline__ void epl_tile(const void* __restrict__ s_x, const uin
 #define GC_RUN(QQ)                                                                          \
     epl_run<FMT, QQ>(s_x, lut, lane4, nrel, phi, m.dphi, e, dp, q, r, c, K, Kmax, span, sgn, \
                      d, ch)
-        switch (q) {
-            case 1: GC_RUN(2); break;
-            case 2: GC_RUN(3); break;
-            case 3: GC_RUN(4); break;
-            case 4: GC_RUN(5); break;
-            case 7: GC_RUN(8); break;
-            case 8: GC_RUN(9); break;
-            case 9: GC_RUN(10); break;
-            case 10: GC_RUN(11); break;
+        switch (q) {  // bins of q or q + 1 samples
+            case 1: GC_RUN(1); break;
+            case 2: GC_RUN(2); break;
+            case 3: GC_RUN(3); break;
+            case 4: GC_RUN(4); break;
+            case 7: GC_RUN(7); break;
+            case 8: GC_RUN(8); break;
+            case 9: GC_RUN(9); break;
+            case 10: GC_RUN(10); break;
             default: GC_RUN(0); break;
         }
 #undef GC_RUN
