@@ -265,3 +265,46 @@ def test_batch_full_workload_sampled(g, ctx):
             assert int(dump_n[i, :nd].astype(np.int64).sum()) + int(st_fin[i]["acc_n"]) == n, i
     finally:
         b.close()
+
+
+def test_batch_many_receivers_item_selection(g, ctx):
+    # 300 receivers (more than one pass of the set-up's item selection over
+    # receivers), some with no channel at all, complex ones (their channels
+    # take the chip-by-chip kernel, so their tiles must be selected) spread
+    # over every pass, real ones at periodic rates (periodic kernel only):
+    # every channel bit-exact against the oracle, with the periodic kernel on
+    # (selection) and off (every item).
+    rng = np.random.default_rng(907)
+    rates = [4.092e6, 8.184e6, 16.368e6]
+    rx, cfgs, states, chan_rx = [], [], [], []
+    for r in range(300):
+        fs = rates[r % 3]
+        fmt = 1 if r % 37 == 5 else (3 if r % 53 == 7 else (0, 2)[r % 2])
+        n = int(rng.integers(2_000, 9_000))
+        rx.append((fmt, n, rng.integers(0, 256, size=block_bytes(fmt, n), dtype=np.uint8)))
+        if r % 11 == 3:
+            continue   # a receiver with no channel
+        for c in range(int(rng.integers(1, 3))):
+            T = int(rng.choice([1, 4]))
+            cfgs.append(g.make_cfg(int(rng.integers(1, 33)), EPL, T))
+            fd = float(rng.uniform(-5000, 5000))
+            states.append(g.gc_nco_init(fs, fs / 4 + fd, float(rng.random()),
+                                        1.023e6 * (1 + fd / 1575.42e6),
+                                        float(rng.uniform(0, 1023 * T)), T))
+            chan_rx.append(r)
+    cfgs = np.array(cfgs, g.CHAN_CFG)
+    states = np.array(states, g.CHAN_STATE)
+    chan_rx = np.array(chan_rx)
+    assert len(set(chan_rx.tolist())) < 300 and max(chan_rx) > 256
+    expect = _oracle_all(rx, cfgs, states, chan_rx)
+    b = _make_batch(g, ctx, rx, cfgs, states, chan_rx)
+    try:
+        s0 = b.state.clone()
+        for grid, chunk in ((0, 0), (0, -1), (5, 2)):
+            b.configure(0, grid, chunk)
+            b.state.copy_(s0)
+            b.out.fill_(7)
+            b.launch()
+            _check(b, cfgs, expect)
+    finally:
+        b.close()

@@ -203,3 +203,25 @@ def test_32_samples_per_chip_edge(g, ctx, rate_scale):
     lib, lst = run_library(torch, ctx, 1, g.GC_CARRIER_LUT, cfgs, states, blocks, lens)
     orc, ost = run_oracle(1, cfgs, states, blocks, lens)
     assert_exact(lib, lst, orc, ost, cfgs)
+
+
+@pytest.mark.parametrize("fs, rate_scale", [
+    (10.7415e6, 1.0 + 2e-6),     # 10.5 samples per chip: whole samples per two chips
+    (20.46e6, 1.0 + 3.05e-5),    # drift per two chips just below the direct form's bound
+    (20.46e6, 1.0 + 3.10e-5),    # just above it: every window by the scatter
+    (16.368e6, 1.0 - 1.5e-5),    # frequent row crossings, negative drift
+])
+@pytest.mark.parametrize("fmt", [1, 3])
+def test_direct_cells_rates_bit_exact(g, ctx, fs, rate_scale, fmt):
+    # Rates that exercise the multi-tap kernel's direct-cell form and its
+    # fallback: half-integer samples per chip, drifts near the bound on
+    # |D2 dp - 2^33| (many row crossings, windows switching between the two
+    # forms), both signs of the drift; 128 taps, dumps of 1/4/1/20 periods,
+    # blocks that cut windows and dumps anywhere.
+    rng = np.random.default_rng(740 + fmt)
+    cfgs, states = _channels(g, rng, fs, 4, TAPS_128, rates=(1.023e6 * rate_scale,))
+    lens = [90_000, 7040 * 3 + 12, 33_001]
+    blocks = _blocks(rng, fmt, lens)
+    lib, lst = run_library(torch, ctx, fmt, g.GC_CARRIER_LUT, cfgs, states, blocks, lens)
+    orc, ost = run_oracle(fmt, cfgs, states, blocks, lens)
+    assert_exact(lib, lst, orc, ost, cfgs)
