@@ -271,14 +271,15 @@ def time_steps(torch, step, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
-def plain_baseline(torch, g, ctx, st, cfgs, states, samples, n, max_dumps, stream, steps, warmup):
+def plain_baseline(torch, g, ctx, st, cfgs, states, samples, n, max_dumps, stream, steps, warmup,
+                   carrier=None):
     """Plain per-channel launches: one plan and one launch per channel, each
     with the direct per-sample kernel, on the same stream and inputs, and
     timed like the headline steps (the library's kernel events on every
     call).  Returns (seconds per step, mean direct-kernel ms per call)."""
     plans, bufs = [], []
     for i in range(len(cfgs)):
-        p = g.Plan(ctx, st.fmt, g.GC_CARRIER_LUT, cfgs[i: i + 1])
+        p = g.Plan(ctx, st.fmt, g.GC_CARRIER_LUT if carrier is None else carrier, cfgs[i: i + 1])
         g.gc_plan_set_kernels(p.handle, 0)
         s0 = p.states_to_device(states[i: i + 1])
         plans.append(p)
@@ -1014,11 +1015,12 @@ def main():
     if args.workload == "twelve" and not f32 and not args.no_served:
         served = served_slice(g, ctx)
     plain_dt = None
-    if not args.no_plain and not f32:
+    if not args.no_plain:
         print("bench: plain per-channel launches", file=sys.stderr, flush=True)
         psteps = 1 if args.workload == "multicorrelator" else max(1, args.steps)
         plain_dt, plain_kms = plain_baseline(torch, g, ctx, st, cfgs, states, samples, n,
-                                             max_dumps, stream, psteps, 1)
+                                             max_dumps, stream, psteps, 1,
+                                             g.GC_CARRIER_F32 if f32 else g.GC_CARRIER_LUT)
     print("bench: warmup %d" % args.warmup, file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()

@@ -239,12 +239,15 @@ __global__ __launch_bounds__(64) void k_setup(const DevChan* __restrict__ chans,
             m.tail_beg = (uint32_t)tb;
             m.path = kPathDirect;
             m.bin_len = 0;
-            const bool epl_ok = c.epl && carrier == GC_CARRIER_LUT && m.c_full1 > m.c_full0;
-            if (epl_ok && (allow & kAllowPeriodic) && !fmt_complex(fmt)) {
+            const bool lut = carrier == GC_CARRIER_LUT;
+            const bool epl_ok = c.epl && m.c_full1 > m.c_full0;
+            if (epl_ok && lut && (allow & kAllowPeriodic) && !fmt_complex(fmt)) {
                 m.bin_len = periodic_bin_len(fmt, m.dp);
                 if (m.bin_len) m.path = kPathPeriodic;
             }
-            if (m.path == kPathDirect && epl_ok && (allow & kAllowBinned) && binned_ok(fmt, m.dp))
+            // (float bin sums have no int16 bound)
+            if (m.path == kPathDirect && epl_ok && (allow & kAllowBinned) &&
+                (lut ? binned_ok(fmt, m.dp) : binned_geometry_ok(m.dp)))
                 m.path = kPathBinned;
             // dense taps on the 1/32-chip grid: at most one sample per 1/32 chip
             if (m.path == kPathDirect && (allow & kAllowMtap) && c.mt_ok &&

@@ -105,9 +105,11 @@ __device__ __forceinline__ uint64_t bin_plane_max(int fmt) {
 // step.  A chip must fit in the staged margin, and a half-chip bin sum must
 // fit int16 (bin length <= q + 1 samples, q = floor(2^31 / dp)).
 constexpr int kEplMarginSamples = 128;
+__device__ __forceinline__ bool binned_geometry_ok(uint64_t dp) {
+    return dp != 0 && dp < (1ull << 31) && dp * (kEplMarginSamples - 1) >= (1ull << 32);
+}
 __device__ __forceinline__ bool binned_ok(int fmt, uint64_t dp) {
-    if (dp == 0 || dp >= (1ull << 31)) return false;
-    if (dp * (kEplMarginSamples - 1) < (1ull << 32)) return false;
+    if (!binned_geometry_ok(dp)) return false;
     const uint64_t q = (1ull << 31) / dp;
     return (q + 1) * bin_plane_max(fmt) <= 32767ull;
 }

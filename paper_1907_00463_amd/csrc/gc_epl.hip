@@ -386,6 +386,182 @@ __device__ __forceinline__ void direct_range(const void* __restrict__ sx, const 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Float carrier (GC_CARRIER_F32): the same bins and runs with the carrier
+// (cos, sin)(2 pi ph) from carrier_f32 and float sums.  A lane's run starts
+// from its first sample's phase in FP64 (reduced to [0, 1)); inside a bin
+// sample j takes ph + j * ff in fp32, and the bin's phase advance is added
+// and reduced once per bin.  Dumps and the state's open dump are float.
+struct DestF {
+    float* out;
+    gc_chan_state* st;
+    uint64_t row0;        // ch * max_dumps
+    int tap_stride;
+    uint32_t m_close;
+    __device__ __forceinline__ float* at(uint32_t w, int slot, int comp) const {
+        if (w < m_close) return out + ((row0 + w) * tap_stride + slot) * 2 + comp;
+        return &st->acc_f[slot][comp];
+    }
+};
+
+__device__ __forceinline__ float sign_f(uint32_t word) { return (float)(int)(short)(word & 0xFFFF); }
+
+// Wiped-off (I, Q) of one bin of len samples (Q > 0: q or q + 1 samples,
+// the last weighted 0 or 1; Q == 0: any length).
+template <int FMT, int Q>
+__device__ __forceinline__ void bin_f32(const void* __restrict__ sx, uint32_t nb, float ph, float ff,
+                                        uint32_t len, float& bi, float& bq) {
+    bi = 0.0f;
+    bq = 0.0f;
+    auto one = [&](uint32_t j, float wt) {
+        float c, s;
+        carrier_f32(ph + (float)j * ff, c, s);
+        if constexpr (fmt_complex(FMT)) {
+            const uint32_t xw = static_cast<const uint32_t*>(sx)[nb + j];
+            const float xi = wt * (float)(int)(short)(xw & 0xFFFF);
+            const float xq = wt * (float)(int)(short)(xw >> 16);
+            bi += xi * c + xq * s;
+            bq += xq * c - xi * s;
+        } else {
+            const float x = wt * (float)static_cast<const short*>(sx)[nb + j];
+            bi += x * c;
+            bq -= x * s;
+        }
+    };
+    if constexpr (Q > 0) {
+#pragma unroll
+        for (int j = 0; j < Q; ++j) one((uint32_t)j, 1.0f);
+        one((uint32_t)Q, len > (uint32_t)Q ? 1.0f : 0.0f);
+    } else {
+        for (uint32_t j = 0; j < len; ++j) one(j, 1.0f);
+    }
+}
+
+// Float run of one lane over chips [c, c + K) (as epl_run): ph0 is the phase
+// of its first sample in cycles, reduced to [0, 1).
+template <int FMT, int Q>
+__device__ __forceinline__ void epl_run_f32(const void* __restrict__ sx, uint32_t nb, float ph,
+                                            float ff, uint32_t e, uint32_t dp, uint32_t q,
+                                            uint32_t r, uint32_t c, uint32_t K, uint32_t Kmax,
+                                            uint32_t span, const uint32_t* __restrict__ sgn,
+                                            const DestF d, const DevChan& ch) {
+    float v[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};  // E, P, L: I, Q
+    uint32_t w = (uint32_t)max(0.0f, (float)c * (1.0f / (float)span) - 1.0f);
+    while ((w + 1) * span <= c) ++w;
+    uint32_t wnext = (w + 1) * span;
+    float sp = sign_f(sgn[0]), sc = sign_f(sgn[1]), sn = sign_f(sgn[2]);
+    const int slot[3] = {ch.slot_e, ch.slot_p, ch.slot_l};
+    const bool active = K > 0;
+    for (uint32_t k = 0; k < Kmax; ++k) {
+        if (k < K) {
+            if (c == wnext) {  // a dump closes before this chip
+#pragma unroll
+                for (int t = 0; t < 6; ++t) {
+                    atomicAdd(d.at(w, slot[t >> 1], t & 1), v[t]);
+                    v[t] = 0.0f;
+                }
+                w += 1;
+                wnext += span;
+            }
+            const float snn = sign_f(sgn[k + 3]);
+            float bi, bq;
+            // bin 0: E, P use C[c], L uses C[c-1]
+            bool lt = e < r;
+            uint32_t len = q + (lt ? 1u : 0u);
+            e = lt ? e + dp - r : e - r;
+            bin_f32<FMT, Q>(sx, nb, ph, ff, len, bi, bq);
+            v[0] += bi * sc; v[1] += bq * sc;
+            v[2] += bi * sc; v[3] += bq * sc;
+            v[4] += bi * sp; v[5] += bq * sp;
+            nb += len;
+            ph += (float)len * ff;
+            ph -= floorf(ph);
+            // bin 1: E uses C[c+1], P, L use C[c]
+            lt = e < r;
+            len = q + (lt ? 1u : 0u);
+            e = lt ? e + dp - r : e - r;
+            bin_f32<FMT, Q>(sx, nb, ph, ff, len, bi, bq);
+            v[0] += bi * sn; v[1] += bq * sn;
+            v[2] += bi * sc; v[3] += bq * sc;
+            v[4] += bi * sc; v[5] += bq * sc;
+            nb += len;
+            ph += (float)len * ff;
+            ph -= floorf(ph);
+            sp = sc;
+            sc = sn;
+            sn = snn;
+            c += 1;
+        }
+    }
+    // dump of the lane's last chip: equal dumps are contiguous lanes, each
+    // group summed once
+    uint64_t pending = __ballot(active);
+    while (pending) {
+        const int first = __ffsll((unsigned long long)pending) - 1;
+        const uint32_t wsel = __builtin_amdgcn_readlane(w, first);
+        const bool mine = active && w == wsel;
+#pragma unroll
+        for (int t = 0; t < 6; ++t) {
+            const float tot = wave_sum(mine ? v[t] : 0.0f);
+            if ((int)(threadIdx.x & 63) == first) atomicAdd(d.at(wsel, slot[t >> 1], t & 1), tot);
+        }
+        pending &= ~__ballot(mine);
+    }
+}
+
+// Float direct per-sample form over tile offsets [lo, hi) for up to 4 taps
+// (as direct_range; each sample's phase in FP64).
+template <int FMT>
+__device__ __forceinline__ void direct_range_f32(const void* __restrict__ sx, uint32_t gtid,
+                                                 uint32_t nthr, uint64_t t0, uint32_t lo,
+                                                 uint32_t hi, const DevMeta& m, const DevChan& ch,
+                                                 const uint32_t* __restrict__ sgn_prn,
+                                                 const DestF d) {
+    if (lo >= hi) return;
+    const uint64_t W = m.window;
+    const uint64_t wa = (m.p0 + (t0 + lo) * m.dp) / W;
+    const uint64_t wb = (m.p0 + (t0 + hi - 1) * m.dp) / W;
+    const int nk = ch.n_taps;
+    for (uint64_t w = wa; w <= wb; ++w) {
+        const uint64_t s_lo = window_start(w, W, m.p0, m.dp);
+        const uint64_t s_hi = window_start(w + 1, W, m.p0, m.dp);
+        const uint32_t a = (uint32_t)max((uint64_t)lo, s_lo > t0 ? s_lo - t0 : 0);
+        const uint32_t b = (uint32_t)min((uint64_t)hi, s_hi - t0);
+        float acc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        for (uint32_t i = a + gtid; i < b; i += nthr) {
+            const uint64_t n = t0 + i;
+            const double p = m.phf0 + (double)n * m.ff;
+            float c, s;
+            carrier_f32((float)(p - floor(p)), c, s);
+            float wi, wq;
+            if constexpr (fmt_complex(FMT)) {
+                const uint32_t xw = static_cast<const uint32_t*>(sx)[i];
+                wipe<GC_I8_IQ, float>((float)(int)(short)(xw & 0xFFFF),
+                                      (float)(int)(short)(xw >> 16), c, s, wi, wq);
+            } else {
+                wipe<GC_I8_REAL, float>((float)static_cast<const short*>(sx)[i], 0.0f, c, s, wi,
+                                        wq);
+            }
+            const uint64_t u = m.p0 + n * m.dp;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (k < nk) {
+                    const int64_t v = (int64_t)u + ch.taps[k];
+                    int32_t chip = (int32_t)(v >> 32) % kCodeLen;
+                    if (chip < 0) chip += kCodeLen;
+                    const float r = sign_f(sgn_prn[chip]);
+                    acc[2 * k] += wi * r;
+                    acc[2 * k + 1] += wq * r;
+                }
+            }
+        }
+        for (int k = 0; k < 2 * nk; ++k) {
+            const float t = wave_sum(acc[k]);
+            if ((threadIdx.x & 63) == 0 && t != 0.0f) atomicAdd(d.at((uint32_t)w, k >> 1, k & 1), t);
+        }
+    }
+}
+
 template <int FMT, int kThreads, int kXSamples>
 __device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, uint64_t n,
                                            uint64_t t0, void* sx, const uint32_t* tables) {
@@ -459,7 +635,7 @@ __device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, 
 
 // Channels [c_begin, c_end) of one receiver on its staged tile [t0, t1);
 // n_act of them are left to this kernel (not refused, not periodic).
-template <int FMT, class SH>
+template <int FMT, class SH, int CARR = GC_CARRIER_LUT>
 __device__ __forceinline__ void epl_tile(const void* __restrict__ s_x, const uint8_t* lut,
                                          uint64_t t0, uint64_t t1, int c_begin, int c_end,
                                          int n_act,
@@ -495,21 +671,25 @@ __device__ __forceinline__ void epl_tile(const void* __restrict__ s_x, const uin
         const DevMeta m = metas[chn];
         const DevChan& ch = chans[chn];
         const Dest d{out, state + chn, (uint64_t)chn * max_dumps, tap_stride, m.m_close};
+        const DestF df{reinterpret_cast<float*>(out), state + chn, (uint64_t)chn * max_dumps,
+                       tap_stride, m.m_close};
         const uint32_t* sgn_prn = tables + kTabSign + (ch.prn - 1) * kSignLen;
         const uint32_t tl = (uint32_t)(t1 - t0);
+        auto direct = [&](uint32_t lo, uint32_t hi) {
+            if constexpr (CARR == GC_CARRIER_F32)
+                direct_range_f32<FMT>(s_x, gtid, kGroup, t0, lo, hi, m, ch, sgn_prn, df);
+            else
+                direct_range<FMT>(s_x, lut, gtid, kGroup, lane4, t0, lo, hi, m, ch, sgn_prn, d);
+        };
         if (m.path != kPathBinned) {
-            direct_range<FMT>(s_x, lut, gtid, kGroup, lane4, t0, 0, tl, m, ch, sgn_prn, d);
+            direct(0, tl);
             continue;
         }
         // block-edge samples outside whole chips
         {
             const uint64_t he = m.head_end, tb = m.tail_beg;
-            if (he > t0)
-                direct_range<FMT>(s_x, lut, gtid, kGroup, lane4, t0, 0, (uint32_t)min(he, t1) - (uint32_t)t0,
-                                       m, ch, sgn_prn, d);
-            if (t1 > tb)
-                direct_range<FMT>(s_x, lut, gtid, kGroup, lane4, t0, (uint32_t)(max(tb, t0) - t0), tl, m,
-                                       ch, sgn_prn, d);
+            if (he > t0) direct(0, (uint32_t)min(he, t1) - (uint32_t)t0);
+            if (t1 > tb) direct((uint32_t)(max(tb, t0) - t0), tl);
         }
         // whole chips whose first sample lies in [t0, t1)
         const uint64_t u0 = m.p0 + t0 * m.dp;
@@ -528,6 +708,7 @@ __device__ __forceinline__ void epl_tile(const void* __restrict__ s_x, const uin
         const uint32_t dp = (uint32_t)m.dp;
         const float inv_dp = 1.0f / (float)dp;
         uint32_t nrel = 0, e = 0, phi = 0;
+        float phf = 0.0f;
         if (K > 0) {
             // first sample of chip c: ceil((c*2^32 - u0) / dp), estimated with
             // a float reciprocal (D < 2^47, so the estimate is within a few
@@ -539,14 +720,22 @@ __device__ __forceinline__ void epl_tile(const void* __restrict__ s_x, const uin
             nrel = (uint32_t)nr;
             e = (uint32_t)(nr * dp - D);
             phi = m.phi0 + (uint32_t)(t0 + nrel) * m.dphi;
+            if constexpr (CARR == GC_CARRIER_F32) {
+                const double p = m.phf0 + (double)(t0 + nrel) * m.ff;
+                phf = (float)(p - floor(p));
+            }
         }
         const uint32_t q = (uint32_t)((1ull << 31) / dp);
         const uint32_t r = (uint32_t)((1ull << 31) - (uint64_t)q * dp);
         const uint32_t span = (uint32_t)(m.window >> 32);
         const uint32_t* sgn = sgn_prn + (c + kCodeLen - 1) % kCodeLen;
-#define GC_RUN(QQ)                                                                          \
-    epl_run<FMT, QQ>(s_x, lut, lane4, nrel, phi, m.dphi, e, dp, q, r, c, K, Kmax, span, sgn, \
-                     d, ch)
+#define GC_RUN(QQ)                                                                           \
+    if constexpr (CARR == GC_CARRIER_F32)                                                     \
+        epl_run_f32<FMT, QQ>(s_x, nrel, phf, (float)m.ff, e, dp, q, r, c, K, Kmax, span, sgn, \
+                             df, ch);                                                         \
+    else                                                                                      \
+        epl_run<FMT, QQ>(s_x, lut, lane4, nrel, phi, m.dphi, e, dp, q, r, c, K, Kmax, span, sgn, \
+                         d, ch)
         switch (q) {  // bins of q or q + 1 samples
             case 1: GC_RUN(1); break;
             case 2: GC_RUN(2); break;
@@ -565,7 +754,7 @@ __device__ __forceinline__ void epl_tile(const void* __restrict__ s_x, const uin
 // One tile [t0, t0 + kTile) of a block of n samples for channels [c_begin,
 // c_end): staged and correlated whole (real input) or as two half tiles
 // (complex input, one dword per sample).
-template <int FMT, class SH>
+template <int FMT, class SH, int CARR = GC_CARRIER_LUT>
 __device__ __forceinline__ void tile_pass(const uint8_t* __restrict__ samples, uint64_t n,
                                           uint64_t t0, void* s_x, const uint8_t* lut,
                                           int c_begin, int c_end, int n_act,
@@ -585,12 +774,12 @@ __device__ __forceinline__ void tile_pass(const uint8_t* __restrict__ samples, u
         __syncthreads();
         stage_tile<FMT, SH::kThreads, kStaged>(samples, n, a, s_x, tables);
         __syncthreads();
-        epl_tile<FMT, SH>(s_x, lut, a, b, c_begin, c_end, n_act, chans, metas, state, out,
-                          tap_stride, max_dumps, tables);
+        epl_tile<FMT, SH, CARR>(s_x, lut, a, b, c_begin, c_end, n_act, chans, metas, state, out,
+                                tap_stride, max_dumps, tables);
     }
 }
 
-template <int FMT>
+template <int FMT, int CARR>
 __global__ __launch_bounds__(ShapePlan::kThreads) void k_epl(
     const uint8_t* __restrict__ samples, uint64_t n, const DevChan* __restrict__ chans,
     const DevMeta* __restrict__ metas, gc_chan_state* __restrict__ state,
@@ -608,12 +797,13 @@ __global__ __launch_bounds__(ShapePlan::kThreads) void k_epl(
     for (int c = 0; c < n_chan; ++c)
         n_act += metas[c].status == GC_OK && metas[c].path != kPathPeriodic;
     if (n_act == 0) return;
-    for (int i = tid; i < kLutWords; i += SH::kThreads) s_lut[i] = tables[kTabLut + (i >> 6)];
+    if constexpr (CARR == GC_CARRIER_LUT)
+        for (int i = tid; i < kLutWords; i += SH::kThreads) s_lut[i] = tables[kTabLut + (i >> 6)];
 
     for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const uint64_t t0 = (uint64_t)tile * SH::kTile;
-        tile_pass<FMT, SH>(samples, n, t0, s_x, s_lds, 0, n_chan, n_act, chans, metas, state, out,
-                           tap_stride, max_dumps, tables);
+        tile_pass<FMT, SH, CARR>(samples, n, t0, s_x, s_lds, 0, n_chan, n_act, chans, metas, state,
+                                 out, tap_stride, max_dumps, tables);
     }
 }
 
@@ -667,10 +857,6 @@ __global__ __launch_bounds__(SH::kThreads) void k_epl_batch(
     }
 }
 
-// The work items of k_epl_batch that have work: the tiles of every receiver
-// with a channel that is neither refused nor on the periodic path, in
-// receiver order, into order[0 .. *count) (one block; a block-wide scan of
-// the receivers' tile counts gives each receiver its place).
 }  // namespace
 
 int epl_blocks_per_device(int device) {
@@ -680,29 +866,46 @@ int epl_blocks_per_device(int device) {
     return cus > 0 ? cus : 256;
 }
 
-hipError_t launch_epl(const uint8_t* samples, uint64_t n, int fmt, const DevChan* chans,
-                      const DevMeta* meta, gc_chan_state* state, int n_chan, int32_t* out,
-                      int tap_stride, uint32_t max_dumps, const uint32_t* tables, int grid,
-                      hipStream_t s) {
+hipError_t launch_epl(const uint8_t* samples, uint64_t n, int fmt, int carrier,
+                      const DevChan* chans, const DevMeta* meta, gc_chan_state* state, int n_chan,
+                      int32_t* out, int tap_stride, uint32_t max_dumps, const uint32_t* tables,
+                      int grid, hipStream_t s) {
     if (n == 0) return hipSuccess;
     using SH = ShapePlan;
     const uint32_t n_tiles = (uint32_t)((n + SH::kTile - 1) / SH::kTile);
     const int g = (int)min((uint32_t)grid, n_tiles);
+#define GC_EPL(F, C)                                                                         \
+    hipLaunchKernelGGL((k_epl<F, C>), dim3(g), dim3(SH::kThreads), 0, s, samples, n, chans, \
+                       meta, state, out, tap_stride, max_dumps, tables, n_chan, n_tiles)
+    const bool f32 = carrier == GC_CARRIER_F32;
     if (fmt == GC_I2_REAL) {
-        hipLaunchKernelGGL((k_epl<GC_I2_REAL>), dim3(g), dim3(SH::kThreads), 0, s, samples, n, chans,
-                           meta, state, out, tap_stride, max_dumps, tables, n_chan, n_tiles);
+        if (f32) {
+            GC_EPL(GC_I2_REAL, GC_CARRIER_F32);
+        } else {
+            GC_EPL(GC_I2_REAL, GC_CARRIER_LUT);
+        }
     } else if (fmt == GC_I8_REAL) {
-        hipLaunchKernelGGL((k_epl<GC_I8_REAL>), dim3(g), dim3(SH::kThreads), 0, s, samples, n, chans,
-                           meta, state, out, tap_stride, max_dumps, tables, n_chan, n_tiles);
+        if (f32) {
+            GC_EPL(GC_I8_REAL, GC_CARRIER_F32);
+        } else {
+            GC_EPL(GC_I8_REAL, GC_CARRIER_LUT);
+        }
     } else if (fmt == GC_I2_IQ) {
-        hipLaunchKernelGGL((k_epl<GC_I2_IQ>), dim3(g), dim3(SH::kThreads), 0, s, samples, n, chans,
-                           meta, state, out, tap_stride, max_dumps, tables, n_chan, n_tiles);
+        if (f32) {
+            GC_EPL(GC_I2_IQ, GC_CARRIER_F32);
+        } else {
+            GC_EPL(GC_I2_IQ, GC_CARRIER_LUT);
+        }
     } else if (fmt == GC_I8_IQ) {
-        hipLaunchKernelGGL((k_epl<GC_I8_IQ>), dim3(g), dim3(SH::kThreads), 0, s, samples, n, chans,
-                           meta, state, out, tap_stride, max_dumps, tables, n_chan, n_tiles);
+        if (f32) {
+            GC_EPL(GC_I8_IQ, GC_CARRIER_F32);
+        } else {
+            GC_EPL(GC_I8_IQ, GC_CARRIER_LUT);
+        }
     } else {
         return hipErrorInvalidValue;
     }
+#undef GC_EPL
     return hipGetLastError();
 }
 

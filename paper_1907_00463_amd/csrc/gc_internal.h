@@ -179,10 +179,11 @@ hipError_t launch_mtap(const uint8_t* samples, uint64_t n_samples, int fmt, cons
                        const DevMeta* meta, gc_chan_state* state, int n_chan, int32_t* out,
                        int tap_stride, uint32_t max_dumps, const uint32_t* d_tables, int grid,
                        hipStream_t s);
-hipError_t launch_epl(const uint8_t* samples, uint64_t n_samples, int fmt, const DevChan* chans,
-                      const DevMeta* meta, gc_chan_state* state, int n_chan, int32_t* out,
-                      int tap_stride, uint32_t max_dumps, const uint32_t* d_tables, int grid,
-                      hipStream_t s);
+// carrier: GC_CARRIER_LUT (integer dumps) or GC_CARRIER_F32 (float dumps in out)
+hipError_t launch_epl(const uint8_t* samples, uint64_t n_samples, int fmt, int carrier,
+                      const DevChan* chans, const DevMeta* meta, gc_chan_state* state, int n_chan,
+                      int32_t* out, int tap_stride, uint32_t max_dumps, const uint32_t* d_tables,
+                      int grid, hipStream_t s);
 int epl_blocks_per_device(int device);
 hipError_t launch_lock_metrics(const int32_t* rows, int stride, int col, const uint32_t* n_dumps,
                                int n_chan, uint32_t max_dumps, uint32_t K, double T,

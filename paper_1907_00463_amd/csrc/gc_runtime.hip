@@ -22,7 +22,7 @@ struct gc_plan {
     int max_taps;
     gc::DevChan* d_chans;
     gc::DevMeta* d_meta;
-    int use_epl;      // all channels <= 4 taps, integer carrier
+    int use_epl;      // all channels <= 4 taps (chip-by-chip kernel, either carrier)
     int use_mtap;     // table carrier and some channel has dense 1/32-chip taps
     int kernels;      // GC_KERNEL_* mask
     int epl_grid;     // persistent blocks of the binned kernel
@@ -149,7 +149,7 @@ hipError_t run_correlation(const Launches& L, const void* samples, uint64_t n_sa
             e = gc::launch_pbin(x, n_samples, L.fmt, L.chans, L.meta, state, L.n_chan, o,
                                 L.tap_stride, max_dumps, L.tables, L.grid, s);
         else if (L.binned)
-            e = gc::launch_epl(x, n_samples, L.fmt, L.chans, L.meta, state, L.n_chan, o,
+            e = gc::launch_epl(x, n_samples, L.fmt, L.carrier, L.chans, L.meta, state, L.n_chan, o,
                                L.tap_stride, max_dumps, L.tables, L.grid, s);
         else
             e = gc::launch_generic(x, n_samples, L.fmt, L.carrier, L.chans, L.meta, state,
@@ -158,7 +158,7 @@ hipError_t run_correlation(const Launches& L, const void* samples, uint64_t n_sa
     }
     if (e == hipSuccess && L.ev_mid) e = hipEventRecord(L.ev_mid, s);
     if (e == hipSuccess && L.periodic)
-        e = gc::launch_epl(x, n_samples, L.fmt, L.chans, L.meta, state, L.n_chan, o,
+        e = gc::launch_epl(x, n_samples, L.fmt, L.carrier, L.chans, L.meta, state, L.n_chan, o,
                            L.tap_stride, max_dumps, L.tables, L.grid, s);
     if (e == hipSuccess && L.mtap)
         e = gc::launch_generic(x, n_samples, L.fmt, L.carrier, L.chans, L.meta, state,
@@ -320,7 +320,7 @@ gc_status gc_plan_create(gc_ctx* ctx, gc_format fmt, gc_carrier carrier, const g
     p->d_chans = nullptr;
     p->d_meta = nullptr;
     p->calls = 0;
-    p->use_epl = carrier == GC_CARRIER_LUT && max_taps <= 4;
+    p->use_epl = max_taps <= 4;
     p->use_mtap = 0;
     if (carrier == GC_CARRIER_LUT && !p->use_epl)
         for (int i = 0; i < n_chan; ++i) p->use_mtap |= h[(size_t)i].mt_ok;
@@ -490,7 +490,8 @@ gc_status gc_correlate(gc_plan* plan, const void* samples, uint64_t n_samples,
     L.carrier = plan->carrier;
     L.n_chan = plan->n_chan;
     L.tap_stride = plan->max_taps;
-    L.periodic = plan->use_epl && (plan->kernels & GC_KERNEL_PERIODIC) && !gc::fmt_complex(plan->fmt);
+    L.periodic = plan->use_epl && (plan->kernels & GC_KERNEL_PERIODIC) &&
+                 !gc::fmt_complex(plan->fmt) && plan->carrier == GC_CARRIER_LUT;
     L.binned = plan->use_epl && (plan->kernels & GC_KERNEL_BINNED);
     L.mtap = plan->use_mtap && (plan->kernels & GC_KERNEL_MTAP);
     L.grid = plan->epl_grid;
@@ -526,13 +527,13 @@ gc_status gc_correlate_noalloc(gc_ctx* ctx, gc_format fmt, gc_carrier carrier,
     hipStream_t s = (hipStream_t)stream;
     // the kernel families a plan with these channels would use: tap_stride
     // stands for the plan's largest n_taps
-    const bool use_epl = carrier == GC_CARRIER_LUT && tap_stride <= 4;
+    const bool use_epl = tap_stride <= 4;
     Launches L{};
     L.fmt = fmt;
     L.carrier = carrier;
     L.n_chan = n_chan;
     L.tap_stride = tap_stride;
-    L.periodic = use_epl && !gc::fmt_complex(fmt);
+    L.periodic = use_epl && !gc::fmt_complex(fmt) && carrier == GC_CARRIER_LUT;
     L.binned = use_epl;
     L.mtap = carrier == GC_CARRIER_LUT && !use_epl;
     L.grid = ctx->n_cu;

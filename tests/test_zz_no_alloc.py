@@ -159,7 +159,7 @@ def test_noalloc_multitap_equals_plan(g, ctx):
 
 
 def test_noalloc_float_carrier_equals_plan(g, ctx):
-    """FP32 carrier on real int8 (the direct kernel, float atomics)."""
+    """FP32 carrier on real int8 (the chip-by-chip kernel, float atomics)."""
     rng = np.random.default_rng(7004)
     fs = 4.092e6
     cfgs, states = _chans(g, rng, 3, fs, fs / 4, np.array([1 << 31, 0, -(1 << 31)], np.int64))
