@@ -181,17 +181,19 @@ gc_status gc_plan_destroy(gc_plan* plan);
 
 /* Kernel families a plan may use for its E/P/L channels (bit mask).  Every
  * family computes the same integer sums (the definition of Eqs. (1)-(3)
- * with the table carrier); the choice only changes speed.
+ * with the table carrier; with the float carrier, sums within the stated
+ * bound); the choice only changes speed.
  *   GC_KERNEL_PERIODIC  half chips of exactly 2, 4, 8 or 10 samples with a
  *                       bounded grid slip (fs an integer multiple of twice the
- *                       code rate)
+ *                       code rate), real input, table carrier
  *   GC_KERNEL_BINNED    any rate of >= 2^32/127 code step, chip by chip
+ *                       (table or float carrier)
  *   GC_KERNEL_MTAP      plans with more than 4 taps: channels whose taps are
  *                       all multiples of 2^27 (1/32 chip) spanning at most 8
  *                       chip shifts, at <= 32 samples per chip (two-stage
  *                       int8 MFMA form, table carrier)
- * Channels that no allowed family takes, and every channel of a plan with
- * the float carrier, use the direct per-sample kernel.  Default: all bits
+ * Channels that no allowed family takes, and every channel of a float-carrier
+ * plan with more than 4 taps, use the direct per-sample kernel.  Default: all bits
  * set.  Takes effect at the next gc_correlate.
  * Errors: GC_EINVAL (null plan, bits outside the mask). */
 #define GC_KERNEL_PERIODIC 1
@@ -248,9 +250,10 @@ gc_status gc_correlate(gc_plan* plan, const void* samples, uint64_t n_samples,
  *              passed the call)
  *   n_chan     1 .. GC_NOALLOC_MAX_CHANNELS
  *   tap_stride taps per output row, 1 .. GC_MAX_TAPS; it also picks the
- *              kernels as a plan's largest n_taps does (<= 4 with the table
- *              carrier: the E/P/L kernels; more: the multi-tap and direct
- *              kernels; float carrier: the direct kernel)
+ *              kernels as a plan's largest n_taps does (<= 4: the E/P/L
+ *              kernels, the periodic one only with the table carrier; more:
+ *              the multi-tap and direct kernels, the direct kernel alone
+ *              with the float carrier)
  *   the rest   as for gc_correlate, with the plan's format and carrier given
  *              here
  * A channel whose cfg a plan would refuse (PRN, n_taps, int_periods,
