@@ -508,6 +508,9 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
     const uint32_t dp32 = (uint32_t)m.dp;
     const uint32_t X2 = 8u * (uint32_t)D2;          // tile bytes per two chips
     const uint32_t F2 = (uint32_t)D2 * m.dphi;      // carrier phase per two chips
+    const uint32_t X2s = __builtin_amdgcn_readfirstlane(X2);
+    const uint32_t F2s = __builtin_amdgcn_readfirstlane(F2);
+    const uint64_t Z2s = ((uint64_t)F2s << 32) | X2s;  // both strides in one word
 
     // contiguous chunk of tiles for this block; chunks belong to the tile
     // holding their first sample
@@ -607,6 +610,9 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
             uint32_t x0 = dx, f0 = df;
             asm("" : "+v"(x0));
             asm("" : "+v"(f0));
+            // the window's four MFMA operands (either form), then one MFMA
+            // chain for both: the accumulator stays in one register set
+            int4_t aop[4];
             if (direct) {
                 // stage 1 in registers: dword i of K step ks is the cell of
                 // window position 8 ks + h + 2 i, row l32
@@ -615,21 +621,25 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
                 // reads the zero table and forms 0 cells)
                 uint2 xv[4];
                 uint32_t cv[4];
-                auto load_step = [&](int ks, uint2* xs, uint32_t* cs) {
+                // running sample address (low word) and carrier phase (high
+                // word), stepped by the uniform two-chip strides with one
+                // 64-bit add: the address stays far below 2^32, so no carry
+                // reaches the phase, and the phase wraps as a 32-bit word
+                uint64_t zc = ((uint64_t)f0 << 32) | x0;
+                auto load_step = [&](uint2* xs, uint32_t* cs) {
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const uint32_t t = (uint32_t)(4 * ks + i);
-                        const uint32_t ph = f0 + t * F2;
-                        cs[i] = *reinterpret_cast<const uint32_t*>(s_lds + lutb + ((ph >> 24) << 2));
-                        xs[i] = x_at(x0 + t * X2);
+                        cs[i] = *reinterpret_cast<const uint32_t*>(s_lds + lutb + ((uint32_t)(zc >> 56) << 2));
+                        xs[i] = x_at((uint32_t)zc);
+                        zc += Z2s;
                     }
                 };
-                load_step(0, xv, cv);
+                load_step(xv, cv);
 #pragma unroll
                 for (int ks = 0; ks < 4; ++ks) {
                     uint2 xn[4];
                     uint32_t cn[4];
-                    if (ks < 3) load_step(ks + 1, xn, cn);
+                    if (ks < 3) load_step(xn, cn);
                     // cell_of for four cells, the +128 kept inside the first
                     // multiply-add of each
                     short2_t pp[4];
@@ -639,14 +649,12 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
                         pp[i] = as_s2(xv[i].y) * __builtin_shufflevector(c2, c2, 1, 1) + k128;
                     }
                     asm("" : "+v"(pp[0]), "+v"(pp[1]), "+v"(pp[2]), "+v"(pp[3]));
-                    int4_t a;
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const short2_t c2 = as_s2(cv[i]);
                         const short2_t w2 = as_s2(xv[i].x) * __builtin_shufflevector(c2, c2, 0, 0) + pp[i];
-                        a[i] = (int)(__builtin_bit_cast(uint32_t, w2) ^ 0x00800080u);
+                        aop[ks][i] = (int)(__builtin_bit_cast(uint32_t, w2) ^ 0x00800080u);
                     }
-                    acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, bop[ks], acc0, 0, 0, 0);
                     if (ks < 3) {
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
@@ -654,7 +662,6 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
                             cv[i] = cn[i];
                         }
                     }
-                    __builtin_amdgcn_sched_barrier(0);
                 }
             } else {
                 // stage 1: clear S (32 x 32 cells), scatter the chunk's samples
@@ -719,18 +726,19 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
                     if (lane + 64 < rest) cell_store(a1, v1);
                 }
                 wave_fence();
-                // stage 2: four K steps of 8 chips, 32 rows q x 32 columns
+                // stage 2 operands: four K steps of 8 chips, 32 rows q
 #pragma unroll
                 for (int ks = 0; ks < 4; ++ks) {
                     const uint8_t* ap = s_lds + a_base + 1024u * ks;
-                    const int4_t a = int4_t{*reinterpret_cast<const int*>(ap),
-                                            *reinterpret_cast<const int*>(ap + 256),
-                                            *reinterpret_cast<const int*>(ap + 512),
-                                            *reinterpret_cast<const int*>(ap + 768)};
-                    acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, bop[ks], acc0, 0, 0, 0);
+                    aop[ks] = int4_t{*reinterpret_cast<const int*>(ap),
+                                     *reinterpret_cast<const int*>(ap + 256),
+                                     *reinterpret_cast<const int*>(ap + 512),
+                                     *reinterpret_cast<const int*>(ap + 768)};
                 }
-
             }
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks)
+                acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(aop[ks], bop[ks], acc0, 0, 0, 0);
             dx += 16u * X2;
             df += 16u * F2;
             dr += 16 * d2;
