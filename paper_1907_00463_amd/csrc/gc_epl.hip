@@ -562,10 +562,94 @@ __device__ __forceinline__ void direct_range_f32(const void* __restrict__ sx, ui
     }
 }
 
+// A nibble of two 2-bit codes (sample j in bits [2j, 2j+1], code c -> 2c - 3)
+// as an int16 pair.
+__device__ __forceinline__ uint32_t codes_to_pair(uint32_t nib) {
+    const short2_t c = as_s2((nib * 0x4001u) & 0x00030003u);
+    const short2_t two = {2, 2}, m3 = {-3, -3};
+    return as_u32(c * two + m3);
+}
+
+// Two int8 samples (bytes 0 and 1 of v) as an int16 pair.
+__device__ __forceinline__ uint32_t bytes_to_pair(uint32_t v) {
+    return ((uint32_t)(uint16_t)(int16_t)(int8_t)(v & 0xFF)) |
+           ((uint32_t)(uint16_t)(int16_t)(int8_t)((v >> 8) & 0xFF) << 16);
+}
+
 template <int FMT, int kThreads, int kXSamples>
 __device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, uint64_t n,
                                            uint64_t t0, void* sx, const uint32_t* tables) {
     uint2* dst = reinterpret_cast<uint2*>(sx);  // 4 samples per 8 bytes (2 for complex)
+    // A staged range inside the block (every one but the block's last):
+    // units of 8 complex or 16 real samples (8, 4, 4 or 16 input bytes, 32
+    // bytes out), four per thread and pass with all four loads issued before
+    // any is decoded, so that the pass waits for memory once (a unit past
+    // the end loads the last one and is not stored; the empty asm takes
+    // every loaded value, so no load is left for after the first wait).
+    constexpr int kPer = fmt_complex(FMT) ? 8 : 16;
+    if constexpr (kXSamples % kPer == 0) {
+        if (t0 + kXSamples <= n) {
+            constexpr int kUnits = kXSamples / kPer;
+            constexpr int kPasses = (kUnits + kThreads - 1) / kThreads;
+            constexpr int kP = kPasses < 4 ? kPasses : 4;
+            auto raw = [&](int u) {
+                uint4 r = uint4{0u, 0u, 0u, 0u};
+                if constexpr (FMT == GC_I8_IQ) {
+                    const uint2* src = reinterpret_cast<const uint2*>(samples + 2 * (t0 + 8ull * u));
+                    const uint2 a = src[0], b = src[1];
+                    r = uint4{a.x, a.y, b.x, b.y};
+                } else if constexpr (FMT == GC_I2_IQ) {
+                    r.x = *reinterpret_cast<const uint32_t*>(samples + (t0 + 8ull * u) / 2);
+                } else if constexpr (FMT == GC_I2_REAL) {
+                    r.x = *reinterpret_cast<const uint32_t*>(samples + (t0 + 16ull * u) / 4);
+                } else {
+                    const uint2* src = reinterpret_cast<const uint2*>(samples + t0 + 16ull * u);
+                    const uint2 a = src[0], b = src[1];
+                    r = uint4{a.x, a.y, b.x, b.y};
+                }
+                return r;
+            };
+            auto put = [&](int u, const uint4 r) {
+                const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    uint2 o;
+                    if constexpr (FMT == GC_I8_IQ || FMT == GC_I8_REAL) {
+                        // two samples (complex) or four (real) per input dword
+                        o.x = bytes_to_pair(w[k]);
+                        o.y = bytes_to_pair(w[k] >> 16);
+                    } else if constexpr (FMT == GC_I2_IQ) {
+                        // one byte: two complex samples, a nibble each
+                        const uint32_t v = (w[0] >> (8 * k)) & 0xFFu;
+                        o.x = codes_to_pair(v & 15u);
+                        o.y = codes_to_pair(v >> 4);
+                    } else {
+                        // one byte: four real samples
+                        const uint32_t v = (w[0] >> (8 * k)) & 0xFFu;
+                        o.x = codes_to_pair(v & 15u);
+                        o.y = codes_to_pair(v >> 4);
+                    }
+                    dst[4 * u + k] = o;
+                }
+            };
+            for (int u0 = threadIdx.x; u0 < kUnits; u0 += kP * kThreads) {
+                uint4 r[4] = {};
+#pragma unroll
+                for (int p = 0; p < kP; ++p) r[p] = raw(min(u0 + p * kThreads, kUnits - 1));
+                asm volatile(""
+                             : "+v"(r[0].x), "+v"(r[0].y), "+v"(r[0].z), "+v"(r[0].w),
+                               "+v"(r[1].x), "+v"(r[1].y), "+v"(r[1].z), "+v"(r[1].w),
+                               "+v"(r[2].x), "+v"(r[2].y), "+v"(r[2].z), "+v"(r[2].w),
+                               "+v"(r[3].x), "+v"(r[3].y), "+v"(r[3].z), "+v"(r[3].w));
+#pragma unroll
+                for (int p = 0; p < kP; ++p) {
+                    const int u = u0 + p * kThreads;
+                    if (u < kUnits) put(u, r[p]);
+                }
+            }
+            return;
+        }
+    }
     if constexpr (FMT == GC_I8_IQ) {
         // kXSamples complex samples from t0 (a multiple of 4): the 4 bytes of
         // two samples give two (xI, xQ) int16 dwords
