@@ -576,9 +576,12 @@ __device__ __forceinline__ uint32_t bytes_to_pair(uint32_t v) {
            ((uint32_t)(uint16_t)(int16_t)(int8_t)((v >> 8) & 0xFF) << 16);
 }
 
+// Samples [t0, t0 + count) of the block into LDS (zero past its end); count
+// is at most kXSamples and a multiple of 8 (complex) or 16 (real input).
 template <int FMT, int kThreads, int kXSamples>
 __device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, uint64_t n,
-                                           uint64_t t0, void* sx, const uint32_t* tables) {
+                                           uint64_t t0, void* sx, const uint32_t* tables,
+                                           uint32_t count) {
     uint2* dst = reinterpret_cast<uint2*>(sx);  // 4 samples per 8 bytes (2 for complex)
     // A staged range inside the block (every one but the block's last):
     // units of 8 complex or 16 real samples (8, 4, 4 or 16 input bytes, 32
@@ -587,73 +590,71 @@ __device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, 
     // the end loads the last one and is not stored; the empty asm takes
     // every loaded value, so no load is left for after the first wait).
     constexpr int kPer = fmt_complex(FMT) ? 8 : 16;
-    if constexpr (kXSamples % kPer == 0) {
-        if (t0 + kXSamples <= n) {
-            constexpr int kUnits = kXSamples / kPer;
-            constexpr int kPasses = (kUnits + kThreads - 1) / kThreads;
-            constexpr int kP = kPasses < 4 ? kPasses : 4;
-            auto raw = [&](int u) {
-                uint4 r = uint4{0u, 0u, 0u, 0u};
-                if constexpr (FMT == GC_I8_IQ) {
-                    const uint2* src = reinterpret_cast<const uint2*>(samples + 2 * (t0 + 8ull * u));
-                    const uint2 a = src[0], b = src[1];
-                    r = uint4{a.x, a.y, b.x, b.y};
-                } else if constexpr (FMT == GC_I2_IQ) {
-                    r.x = *reinterpret_cast<const uint32_t*>(samples + (t0 + 8ull * u) / 2);
-                } else if constexpr (FMT == GC_I2_REAL) {
-                    r.x = *reinterpret_cast<const uint32_t*>(samples + (t0 + 16ull * u) / 4);
-                } else {
-                    const uint2* src = reinterpret_cast<const uint2*>(samples + t0 + 16ull * u);
-                    const uint2 a = src[0], b = src[1];
-                    r = uint4{a.x, a.y, b.x, b.y};
-                }
-                return r;
-            };
-            auto put = [&](int u, const uint4 r) {
-                const uint32_t w[4] = {r.x, r.y, r.z, r.w};
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    uint2 o;
-                    if constexpr (FMT == GC_I8_IQ || FMT == GC_I8_REAL) {
-                        // two samples (complex) or four (real) per input dword
-                        o.x = bytes_to_pair(w[k]);
-                        o.y = bytes_to_pair(w[k] >> 16);
-                    } else if constexpr (FMT == GC_I2_IQ) {
-                        // one byte: two complex samples, a nibble each
-                        const uint32_t v = (w[0] >> (8 * k)) & 0xFFu;
-                        o.x = codes_to_pair(v & 15u);
-                        o.y = codes_to_pair(v >> 4);
-                    } else {
-                        // one byte: four real samples
-                        const uint32_t v = (w[0] >> (8 * k)) & 0xFFu;
-                        o.x = codes_to_pair(v & 15u);
-                        o.y = codes_to_pair(v >> 4);
-                    }
-                    dst[4 * u + k] = o;
-                }
-            };
-            for (int u0 = threadIdx.x; u0 < kUnits; u0 += kP * kThreads) {
-                uint4 r[4] = {};
-#pragma unroll
-                for (int p = 0; p < kP; ++p) r[p] = raw(min(u0 + p * kThreads, kUnits - 1));
-                asm volatile(""
-                             : "+v"(r[0].x), "+v"(r[0].y), "+v"(r[0].z), "+v"(r[0].w),
-                               "+v"(r[1].x), "+v"(r[1].y), "+v"(r[1].z), "+v"(r[1].w),
-                               "+v"(r[2].x), "+v"(r[2].y), "+v"(r[2].z), "+v"(r[2].w),
-                               "+v"(r[3].x), "+v"(r[3].y), "+v"(r[3].z), "+v"(r[3].w));
-#pragma unroll
-                for (int p = 0; p < kP; ++p) {
-                    const int u = u0 + p * kThreads;
-                    if (u < kUnits) put(u, r[p]);
-                }
+    constexpr int kMaxPasses = (kXSamples / kPer + kThreads - 1) / kThreads;
+    constexpr int kP = kMaxPasses < 4 ? kMaxPasses : 4;
+    if (count % kPer == 0 && t0 + count <= n) {
+        const int units = (int)(count / kPer);
+        auto raw = [&](int u) {
+            uint4 r = uint4{0u, 0u, 0u, 0u};
+            if constexpr (FMT == GC_I8_IQ) {
+                const uint2* src = reinterpret_cast<const uint2*>(samples + 2 * (t0 + 8ull * u));
+                const uint2 a = src[0], b = src[1];
+                r = uint4{a.x, a.y, b.x, b.y};
+            } else if constexpr (FMT == GC_I2_IQ) {
+                r.x = *reinterpret_cast<const uint32_t*>(samples + (t0 + 8ull * u) / 2);
+            } else if constexpr (FMT == GC_I2_REAL) {
+                r.x = *reinterpret_cast<const uint32_t*>(samples + (t0 + 16ull * u) / 4);
+            } else {
+                const uint2* src = reinterpret_cast<const uint2*>(samples + t0 + 16ull * u);
+                const uint2 a = src[0], b = src[1];
+                r = uint4{a.x, a.y, b.x, b.y};
             }
-            return;
+            return r;
+        };
+        auto put = [&](int u, const uint4 r) {
+            const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                uint2 o;
+                if constexpr (FMT == GC_I8_IQ || FMT == GC_I8_REAL) {
+                    // two samples (complex) or four (real) per input dword
+                    o.x = bytes_to_pair(w[k]);
+                    o.y = bytes_to_pair(w[k] >> 16);
+                } else if constexpr (FMT == GC_I2_IQ) {
+                    // one byte: two complex samples, a nibble each
+                    const uint32_t v = (w[0] >> (8 * k)) & 0xFFu;
+                    o.x = codes_to_pair(v & 15u);
+                    o.y = codes_to_pair(v >> 4);
+                } else {
+                    // one byte: four real samples
+                    const uint32_t v = (w[0] >> (8 * k)) & 0xFFu;
+                    o.x = codes_to_pair(v & 15u);
+                    o.y = codes_to_pair(v >> 4);
+                }
+                dst[4 * u + k] = o;
+            }
+        };
+        for (int u0 = threadIdx.x; u0 < units; u0 += kP * kThreads) {
+            uint4 r[4] = {};
+#pragma unroll
+            for (int p = 0; p < kP; ++p) r[p] = raw(min(u0 + p * kThreads, units - 1));
+            asm volatile(""
+                         : "+v"(r[0].x), "+v"(r[0].y), "+v"(r[0].z), "+v"(r[0].w),
+                           "+v"(r[1].x), "+v"(r[1].y), "+v"(r[1].z), "+v"(r[1].w),
+                           "+v"(r[2].x), "+v"(r[2].y), "+v"(r[2].z), "+v"(r[2].w),
+                           "+v"(r[3].x), "+v"(r[3].y), "+v"(r[3].z), "+v"(r[3].w));
+#pragma unroll
+            for (int p = 0; p < kP; ++p) {
+                const int u = u0 + p * kThreads;
+                if (u < units) put(u, r[p]);
+            }
         }
+        return;
     }
     if constexpr (FMT == GC_I8_IQ) {
-        // kXSamples complex samples from t0 (a multiple of 4): the 4 bytes of
+        // count complex samples from t0 (a multiple of 4): the 4 bytes of
         // two samples give two (xI, xQ) int16 dwords
-        for (int i = threadIdx.x; i < kXSamples / 2; i += kThreads) {
+        for (int i = threadIdx.x; i < (int)count / 2; i += kThreads) {
             const uint64_t smp = t0 + 2ull * i;
             uint32_t v = 0;
             if (smp + 2 <= n) {
@@ -671,7 +672,7 @@ __device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, 
     } else if constexpr (FMT == GC_I2_IQ) {
         // t0 is even: byte t0/2 + i holds tile samples 2i and 2i+1, each a
         // nibble of I then Q codes; samples past the block read as zero
-        for (int i = threadIdx.x; i < kXSamples / 2; i += kThreads) {
+        for (int i = threadIdx.x; i < (int)count / 2; i += kThreads) {
             const uint64_t smp = t0 + 2ull * i;
             const uint32_t v = smp < n ? samples[smp >> 1] : 0u;
             const auto iq = [](uint32_t nib) {
@@ -687,7 +688,7 @@ __device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, 
         // t0 is a multiple of 4: byte t0/4 + i holds tile samples 4i .. 4i+3
         const uint64_t nbytes = (n + 3) / 4;
         const uint64_t b0 = t0 / 4;
-        for (int i = threadIdx.x; i < kXSamples / 4; i += kThreads) {
+        for (int i = threadIdx.x; i < (int)count / 4; i += kThreads) {
             const uint64_t b = b0 + i;
             uint2 o = {0u, 0u};
             if (b < nbytes) {
@@ -698,7 +699,7 @@ __device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, 
             dst[i] = o;
         }
     } else {
-        for (int i = threadIdx.x; i < kXSamples / 4; i += kThreads) {
+        for (int i = threadIdx.x; i < (int)count / 4; i += kThreads) {
             const uint64_t b = t0 + 4ull * i;
             uint32_t v = 0;
             if (b + 4 <= n) {
@@ -835,12 +836,14 @@ __device__ __forceinline__ void epl_tile(const void* __restrict__ s_x, const uin
     }
 }
 
-// One tile [t0, t0 + kTile) of a block of n samples for channels [c_begin,
-// c_end): staged and correlated whole (real input) or as two half tiles
-// (complex input, one dword per sample).
+// One tile [t0, t0 + tile_len) of a block of n samples for channels
+// [c_begin, c_end): staged and correlated whole (real input) or as two half
+// tiles (complex input, one dword per sample).  tile_len is at most SH::kTile
+// and a multiple of 16.
 template <int FMT, class SH, int CARR = GC_CARRIER_LUT>
 __device__ __forceinline__ void tile_pass(const uint8_t* __restrict__ samples, uint64_t n,
-                                          uint64_t t0, void* s_x, const uint8_t* lut,
+                                          uint64_t t0, uint32_t tile_len, void* s_x,
+                                          const uint8_t* lut,
                                           int c_begin, int c_end, int n_act,
                                           const DevChan* __restrict__ chans,
                                           const DevMeta* __restrict__ metas,
@@ -848,15 +851,15 @@ __device__ __forceinline__ void tile_pass(const uint8_t* __restrict__ samples, u
                                           int32_t* __restrict__ out, int tap_stride,
                                           uint32_t max_dumps, const uint32_t* __restrict__ tables) {
     constexpr int kParts = fmt_complex(FMT) ? 2 : 1;
-    constexpr int kPart = SH::kTile / kParts;
     constexpr int kStaged = fmt_complex(FMT) ? SH::kXSamplesIQ : SH::kXSamples;
+    const uint32_t part = tile_len / kParts;
 #pragma unroll
     for (int h = 0; h < kParts; ++h) {
-        const uint64_t a = t0 + (uint64_t)h * kPart;
+        const uint64_t a = t0 + (uint64_t)h * part;
         if (a >= n) break;
-        const uint64_t b = min(n, a + kPart);
+        const uint64_t b = min(n, a + part);
         __syncthreads();
-        stage_tile<FMT, SH::kThreads, kStaged>(samples, n, a, s_x, tables);
+        stage_tile<FMT, SH::kThreads, kStaged>(samples, n, a, s_x, tables, part + kMargin);
         __syncthreads();
         epl_tile<FMT, SH, CARR>(s_x, lut, a, b, c_begin, c_end, n_act, chans, metas, state, out,
                                 tap_stride, max_dumps, tables);
@@ -868,7 +871,7 @@ __global__ __launch_bounds__(ShapePlan::kThreads) void k_epl(
     const uint8_t* __restrict__ samples, uint64_t n, const DevChan* __restrict__ chans,
     const DevMeta* __restrict__ metas, gc_chan_state* __restrict__ state,
     int32_t* __restrict__ out, int tap_stride, uint32_t max_dumps,
-    const uint32_t* __restrict__ tables, int n_chan, uint32_t n_tiles) {
+    const uint32_t* __restrict__ tables, int n_chan, uint32_t n_tiles, uint32_t tile_len) {
     using SH = ShapePlan;
     // one LDS block: the per-lane carrier tables at offset 0 (so the v_perm
     // result is the address itself), then the staged samples
@@ -885,9 +888,9 @@ __global__ __launch_bounds__(ShapePlan::kThreads) void k_epl(
         for (int i = tid; i < kLutWords; i += SH::kThreads) s_lut[i] = tables[kTabLut + (i >> 6)];
 
     for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const uint64_t t0 = (uint64_t)tile * SH::kTile;
-        tile_pass<FMT, SH, CARR>(samples, n, t0, s_x, s_lds, 0, n_chan, n_act, chans, metas, state,
-                                 out, tap_stride, max_dumps, tables);
+        const uint64_t t0 = (uint64_t)tile * tile_len;
+        tile_pass<FMT, SH, CARR>(samples, n, t0, tile_len, s_x, s_lds, 0, n_chan, n_act, chans,
+                                 metas, state, out, tap_stride, max_dumps, tables);
     }
 }
 
@@ -927,16 +930,16 @@ __global__ __launch_bounds__(SH::kThreads) void k_epl_batch(
         if (n_act == 0) continue;
         const uint64_t t0 = (uint64_t)(item - R.tile_begin) * SH::kTile;
         if (R.fmt == GC_I2_REAL)
-            tile_pass<GC_I2_REAL, SH>(R.samples, R.n, t0, s_x, s_lds, R.chan_begin, R.chan_end, n_act,
+            tile_pass<GC_I2_REAL, SH>(R.samples, R.n, t0, SH::kTile, s_x, s_lds, R.chan_begin, R.chan_end, n_act,
                                       chans, metas, state, out, tap_stride, max_dumps, tables);
         else if (R.fmt == GC_I8_IQ)
-            tile_pass<GC_I8_IQ, SH>(R.samples, R.n, t0, s_x, s_lds, R.chan_begin, R.chan_end, n_act,
+            tile_pass<GC_I8_IQ, SH>(R.samples, R.n, t0, SH::kTile, s_x, s_lds, R.chan_begin, R.chan_end, n_act,
                                     chans, metas, state, out, tap_stride, max_dumps, tables);
         else if (R.fmt == GC_I2_IQ)
-            tile_pass<GC_I2_IQ, SH>(R.samples, R.n, t0, s_x, s_lds, R.chan_begin, R.chan_end, n_act,
+            tile_pass<GC_I2_IQ, SH>(R.samples, R.n, t0, SH::kTile, s_x, s_lds, R.chan_begin, R.chan_end, n_act,
                                     chans, metas, state, out, tap_stride, max_dumps, tables);
         else
-            tile_pass<GC_I8_REAL, SH>(R.samples, R.n, t0, s_x, s_lds, R.chan_begin, R.chan_end, n_act,
+            tile_pass<GC_I8_REAL, SH>(R.samples, R.n, t0, SH::kTile, s_x, s_lds, R.chan_begin, R.chan_end, n_act,
                                       chans, metas, state, out, tap_stride, max_dumps, tables);
     }
 }
@@ -956,11 +959,28 @@ hipError_t launch_epl(const uint8_t* samples, uint64_t n, int fmt, int carrier,
                       int grid, hipStream_t s) {
     if (n == 0) return hipSuccess;
     using SH = ShapePlan;
-    const uint32_t n_tiles = (uint32_t)((n + SH::kTile - 1) / SH::kTile);
+    // Balanced tiles: every block takes k = ceil(n / (kTile grid)) tiles, of
+    // 256 m samples with m the smallest odd number reaching n / (k grid), so
+    // that the last round does not leave blocks idle.  256 m keeps a group's
+    // lane runs an odd or half-odd number of LDS dwords apart (few bank
+    // conflicts for complex samples, one dword each); taken only when it
+    // shortens the largest block's share by more than 1/16, as other
+    // lengths can split the chips of a periodic-rate tile unevenly over the
+    // lanes.
+    constexpr uint64_t kMinTile = 2048;
+    const uint64_t G = (uint64_t)max(grid, 1);
+    const uint64_t per = (n + (uint64_t)SH::kTile * G - 1) / ((uint64_t)SH::kTile * G);
+    uint64_t m = ((n + per * G - 1) / (per * G) + 255) / 256;
+    m |= 1;
+    const uint64_t cand = max(kMinTile, 256 * m);
+    const uint64_t tl = 16 * cand < 15 * (uint64_t)SH::kTile ? cand : (uint64_t)SH::kTile;
+    const uint32_t tile_len = (uint32_t)tl;
+    const uint32_t n_tiles = (uint32_t)((n + tl - 1) / tl);
     const int g = (int)min((uint32_t)grid, n_tiles);
 #define GC_EPL(F, C)                                                                         \
     hipLaunchKernelGGL((k_epl<F, C>), dim3(g), dim3(SH::kThreads), 0, s, samples, n, chans, \
-                       meta, state, out, tap_stride, max_dumps, tables, n_chan, n_tiles)
+                       meta, state, out, tap_stride, max_dumps, tables, n_chan, n_tiles,     \
+                       tile_len)
     const bool f32 = carrier == GC_CARRIER_F32;
     if (fmt == GC_I2_REAL) {
         if (f32) {

@@ -207,18 +207,19 @@ __device__ __forceinline__ void chunk_next(Chunk& k, uint64_t span, uint64_t dp,
     k.sb = min(n, k.fb);
 }
 
-// Tile samples [t0, t0 + kXSamples) as two int16 pairs each: (xI, xQ) and
+// Tile samples [t0, t0 + count) as two int16 pairs each: (xI, xQ) and
 // (xQ, -xI) (real input: (x, 0) and (0, -x)); zero past the block.  Each
 // thread takes units of 8 samples: one 16-byte (complex int8), 8-byte (real
 // int8), 4-byte (2-bit complex) or 2-byte (2-bit real) load, four 16-byte
 // LDS stores.
 template <int FMT>
 __device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, uint64_t n,
-                                           uint64_t t0, uint8_t* lds, int nthreads) {
+                                           uint64_t t0, uint8_t* lds, int nthreads,
+                                           uint32_t count) {
     static_assert(kXSamples % 8 == 0, "staging unit");
     uint4* dst = reinterpret_cast<uint4*>(lds + kOffX);
-    const uint32_t avail = (uint32_t)min(n - t0, (uint64_t)kXSamples);
-    for (int u = threadIdx.x; u < kXSamples / 8; u += nthreads) {
+    const uint32_t avail = (uint32_t)min(n - t0, (uint64_t)count);
+    for (int u = threadIdx.x; u < (int)count / 8; u += nthreads) {
         const uint32_t s0 = 8u * (uint32_t)u;
         const bool whole = s0 + 8 <= avail;
         int xi[8], xq[8];
@@ -407,7 +408,8 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
                                                       int32_t* __restrict__ out, int tap_stride,
                                                       uint32_t max_dumps,
                                                       const uint32_t* __restrict__ tables,
-                                                      int n_chan, uint32_t n_tiles) {
+                                                      int n_chan, uint32_t n_tiles,
+                                                      uint32_t tile_len) {
     __shared__ __attribute__((aligned(16))) uint8_t s_lds[kLdsBytes];
     int* s_list = reinterpret_cast<int*>(s_lds + kOffList);
     const int tid = threadIdx.x;
@@ -516,7 +518,8 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
     // holding their first sample
     const uint32_t tb0 = (uint32_t)(((uint64_t)blockIdx.x * n_tiles) / gridDim.x);
     const uint32_t tb1 = (uint32_t)(((uint64_t)(blockIdx.x + 1) * n_tiles) / gridDim.x);
-    const uint64_t T0 = (uint64_t)tb0 * kTile;
+    const uint64_t T0 = (uint64_t)tb0 * tile_len;
+    const uint32_t staged = tile_len + kMargin;  // samples staged per tile
 
     i32x16 acc0;
 #pragma unroll
@@ -549,15 +552,15 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
     int32_t dr = 0;
     uint64_t dw0 = ~0ull;
     for (uint32_t tile = tb0; tile < tb1; ++tile) {
-        const uint64_t t0 = (uint64_t)tile * kTile;
-        const uint64_t t1 = min(n, t0 + kTile);
+        const uint64_t t0 = (uint64_t)tile * tile_len;
+        const uint64_t t1 = min(n, t0 + tile_len);
         __syncthreads();
-        stage_tile<FMT>(samples, n, t0, s_lds, nthreads);
+        stage_tile<FMT>(samples, n, t0, s_lds, nthreads, staged);
         __syncthreads();
         if (!active) continue;
         if (tile > tb0) {
-            xsa -= 8u * kTile;
-            dx -= 8u * kTile;
+            xsa -= 8u * tile_len;
+            dx -= 8u * tile_len;
         }
         while (k.sa < t1 && k.sa < k.sb) {
             // the window's replica operand, in flight during stage 1
@@ -672,7 +675,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
                 }
                 wave_fence();
                 // at most 32 chips of at most 32 samples, inside the staged tile
-                const uint32_t cnt = min(adv, (uint32_t)(kXSamples - (uint32_t)(k.sa - t0)));
+                const uint32_t cnt = min(adv, (uint32_t)(staged - (uint32_t)(k.sa - t0)));
                 uint64_t U = Ua + lane_dU;
                 uint32_t ph = pha + lane_dph, xa = xsa + lane * 8u;
                 // pairs of full steps, software-pipelined over two register
@@ -766,12 +769,22 @@ template <int FMT>
 void launch_one(const uint8_t* samples, uint64_t n, const DevChan* chans, const DevMeta* meta,
                 gc_chan_state* state, int n_chan, int32_t* out, int tap_stride, uint32_t max_dumps,
                 const uint32_t* tables, int grid, hipStream_t s) {
-    const uint32_t n_tiles = (uint32_t)((n + kTile - 1) / kTile);
+    // every block takes the same number of tiles: k = ceil(n / (kTile grid))
+    // each, of ceil(n / (k grid)) samples rounded up to 16 (at most kTile, at
+    // least kMinTile)
+    constexpr uint64_t kMinTile = 2048;
+    const uint64_t G = (uint64_t)max(grid, 1);
+    const uint64_t per = (n + (uint64_t)kTile * G - 1) / ((uint64_t)kTile * G);
+    uint64_t tl = (n + per * G - 1) / (per * G);
+    tl = min((uint64_t)kTile, max(kMinTile, (tl + 15) & ~15ull));
+    const uint32_t tile_len = (uint32_t)tl;
+    const uint32_t n_tiles = (uint32_t)((n + tl - 1) / tl);
     const int g = (int)min((uint32_t)grid, n_tiles);
     const int waves = min(n_chan, kWaves);
     const int groups = (n_chan + kWaves - 1) / kWaves;
     hipLaunchKernelGGL((k_mtap<FMT>), dim3(g, groups), dim3(64 * waves), 0, s, samples, n, chans,
-                       meta, state, out, tap_stride, max_dumps, tables, n_chan, n_tiles);
+                       meta, state, out, tap_stride, max_dumps, tables, n_chan, n_tiles,
+                       tile_len);
 }
 
 }  // namespace

@@ -9,7 +9,8 @@
 // code Doppler "slip").  Bin k of a run then starts at sample s_0 + k*L, so
 // consecutive lanes can take consecutive bins with fixed per-lane offsets:
 //
-//   * a block streams through a contiguous chunk of tiles of kTile samples,
+//   * a block streams through a contiguous chunk of tiles (of at most kTile
+//     samples, sized per launch so that the blocks get equal shares),
 //     staged once in LDS as int16 in two copies (aligned, and shifted by one
 //     sample) so that every bin starts on a dword of one of them; each wave
 //     owns one channel and keeps its E/P/L sums in registers across tiles,
@@ -363,19 +364,20 @@ __device__ __forceinline__ uint32_t expand2(uint32_t nib) {
     return __builtin_bit_cast(uint32_t, c * two + m3);
 }
 
-// Tile samples [t0, t0 + kXSamples) into copies A and B (int16; zero past
-// the end of the block).
+// Tile samples [t0, t0 + count) into copies A and B (int16; zero past the
+// end of the block); count is at most kXSamples and a multiple of 16.
 template <int FMT>
 __device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, uint64_t n,
-                                           uint64_t t0, uint8_t* lds, int nthreads) {
+                                           uint64_t t0, uint8_t* lds, int nthreads,
+                                           uint32_t count) {
     static_assert(kXSamples % 16 == 0, "staging granule");
     uint4* dA = reinterpret_cast<uint4*>(lds + kXA);
     uint4* dB = reinterpret_cast<uint4*>(lds + kXB);
     if constexpr (FMT == GC_I2_REAL) {
         // one input dword (16 samples) per thread and pass
         const uint8_t* src = samples + t0 / 4;
-        const uint32_t avail = (uint32_t)min((n - t0 + 3) / 4, (uint64_t)kXSamples / 4);  // bytes
-        for (int i = threadIdx.x; i < kXSamples / 16; i += nthreads) {
+        const uint32_t avail = (uint32_t)min((n - t0 + 3) / 4, (uint64_t)count / 4);  // bytes
+        for (int i = threadIdx.x; i < (int)count / 16; i += nthreads) {
             const uint32_t b = 4u * i;
             uint32_t v = 0, nx = 0;
             if (b + 4 <= avail) {
@@ -406,8 +408,8 @@ __device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, 
     } else {
         // 16 int8 samples per thread and pass
         const uint8_t* src = samples + t0;
-        const uint32_t avail = (uint32_t)min(n - t0, (uint64_t)kXSamples);
-        for (int i = threadIdx.x; i < kXSamples / 16; i += nthreads) {
+        const uint32_t avail = (uint32_t)min(n - t0, (uint64_t)count);
+        for (int i = threadIdx.x; i < (int)count / 16; i += nthreads) {
             const uint32_t b = 16u * i;
             uint32_t v[5] = {0, 0, 0, 0, 0};
             if (b + 16 <= avail) {
@@ -545,7 +547,8 @@ __device__ __forceinline__ void channel_tile(Slot& S, const uint8_t* lds, uint32
     }
 }
 
-// Tiles [tb0, tb1) of one sample block for the block's channel list
+// Tiles [tb0, tb1) of tile_len samples (at most kTile, a multiple of 16) of
+// one sample block for the block's channel list
 // s_list[0 .. nlist), nlist <= blockDim.x / 64.  The channels' bins are
 // shared evenly among W waves (W below): wave w takes positions [w*nlist,
 // (w+1)*nlist) of nlist*W, channel c holding [c*W, (c+1)*W), so each wave
@@ -556,7 +559,7 @@ __device__ __forceinline__ void channel_tile(Slot& S, const uint8_t* lds, uint32
 template <int FMT>
 __device__ __forceinline__ void pbin_chunk(uint8_t* s_lds, const int* s_list, int nlist,
                                            const uint8_t* __restrict__ samples, uint64_t n,
-                                           uint32_t tb0, uint32_t tb1,
+                                           uint32_t tb0, uint32_t tb1, uint32_t tile_len,
                                            const DevChan* __restrict__ chans,
                                            const DevMeta* __restrict__ metas,
                                            gc_chan_state* __restrict__ state,
@@ -615,10 +618,10 @@ __device__ __forceinline__ void pbin_chunk(uint8_t* s_lds, const int* s_list, in
         reset();
     };
     for (uint32_t tile = tb0; tile < tb1; ++tile) {
-        const uint64_t t0 = (uint64_t)tile * kTile;
-        const uint64_t t1 = min(n, t0 + kTile);
+        const uint64_t t0 = (uint64_t)tile * tile_len;
+        const uint64_t t1 = min(n, t0 + tile_len);
         __syncthreads();
-        stage_tile<FMT>(samples, n, t0, s_lds, nthreads);
+        stage_tile<FMT>(samples, n, t0, s_lds, nthreads, tile_len + kMarginS);
         __syncthreads();
         for (uint32_t j = 0; j < (busy ? (two ? 2u : 1u) : 0u); ++j) {
             const uint32_t slot = j ? cB : cA;
@@ -647,7 +650,9 @@ __device__ __forceinline__ void list_periodic(int* s_list, const DevMeta* __rest
     }
 }
 
-template <int FMT>
+// FIXED: tiles of kTile samples (tile_len unused), the common case, where a
+// compile-time tile length keeps the walk's scalar state out of spill slots
+template <int FMT, bool FIXED>
 __global__ __launch_bounds__(kMaxWaves * 64) void k_pbin(const uint8_t* __restrict__ samples,
                                                          uint64_t n,
                                                          const DevChan* __restrict__ chans,
@@ -657,7 +662,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) void k_pbin(const uint8_t* __restri
                                                          uint32_t max_dumps,
                                                          const uint32_t* __restrict__ tables,
                                                          int n_chan, uint32_t n_tiles,
-                                                         int per_block) {
+                                                         uint32_t tile_len, int per_block) {
     // one LDS block: the per-lane carrier tables at offset 0 (the v_perm
     // result is the address itself), the two staged copies, the channel list
     __shared__ __attribute__((aligned(16))) uint8_t s_lds[kLdsBytes + 4 * (kMaxWaves + 1)];
@@ -674,8 +679,8 @@ __global__ __launch_bounds__(kMaxWaves * 64) void k_pbin(const uint8_t* __restri
     // contiguous chunk of tiles for this block
     const uint32_t tb0 = (uint32_t)(((uint64_t)blockIdx.x * n_tiles) / gridDim.x);
     const uint32_t tb1 = (uint32_t)(((uint64_t)(blockIdx.x + 1) * n_tiles) / gridDim.x);
-    pbin_chunk<FMT>(s_lds, s_list, nlist, samples, n, tb0, tb1, chans, metas, state, out,
-                    tap_stride, max_dumps, tables);
+    pbin_chunk<FMT>(s_lds, s_list, nlist, samples, n, tb0, tb1, FIXED ? (uint32_t)kTile : tile_len,
+                    chans, metas, state, out, tap_stride, max_dumps, tables);
 }
 
 // Many receivers in one persistent launch: item i is a chunk of tiles of
@@ -710,11 +715,11 @@ __global__ __launch_bounds__(kMaxWaves * 64) void k_pbin_batch(
         const DevRx& X = rx[I.rx];
         if (X.fmt == GC_I2_REAL)
             pbin_chunk<GC_I2_REAL>(s_lds, s_list, nlist, X.samples, X.n, I.tile_begin,
-                                   I.tile_end, chans, metas, state, out, tap_stride, max_dumps,
+                                   I.tile_end, kTile, chans, metas, state, out, tap_stride, max_dumps,
                                    tables);
         else
             pbin_chunk<GC_I8_REAL>(s_lds, s_list, nlist, X.samples, X.n, I.tile_begin,
-                                   I.tile_end, chans, metas, state, out, tap_stride, max_dumps,
+                                   I.tile_end, kTile, chans, metas, state, out, tap_stride, max_dumps,
                                    tables);
     }
 }
@@ -723,7 +728,18 @@ template <int FMT>
 void launch_one(const uint8_t* samples, uint64_t n, const DevChan* chans, const DevMeta* meta,
                 gc_chan_state* state, int n_chan, int32_t* out, int tap_stride, uint32_t max_dumps,
                 const uint32_t* tables, int grid, hipStream_t s) {
-    const uint32_t n_tiles = (uint32_t)((n + kTile - 1) / kTile);
+    // Balanced tiles: every block takes k = ceil(n / (kTile grid)) tiles, of
+    // n / (k grid) samples rounded up to 512 (whole 64-lane steps of the 2-,
+    // 4- and 8-sample bins, as kTile is), so that the last round does not
+    // leave blocks idle; taken only when that shortens the largest block's
+    // share by more than 1/16 (below that it measured no faster).
+    constexpr uint64_t kMinTile = 2048;
+    const uint64_t G = (uint64_t)max(grid, 1);
+    const uint64_t per = (n + (uint64_t)kTile * G - 1) / ((uint64_t)kTile * G);
+    const uint64_t cand = max(kMinTile, ((n + per * G - 1) / (per * G) + 511) & ~511ull);
+    const uint64_t tl = 16 * cand < 15 * (uint64_t)kTile ? cand : (uint64_t)kTile;
+    const uint32_t tile_len = (uint32_t)tl;
+    const uint32_t n_tiles = (uint32_t)((n + tl - 1) / tl);
     const int g = (int)min((uint32_t)grid, n_tiles);
     // up to kMaxWaves channels per block, one wave each; a plan with fewer
     // channels lets R = kMaxWaves / n_chan waves share each channel (more
@@ -732,9 +748,14 @@ void launch_one(const uint8_t* samples, uint64_t n, const DevChan* chans, const 
     const int per_block = min(n_chan, kMaxWaves);
     const int R = kMaxWaves / per_block;
     const int groups = (n_chan + per_block - 1) / per_block;
-    hipLaunchKernelGGL((k_pbin<FMT>), dim3(g, groups), dim3(64 * per_block * R), 0, s, samples, n,
-                       chans, meta, state, out, tap_stride, max_dumps, tables, n_chan, n_tiles,
-                       per_block);
+    if (tile_len == (uint32_t)kTile)
+        hipLaunchKernelGGL((k_pbin<FMT, true>), dim3(g, groups), dim3(64 * per_block * R), 0, s,
+                           samples, n, chans, meta, state, out, tap_stride, max_dumps, tables,
+                           n_chan, n_tiles, tile_len, per_block);
+    else
+        hipLaunchKernelGGL((k_pbin<FMT, false>), dim3(g, groups), dim3(64 * per_block * R), 0, s,
+                           samples, n, chans, meta, state, out, tap_stride, max_dumps, tables,
+                           n_chan, n_tiles, tile_len, per_block);
 }
 
 }  // namespace
