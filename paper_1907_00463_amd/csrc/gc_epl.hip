@@ -866,7 +866,9 @@ __device__ __forceinline__ void tile_pass(const uint8_t* __restrict__ samples, u
     }
 }
 
-template <int FMT, int CARR>
+// FIXED: tiles of ShapePlan::kTile samples (tile_len unused), where a
+// compile-time tile length keeps scalar state out of spill slots
+template <int FMT, int CARR, bool FIXED>
 __global__ __launch_bounds__(ShapePlan::kThreads) void k_epl(
     const uint8_t* __restrict__ samples, uint64_t n, const DevChan* __restrict__ chans,
     const DevMeta* __restrict__ metas, gc_chan_state* __restrict__ state,
@@ -887,10 +889,11 @@ __global__ __launch_bounds__(ShapePlan::kThreads) void k_epl(
     if constexpr (CARR == GC_CARRIER_LUT)
         for (int i = tid; i < kLutWords; i += SH::kThreads) s_lut[i] = tables[kTabLut + (i >> 6)];
 
+    const uint32_t tl = FIXED ? (uint32_t)SH::kTile : tile_len;
     for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const uint64_t t0 = (uint64_t)tile * tile_len;
-        tile_pass<FMT, SH, CARR>(samples, n, t0, tile_len, s_x, s_lds, 0, n_chan, n_act, chans,
-                                 metas, state, out, tap_stride, max_dumps, tables);
+        const uint64_t t0 = (uint64_t)tile * tl;
+        tile_pass<FMT, SH, CARR>(samples, n, t0, tl, s_x, s_lds, 0, n_chan, n_act, chans, metas,
+                                 state, out, tap_stride, max_dumps, tables);
     }
 }
 
@@ -977,10 +980,18 @@ hipError_t launch_epl(const uint8_t* samples, uint64_t n, int fmt, int carrier,
     const uint32_t tile_len = (uint32_t)tl;
     const uint32_t n_tiles = (uint32_t)((n + tl - 1) / tl);
     const int g = (int)min((uint32_t)grid, n_tiles);
-#define GC_EPL(F, C)                                                                         \
-    hipLaunchKernelGGL((k_epl<F, C>), dim3(g), dim3(SH::kThreads), 0, s, samples, n, chans, \
-                       meta, state, out, tap_stride, max_dumps, tables, n_chan, n_tiles,     \
-                       tile_len)
+    const bool fixed = tile_len == (uint32_t)SH::kTile;
+#define GC_EPL(F, C)                                                                            \
+    do {                                                                                        \
+        if (fixed)                                                                              \
+            hipLaunchKernelGGL((k_epl<F, C, true>), dim3(g), dim3(SH::kThreads), 0, s, samples, \
+                               n, chans, meta, state, out, tap_stride, max_dumps, tables,       \
+                               n_chan, n_tiles, tile_len);                                      \
+        else                                                                                    \
+            hipLaunchKernelGGL((k_epl<F, C, false>), dim3(g), dim3(SH::kThreads), 0, s,         \
+                               samples, n, chans, meta, state, out, tap_stride, max_dumps,      \
+                               tables, n_chan, n_tiles, tile_len);                              \
+    } while (0)
     const bool f32 = carrier == GC_CARRIER_F32;
     if (fmt == GC_I2_REAL) {
         if (f32) {
