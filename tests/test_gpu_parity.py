@@ -399,6 +399,46 @@ def test_paper_workload_full_size_bit_exact(g, ctx):
     assert_exact(lib, lst, orc, sts, cfgs)
 
 
+def _epl_full_tiles(n, cus, tile=47104):
+    """Whether the chip-by-chip kernel keeps its full tiles for a block of n
+    samples on cus compute units: balanced tiles (256 m samples, m odd, k
+    per block) are taken only when they shorten the largest block share by
+    more than 1/16."""
+    per = -(-n // (tile * cus))
+    m = -(-(-(-n // (per * cus))) // 256) | 1
+    return not 16 * max(2048, 256 * m) < 15 * tile
+
+
+@pytest.mark.parametrize("name,seconds", [("iq2", 1.4), ("paper", 2.3)])
+def test_chip_by_chip_full_tiles_bit_exact(g, ctx, name, seconds):
+    # complex input at a length (about 11.5 M samples) for which the
+    # chip-by-chip kernel keeps its full 47,104-sample tiles (the instance
+    # with a compile-time tile length); the other tests' lengths take
+    # balanced tiles: every dump of every channel against the oracle
+    from concurrent.futures import ThreadPoolExecutor
+
+    from paper_1907_00463_amd import synth
+    make = {"iq2": synth.workload_iq2, "paper": synth.workload_paper}[name]
+    st, chans, rng = make(seconds=seconds)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    assert _epl_full_tiles(st.n, cus), (st.n, cus)
+    buf = synth.synth_samples(st, rng)
+    cfgs, states = _cfgs_states_for(g, st, chans)
+    lib, lst = run_library(torch, ctx, st.fmt, g.GC_CARRIER_LUT, cfgs, states, [buf], [st.n])
+    sts = [None] * len(cfgs)
+
+    def one(i):
+        r, s = run_oracle(st.fmt, cfgs[i: i + 1], states[i: i + 1], [buf], [st.n])
+        sts[i] = s[0]
+        return r[0][0][0], r[0][1][0]
+
+    with ThreadPoolExecutor(max_workers=12) as ex:
+        parts = list(ex.map(one, range(len(cfgs))))
+    orc = [([p[0] for p in parts], [p[1] for p in parts])]
+    assert int(lib[0][2].min()) >= int(seconds * 1000) - 1
+    assert_exact(lib, lst, orc, sts, cfgs)
+
+
 @pytest.mark.parametrize("name", ["iq2", "if_recording"])
 def test_more_formats_workloads_bit_exact(g, ctx, name):
     # 2-bit complex baseband at 8.184 MHz (chip-by-chip kernel) and a GN3S-style
