@@ -209,7 +209,8 @@ gc_status gc_plan_info(const gc_plan* plan, int32_t* tap_stride, int32_t* n_chan
  *
  *   samples   device, the block in the plan's format; n_samples samples
  *             (n_samples bytes, 2*n_samples bytes, ceil(n_samples/4) bytes or
- *             ceil(n_samples/2) bytes)
+ *             ceil(n_samples/2) bytes), starting on a 16-byte boundary (the
+ *             kernels read it in aligned words of 4 to 16 bytes)
  *   n_samples 0 .. 2^31-1
  *   state     device, gc_chan_state[n_chan], read and updated in place:
  *             NCO phases advance by n_samples, the open dump is carried
