@@ -26,9 +26,10 @@
 // dump is stored.
 //
 // One wave per channel (16 per block), blocks take contiguous chunks of
-// sample tiles; the tile (8 B per sample: (xI, xQ) and (xQ, -xI) as int16)
-// and a 4-copy carrier table are shared by the block's waves.  The complex
-// wipe-off is two packed int16 multiply-adds per sample; lanes take
+// sample tiles; the tile (4 B per sample: (xI, xQ) as int16) and a 4-copy
+// carrier table of (c, s, s, -s) entries are shared by the block's waves.
+// The complex wipe-off is two packed int16 multiply-adds per sample (the
+// (xQ, xI) operand by a half swap of the sample word); lanes take
 // consecutive samples.  The window walk runs on uniform (scalar) values.
 #include "gc_device.h"
 
@@ -41,20 +42,20 @@ constexpr int kChunkChips = 32;                   // chips per window (4 MFMA K 
 constexpr int kRows = 32;                         // q
 constexpr int kSBytes = kChunkChips * kRows * 4;  // 4096 per wave, cell (p, q) at 128 p + 4 q
 constexpr int kLutCopies = 4;
-constexpr int kLutStride = 257;                   // words between copies
+constexpr int kLutStride = 514;                   // words between copies (256 two-word entries + 2)
 constexpr int kLutBytes = kLutCopies * kLutStride * 4;
-constexpr int kTile = 10384;                      // samples per tile (what the LDS leaves)
+constexpr int kTile = 20704;                      // samples per tile (what the LDS leaves)
 constexpr int kMargin = kChunkChips * 32 + 64 + 128;  // <= 32 chips of <= 32 samples, + one pair read ahead
 constexpr int kXSamples = kTile + kMargin;
 constexpr int kOffS = 0;                          // S areas first: bases are multiples of 4096
 constexpr int kOffLut = kOffS + kWaves * kSBytes;
 constexpr int kOffX = kOffLut + kLutBytes;
-constexpr int kOffList = kOffX + kXSamples * 8;
-// 256 zero words: the carrier table of direct-form lanes whose row holds no
+constexpr int kOffList = kOffX + kXSamples * 4;
+// 256 zero entries: the carrier table of direct-form lanes whose row holds no
 // sample (their cells come out 0 with no branch); offset by 32 banks from
 // the first table copy, so that the same entry of both is in different banks
 constexpr int kOffZero = ((kOffList + 4 * (kWaves + 1) + 255) & ~255) + (((kOffLut / 4 + 32) % 64) * 4);
-constexpr int kLdsBytes = kOffZero + 1024;
+constexpr int kLdsBytes = kOffZero + 256 * 8;
 static_assert(kLdsBytes <= 160 * 1024, "LDS per block");
 static_assert(kOffS % 4096 == 0 && kSBytes == 4096, "cell offset = (U >> 25) & 0xFFC | wave base");
 static_assert((kOffZero / 4 - kOffLut / 4) % 64 == 32, "zero table 32 banks from the first copy");
@@ -291,30 +292,30 @@ __device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, 
                 if (s0 + k >= avail) xi[k] = xq[k] = 0;
         }
 #pragma unroll
-        for (int k = 0; k < 8; k += 2) {
-            uint4 o;
-            o.x = (uint32_t)(uint16_t)xi[k] | ((uint32_t)(uint16_t)xq[k] << 16);
-            o.y = (uint32_t)(uint16_t)xq[k] | ((uint32_t)(uint16_t)(-xi[k]) << 16);
-            o.z = (uint32_t)(uint16_t)xi[k + 1] | ((uint32_t)(uint16_t)xq[k + 1] << 16);
-            o.w = (uint32_t)(uint16_t)xq[k + 1] | ((uint32_t)(uint16_t)(-xi[k + 1]) << 16);
-            dst[(s0 + k) / 2] = o;
+        for (int k = 0; k < 8; k += 4) {
+            uint32_t o[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                o[j] = (uint32_t)(uint16_t)xi[k + j] | ((uint32_t)(uint16_t)xq[k + j] << 16);
+            dst[(s0 + k) / 4] = uint4{o[0], o[1], o[2], o[3]};
         }
     }
 }
 
 // Stage 1 for one sample: the wiped-off (wI, wQ) + 128 as int16 pairs,
-// (xI, xQ) c + ((xQ, -xI) s + 128): every product and sum stays below 2^15
+// (xI, xQ) c + ((xQ, xI) (s, -s) + 128), the swapped sample pair and the
+// table entry's second word (s, -s): every product and sum stays below 2^15
 // in magnitude (|x c| <= 3072, |w| <= 4352), so the 16-bit lanes hold the
 // exact values; XOR 0x80 per half gives the cell bytes (lo, hi).  The empty
 // asm keeps the +128 inside the first packed multiply-add (the compiler
 // would otherwise add it separately after both products).
-__device__ __forceinline__ uint32_t cell_of(uint2 xw, uint32_t cs, short2_t k128) {
-    const short2_t c2 = as_s2(cs);
+__device__ __forceinline__ uint32_t cell_of(uint32_t xw, uint2 cs, short2_t k128) {
+    const short2_t x = as_s2(xw);
+    const short2_t c2 = as_s2(cs.x);
     const short2_t cc = __builtin_shufflevector(c2, c2, 0, 0);
-    const short2_t ss = __builtin_shufflevector(c2, c2, 1, 1);
-    short2_t p = as_s2(xw.y) * ss + k128;
+    short2_t p = __builtin_shufflevector(x, x, 1, 0) * as_s2(cs.y) + k128;
     asm("" : "+v"(p));
-    const short2_t w2 = as_s2(xw.x) * cc + p;
+    const short2_t w2 = x * cc + p;
     return __builtin_bit_cast(uint32_t, w2) ^ 0x00800080u;
 }
 
@@ -433,13 +434,20 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
     const int nlist = __builtin_amdgcn_readfirstlane(s_list[kWaves]);
     if (nlist == 0) return;
     {
+        // entry e of a copy: (c, s) of the table, then (s, -s)
         uint32_t* lut = reinterpret_cast<uint32_t*>(s_lds + kOffLut);
         for (int i = tid; i < kLutCopies * kLutStride; i += nthreads) {
-            const int e = i % kLutStride;
-            lut[i] = e < 256 ? tables[kTabLut + e] : 0u;
+            const int w = i % kLutStride, e = w / 2;
+            uint32_t v = 0u;
+            if (e < 256) {
+                const uint32_t cs = tables[kTabLut + e];
+                const uint32_t sn = cs >> 16;
+                v = (w & 1) ? sn | ((uint32_t)(uint16_t)(-(int16_t)sn) << 16) : cs;
+            }
+            lut[i] = v;
         }
         uint32_t* zero = reinterpret_cast<uint32_t*>(s_lds + kOffZero);
-        for (int i = tid; i < 256; i += nthreads) zero[i] = 0u;
+        for (int i = tid; i < 512; i += nthreads) zero[i] = 0u;
     }
 
     const bool active = wave < nlist;
@@ -509,7 +517,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
     const bool direct_ok = m.dp < (1ull << 30) && d2l >= -(1ll << 18) && d2l <= (1ll << 18);
     const int32_t d2 = (int32_t)d2l;
     const uint32_t dp32 = (uint32_t)m.dp;
-    const uint32_t X2 = 8u * (uint32_t)D2;          // tile bytes per two chips
+    const uint32_t X2 = 4u * (uint32_t)D2;          // tile bytes per two chips
     const uint32_t F2 = (uint32_t)D2 * m.dphi;      // carrier phase per two chips
     const uint32_t X2s = __builtin_amdgcn_readfirstlane(X2);
     const uint32_t F2s = __builtin_amdgcn_readfirstlane(F2);
@@ -538,11 +546,11 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
         const uint64_t sa = uni64(k.sa);
         Ua = m.p0 + sa * m.dp;
         pha = m.phi0 + (uint32_t)sa * m.dphi;
-        xsa = kOffX + (uint32_t)(sa - T0) * 8u;
+        xsa = kOffX + (uint32_t)(sa - T0) * 4u;
     }
-    auto x_at = [&](uint32_t a) { return *reinterpret_cast<const uint2*>(s_lds + a); };
+    auto x_at = [&](uint32_t a) { return *reinterpret_cast<const uint32_t*>(s_lds + a); };
     auto lut_at = [&](uint32_t phase) {
-        return *reinterpret_cast<const uint32_t*>(s_lds + lut_base + ((phase >> 24) << 2));
+        return *reinterpret_cast<const uint2*>(s_lds + lut_base + ((phase >> 24) << 3));
     };
     auto cell_store = [&](uint32_t a, uint32_t v) { *reinterpret_cast<uint32_t*>(s_lds + a) = v; };
 
@@ -560,8 +568,8 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
         __syncthreads();
         if (!active) continue;
         if (tile > tb0) {
-            xsa -= 8u * tile_len;
-            dx -= 8u * tile_len;
+            xsa -= 4u * tile_len;
+            dx -= 4u * tile_len;
         }
         while (k.sa < t1 && k.sa < k.sb) {
             // the window's replica operand, in flight during stage 1
@@ -595,7 +603,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
                         if (r >= (int64_t)m.dp) { r -= (int64_t)m.dp; --n0; }
                     }
                     dr = (int32_t)r;
-                    dx = xsa + 8u * (uint32_t)n0;
+                    dx = xsa + 4u * (uint32_t)n0;
                     df = pha + (uint32_t)n0 * m.dphi;
                     dw0 = k.w0;
                 }
@@ -623,17 +631,17 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
                 // (one K step at a time, the next step's reads issued before
                 // this step's arithmetic; a lane whose row holds no sample
                 // reads the zero table and forms 0 cells)
-                uint2 xv[4];
-                uint32_t cv[4];
+                uint32_t xv[4];
+                uint2 cv[4];
                 // running sample address (low word) and carrier phase (high
                 // word), stepped by the uniform two-chip strides with one
                 // 64-bit add: the address stays far below 2^32, so no carry
                 // reaches the phase, and the phase wraps as a 32-bit word
                 uint64_t zc = ((uint64_t)f0 << 32) | x0;
-                auto load_step = [&](uint2* xs, uint32_t* cs) {
+                auto load_step = [&](uint32_t* xs, uint2* cs) {
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        cs[i] = *reinterpret_cast<const uint32_t*>(s_lds + lutb + ((uint32_t)(zc >> 56) << 2));
+                        cs[i] = *reinterpret_cast<const uint2*>(s_lds + lutb + ((uint32_t)(zc >> 56) << 3));
                         xs[i] = x_at((uint32_t)zc);
                         zc += Z2s;
                     }
@@ -641,22 +649,22 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
                 load_step(xv, cv);
 #pragma unroll
                 for (int ks = 0; ks < 4; ++ks) {
-                    uint2 xn[4];
-                    uint32_t cn[4];
+                    uint32_t xn[4];
+                    uint2 cn[4];
                     if (ks < 3) load_step(xn, cn);
                     // cell_of for four cells, the +128 kept inside the first
                     // multiply-add of each
                     short2_t pp[4];
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const short2_t c2 = as_s2(cv[i]);
-                        pp[i] = as_s2(xv[i].y) * __builtin_shufflevector(c2, c2, 1, 1) + k128;
+                        const short2_t x = as_s2(xv[i]);
+                        pp[i] = __builtin_shufflevector(x, x, 1, 0) * as_s2(cv[i].y) + k128;
                     }
                     asm("" : "+v"(pp[0]), "+v"(pp[1]), "+v"(pp[2]), "+v"(pp[3]));
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const short2_t c2 = as_s2(cv[i]);
-                        const short2_t w2 = as_s2(xv[i].x) * __builtin_shufflevector(c2, c2, 0, 0) + pp[i];
+                        const short2_t c2 = as_s2(cv[i].x);
+                        const short2_t w2 = as_s2(xv[i]) * __builtin_shufflevector(c2, c2, 0, 0) + pp[i];
                         aop[ks][i] = (int)(__builtin_bit_cast(uint32_t, w2) ^ 0x00800080u);
                     }
                     if (ks < 3) {
@@ -678,26 +686,26 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
                 // at most 32 chips of at most 32 samples, inside the staged tile
                 const uint32_t cnt = min(adv, (uint32_t)(staged - (uint32_t)(k.sa - t0)));
                 uint64_t U = Ua + lane_dU;
-                uint32_t ph = pha + lane_dph, xa = xsa + lane * 8u;
+                uint32_t ph = pha + lane_dph, xa = xsa + lane * 4u;
                 // pairs of full steps, software-pipelined over two register
                 // sets: the reads of the next pair (unconditional: the staged
                 // tile extends one pair past any chunk) are issued before the
                 // stores of the current one
                 uint32_t pairs = __builtin_amdgcn_readfirstlane(cnt / 128);
                 if (pairs > 0) {
-                    uint2 xa0 = x_at(xa), xa1 = x_at(xa + 512u);
-                    uint32_t ca0 = lut_at(ph), ca1 = lut_at(ph + dph);
-                    uint2 xb0, xb1;
-                    uint32_t cb0, cb1;
+                    uint32_t xa0 = x_at(xa), xa1 = x_at(xa + 256u);
+                    uint2 ca0 = lut_at(ph), ca1 = lut_at(ph + dph);
+                    uint32_t xb0, xb1;
+                    uint2 cb0, cb1;
                     for (;;) {
                         {
                             const uint32_t v0 = cell_of(xa0, ca0, k128), v1 = cell_of(xa1, ca1, k128);
                             const uint32_t a0 = cell_addr(U, s_base_v), a1 = cell_addr(U + dUv, s_base_v);
                             U += dU2v;
                             ph += dph2v;
-                            xa += 1024u;
+                            xa += 512u;
                             xb0 = x_at(xa);
-                            xb1 = x_at(xa + 512u);
+                            xb1 = x_at(xa + 256u);
                             cb0 = lut_at(ph);
                             cb1 = lut_at(ph + dph);
                             cell_store(a0, v0);
@@ -709,9 +717,9 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
                             const uint32_t a0 = cell_addr(U, s_base_v), a1 = cell_addr(U + dUv, s_base_v);
                             U += dU2v;
                             ph += dph2v;
-                            xa += 1024u;
+                            xa += 512u;
                             xa0 = x_at(xa);
-                            xa1 = x_at(xa + 512u);
+                            xa1 = x_at(xa + 256u);
                             ca0 = lut_at(ph);
                             ca1 = lut_at(ph + dph);
                             cell_store(a0, v0);
@@ -724,7 +732,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
                 const uint32_t rest = cnt % 128;
                 if (rest > 0) {
                     const uint32_t v0 = cell_of(x_at(xa), lut_at(ph), k128);
-                    const uint32_t v1 = cell_of(x_at(xa + 512u), lut_at(ph + dph), k128);
+                    const uint32_t v1 = cell_of(x_at(xa + 256u), lut_at(ph + dph), k128);
                     const uint32_t a0 = cell_addr(U, s_base_v), a1 = cell_addr(U + dUv, s_base_v);
                     if (lane < rest) cell_store(a0, v0);
                     if (lane + 64 < rest) cell_store(a1, v1);
@@ -754,7 +762,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_mtap(const uint8_t* __restrict_
             }
             Ua += (uint64_t)adv * m.dp;
             pha += adv * m.dphi;
-            xsa += 8u * adv;
+            xsa += 4u * adv;
             const bool was_last = k.last;
             chunk_next(k, span, m.dp, inv_dp, n, fs);
             if (was_last) seen_first = true;
