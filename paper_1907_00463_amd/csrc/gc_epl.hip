@@ -47,6 +47,25 @@ constexpr int kMargin = kEplMarginSamples;    // chips that start in a tile end 
 constexpr int kLutWords = 256 * 64;           // entry l of lane L at word l*64 + L
 constexpr uint32_t kPermSel = 0x0C0C0700u;    // byte1 = phase[31:24], byte0 = lane*4
 
+// Complex samples in LDS: one dword each, either plain (sample i at dword
+// i) or blocked: blocks of kIqBlk samples, each followed by copies of the
+// next block's first kIqPad samples, so sample i sits at dword iq_at(i)
+// and the samples of a bin of up to kIqPad + 1 are consecutive dwords from
+// iq_at of its first.  The lanes of a wave walk runs a whole number of
+// chips apart; at a whole number of samples per chip that is a multiple of
+// 8 (8.184, 16.368 MHz) their starts fall on 8 or fewer of the banks, and
+// the odd shift of kIqPad per block spreads them.  Elsewhere the plain
+// layout spreads them already and saves the per-bin address arithmetic.
+constexpr uint32_t kIqBlk = 256;
+constexpr uint32_t kIqPad = 5;
+__device__ __forceinline__ uint32_t iq_at(uint32_t i) { return i + kIqPad * (i >> 8); }
+template <bool PAD>
+__device__ __forceinline__ uint32_t iq_idx(uint32_t i) { return PAD ? iq_at(i) : i; }
+static_assert(kIqBlk == 256, "iq_at shifts by 8");
+constexpr int iq_words(int samples) {
+    return (samples + (int)kIqBlk - 1) / (int)kIqBlk * (int)(kIqBlk + kIqPad);
+}
+
 // Block shape: THREADS lanes, each walking a run of about RUN samples per
 // channel (RUN/2 LDS dwords, odd, so that lanes start in different banks).
 template <int THREADS, int RUN>
@@ -55,11 +74,13 @@ struct Shape {
     static constexpr int kRun = RUN;
     static constexpr int kTile = THREADS * RUN;                 // samples per tile
     static constexpr int kXSamples = kTile + kMargin;           // staged as int16
-    // complex input: half tiles of kTile / 2 samples (+ margin), one dword each
+    // complex input: half tiles of kTile / 2 samples (+ margin), one dword
+    // each, plain or blocked (iq_at; sized for the blocked one)
     static constexpr int kHalf = kTile / 2;
     static constexpr int kXSamplesIQ = kHalf + kMargin;
-    static constexpr int kXBytes = kXSamples * 2 > kXSamplesIQ * 4 ? kXSamples * 2
-                                                                   : kXSamplesIQ * 4;
+    static constexpr int kXBytes = kXSamples * 2 > iq_words(kXSamplesIQ) * 4
+                                       ? kXSamples * 2
+                                       : iq_words(kXSamplesIQ) * 4;
     static constexpr int kLdsBytes = kLutWords * 4 + kXBytes;   // table at LDS offset 0
     static_assert((RUN / 2) % 2 == 1, "odd dword stride between lanes");
     static_assert(kTile % 8 == 0, "half tiles start on a multiple of 4 samples");
@@ -114,21 +135,32 @@ __device__ __forceinline__ void mac_iq(short2_t& a, short2_t& b, uint32_t xw, ui
     b = xs * __builtin_shufflevector(cs, cs, 1, 1) + b;
 }
 
-// Complex bin of len samples (as bin_sum): the planes a = sum (xI, xQ)*c and
-// b = sum (xQ, xI)*s, each within int16 (len * 128 * 24 <= 32767).
-template <int Q>
-__device__ __forceinline__ void bin_sum_iq(const uint32_t* __restrict__ xs, uint32_t phi,
-                                           uint32_t dphi, uint32_t lane4, const uint8_t* lut,
-                                           uint32_t len, short2_t& a, short2_t& b) {
+// Complex bin of len samples from tile sample nb (as bin_sum): the planes
+// a = sum (xI, xQ)*c and b = sum (xQ, xI)*s, each within int16
+// (len * 128 * 24 <= 32767).  In the blocked layout bins of at most
+// kIqPad + 1 samples read consecutive dwords and longer ones map each
+// sample.
+template <int Q, bool PAD>
+__device__ __forceinline__ void bin_sum_iq(const uint32_t* __restrict__ sx, uint32_t nb,
+                                           uint32_t phi, uint32_t dphi, uint32_t lane4,
+                                           const uint8_t* lut, uint32_t len, short2_t& a,
+                                           short2_t& b) {
     a = short2_t{0, 0};
     b = short2_t{0, 0};
-    if constexpr (Q > 0) {
+    if constexpr (Q > 0 && (!PAD || Q <= (int)kIqPad)) {
+        const uint32_t* xs = sx + iq_idx<PAD>(nb);
 #pragma unroll
         for (int j = 0; j < Q; ++j) mac_iq(a, b, xs[j], phi + j * dphi, lane4, lut);
         const uint32_t x2 = len > (uint32_t)Q ? xs[Q] : 0u;
         mac_iq(a, b, x2, phi + Q * dphi, lane4, lut);
+    } else if constexpr (Q > 0) {
+#pragma unroll
+        for (int j = 0; j < Q; ++j) mac_iq(a, b, sx[iq_at(nb + j)], phi + j * dphi, lane4, lut);
+        const uint32_t x2 = len > (uint32_t)Q ? sx[iq_at(nb + Q)] : 0u;
+        mac_iq(a, b, x2, phi + Q * dphi, lane4, lut);
     } else {
-        for (uint32_t j = 0; j < len; ++j) mac_iq(a, b, xs[j], phi + j * dphi, lane4, lut);
+        for (uint32_t j = 0; j < len; ++j)
+            mac_iq(a, b, sx[iq_idx<PAD>(nb + j)], phi + j * dphi, lane4, lut);
     }
 }
 
@@ -231,7 +263,7 @@ __device__ __forceinline__ void flush_lane(const EplAcc<FMT>& acc, const Dest& d
 
 // Binned run of one lane over chips [c, c + K) whose samples start at tile
 // offset nb with code-phase overshoot e past the chip start.
-template <int FMT, int Q>
+template <int FMT, int Q, bool PAD>
 __device__ __forceinline__ void epl_run(const void* __restrict__ sx, const uint8_t* lut,
                                      uint32_t lane4, uint32_t nb, uint32_t phi, uint32_t dphi,
                                      uint32_t e, uint32_t dp, uint32_t q, uint32_t r, uint32_t c,
@@ -262,7 +294,7 @@ __device__ __forceinline__ void epl_run(const void* __restrict__ sx, const uint8
             e = lt ? e + dp - r : e - r;
             short2_t a0, b0, a1, b1;
             if constexpr (fmt_complex(FMT)) {
-                bin_sum_iq<Q>(static_cast<const uint32_t*>(sx) + nb, phi, dphi, lane4, lut, len,
+                bin_sum_iq<Q, PAD>(static_cast<const uint32_t*>(sx), nb, phi, dphi, lane4, lut, len,
                               a0, b0);
             } else {
                 a0 = bin_sum<Q>(static_cast<const short*>(sx) + nb, phi, dphi, lane4, lut, len);
@@ -275,7 +307,7 @@ __device__ __forceinline__ void epl_run(const void* __restrict__ sx, const uint8
             len = q + (lt ? 1u : 0u);
             e = lt ? e + dp - r : e - r;
             if constexpr (fmt_complex(FMT)) {
-                bin_sum_iq<Q>(static_cast<const uint32_t*>(sx) + nb, phi, dphi, lane4, lut, len,
+                bin_sum_iq<Q, PAD>(static_cast<const uint32_t*>(sx), nb, phi, dphi, lane4, lut, len,
                               a1, b1);
             } else {
                 a1 = bin_sum<Q>(static_cast<const short*>(sx) + nb, phi, dphi, lane4, lut, len);
@@ -333,7 +365,7 @@ __device__ __forceinline__ void epl_run(const void* __restrict__ sx, const uint8
 // Direct per-sample form over tile offsets [lo, hi) for up to 4 taps (chips
 // cut by the block ends, and channels the binned form does not cover), by
 // the nthr threads of a group (gtid = 0 .. nthr - 1, whole waves).
-template <int FMT>
+template <int FMT, bool PAD>
 __device__ __forceinline__ void direct_range(const void* __restrict__ sx, const uint8_t* lut,
                                              uint32_t gtid, uint32_t nthr,
                                              uint32_t lane4, uint64_t t0, uint32_t lo, uint32_t hi,
@@ -359,7 +391,7 @@ __device__ __forceinline__ void direct_range(const void* __restrict__ sx, const 
             lut_cs(e, c, s);
             int wi, wq;
             if constexpr (fmt_complex(FMT)) {
-                const uint32_t xw = static_cast<const uint32_t*>(sx)[i];
+                const uint32_t xw = static_cast<const uint32_t*>(sx)[iq_idx<PAD>(i)];
                 const int xi = (int)(short)(xw & 0xFFFF), xq = (int)(short)(xw >> 16);
                 wipe<GC_I8_IQ, int>(xi, xq, c, s, wi, wq);
             } else {
@@ -408,7 +440,7 @@ __device__ __forceinline__ float sign_f(uint32_t word) { return (float)(int)(sho
 
 // Wiped-off (I, Q) of one bin of len samples (Q > 0: q or q + 1 samples,
 // the last weighted 0 or 1; Q == 0: any length).
-template <int FMT, int Q>
+template <int FMT, int Q, bool PAD>
 __device__ __forceinline__ void bin_f32(const void* __restrict__ sx, uint32_t nb, float ph, float ff,
                                         uint32_t len, float& bi, float& bq) {
     bi = 0.0f;
@@ -417,7 +449,12 @@ __device__ __forceinline__ void bin_f32(const void* __restrict__ sx, uint32_t nb
         float c, s;
         carrier_f32(ph + (float)j * ff, c, s);
         if constexpr (fmt_complex(FMT)) {
-            const uint32_t xw = static_cast<const uint32_t*>(sx)[nb + j];
+            // blocked layout: bins of at most kIqPad + 1 samples are
+            // consecutive dwords
+            const uint32_t* xp = static_cast<const uint32_t*>(sx);
+            const uint32_t xw = (Q > 0 && (!PAD || Q <= (int)kIqPad))
+                                    ? xp[iq_idx<PAD>(nb) + j]
+                                    : xp[iq_idx<PAD>(nb + j)];
             const float xi = wt * (float)(int)(short)(xw & 0xFFFF);
             const float xq = wt * (float)(int)(short)(xw >> 16);
             bi += xi * c + xq * s;
@@ -439,7 +476,7 @@ __device__ __forceinline__ void bin_f32(const void* __restrict__ sx, uint32_t nb
 
 // Float run of one lane over chips [c, c + K) (as epl_run): ph0 is the phase
 // of its first sample in cycles, reduced to [0, 1).
-template <int FMT, int Q>
+template <int FMT, int Q, bool PAD>
 __device__ __forceinline__ void epl_run_f32(const void* __restrict__ sx, uint32_t nb, float ph,
                                             float ff, uint32_t e, uint32_t dp, uint32_t q,
                                             uint32_t r, uint32_t c, uint32_t K, uint32_t Kmax,
@@ -469,7 +506,7 @@ __device__ __forceinline__ void epl_run_f32(const void* __restrict__ sx, uint32_
             bool lt = e < r;
             uint32_t len = q + (lt ? 1u : 0u);
             e = lt ? e + dp - r : e - r;
-            bin_f32<FMT, Q>(sx, nb, ph, ff, len, bi, bq);
+            bin_f32<FMT, Q, PAD>(sx, nb, ph, ff, len, bi, bq);
             v[0] += bi * sc; v[1] += bq * sc;
             v[2] += bi * sc; v[3] += bq * sc;
             v[4] += bi * sp; v[5] += bq * sp;
@@ -480,7 +517,7 @@ __device__ __forceinline__ void epl_run_f32(const void* __restrict__ sx, uint32_
             lt = e < r;
             len = q + (lt ? 1u : 0u);
             e = lt ? e + dp - r : e - r;
-            bin_f32<FMT, Q>(sx, nb, ph, ff, len, bi, bq);
+            bin_f32<FMT, Q, PAD>(sx, nb, ph, ff, len, bi, bq);
             v[0] += bi * sn; v[1] += bq * sn;
             v[2] += bi * sc; v[3] += bq * sc;
             v[4] += bi * sc; v[5] += bq * sc;
@@ -511,7 +548,7 @@ __device__ __forceinline__ void epl_run_f32(const void* __restrict__ sx, uint32_
 
 // Float direct per-sample form over tile offsets [lo, hi) for up to 4 taps
 // (as direct_range; each sample's phase in FP64).
-template <int FMT>
+template <int FMT, bool PAD>
 __device__ __forceinline__ void direct_range_f32(const void* __restrict__ sx, uint32_t gtid,
                                                  uint32_t nthr, uint64_t t0, uint32_t lo,
                                                  uint32_t hi, const DevMeta& m, const DevChan& ch,
@@ -535,7 +572,7 @@ __device__ __forceinline__ void direct_range_f32(const void* __restrict__ sx, ui
             carrier_f32((float)(p - floor(p)), c, s);
             float wi, wq;
             if constexpr (fmt_complex(FMT)) {
-                const uint32_t xw = static_cast<const uint32_t*>(sx)[i];
+                const uint32_t xw = static_cast<const uint32_t*>(sx)[iq_idx<PAD>(i)];
                 wipe<GC_I8_IQ, float>((float)(int)(short)(xw & 0xFFFF),
                                       (float)(int)(short)(xw >> 16), c, s, wi, wq);
             } else {
@@ -576,13 +613,35 @@ __device__ __forceinline__ uint32_t bytes_to_pair(uint32_t v) {
            ((uint32_t)(uint16_t)(int16_t)(int8_t)((v >> 8) & 0xFF) << 16);
 }
 
+// Complex tile samples s and s + 1 (s even) at their dwords: plain, or
+// blocked (iq_at) and then again among the copies ending the previous
+// block when they are among the first kIqPad of theirs.
+template <bool PAD>
+__device__ __forceinline__ void put_iq_pair(uint32_t* __restrict__ x, uint32_t s, uint32_t lo,
+                                            uint32_t hi) {
+    if constexpr (!PAD) {
+        *reinterpret_cast<uint2*>(x + s) = uint2{lo, hi};
+        return;
+    }
+    const uint32_t p = iq_at(s);
+    x[p] = lo;
+    x[p + 1] = hi;
+    const uint32_t o = s & (kIqBlk - 1);
+    if (s >= kIqBlk && o < kIqPad) {
+        x[p - kIqPad] = lo;
+        if (o + 1 < kIqPad) x[p + 1 - kIqPad] = hi;
+    }
+}
+
 // Samples [t0, t0 + count) of the block into LDS (zero past its end); count
 // is at most kXSamples and a multiple of 8 (complex) or 16 (real input).
-template <int FMT, int kThreads, int kXSamples>
+// Complex samples take the plain or (PAD) the blocked layout.
+template <int FMT, int kThreads, int kXSamples, bool PAD = false>
 __device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, uint64_t n,
                                            uint64_t t0, void* sx, const uint32_t* tables,
                                            uint32_t count) {
-    uint2* dst = reinterpret_cast<uint2*>(sx);  // 4 samples per 8 bytes (2 for complex)
+    uint2* dst = reinterpret_cast<uint2*>(sx);  // real input: 4 samples per 8 bytes
+    uint32_t* dx = reinterpret_cast<uint32_t*>(sx);  // complex input: see iq_at
     // A staged range inside the block (every one but the block's last):
     // units of 8 complex or 16 real samples (8, 4, 4 or 16 input bytes, 32
     // bytes out), four per thread and pass with all four loads issued before
@@ -631,7 +690,10 @@ __device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, 
                     o.x = codes_to_pair(v & 15u);
                     o.y = codes_to_pair(v >> 4);
                 }
-                dst[4 * u + k] = o;
+                if constexpr (fmt_complex(FMT))
+                    put_iq_pair<PAD>(dx, 8u * u + 2u * k, o.x, o.y);
+                else
+                    dst[4 * u + k] = o;
             }
         };
         for (int u0 = threadIdx.x; u0 < units; u0 += kP * kThreads) {
@@ -667,7 +729,7 @@ __device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, 
                   ((uint32_t)(uint16_t)(int16_t)(int8_t)((v >> 8) & 0xFF) << 16);
             o.y = ((uint32_t)(uint16_t)(int16_t)(int8_t)((v >> 16) & 0xFF)) |
                   ((uint32_t)(uint16_t)(int16_t)(int8_t)(v >> 24) << 16);
-            dst[i] = o;
+            put_iq_pair<PAD>(dx, 2u * i, o.x, o.y);
         }
     } else if constexpr (FMT == GC_I2_IQ) {
         // t0 is even: byte t0/2 + i holds tile samples 2i and 2i+1, each a
@@ -682,7 +744,7 @@ __device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, 
             uint2 o;
             o.x = smp < n ? iq(v & 15u) : 0u;
             o.y = smp + 1 < n ? iq(v >> 4) : 0u;
-            dst[i] = o;
+            put_iq_pair<PAD>(dx, 2u * i, o.x, o.y);
         }
     } else if constexpr (FMT == GC_I2_REAL) {
         // t0 is a multiple of 4: byte t0/4 + i holds tile samples 4i .. 4i+3
@@ -720,7 +782,7 @@ __device__ __forceinline__ void stage_tile(const uint8_t* __restrict__ samples, 
 
 // Channels [c_begin, c_end) of one receiver on its staged tile [t0, t1);
 // n_act of them are left to this kernel (not refused, not periodic).
-template <int FMT, class SH, int CARR = GC_CARRIER_LUT>
+template <int FMT, class SH, int CARR = GC_CARRIER_LUT, bool PAD = false>
 __device__ __forceinline__ void epl_tile(const void* __restrict__ s_x, const uint8_t* lut,
                                          uint64_t t0, uint64_t t1, int c_begin, int c_end,
                                          int n_act,
@@ -762,9 +824,9 @@ __device__ __forceinline__ void epl_tile(const void* __restrict__ s_x, const uin
         const uint32_t tl = (uint32_t)(t1 - t0);
         auto direct = [&](uint32_t lo, uint32_t hi) {
             if constexpr (CARR == GC_CARRIER_F32)
-                direct_range_f32<FMT>(s_x, gtid, kGroup, t0, lo, hi, m, ch, sgn_prn, df);
+                direct_range_f32<FMT, PAD>(s_x, gtid, kGroup, t0, lo, hi, m, ch, sgn_prn, df);
             else
-                direct_range<FMT>(s_x, lut, gtid, kGroup, lane4, t0, lo, hi, m, ch, sgn_prn, d);
+                direct_range<FMT, PAD>(s_x, lut, gtid, kGroup, lane4, t0, lo, hi, m, ch, sgn_prn, d);
         };
         if (m.path != kPathBinned) {
             direct(0, tl);
@@ -816,10 +878,10 @@ __device__ __forceinline__ void epl_tile(const void* __restrict__ s_x, const uin
         const uint32_t* sgn = sgn_prn + (c + kCodeLen - 1) % kCodeLen;
 #define GC_RUN(QQ)                                                                           \
     if constexpr (CARR == GC_CARRIER_F32)                                                     \
-        epl_run_f32<FMT, QQ>(s_x, nrel, phf, (float)m.ff, e, dp, q, r, c, K, Kmax, span, sgn, \
+        epl_run_f32<FMT, QQ, PAD>(s_x, nrel, phf, (float)m.ff, e, dp, q, r, c, K, Kmax, span, sgn, \
                              df, ch);                                                         \
     else                                                                                      \
-        epl_run<FMT, QQ>(s_x, lut, lane4, nrel, phi, m.dphi, e, dp, q, r, c, K, Kmax, span, sgn, \
+        epl_run<FMT, QQ, PAD>(s_x, lut, lane4, nrel, phi, m.dphi, e, dp, q, r, c, K, Kmax, span, sgn, \
                          d, ch)
         switch (q) {  // bins of q or q + 1 samples
             case 1: GC_RUN(1); break;
@@ -840,7 +902,7 @@ __device__ __forceinline__ void epl_tile(const void* __restrict__ s_x, const uin
 // [c_begin, c_end): staged and correlated whole (real input) or as two half
 // tiles (complex input, one dword per sample).  tile_len is at most SH::kTile
 // and a multiple of 16.
-template <int FMT, class SH, int CARR = GC_CARRIER_LUT>
+template <int FMT, class SH, int CARR = GC_CARRIER_LUT, bool PAD = false>
 __device__ __forceinline__ void tile_pass(const uint8_t* __restrict__ samples, uint64_t n,
                                           uint64_t t0, uint32_t tile_len, void* s_x,
                                           const uint8_t* lut,
@@ -859,11 +921,27 @@ __device__ __forceinline__ void tile_pass(const uint8_t* __restrict__ samples, u
         if (a >= n) break;
         const uint64_t b = min(n, a + part);
         __syncthreads();
-        stage_tile<FMT, SH::kThreads, kStaged>(samples, n, a, s_x, tables, part + kMargin);
+        stage_tile<FMT, SH::kThreads, kStaged, PAD>(samples, n, a, s_x, tables, part + kMargin);
         __syncthreads();
-        epl_tile<FMT, SH, CARR>(s_x, lut, a, b, c_begin, c_end, n_act, chans, metas, state, out,
+        epl_tile<FMT, SH, CARR, PAD>(s_x, lut, a, b, c_begin, c_end, n_act, chans, metas, state, out,
                                 tap_stride, max_dumps, tables);
     }
+}
+
+// Whether complex tiles take the blocked layout: some binned channel's
+// samples per chip (2^32 / dp) lie within 1/256 of a nonzero multiple of 8,
+// so that its lanes' runs would start on a few banks.  The same for every
+// block of a launch (it reads only the call's metas).
+__device__ __forceinline__ bool iq_blocked(const DevMeta* __restrict__ metas, int n_chan) {
+    bool pad = false;
+    for (int c = 0; c < n_chan; ++c) {
+        const DevMeta& m = metas[c];
+        if (m.status != GC_OK || m.path != kPathBinned || m.dp == 0) continue;
+        const float spc = 4294967296.0f / (float)m.dp;
+        const float k = rintf(spc * 0.125f);
+        pad = pad || (k >= 1.0f && fabsf(spc - 8.0f * k) < 1.0f / 256.0f);
+    }
+    return __builtin_amdgcn_readfirstlane((int)pad) != 0;
 }
 
 // FIXED: tiles of ShapePlan::kTile samples (tile_len unused), where a
@@ -890,10 +968,16 @@ __global__ __launch_bounds__(ShapePlan::kThreads) void k_epl(
         for (int i = tid; i < kLutWords; i += SH::kThreads) s_lut[i] = tables[kTabLut + (i >> 6)];
 
     const uint32_t tl = FIXED ? (uint32_t)SH::kTile : tile_len;
+    const bool pad = fmt_complex(FMT) && iq_blocked(metas, n_chan);
     for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const uint64_t t0 = (uint64_t)tile * tl;
-        tile_pass<FMT, SH, CARR>(samples, n, t0, tl, s_x, s_lds, 0, n_chan, n_act, chans, metas,
-                                 state, out, tap_stride, max_dumps, tables);
+        if (pad)
+            tile_pass<FMT, SH, CARR, fmt_complex(FMT)>(samples, n, t0, tl, s_x, s_lds, 0, n_chan,
+                                                       n_act, chans, metas, state, out,
+                                                       tap_stride, max_dumps, tables);
+        else
+            tile_pass<FMT, SH, CARR>(samples, n, t0, tl, s_x, s_lds, 0, n_chan, n_act, chans,
+                                     metas, state, out, tap_stride, max_dumps, tables);
     }
 }
 

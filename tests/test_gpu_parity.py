@@ -231,12 +231,14 @@ def test_fp32_sincos_error_exhaustive(g, ctx):
 
 
 @pytest.mark.parametrize("fmt,fs,if_frac", [(0, 4.092e6, 0.25), (1, 5.0e6, 0.0),
-                                            (2, 16.368e6, 0.25), (1, 20.46e6, 0.0)])
+                                            (2, 16.368e6, 0.25), (1, 20.46e6, 0.0),
+                                            (3, 8.184e6, 0.0), (1, 16.368e6, 0.0)])
 def test_fp32_carrier_strong_signal(g, ctx, fmt, fs, if_frac):
     """Strong synthetic signals (C/N0 80 dB-Hz, |P| hundreds of noise sigmas
     above zero) at several Dopplers, 1- and 20-period dumps: every E, P and L
     of every dump within 1e-5 * |P_ref| of the FP64 oracle, with no noise
-    floor in the bound."""
+    floor in the bound.  Complex input at 8 and 16 samples per chip takes the
+    chip-by-chip kernel's blocked sample layout (bins of 4-5 and 8-9)."""
     from paper_1907_00463_amd import synth
     rng = np.random.default_rng(4100 + fmt + int(fs) % 97)
     n = int(0.12 * fs)
