@@ -309,6 +309,34 @@ def test_binned_epl_rates_bit_exact(g, ctx, fs, fmt, kernels):
     assert_exact(lib, lst, orc, ost, cfgs)
 
 
+@pytest.mark.parametrize("kernels", ["default", "binned"])
+@pytest.mark.parametrize("fs", [24.552e6, 32.736e6])
+@pytest.mark.parametrize("fmt", [1, 3])
+def test_complex_long_bins_bit_exact(g, ctx, fs, fmt, kernels):
+    # complex input at 24 and 32 samples per chip, several tiles per block,
+    # Doppler of either sign: 2-bit I/Q takes the chip-by-chip kernel's
+    # blocked sample layout with bins of 11-13 and 15-17 samples (the
+    # any-length bin loop, each sample's dword mapped); int8 I/Q bins that
+    # long would overflow the int16 bin planes, so those channels take the
+    # multi-tap or direct kernel
+    rng = np.random.default_rng(int(fs) % 100003 + 11 * fmt)
+    n_chan = 4
+    cfgs = np.zeros(n_chan, g.CHAN_CFG)
+    states = np.zeros(n_chan, g.CHAN_STATE)
+    for i in range(n_chan):
+        T = [1, 4, 10, 1][i]   # 20 ms of int8 I/Q at 32.736 MHz could leave int32
+        cfgs[i] = g.make_cfg(int(rng.integers(1, 33)), [1 << 31, 0, -(1 << 31)], T)
+        fd = (-4100.0, 2900.0, -700.0, 4800.0)[i]
+        states[i] = g.gc_nco_init(fs, fd, float(rng.random()), 1.023e6 * (1 + fd / 1575.42e6),
+                                  float(rng.uniform(0, 1023 * T)), T)
+    lens = [400000, 98304 * 4 + 36]
+    blocks = _random_blocks(rng, fmt, lens)
+    lib, lst = run_library(torch, ctx, fmt, g.GC_CARRIER_LUT, cfgs, states, blocks, lens,
+                           kernels=KERNEL_SETS[kernels])
+    orc, ost = run_oracle(fmt, cfgs, states, blocks, lens)
+    assert_exact(lib, lst, orc, ost, cfgs)
+
+
 def _epl_channels_at(g, rng, fs, n_chan, ratios, periods=(1, 4, 20)):
     """E/P/L channels at sample rate fs whose code rate is 1.023 MHz * (1 + r)
     for r drawn from ``ratios`` (r = 0: exact half-chip bins)."""
